@@ -1,0 +1,119 @@
+"""RGS-Arnoldi (Algorithm 3) and randomized GMRES (Sec. 4.2) -- oracle; test infrastructure.
+
+One restart cycle builds the Krylov basis with RGS, Algorithm 2, column by
+column: w_1 = r_0 (the current residual; b on the first cycle, since x0 = 0),
+then w_i = A q_{i-1}.  The Hessenberg matrix is H = R(1:i, 2:i) (Sec. 4.1),
+and y = argmin_z || H z - r_11 e_1 || is solved with Givens rotations in fp64
+(Sec. 4.2 and the experiment of Sec. 5.3); x_{i-1} = Q_{i-1} y.  By the
+identity of Sec. 4.2, |g_i| after the i-th rotation is the sketched residual
+|| Theta (b - A x_{i-1}) ||.
+
+Readings (the paper runs a single unrestarted Arnoldi process):
+  * restart after ``restart`` inner steps (restart + 1 basis vectors);
+  * cycle c uses a fresh sketch (sketch_id = 2 + c) unless ``reuse_theta``;
+  * inner stop when |g_i| / ||b|| <= tol, outer stop on the true residual
+    ||b - A x|| / ||b|| <= tol computed in fp64; x is kept in fp64;
+  * h_{i,i-1} = r_ii below 2**-50 ||p_i|| is a lucky breakdown: the cycle
+    ends with the current H;
+  * iteration count = total number of inner steps (mat-vecs A q).
+Precision 'fp32' follows the multi-precision model: basis, mat-vec and the
+projection in float32, sketches / least squares / Givens / x in fp64.
+"""
+
+import numpy as np
+import scipy.linalg
+
+from .rgs import _ls, BREAKDOWN_RATIO
+
+
+def _givens(a, b):
+    """c, s, rho with [c s; -s c] [a; b] = [rho; 0]."""
+    if b == 0.0:
+        return 1.0, 0.0, a
+    rho = np.hypot(a, b)
+    return a / rho, b / rho, rho
+
+
+def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp64",
+           ls="householder", reuse_theta=False, max_cycles=None):
+    """Restarted randomized GMRES.
+
+    apply_A(u, dtype) -> A u in arithmetic ``dtype``; make_theta(cycle) -> sketch.
+    Returns dict(x, hist, iters, cycles, true_relres, converged, cond_info).
+    hist[t] = |g| / ||b|| after global inner step t.
+    """
+    store = np.float64 if precision == "fp64" else np.float32
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    bnorm = np.linalg.norm(b)
+    x = np.zeros(n)
+    r0 = b.copy()
+    hist = []
+    iters = 0
+    cycle = 0
+    converged = False
+    true_relres = 1.0
+    while iters < max_iters and (max_cycles is None or cycle < max_cycles):
+        theta = make_theta(0 if reuse_theta else cycle)
+        k = theta.k
+        mmax = restart + 1
+        Q = np.zeros((n, mmax), dtype=store)
+        S = np.zeros((k, mmax))
+        R = np.zeros((mmax, mmax))
+        # step 1-2 of Algorithm 3: w_1 = r_0, first RGS iteration
+        w = r0.astype(store)
+        p = theta.apply(w.astype(np.float64))
+        r11 = np.linalg.norm(p)
+        if r11 == 0.0:
+            converged = True
+            break
+        R[0, 0] = r11
+        S[:, 0] = p / r11
+        Q[:, 0] = (w.astype(np.float64) / r11).astype(store)
+        g = np.zeros(mmax)
+        g[0] = r11
+        cs = np.zeros(mmax)
+        sn = np.zeros(mmax)
+        used = 0                                    # columns of H (= inner steps)
+        for i in range(1, mmax):                    # 0-based index of the new column
+            w = apply_A(Q[:, i - 1], store)         # step 3 of Algorithm 3
+            p = theta.apply(w.astype(np.float64))   # RGS step 1
+            r = _ls(S[:, :i], p, ls)                # RGS step 2
+            R[:i, i] = r
+            qp = w - Q[:, :i] @ r.astype(store)     # RGS step 3
+            sp = theta.apply(qp.astype(np.float64))  # RGS step 4
+            rii = np.linalg.norm(sp)                # RGS step 5
+            lucky = rii == 0.0 or rii <= BREAKDOWN_RATIO * np.linalg.norm(p)
+            R[i, i] = 0.0 if lucky else rii
+            if not lucky:
+                S[:, i] = sp / rii                  # RGS step 6
+                Q[:, i] = (qp.astype(np.float64) / rii).astype(store)  # RGS step 7
+            # Hessenberg column i-1 (0-based) = R(0:i+1, i); Givens in fp64
+            h = R[: i + 1, i].copy()
+            for t in range(i - 1):
+                a, bb = h[t], h[t + 1]
+                h[t] = cs[t] * a + sn[t] * bb
+                h[t + 1] = -sn[t] * a + cs[t] * bb
+            c, s, rho = _givens(h[i - 1], h[i])
+            cs[i - 1], sn[i - 1] = c, s
+            h[i - 1], h[i] = rho, 0.0
+            R[: i + 1, i] = h                       # keep the rotated column
+            g[i] = -s * g[i - 1]
+            g[i - 1] = c * g[i - 1]
+            used = i
+            iters += 1
+            hist.append(abs(g[i]) / bnorm)
+            if lucky or abs(g[i]) / bnorm <= tol or iters >= max_iters:
+                break
+        # y = argmin || H z - r11 e1 ||: back substitution on the rotated H
+        Hr = R[:used, 1:used + 1]
+        y = scipy.linalg.solve_triangular(Hr, g[:used], lower=False)
+        x = x + Q[:, :used].astype(np.float64) @ y
+        r0 = b - apply_A(x, np.float64)
+        true_relres = np.linalg.norm(r0) / bnorm
+        cycle += 1
+        if true_relres <= tol:
+            converged = True
+            break
+    return {"x": x, "hist": np.array(hist), "iters": iters, "cycles": cycle,
+            "true_relres": true_relres, "converged": converged}

@@ -1,0 +1,152 @@
+"""Pins of the oracle's Algorithm 2 (RGS) and of its classical references.
+
+* Closed form: in exact arithmetic S R = P = Theta W with S orthonormal and
+  r_ii > 0, so R is the positive-diagonal R factor of the thin QR of Theta W
+  (LAPACK through numpy), Q = W R^-1 and S = Theta W R^-1.
+* Theta = I with the one-sweep Richardson solver (Sec. 2.3: "exactly
+  corresponds to ... the classical Gram-Schmidt process") is CGS bit for bit.
+* Theta = I with the Householder solver is exact-arithmetic Gram-Schmidt, so
+  |R| agrees with |R| of a Householder QR of W.
+* A fully sampled SRHT is an isometry, so the same agreement holds.
+* Invariants of Theorems 3.2/3.3 and Corollary 2.2 on the outputs.
+* Breakdowns and argument errors.
+* Sec. 5.1 (qualitative, reduced n): in float32, CGS loses orthogonality,
+  MGS degrades, multi-precision RGS keeps cond(Q) close to 1.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rgs, sketch, metrics
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def _wellcond(n, m, smin=1e-2, tag=0):
+    return synth.svd_matrix(n, m, smin, tag=tag)
+
+
+@pytest.mark.parametrize("kind,n,m,k", [("gaussian", 512, 8, 64), ("srht", 1000, 12, 96),
+                                         ("gaussian", 300, 20, 20)])
+def test_closed_form_R_from_qr_of_sketch(kind, n, m, k):
+    W = _wellcond(n, m, tag=1)
+    th = sketch.make(kind, n, k, seed=4)
+    out = rgs.rgs_qr(W, th)
+    P = th.apply(W)
+    _, Rq = np.linalg.qr(P)
+    Rq = np.sign(np.diag(Rq))[:, None] * Rq            # positive diagonal
+    kappa = metrics.cond(W)
+    assert np.linalg.norm(out["R"] - Rq) / np.linalg.norm(Rq) <= 1e-13 * kappa
+    Qc = np.linalg.solve(Rq.T, W.T).T                    # W R^-1
+    assert np.linalg.norm(out["Q"] - Qc) / np.linalg.norm(Qc) <= 1e-13 * kappa
+    np.testing.assert_allclose(out["P"], P, rtol=0, atol=1e-14 * np.abs(P).max())
+
+
+def test_identity_sketch_with_richardson1_is_cgs_bitwise():
+    n, m = 256, 16
+    W = _wellcond(n, m, smin=1e-3, tag=2)
+    out = rgs.rgs_qr(W, sketch.Identity(n), ls="richardson1")
+    Qc, Rc = rgs.cgs(W)
+    assert np.array_equal(out["Q"], Qc)
+    assert np.array_equal(out["R"], Rc)
+
+
+def test_identity_sketch_householder_matches_householder_qr():
+    n, m = 400, 24
+    W = _wellcond(n, m, smin=1e-2, tag=3)
+    out = rgs.rgs_qr(W, sketch.Identity(n))
+    _, Rh = np.linalg.qr(W)
+    assert np.linalg.norm(np.abs(out["R"]) - np.abs(Rh)) / np.linalg.norm(Rh) <= 1e-12
+
+
+def test_full_srht_matches_householder_qr():
+    n, m = 200, 10                                     # s = 256
+    W = _wellcond(n, m, smin=1e-2, tag=4)
+    out = rgs.rgs_qr(W, sketch.SRHT(n, 256, seed=1))
+    _, Rh = np.linalg.qr(W)
+    assert np.linalg.norm(np.abs(out["R"]) - np.abs(Rh)) / np.linalg.norm(Rh) <= 1e-12
+    assert metrics.orth_loss_2(out["Q"]) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+def test_output_invariants_fp64(kind):
+    n, m, k = 2048, 32, 512
+    W = synth.svd_matrix(n, m, 1e-6, tag=5)
+    th = sketch.make(kind, n, k, seed=42)
+    out = rgs.rgs_qr(W, th)
+    Q, R, S, P = out["Q"], out["R"], out["S"], out["P"]
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    assert np.max(np.abs(np.linalg.norm(S, axis=0) - 1.0)) <= 8 * U64
+    assert metrics.backward_error(W, Q, R) <= 3.7 * U64 * m ** 1.5          # Thm 3.2
+    assert metrics.delta_tilde_F(P, S, R) <= 6 * U64 * m ** 1.5               # Thm 3.3
+    assert metrics.delta_F(S) <= 20 * U64 * m ** 2 * metrics.cond(W)          # Thm 3.3
+    SQ = th.apply(Q)
+    assert np.linalg.norm(S - SQ) <= 1e-13 * (np.linalg.norm(Q) + 1)
+    eps = metrics.omega(SQ, Q)                                                # Cor. 2.2
+    assert eps < 1
+    assert metrics.cond(Q) <= math.sqrt((1 + eps) / (1 - eps)) * metrics.cond(S) * (1 + 1e-10)
+
+
+def test_fp32_model_tolerances():
+    n, m, k = 8192, 64, 256
+    W = synth.svd_matrix(n, m, 1e-3, tag=6)
+    out = rgs.rgs_qr(W, sketch.SRHT(n, k, seed=42), precision="fp32")
+    assert out["Q"].dtype == np.float32
+    assert metrics.backward_error(W.astype(np.float32), out["Q"], out["R"]) <= 1e-5
+    assert metrics.delta_2(out["S"]) <= 1e-4
+
+
+def test_breakdown_duplicate_column():
+    n, m = 512, 6
+    W = _wellcond(n, m, tag=7)
+    W[:, 3] = W[:, 1]
+    with pytest.raises(rgs.Breakdown) as e:
+        rgs.rgs_qr(W, sketch.Gaussian(n, 32, seed=1))
+    assert e.value.column == 3 and not e.value.nonfinite
+
+
+def test_breakdown_nonfinite():
+    n, m = 512, 6
+    W = _wellcond(n, m, tag=8)
+    W[10, 2] = np.nan
+    with pytest.raises(rgs.Breakdown) as e:
+        rgs.rgs_qr(W, sketch.SRHT(n, 32, seed=1))
+    assert e.value.column == 2 and e.value.nonfinite
+
+
+def test_k_smaller_than_m_is_rejected():
+    with pytest.raises(ValueError):
+        rgs.rgs_qr(np.ones((64, 10)), sketch.Gaussian(64, 8))
+
+
+def test_step_function_matches_loop():
+    n, m, k = 1024, 10, 64
+    W = _wellcond(n, m, tag=9)
+    th = sketch.SRHT(n, k, seed=2)
+    out = rgs.rgs_qr(W, th)
+    st = rgs.rgs_step(out["Q"][:, :6], out["S"][:, :6], W[:, 6], th)
+    np.testing.assert_allclose(st["r"], out["R"][:6, 6], rtol=1e-14)
+    np.testing.assert_allclose(st["rii"], out["R"][6, 6], rtol=1e-14)
+    np.testing.assert_allclose(st["q"], out["Q"][:, 6], rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.slow
+def test_sec51_qualitative_ordering():
+    # Sec. 5.1 at reduced n: float32 CGS breaks down badly, MGS degrades,
+    # multi-precision RGS keeps cond(Q) close to 1 (and below MGS's).
+    n, m, k = 1 << 13, 160, 1500
+    W = synth.f_mu_matrix(n, m)
+    Qc, _ = rgs.cgs(W, np.float32)
+    Qm, _ = rgs.mgs(W, np.float32)
+    out = rgs.rgs_qr(W, sketch.SRHT(n, k, seed=42), precision="fp32")
+    c_cgs, c_mgs, c_rgs = metrics.cond(Qc), metrics.cond(Qm), metrics.cond(out["Q"])
+    assert c_rgs < 3.0
+    assert c_mgs > c_rgs
+    assert c_cgs > 100 * c_rgs
+    assert metrics.backward_error(W.astype(np.float32), out["Q"], out["R"]) < 1e-5
+    # cond(S) estimates cond(Q) (Sec. 5.1, third panel)
+    assert abs(math.log(metrics.cond(out["S"])) - math.log(c_rgs)) < math.log(2.0)

@@ -1,0 +1,130 @@
+"""Pins of the oracle's sketching operators (Sec. 2.1).
+
+Each check is tied to something outside the code under test: the textbook
+Sylvester-Hadamard matrix (scipy), the exact column norms of an SRHT, the
+isometry of a fully sampled SRHT, the N(0, 1/k) law of the Gaussian entries,
+the uniformity of a Fisher-Yates draw, and the definition of an
+epsilon-embedding (Sec. 2.1, Definition 2.1) checked by brute force.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+from oracle import sketch, metrics
+
+
+@pytest.mark.parametrize("s", [1, 2, 4, 8, 64, 1024, 4096])
+def test_fwht_matches_sylvester_hadamard(s):
+    g = np.random.Generator(np.random.PCG64(s))
+    x = g.integers(-1000, 1000, size=(s, 3)).astype(np.float64)
+    ref = scipy.linalg.hadamard(s).astype(np.float64) @ x if s > 1 else x
+    assert np.array_equal(sketch.fwht(x), ref)          # exact on integers
+
+
+@pytest.mark.parametrize("n,k", [(1000, 64), (1024, 1024), (37, 16), (4096, 300)])
+def test_srht_frobenius_norm_is_exactly_n(n, k):
+    th = sketch.SRHT(n, k, seed=3)
+    T = th.materialize()
+    # every entry is +-1/sqrt(k): each column has squared norm exactly 1
+    assert np.allclose(np.abs(T) * math.sqrt(k), 1.0, atol=0, rtol=1e-15)
+    assert abs((T ** 2).sum() - n) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("n,k", [(1000, 64), (37, 16), (4096, 300)])
+def test_srht_apply_equals_dense_definition(n, k):
+    th = sketch.SRHT(n, k, seed=11, sketch_id=1, instance=4)
+    s = th.s
+    H = scipy.linalg.hadamard(s).astype(np.float64)
+    dense = H[th.rows][:, :n] * th.d[None, :] / math.sqrt(k)
+    assert np.array_equal(dense, th.materialize())
+    X = np.random.Generator(np.random.PCG64(1)).standard_normal((n, 5))
+    np.testing.assert_allclose(th.apply(X), dense @ X, rtol=1e-12, atol=1e-12)
+
+
+def test_srht_full_sample_is_an_isometry():
+    n = 200                       # s = 256
+    th = sketch.SRHT(n, 256, seed=5)
+    T = th.materialize()
+    np.testing.assert_allclose(T.T @ T, np.eye(n) * 256 / 256, atol=1e-12)
+
+
+def test_srht_rows_distinct_and_in_range():
+    for s, k in [(8, 8), (1024, 1000), (1 << 22, 2048)]:
+        rows = sketch.srht_rows(s, k, 42, 0, 0)
+        assert rows.min() >= 0 and rows.max() < s
+        assert np.unique(rows).size == k
+    assert np.array_equal(np.sort(sketch.srht_rows(16, 16, 1, 0, 0)), np.arange(16))
+
+
+def test_fisher_yates_draw_is_uniform_over_ordered_pairs():
+    # s = 5, k = 2: 20 ordered pairs, each with probability 1/20
+    counts = {}
+    trials = 8000
+    for seed in range(trials):
+        r = tuple(sketch.srht_rows(5, 2, seed, 0, 0))
+        counts[r] = counts.get(r, 0) + 1
+    assert len(counts) == 20
+    obs = np.array(list(counts.values()))
+    chi2 = ((obs - trials / 20) ** 2 / (trials / 20)).sum()
+    assert chi2 < scipy.stats.chi2.ppf(0.999, 19)
+
+
+def test_srht_signs_balanced():
+    d = sketch.srht_signs(1 << 16, 42, 0, 0)
+    assert set(np.unique(d)) == {-1.0, 1.0}
+    assert abs(d.mean()) < 5 * (1 << 16) ** -0.5
+
+
+def test_gaussian_entries_are_n01_over_k():
+    k = 64
+    T = sketch.gaussian_block(k, 42, 0, 0, 0, k, 0, 4096) * math.sqrt(k)
+    z = T.reshape(-1)
+    assert abs(z.mean()) < 5 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / z.size)
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+
+
+def test_gaussian_block_views_agree():
+    k = 16
+    full = sketch.gaussian_block(k, 9, 1, 2, 0, k, 0, 103)
+    part = sketch.gaussian_block(k, 9, 1, 2, 3, 11, 5, 94)
+    assert np.array_equal(full[3:11, 5:94], part)
+    th = sketch.Gaussian(103, k, seed=9, sketch_id=1, instance=2, cache_limit=0)
+    X = np.random.Generator(np.random.PCG64(2)).standard_normal((103, 3))
+    np.testing.assert_allclose(th.apply(X), full @ X, rtol=1e-13, atol=1e-13)
+
+
+def test_gaussian_expected_gram_is_identity():
+    # E[Theta^T Theta] = I: Monte-Carlo over sketch ids
+    n, k, reps = 8, 32, 400
+    acc = np.zeros((n, n))
+    for t in range(reps):
+        T = sketch.gaussian_block(k, 42, 10 + t, 0, 0, k, 0, n)
+        acc += T.T @ T
+    acc /= reps
+    # entries of the mean have sd about sqrt(1/(k reps)) off the diagonal
+    assert np.max(np.abs(acc - np.eye(n))) < 6 * math.sqrt(2.0 / (k * reps))
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+def test_omega_equals_bruteforce_embedding_distortion(kind):
+    # Definition 2.1: omega is the smallest eps with
+    # |<x,y> - <Theta x, Theta y>| <= eps ||x|| ||y|| for all x, y in range(V).
+    n, d, k = 48, 2, 24
+    g = np.random.Generator(np.random.PCG64(3))
+    V, _ = np.linalg.qr(g.standard_normal((n, d)))
+    th = sketch.make(kind, n, k, seed=8)
+    TV = th.apply(V)
+    ang = np.linspace(0.0, np.pi, 721)
+    A = np.stack([np.cos(ang), np.sin(ang)], axis=1)             # unit coefficient vectors
+    X = A @ V.T                                                  # unit vectors in range(V)
+    TX = A @ TV.T
+    dev = np.abs(X @ X.T - TX @ TX.T)
+    brute = dev.max()
+    om = metrics.omega(TV, V)
+    assert brute <= om * (1 + 1e-12)
+    assert brute >= om * (1 - 1e-4)

@@ -1,0 +1,120 @@
+"""Pins of the oracle's stencil mat-vec and of Algorithm 3 / randomized GMRES.
+
+* The stencil equals an independently assembled sparse matrix (Kronecker
+  sums of 1-D shift operators) and, with no convection, has the discrete
+  sine modes as eigenvectors with the textbook eigenvalues.
+* With Theta = I and no restart, randomized GMRES is GMRES: after j steps its
+  iterate minimises ||b - A x|| over the Krylov space K_j(A, b), which is
+  checked against a brute-force least-squares solve on that space.
+* The residual estimate |g_i| is the sketched residual ||Theta (b - A x)||
+  (the identity of Sec. 4.2) -- checked against the explicit residual.
+* A = I is a lucky breakdown after one step.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import stencil, gmres, sketch
+
+
+def _assembled(dims, coeffs):
+    nx, ny, nz = dims
+    c0, cxm, cxp, cym, cyp, czm, czp = coeffs
+
+    def shift(n, off):
+        return sp.diags([np.ones(n - abs(off))], [off], shape=(n, n))
+
+    Ix, Iy, Iz = sp.identity(nx), sp.identity(ny), sp.identity(nz)
+    A = c0 * sp.kron(Iz, sp.kron(Iy, Ix))
+    A = A + cxm * sp.kron(Iz, sp.kron(Iy, shift(nx, -1))) + cxp * sp.kron(Iz, sp.kron(Iy, shift(nx, 1)))
+    A = A + cym * sp.kron(Iz, sp.kron(shift(ny, -1), Ix)) + cyp * sp.kron(Iz, sp.kron(shift(ny, 1), Ix))
+    A = A + czm * sp.kron(shift(nz, -1), sp.kron(Iy, Ix)) + czp * sp.kron(shift(nz, 1), sp.kron(Iy, Ix))
+    return A.tocsr()
+
+
+def test_stencil_matches_assembled_matrix():
+    dims = (5, 4, 3)
+    coeffs = (6.1, -1.2, -0.8, -1.05, -0.95, -1.3, -0.7)
+    A = _assembled(dims, coeffs)
+    u = np.random.Generator(np.random.PCG64(0)).standard_normal(60)
+    np.testing.assert_allclose(stencil.apply(u, dims, coeffs), A @ u, rtol=1e-14, atol=1e-14)
+
+
+def test_poisson_sine_modes_are_eigenvectors():
+    N = 9
+    dims, coeffs = synth.convdiff_coeffs(N, 0.0)
+    h = 1.0 / (N + 1)
+    g = np.arange(1, N + 1) * h
+    a, b, c = 2, 5, 7
+    u = (np.sin(c * np.pi * g)[:, None, None] * np.sin(b * np.pi * g)[None, :, None]
+         * np.sin(a * np.pi * g)[None, None, :]).reshape(-1)
+    lam = 6 - 2 * (math.cos(a * np.pi * h) + math.cos(b * np.pi * h) + math.cos(c * np.pi * h))
+    np.testing.assert_allclose(stencil.apply(u, dims, coeffs), lam * u, atol=1e-13)
+
+
+def _krylov_min_residual(A, b, j):
+    K = np.empty((b.size, j))
+    v = b.copy()
+    for t in range(j):
+        K[:, t] = v
+        v = A @ v
+    U, _ = np.linalg.qr(K)                      # orthonormal basis of K_j
+    z, *_ = np.linalg.lstsq(A @ U, b, rcond=None)
+    return U @ z
+
+
+def test_identity_sketch_rgmres_is_gmres():
+    N, Pe = 4, 20.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    A = _assembled(dims, coeffs).toarray()
+    n = A.shape[0]
+    b = synth.rhs(n, tag=1)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    for j in (1, 3, 6, 10):
+        out = gmres.rgmres(applyA, b, lambda c: sketch.Identity(n), restart=j, tol=1e-30,
+                           max_iters=j, max_cycles=1)
+        xref = _krylov_min_residual(A, b, j)
+        np.testing.assert_allclose(out["x"], xref, rtol=1e-9, atol=1e-9 * np.abs(xref).max())
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+def test_residual_estimate_is_sketched_residual(kind):
+    N, Pe = 6, 30.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=2)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    th = sketch.make(kind, n, 64, seed=42, sketch_id=2)
+    out = gmres.rgmres(applyA, b, lambda c: th, restart=12, tol=1e-30, max_iters=12, max_cycles=1)
+    est = out["hist"][-1] * np.linalg.norm(b)
+    true_sk = np.linalg.norm(th.apply(b - applyA(out["x"], np.float64)))
+    assert abs(est - true_sk) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_identity_operator_lucky_breakdown():
+    n = 64
+    b = synth.rhs(n, tag=3)
+    out = gmres.rgmres(lambda u, dt: np.asarray(u, dtype=dt).copy(), b,
+                       lambda c: sketch.Gaussian(n, 32, seed=1, sketch_id=2 + c),
+                       restart=10, tol=1e-12)
+    assert out["iters"] == 1 and out["converged"]
+    assert out["true_relres"] <= 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_convdiff_converges_restarted(precision):
+    N, Pe = 10, 50.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=4)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    out = gmres.rgmres(applyA, b, lambda c: sketch.Gaussian(n, 80, seed=42, sketch_id=2 + c),
+                       restart=20, tol=1e-6, precision=precision)
+    assert out["converged"] and out["true_relres"] <= 1e-6
+    r = b - applyA(out["x"], np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
+    assert out["cycles"] >= 2                  # restarts really happened
