@@ -1,0 +1,189 @@
+/*
+ * rgs.h -- C ABI of librgs: randomized Gram-Schmidt (RGS) and randomized
+ * GMRES on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: O. Balabanov, L. Grigori, "Randomized Gram-Schmidt process with
+ * application to GMRES", arXiv:2011.05090.
+ *   - RGS column step: Algorithm 2 (Sec. 2.3).
+ *   - RGS-Arnoldi: Algorithm 3 (Sec. 4.1); randomized GMRES: Sec. 4.2.
+ *   - Sketching operators (Gaussian, P-SRHT) and seeded generation: Sec. 2.1.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major with an explicit leading dimension (in
+ *     elements).  Vectors are contiguous.
+ *   - Every array argument is DEVICE memory owned by the caller, unless the
+ *     parameter comment says "host".  The library never frees caller memory;
+ *     its own scratch lives in the handle and is grown on demand.
+ *   - The element type of W, Q and X is fixed by the precision field:
+ *       RGS_P_FP64       -> double
+ *       RGS_P_FP32_LS64  -> float   (step 3 in fp32; sketches, least
+ *                                    squares and normalisation in fp64)
+ *     R, S, P, b, x and histories are always double.
+ *   - Work is ordered on the handle's stream.  Calls that return a report
+ *     synchronise that stream before returning.
+ *   - Errors are negative rgs_status codes; nothing is thrown across the ABI.
+ *     Argument errors are detected before any device work is enqueued.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ */
+#ifndef RGS_H
+#define RGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RGS_ABI_VERSION 1
+
+typedef struct rgs_handle rgs_handle;  /* opaque */
+typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+    RGS_OK = 0,
+    RGS_EINVAL = -1,      /* bad argument (sizes, pointers, leading dims, enums) */
+    RGS_ENOMEM = -2,      /* device scratch allocation failed */
+    RGS_EDEVICE = -3,     /* a HIP runtime call or a kernel launch failed */
+    RGS_EBREAKDOWN = -4,  /* r_ii = 0 or r_ii <= 2^-50 ||p_i||: w_i numerically in
+                             span(Q_{i-1}); columns before report.failed_column are valid */
+    RGS_ENONFINITE = -5,  /* a sketch p_i or s'_i is not finite (NaN/Inf in the input) */
+    RGS_ENOCONV = -6      /* GMRES hit max_iters; x holds the last iterate */
+} rgs_status;
+
+typedef enum {
+    RGS_SKETCH_GAUSSIAN = 0, /* entries N(0,1/k), Philox4x32-10 + Box-Muller, generated on the fly */
+    RGS_SKETCH_SRHT = 1,     /* P-SRHT: k^-1/2 Rows H_s D on the zero-padded input */
+    RGS_SKETCH_IDENTITY = 2  /* test sketch: k = n, Theta = I */
+} rgs_sketch;
+
+typedef enum {
+    RGS_P_FP64 = 0,       /* u_crs = u_fine = fp64 */
+    RGS_P_FP32_LS64 = 1   /* multi-precision model: u_crs = fp32, u_fine = fp64 */
+} rgs_precision;
+
+/* Flags for rgs_qr_desc.flags / rgs_gmres_desc.flags */
+#define RGS_FLAG_DIAGNOSTICS 1u  /* compute step 8 of Algorithm 2 (Delta_m, tilde Delta_m) */
+#define RGS_FLAG_TIME_KERNELS 2u /* time every projection+sketch launch with events */
+
+/* Describes one RGS factorisation and its sketch Theta (k x n).
+ * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
+ * regenerated on demand and never stored (Sec. 2.1, seeded generation). */
+typedef struct {
+    int64_t n;           /* rows of W (high dimension), n >= 1 */
+    int64_t m;           /* columns of W, 1 <= m <= k */
+    int64_t k;           /* sketch rows; k <= 2^ceil(log2 n) for SRHT, k = n for IDENTITY */
+    uint64_t seed;       /* Philox key */
+    uint32_t sketch_id;  /* counter word 2: independent sketches from one seed */
+    uint32_t instance;   /* counter word 3 */
+    int32_t sketch;      /* rgs_sketch */
+    int32_t prec;        /* rgs_precision */
+    uint32_t flags;      /* RGS_FLAG_* */
+    uint32_t reserved;   /* must be 0 */
+} rgs_qr_desc;
+
+/* Constant-coefficient 7-point operator on an nx*ny*nz box, Dirichlet 0,
+ * lexicographic order with x fastest (l = x + nx*(y + ny*z)):
+ * (A u)_l = c0 u_l + cxm u_{x-1} + cxp u_{x+1} + cym u_{y-1} + cyp u_{y+1}
+ *                  + czm u_{z-1} + czp u_{z+1}.  It is the Arnoldi mat-vec
+ * w_i = A q_{i-1} of Algorithm 3 (Sec. 4.1). */
+typedef struct {
+    int64_t nx, ny, nz;
+    double c0, cxm, cxp, cym, cyp, czm, czp;
+} rgs_stencil7;
+
+/* Restarted randomized GMRES (Sec. 4.2). */
+typedef struct {
+    int64_t restart;    /* inner steps per cycle (basis of restart+1 vectors), 1 <= restart < k */
+    int64_t max_iters;  /* cap on the total number of inner steps (mat-vecs) */
+    int64_t k;          /* sketch rows */
+    double tol;         /* stop when ||b - A x||_2 / ||b||_2 <= tol (fp64) */
+    uint64_t seed;
+    int32_t sketch;     /* rgs_sketch (GAUSSIAN or SRHT) */
+    int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
+    int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
+    uint32_t flags;
+} rgs_gmres_desc;
+
+typedef struct {
+    int64_t failed_column;  /* first invalid column on BREAKDOWN/NONFINITE, else -1 */
+    int64_t iters;          /* GMRES: total inner steps; QR: m on success */
+    int64_t cycles;         /* GMRES restart cycles */
+    double delta_F;         /* ||I - S^T S||_F      (step 8; NaN unless requested) */
+    double delta_tilde_F;   /* ||P - S R||_F/||P||_F (step 8; NaN unless requested) */
+    double true_relres;     /* GMRES: ||b - A x||_2 / ||b||_2 at exit (fp64) */
+    double seconds;         /* host wall time of the call, including the final sync */
+    double proj_kernel_ms;  /* with RGS_FLAG_TIME_KERNELS: summed duration of the
+                               projection+sketch launches, else 0 */
+    int64_t proj_launches;  /* number of projection+sketch launches */
+} rgs_report;
+
+/* Library version of this header (RGS_ABI_VERSION). */
+int rgs_abi_version(void);
+
+/* Static English description of a status code.  Never NULL. */
+const char *rgs_status_string(rgs_status s);
+
+/* Create a handle bound to HIP device `device` and stream `stream`.
+ * *h receives the handle.  EINVAL: h == NULL or bad device; EDEVICE: HIP
+ * failure.  The handle owns all scratch memory. */
+rgs_status rgs_create(rgs_handle **h, int device, rgs_stream stream);
+
+/* Release the handle and its scratch (synchronises its stream first). */
+rgs_status rgs_destroy(rgs_handle *h);
+
+/* Re-bind the handle to another stream of the same device. */
+rgs_status rgs_set_stream(rgs_handle *h, rgs_stream stream);
+
+/* RGS QR factorisation, Algorithm 2 (Sec. 2.3), W = Q R.
+ *   W  [n x m, ldw >= n] input, element type per desc->prec.
+ *   Q  [n x m, ldq >= n] output, same element type; Q = W R^-1 is orthonormal
+ *      in the sketched inner product <Theta ., Theta .> (not in l2).
+ *   R  [m x m, ldr >= m] output, upper triangular, r_ii > 0 (strict lower part
+ *      is zeroed).
+ *   S  [k x m, lds >= k] output, S = Theta Q as computed in steps 4-6.
+ *   rep (host, may be NULL) receives the report.
+ * Step 2 uses a Householder QR of S kept in compact-WY form (Sec. 2.3; the
+ * solver of the experiments, Sec. 5).  W and Q must not overlap.
+ * Returns OK, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN or ENONFINITE. */
+rgs_status rgs_qr(rgs_handle *h, const rgs_qr_desc *desc,
+                  const void *W, int64_t ldw, void *Q, int64_t ldq,
+                  double *R, int64_t ldr, double *S, int64_t lds, rgs_report *rep);
+
+/* Y = Theta X for ncols columns (the sketch of steps 1 and 4 of Algorithm 2).
+ *   X [n x ncols, ldx >= n], element type per desc->prec; Y [k x ncols, ldy >= k].
+ * desc->m is ignored.  Synchronous.  Returns OK, EINVAL, ENOMEM or EDEVICE. */
+rgs_status rgs_sketch_apply(rgs_handle *h, const rgs_qr_desc *desc, const void *X,
+                            int64_t ldx, int64_t ncols, double *Y, int64_t ldy);
+
+/* Dense block Theta[j0:j1, l0:l1] (0-based, half-open) into out
+ * [(j1-j0) x (l1-l0), ldo >= j1-j0], as the device generates it in the working
+ * precision of desc->prec (fp32 entries are widened).  Test hook for the
+ * on-the-fly generation of Sec. 2.1.  Synchronous. */
+rgs_status rgs_sketch_materialize(rgs_handle *h, const rgs_qr_desc *desc, int64_t j0,
+                                  int64_t j1, int64_t l0, int64_t l1, double *out,
+                                  int64_t ldo);
+
+/* Restarted randomized GMRES (Sec. 4.2) on the 7-point operator A, built on
+ * RGS-Arnoldi (Algorithm 3): H = R(1:i, 2:i), Givens rotations in fp64, x kept
+ * in fp64, x0 = 0.
+ *   b  [n] input (device, double), n = nx*ny*nz.
+ *   x  [n] output (device, double).
+ *   res_hist (host, may be NULL) receives |g_i|/||b||_2 after each inner step,
+ *      up to hist_cap entries (the sketched residual ||Theta(b - A x_i)||, Sec. 4.2).
+ *   rep (host, may be NULL).
+ * Returns OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE or ENOCONV. */
+rgs_status rgs_gmres(rgs_handle *h, const rgs_stencil7 *A, const rgs_gmres_desc *desc,
+                     const double *b, double *x, double *res_hist, int64_t hist_cap,
+                     rgs_report *rep);
+
+/* w = A u for the 7-point operator (the mat-vec of Algorithm 3, step 3), in
+ * the working precision of `prec` (u, w: float for FP32_LS64, double for FP64).
+ * Test hook.  Synchronous. */
+rgs_status rgs_stencil_apply(rgs_handle *h, const rgs_stencil7 *A, int32_t prec,
+                             const void *u, void *w);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGS_H */

@@ -12,7 +12,8 @@ Gaussian (Sec. 2.1; entries N(0, 1/k)):
     theta[j, l] = z(j, l) / sqrt(k), where z comes from one Philox4x32-10
     call at counter (floor(l/4), j, sketch_id, instance), key = seed, and
     Box-Muller on the word pairs (x0, x1) -> l%4 in {0, 1}, (x2, x3) ->
-    l%4 in {2, 3}:  u1 = ((x_a >> 8) + 1/2) * 2**-24,  u2 = (x_b >> 8) * 2**-24,
+    l%4 in {2, 3}:  u1 = ((x_a >> 9) + 1/2) * 2**-23,  u2 = (x_b >> 8) * 2**-24
+    (both exactly representable in float32 and fp64),
     rho = sqrt(-2 ln u1),  z_a = rho cos(2 pi u2),  z_b = rho sin(2 pi u2).
 
 P-SRHT (Sec. 2.1): with s = 2**ceil(log2 n), n <= s < 2n,
@@ -55,9 +56,9 @@ def gaussian_block(k, seed, sketch_id, instance, j0, j1, l0, l1):
     ctr[..., 2] = sketch_id
     ctr[..., 3] = instance
     x = philox4x32(ctr, key).astype(np.uint64)            # (J, B, 4)
-    u1a = ((x[..., 0] >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+    u1a = ((x[..., 0] >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
     u2a = (x[..., 1] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
-    u1b = ((x[..., 2] >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+    u1b = ((x[..., 2] >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
     u2b = (x[..., 3] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
     ra = np.sqrt(-2.0 * np.log(u1a))
     rb = np.sqrt(-2.0 * np.log(u1b))

@@ -1,0 +1,254 @@
+"""Python binding of librgs (randomized Gram-Schmidt / randomized GMRES on MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``librgs.so`` (built in-tree by ``python -m paper_2011_05090_amd.build``).  The
+functions carry the names of the C entry points declared in ``include/rgs.h``
+and take torch tensors for device memory; torch is used for allocation and
+streams, nothing else.  If the library is missing, importing works but every
+call raises -- there is no fallback path.
+
+Matrices are column-major: an n x m matrix is a tensor of shape (n, m) with
+stride(0) == 1 (``colmajor`` allocates one).
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librgs.so")
+
+RGS_OK, RGS_EINVAL, RGS_ENOMEM, RGS_EDEVICE, RGS_EBREAKDOWN, RGS_ENONFINITE, RGS_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+SKETCH = {"gaussian": 0, "srht": 1, "identity": 2}
+PREC = {"fp64": 0, "fp32": 1}
+FLAG_DIAGNOSTICS = 1
+FLAG_TIME_KERNELS = 2
+
+
+class RgsError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__("%s failed: %s (%d)" % (where, status_string(status), status))
+        self.status = status
+
+
+class QrDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("sketch_id", ctypes.c_uint32), ("instance", ctypes.c_uint32),
+                ("sketch", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Stencil7(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("c0", ctypes.c_double), ("cxm", ctypes.c_double), ("cxp", ctypes.c_double),
+                ("cym", ctypes.c_double), ("cyp", ctypes.c_double), ("czm", ctypes.c_double),
+                ("czp", ctypes.c_double)]
+
+
+class GmresDesc(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int64), ("max_iters", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("sketch", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("reuse_theta", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("failed_column", ctypes.c_int64), ("iters", ctypes.c_int64), ("cycles", ctypes.c_int64),
+                ("delta_F", ctypes.c_double), ("delta_tilde_F", ctypes.c_double),
+                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("proj_kernel_ms", ctypes.c_double), ("proj_launches", ctypes.c_int64)]
+
+    status = RGS_OK
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["status"] = self.status
+        return d
+
+
+# C entry points declared in include/rgs.h: name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_DESCP = ctypes.POINTER(QrDesc)
+SIGNATURES = {
+    "rgs_abi_version": (ctypes.c_int, []),
+    "rgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rgs_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "rgs_destroy": (ctypes.c_int, [_P]),
+    "rgs_set_stream": (ctypes.c_int, [_P, _P]),
+    "rgs_qr": (ctypes.c_int, [_P, _DESCP, _P, _I64, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(Report)]),
+    "rgs_sketch_apply": (ctypes.c_int, [_P, _DESCP, _P, _I64, _I64, _P, _I64]),
+    "rgs_sketch_materialize": (ctypes.c_int, [_P, _DESCP, _I64, _I64, _I64, _I64, _P, _I64]),
+    "rgs_gmres": (ctypes.c_int, [_P, ctypes.POINTER(Stencil7), ctypes.POINTER(GmresDesc), _P, _P, _P, _I64,
+                                 ctypes.POINTER(Report)]),
+    "rgs_stencil_apply": (ctypes.c_int, [_P, ctypes.POINTER(Stencil7), ctypes.c_int32, _P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librgs.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librgs.so is not built (run: python -m paper_2011_05090_amd.build); "
+                               "there is no fallback implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    try:
+        return lib().rgs_status_string(int(status)).decode()
+    except Exception:   # library unavailable: still produce a message
+        return "status %d" % status
+
+
+def rgs_abi_version():
+    return lib().rgs_abi_version()
+
+
+def _check(status, where, allow=()):
+    if status != RGS_OK and status not in allow:
+        raise RgsError(status, where)
+    return status
+
+
+def colmajor(n, m, dtype, device="cuda"):
+    """Uninitialised column-major n x m tensor (shape (n, m), stride (1, n))."""
+    import torch
+    return torch.empty((m, n), dtype=dtype, device=device).t()
+
+
+def _ld(t, rows):
+    if t.dim() == 1:
+        return max(rows, 1)
+    if t.stride(0) != 1 and t.shape[0] > 1:
+        raise ValueError("matrix arguments must be column-major (stride(0) == 1)")
+    return max(t.stride(1), rows) if t.shape[1] > 1 else max(rows, 1)
+
+
+def _dev(t, name, dtype=None):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _torch_dtype(prec):
+    import torch
+    return torch.float64 if PREC[prec] == 0 else torch.float32
+
+
+class Handle:
+    """rgs_create / rgs_destroy.  Bound to a device and a stream (default: torch's current)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().rgs_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream.cuda_stream)), "rgs_create")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().rgs_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "rgs_set_stream")
+
+    def close(self):
+        if self._h:
+            lib().rgs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=0, flags=0):
+    return QrDesc(n=n, m=m, k=k, seed=seed, sketch_id=sketch_id, instance=instance,
+                  sketch=SKETCH[sketch], prec=PREC[prec], flags=flags, reserved=0)
+
+
+def rgs_qr(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
+    """Algorithm 2 on W -> Q, R, S (all preallocated device tensors).  Returns the Report."""
+    import torch
+    dt = torch.float64 if desc.prec == 0 else torch.float32
+    n, m, k = desc.n, desc.m, desc.k
+    if tuple(W.shape) != (n, m) or tuple(Q.shape) != (n, m) or tuple(R.shape) != (m, m) or tuple(S.shape) != (k, m):
+        raise ValueError("shape mismatch")
+    rep = Report()
+    st = lib().rgs_qr(handle.ptr, ctypes.byref(desc), _dev(W, "W", dt), _ld(W, n), _dev(Q, "Q", dt), _ld(Q, n),
+                      _dev(R, "R", torch.float64), _ld(R, m), _dev(S, "S", torch.float64), _ld(S, k),
+                      ctypes.byref(rep))
+    _check(st, "rgs_qr", allow)
+    rep.status = st
+    return rep
+
+
+def rgs_sketch_apply(handle, desc, X, Y):
+    """Y = Theta X (X: n x ncols column-major in the working precision; Y: k x ncols fp64)."""
+    import torch
+    dt = torch.float64 if desc.prec == 0 else torch.float32
+    Xm = X if X.dim() == 2 else X.reshape(-1, 1)
+    Ym = Y if Y.dim() == 2 else Y.reshape(-1, 1)
+    ncols = Xm.shape[1]
+    st = lib().rgs_sketch_apply(handle.ptr, ctypes.byref(desc), _dev(Xm, "X", dt), _ld(Xm, desc.n), ncols,
+                                _dev(Ym, "Y", torch.float64), _ld(Ym, desc.k))
+    _check(st, "rgs_sketch_apply")
+
+
+def rgs_sketch_materialize(handle, desc, j0, j1, l0, l1, out):
+    import torch
+    st = lib().rgs_sketch_materialize(handle.ptr, ctypes.byref(desc), j0, j1, l0, l1,
+                                      _dev(out, "out", torch.float64), _ld(out, j1 - j0))
+    _check(st, "rgs_sketch_materialize")
+
+
+def stencil7(dims, coeffs):
+    nx, ny, nz = dims
+    c0, cxm, cxp, cym, cyp, czm, czp = coeffs
+    return Stencil7(nx=nx, ny=ny, nz=nz, c0=c0, cxm=cxm, cxp=cxp, cym=cym, cyp=cyp, czm=czm, czp=czp)
+
+
+def gmres_desc(restart, k, tol, max_iters=100000, sketch="gaussian", prec="fp32", seed=42, reuse_theta=False,
+               flags=0):
+    return GmresDesc(restart=restart, max_iters=max_iters, k=k, tol=tol, seed=seed, sketch=SKETCH[sketch],
+                     prec=PREC[prec], reuse_theta=1 if reuse_theta else 0, flags=flags)
+
+
+def rgs_gmres(handle, A, desc, b, x, res_hist=None, allow=(RGS_ENOCONV,)):
+    """Randomized GMRES on the 7-point operator.  Returns (Report, history as a list)."""
+    import torch
+    n = A.nx * A.ny * A.nz
+    if b.numel() != n or x.numel() != n:
+        raise ValueError("b and x must have nx*ny*nz entries")
+    cap = 0 if res_hist is None else int(res_hist)
+    hist = (ctypes.c_double * max(cap, 1))()
+    rep = Report()
+    st = lib().rgs_gmres(handle.ptr, ctypes.byref(A), ctypes.byref(desc), _dev(b, "b", torch.float64),
+                         _dev(x, "x", torch.float64), hist if cap else None, cap, ctypes.byref(rep))
+    _check(st, "rgs_gmres", allow)
+    rep.status = st
+    used = min(cap, rep.iters)
+    return rep, [hist[i] for i in range(used)]
+
+
+def rgs_stencil_apply(handle, A, prec, u, w):
+    dt = _torch_dtype(prec)
+    st = lib().rgs_stencil_apply(handle.ptr, ctypes.byref(A), PREC[prec], _dev(u, "u", dt), _dev(w, "w", dt))
+    _check(st, "rgs_stencil_apply")

@@ -1,0 +1,450 @@
+// Host side of librgs: the C ABI declared in include/rgs.h.
+//
+// rgs_qr drives Algorithm 2 (Sec. 2.3 of Balabanov & Grigori) column by column
+// with no host synchronisation inside the loop: every step's scalars (r_ii,
+// 1/r_ii, the Householder tau/beta, the breakdown status) stay in device
+// memory and the host only enqueues launches on the handle's stream.  The
+// stream is synchronised once, at the end, to read the status word.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+#include "rgs.h"
+#include "rgs_device.hpp"
+#include "rgs_internal.hpp"
+
+using namespace rgs;
+
+struct rgs_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count) {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        const size_t at = off;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return at;
+    }
+};
+
+rgs_status ensure_arena(rgs_handle* h, size_t bytes) {
+    if (h->arena_bytes >= bytes) return RGS_OK;
+    if (h->arena) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return RGS_EDEVICE;
+        hipFree(h->arena);
+        h->arena = nullptr;
+        h->arena_bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return RGS_ENOMEM;
+    }
+    h->arena = static_cast<char*>(p);
+    h->arena_bytes = bytes;
+    return RGS_OK;
+}
+
+rgs_status ensure_events(rgs_handle* h, size_t count) {
+    while (h->events.size() < count) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return RGS_EDEVICE;
+        h->events.push_back(e);
+    }
+    return RGS_OK;
+}
+
+int64_t srht_order(int64_t n) {
+    int64_t s = 1;
+    while (s < n) s <<= 1;
+    return s;
+}
+
+// k distinct rows of [0, s) by a partial Fisher-Yates shuffle; draw t uses
+// Philox(t, 0xFFFFFFFE, sketch_id, instance) and swaps position t with
+// t + floor((x1 2^32 + x0) (s - t) / 2^64).  Rows are kept in draw order.
+void srht_rows_host(int64_t s, int k, const SketchArgs& sk, std::vector<int>& rows) {
+    std::unordered_map<uint64_t, uint64_t> perm;
+    perm.reserve(2 * (size_t)k + 1);
+    rows.resize(k);
+    for (int t = 0; t < k; ++t) {
+        uint32_t x[4];
+        philox4x32_10((uint32_t)t, kTagRows, sk.sid, sk.inst, sk.k0, sk.k1, x);
+        const uint64_t r64 = ((uint64_t)x[1] << 32) | x[0];
+        const uint64_t span = (uint64_t)(s - t);
+        const uint64_t off = (uint64_t)(((unsigned __int128)r64 * span) >> 64);
+        const uint64_t idx = (uint64_t)t + off;
+        auto it_t = perm.find((uint64_t)t);
+        auto it_i = perm.find(idx);
+        const uint64_t at = it_t == perm.end() ? (uint64_t)t : it_t->second;
+        const uint64_t ai = it_i == perm.end() ? idx : it_i->second;
+        perm[(uint64_t)t] = ai;
+        perm[idx] = at;
+        rows[t] = (int)ai;
+    }
+}
+
+SketchArgs make_sketch(int sketch, int64_t k, uint64_t seed, uint32_t sid, uint32_t inst) {
+    SketchArgs sk{};
+    sk.sketch = sketch;
+    sk.k = (int)k;
+    sk.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    sk.k1 = (uint32_t)(seed >> 32);
+    sk.sid = sid;
+    sk.inst = inst;
+    return sk;
+}
+
+bool valid_desc(const rgs_qr_desc* d, bool need_m) {
+    if (!d) return false;
+    if (d->n < 1 || d->k < 1) return false;
+    if (need_m && (d->m < 1 || d->m > d->k)) return false;
+    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64) return false;
+    if (d->reserved != 0) return false;
+    switch (d->sketch) {
+        case RGS_SKETCH_GAUSSIAN:
+            if (d->k > (int64_t)kKptMax * kWG) return false;
+            if (d->n > ((int64_t)1 << 34)) return false;   // counter word 0 holds l/4
+            break;
+        case RGS_SKETCH_SRHT:
+            if (d->k > (int64_t)kKptMax * kWG) return false;
+            if (d->k > srht_order(d->n)) return false;
+            if (d->n > ((int64_t)1 << 31)) return false;
+            break;
+        case RGS_SKETCH_IDENTITY:
+            if (d->k != d->n) return false;
+            if (d->n > ((int64_t)1 << 24)) return false;
+            break;
+        default:
+            return false;
+    }
+    return true;
+}
+
+// Prepares the sketch tables (SRHT sign bits, sampled rows) in `sk`.
+rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* signs_dev, int* rows_dev) {
+    if (sk.sketch != SK_SRHT) return RGS_OK;
+    const int64_t nwords = (n + 31) / 32;
+    if (!launch_srht_signs(h->stream, signs_dev, nwords, sk)) return RGS_EDEVICE;
+    std::vector<int> rows;
+    srht_rows_host(srht_order(n), sk.k, sk, rows);
+    if (hipMemcpyAsync(rows_dev, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess)
+        return RGS_EDEVICE;
+    // rows lives on the host stack frame: wait for the copy before returning
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return RGS_EDEVICE;
+    sk.signs = signs_dev;
+    sk.rows = rows_dev;
+    return RGS_OK;
+}
+
+// Layout of the scratch arena for one factorisation.
+struct QrPlan {
+    size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2;
+    size_t rr, invr, pnorm, tau, beta, status, coef, diag;
+    size_t total;
+    int G_P, cc;
+    int64_t nblk;
+};
+
+QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
+    QrPlan p{};
+    Carver c;
+    p.nblk = (n + kBlock - 1) / kBlock;
+    const int64_t nsl = (k + kSlice - 1) / kSlice;
+    p.G_P = (int)std::min<int64_t>(p.nblk, 64);
+    const size_t per_col = (size_t)p.G_P * k * tsize;
+    p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
+    p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
+    p.rows = c.take<int>(k);
+    p.part_proj = c.take<char>((sketch == SK_IDENT ? (size_t)n : (size_t)p.nblk * k) * tsize);
+    p.part_P = c.take<char>(per_col * p.cc);
+    p.P = c.take<double>(k * m);
+    p.Vc = c.take<double>(k * m);
+    p.Vr = c.take<double>(k * m);
+    p.Wc = c.take<double>(k * m);
+    p.Wr = c.take<double>(k * m);
+    p.X = c.take<double>(m * m);
+    p.sp = c.take<double>(k);
+    p.u = c.take<double>(k);
+    p.v = c.take<double>(k);
+    p.uh = c.take<double>(m);
+    p.pd = c.take<double>(nsl * (m + 1));
+    p.pd2 = c.take<double>(nsl);
+    p.rr = c.take<double>(m);
+    p.invr = c.take<double>(m);
+    p.pnorm = c.take<double>(m);
+    p.tau = c.take<double>(m);
+    p.beta = c.take<double>(m);
+    p.status = c.take<int>(4);
+    p.coef = c.take<char>(m * tsize);
+    p.diag = c.take<double>(3 * m);
+    p.total = c.off + kAlign;
+    return p;
+}
+
+template <typename T>
+rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const T* X, int64_t ldx, int64_t n, int64_t ncols,
+                         int G, int cc, T* part, double* out, int64_t ldo) {
+    const double scale = sk.sketch == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)sk.k);
+    for (int64_t c0 = 0; c0 < ncols; c0 += cc) {
+        const int nc = (int)std::min<int64_t>(cc, ncols - c0);
+        if (sk.sketch == SK_IDENT) {
+            // Theta = I: the sketch of a column is the column (reduce over G = 1 partial)
+            for (int c = 0; c < nc; ++c)
+                if (!launch_reduce<T>(h->stream, X + (c0 + c) * ldx, 1, (int)n, 1, 1.0, out + (c0 + c) * ldo, ldo))
+                    return RGS_EDEVICE;
+            continue;
+        }
+        if (!launch_sketch_cols<T, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
+        if (!launch_reduce<T>(h->stream, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
+    }
+    return RGS_OK;
+}
+
+template <typename T>
+rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, T* Q, int64_t ldq, double* R,
+                  int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = d->n, m = d->m, k = d->k;
+    const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+    const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T));
+    rgs_status st = ensure_arena(h, pl.total);
+    if (st != RGS_OK) return st;
+    char* A = h->arena;
+    SketchArgs sk = make_sketch(sk_kind, k, d->seed, d->sketch_id, d->instance);
+    st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
+    if (st != RGS_OK) return st;
+
+    SpaceArgs sa{};
+    sa.k = (int)k;
+    sa.mcap = (int)m;
+    sa.Vc = reinterpret_cast<double*>(A + pl.Vc);
+    sa.Vr = reinterpret_cast<double*>(A + pl.Vr);
+    sa.Wc = reinterpret_cast<double*>(A + pl.Wc);
+    sa.Wr = reinterpret_cast<double*>(A + pl.Wr);
+    sa.X = reinterpret_cast<double*>(A + pl.X);
+    sa.sp = reinterpret_cast<double*>(A + pl.sp);
+    sa.u = reinterpret_cast<double*>(A + pl.u);
+    sa.v = reinterpret_cast<double*>(A + pl.v);
+    sa.uh = reinterpret_cast<double*>(A + pl.uh);
+    sa.pd = reinterpret_cast<double*>(A + pl.pd);
+    sa.pd2 = reinterpret_cast<double*>(A + pl.pd2);
+    sa.rr = reinterpret_cast<double*>(A + pl.rr);
+    sa.invr = reinterpret_cast<double*>(A + pl.invr);
+    sa.pnorm = reinterpret_cast<double*>(A + pl.pnorm);
+    sa.tau = reinterpret_cast<double*>(A + pl.tau);
+    sa.beta = reinterpret_cast<double*>(A + pl.beta);
+    sa.status = reinterpret_cast<int*>(A + pl.status);
+    double* P = reinterpret_cast<double*>(A + pl.P);
+    T* coef = reinterpret_cast<T*>(A + pl.coef);
+    T* part = reinterpret_cast<T*>(A + pl.part_proj);
+    T* partP = reinterpret_cast<T*>(A + pl.part_P);
+
+    hipStream_t s = h->stream;
+    if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
+    if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
+
+    // Step 1 for every column at once: P = Theta W.
+    st = sketch_matrix<T>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
+    if (st != RGS_OK) return st;
+
+    const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;
+    if (timed && ensure_events(h, 2 * (size_t)m) != RGS_OK) return RGS_EDEVICE;
+    const bool vec_ok = (ldq % 4 == 0) && (ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) &&
+                        ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
+    const double scale = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)k);
+    const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nblk;
+
+    for (int64_t i = 0; i < m; ++i) {
+        const double* p_i = P + i * k;
+        if (i > 0 && !launch_ls<T>(s, sa, p_i, (int)i, R, ldr, coef)) return RGS_EDEVICE;
+        if (timed) (void)hipEventRecord(h->events[2 * i], s);
+        if (!launch_project<T, T>(s, W + i * ldw, Q, ldq, n, (int)i, coef, i > 0 ? sa.invr + (i - 1) : nullptr,
+                                  i > 0 ? 1 : 0, i > 0 ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
+            return RGS_EDEVICE;
+        if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
+        if (!launch_append<T>(s, sa, part, Gp, scale, i == 0 ? p_i : nullptr, (int)i, S, lds, R, ldr))
+            return RGS_EDEVICE;
+    }
+    if (!launch_scale_col<T>(s, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;
+
+    double* diag = reinterpret_cast<double*>(A + pl.diag);
+    const bool want_diag = (d->flags & RGS_FLAG_DIAGNOSTICS) != 0;
+    if (want_diag && !launch_diagnostics(s, P, k, S, lds, R, ldr, (int)k, (int)m, diag, diag + m))
+        return RGS_EDEVICE;
+
+    int status[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(status, sa.status, sizeof(status), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return RGS_EDEVICE;
+    std::vector<double> dh;
+    if (want_diag) {
+        dh.resize(3 * m);
+        if (hipMemcpyAsync(dh.data(), diag, 3 * m * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return RGS_EDEVICE;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+    const auto t1 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->failed_column = status[0] ? status[1] : -1;
+        rep->iters = status[0] ? status[1] : m;
+        rep->cycles = 0;
+        rep->delta_F = NAN;
+        rep->delta_tilde_F = NAN;
+        rep->true_relres = NAN;
+        if (want_diag && status[0] == 0) {
+            double g = 0, e = 0, p2 = 0;
+            for (int64_t c = 0; c < m; ++c) {
+                g += dh[c];
+                e += dh[m + 2 * c];
+                p2 += dh[m + 2 * c + 1];
+            }
+            rep->delta_F = std::sqrt(g);
+            rep->delta_tilde_F = std::sqrt(e / p2);
+        }
+        rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+        rep->proj_launches = m;
+        rep->proj_kernel_ms = 0.0;
+        if (timed) {
+            double tot = 0.0;
+            for (int64_t i = 0; i < m; ++i) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, h->events[2 * i], h->events[2 * i + 1]);
+                tot += ms;
+            }
+            rep->proj_kernel_ms = tot;
+        }
+    }
+    if (status[0] == kStatusBreakdown) return RGS_EBREAKDOWN;
+    if (status[0] == kStatusNonfinite) return RGS_ENONFINITE;
+    return RGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rgs_abi_version(void) { return RGS_ABI_VERSION; }
+
+const char* rgs_status_string(rgs_status s) {
+    switch (s) {
+        case RGS_OK: return "success";
+        case RGS_EINVAL: return "invalid argument";
+        case RGS_ENOMEM: return "device memory allocation failed";
+        case RGS_EDEVICE: return "HIP runtime or kernel launch failure";
+        case RGS_EBREAKDOWN: return "breakdown: column numerically in the span of the previous ones";
+        case RGS_ENONFINITE: return "non-finite sketch (NaN or Inf in the input)";
+        case RGS_ENOCONV: return "GMRES did not converge within max_iters";
+    }
+    return "unknown status";
+}
+
+rgs_status rgs_create(rgs_handle** h, int device, rgs_stream stream) {
+    if (!h) return RGS_EINVAL;
+    *h = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) {
+        (void)hipGetLastError();
+        return RGS_EDEVICE;
+    }
+    if (device < 0 || device >= count) return RGS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return RGS_EDEVICE;
+    rgs_handle* p = new rgs_handle();
+    p->device = device;
+    p->stream = static_cast<hipStream_t>(stream);
+    *h = p;
+    return RGS_OK;
+}
+
+rgs_status rgs_destroy(rgs_handle* h) {
+    if (!h) return RGS_EINVAL;
+    hipSetDevice(h->device);
+    hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) hipEventDestroy(e);
+    if (h->arena) hipFree(h->arena);
+    delete h;
+    return RGS_OK;
+}
+
+rgs_status rgs_set_stream(rgs_handle* h, rgs_stream stream) {
+    if (!h) return RGS_EINVAL;
+    h->stream = static_cast<hipStream_t>(stream);
+    return RGS_OK;
+}
+
+rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ldw, void* Q, int64_t ldq,
+                  double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
+    if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
+    if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
+    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS)) != 0) return RGS_EINVAL;
+    if (d->m > 4096) return RGS_EINVAL;   // dynamic LDS of the sketch-space kernels
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    if (d->prec == RGS_P_FP64)
+        return run_qr<double>(h, d, static_cast<const double*>(W), ldw, static_cast<double*>(Q), ldq, R, ldr, S,
+                              lds, rep);
+    return run_qr<float>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R, ldr, S, lds,
+                         rep);
+}
+
+rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, int64_t ldx, int64_t ncols,
+                            double* Y, int64_t ldy) {
+    if (!h || !valid_desc(d, false) || !X || !Y || ncols < 1 || ldx < d->n || ldy < d->k) return RGS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+    const size_t tsize = d->prec == RGS_P_FP64 ? sizeof(double) : sizeof(float);
+    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize);
+    rgs_status st = ensure_arena(h, pl.total);
+    if (st != RGS_OK) return st;
+    char* A = h->arena;
+    SketchArgs sk = make_sketch(sk_kind, d->k, d->seed, d->sketch_id, d->instance);
+    st = setup_sketch(h, sk, d->n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
+    if (st != RGS_OK) return st;
+    if (d->prec == RGS_P_FP64)
+        st = sketch_matrix<double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
+                                   reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
+    else
+        st = sketch_matrix<float>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
+                                  reinterpret_cast<float*>(A + pl.part_P), Y, ldy);
+    if (st != RGS_OK) return st;
+    return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+}
+
+rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j0, int64_t j1, int64_t l0,
+                                  int64_t l1, double* out, int64_t ldo) {
+    if (!h || !valid_desc(d, false) || !out) return RGS_EINVAL;
+    if (j0 < 0 || j1 < j0 || j1 > d->k || l0 < 0 || l1 < l0 || l1 > d->n || ldo < std::max<int64_t>(1, j1 - j0))
+        return RGS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+    const QrPlan pl = plan_qr(d->n, 1, d->k, sk_kind, sizeof(double));
+    rgs_status st = ensure_arena(h, pl.total);
+    if (st != RGS_OK) return st;
+    char* A = h->arena;
+    SketchArgs sk = make_sketch(sk_kind, d->k, d->seed, d->sketch_id, d->instance);
+    st = setup_sketch(h, sk, d->n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
+    if (st != RGS_OK) return st;
+    const double rsk = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)d->k);
+    const bool ok = d->prec == RGS_P_FP64
+                        ? launch_materialize<double>(h->stream, sk, j0, j1, l0, l1, rsk, out, ldo)
+                        : launch_materialize<float>(h->stream, sk, j0, j1, l0, l1, rsk, out, ldo);
+    if (!ok) return RGS_EDEVICE;
+    return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+}
+
+}  // extern "C"

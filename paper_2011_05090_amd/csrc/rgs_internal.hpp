@@ -1,0 +1,61 @@
+// Internal declarations shared by the kernels (rgs_kernels.hip, rgs_gmres.hip)
+// and the host C ABI (rgs_api.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rgs {
+
+enum { SK_GAUSS = 0, SK_SRHT = 1, SK_IDENT = 2 };
+enum { kStatusOk = 0, kStatusBreakdown = 1, kStatusNonfinite = 2 };
+
+// Everything a kernel needs to regenerate Theta (k x n) on the fly.
+struct SketchArgs {
+    int sketch;             // SK_*
+    int k;
+    uint32_t k0, k1;        // Philox key (seed low / high word)
+    uint32_t sid, inst;     // counter words 2 and 3
+    const uint32_t* signs;  // SRHT: bit table of D
+    const int* rows;        // SRHT: sampled rows of H_s
+};
+
+// Device pointers of the sketch-space state (all fp64).
+struct SpaceArgs {
+    int k, mcap;
+    double *Vc, *Vr;        // reflectors, column-major (k x mcap) and row-major (k rows of mcap)
+    double *Wc, *Wr;        // Wm = V T, same two layouts
+    double* X;              // R_S^{-1}, mcap x mcap column-major
+    double *sp, *u, *v;     // k-vectors: s', U^T s, current reflector
+    double *uh;             // mcap: head of U^T p
+    double *pd, *pd2;       // per-slice partial sums: nsl x (mcap+1), nsl
+    double *rr, *invr, *pnorm, *tau, *beta;  // per-column scalars (mcap each)
+    int* status;            // [0] = kStatus*, [1] = failed column
+};
+
+bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const SketchArgs& sk);
+template <typename T, typename PT>
+bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int ncols, int G,
+                        const SketchArgs& sk, PT* partials);
+template <typename PT>
+bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
+                   int64_t ldo);
+template <typename T, typename PT>
+bool launch_project(hipStream_t st, const T* w, T* Q, int64_t ldq, int64_t n, int j, const T* coef,
+                    const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
+                    PT* partials, const int* status);
+template <typename T>
+bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const int* status);
+template <typename T>
+bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, double* R, int64_t ldr, T* coef);
+template <typename PT>
+bool launch_append(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
+                   const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr);
+bool launch_zero_mat(hipStream_t st, double* A, int64_t rows, int64_t cols, int64_t lda);
+template <typename T>
+bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_t j1, int64_t l0, int64_t l1,
+                        double rsk, double* out, int64_t ldo);
+bool launch_diagnostics(hipStream_t st, const double* P, int64_t ldp, const double* S, int64_t lds,
+                        const double* R, int64_t ldr, int k, int m, double* gram_out, double* resid_out);
+
+}  // namespace rgs
