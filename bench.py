@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the randomized Gram-Schmidt hot path on one MI355X.
+
+One step = one complete RGS QR factorisation (Algorithm 2 of Balabanov &
+Grigori, every column: sketch, fp64 sketched least squares, fused fp32
+projection + sketch, normalisation) of W = U diag(sigma) V^T with
+n = 2^22, m = 512, sigma log-spaced 1 -> 1e-8, P-SRHT sketch k = 2048, fp32
+working precision with fp64 least squares.  Inputs are resident in HBM before
+the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints ONE JSON line on stdout; progress goes to stderr.  ``value`` is the
+algorithmic bandwidth of the whole factorisation in GB/s,
+  B = b * n * (m(m-1)/2 + 4m) bytes per QR (b = 4 for fp32):
+  step 3 reads Q_{i-1} and w_i and writes q'_i, step 1 reads w_i, step 7
+  writes q_i.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def qr_bytes(n, m, b):
+    return b * n * (m * (m - 1) / 2 + 4 * m)
+
+
+def project_bytes(n, m, b):
+    """Algorithmic bytes of all projection+sketch launches of one QR:
+    column 0 reads w and writes q'; column i >= 1 reads Q_{i-1} (i columns),
+    reads w_i, writes q'_i and writes the normalised q_{i-1}."""
+    return b * n * (2 + sum(i + 3 for i in range(1, m)))
+
+
+def run_steps(rgs, torch, h, desc, W, Q, R, S, steps, warmup):
+    for _ in range(warmup):
+        rgs.rgs_qr(h, desc, W, Q, R, S)
+    torch.cuda.synchronize()
+    kern_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rep = rgs.rgs_qr(h, desc, W, Q, R, S)
+        kern_ms += rep.proj_kernel_ms
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1000.0 / steps, kern_ms, rep
+
+
+def quality(torch, W, Q, R, S):
+    """||W - QR||_F/||W||_F, ||I - S^T S||_2, ||I - Q^T Q||_2 in fp64 (not timed)."""
+    W64 = W.double()
+    Q64 = Q.double()
+    res = torch.linalg.norm(W64 - Q64 @ R) / torch.linalg.norm(W64)
+    m = S.shape[1]
+    I = torch.eye(m, dtype=torch.float64, device=S.device)
+    d2 = torch.linalg.matrix_norm(I - S.T @ S, ord=2)
+    o2 = torch.linalg.matrix_norm(I - Q64.T @ Q64, ord=2)
+    return float(res), float(d2), float(o2)
+
+
+def cpu_baseline(n=1 << 20, m=32, k=2048):
+    """The oracle (fp32 model, SRHT) on a bounded sample, on the host cores."""
+    import numpy as np
+    import synth
+    from oracle import rgs as orgs, sketch as osk
+    W = synth.svd_matrix(n, m, 1e-8, tag=0).astype(np.float32)
+    th = osk.SRHT(n, k, seed=42)
+    t0 = time.perf_counter()
+    orgs.rgs_qr(W, th, precision="fp32")
+    dt = time.perf_counter() - t0
+    try:
+        import threadpoolctl
+        cores = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": qr_bytes(n, m, 4) / dt / 1e9, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+            "sample": "oracle fp32-model RGS, P-SRHT k=%d, W %dx%d (sigma 1..1e-8), %.1f s wall" % (k, n, m, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 22)
+    ap.add_argument("--m", type=int, default=512)
+    ap.add_argument("--k", type=int, default=2048)
+    ap.add_argument("--no-extra", action="store_true", help="skip the fp64 / Gaussian / companion legs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the row-block sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2011_05090_amd as rgs
+
+    n, m, k = args.n, args.m, args.k
+    dev = torch.device("cuda:0")
+    log("generating W (%d x %d, sigma 1..1e-8) on the device" % (n, m))
+    W64 = synth.svd_matrix_torch(n, m, 1e-8, tag=0, device=dev)
+    W32 = rgs.colmajor(n, m, torch.float32)
+    W32.copy_(W64)
+    Q = rgs.colmajor(n, m, torch.float32)
+    R = rgs.colmajor(m, m, torch.float64)
+    S = rgs.colmajor(k, m, torch.float64)
+    h = rgs.Handle(0)
+
+    desc = rgs.qr_desc(n, m, k, sketch="srht", prec="fp32", flags=rgs.FLAG_TIME_KERNELS)
+    log("fp32/fp64-LS RGS, SRHT: warmup %d, steps %d" % (args.warmup, args.steps))
+    ms, kern_ms, rep = run_steps(rgs, torch, h, desc, W32, Q, R, S, args.steps, args.warmup)
+    if rep.status != 0:
+        raise SystemExit("rgs_qr failed: status %d at column %d" % (rep.status, rep.failed_column))
+    B = qr_bytes(n, m, 4)
+    value = B / (ms / 1000.0) / 1e9
+    avg_launch_ms = kern_ms / (args.steps * m)
+    avg_launch_bytes = project_bytes(n, m, 4) / m
+    achieved = avg_launch_bytes / (avg_launch_ms / 1000.0) / 1e9
+    res, d2, o2 = quality(torch, W32, Q, R, S)
+    log("  %.2f ms/QR  %.1f GB/s  (%.1f%% of HBM peak); projection kernel %.1f GB/s; "
+        "||W-QR||/||W|| %.2e  ||I-S^TS||_2 %.2e  ||I-Q^TQ||_2 %.2e" %
+        (ms, value, 100 * value / HBM_PEAK_GBS, achieved, res, d2, o2))
+    out = {
+        "metric": "RGS QR GB/s (% HBM peak) & RGMRES time-to-1e-6 vs plain FP64 RGS, 1 GPU",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "RGS QR, fp32 projection + fp64 sketched least squares, P-SRHT sketch",
+                   "n": n, "m": m, "k": k, "sketch": "srht", "ls_dtype": "f64",
+                   "W": "U diag(logspace(0,-8,m)) V^T, U,V from QR of seeded N(0,1)",
+                   "pct_hbm_peak": 100 * value / HBM_PEAK_GBS, "bytes_per_step": B},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_project<float,float,SRHT>",
+                     "avg_launch_ms": avg_launch_ms, "avg_launch_bytes": avg_launch_bytes},
+        "quality": {"backward_error": res, "norm2_I_minus_StS": d2, "norm2_I_minus_QtQ": o2},
+    }
+    if not args.no_extra:
+        extra = {}
+        # plain fp64 RGS on the same GPU, same sketch
+        Q64 = rgs.colmajor(n, m, torch.float64)
+        d64 = rgs.qr_desc(n, m, k, sketch="srht", prec="fp64")
+        log("plain fp64 RGS, SRHT: 1 warmup, 2 steps")
+        ms64, _, rep64 = run_steps(rgs, torch, h, d64, W64, Q64, R, S, 2, 1)
+        extra["fp64_rgs_srht"] = {"ms_per_qr": ms64, "gbs": qr_bytes(n, m, 8) / (ms64 / 1000) / 1e9,
+                                  "status": rep64.status}
+        extra["speedup_fp32_vs_fp64"] = ms64 / ms
+        log("  %.2f ms/QR (fp32 path %.2fx faster)" % (ms64, ms64 / ms))
+        del Q64
+        # Gaussian sketch, fp32 path (VALU-bound on generation)
+        dg = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32")
+        log("fp32 RGS, Gaussian sketch: 1 step")
+        msg, _, repg = run_steps(rgs, torch, h, dg, W32, Q, R, S, 1, 0)
+        draws = float(k) * n * (2 * m - 1)
+        extra["fp32_rgs_gaussian"] = {"ms_per_qr": msg, "gbs": B / (msg / 1000) / 1e9, "status": repg.status,
+                                      "gaussian_draws_per_s": draws / (msg / 1000)}
+        log("  %.2f ms/QR" % msg)
+        # companion input, sigma 1 -> 1e-3: the 1e-4 gate on ||I - S^T S||_2
+        del W64
+        Wc64 = synth.svd_matrix_torch(n, m, 1e-3, tag=1, device=dev)
+        W32.copy_(Wc64)
+        del Wc64
+        d1 = rgs.qr_desc(n, m, k, sketch="srht", prec="fp32")
+        rgs.rgs_qr(h, d1, W32, Q, R, S)
+        torch.cuda.synchronize()
+        cres, cd2, co2 = quality(torch, W32, Q, R, S)
+        extra["companion_sigma_1e-3"] = {"backward_error": cres, "norm2_I_minus_StS": cd2,
+                                         "norm2_I_minus_QtQ": co2}
+        log("  companion sigma->1e-3: ||W-QR||/||W|| %.2e  ||I-S^TS||_2 %.2e" % (cres, cd2))
+        out["extra"] = extra
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline()
+        log("  %s" % out["cpu_baseline"])
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -156,24 +156,25 @@ rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* sign
 
 // Layout of the scratch arena for one factorisation.
 struct QrPlan {
-    size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2;
+    size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2, pdb;
     size_t rr, invr, pnorm, tau, beta, status, coef, diag;
     size_t total;
     int G_P, cc;
-    int64_t nblk;
+    int64_t nblk, nproj;
 };
 
 QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     QrPlan p{};
     Carver c;
     p.nblk = (n + kBlock - 1) / kBlock;
+    p.nproj = (n + kProjRows - 1) / kProjRows;
     const int64_t nsl = (k + kSlice - 1) / kSlice;
     p.G_P = (int)std::min<int64_t>(p.nblk, 64);
     const size_t per_col = (size_t)p.G_P * k * tsize;
     p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
     p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
     p.rows = c.take<int>(k);
-    p.part_proj = c.take<char>((sketch == SK_IDENT ? (size_t)n : (size_t)p.nblk * k) * tsize);
+    p.part_proj = c.take<char>((sketch == SK_IDENT ? (size_t)n : (size_t)p.nproj * k) * tsize);
     p.part_P = c.take<char>(per_col * p.cc);
     p.P = c.take<double>(k * m);
     p.Vc = c.take<double>(k * m);
@@ -184,9 +185,10 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     p.sp = c.take<double>(k);
     p.u = c.take<double>(k);
     p.v = c.take<double>(k);
-    p.uh = c.take<double>(m);
+    p.uh = c.take<double>(m + 1);
     p.pd = c.take<double>(nsl * (m + 1));
     p.pd2 = c.take<double>(nsl);
+    p.pdb = c.take<double>(nsl * (m + 2));
     p.rr = c.take<double>(m);
     p.invr = c.take<double>(m);
     p.pnorm = c.take<double>(m);
@@ -246,6 +248,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     sa.uh = reinterpret_cast<double*>(A + pl.uh);
     sa.pd = reinterpret_cast<double*>(A + pl.pd);
     sa.pd2 = reinterpret_cast<double*>(A + pl.pd2);
+    sa.pdb = reinterpret_cast<double*>(A + pl.pdb);
     sa.rr = reinterpret_cast<double*>(A + pl.rr);
     sa.invr = reinterpret_cast<double*>(A + pl.invr);
     sa.pnorm = reinterpret_cast<double*>(A + pl.pnorm);
@@ -270,17 +273,19 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const bool vec_ok = (ldq % 4 == 0) && (ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) &&
                         ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
     const double scale = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)k);
-    const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nblk;
+    const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nproj;
 
     for (int64_t i = 0; i < m; ++i) {
-        const double* p_i = P + i * k;
-        if (i > 0 && !launch_ls<T>(s, sa, p_i, (int)i, R, ldr, coef)) return RGS_EDEVICE;
+        // column i: step 3 (+4, + step 7 of column i-1) with the coefficients solved at the end
+        // of column i-1, then steps 5-6, the Householder append of s_i and step 2 for column i+1
+        const double* pnext = (i + 1 < m) ? P + (i + 1) * k : nullptr;
         if (timed) (void)hipEventRecord(h->events[2 * i], s);
         if (!launch_project<T, T>(s, W + i * ldw, Q, ldq, n, (int)i, coef, i > 0 ? sa.invr + (i - 1) : nullptr,
                                   i > 0 ? 1 : 0, i > 0 ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
-        if (!launch_append<T>(s, sa, part, Gp, scale, i == 0 ? p_i : nullptr, (int)i, S, lds, R, ldr))
+        if (!launch_column<T, T>(s, sa, part, Gp, scale, i == 0 ? P : nullptr, (int)i, S, lds, R, ldr, pnext,
+                                 coef))
             return RGS_EDEVICE;
     }
     if (!launch_scale_col<T>(s, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;

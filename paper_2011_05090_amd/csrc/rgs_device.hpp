@@ -20,6 +20,8 @@ constexpr int kTile = 1024;    // rows per wave tile = in-wave FWHT order
 constexpr int kBlock = 4096;   // rows per workgroup block (4 wave tiles)
 constexpr int kSlice = 64;     // sketch-space rows per workgroup
 constexpr int kKptMax = 16;    // sketch rows per thread: k <= 16 * 256
+constexpr int kProjWaves = 8;  // wave tiles per workgroup of the projection kernel
+constexpr int kProjRows = kProjWaves * kTile;
 
 constexpr uint32_t kTagSigns = 0xFFFFFFFFu;  // counter word 1 of the SRHT sign draws
 constexpr uint32_t kTagRows = 0xFFFFFFFEu;   // counter word 1 of the SRHT row draws

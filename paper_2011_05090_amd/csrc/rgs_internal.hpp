@@ -29,6 +29,7 @@ struct SpaceArgs {
     double *sp, *u, *v;     // k-vectors: s', U^T s, current reflector
     double *uh;             // mcap: head of U^T p
     double *pd, *pd2;       // per-slice partial sums: nsl x (mcap+1), nsl
+    double* pdb;            // per-slice partials for the next right-hand side: nsl x (mcap+2)
     double *rr, *invr, *pnorm, *tau, *beta;  // per-column scalars (mcap each)
     int* status;            // [0] = kStatus*, [1] = failed column
 };
@@ -48,9 +49,10 @@ template <typename T>
 bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const int* status);
 template <typename T>
 bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, double* R, int64_t ldr, T* coef);
-template <typename PT>
-bool launch_append(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
-                   const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr);
+template <typename T, typename PT>
+bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
+                   const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
+                   const double* pnext, T* coef);
 bool launch_zero_mat(hipStream_t st, double* A, int64_t rows, int64_t cols, int64_t lda);
 template <typename T>
 bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_t j1, int64_t l0, int64_t l1,

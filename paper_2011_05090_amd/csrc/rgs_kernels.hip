@@ -19,6 +19,8 @@
 // All cross-workgroup sums are taken in a fixed order, so results are
 // bitwise reproducible run to run.
 
+#include <algorithm>
+
 #include "rgs_device.hpp"
 #include "rgs_internal.hpp"
 
@@ -37,7 +39,12 @@ namespace rgs {
 // ---------------------------------------------------------------------------
 // Loads/stores of the 16 rows a lane owns in a wave tile:
 // rows row0[e] .. row0[e] + 3, e = 0..3 (row0[e] is a multiple of 4).
+// Full tiles use nontemporal vector accesses: every column of W and Q is
+// touched once per pass and the basis is far larger than any cache level.
 // ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 template <typename T>
 __device__ __forceinline__ void load16(const T* __restrict__ p, const int64_t row0[4], int64_t n,
                                        bool full, T v[16]) {
@@ -45,7 +52,7 @@ __device__ __forceinline__ void load16(const T* __restrict__ p, const int64_t ro
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float4 t = *reinterpret_cast<const float4*>(p + row0[e]);
+                const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p + row0[e]));
                 v[4 * e] = t.x;
                 v[4 * e + 1] = t.y;
                 v[4 * e + 2] = t.z;
@@ -54,8 +61,8 @@ __device__ __forceinline__ void load16(const T* __restrict__ p, const int64_t ro
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const double2 a = *reinterpret_cast<const double2*>(p + row0[e]);
-                const double2 b = *reinterpret_cast<const double2*>(p + row0[e] + 2);
+                const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + row0[e]));
+                const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + row0[e] + 2));
                 v[4 * e] = a.x;
                 v[4 * e + 1] = a.y;
                 v[4 * e + 2] = b.x;
@@ -76,14 +83,17 @@ __device__ __forceinline__ void store16(T* __restrict__ p, const int64_t row0[4]
     if (full) {
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                *reinterpret_cast<float4*>(p + row0[e]) =
-                    make_float4(v[4 * e], v[4 * e + 1], v[4 * e + 2], v[4 * e + 3]);
+            for (int e = 0; e < 4; ++e) {
+                const f32x4 t = {v[4 * e], v[4 * e + 1], v[4 * e + 2], v[4 * e + 3]};
+                __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p + row0[e]));
+            }
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                *reinterpret_cast<double2*>(p + row0[e]) = make_double2(v[4 * e], v[4 * e + 1]);
-                *reinterpret_cast<double2*>(p + row0[e] + 2) = make_double2(v[4 * e + 2], v[4 * e + 3]);
+                const f64x2 a = {v[4 * e], v[4 * e + 1]};
+                const f64x2 b = {v[4 * e + 2], v[4 * e + 3]};
+                __builtin_nontemporal_store(a, reinterpret_cast<f64x2*>(p + row0[e]));
+                __builtin_nontemporal_store(b, reinterpret_cast<f64x2*>(p + row0[e] + 2));
             }
         }
     } else {
@@ -95,33 +105,37 @@ __device__ __forceinline__ void store16(T* __restrict__ p, const int64_t row0[4]
     }
 }
 
+// Rows of this lane in block blk of a workgroup with NW wave tiles.
+template <int NW>
 __device__ __forceinline__ void lane_rows(int64_t blk, int64_t row0[4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) row0[e] = blk * kBlock + wave * kTile + 256 * e + 4 * lane;
+    for (int e = 0; e < 4; ++e) row0[e] = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
 }
 
 // ---------------------------------------------------------------------------
-// Sketch of one 4096-row block held in registers (v = this lane's 16 rows),
-// accumulated into acc[u] for the sketch rows j = threadIdx.x + 256 u.
+// Sketch of one block of NW * 1024 rows held in registers (v = this lane's 16
+// rows), accumulated into acc[u] for the sketch rows j = threadIdx.x + 64 NW u.
 // The 1/sqrt(k) scale is applied later, in fp64.
 //
 // SRHT: with s = 2^a T (T = 1024 the in-wave FWHT order) the Sylvester
 // Hadamard matrix factors as H_s = H_{s/T} (x) H_T, so for a sampled row
 // rho = alpha T + beta and the tile index t of rows [tT, (t+1)T):
 //   (H_s D x)[rho] = sum_t (-1)^popcount(alpha & t) (H_T D x_t)[beta].
-// Each wave transforms its tile in registers; the block's four tiles are then
-// combined per sampled row through LDS.
+// Each wave transforms its tile in registers; the block's NW tiles are then
+// combined per sampled row through LDS (tile t = NW blk + w, and since the
+// bits of w and NW blk are disjoint the sign factors into both parts).
 // Gaussian: theta_{j,l} generated on the fly, 4 entries per Philox call.
 // ---------------------------------------------------------------------------
-template <typename T, typename PT, int SK>
+template <typename T, typename PT, int SK, int NW>
 __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, const SketchArgs& sk,
                                              PT acc[kKptMax], T* __restrict__ lds) {
+    constexpr int NT = NW * kWave;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int kpt = (sk.k + kWG - 1) / kWG;
+    const int kpt = (sk.k + NT - 1) / NT;
     if constexpr (SK == SK_SRHT) {
         int64_t row0[4];
-        lane_rows(blk, row0);
+        lane_rows<NW>(blk, row0);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (row0[e] < n) {
@@ -138,18 +152,19 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
 #pragma unroll
             for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
         __syncthreads();
-        const uint32_t tb = (uint32_t)(blk * 4);  // tile index of wave 0
+        const uint32_t tb = (uint32_t)(blk * NW);  // tile index of wave 0
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) {
-            const int j = t + kWG * u;
+            const int j = t + NT * u;
             if (u < kpt && j < sk.k) {
                 const uint32_t rho = (uint32_t)sk.rows[j];
                 const uint32_t alpha = rho >> 10, beta = rho & 1023u;
-                const T z0 = lds[beta], z1 = lds[kTile + beta];
-                const T z2 = lds[2 * kTile + beta], z3 = lds[3 * kTile + beta];
-                const T s01 = (alpha & 1u) ? z0 - z1 : z0 + z1;
-                const T s23 = (alpha & 1u) ? z2 - z3 : z2 + z3;
-                T tot = (alpha & 2u) ? s01 - s23 : s01 + s23;
+                T tot = T(0);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const T z = lds[w * kTile + beta];
+                    tot = (__popc(alpha & (uint32_t)w) & 1) ? tot - z : tot + z;
+                }
                 if (__popc(alpha & tb) & 1) tot = -tot;
                 acc[u] += (PT)tot;
             }
@@ -161,14 +176,14 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
 #pragma unroll
             for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
         __syncthreads();
-        const int64_t rem = n - blk * kBlock;
-        const int nq = rem >= kBlock ? kBlock / 4 : (int)((rem + 3) / 4);
-        const uint32_t q0 = (uint32_t)(blk * (kBlock / 4));
+        const int64_t rem = n - blk * (NW * kTile);
+        const int nq = rem >= NW * kTile ? NW * kTile / 4 : (int)((rem + 3) / 4);
+        const uint32_t q0 = (uint32_t)(blk * (NW * kTile / 4));
         for (int q = 0; q < nq; ++q) {
             const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
 #pragma unroll
             for (int u = 0; u < kKptMax; ++u) {
-                const int j = t + kWG * u;
+                const int j = t + NT * u;
                 if (u < kpt && j < sk.k) {
                     T z[4];
                     gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
@@ -194,7 +209,7 @@ __global__ void k_srht_signs(uint32_t* __restrict__ signs, int64_t nwords, uint3
 }
 
 // Partial sketches of ncols columns of X: workgroup (g, col) covers row blocks
-// g, g + G, ... and writes partials[(col * G + g) * k + j].
+// g, g + G, ... (4096 rows each) and writes partials[(col * G + g) * k + j].
 template <typename T, typename PT, int SK>
 __global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, int64_t ldx, int64_t n,
                                                      int64_t nblk, int G, SketchArgs sk,
@@ -208,11 +223,11 @@ __global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, in
     const bool vec_ok = ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
     for (int64_t blk = g; blk < nblk; blk += G) {
         int64_t row0[4];
-        lane_rows(blk, row0);
+        lane_rows<4>(blk, row0);
         const bool full = vec_ok && (blk + 1) * kBlock <= n;
         T v[16];
         load16(x, row0, n, full, v);
-        block_sketch<T, PT, SK>(v, blk, n, sk, acc, lds);
+        block_sketch<T, PT, SK, 4>(v, blk, n, sk, acc, lds);
     }
     PT* out = partials + ((int64_t)col * G + g) * sk.k;
     const int kpt = (sk.k + kWG - 1) / kWG;
@@ -248,29 +263,28 @@ __global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials,
     }
 }
 
-// Step 3 (+ step 4 partials, + step 7 of the previous column):
+// Step 3 (+ step 4 partials, + step 7 of the previous column), for one block
+// of kProjWaves * 1024 rows per workgroup:
 //   q'_i = w_i - sum_{c<j} coef[c] q_c           (working precision T, fma chain in c order)
 // where, if normalize_last, column j-1 still holds q'_{i-1} and is first
 // scaled to q_{i-1} = q'_{i-1} / r_{i-1,i-1} (fp64 multiply by the reciprocal,
 // rounded to T) and written back.  q'_i is stored in column j.  Then the
 // block's sketch partials of q'_i are written (or q'_i itself for Theta = I).
 template <typename T, typename PT, int SK>
-__global__ __launch_bounds__(kWG) void k_project(const T* __restrict__ w, T* __restrict__ Q, int64_t ldq,
-                                                 int64_t n, int j, const T* __restrict__ coef,
-                                                 const double* __restrict__ invr, int normalize_last,
-                                                 int do_sketch, int vec_ok, SketchArgs sk,
-                                                 PT* __restrict__ partials,
-                                                 const int* __restrict__ status) {
-    __shared__ T lds[kBlock];
+__global__ __launch_bounds__(kProjWaves * kWave) void k_project(
+    const T* __restrict__ w, T* __restrict__ Q, int64_t ldq, int64_t n, int j, const T* __restrict__ coef,
+    const double* __restrict__ invr, int normalize_last, int do_sketch, int vec_ok, SketchArgs sk,
+    PT* __restrict__ partials, const int* __restrict__ status) {
+    constexpr int NW = kProjWaves;
+    __shared__ T lds[NW * kTile];
     RGS_EXIT_IF_FAILED(status);
     const int64_t blk = blockIdx.x;
     int64_t row0[4];
-    lane_rows(blk, row0);
-    const bool full = vec_ok && (blk + 1) * kBlock <= n;
+    lane_rows<NW>(blk, row0);
+    const bool full = vec_ok && (blk + 1) * (NW * kTile) <= n;
     T v[16];
     load16(w, row0, n, full, v);
     const int jl = normalize_last ? j - 1 : j;
-#pragma unroll 2
     for (int c = 0; c < jl; ++c) {
         const T a = coef[c];
         T q[16];
@@ -299,12 +313,13 @@ __global__ __launch_bounds__(kWG) void k_project(const T* __restrict__ w, T* __r
         PT acc[kKptMax];
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
-        block_sketch<T, PT, SK>(v, blk, n, sk, acc, lds);
+        block_sketch<T, PT, SK, NW>(v, blk, n, sk, acc, lds);
         PT* out = partials + blk * sk.k;
-        const int kpt = (sk.k + kWG - 1) / kWG;
+        constexpr int NT = NW * kWave;
+        const int kpt = (sk.k + NT - 1) / NT;
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) {
-            const int jj = threadIdx.x + kWG * u;
+            const int jj = threadIdx.x + NT * u;
             if (u < kpt && jj < sk.k) out[jj] = acc[u];
         }
     }
@@ -320,146 +335,201 @@ __global__ void k_scale_col(T* __restrict__ q, int64_t n, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Sketch-space kernels (fp64).  i = 0-based index of the current column,
-// j = i columns are already factorised.  SL = 64 rows per workgroup slice,
-// pd = per-slice partial dot products, row stride m1 = mcap + 1.
+// Sketch-space kernels (fp64).  i = 0-based index of the current column;
+// i columns are already factorised.  A "slice" is 64 consecutive sketch rows
+// (one workgroup); pd buffers hold per-slice partial dot products.  These
+// kernels are latency-bound, so every loop over global memory issues its
+// loads in batches (independent loads first, then the fixed-order sums) to
+// keep the number of dependent round trips per kernel at two or three.
+// Column-parallel dot products run one thread per column over a slice;
+// row-parallel products run 64 rows x 16 column groups (1024 threads).
 // ---------------------------------------------------------------------------
+constexpr int kGW = 1024;   // threads of the sketch-space kernels
+constexpr int kGQ = 16;     // column groups of the row-parallel products
+constexpr int kBatch = 16;  // loads issued back to back per thread
 
-// Step 2, part 1: per-slice partials of c = Wm_i^T p (c < i) and of ||p||^2 (slot i).
-__global__ __launch_bounds__(kWG) void k_ls1(const double* __restrict__ p, int k, int i,
-                                             const double* __restrict__ Wr, int mcap,
-                                             double* __restrict__ pd, const int* __restrict__ status) {
-    RGS_EXIT_IF_FAILED(status);
-    const int s = blockIdx.x, r0 = s * kSlice, r1 = min(k, r0 + kSlice);
-    for (int c = threadIdx.x; c <= i; c += kWG) {
-        double acc = 0.0;
-        if (c < i) {
-            for (int r = r0; r < r1; ++r) acc = fma(Wr[(int64_t)r * mcap + c], p[r], acc);
-        } else {
-            for (int r = r0; r < r1; ++r) acc = fma(p[r], p[r], acc);
-        }
-        pd[(int64_t)s * (mcap + 1) + c] = acc;
+// sum_{s < nsl} pd[s * stride + c] (fixed order in s)
+__device__ __forceinline__ double sum_col(const double* __restrict__ pd, int nsl, int stride, int c) {
+    double acc = 0.0;
+    for (int s0 = 0; s0 < nsl; s0 += kBatch) {
+        double t[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) t[u] = (s0 + u < nsl) ? pd[(int64_t)(s0 + u) * stride + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) acc += t[u];
     }
+    return acc;
+}
+
+__device__ __forceinline__ void sum_slices(const double* __restrict__ pd, int nsl, int stride, int cnt,
+                                           double* __restrict__ out) {
+    for (int c = threadIdx.x; c < cnt; c += blockDim.x) out[c] = sum_col(pd, nsl, stride, c);
+}
+
+// sum_{rr < 64} M[row(rr), c] * xs[rr], M row-major with row stride mcap; rows
+// past k are clamped (xs is 0 there).
+__device__ __forceinline__ double slice_dot(const double* __restrict__ Mr, int mcap, int r0, int k,
+                                            const double* __restrict__ xs, int c) {
+    double acc = 0.0;
+#pragma unroll 1
+    for (int b = 0; b < kSlice; b += kBatch) {
+        double t[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) t[u] = Mr[(int64_t)min(r0 + b + u, k - 1) * mcap + c];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) acc = fma(t[u], xs[b + u], acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double slice_sq(const double* __restrict__ xs) {
+    double acc = 0.0;
+    for (int rr = 0; rr < kSlice; ++rr) acc = fma(xs[rr], xs[rr], acc);
+    return acc;
+}
+
+__device__ __forceinline__ double slice_xy(const double* __restrict__ xs, const double* __restrict__ ys) {
+    double acc = 0.0;
+    for (int rr = 0; rr < kSlice; ++rr) acc = fma(xs[rr], ys[rr], acc);
+    return acc;
+}
+
+// Row-parallel partial: sum over c in [c0, c1) with c = q (mod kGQ), ascending,
+// of M[r, c] * xl[c]; M column-major with leading dimension ld.
+__device__ __forceinline__ double row_part(const double* __restrict__ Mc, int64_t ld, int r, int c0, int c1,
+                                           const double* __restrict__ xl, int q) {
+    double acc = 0.0;
+    for (int c = c0 + ((q - c0) % kGQ + kGQ) % kGQ; c < c1; c += kGQ * kBatch) {
+        double t[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int cc = c + kGQ * u;
+            t[u] = (cc < c1) ? Mc[r + (int64_t)cc * ld] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int cc = c + kGQ * u;
+            if (cc < c1) acc = fma(t[u], xl[cc], acc);
+        }
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double combine16(double (*red)[64], int rl) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGQ; ++q) t += red[q][rl];
+    return t;
+}
+
+// Step 2 for a right-hand side p known only now (Arnoldi): part 1, per-slice
+// partials of c = Wm_i^T p (c < i) and of ||p||^2 (slot i).
+__global__ __launch_bounds__(kGW) void k_ls1(const double* __restrict__ p, int k, int i,
+                                             const double* __restrict__ Wr, int mcap, double* __restrict__ pd) {
+    __shared__ double xs[kSlice];
+    const int s = blockIdx.x, r0 = s * kSlice;
+    if (threadIdx.x < kSlice) xs[threadIdx.x] = (r0 + threadIdx.x < k) ? p[r0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    double* out = pd + (int64_t)s * (mcap + 1);
+    for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
 // Step 2, part 2: c = sum of slice partials; head of U_i^T p:
 //   uh[r] = p[r] - sum_{c <= r} V[r, c] c[c],  r < i.
-__global__ __launch_bounds__(kWG) void k_ls2(const double* __restrict__ p, int k, int i, int nsl,
+__global__ __launch_bounds__(kGW) void k_ls2(const double* __restrict__ p, int k, int i, int nsl,
                                              const double* __restrict__ Vc, int mcap,
                                              const double* __restrict__ pd, double* __restrict__ uh,
-                                             double* __restrict__ pnorm, const int* __restrict__ status) {
+                                             double* __restrict__ pnorm) {
     extern __shared__ double cp[];  // [i + 1]
-    __shared__ double red[4][64];
-    RGS_EXIT_IF_FAILED(status);
-    for (int c = threadIdx.x; c <= i; c += kWG) {
-        double acc = 0.0;
-        for (int s = 0; s < nsl; ++s) acc += pd[(int64_t)s * (mcap + 1) + c];
-        cp[c] = acc;
-    }
+    __shared__ double red[kGQ][64];
+    sum_slices(pd, nsl, mcap + 1, i + 1, cp);
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) pnorm[i] = sqrt(cp[i]);
     const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r = blockIdx.x * 64 + rl;
-    double part = 0.0;
-    if (r < i) {
-        const int cmax = min(r, i - 1);
-        for (int c = q; c <= cmax; c += 4) part = fma(Vc[r + (int64_t)c * k], cp[c], part);
-    }
-    red[q][rl] = part;
+    red[q][rl] = (r < i) ? row_part(Vc, k, r, 0, min(r, i - 1) + 1, cp, q) : 0.0;
     __syncthreads();
-    if (q == 0 && r < i) uh[r] = p[r] - (((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl]);
+    if (q == 0 && r < i) uh[r] = p[r] - combine16(red, rl);
 }
 
-// Step 2, part 3: y = R_S^{-1} uh with X = R_S^{-1} (upper triangular):
-//   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:i, i), and coef (working precision).
+// Step 2, last part: y = R_S^{-1} uh with X = R_S^{-1} (upper triangular, nr x nr):
+//   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:nr, col) and coef (working precision).
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_ls3(int i, const double* __restrict__ X, int mcap,
+__global__ __launch_bounds__(kGW) void k_ls3(int nr, int col, const double* __restrict__ X, int mcap,
                                              const double* __restrict__ uh, double* __restrict__ R,
-                                             int64_t ldr, T* __restrict__ coef,
-                                             const int* __restrict__ status) {
-    extern __shared__ double us[];  // [i]
-    __shared__ double red[4][64];
-    RGS_EXIT_IF_FAILED(status);
-    for (int c = threadIdx.x; c < i; c += kWG) us[c] = uh[c];
+                                             int64_t ldr, T* __restrict__ coef) {
+    extern __shared__ double us[];  // [nr]
+    __shared__ double red[kGQ][64];
+    for (int c = threadIdx.x; c < nr; c += kGW) us[c] = uh[c];
     __syncthreads();
     const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r = blockIdx.x * 64 + rl;
-    double part = 0.0;
-    if (r < i) {
-        for (int c = r + ((q - r) & 3); c < i; c += 4) part = fma(X[r + (int64_t)c * mcap], us[c], part);
-    }
-    red[q][rl] = part;
+    red[q][rl] = (r < nr) ? row_part(X, mcap, r, r, nr, us, q) : 0.0;
     __syncthreads();
-    if (q == 0 && r < i) {
-        const double y = ((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl];
-        R[r + (int64_t)i * ldr] = y;
+    if (q == 0 && r < nr) {
+        const double y = combine16(red, rl);
+        R[r + (int64_t)col * ldr] = y;
         coef[r] = (T)y;
     }
 }
 
-// Append, part 1: s' = scale * (sum of block partials) for this slice (or a copy
-// of src when src != nullptr), stored in sp; per-slice partials of
+// Column step A: s' = scale * (sum of the projection kernel's block partials)
+// for this slice (or a copy of src), stored in sp; per-slice partials of
 // c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
 template <typename PT>
-__global__ __launch_bounds__(kWG) void k_ap1(const PT* __restrict__ partials, int G, double scale,
-                                             const double* __restrict__ src, int k, int i,
-                                             const double* __restrict__ Wr, int mcap,
-                                             double* __restrict__ sp, double* __restrict__ pd,
-                                             const int* __restrict__ status) {
-    __shared__ double red[4][64];
-    __shared__ double ss[64];
-    RGS_EXIT_IF_FAILED(status);
-    const int s = blockIdx.x, r0 = s * kSlice, r1 = min(k, r0 + kSlice);
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+__global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int G, double scale,
+                                            const double* __restrict__ src, int k, int i,
+                                            const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
+                                            double* __restrict__ pd) {
+    __shared__ double red[kGQ][64];
+    __shared__ double xs[kSlice];
+    const int s = blockIdx.x, r0 = s * kSlice, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r = r0 + rl;
     if (src) {
-        if (q == 0 && r < k) {
-            ss[rl] = src[r];
-            sp[r] = src[r];
+        if (q == 0) {
+            const double val = (r < k) ? src[r] : 0.0;
+            xs[rl] = val;
+            if (r < k) sp[r] = val;
         }
     } else {
-        const int g0 = (int)((int64_t)G * q / 4), g1 = (int)((int64_t)G * (q + 1) / 4);
+        // group q sums the block partials g in [G q / 16, G (q+1) / 16), in order
+        const int g0 = (int)((int64_t)G * q / kGQ), g1 = (int)((int64_t)G * (q + 1) / kGQ);
         double acc = 0.0;
-        if (r < k)
-            for (int g = g0; g < g1; ++g) acc += (double)partials[(int64_t)g * k + r];
+        if (r < k) {
+            for (int g = g0; g < g1; g += 32) {
+                PT t[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) t[u] = (g + u < g1) ? partials[(int64_t)(g + u) * k + r] : PT(0);
+#pragma unroll
+                for (int u = 0; u < 32; ++u) acc += (double)t[u];
+            }
+        }
         red[q][rl] = acc;
         __syncthreads();
-        if (q == 0 && r < k) {
-            const double val = ((((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl])) * scale;
-            ss[rl] = val;
-            sp[r] = val;
+        if (q == 0) {
+            const double val = (r < k) ? combine16(red, rl) * scale : 0.0;
+            xs[rl] = val;
+            if (r < k) sp[r] = val;
         }
     }
     __syncthreads();
-    for (int c = threadIdx.x; c <= i; c += kWG) {
-        double acc = 0.0;
-        if (c < i) {
-            for (int rr = r0; rr < r1; ++rr) acc = fma(Wr[(int64_t)rr * mcap + c], ss[rr - r0], acc);
-        } else {
-            for (int rr = r0; rr < r1; ++rr) acc = fma(ss[rr - r0], ss[rr - r0], acc);
-        }
-        pd[(int64_t)s * (mcap + 1) + c] = acc;
-    }
+    double* out = pd + (int64_t)s * (mcap + 1);
+    for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
-// Append, part 2: steps 5-6.  r_ii = ||s'||, S(:, i) = s'/r_ii, breakdown test,
+// Column step B (steps 5-6): r_ii = ||s'||, S(:, i) = s'/r_ii, breakdown test,
 // u = U_i^T s_i = (s' - V c1) / r_ii, per-slice partials of ||u(i+1:k)||^2.
-__global__ __launch_bounds__(kWG) void k_ap2(int k, int i, int nsl, const double* __restrict__ sp,
-                                             const double* __restrict__ Vc, int mcap,
-                                             const double* __restrict__ pd, double* __restrict__ u,
-                                             double* __restrict__ pd2, double* __restrict__ S, int64_t lds,
-                                             double* __restrict__ R, int64_t ldr,
-                                             double* __restrict__ rr, double* __restrict__ invr,
-                                             const double* __restrict__ pnorm, int* __restrict__ status) {
+__global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
+                                            const double* __restrict__ Vc, int mcap,
+                                            const double* __restrict__ pd, double* __restrict__ u,
+                                            double* __restrict__ pd2, double* __restrict__ S, int64_t lds,
+                                            double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
+                                            double* __restrict__ invr, const double* __restrict__ pnorm,
+                                            int* __restrict__ status) {
     extern __shared__ double c1[];  // [i + 1]
-    __shared__ double red[4][64];
+    __shared__ double red[kGQ][64];
     __shared__ double tl[64];
-    RGS_EXIT_IF_FAILED(status);
-    for (int c = threadIdx.x; c <= i; c += kWG) {
-        double acc = 0.0;
-        for (int s = 0; s < nsl; ++s) acc += pd[(int64_t)s * (mcap + 1) + c];
-        c1[c] = acc;
-    }
+    sum_slices(pd, nsl, mcap + 1, i + 1, c1);
     __syncthreads();
     const double rii = sqrt(c1[i]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -467,26 +537,25 @@ __global__ __launch_bounds__(kWG) void k_ap2(int k, int i, int nsl, const double
         invr[i] = 1.0 / rii;
         R[i + (int64_t)i * ldr] = rii;
         const double pn = (i == 0) ? rii : pnorm[i];
-        if (!isfinite(rii) || !isfinite(pn)) {
-            status[1] = i;
-            status[0] = kStatusNonfinite;
-        } else if (rii == 0.0 || rii <= 0x1p-50 * pn) {
-            status[1] = i;
-            status[0] = kStatusBreakdown;
+        if (status[0] == 0) {
+            if (!isfinite(rii) || !isfinite(pn)) {
+                status[1] = i;
+                status[0] = kStatusNonfinite;
+            } else if (rii == 0.0 || rii <= 0x1p-50 * pn) {
+                status[1] = i;
+                status[0] = kStatusBreakdown;
+            }
         }
     }
     const int s = blockIdx.x, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r = s * kSlice + rl;
-    double part = 0.0;
-    if (r < k)
-        for (int c = q; c < i; c += 4) part = fma(Vc[r + (int64_t)c * k], c1[c], part);
-    red[q][rl] = part;
+    red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : 0.0;
     __syncthreads();
     if (q == 0) {
         double t2 = 0.0;
         if (r < k) {
             const double spr = sp[r];
-            const double val = (spr - (((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl])) / rii;
+            const double val = (spr - combine16(red, rl)) / rii;
             u[r] = val;
             S[r + (int64_t)i * lds] = spr / rii;
             if (r > i) t2 = val * val;
@@ -501,17 +570,20 @@ __global__ __launch_bounds__(kWG) void k_ap2(int k, int i, int nsl, const double
     }
 }
 
-// Append, part 3: Householder reflector of u(i:k) (dlarfg convention):
-// beta = -sign(u_i) ||u(i:k)||, tau = (beta - u_i)/beta, v = [0; 1; u(i+1:k)/(u_i - beta)].
-// Stores v as column i of V (both layouts); per-slice partials of d = V_i^T v.
-__global__ __launch_bounds__(kWG) void k_ap3(int k, int i, int nsl, const double* __restrict__ u,
-                                             const double* __restrict__ pd2, double* __restrict__ v,
-                                             double* __restrict__ Vc, double* __restrict__ Vr, int mcap,
-                                             double* __restrict__ pd, double* __restrict__ tau_a,
-                                             double* __restrict__ beta_a, int* __restrict__ status) {
-    __shared__ double vs[64];
+// Column step C: Householder reflector of u(i:k) (dlarfg convention):
+// beta = -sign(u_i) ||u(i:k)||, tau = (beta - u_i)/beta, v = [0; 1; u(i+1:k)/(u_i - beta)],
+// stored as column i of V (both layouts).  Per-slice partials of d = V_i^T v
+// (pd, stride mcap+1) and, when the next right-hand side pn = p_{i+1} is given,
+// of e = Wm_i^T pn, v.pn and ||pn||^2 (pdb, stride mcap+2, slots [0,i), i, i+1).
+__global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
+                                            const double* __restrict__ pd2, const double* __restrict__ pn,
+                                            double* __restrict__ v, double* __restrict__ Vc,
+                                            double* __restrict__ Vr, const double* __restrict__ Wr, int mcap,
+                                            double* __restrict__ pd, double* __restrict__ pdb,
+                                            double* __restrict__ tau_a, double* __restrict__ beta_a,
+                                            int* __restrict__ status) {
+    __shared__ double vs[kSlice], ps[kSlice];
     __shared__ double hh[3];
-    RGS_EXIT_IF_FAILED(status);
     if (threadIdx.x == 0) {
         double tail2 = 0.0;
         for (int s = 0; s < nsl; ++s) tail2 += pd2[s];
@@ -532,17 +604,16 @@ __global__ __launch_bounds__(kWG) void k_ap3(int k, int i, int nsl, const double
         if (blockIdx.x == 0) {
             tau_a[i] = tau;
             beta_a[i] = beta;
-            if (!(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1}) in sketch space
+            if (status[0] == 0 && !(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1}) in sketch space
                 status[1] = i;
                 status[0] = kStatusBreakdown;
             }
         }
     }
     __syncthreads();
-    const int s = blockIdx.x, r0 = s * kSlice, r1 = min(k, r0 + kSlice);
-    const int t = threadIdx.x;
-    if (t < 64) {
-        const int r = r0 + t;
+    const int s = blockIdx.x, r0 = s * kSlice;
+    if (threadIdx.x < kSlice) {
+        const int r = r0 + threadIdx.x;
         double val = 0.0;
         if (r < k) {
             val = (r < i) ? 0.0 : (r == i ? 1.0 : u[r] * hh[2]);
@@ -550,59 +621,93 @@ __global__ __launch_bounds__(kWG) void k_ap3(int k, int i, int nsl, const double
             Vc[r + (int64_t)i * k] = val;
             Vr[(int64_t)r * mcap + i] = val;
         }
-        vs[t] = val;
+        vs[threadIdx.x] = val;
+        ps[threadIdx.x] = (pn && r < k) ? pn[r] : 0.0;
     }
     __syncthreads();
-    for (int c = t; c < i; c += kWG) {
-        double acc = 0.0;
-        for (int r = max(r0, c); r < r1; ++r) acc = fma(Vr[(int64_t)r * mcap + c], vs[r - r0], acc);
-        pd[(int64_t)s * (mcap + 1) + c] = acc;
+    const int ntot = pn ? 2 * i + 2 : i;
+    double* outd = pd + (int64_t)s * (mcap + 1);
+    double* oute = pdb + (int64_t)s * (mcap + 2);
+    for (int c = threadIdx.x; c < ntot; c += kGW) {
+        const bool isd = c < i;
+        const int ce = isd ? c : c - i;
+        double val;
+        if (isd || ce < i) {
+            val = slice_dot(isd ? Vr : Wr, mcap, r0, k, isd ? vs : ps, ce);
+        } else {
+            val = (ce == i) ? slice_xy(vs, ps) : slice_sq(ps);
+        }
+        if (isd) outd[c] = val;
+        else oute[ce] = val;
     }
 }
 
-// Append, part 4.  Blocks [0, nsl): Wm(:, i) = tau (v - Wm_i d), d = sum of slice partials.
-// Blocks [nsl, nsl + ceil(i/64)): column i of X = R_S^{-1}:
-//   X(r, i) = -(sum_{c=r}^{i-1} X(r, c) u(c)) / beta  (u(0:i) is R_S(0:i, i)),  X(i, i) = 1/beta.
-__global__ __launch_bounds__(kWG) void k_ap4(int k, int i, int nsl, const double* __restrict__ v,
-                                             const double* __restrict__ u, double* __restrict__ Wc,
-                                             double* __restrict__ Wr, int mcap, const double* __restrict__ pd,
-                                             double* __restrict__ X, const double* __restrict__ tau_a,
-                                             const double* __restrict__ beta_a, const int* __restrict__ status) {
-    extern __shared__ double dsh[];  // [i]
-    __shared__ double red[4][64];
-    RGS_EXIT_IF_FAILED(status);
+// Column step D.  Blocks [0, nsl): Wm(:, i) = tau (v - Wm_i d), d = sum of the slice partials.
+// Blocks [nsl, ...), rows r of [64 b, 64 b + 64):
+//   column i of X = R_S^{-1}: X(r, i) = -(sum_{c=r}^{i-1} X(r, c) u(c)) / beta for r < i
+//   (u(0:i) is R_S(0:i, i)), X(i, i) = 1/beta;
+//   when pn is given, the head of U_{i+1}^T pn for the next column's least squares:
+//   cp = Wm_{i+1}^T pn = [e; tau (v.pn - d.e)],  uh(r) = pn(r) - sum_{c <= min(r,i)} V(r, c) cp(c), r <= i.
+__global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
+                                            const double* __restrict__ u, const double* __restrict__ pn,
+                                            double* __restrict__ Wc, double* __restrict__ Wr,
+                                            const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
+                                            const double* __restrict__ pdb, double* __restrict__ X,
+                                            double* __restrict__ uh, double* __restrict__ pnorm,
+                                            const double* __restrict__ tau_a, const double* __restrict__ beta_a) {
+    extern __shared__ double dyn[];  // [3 (i + 2)]
+    __shared__ double red[kGQ][64];
+    __shared__ double tree[kGW];
     const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const double tau = tau_a[i];
     if ((int)blockIdx.x < nsl) {
-        for (int c = threadIdx.x; c < i; c += kWG) {
-            double acc = 0.0;
-            for (int s = 0; s < nsl; ++s) acc += pd[(int64_t)s * (mcap + 1) + c];
-            dsh[c] = acc;
-        }
+        double* dsh = dyn;
+        sum_slices(pd, nsl, mcap + 1, i, dsh);
         __syncthreads();
         const int r = blockIdx.x * kSlice + rl;
-        double part = 0.0;
-        if (r < k)
-            for (int c = q; c < i; c += 4) part = fma(Wc[r + (int64_t)c * k], dsh[c], part);
-        red[q][rl] = part;
+        red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : 0.0;
         __syncthreads();
         if (q == 0 && r < k) {
-            const double val = tau_a[i] * (v[r] - (((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl]));
+            const double val = tau * (v[r] - combine16(red, rl));
             Wc[r + (int64_t)i * k] = val;
             Wr[(int64_t)r * mcap + i] = val;
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) X[i + (int64_t)i * mcap] = 1.0 / beta_a[i];
-    } else {
-        for (int c = threadIdx.x; c < i; c += kWG) dsh[c] = u[c];
-        __syncthreads();
-        const int r = (blockIdx.x - nsl) * 64 + rl;
-        double part = 0.0;
-        if (r < i)
-            for (int c = r + ((q - r) & 3); c < i; c += 4) part = fma(X[r + (int64_t)c * mcap], dsh[c], part);
-        red[q][rl] = part;
-        __syncthreads();
-        if (q == 0 && r < i)
-            X[r + (int64_t)i * mcap] = -((((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl])) / beta_a[i];
+        return;
     }
+    double* ush = dyn;            // u(0:i)
+    double* dsh = dyn + (i + 1);  // d
+    double* csh = dsh + (i + 1);  // cp
+    for (int c = threadIdx.x; c < i; c += kGW) ush[c] = u[c];
+    if (pn) {
+        for (int c = threadIdx.x; c < 2 * i + 2; c += kGW) {
+            if (c < i) dsh[c] = sum_col(pd, nsl, mcap + 1, c);
+            else csh[c - i] = sum_col(pdb, nsl, mcap + 2, c - i);   // e, then v.pn at i, ||pn||^2 at i+1
+        }
+    }
+    __syncthreads();
+    const int r = (blockIdx.x - nsl) * 64 + rl;
+    red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : 0.0;
+    __syncthreads();
+    if (q == 0 && r < i) X[r + (int64_t)i * mcap] = -combine16(red, rl) / beta_a[i];
+    if (!pn) return;
+    // d.e by a fixed-shape tree, then cp(i) = tau (v.pn - d.e)
+    double part = 0.0;
+    for (int c = threadIdx.x; c < i; c += kGW) part = fma(dsh[c], csh[c], part);
+    tree[threadIdx.x] = part;
+    __syncthreads();
+    for (int w = kGW / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double vp = csh[i], pp = csh[i + 1];
+    __syncthreads();
+    if (threadIdx.x == 0) csh[i] = tau * (vp - tree[0]);
+    if (blockIdx.x == (unsigned)nsl && threadIdx.x == 0) pnorm[i + 1] = sqrt(pp);
+    __syncthreads();
+    red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : 0.0;
+    __syncthreads();
+    if (q == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
 }
 
 __global__ void k_zero_mat(double* __restrict__ A, int64_t rows, int64_t cols, int64_t lda) {
@@ -731,18 +836,19 @@ template <typename T, typename PT>
 bool launch_project(hipStream_t st, const T* w, T* Q, int64_t ldq, int64_t n, int j, const T* coef,
                     const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
                     PT* partials, const int* status) {
-    const unsigned nblk = nblocks(n, kBlock);
+    const unsigned nblk = nblocks(n, kProjRows);
+    const dim3 thr(kProjWaves * kWave);
     switch (sk.sketch) {
         case SK_SRHT:
-            hipLaunchKernelGGL((k_project<T, PT, SK_SRHT>), dim3(nblk), dim3(kWG), 0, st, w, Q, ldq, n, j, coef,
+            hipLaunchKernelGGL((k_project<T, PT, SK_SRHT>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j, coef,
                                invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
             break;
         case SK_GAUSS:
-            hipLaunchKernelGGL((k_project<T, PT, SK_GAUSS>), dim3(nblk), dim3(kWG), 0, st, w, Q, ldq, n, j,
+            hipLaunchKernelGGL((k_project<T, PT, SK_GAUSS>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
                                coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
             break;
         default:
-            hipLaunchKernelGGL((k_project<T, PT, SK_IDENT>), dim3(nblk), dim3(kWG), 0, st, w, Q, ldq, n, j,
+            hipLaunchKernelGGL((k_project<T, PT, SK_IDENT>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
                                coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
     }
     RGS_LAUNCH_CHECK();
@@ -759,34 +865,41 @@ bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const
 template <typename T>
 bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, double* R, int64_t ldr, T* coef) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_ls1, dim3(nsl), dim3(kWG), 0, st, p, a.k, i, a.Wr, a.mcap, a.pd, a.status);
+    hipLaunchKernelGGL(k_ls1, dim3(nsl), dim3(kGW), 0, st, p, a.k, i, a.Wr, a.mcap, a.pd);
     RGS_LAUNCH_CHECK();
     const unsigned nrb = nblocks(i, 64);
-    hipLaunchKernelGGL(k_ls2, dim3(nrb), dim3(kWG), (i + 1) * sizeof(double), st, p, a.k, i, nsl, a.Vc, a.mcap,
-                       a.pd, a.uh, a.pnorm, a.status);
+    hipLaunchKernelGGL(k_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, p, a.k, i, nsl, a.Vc, a.mcap,
+                       a.pd, a.uh, a.pnorm);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kWG), (i + 1) * sizeof(double), st, i, a.X, a.mcap, a.uh, R,
-                       ldr, coef, a.status);
+    hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, a.X, a.mcap, a.uh, R,
+                       ldr, coef);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-template <typename PT>
-bool launch_append(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
-                   const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr) {
+template <typename T, typename PT>
+bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
+                   const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
+                   const double* pnext, T* coef) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_ap1<PT>, dim3(nsl), dim3(kWG), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap,
-                       a.sp, a.pd, a.status);
+    hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap, a.sp,
+                       a.pd);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ap2, dim3(nsl), dim3(kWG), (i + 1) * sizeof(double), st, a.k, i, nsl, a.sp, a.Vc,
-                       a.mcap, a.pd, a.u, a.pd2, S, lds, R, ldr, a.rr, a.invr, a.pnorm, a.status);
+    hipLaunchKernelGGL(k_qb, dim3(nsl), dim3(kGW), (i + 1) * sizeof(double), st, a.k, i, nsl, a.sp, a.Vc, a.mcap,
+                       a.pd, a.u, a.pd2, S, lds, R, ldr, a.rr, a.invr, a.pnorm, a.status);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ap3, dim3(nsl), dim3(kWG), 0, st, a.k, i, nsl, a.u, a.pd2, a.v, a.Vc, a.Vr, a.mcap,
-                       a.pd, a.tau, a.beta, a.status);
+    hipLaunchKernelGGL(k_qc, dim3(nsl), dim3(kGW), 0, st, a.k, i, nsl, a.u, a.pd2, pnext, a.v, a.Vc, a.Vr, a.Wr,
+                       a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ap4, dim3(nsl + nblocks(i, 64)), dim3(kWG), (i + 1) * sizeof(double), st, a.k, i, nsl,
-                       a.v, a.u, a.Wc, a.Wr, a.mcap, a.pd, a.X, a.tau, a.beta, a.status);
+    hipLaunchKernelGGL(k_qd, dim3(nsl + nblocks(i + 1, 64)), dim3(kGW), 3 * (i + 2) * sizeof(double), st, a.k, i,
+                       nsl, a.v, a.u, pnext, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
+                       a.beta);
     RGS_LAUNCH_CHECK();
+    if (pnext) {
+        hipLaunchKernelGGL(k_ls3<T>, dim3(nblocks(i + 1, 64)), dim3(kGW), (i + 1) * sizeof(double), st, i + 1,
+                           i + 1, a.X, a.mcap, a.uh, R, ldr, coef);
+        RGS_LAUNCH_CHECK();
+    }
     return true;
 }
 
@@ -839,10 +952,11 @@ template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double
 template bool launch_scale_col<double>(hipStream_t, double*, int64_t, const double*, const int*);
 template bool launch_ls<float>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, float*);
 template bool launch_ls<double>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, double*);
-template bool launch_append<float>(hipStream_t, const SpaceArgs&, const float*, int, double, const double*, int,
-                                   double*, int64_t, double*, int64_t);
-template bool launch_append<double>(hipStream_t, const SpaceArgs&, const double*, int, double, const double*,
-                                    int, double*, int64_t, double*, int64_t);
+template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, const double*,
+                                          int, double*, int64_t, double*, int64_t, const double*, float*);
+template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
+                                            const double*, int, double*, int64_t, double*, int64_t, const double*,
+                                            double*);
 template bool launch_materialize<float>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,
                                         double, double*, int64_t);
 template bool launch_materialize<double>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,

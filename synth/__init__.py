@@ -78,3 +78,21 @@ def batch_gmres_sizes(batch, N_lo=32, N_hi=96, pe_lo=1.0, pe_hi=100.0, tag=0):
     Ns = g.integers(N_lo, N_hi + 1, size=batch)
     Pes = g.uniform(pe_lo, pe_hi, size=batch)
     return Ns, Pes
+
+
+def svd_matrix_torch(n, m, sigma_min, tag=0, device="cuda"):
+    """Device-side draw of the same recipe as ``svd_matrix`` for sizes a host QR
+    would take minutes on (fp64, column-major (n, m) tensor).  Uses torch's
+    seeded device generator, so its values differ from ``svd_matrix``'s."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(ROOT_ENTROPY * 1000 + int(tag))
+    G = torch.randn((n, m), generator=gen, dtype=torch.float64, device=device)
+    U, _ = torch.linalg.qr(G)
+    del G
+    H = torch.randn((m, m), generator=gen, dtype=torch.float64, device=device)
+    V, _ = torch.linalg.qr(H)
+    sigma = torch.logspace(0.0, float(np.log10(sigma_min)), m, dtype=torch.float64, device=device)
+    W = (U * sigma[None, :]) @ V.T.contiguous()
+    del U
+    return W.t().contiguous().t()          # column-major copy
