@@ -156,7 +156,7 @@ rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* sign
 
 // Layout of the scratch arena for one factorisation.
 struct QrPlan {
-    size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2, pdb;
+    size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2, pdb, pbuf;
     size_t rr, invr, pnorm, tau, beta, status, coef, diag;
     size_t total;
     int G_P, cc;
@@ -189,6 +189,7 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     p.pd = c.take<double>(nsl * (m + 1));
     p.pd2 = c.take<double>(nsl);
     p.pdb = c.take<double>(nsl * (m + 2));
+    p.pbuf = c.take<double>(k);
     p.rr = c.take<double>(m);
     p.invr = c.take<double>(m);
     p.pnorm = c.take<double>(m);
@@ -199,6 +200,32 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     p.diag = c.take<double>(3 * m);
     p.total = c.off + kAlign;
     return p;
+}
+
+SpaceArgs space_args(char* A, const QrPlan& pl, int64_t k, int64_t m) {
+    SpaceArgs sa{};
+    sa.k = (int)k;
+    sa.mcap = (int)m;
+    sa.Vc = reinterpret_cast<double*>(A + pl.Vc);
+    sa.Vr = reinterpret_cast<double*>(A + pl.Vr);
+    sa.Wc = reinterpret_cast<double*>(A + pl.Wc);
+    sa.Wr = reinterpret_cast<double*>(A + pl.Wr);
+    sa.X = reinterpret_cast<double*>(A + pl.X);
+    sa.sp = reinterpret_cast<double*>(A + pl.sp);
+    sa.u = reinterpret_cast<double*>(A + pl.u);
+    sa.v = reinterpret_cast<double*>(A + pl.v);
+    sa.uh = reinterpret_cast<double*>(A + pl.uh);
+    sa.pd = reinterpret_cast<double*>(A + pl.pd);
+    sa.pd2 = reinterpret_cast<double*>(A + pl.pd2);
+    sa.pdb = reinterpret_cast<double*>(A + pl.pdb);
+    sa.pbuf = reinterpret_cast<double*>(A + pl.pbuf);
+    sa.rr = reinterpret_cast<double*>(A + pl.rr);
+    sa.invr = reinterpret_cast<double*>(A + pl.invr);
+    sa.pnorm = reinterpret_cast<double*>(A + pl.pnorm);
+    sa.tau = reinterpret_cast<double*>(A + pl.tau);
+    sa.beta = reinterpret_cast<double*>(A + pl.beta);
+    sa.status = reinterpret_cast<int*>(A + pl.status);
+    return sa;
 }
 
 template <typename T>
@@ -234,27 +261,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
 
-    SpaceArgs sa{};
-    sa.k = (int)k;
-    sa.mcap = (int)m;
-    sa.Vc = reinterpret_cast<double*>(A + pl.Vc);
-    sa.Vr = reinterpret_cast<double*>(A + pl.Vr);
-    sa.Wc = reinterpret_cast<double*>(A + pl.Wc);
-    sa.Wr = reinterpret_cast<double*>(A + pl.Wr);
-    sa.X = reinterpret_cast<double*>(A + pl.X);
-    sa.sp = reinterpret_cast<double*>(A + pl.sp);
-    sa.u = reinterpret_cast<double*>(A + pl.u);
-    sa.v = reinterpret_cast<double*>(A + pl.v);
-    sa.uh = reinterpret_cast<double*>(A + pl.uh);
-    sa.pd = reinterpret_cast<double*>(A + pl.pd);
-    sa.pd2 = reinterpret_cast<double*>(A + pl.pd2);
-    sa.pdb = reinterpret_cast<double*>(A + pl.pdb);
-    sa.rr = reinterpret_cast<double*>(A + pl.rr);
-    sa.invr = reinterpret_cast<double*>(A + pl.invr);
-    sa.pnorm = reinterpret_cast<double*>(A + pl.pnorm);
-    sa.tau = reinterpret_cast<double*>(A + pl.tau);
-    sa.beta = reinterpret_cast<double*>(A + pl.beta);
-    sa.status = reinterpret_cast<int*>(A + pl.status);
+    SpaceArgs sa = space_args(A, pl, k, m);
     double* P = reinterpret_cast<double*>(A + pl.P);
     T* coef = reinterpret_cast<T*>(A + pl.coef);
     T* part = reinterpret_cast<T*>(A + pl.part_proj);
@@ -339,6 +346,154 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     if (status[0] == kStatusBreakdown) return RGS_EBREAKDOWN;
     if (status[0] == kStatusNonfinite) return RGS_ENONFINITE;
     return RGS_OK;
+}
+
+
+int sketch_kind(int32_t sketch) {
+    return sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+}
+
+StencilArgs stencil_args(const rgs_stencil7* A) {
+    StencilArgs s{};
+    s.nx = A->nx;
+    s.ny = A->ny;
+    s.nz = A->nz;
+    s.c[0] = A->c0;
+    s.c[1] = A->cxm;
+    s.c[2] = A->cxp;
+    s.c[3] = A->cym;
+    s.c[4] = A->cyp;
+    s.c[5] = A->czm;
+    s.c[6] = A->czp;
+    return s;
+}
+
+// Restarted randomized GMRES (Sec. 4.2) driven from the host: one restart
+// cycle is enqueued in full (its inner steps stop themselves on the device
+// once converged), then the host synchronises once to read the true residual.
+template <typename T>
+rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc* d, const double* b, double* x,
+                     double* res_hist, int64_t hist_cap, rgs_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const StencilArgs A = stencil_args(Ad);
+    const int64_t n = A.nx * A.ny * A.nz, mcap = d->restart + 1, k = d->k;
+    const int sk_kind = sketch_kind(d->sketch);
+    const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T));
+    Carver c;
+    c.off = pl.total;
+    const size_t oQ = c.take<T>((size_t)n * mcap), oW = c.take<T>(n), oR = c.take<double>(mcap * mcap);
+    const size_t oS = c.take<double>(k * mcap), oHr = c.take<double>(mcap * mcap), ocs = c.take<double>(mcap);
+    const size_t osn = c.take<double>(mcap), ogv = c.take<double>(mcap + 1), oy = c.take<double>(mcap);
+    const size_t ohist = c.take<double>(mcap), oused = c.take<int>(4), or_ = c.take<double>(n);
+    const size_t opart = c.take<double>((n + 255) / 256), onorm = c.take<double>(4);
+    rgs_status st = ensure_arena(h, c.off + kAlign);
+    if (st != RGS_OK) return st;
+    char* Ar = h->arena;
+    SpaceArgs sa = space_args(Ar, pl, k, mcap);
+    T* Q = reinterpret_cast<T*>(Ar + oQ);
+    T* wbuf = reinterpret_cast<T*>(Ar + oW);
+    double* R = reinterpret_cast<double*>(Ar + oR);
+    double* S = reinterpret_cast<double*>(Ar + oS);
+    double* Hr = reinterpret_cast<double*>(Ar + oHr);
+    double* cs = reinterpret_cast<double*>(Ar + ocs);
+    double* sn = reinterpret_cast<double*>(Ar + osn);
+    double* gv = reinterpret_cast<double*>(Ar + ogv);
+    double* y = reinterpret_cast<double*>(Ar + oy);
+    double* hist = reinterpret_cast<double*>(Ar + ohist);
+    int* used = reinterpret_cast<int*>(Ar + oused);
+    double* r = reinterpret_cast<double*>(Ar + or_);
+    double* rpart = reinterpret_cast<double*>(Ar + opart);
+    double* norm = reinterpret_cast<double*>(Ar + onorm);
+    T* coef = reinterpret_cast<T*>(Ar + pl.coef);
+    T* part = reinterpret_cast<T*>(Ar + pl.part_proj);
+    hipStream_t s = h->stream;
+    const double scale = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)k);
+    const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nproj;
+    const bool vec_ok = (n % 4 == 0);
+
+    // x0 = 0, r0 = b, ||b||
+    if (hipMemsetAsync(x, 0, n * sizeof(double), s) != hipSuccess) return RGS_EDEVICE;
+    if (!launch_residual(s, A, b, x, r, rpart, norm)) return RGS_EDEVICE;
+    double bnorm = 0.0;
+    if (hipMemcpyAsync(&bnorm, norm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return RGS_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+    int64_t iters = 0, cycles = 0, nhist = 0;
+    double relres = bnorm > 0 ? 1.0 : 0.0;
+    rgs_status result = RGS_OK;
+    std::vector<double> hh((size_t)mcap);
+    while (bnorm > 0 && std::isfinite(bnorm)) {
+        if (iters >= d->max_iters) {
+            result = RGS_ENOCONV;
+            break;
+        }
+        const uint32_t sid = d->reuse_theta ? 2u : (uint32_t)(2 + cycles);
+        SketchArgs sk = make_sketch(sk_kind, k, d->seed, sid, 0);
+        st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(Ar + pl.signs), reinterpret_cast<int*>(Ar + pl.rows));
+        if (st != RGS_OK) return st;
+        if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
+        // RGS step 1 of Algorithm 3: w_1 = r_0
+        if (!launch_cast<T>(s, r, wbuf, n)) return RGS_EDEVICE;
+        if (!launch_project<T, T>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, 1, vec_ok ? 1 : 0, sk, part, sa.status))
+            return RGS_EDEVICE;
+        if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, 0, S, k, R, mcap, nullptr, coef))
+            return RGS_EDEVICE;
+        if (!launch_givens_init(s, R, gv, used)) return RGS_EDEVICE;
+        const int64_t steps = std::min<int64_t>(d->restart, d->max_iters - iters);
+        for (int64_t ci = 1; ci <= steps; ++ci) {
+            const int i = (int)ci;
+            // w_i = A q_{i-1}, sketched: p_i (step 3 of Algorithm 3, step 1 of Algorithm 2)
+            if (!launch_stencil_sketch<T, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
+                                             sa.status))
+                return RGS_EDEVICE;
+            if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef)) return RGS_EDEVICE;
+            if (!launch_project<T, T>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), 1, 1, vec_ok ? 1 : 0, sk, part,
+                                      sa.status))
+                return RGS_EDEVICE;
+            if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef))
+                return RGS_EDEVICE;
+            if (!launch_givens(s, i, R, (int)mcap, Hr, cs, sn, gv, bnorm, d->tol, hist, sa.status, used))
+                return RGS_EDEVICE;
+        }
+        if (!launch_update_x<T>(s, Hr, (int)mcap, gv, used, y, x, Q, n, n)) return RGS_EDEVICE;
+        if (!launch_residual(s, A, b, x, r, rpart, norm)) return RGS_EDEVICE;
+        int stat[4] = {0, 0, 0, 0};
+        int u = 0;
+        double rn = 0.0;
+        if (hipMemcpyAsync(stat, sa.status, sizeof(stat), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&u, used, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&rn, norm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hh.data(), hist, mcap * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return RGS_EDEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+        ++cycles;
+        iters += u;
+        for (int t = 0; t < u && nhist < hist_cap && res_hist; ++t) res_hist[nhist++] = hh[t];
+        relres = rn / bnorm;
+        if (stat[0] == kStatusNonfinite || !std::isfinite(rn)) {
+            result = RGS_ENONFINITE;
+            break;
+        }
+        if (relres <= d->tol) break;
+        if (u == 0) {             // no inner step could run: breakdown of the very first column
+            result = RGS_ENOCONV;
+            break;
+        }
+    }
+    if (!(bnorm > 0) && std::isfinite(bnorm)) relres = 0.0;
+    if (!std::isfinite(bnorm)) result = RGS_ENONFINITE;
+    const auto t1 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->failed_column = -1;
+        rep->iters = iters;
+        rep->cycles = cycles;
+        rep->delta_F = NAN;
+        rep->delta_tilde_F = NAN;
+        rep->true_relres = relres;
+        rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+        rep->proj_kernel_ms = 0.0;
+        rep->proj_launches = iters;
+    }
+    return result;
 }
 
 }  // namespace
@@ -448,6 +603,50 @@ rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j
     const bool ok = d->prec == RGS_P_FP64
                         ? launch_materialize<double>(h->stream, sk, j0, j1, l0, l1, rsk, out, ldo)
                         : launch_materialize<float>(h->stream, sk, j0, j1, l0, l1, rsk, out, ldo);
+    if (!ok) return RGS_EDEVICE;
+    return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+}
+
+rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc* d, const double* b, double* x,
+                     double* res_hist, int64_t hist_cap, rgs_report* rep) {
+    if (!h || !A || !d || !b || !x || hist_cap < 0) return RGS_EINVAL;
+    if (A->nx < 1 || A->ny < 1 || A->nz < 1) return RGS_EINVAL;
+    const int64_t n = A->nx * A->ny * A->nz;
+    if (n > ((int64_t)1 << 31) - 1) return RGS_EINVAL;
+    if (d->restart < 1 || d->restart + 1 > d->k || d->restart > 4000 || d->max_iters < 1 || !(d->tol >= 0))
+        return RGS_EINVAL;
+    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64) return RGS_EINVAL;
+    rgs_qr_desc q{};
+    q.n = n;
+    q.m = d->restart + 1;
+    q.k = d->k;
+    q.sketch = d->sketch;
+    q.prec = d->prec;
+    if (!valid_desc(&q, true)) return RGS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    if (d->prec == RGS_P_FP64) return run_gmres<double>(h, A, d, b, x, res_hist, hist_cap, rep);
+    return run_gmres<float>(h, A, d, b, x, res_hist, hist_cap, rep);
+}
+
+rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec, const void* u, void* w) {
+    if (!h || !Ad || !u || !w) return RGS_EINVAL;
+    if (Ad->nx < 1 || Ad->ny < 1 || Ad->nz < 1) return RGS_EINVAL;
+    if (Ad->nx * Ad->ny * Ad->nz > ((int64_t)1 << 31) - 1) return RGS_EINVAL;
+    if (prec != RGS_P_FP64 && prec != RGS_P_FP32_LS64) return RGS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    rgs_status st = ensure_arena(h, 4096);
+    if (st != RGS_OK) return st;
+    int* status = reinterpret_cast<int*>(h->arena);
+    if (hipMemsetAsync(status, 0, 4 * sizeof(int), h->stream) != hipSuccess) return RGS_EDEVICE;
+    const StencilArgs A = stencil_args(Ad);
+    SketchArgs sk{};
+    bool ok;
+    if (prec == RGS_P_FP64)
+        ok = launch_stencil_sketch<double, double>(h->stream, A, static_cast<const double*>(u), nullptr,
+                                                   static_cast<double*>(w), 0, sk, nullptr, status);
+    else
+        ok = launch_stencil_sketch<float, float>(h->stream, A, static_cast<const float*>(u), nullptr,
+                                                 static_cast<float*>(w), 0, sk, nullptr, status);
     if (!ok) return RGS_EDEVICE;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
 }

@@ -20,6 +20,13 @@ struct SketchArgs {
     const int* rows;        // SRHT: sampled rows of H_s
 };
 
+// The 7-point operator: (A u)_l = c[0] u_l + c[1] u_{x-1} + c[2] u_{x+1} + c[3] u_{y-1}
+// + c[4] u_{y+1} + c[5] u_{z-1} + c[6] u_{z+1}, Dirichlet 0 outside the box.
+struct StencilArgs {
+    int64_t nx, ny, nz;
+    double c[7];
+};
+
 // Device pointers of the sketch-space state (all fp64).
 struct SpaceArgs {
     int k, mcap;
@@ -31,7 +38,8 @@ struct SpaceArgs {
     double *pd, *pd2;       // per-slice partial sums: nsl x (mcap+1), nsl
     double* pdb;            // per-slice partials for the next right-hand side: nsl x (mcap+2)
     double *rr, *invr, *pnorm, *tau, *beta;  // per-column scalars (mcap each)
-    int* status;            // [0] = kStatus*, [1] = failed column
+    double* pbuf;           // k: sketch of the current Arnoldi vector
+    int* status;            // [0] = kStatus*, [1] = failed column, [2] = cycle done
 };
 
 bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const SketchArgs& sk);
@@ -59,5 +67,24 @@ bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_
                         double rsk, double* out, int64_t ldo);
 bool launch_diagnostics(hipStream_t st, const double* P, int64_t ldp, const double* S, int64_t lds,
                         const double* R, int64_t ldr, int k, int m, double* gram_out, double* resid_out);
+
+template <typename T, typename PT>
+bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const T* qp, const double* invr, T* w,
+                           int do_sketch, const SketchArgs& sk, PT* partials, const int* status);
+bool launch_residual(hipStream_t st, const StencilArgs& A, const double* b, const double* x, double* r,
+                     double* part, double* norm_out);
+template <typename T>
+bool launch_cast(hipStream_t st, const double* src, T* dst, int64_t n);
+bool launch_givens_init(hipStream_t st, const double* R, double* gv, int* used);
+bool launch_givens(hipStream_t st, int c, const double* R, int mcap, double* Hr, double* cs, double* sn,
+                   double* gv, double bnorm, double tol, double* hist, int* status, int* used);
+template <typename T>
+bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* gv, const int* used, double* y,
+                     double* x, const T* Q, int64_t ldq, int64_t n);
+// Step 2 when the right-hand side arrives as block partials (Arnoldi): reduce to
+// a.pbuf, then the least-squares solve of column i (R(0:i, i) and coef).
+template <typename T, typename PT>
+bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
+                        double* R, int64_t ldr, T* coef);
 
 }  // namespace rgs

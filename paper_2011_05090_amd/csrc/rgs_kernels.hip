@@ -21,6 +21,7 @@
 
 #include <algorithm>
 
+#include "rgs_block.hpp"
 #include "rgs_device.hpp"
 #include "rgs_internal.hpp"
 
@@ -31,169 +32,10 @@ namespace rgs {
 #define RGS_EXIT_IF_FAILED(status)                      \
     do {                                                \
         __shared__ int rgs_stop_;                       \
-        if (threadIdx.x == 0) rgs_stop_ = (status)[0];  \
+        if (threadIdx.x == 0) rgs_stop_ = (status)[0] | (status)[2]; \
         __syncthreads();                                \
         if (rgs_stop_ != 0) return;                     \
     } while (0)
-
-// ---------------------------------------------------------------------------
-// Loads/stores of the 16 rows a lane owns in a wave tile:
-// rows row0[e] .. row0[e] + 3, e = 0..3 (row0[e] is a multiple of 4).
-// Full tiles use nontemporal vector accesses: every column of W and Q is
-// touched once per pass and the basis is far larger than any cache level.
-// ---------------------------------------------------------------------------
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-__device__ __forceinline__ void load16(const T* __restrict__ p, const int64_t row0[4], int64_t n,
-                                       bool full, T v[16]) {
-    if (full) {
-        if constexpr (sizeof(T) == 4) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p + row0[e]));
-                v[4 * e] = t.x;
-                v[4 * e + 1] = t.y;
-                v[4 * e + 2] = t.z;
-                v[4 * e + 3] = t.w;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + row0[e]));
-                const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + row0[e] + 2));
-                v[4 * e] = a.x;
-                v[4 * e + 1] = a.y;
-                v[4 * e + 2] = b.x;
-                v[4 * e + 3] = b.y;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[4 * e + r] = (row0[e] + r < n) ? p[row0[e] + r] : T(0);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void store16(T* __restrict__ p, const int64_t row0[4], int64_t n,
-                                        bool full, const T v[16]) {
-    if (full) {
-        if constexpr (sizeof(T) == 4) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const f32x4 t = {v[4 * e], v[4 * e + 1], v[4 * e + 2], v[4 * e + 3]};
-                __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p + row0[e]));
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const f64x2 a = {v[4 * e], v[4 * e + 1]};
-                const f64x2 b = {v[4 * e + 2], v[4 * e + 3]};
-                __builtin_nontemporal_store(a, reinterpret_cast<f64x2*>(p + row0[e]));
-                __builtin_nontemporal_store(b, reinterpret_cast<f64x2*>(p + row0[e] + 2));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (row0[e] + r < n) p[row0[e] + r] = v[4 * e + r];
-    }
-}
-
-// Rows of this lane in block blk of a workgroup with NW wave tiles.
-template <int NW>
-__device__ __forceinline__ void lane_rows(int64_t blk, int64_t row0[4]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) row0[e] = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
-}
-
-// ---------------------------------------------------------------------------
-// Sketch of one block of NW * 1024 rows held in registers (v = this lane's 16
-// rows), accumulated into acc[u] for the sketch rows j = threadIdx.x + 64 NW u.
-// The 1/sqrt(k) scale is applied later, in fp64.
-//
-// SRHT: with s = 2^a T (T = 1024 the in-wave FWHT order) the Sylvester
-// Hadamard matrix factors as H_s = H_{s/T} (x) H_T, so for a sampled row
-// rho = alpha T + beta and the tile index t of rows [tT, (t+1)T):
-//   (H_s D x)[rho] = sum_t (-1)^popcount(alpha & t) (H_T D x_t)[beta].
-// Each wave transforms its tile in registers; the block's NW tiles are then
-// combined per sampled row through LDS (tile t = NW blk + w, and since the
-// bits of w and NW blk are disjoint the sign factors into both parts).
-// Gaussian: theta_{j,l} generated on the fly, 4 entries per Philox call.
-// ---------------------------------------------------------------------------
-template <typename T, typename PT, int SK, int NW>
-__device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, const SketchArgs& sk,
-                                             PT acc[kKptMax], T* __restrict__ lds) {
-    constexpr int NT = NW * kWave;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int kpt = (sk.k + NT - 1) / NT;
-    if constexpr (SK == SK_SRHT) {
-        int64_t row0[4];
-        lane_rows<NW>(blk, row0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (row0[e] < n) {
-                const uint32_t word = sk.signs[row0[e] >> 5];
-                const int sh = (int)(row0[e] & 31);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if ((word >> (sh + r)) & 1u) v[4 * e + r] = -v[4 * e + r];
-            }
-        }
-        fwht1024_wave<T>(v, lane);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
-        __syncthreads();
-        const uint32_t tb = (uint32_t)(blk * NW);  // tile index of wave 0
-#pragma unroll
-        for (int u = 0; u < kKptMax; ++u) {
-            const int j = t + NT * u;
-            if (u < kpt && j < sk.k) {
-                const uint32_t rho = (uint32_t)sk.rows[j];
-                const uint32_t alpha = rho >> 10, beta = rho & 1023u;
-                T tot = T(0);
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const T z = lds[w * kTile + beta];
-                    tot = (__popc(alpha & (uint32_t)w) & 1) ? tot - z : tot + z;
-                }
-                if (__popc(alpha & tb) & 1) tot = -tot;
-                acc[u] += (PT)tot;
-            }
-        }
-        __syncthreads();
-    } else if constexpr (SK == SK_GAUSS) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
-        __syncthreads();
-        const int64_t rem = n - blk * (NW * kTile);
-        const int nq = rem >= NW * kTile ? NW * kTile / 4 : (int)((rem + 3) / 4);
-        const uint32_t q0 = (uint32_t)(blk * (NW * kTile / 4));
-        for (int q = 0; q < nq; ++q) {
-            const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
-#pragma unroll
-            for (int u = 0; u < kKptMax; ++u) {
-                const int j = t + NT * u;
-                if (u < kpt && j < sk.k) {
-                    T z[4];
-                    gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
-                    acc[u] += (PT)(z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3);
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
 
 // SRHT diagonal D as a bit table: bit b of word w is set iff d_{32w+b} = -1.
 // Word w comes from word (w mod 4) of Philox(w/4, 0xFFFFFFFF, sketch_id, instance).
@@ -537,7 +379,7 @@ __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double*
         invr[i] = 1.0 / rii;
         R[i + (int64_t)i * ldr] = rii;
         const double pn = (i == 0) ? rii : pnorm[i];
-        if (status[0] == 0) {
+        if (status[0] == 0 && status[2] == 0) {
             if (!isfinite(rii) || !isfinite(pn)) {
                 status[1] = i;
                 status[0] = kStatusNonfinite;
@@ -604,7 +446,7 @@ __global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double*
         if (blockIdx.x == 0) {
             tau_a[i] = tau;
             beta_a[i] = beta;
-            if (status[0] == 0 && !(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1}) in sketch space
+            if (status[0] == 0 && status[2] == 0 && !(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1})
                 status[1] = i;
                 status[0] = kStatusBreakdown;
             }
@@ -878,6 +720,23 @@ bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, doubl
 }
 
 template <typename T, typename PT>
+bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
+                        double* R, int64_t ldr, T* coef) {
+    const int nsl = (a.k + kSlice - 1) / kSlice;
+    hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, (const double*)nullptr, a.k, i,
+                       a.Wr, a.mcap, a.pbuf, a.pd);
+    RGS_LAUNCH_CHECK();
+    const unsigned nrb = nblocks(i, 64);
+    hipLaunchKernelGGL(k_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, a.pbuf, a.k, i, nsl, a.Vc,
+                       a.mcap, a.pd, a.uh, a.pnorm);
+    RGS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, a.X, a.mcap, a.uh, R,
+                       ldr, coef);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename T, typename PT>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
                    const double* pnext, T* coef) {
@@ -952,6 +811,10 @@ template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double
 template bool launch_scale_col<double>(hipStream_t, double*, int64_t, const double*, const int*);
 template bool launch_ls<float>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, float*);
 template bool launch_ls<double>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, double*);
+template bool launch_ls_partials<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, int,
+                                               double*, int64_t, float*);
+template bool launch_ls_partials<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double, int,
+                                                 double*, int64_t, double*);
 template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, const double*,
                                           int, double*, int64_t, double*, int64_t, const double*, float*);
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,

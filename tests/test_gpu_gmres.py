@@ -1,0 +1,137 @@
+"""GPU parity of the RGMRES path (Algorithm 3 + Sec. 4.2) against the oracle.
+
+* the 7-point mat-vec of Algorithm 3 (fp64 bit-near, fp32 to rounding);
+* restarted randomized GMRES on convection-diffusion systems of the recipe
+  (grids that span several 8192-row blocks plus a ragged one): iteration
+  count within +-2 of the fp64 oracle, residual history, true residual;
+* fp32 basis / fp64 least squares against the fp64 oracle's iteration count;
+* the identity sketch (k = n) reproduces textbook GMRES iterates;
+* lucky breakdown (A = I) and the max_iters cap.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gmres as ogm, sketch as osk, stencil as ost
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _rgs():
+    import paper_2011_05090_amd as rgs
+    return rgs
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stencil_apply_matches_oracle(gpu_handle, prec):
+    rgs = _rgs()
+    dims, coeffs = synth.convdiff_coeffs(23, 37.0)
+    dims = (23, 19, 29)
+    n = 23 * 19 * 29
+    u = np.random.Generator(np.random.PCG64(3)).standard_normal(n)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        u = u.astype(np.float32).astype(np.float64)
+    w = torch.empty(n, dtype=dt, device="cuda")
+    rgs.rgs_stencil_apply(gpu_handle, rgs.stencil7(dims, coeffs), prec, dev(u, dt), w)
+    torch.cuda.synchronize()
+    ref = ost.apply(u, dims, coeffs, np.float64)
+    got = w.cpu().numpy().astype(np.float64)
+    tol = 1e-14 if prec == "fp64" else 4e-7
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def _oracle(N, Pe, restart, k, tol, sketch, precision, tag, max_iters=100000):
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=tag)
+    out = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b,
+                     lambda c: osk.make(sketch, n, k, seed=42, sketch_id=2 + c),
+                     restart=restart, tol=tol, precision=precision, max_iters=max_iters)
+    return dims, coeffs, b, out
+
+
+def _gpu(h, dims, coeffs, b, restart, k, tol, sketch, prec, max_iters=100000):
+    rgs = _rgs()
+    n = b.size
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    rep, hist = rgs.rgs_gmres(h, rgs.stencil7(dims, coeffs),
+                              rgs.gmres_desc(restart, k, tol, max_iters=max_iters, sketch=sketch, prec=prec),
+                              dev(b), x, res_hist=100000)
+    torch.cuda.synchronize()
+    return rep, np.array(hist), x.cpu().numpy()
+
+
+@pytest.mark.parametrize("sketch", ["gaussian", "srht"])
+def test_rgmres_fp64_matches_oracle(gpu_handle, sketch):
+    N, Pe, restart, k, tol = 24, 50.0, 20, 96, 1e-6        # n = 13824: 2 blocks, ragged
+    dims, coeffs, b, ref = _oracle(N, Pe, restart, k, tol, sketch, "fp64", tag=1)
+    rep, hist, x = _gpu(gpu_handle, dims, coeffs, b, restart, k, tol, sketch, "fp64")
+    assert rep.status == 0 and ref["converged"]
+    assert abs(rep.iters - ref["iters"]) <= 2
+    assert rep.cycles == ref["cycles"]
+    assert rep.true_relres <= tol
+    r = b - ost.apply(x, dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
+    # the residual histories agree while both are far above rounding level
+    L = min(len(hist), len(ref["hist"]), restart)
+    np.testing.assert_allclose(hist[:L], ref["hist"][:L], rtol=1e-8)
+
+
+def test_rgmres_fp32_basis_iterations_near_fp64_oracle(gpu_handle):
+    N, Pe, restart, k, tol = 32, 50.0, 30, 120, 1e-6        # n = 32768: 4 full blocks
+    dims, coeffs, b, ref = _oracle(N, Pe, restart, k, tol, "gaussian", "fp64", tag=2)
+    rep, hist, x = _gpu(gpu_handle, dims, coeffs, b, restart, k, tol, "gaussian", "fp32")
+    assert rep.status == 0
+    assert abs(rep.iters - ref["iters"]) <= 2
+    r = b - ost.apply(x, dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
+    # the fp32 model of the oracle agrees as well
+    _, _, _, ref32 = _oracle(N, Pe, restart, k, tol, "gaussian", "fp32", tag=2)
+    assert abs(rep.iters - ref32["iters"]) <= 2
+
+
+def test_identity_sketch_is_textbook_gmres(gpu_handle):
+    N, Pe = 6, 30.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=3)
+    j = 12
+    rep, hist, x = _gpu(gpu_handle, dims, coeffs, b, j, n, 0.0, "identity", "fp64", max_iters=j)
+    # x minimises ||b - A x|| over K_j(A, b): brute-force least squares on that space
+    A = np.stack([ost.apply(e, dims, coeffs) for e in np.eye(n)], axis=1)
+    K = np.empty((n, j))
+    v = b.copy()
+    for t in range(j):
+        K[:, t] = v
+        v = A @ v
+    U, _ = np.linalg.qr(K)
+    z, *_ = np.linalg.lstsq(A @ U, b, rcond=None)
+    xref = U @ z
+    assert np.abs(x - xref).max() <= 1e-9 * np.abs(xref).max()
+
+
+def test_lucky_breakdown_identity_operator(gpu_handle):
+    dims = (10, 10, 10)
+    coeffs = (1.0, 0, 0, 0, 0, 0, 0)
+    b = synth.rhs(1000, tag=4)
+    rep, hist, x = _gpu(gpu_handle, dims, coeffs, b, 10, 64, 1e-12, "gaussian", "fp64")
+    assert rep.status == 0 and rep.iters == 1
+    assert np.abs(x - b).max() <= 1e-14 * np.abs(b).max()
+
+
+def test_max_iters_cap(gpu_handle):
+    rgs = _rgs()
+    N = 16
+    dims, coeffs = synth.convdiff_coeffs(N, 20.0)
+    b = synth.rhs(N ** 3, tag=5)
+    rep, hist, x = _gpu(gpu_handle, dims, coeffs, b, 10, 64, 1e-14, "gaussian", "fp32", max_iters=7)
+    assert rep.status == rgs.RGS_ENOCONV
+    assert rep.iters == 7 and len(hist) == 7
+    assert np.all(np.diff(hist) <= 1e-12)         # GMRES residuals never increase within a cycle
