@@ -45,6 +45,29 @@ def project_bytes(n, m, b):
     return b * n * (2 + sum(i + 3 for i in range(1, m)))
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_project_srht_f32_n4194304_m512_k2048_traffic.json")
+
+
+def measured_traffic(n, m, k):
+    """HBM bytes per launch of the projection kernel from the committed counter
+    record, or None when the record is for another size or the kernel sources
+    have changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if (n, m, k) != (1 << 22, 512, 2048):
+        return None
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def run_steps(rgs, torch, h, desc, W, Q, R, S, steps, warmup):
     for _ in range(warmup):
         rgs.rgs_qr(h, desc, W, Q, R, S)
@@ -60,18 +83,21 @@ def run_steps(rgs, torch, h, desc, W, Q, R, S, steps, warmup):
 
 
 def quality(torch, W, Q, R, S):
-    """||W - QR||_F/||W||_F, ||I - S^T S||_2, ||I - Q^T Q||_2 in fp64 (not timed)."""
+    """||W - QR||_F/||W||_F, ||I - S^T S||_2, ||I - Q^T Q||_2 in fp64 (not timed).
+    Products on the device, the m x m spectral norms on the host."""
+    import numpy as np
     W64 = W.double()
     Q64 = Q.double()
     res = torch.linalg.norm(W64 - Q64 @ R) / torch.linalg.norm(W64)
     m = S.shape[1]
-    I = torch.eye(m, dtype=torch.float64, device=S.device)
-    d2 = torch.linalg.matrix_norm(I - S.T @ S, ord=2)
-    o2 = torch.linalg.matrix_norm(I - Q64.T @ Q64, ord=2)
+    I = np.eye(m)
+    d2 = np.linalg.norm(I - (S.T @ S).cpu().numpy(), 2)
+    o2 = np.linalg.norm(I - (Q64.T @ Q64).cpu().numpy(), 2)
+    del W64, Q64
     return float(res), float(d2), float(o2)
 
 
-def cpu_baseline(n=1 << 20, m=32, k=2048):
+def cpu_baseline(n=1 << 21, m=48, k=2048):
     """The oracle (fp32 model, SRHT) on a bounded sample, on the host cores."""
     import numpy as np
     import synth
@@ -90,6 +116,32 @@ def cpu_baseline(n=1 << 20, m=32, k=2048):
             "sample": "oracle fp32-model RGS, P-SRHT k=%d, W %dx%d (sigma 1..1e-8), %.1f s wall" % (k, n, m, dt)}
 
 
+def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6):
+    """Time-to-1e-6 of restarted randomized GMRES on the 7-point convection-diffusion
+    system (N^3 unknowns, b ~ N(0,1)), fp32 basis vs plain fp64, Gaussian and SRHT."""
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = torch.from_numpy(synth.rhs(n, tag=0)).to("cuda")
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    A = rgs.stencil7(dims, coeffs)
+    res = {"grid": N, "n": n, "Pe": Pe, "restart": restart, "k": k, "tol": tol}
+    for sketch in ("gaussian", "srht"):
+        for prec in ("fp32", "fp64"):
+            d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch=sketch, prec=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep, _ = rgs.rgs_gmres(h, A, d, b, x)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res["%s_%s" % (sketch, prec)] = {"seconds_to_tol": dt, "iters": rep.iters, "cycles": rep.cycles,
+                                             "true_relres": rep.true_relres, "status": rep.status}
+            log("  rgmres %s/%s: %d iters, %d cycles, relres %.2e, %.3f s" %
+                (sketch, prec, rep.iters, rep.cycles, rep.true_relres, dt))
+        res["%s_speedup_fp32_vs_fp64" % sketch] = (res["%s_fp64" % sketch]["seconds_to_tol"] /
+                                                   res["%s_fp32" % sketch]["seconds_to_tol"])
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,12 +150,16 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--m", type=int, default=512)
     ap.add_argument("--k", type=int, default=2048)
-    ap.add_argument("--no-extra", action="store_true", help="skip the fp64 / Gaussian / companion legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the fp64 / Gaussian / companion QR legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gmres", action="store_true", help="skip the randomized GMRES leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the row-block sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "(rows would be sharded by blocks with one all-reduce of the sketch per column); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -145,7 +201,7 @@ def main():
                    "W": "U diag(logspace(0,-8,m)) V^T, U,V from QR of seeded N(0,1)",
                    "pct_hbm_peak": 100 * value / HBM_PEAK_GBS, "bytes_per_step": B},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n, m, k),
                      "kernel": "k_project<float,float,SRHT>",
                      "avg_launch_ms": avg_launch_ms, "avg_launch_bytes": avg_launch_bytes},
         "quality": {"backward_error": res, "norm2_I_minus_StS": d2, "norm2_I_minus_QtQ": o2},
@@ -183,6 +239,17 @@ def main():
                                          "norm2_I_minus_QtQ": co2}
         log("  companion sigma->1e-3: ||W-QR||/||W|| %.2e  ||I-S^TS||_2 %.2e" % (cres, cd2))
         out["extra"] = extra
+    if not args.no_gmres:
+        out.setdefault("extra", {})["rgmres_convdiff_192"] = gmres_leg(rgs, torch, synth, h)
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline()

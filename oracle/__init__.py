@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
 Python binding) may import, call or link anything in this package.  Only the
-test-suite, the smoke check of the graft entry point and the CPU-baseline leg
+test-suite, the smoke check in __graft_entry__.py and the CPU-baseline leg
 of the benchmark use it.
 
 It follows Balabanov & Grigori, "Randomized Gram-Schmidt process with

@@ -83,16 +83,23 @@ def batch_gmres_sizes(batch, N_lo=32, N_hi=96, pe_lo=1.0, pe_hi=100.0, tag=0):
 def svd_matrix_torch(n, m, sigma_min, tag=0, device="cuda"):
     """Device-side draw of the same recipe as ``svd_matrix`` for sizes a host QR
     would take minutes on (fp64, column-major (n, m) tensor).  Uses torch's
-    seeded device generator, so its values differ from ``svd_matrix``'s."""
+    seeded device generator, so its values differ from ``svd_matrix``'s.
+    The Q factor of the tall Gaussian G is formed by Cholesky QR
+    (G^T G = C^T C, U = G C^-1): the same positive-diagonal QR factor, accurate
+    to rounding because a tall Gaussian matrix is well conditioned.  Only
+    matrix products run on the device; the m x m factorisations run on the host."""
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(ROOT_ENTROPY * 1000 + int(tag))
     G = torch.randn((n, m), generator=gen, dtype=torch.float64, device=device)
-    U, _ = torch.linalg.qr(G)
+    gram = (G.T @ G).cpu().numpy()
+    C = np.linalg.cholesky(gram).T                       # gram = C^T C, C upper
+    Cinv = np.linalg.inv(C)
+    U = G @ torch.from_numpy(Cinv).to(device)
     del G
-    H = torch.randn((m, m), generator=gen, dtype=torch.float64, device=device)
-    V, _ = torch.linalg.qr(H)
-    sigma = torch.logspace(0.0, float(np.log10(sigma_min)), m, dtype=torch.float64, device=device)
-    W = (U * sigma[None, :]) @ V.T.contiguous()
+    V, _ = np.linalg.qr(rng("V", m, tag).standard_normal((m, m)))
+    sigma = np.logspace(0.0, np.log10(sigma_min), m)
+    SVt = torch.from_numpy(np.ascontiguousarray((sigma[:, None] * V.T))).to(device)
+    W = U @ SVt
     del U
     return W.t().contiguous().t()          # column-major copy

@@ -1,0 +1,129 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py times.
+
+The factorisation W = Q R (n = 2^22, m = 512, k = 2048, fp32 projection with
+fp64 least squares; W = U diag(logspace(0,-8,m)) V^T drawn on the device) is
+too large for the oracle to redo, so it is checked
+* on sampled outputs the oracle recomputes one column at a time: given the
+  device's Q_{i-1} and S_{i-1} as inputs, the oracle's step of Algorithm 2
+  for column i must reproduce R(1:i, i), r_ii and q_i;
+* on S = Theta Q at sampled columns (the oracle's own P-SRHT applied to the
+  device's Q);
+* on properties that hold at any size: ||W - QR|| / ||W||, and on a
+  companion input with sigma down to 1e-3 the fp32-path gate ||I - S^T S||_2 <= 1e-4.
+The randomized GMRES of the same suite (192^3 grid, restart 100, k = 400,
+tol 1e-6) is checked by recomputing its true residual with the oracle's
+operator in fp64.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rgs as orgs, sketch as osk, stencil as ost
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N, M, K = 1 << 22, 512, 2048
+
+
+def _rgs():
+    import paper_2011_05090_amd as rgs
+    return rgs
+
+
+@pytest.fixture(scope="module")
+def big_qr(gpu_handle):
+    rgs = _rgs()
+    W64 = synth.svd_matrix_torch(N, M, 1e-8, tag=0)
+    W = rgs.colmajor(N, M, torch.float32)
+    W.copy_(W64)
+    del W64
+    Q = rgs.colmajor(N, M, torch.float32)
+    R = rgs.colmajor(M, M, torch.float64)
+    S = rgs.colmajor(K, M, torch.float64)
+    rep = rgs.rgs_qr(gpu_handle, rgs.qr_desc(N, M, K, sketch="srht", prec="fp32"), W, Q, R, S)
+    torch.cuda.synchronize()
+    assert rep.status == 0
+    yield W, Q, R, S
+    del W, Q, R, S
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_backward_error(big_qr):
+    W, Q, R, S = big_qr
+    res = torch.linalg.norm(W.double() - Q.double() @ R) / torch.linalg.norm(W.double())
+    assert float(res) <= 1e-5
+    Rh = R.cpu().numpy()
+    assert np.all(np.tril(Rh, -1) == 0) and np.all(np.diag(Rh) > 0)
+
+
+@pytest.mark.parametrize("cols", [(0, 1, 255, 511)])
+def test_fullsize_sketch_of_q(big_qr, cols):
+    W, Q, R, S = big_qr
+    th = osk.SRHT(N, K, seed=42)
+    for c in cols:
+        q = Q[:, c].cpu().numpy().astype(np.float64)
+        s = S[:, c].cpu().numpy()
+        sq = th.apply(q)
+        assert np.linalg.norm(s - sq) <= 2e-6 * np.linalg.norm(s)
+
+
+@pytest.mark.parametrize("col", [1, 64, 200])
+def test_fullsize_sampled_column_steps(big_qr, col):
+    W, Q, R, S = big_qr
+    th = osk.SRHT(N, K, seed=42)
+    Qprev = Q[:, :col].cpu().numpy()                    # device basis (float32) as the oracle's input
+    Sprev = S[:, :col].cpu().numpy()
+    w = W[:, col].cpu().numpy()
+    st = orgs.rgs_step(Qprev, Sprev, w, th, precision="fp32")
+    Rg = R[:, col].cpu().numpy()
+    np.testing.assert_allclose(Rg[:col], st["r"], rtol=0, atol=2e-6 * np.abs(st["r"]).max())
+    # q'_i = w_i - Q r carries fp32 rounding of order sqrt(i) u32 ||w_i|| on both
+    # sides (different summation orders); relative to q'_i that is amplified by
+    # ||w_i|| / ||q'_i||, which grows as the columns of W become dependent.
+    amp = np.linalg.norm(w.astype(np.float64)) / np.linalg.norm(st["qp"].astype(np.float64))
+    tol = 50 * 2.0 ** -24 * math.sqrt(col + 1) * amp
+    assert abs(Rg[col] - st["rii"]) <= tol * st["rii"]
+    qg = Q[:, col].cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(qg - st["q"]) <= tol * np.linalg.norm(st["q"])
+
+
+def test_fullsize_companion_gate(gpu_handle):
+    rgs = _rgs()
+    W64 = synth.svd_matrix_torch(N, M, 1e-3, tag=1)
+    W = rgs.colmajor(N, M, torch.float32)
+    W.copy_(W64)
+    del W64
+    Q = rgs.colmajor(N, M, torch.float32)
+    R = rgs.colmajor(M, M, torch.float64)
+    S = rgs.colmajor(K, M, torch.float64)
+    rep = rgs.rgs_qr(gpu_handle, rgs.qr_desc(N, M, K, sketch="srht", prec="fp32"), W, Q, R, S)
+    torch.cuda.synchronize()
+    assert rep.status == 0
+    G = (S.T @ S).cpu().numpy()
+    assert np.linalg.norm(np.eye(M) - G, 2) <= 1e-4
+    res = torch.linalg.norm(W.double() - Q.double() @ R) / torch.linalg.norm(W.double())
+    assert float(res) <= 1e-5
+    del W, Q, R, S
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_rgmres_true_residual(gpu_handle):
+    rgs = _rgs()
+    Ng = 192
+    dims, coeffs = synth.convdiff_coeffs(Ng, 50.0)
+    n = Ng ** 3
+    b = synth.rhs(n, tag=0)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    rep, hist = rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs),
+                              rgs.gmres_desc(100, 400, 1e-6, max_iters=5000, sketch="srht", prec="fp32"),
+                              torch.from_numpy(b).cuda(), x, res_hist=5000)
+    torch.cuda.synchronize()
+    assert rep.status == 0 and rep.true_relres <= 1e-6
+    r = b - ost.apply(x.cpu().numpy(), dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6 * (1 + 1e-6)
+    assert len(hist) == rep.iters
+    assert math.isclose(rep.true_relres, np.linalg.norm(r) / np.linalg.norm(b), rel_tol=1e-6)
