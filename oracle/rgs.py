@@ -28,6 +28,12 @@ Precision models (Sec. 2.3, the paragraph after Algorithm 2):
   'fp64'  u_crs = u_fine = fp64;
   'fp32'  multi-precision: W and Q stored in float32 and step 3 done in
           float32 arithmetic with float32 accumulation; all other steps fp64.
+  'bf16q' as 'fp32', but the basis is stored in bfloat16 (round to nearest
+          even).  To keep S the sketch of what is stored, column i is kept
+          unnormalised as qb_i = bf16(q'_i) with an fp64 scale 1/r_ii, step 4
+          sketches qb_i, and step 3 uses the stored columns with the
+          coefficients y_c / r_cc rounded to float32.  The returned Q is
+          bf16(qb_i / r_ii).
 
 Breakdown (not specified by the paper): a non-finite p_i or s'_i, r_ii = 0,
 or r_ii <= 2**-50 ||p_i|| stops the factorisation and reports the column.
@@ -44,6 +50,14 @@ class Breakdown(Exception):
         super().__init__("breakdown at column %d%s" % (column, " (non-finite)" if nonfinite else ""))
         self.column = column
         self.nonfinite = nonfinite
+
+
+def bf16_round(x):
+    """Round float32 values to the nearest bfloat16 (ties to even), returned as float32."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)) << np.uint64(16)
+    return (r & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.float32).reshape(x.shape)
 
 
 def _ls(S, p, method):
@@ -65,15 +79,18 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
     Returns dict(Q, R, S, P).  Q has the storage type of the precision model
     (fp64, or float32 for 'fp32'); R, S and P are fp64.  Raises Breakdown.
     """
-    if precision not in ("fp64", "fp32"):
+    if precision not in ("fp64", "fp32", "bf16q"):
         raise ValueError(precision)
     store = np.float64 if precision == "fp64" else np.float32
+    bf16 = precision == "bf16q"
     W = np.asarray(W).astype(store)
     n, m = W.shape
     k = theta.k
     if not (1 <= m <= k):
         raise ValueError("need 1 <= m <= k")
     Q = np.zeros((n, m), dtype=store)
+    Qb = np.zeros((n, m), dtype=np.float32) if bf16 else None   # stored unnormalised columns
+    scale = np.zeros(m)
     R = np.zeros((m, m))
     S = np.zeros((k, m))
     P = np.zeros((k, m))
@@ -83,7 +100,16 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
         P[:, i] = p
         if not np.all(np.isfinite(p)):
             raise Breakdown(i, True)
-        if i == 0:
+        if bf16:
+            if i == 0:
+                qp = w.copy()
+            else:
+                r = _ls(S[:, :i], p, ls)                 # step 2
+                R[:i, i] = r
+                qp = w - Qb[:, :i] @ (r * scale[:i]).astype(np.float32)   # step 3 on stored columns
+            Qb[:, i] = bf16_round(qp)
+            sp = theta.apply(Qb[:, i].astype(np.float64))                 # step 4: sketch of the stored column
+        elif i == 0:
             qp = w.copy()                                # q'_1 = w_1
             sp = p.copy()                                # s'_1 = p_1
         else:
@@ -98,7 +124,11 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
             raise Breakdown(i, False)
         R[i, i] = rii
         S[:, i] = sp / rii                               # step 6
-        Q[:, i] = (qp.astype(np.float64) / rii).astype(store)   # step 7
+        if bf16:
+            scale[i] = 1.0 / rii
+            Q[:, i] = bf16_round((Qb[:, i].astype(np.float64) * scale[i]).astype(np.float32))   # step 7
+        else:
+            Q[:, i] = (qp.astype(np.float64) / rii).astype(store)   # step 7
     return {"Q": Q, "R": R, "S": S, "P": P}
 
 

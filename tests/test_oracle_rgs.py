@@ -150,3 +150,29 @@ def test_sec51_qualitative_ordering():
     assert metrics.backward_error(W.astype(np.float32), out["Q"], out["R"]) < 1e-5
     # cond(S) estimates cond(Q) (Sec. 5.1, third panel)
     assert abs(math.log(metrics.cond(out["S"])) - math.log(c_rgs)) < math.log(2.0)
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    g = np.random.Generator(np.random.PCG64(11))
+    x = np.concatenate([g.standard_normal(20000) * 10.0 ** g.uniform(-20, 20, 20000),
+                        np.array([0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0, 1e-40])]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(rgs.bf16_round(x), ref)
+
+
+def test_bf16q_model_tolerances():
+    # bf16 storage (u = 2^-9) sets both the backward error and Delta: the rounding
+    # of q'_i to bf16 has a sketch with a component in span(S_{i-1}) of relative
+    # size ~u (Theorem 3.3 bounds Delta by the storage roundoff u_crs).
+    n, m, k = 8192, 48, 192
+    W = synth.svd_matrix(n, m, 1e-3, tag=21).astype(np.float32)
+    th = sketch.Gaussian(n, k, seed=42)
+    out = rgs.rgs_qr(W, th, precision="bf16q")
+    assert np.all(out["Q"] == rgs.bf16_round(out["Q"]))
+    be = metrics.backward_error(W, out["Q"], out["R"])
+    assert 1e-4 < be < 2e-2                      # bf16 unit roundoff 2^-9 = 2e-3
+    assert 1e-4 < metrics.delta_2(out["S"]) < 2e-2
+    assert metrics.cond(out["Q"]) < 5.0          # still well conditioned (Gaussian k = 4m)
+    out32 = rgs.rgs_qr(W, th, precision="fp32")
+    assert metrics.delta_2(out32["S"]) < 1e-2 * metrics.delta_2(out["S"])
