@@ -18,6 +18,9 @@
  *       RGS_P_FP64       -> double
  *       RGS_P_FP32_LS64  -> float   (step 3 in fp32; sketches, least
  *                                    squares and normalisation in fp64)
+ *       RGS_P_BF16Q_FP32_LS64 -> W and X float, Q bfloat16 (raw 16-bit
+ *                                    words): the basis is stored in bf16,
+ *                                    step 3 computes in fp32
  *     R, S, P, b, x and histories are always double.
  *   - Work is ordered on the handle's stream.  Calls that return a report
  *     synchronise that stream before returning.
@@ -57,8 +60,12 @@ typedef enum {
 } rgs_sketch;
 
 typedef enum {
-    RGS_P_FP64 = 0,       /* u_crs = u_fine = fp64 */
-    RGS_P_FP32_LS64 = 1   /* multi-precision model: u_crs = fp32, u_fine = fp64 */
+    RGS_P_FP64 = 0,            /* u_crs = u_fine = fp64 */
+    RGS_P_FP32_LS64 = 1,       /* multi-precision model: u_crs = fp32, u_fine = fp64 */
+    RGS_P_BF16Q_FP32_LS64 = 2  /* as FP32_LS64 with the basis stored in bfloat16 (round to nearest
+                                  even): columns are kept unnormalised with an fp64 scale 1/r_ii,
+                                  step 4 sketches the stored column, the coefficients of step 3
+                                  carry the scales, and the returned Q is bf16(q'_i / r_ii) */
 } rgs_precision;
 
 /* Flags for rgs_qr_desc.flags / rgs_gmres_desc.flags */
@@ -117,6 +124,19 @@ typedef struct {
     int64_t proj_launches;  /* number of projection+sketch launches */
 } rgs_report;
 
+/* One factorisation of a batched call (all pointers device memory, as in rgs_qr). */
+typedef struct {
+    int64_t n, m, k;      /* 1 <= m <= k, per factorisation */
+    const void *W;        /* n x m, ldw >= n, float */
+    int64_t ldw;
+    void *Q;              /* n x m, ldq >= n, float or bf16 per the batch precision */
+    int64_t ldq;
+    double *R;            /* m x m, ldr >= m */
+    int64_t ldr;
+    double *S;            /* k x m, lds >= k */
+    int64_t lds;
+} rgs_qr_item;
+
 /* Library version of this header (RGS_ABI_VERSION). */
 int rgs_abi_version(void);
 
@@ -148,6 +168,24 @@ rgs_status rgs_set_stream(rgs_handle *h, rgs_stream stream);
 rgs_status rgs_qr(rgs_handle *h, const rgs_qr_desc *desc,
                   const void *W, int64_t ldw, void *Q, int64_t ldq,
                   double *R, int64_t ldr, double *S, int64_t lds, rgs_report *rep);
+
+/* A batch of independent RGS QR factorisations (Algorithm 2, Sec. 2.3) of
+ * uneven sizes, advanced in lockstep: each column step is one launch of each
+ * kernel covering every factorisation that still has that column, so small
+ * factorisations fill the device together.
+ *   items (host array of `batch` <= 65535 entries) describe device buffers as in rgs_qr.
+ *   prec: RGS_P_FP32_LS64 or RGS_P_BF16Q_FP32_LS64.
+ *   Sketches: SRHT -- factorisation b uses counter word 3 (instance) = b;
+ *   GAUSSIAN -- every factorisation uses the leading k_b x n_b block of one
+ *   master Gaussian matrix (instance 0, entries scaled by 1/sqrt(k_b)).
+ *   item_status / failed_column (host arrays of `batch`, may be NULL) receive
+ *   each factorisation's status (RGS_OK, RGS_EBREAKDOWN, RGS_ENONFINITE) and
+ *   first invalid column (-1 if none).
+ * Returns RGS_OK when every factorisation succeeded, the first failing
+ * status otherwise, or EINVAL / ENOMEM / EDEVICE. */
+rgs_status rgs_qr_batched(rgs_handle *h, int64_t batch, const rgs_qr_item *items, int32_t sketch,
+                          int32_t prec, uint64_t seed, uint32_t sketch_id, int32_t *item_status,
+                          int64_t *failed_column, rgs_report *rep);
 
 /* Y = Theta X for ncols columns (the sketch of steps 1 and 4 of Algorithm 2).
  *   X [n x ncols, ldx >= n], element type per desc->prec; Y [k x ncols, ldy >= k].

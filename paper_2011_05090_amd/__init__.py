@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librgs.so")
 
 RGS_OK, RGS_EINVAL, RGS_ENOMEM, RGS_EDEVICE, RGS_EBREAKDOWN, RGS_ENONFINITE, RGS_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 SKETCH = {"gaussian": 0, "srht": 1, "identity": 2}
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16q": 2}
 FLAG_DIAGNOSTICS = 1
 FLAG_TIME_KERNELS = 2
 
@@ -48,6 +48,12 @@ class GmresDesc(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int64), ("max_iters", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("sketch", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("reuse_theta", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class QrItem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("W", ctypes.c_void_p), ("ldw", ctypes.c_int64), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64),
+                ("R", ctypes.c_void_p), ("ldr", ctypes.c_int64), ("S", ctypes.c_void_p), ("lds", ctypes.c_int64)]
 
 
 class Report(ctypes.Structure):
@@ -80,6 +86,9 @@ SIGNATURES = {
     "rgs_gmres": (ctypes.c_int, [_P, ctypes.POINTER(Stencil7), ctypes.POINTER(GmresDesc), _P, _P, _P, _I64,
                                  ctypes.POINTER(Report)]),
     "rgs_stencil_apply": (ctypes.c_int, [_P, ctypes.POINTER(Stencil7), ctypes.c_int32, _P, _P]),
+    "rgs_qr_batched": (ctypes.c_int, [_P, _I64, ctypes.POINTER(QrItem), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Report)]),
 }
 
 _lib = None
@@ -147,6 +156,16 @@ def _torch_dtype(prec):
     return torch.float64 if PREC[prec] == 0 else torch.float32
 
 
+def _dtypes(prec_code):
+    """(W dtype, Q dtype) of a precision code."""
+    import torch
+    if prec_code == 0:
+        return torch.float64, torch.float64
+    if prec_code == 2:
+        return torch.float32, torch.bfloat16
+    return torch.float32, torch.float32
+
+
 class Handle:
     """rgs_create / rgs_destroy.  Bound to a device and a stream (default: torch's current)."""
 
@@ -180,6 +199,7 @@ class Handle:
 
 
 def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=0, flags=0):
+    """prec: 'fp64', 'fp32' (fp32 projection, fp64 least squares) or 'bf16q' (bf16 basis)."""
     return QrDesc(n=n, m=m, k=k, seed=seed, sketch_id=sketch_id, instance=instance,
                   sketch=SKETCH[sketch], prec=PREC[prec], flags=flags, reserved=0)
 
@@ -187,12 +207,12 @@ def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=
 def rgs_qr(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
     """Algorithm 2 on W -> Q, R, S (all preallocated device tensors).  Returns the Report."""
     import torch
-    dt = torch.float64 if desc.prec == 0 else torch.float32
+    dw, dq = _dtypes(desc.prec)
     n, m, k = desc.n, desc.m, desc.k
     if tuple(W.shape) != (n, m) or tuple(Q.shape) != (n, m) or tuple(R.shape) != (m, m) or tuple(S.shape) != (k, m):
         raise ValueError("shape mismatch")
     rep = Report()
-    st = lib().rgs_qr(handle.ptr, ctypes.byref(desc), _dev(W, "W", dt), _ld(W, n), _dev(Q, "Q", dt), _ld(Q, n),
+    st = lib().rgs_qr(handle.ptr, ctypes.byref(desc), _dev(W, "W", dw), _ld(W, n), _dev(Q, "Q", dq), _ld(Q, n),
                       _dev(R, "R", torch.float64), _ld(R, m), _dev(S, "S", torch.float64), _ld(S, k),
                       ctypes.byref(rep))
     _check(st, "rgs_qr", allow)
@@ -200,10 +220,33 @@ def rgs_qr(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
     return rep
 
 
+def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id=0,
+                   allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
+    """A batch of factorisations; items = list of (W, Q, R, S, k) device tensors.
+    Returns (Report, per-item statuses, per-item failed columns)."""
+    import torch
+    dw, dq = _dtypes(PREC[prec])
+    arr = (QrItem * len(items))()
+    for b, (W, Q, R, S, k) in enumerate(items):
+        n, m = W.shape
+        if tuple(Q.shape) != (n, m) or tuple(R.shape) != (m, m) or tuple(S.shape) != (k, m):
+            raise ValueError("shape mismatch in item %d" % b)
+        arr[b] = QrItem(n=n, m=m, k=k, W=_dev(W, "W", dw), ldw=_ld(W, n), Q=_dev(Q, "Q", dq), ldq=_ld(Q, n),
+                        R=_dev(R, "R", torch.float64), ldr=_ld(R, m), S=_dev(S, "S", torch.float64), lds=_ld(S, k))
+    stat = (ctypes.c_int32 * len(items))()
+    fcol = (ctypes.c_int64 * len(items))()
+    rep = Report()
+    st = lib().rgs_qr_batched(handle.ptr, len(items), arr, SKETCH[sketch], PREC[prec], seed, sketch_id, stat, fcol,
+                              ctypes.byref(rep))
+    _check(st, "rgs_qr_batched", allow)
+    rep.status = st
+    return rep, list(stat), list(fcol)
+
+
 def rgs_sketch_apply(handle, desc, X, Y):
     """Y = Theta X (X: n x ncols column-major in the working precision; Y: k x ncols fp64)."""
     import torch
-    dt = torch.float64 if desc.prec == 0 else torch.float32
+    dt = _dtypes(desc.prec)[0]
     Xm = X if X.dim() == 2 else X.reshape(-1, 1)
     Ym = Y if Y.dim() == 2 else Y.reshape(-1, 1)
     ncols = Xm.shape[1]

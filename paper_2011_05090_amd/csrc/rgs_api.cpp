@@ -115,7 +115,7 @@ bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (!d) return false;
     if (d->n < 1 || d->k < 1) return false;
     if (need_m && (d->m < 1 || d->m > d->k)) return false;
-    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64) return false;
+    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64 && d->prec != RGS_P_BF16Q_FP32_LS64) return false;
     if (d->reserved != 0) return false;
     switch (d->sketch) {
         case RGS_SKETCH_GAUSSIAN:
@@ -247,8 +247,8 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const T* X, int64_
     return RGS_OK;
 }
 
-template <typename T>
-rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, T* Q, int64_t ldq, double* R,
+template <typename T, typename TQ, bool DEFER>
+rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, TQ* Q, int64_t ldq, double* R,
                   int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = d->n, m = d->m, k = d->k;
@@ -287,15 +287,20 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
         // of column i-1, then steps 5-6, the Householder append of s_i and step 2 for column i+1
         const double* pnext = (i + 1 < m) ? P + (i + 1) * k : nullptr;
         if (timed) (void)hipEventRecord(h->events[2 * i], s);
-        if (!launch_project<T, T>(s, W + i * ldw, Q, ldq, n, (int)i, coef, i > 0 ? sa.invr + (i - 1) : nullptr,
-                                  i > 0 ? 1 : 0, i > 0 ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
+        if (!launch_project<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
+                                          i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
+                                          (DEFER || i > 0) ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
-        if (!launch_column<T, T>(s, sa, part, Gp, scale, i == 0 ? P : nullptr, (int)i, S, lds, R, ldr, pnext,
-                                 coef))
+        if (!launch_column<T, T>(s, sa, part, Gp, scale, (i == 0 && !DEFER) ? P : nullptr, (int)i, S, lds, R, ldr,
+                                 pnext, coef, DEFER ? sa.invr : nullptr))
             return RGS_EDEVICE;
     }
-    if (!launch_scale_col<T>(s, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;
+    if constexpr (DEFER) {
+        if (!launch_scale_cols_bf16(s, Q, ldq, n, (int)m, sa.invr, sa.status)) return RGS_EDEVICE;
+    } else {
+        if (!launch_scale_col<T>(s, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;
+    }
 
     double* diag = reinterpret_cast<double*>(A + pl.diag);
     const bool want_diag = (d->flags & RGS_FLAG_DIAGNOSTICS) != 0;
@@ -433,9 +438,9 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
         // RGS step 1 of Algorithm 3: w_1 = r_0
         if (!launch_cast<T>(s, r, wbuf, n)) return RGS_EDEVICE;
-        if (!launch_project<T, T>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, 1, vec_ok ? 1 : 0, sk, part, sa.status))
+        if (!launch_project<T, T, false>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, 1, vec_ok ? 1 : 0, sk, part, sa.status))
             return RGS_EDEVICE;
-        if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, 0, S, k, R, mcap, nullptr, coef))
+        if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, 0, S, k, R, mcap, nullptr, coef, nullptr))
             return RGS_EDEVICE;
         if (!launch_givens_init(s, R, gv, used)) return RGS_EDEVICE;
         const int64_t steps = std::min<int64_t>(d->restart, d->max_iters - iters);
@@ -445,11 +450,11 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
             if (!launch_stencil_sketch<T, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
                                              sa.status))
                 return RGS_EDEVICE;
-            if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef)) return RGS_EDEVICE;
-            if (!launch_project<T, T>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), 1, 1, vec_ok ? 1 : 0, sk, part,
-                                      sa.status))
+            if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, nullptr)) return RGS_EDEVICE;
+            if (!launch_project<T, T, false>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), 1, 1, vec_ok ? 1 : 0, sk,
+                                             part, sa.status))
                 return RGS_EDEVICE;
-            if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef))
+            if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef, nullptr))
                 return RGS_EDEVICE;
             if (!launch_givens(s, i, R, (int)mcap, Hr, cs, sn, gv, bnorm, d->tol, hist, sa.status, used))
                 return RGS_EDEVICE;
@@ -492,6 +497,221 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         rep->seconds = std::chrono::duration<double>(t1 - t0).count();
         rep->proj_kernel_ms = 0.0;
         rep->proj_launches = iters;
+    }
+    return result;
+}
+
+// ---------------------------------------------------------------------------
+// Batched QR: every factorisation gets its own scratch; per column step the
+// host-built maps list (factorisation, local block) for each launch.
+// ---------------------------------------------------------------------------
+bool valid_item(const rgs_qr_item& it, int sk_kind) {
+    if (it.n < 1 || it.m < 1 || it.k < it.m || !it.W || !it.Q || !it.R || !it.S) return false;
+    if (it.ldw < it.n || it.ldq < it.n || it.ldr < it.m || it.lds < it.k) return false;
+    if (it.k > (int64_t)kKptMax * kWG || it.m > 4096) return false;
+    if (sk_kind == SK_SRHT && (it.k > srht_order(it.n) || it.n > ((int64_t)1 << 31))) return false;
+    if (sk_kind == SK_GAUSS && it.n > ((int64_t)1 << 34)) return false;
+    return true;
+}
+
+template <typename TQ, bool DEFER>
+rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
+                          uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    typedef float T;
+    hipStream_t s = h->stream;
+    std::vector<BatchItem> bi((size_t)batch);
+    std::vector<size_t> o_signs(batch), o_part(batch), o_P(batch), o_Vc(batch), o_Vr(batch), o_Wc(batch),
+        o_Wr(batch), o_X(batch), o_sp(batch), o_u(batch), o_v(batch), o_pbuf(batch), o_uh(batch), o_pd(batch),
+        o_pdb(batch), o_pd2(batch), o_rr(batch), o_invr(batch), o_pnorm(batch), o_tau(batch), o_beta(batch),
+        o_coef(batch);
+    Carver c;
+    int64_t max_m = 0, ktot = 0;
+    size_t max_partP = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        const rgs_qr_item& it = items[b];
+        const int64_t n = it.n, m = it.m, k = it.k;
+        const int64_t nproj = (n + kProjRows - 1) / kProjRows, nsl = (k + kSlice - 1) / kSlice;
+        max_m = std::max(max_m, m);
+        ktot += k;
+        const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T));
+        max_partP = std::max(max_partP, (size_t)pl.G_P * k * sizeof(T) * pl.cc);
+        o_signs[b] = c.take<uint32_t>((n + 31) / 32 + 4);
+        o_part[b] = c.take<T>(nproj * k);
+        o_P[b] = c.take<double>(k * m);
+        o_Vc[b] = c.take<double>(k * m);
+        o_Vr[b] = c.take<double>(k * m);
+        o_Wc[b] = c.take<double>(k * m);
+        o_Wr[b] = c.take<double>(k * m);
+        o_X[b] = c.take<double>(m * m);
+        o_sp[b] = c.take<double>(k);
+        o_u[b] = c.take<double>(k);
+        o_v[b] = c.take<double>(k);
+        o_pbuf[b] = c.take<double>(k);
+        o_uh[b] = c.take<double>(m + 1);
+        o_pd[b] = c.take<double>(nsl * (m + 1));
+        o_pdb[b] = c.take<double>(nsl * (m + 2));
+        o_pd2[b] = c.take<double>(nsl);
+        o_rr[b] = c.take<double>(m);
+        o_invr[b] = c.take<double>(m);
+        o_pnorm[b] = c.take<double>(m);
+        o_tau[b] = c.take<double>(m);
+        o_beta[b] = c.take<double>(m);
+        o_coef[b] = c.take<T>(m);
+    }
+    const size_t o_rows = c.take<int>(ktot), o_status = c.take<int>(4 * batch), o_items = c.take<BatchItem>(batch);
+    const size_t o_partP = c.take<char>(max_partP);
+    // launch maps, column by column
+    std::vector<int2> maps;
+    struct ColMaps {
+        size_t proj, sl, qd, ls;
+        int nproj, nsl, nqd, nls;
+    };
+    std::vector<ColMaps> cm((size_t)max_m);
+    for (int64_t i = 0; i < max_m; ++i) {
+        ColMaps& x = cm[i];
+        const int64_t rb = (i + 1 + 63) / 64;
+        x.proj = maps.size();
+        for (int64_t b = 0; b < batch; ++b)
+            if (items[b].m > i)
+                for (int64_t g = 0; g < (items[b].n + kProjRows - 1) / kProjRows; ++g) maps.push_back({(int)b, (int)g});
+        x.nproj = (int)(maps.size() - x.proj);
+        x.sl = maps.size();
+        for (int64_t b = 0; b < batch; ++b)
+            if (items[b].m > i)
+                for (int64_t g = 0; g < (items[b].k + kSlice - 1) / kSlice; ++g) maps.push_back({(int)b, (int)g});
+        x.nsl = (int)(maps.size() - x.sl);
+        x.qd = maps.size();
+        for (int64_t b = 0; b < batch; ++b)
+            if (items[b].m > i)
+                for (int64_t g = 0; g < (items[b].k + kSlice - 1) / kSlice + rb; ++g) maps.push_back({(int)b, (int)g});
+        x.nqd = (int)(maps.size() - x.qd);
+        x.ls = maps.size();
+        for (int64_t b = 0; b < batch; ++b)
+            if (items[b].m > i + 1)
+                for (int64_t g = 0; g < rb; ++g) maps.push_back({(int)b, (int)g});
+        x.nls = (int)(maps.size() - x.ls);
+    }
+    const size_t scale_at = maps.size();
+    for (int64_t b = 0; b < batch; ++b)
+        for (int64_t g = 0; g < (items[b].n + 255) / 256; ++g) maps.push_back({(int)b, (int)g});
+    const int nscale = (int)(maps.size() - scale_at);
+    const size_t o_maps = c.take<int2>(maps.size());
+    rgs_status st = ensure_arena(h, c.off + kAlign);
+    if (st != RGS_OK) return st;
+    char* A = h->arena;
+    std::vector<int> rows_all((size_t)ktot);
+    int64_t rpos = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        const rgs_qr_item& it = items[b];
+        BatchItem& x = bi[b];
+        x.n = it.n;
+        x.m = (int)it.m;
+        x.k = (int)it.k;
+        x.nproj = (int)((it.n + kProjRows - 1) / kProjRows);
+        x.nsl = (int)((it.k + kSlice - 1) / kSlice);
+        x.W = it.W;
+        x.ldw = it.ldw;
+        x.Q = it.Q;
+        x.ldq = it.ldq;
+        x.R = it.R;
+        x.ldr = it.ldr;
+        x.S = it.S;
+        x.lds = it.lds;
+        x.P = reinterpret_cast<double*>(A + o_P[b]);
+        x.part = A + o_part[b];
+        x.coef = A + o_coef[b];
+        x.sketch_scale = 1.0 / std::sqrt((double)it.k);
+        x.vec_ok = (it.ldq % 4 == 0) && (it.ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.Q) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(it.W) & 15) == 0);
+        x.defer = DEFER ? 1 : 0;
+        SpaceArgs& a = x.sa;
+        a.k = (int)it.k;
+        a.mcap = (int)it.m;
+        a.Vc = reinterpret_cast<double*>(A + o_Vc[b]);
+        a.Vr = reinterpret_cast<double*>(A + o_Vr[b]);
+        a.Wc = reinterpret_cast<double*>(A + o_Wc[b]);
+        a.Wr = reinterpret_cast<double*>(A + o_Wr[b]);
+        a.X = reinterpret_cast<double*>(A + o_X[b]);
+        a.sp = reinterpret_cast<double*>(A + o_sp[b]);
+        a.u = reinterpret_cast<double*>(A + o_u[b]);
+        a.v = reinterpret_cast<double*>(A + o_v[b]);
+        a.pbuf = reinterpret_cast<double*>(A + o_pbuf[b]);
+        a.uh = reinterpret_cast<double*>(A + o_uh[b]);
+        a.pd = reinterpret_cast<double*>(A + o_pd[b]);
+        a.pdb = reinterpret_cast<double*>(A + o_pdb[b]);
+        a.pd2 = reinterpret_cast<double*>(A + o_pd2[b]);
+        a.rr = reinterpret_cast<double*>(A + o_rr[b]);
+        a.invr = reinterpret_cast<double*>(A + o_invr[b]);
+        a.pnorm = reinterpret_cast<double*>(A + o_pnorm[b]);
+        a.tau = reinterpret_cast<double*>(A + o_tau[b]);
+        a.beta = reinterpret_cast<double*>(A + o_beta[b]);
+        a.status = reinterpret_cast<int*>(A + o_status) + 4 * b;
+        // Theta of factorisation b: SRHT per factorisation (instance b); Gaussian: the
+        // leading k_b x n_b block of one master matrix (instance 0)
+        x.sk = make_sketch(sk_kind, it.k, seed, sid, sk_kind == SK_SRHT ? (uint32_t)b : 0u);
+        if (sk_kind == SK_SRHT) {
+            uint32_t* signs = reinterpret_cast<uint32_t*>(A + o_signs[b]);
+            if (!launch_srht_signs(s, signs, (it.n + 31) / 32, x.sk)) return RGS_EDEVICE;
+            std::vector<int> rows;
+            srht_rows_host(srht_order(it.n), (int)it.k, x.sk, rows);
+            std::copy(rows.begin(), rows.end(), rows_all.begin() + rpos);
+            x.sk.signs = signs;
+            x.sk.rows = reinterpret_cast<int*>(A + o_rows) + rpos;
+        }
+        rpos += it.k;
+    }
+    if (hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(A + o_maps, maps.data(), maps.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        return RGS_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // host staging vectors stay alive till here
+    const BatchItem* itd = reinterpret_cast<const BatchItem*>(A + o_items);
+    const int2* mp = reinterpret_cast<const int2*>(A + o_maps);
+    if (!launch_batch_init(s, itd, (int)batch, max_m * max_m)) return RGS_EDEVICE;
+    // step 1 for every column of every factorisation: P_b = Theta_b W_b
+    T* partP = reinterpret_cast<T*>(A + o_partP);
+    for (int64_t b = 0; b < batch; ++b) {
+        const rgs_qr_item& it = items[b];
+        const QrPlan pl = plan_qr(it.n, it.m, it.k, sk_kind, sizeof(T));
+        st = sketch_matrix<T>(h, bi[b].sk, static_cast<const T*>(it.W), it.ldw, it.n, it.m, pl.G_P, pl.cc, partP,
+                              bi[b].P, it.k);
+        if (st != RGS_OK) return st;
+    }
+    for (int64_t i = 0; i < max_m; ++i) {
+        const ColMaps& x = cm[i];
+        if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, mp + x.proj, x.nproj, (int)i)) return RGS_EDEVICE;
+        if (!launch_batch_column<T>(s, itd, mp + x.sl, x.nsl, mp + x.qd, x.nqd, mp + x.ls, x.nls, (int)i))
+            return RGS_EDEVICE;
+    }
+    if (!launch_batch_scale<TQ, DEFER>(s, itd, mp + scale_at, nscale)) return RGS_EDEVICE;
+    std::vector<int> stat((size_t)(4 * batch));
+    if (hipMemcpyAsync(stat.data(), A + o_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return RGS_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+    rgs_status result = RGS_OK;
+    for (int64_t b = 0; b < batch; ++b) {
+        const int code = stat[4 * b];
+        const rgs_status sb = code == kStatusBreakdown ? RGS_EBREAKDOWN
+                              : code == kStatusNonfinite ? RGS_ENONFINITE
+                                                         : RGS_OK;
+        if (item_status) item_status[b] = sb;
+        if (failed_column) failed_column[b] = code ? stat[4 * b + 1] : -1;
+        if (sb != RGS_OK && result == RGS_OK) result = sb;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->failed_column = -1;
+        rep->iters = max_m;
+        rep->cycles = 0;
+        rep->delta_F = NAN;
+        rep->delta_tilde_F = NAN;
+        rep->true_relres = NAN;
+        rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+        rep->proj_kernel_ms = 0.0;
+        rep->proj_launches = max_m;
     }
     return result;
 }
@@ -556,10 +776,13 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
     if (d->m > 4096) return RGS_EINVAL;   // dynamic LDS of the sketch-space kernels
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64)
-        return run_qr<double>(h, d, static_cast<const double*>(W), ldw, static_cast<double*>(Q), ldq, R, ldr, S,
-                              lds, rep);
-    return run_qr<float>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R, ldr, S, lds,
-                         rep);
+        return run_qr<double, double, false>(h, d, static_cast<const double*>(W), ldw, static_cast<double*>(Q), ldq,
+                                             R, ldr, S, lds, rep);
+    if (d->prec == RGS_P_BF16Q_FP32_LS64)
+        return run_qr<float, bf16, true>(h, d, static_cast<const float*>(W), ldw, static_cast<bf16*>(Q), ldq, R,
+                                         ldr, S, lds, rep);
+    return run_qr<float, float, false>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R,
+                                       ldr, S, lds, rep);
 }
 
 rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, int64_t ldx, int64_t ncols,
@@ -568,7 +791,7 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
     const size_t tsize = d->prec == RGS_P_FP64 ? sizeof(double) : sizeof(float);
-    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize);
+    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize);   // W and X are float on the bf16 path
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -649,6 +872,21 @@ rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec
                                                  static_cast<float*>(w), 0, sk, nullptr, status);
     if (!ok) return RGS_EDEVICE;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+}
+
+rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int32_t sketch, int32_t prec,
+                          uint64_t seed, uint32_t sketch_id, int32_t* item_status, int64_t* failed_column,
+                          rgs_report* rep) {
+    if (!h || batch < 1 || batch > 65535 || !items) return RGS_EINVAL;
+    if (sketch != RGS_SKETCH_GAUSSIAN && sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
+    if (prec != RGS_P_FP32_LS64 && prec != RGS_P_BF16Q_FP32_LS64) return RGS_EINVAL;
+    const int sk_kind = sketch_kind(sketch);
+    for (int64_t b = 0; b < batch; ++b)
+        if (!valid_item(items[b], sk_kind)) return RGS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    if (prec == RGS_P_BF16Q_FP32_LS64)
+        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
+    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
 }
 
 }  // extern "C"

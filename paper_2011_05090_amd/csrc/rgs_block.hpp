@@ -78,6 +78,62 @@ __device__ __forceinline__ void store16(T* __restrict__ p, const int64_t row0[4]
     }
 }
 
+// ---------------------------------------------------------------------------
+// bfloat16 storage of the basis: round to nearest even on store, exact on load.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t float_to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load16(const bf16* __restrict__ p, const int64_t row0[4], int64_t n, bool full,
+                                       float v[16]) {
+    if (full) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const u32x2 t = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p + row0[e]));
+            v[4 * e] = __uint_as_float(t.x << 16);
+            v[4 * e + 1] = __uint_as_float(t.x & 0xFFFF0000u);
+            v[4 * e + 2] = __uint_as_float(t.y << 16);
+            v[4 * e + 3] = __uint_as_float(t.y & 0xFFFF0000u);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[4 * e + r] = (row0[e] + r < n) ? bf16_to_float(p[row0[e] + r].bits) : 0.f;
+    }
+}
+
+// Stores fl_bf16(v) and replaces v by the stored values.
+__device__ __forceinline__ void store16(bf16* __restrict__ p, const int64_t row0[4], int64_t n, bool full,
+                                        float v[16]) {
+    uint16_t h[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        h[t] = float_to_bf16(v[t]);
+        v[t] = bf16_to_float(h[t]);
+    }
+    if (full) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const u32x2 t = {(uint32_t)h[4 * e] | ((uint32_t)h[4 * e + 1] << 16),
+                             (uint32_t)h[4 * e + 2] | ((uint32_t)h[4 * e + 3] << 16)};
+            __builtin_nontemporal_store(t, reinterpret_cast<u32x2*>(p + row0[e]));
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (row0[e] + r < n) p[row0[e] + r].bits = h[4 * e + r];
+    }
+}
+
 // Rows of this lane in block blk of a workgroup with NW wave tiles.
 template <int NW>
 __device__ __forceinline__ void lane_rows(int64_t blk, int64_t row0[4]) {

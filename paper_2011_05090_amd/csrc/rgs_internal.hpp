@@ -27,6 +27,11 @@ struct StencilArgs {
     double c[7];
 };
 
+// bfloat16 storage element of the basis (round to nearest even).
+struct bf16 {
+    uint16_t bits;
+};
+
 // Device pointers of the sketch-space state (all fp64).
 struct SpaceArgs {
     int k, mcap;
@@ -42,6 +47,27 @@ struct SpaceArgs {
     int* status;            // [0] = kStatus*, [1] = failed column, [2] = cycle done
 };
 
+// One factorisation of a batched call, as the batched kernels see it.
+struct BatchItem {
+    int64_t n;
+    int m, k, nproj, nsl;
+    const void* W;
+    int64_t ldw;
+    void* Q;
+    int64_t ldq;
+    double* R;
+    int64_t ldr;
+    double* S;
+    int64_t lds;
+    double* P;            // k x m: sketches of the columns of W
+    void* part;           // nproj x k block partials (working precision)
+    void* coef;           // m coefficients of the projection (working precision)
+    double sketch_scale;  // 1 / sqrt(k)
+    int vec_ok, defer;
+    SpaceArgs sa;
+    SketchArgs sk;
+};
+
 bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const SketchArgs& sk);
 template <typename T, typename PT>
 bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int ncols, int G,
@@ -49,10 +75,10 @@ bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int 
 template <typename PT>
 bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
                    int64_t ldo);
-template <typename T, typename PT>
-bool launch_project(hipStream_t st, const T* w, T* Q, int64_t ldq, int64_t n, int j, const T* coef,
+template <typename TW, typename TQ, bool DEFER>
+bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
                     const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
-                    PT* partials, const int* status);
+                    TW* partials, const int* status);
 template <typename T>
 bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const int* status);
 template <typename T>
@@ -60,8 +86,18 @@ bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, doubl
 template <typename T, typename PT>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
-                   const double* pnext, T* coef);
+                   const double* pnext, T* coef, const double* cscale);
 bool launch_zero_mat(hipStream_t st, double* A, int64_t rows, int64_t cols, int64_t lda);
+bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr,
+                            const int* status);
+bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64_t max_m2);
+template <typename TW, typename TQ, bool DEFER>
+bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const int2* map, int count, int i);
+template <typename TW>
+bool launch_batch_column(hipStream_t st, const BatchItem* items, const int2* map_sl, int n_sl, const int2* map_qd,
+                         int n_qd, const int2* map_ls, int n_ls, int i);
+template <typename TQ, bool DEFER>
+bool launch_batch_scale(hipStream_t st, const BatchItem* items, const int2* map, int count);
 template <typename T>
 bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_t j1, int64_t l0, int64_t l1,
                         double rsk, double* out, int64_t ldo);
@@ -85,6 +121,6 @@ bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* g
 // a.pbuf, then the least-squares solve of column i (R(0:i, i) and coef).
 template <typename T, typename PT>
 bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
-                        double* R, int64_t ldr, T* coef);
+                        double* R, int64_t ldr, T* coef, const double* cscale);
 
 }  // namespace rgs

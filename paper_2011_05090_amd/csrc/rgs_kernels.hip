@@ -105,49 +105,51 @@ __global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials,
     }
 }
 
-// Step 3 (+ step 4 partials, + step 7 of the previous column), for one block
-// of kProjWaves * 1024 rows per workgroup:
-//   q'_i = w_i - sum_{c<j} coef[c] q_c           (working precision T, fma chain in c order)
-// where, if normalize_last, column j-1 still holds q'_{i-1} and is first
-// scaled to q_{i-1} = q'_{i-1} / r_{i-1,i-1} (fp64 multiply by the reciprocal,
-// rounded to T) and written back.  q'_i is stored in column j.  Then the
-// block's sketch partials of q'_i are written (or q'_i itself for Theta = I).
-template <typename T, typename PT, int SK>
-__global__ __launch_bounds__(kProjWaves * kWave) void k_project(
-    const T* __restrict__ w, T* __restrict__ Q, int64_t ldq, int64_t n, int j, const T* __restrict__ coef,
-    const double* __restrict__ invr, int normalize_last, int do_sketch, int vec_ok, SketchArgs sk,
-    PT* __restrict__ partials, const int* __restrict__ status) {
+// Step 3 (+ step 4 partials, + step 7 of the previous column), for row block
+// blk of kProjWaves * 1024 rows:
+//   q'_i = w_i - sum_{c<j} coef[c] q_c        (working precision TW, fma chain in c order)
+// If normalize_last, column j-1 still holds q'_{i-1} and is first scaled to
+// q_{i-1} = q'_{i-1} / r_{i-1,i-1} (fp64 multiply by the reciprocal, rounded
+// to the storage type) and written back.  q'_i is stored in column j, then the
+// block's sketch partials of the stored q'_i are written (or q'_i itself for
+// Theta = I).  DEFER (bf16 storage): columns stay unnormalised, the
+// coefficients already carry 1/r_cc, and the sketch is taken of the rounded,
+// stored q'_i.
+template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
+__device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n,
+                                             int j, const TW* __restrict__ coef, const double* __restrict__ invr,
+                                             int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
+                                             PT* __restrict__ partials, int64_t blk, TW* __restrict__ lds) {
     constexpr int NW = kProjWaves;
-    __shared__ T lds[NW * kTile];
-    RGS_EXIT_IF_FAILED(status);
-    const int64_t blk = blockIdx.x;
     int64_t row0[4];
     lane_rows<NW>(blk, row0);
     const bool full = vec_ok && (blk + 1) * (NW * kTile) <= n;
-    T v[16];
+    TW v[16];
     load16(w, row0, n, full, v);
-    const int jl = normalize_last ? j - 1 : j;
+    const int jl = (!DEFER && normalize_last) ? j - 1 : j;
     for (int c = 0; c < jl; ++c) {
-        const T a = coef[c];
-        T q[16];
+        const TW a = coef[c];
+        TW q[16];
         load16(Q + (int64_t)c * ldq, row0, n, full, q);
 #pragma unroll
         for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
     }
-    if (normalize_last) {
-        const int c = j - 1;
-        const T a = coef[c];
-        const double ir = invr[0];
-        T q[16];
-        T* qc = Q + (int64_t)c * ldq;
-        load16(qc, row0, n, full, q);
+    if constexpr (!DEFER) {
+        if (normalize_last) {
+            const int c = j - 1;
+            const TW a = coef[c];
+            const double ir = invr[0];
+            TW q[16];
+            TQ* qc = Q + (int64_t)c * ldq;
+            load16(qc, row0, n, full, q);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) q[t] = (T)((double)q[t] * ir);
-        store16(qc, row0, n, full, q);
+            for (int t = 0; t < 16; ++t) q[t] = (TW)((double)q[t] * ir);
+            store16(qc, row0, n, full, q);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
+            for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
+        }
     }
-    store16(Q + (int64_t)j * ldq, row0, n, full, v);
+    store16(Q + (int64_t)j * ldq, row0, n, full, v);   // bf16: v becomes the stored value
     if (!do_sketch) return;
     if constexpr (SK == SK_IDENT) {
         store16(partials, row0, n, false, v);   // Theta = I: the "sketch" is q' itself
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_project(
         PT acc[kKptMax];
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
-        block_sketch<T, PT, SK, NW>(v, blk, n, sk, acc, lds);
+        block_sketch<TW, PT, SK, NW>(v, blk, n, sk, acc, lds);
         PT* out = partials + blk * sk.k;
         constexpr int NT = NW * kWave;
         const int kpt = (sk.k + NT - 1) / NT;
@@ -167,6 +169,33 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_project(
     }
 }
 
+template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void k_project(
+    const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n, int j, const TW* __restrict__ coef,
+    const double* __restrict__ invr, int normalize_last, int do_sketch, int vec_ok, SketchArgs sk,
+    PT* __restrict__ partials, const int* __restrict__ status) {
+    __shared__ TW lds[kProjWaves * kTile];
+    RGS_EXIT_IF_FAILED(status);
+    project_body<TW, TQ, PT, SK, DEFER>(w, Q, ldq, n, j, coef, invr, normalize_last, do_sketch, vec_ok, sk,
+                                        partials, blockIdx.x, lds);
+}
+
+// Batched: workgroup -> (factorisation, row block) through map; column i of
+// every factorisation listed in the map.
+template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem* __restrict__ items,
+                                                                 const int2* __restrict__ map, int i) {
+    __shared__ TW lds[kProjWaves * kTile];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_FAILED(it.sa.status);
+    const TW* W = static_cast<const TW*>(it.W);
+    project_body<TW, TQ, PT, SK, DEFER>(W + (int64_t)i * it.ldw, static_cast<TQ*>(it.Q), it.ldq, it.n, i,
+                                        static_cast<const TW*>(it.coef), i > 0 ? it.sa.invr + (i - 1) : nullptr,
+                                        (!DEFER && i > 0) ? 1 : 0, (DEFER || i > 0) ? 1 : 0, it.vec_ok, it.sk,
+                                        static_cast<PT*>(it.part), bm.y, lds);
+}
+
 // Final step 7 for the last column: q = q' / r (fp64 reciprocal, rounded to T).
 template <typename T>
 __global__ void k_scale_col(T* __restrict__ q, int64_t n, const double* __restrict__ invr,
@@ -174,6 +203,47 @@ __global__ void k_scale_col(T* __restrict__ q, int64_t n, const double* __restri
     RGS_EXIT_IF_FAILED(status);
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l < n) q[l] = (T)((double)q[l] * invr[0]);
+}
+
+// Step 7 for bf16 storage, all columns at the end: q_c = fl_bf16(fl32(q'_c / r_cc)).
+__device__ __forceinline__ void scale_cols_bf16_body(bf16* __restrict__ Q, int64_t ldq, int64_t n, int m,
+                                                     const double* __restrict__ invr, int64_t l) {
+    if (l >= n) return;
+    for (int c = 0; c < m; ++c) {
+        bf16* p = Q + l + (int64_t)c * ldq;
+        p->bits = float_to_bf16((float)((double)bf16_to_float(p->bits) * invr[c]));
+    }
+}
+
+__global__ void k_scale_cols_bf16(bf16* __restrict__ Q, int64_t ldq, int64_t n, int m,
+                                  const double* __restrict__ invr, const int* __restrict__ status) {
+    RGS_EXIT_IF_FAILED(status);
+    scale_cols_bf16_body(Q, ldq, n, m, invr, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched end of step 7: map entries (factorisation, block of 256 rows).
+template <typename TQ, bool DEFER>
+__global__ void kb_scale(const BatchItem* __restrict__ items, const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_FAILED(it.sa.status);
+    const int64_t l = (int64_t)bm.y * blockDim.x + threadIdx.x;
+    if constexpr (DEFER) {
+        scale_cols_bf16_body(static_cast<bf16*>(it.Q), it.ldq, it.n, it.m, it.sa.invr, l);
+    } else {
+        TQ* q = static_cast<TQ*>(it.Q) + (int64_t)(it.m - 1) * it.ldq;
+        if (l < it.n) q[l] = (TQ)((double)q[l] * it.sa.invr[it.m - 1]);
+    }
+}
+
+// Batched: zero R and reset the status word of every factorisation.
+__global__ void kb_init(const BatchItem* __restrict__ items, int nitems) {
+    const int b = blockIdx.y;
+    if (b >= nitems) return;
+    const BatchItem& it = items[b];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < (int64_t)it.m * it.m) it.R[idx % it.m + (idx / it.m) * it.ldr] = 0.0;
+    if (idx < 4) it.sa.status[idx] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -295,37 +365,47 @@ __global__ __launch_bounds__(kGW) void k_ls2(const double* __restrict__ p, int k
 }
 
 // Step 2, last part: y = R_S^{-1} uh with X = R_S^{-1} (upper triangular, nr x nr):
-//   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:nr, col) and coef (working precision).
+//   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:nr, col) and the working-
+// precision coefficients coef[r] = y[r] (times cscale[r] = 1/r_rr when the
+// basis is kept unnormalised).  bid = row block of 64.
 template <typename T>
-__global__ __launch_bounds__(kGW) void k_ls3(int nr, int col, const double* __restrict__ X, int mcap,
-                                             const double* __restrict__ uh, double* __restrict__ R,
-                                             int64_t ldr, T* __restrict__ coef) {
-    extern __shared__ double us[];  // [nr]
+__device__ __forceinline__ void ls3_body(int nr, int col, const double* __restrict__ X, int mcap,
+                                         const double* __restrict__ uh, double* __restrict__ R, int64_t ldr,
+                                         T* __restrict__ coef, const double* __restrict__ cscale, int bid,
+                                         double* __restrict__ us) {
     __shared__ double red[kGQ][64];
     for (int c = threadIdx.x; c < nr; c += kGW) us[c] = uh[c];
     __syncthreads();
     const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int r = blockIdx.x * 64 + rl;
+    const int r = bid * 64 + rl;
     red[q][rl] = (r < nr) ? row_part(X, mcap, r, r, nr, us, q) : 0.0;
     __syncthreads();
     if (q == 0 && r < nr) {
         const double y = combine16(red, rl);
         R[r + (int64_t)col * ldr] = y;
-        coef[r] = (T)y;
+        coef[r] = (T)(cscale ? y * cscale[r] : y);
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kGW) void k_ls3(int nr, int col, const double* __restrict__ X, int mcap,
+                                             const double* __restrict__ uh, double* __restrict__ R,
+                                             int64_t ldr, T* __restrict__ coef, const double* __restrict__ cscale) {
+    extern __shared__ double us[];  // [nr]
+    ls3_body<T>(nr, col, X, mcap, uh, R, ldr, coef, cscale, blockIdx.x, us);
+}
+
 // Column step A: s' = scale * (sum of the projection kernel's block partials)
-// for this slice (or a copy of src), stored in sp; per-slice partials of
+// for slice bid (or a copy of src), stored in sp; per-slice partials of
 // c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
 template <typename PT>
-__global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int G, double scale,
-                                            const double* __restrict__ src, int k, int i,
-                                            const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                            double* __restrict__ pd) {
+__device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, double scale,
+                                        const double* __restrict__ src, int k, int i,
+                                        const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
+                                        double* __restrict__ pd, int bid) {
     __shared__ double red[kGQ][64];
     __shared__ double xs[kSlice];
-    const int s = blockIdx.x, r0 = s * kSlice, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r = r0 + rl;
     if (src) {
         if (q == 0) {
@@ -359,22 +439,28 @@ __global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int
     for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
+template <typename PT>
+__global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int G, double scale,
+                                            const double* __restrict__ src, int k, int i,
+                                            const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
+                                            double* __restrict__ pd) {
+    qa_body<PT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x);
+}
+
 // Column step B (steps 5-6): r_ii = ||s'||, S(:, i) = s'/r_ii, breakdown test,
 // u = U_i^T s_i = (s' - V c1) / r_ii, per-slice partials of ||u(i+1:k)||^2.
-__global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
-                                            const double* __restrict__ Vc, int mcap,
-                                            const double* __restrict__ pd, double* __restrict__ u,
-                                            double* __restrict__ pd2, double* __restrict__ S, int64_t lds,
-                                            double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
-                                            double* __restrict__ invr, const double* __restrict__ pnorm,
-                                            int* __restrict__ status) {
-    extern __shared__ double c1[];  // [i + 1]
+__device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __restrict__ sp,
+                                        const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
+                                        double* __restrict__ u, double* __restrict__ pd2, double* __restrict__ S,
+                                        int64_t lds, double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
+                                        double* __restrict__ invr, const double* __restrict__ pnorm,
+                                        int* __restrict__ status, int bid, double* __restrict__ c1) {
     __shared__ double red[kGQ][64];
     __shared__ double tl[64];
     sum_slices(pd, nsl, mcap + 1, i + 1, c1);
     __syncthreads();
     const double rii = sqrt(c1[i]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         rr[i] = rii;
         invr[i] = 1.0 / rii;
         R[i + (int64_t)i * ldr] = rii;
@@ -389,7 +475,7 @@ __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double*
             }
         }
     }
-    const int s = blockIdx.x, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int s = bid, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r = s * kSlice + rl;
     red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : 0.0;
     __syncthreads();
@@ -412,18 +498,28 @@ __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double*
     }
 }
 
+__global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
+                                            const double* __restrict__ Vc, int mcap,
+                                            const double* __restrict__ pd, double* __restrict__ u,
+                                            double* __restrict__ pd2, double* __restrict__ S, int64_t lds,
+                                            double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
+                                            double* __restrict__ invr, const double* __restrict__ pnorm,
+                                            int* __restrict__ status) {
+    extern __shared__ double c1[];  // [i + 1]
+    qb_body(k, i, nsl, sp, Vc, mcap, pd, u, pd2, S, lds, R, ldr, rr, invr, pnorm, status, blockIdx.x, c1);
+}
+
 // Column step C: Householder reflector of u(i:k) (dlarfg convention):
 // beta = -sign(u_i) ||u(i:k)||, tau = (beta - u_i)/beta, v = [0; 1; u(i+1:k)/(u_i - beta)],
 // stored as column i of V (both layouts).  Per-slice partials of d = V_i^T v
 // (pd, stride mcap+1) and, when the next right-hand side pn = p_{i+1} is given,
 // of e = Wm_i^T pn, v.pn and ||pn||^2 (pdb, stride mcap+2, slots [0,i), i, i+1).
-__global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
-                                            const double* __restrict__ pd2, const double* __restrict__ pn,
-                                            double* __restrict__ v, double* __restrict__ Vc,
-                                            double* __restrict__ Vr, const double* __restrict__ Wr, int mcap,
-                                            double* __restrict__ pd, double* __restrict__ pdb,
-                                            double* __restrict__ tau_a, double* __restrict__ beta_a,
-                                            int* __restrict__ status) {
+__device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __restrict__ u,
+                                        const double* __restrict__ pd2, const double* __restrict__ pn,
+                                        double* __restrict__ v, double* __restrict__ Vc, double* __restrict__ Vr,
+                                        const double* __restrict__ Wr, int mcap, double* __restrict__ pd,
+                                        double* __restrict__ pdb, double* __restrict__ tau_a,
+                                        double* __restrict__ beta_a, int* __restrict__ status, int bid) {
     __shared__ double vs[kSlice], ps[kSlice];
     __shared__ double hh[3];
     if (threadIdx.x == 0) {
@@ -443,7 +539,7 @@ __global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double*
         hh[0] = beta;
         hh[1] = tau;
         hh[2] = scal;
-        if (blockIdx.x == 0) {
+        if (bid == 0) {
             tau_a[i] = tau;
             beta_a[i] = beta;
             if (status[0] == 0 && status[2] == 0 && !(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1})
@@ -453,7 +549,7 @@ __global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double*
         }
     }
     __syncthreads();
-    const int s = blockIdx.x, r0 = s * kSlice;
+    const int s = bid, r0 = s * kSlice;
     if (threadIdx.x < kSlice) {
         const int r = r0 + threadIdx.x;
         double val = 0.0;
@@ -484,29 +580,39 @@ __global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double*
     }
 }
 
+__global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
+                                            const double* __restrict__ pd2, const double* __restrict__ pn,
+                                            double* __restrict__ v, double* __restrict__ Vc,
+                                            double* __restrict__ Vr, const double* __restrict__ Wr, int mcap,
+                                            double* __restrict__ pd, double* __restrict__ pdb,
+                                            double* __restrict__ tau_a, double* __restrict__ beta_a,
+                                            int* __restrict__ status) {
+    qc_body(k, i, nsl, u, pd2, pn, v, Vc, Vr, Wr, mcap, pd, pdb, tau_a, beta_a, status, blockIdx.x);
+}
+
 // Column step D.  Blocks [0, nsl): Wm(:, i) = tau (v - Wm_i d), d = sum of the slice partials.
 // Blocks [nsl, ...), rows r of [64 b, 64 b + 64):
 //   column i of X = R_S^{-1}: X(r, i) = -(sum_{c=r}^{i-1} X(r, c) u(c)) / beta for r < i
 //   (u(0:i) is R_S(0:i, i)), X(i, i) = 1/beta;
 //   when pn is given, the head of U_{i+1}^T pn for the next column's least squares:
 //   cp = Wm_{i+1}^T pn = [e; tau (v.pn - d.e)],  uh(r) = pn(r) - sum_{c <= min(r,i)} V(r, c) cp(c), r <= i.
-__global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
-                                            const double* __restrict__ u, const double* __restrict__ pn,
-                                            double* __restrict__ Wc, double* __restrict__ Wr,
-                                            const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                            const double* __restrict__ pdb, double* __restrict__ X,
-                                            double* __restrict__ uh, double* __restrict__ pnorm,
-                                            const double* __restrict__ tau_a, const double* __restrict__ beta_a) {
-    extern __shared__ double dyn[];  // [3 (i + 2)]
+__device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __restrict__ v,
+                                        const double* __restrict__ u, const double* __restrict__ pn,
+                                        double* __restrict__ Wc, double* __restrict__ Wr,
+                                        const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
+                                        const double* __restrict__ pdb, double* __restrict__ X,
+                                        double* __restrict__ uh, double* __restrict__ pnorm,
+                                        const double* __restrict__ tau_a, const double* __restrict__ beta_a,
+                                        int bid, double* __restrict__ dyn) {
     __shared__ double red[kGQ][64];
     __shared__ double tree[kGW];
     const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const double tau = tau_a[i];
-    if ((int)blockIdx.x < nsl) {
+    if (bid < nsl) {
         double* dsh = dyn;
         sum_slices(pd, nsl, mcap + 1, i, dsh);
         __syncthreads();
-        const int r = blockIdx.x * kSlice + rl;
+        const int r = bid * kSlice + rl;
         red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : 0.0;
         __syncthreads();
         if (q == 0 && r < k) {
@@ -514,7 +620,7 @@ __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double*
             Wc[r + (int64_t)i * k] = val;
             Wr[(int64_t)r * mcap + i] = val;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) X[i + (int64_t)i * mcap] = 1.0 / beta_a[i];
+        if (bid == 0 && threadIdx.x == 0) X[i + (int64_t)i * mcap] = 1.0 / beta_a[i];
         return;
     }
     double* ush = dyn;            // u(0:i)
@@ -528,7 +634,7 @@ __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double*
         }
     }
     __syncthreads();
-    const int r = (blockIdx.x - nsl) * 64 + rl;
+    const int r = (bid - nsl) * 64 + rl;
     red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : 0.0;
     __syncthreads();
     if (q == 0 && r < i) X[r + (int64_t)i * mcap] = -combine16(red, rl) / beta_a[i];
@@ -545,11 +651,80 @@ __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double*
     const double vp = csh[i], pp = csh[i + 1];
     __syncthreads();
     if (threadIdx.x == 0) csh[i] = tau * (vp - tree[0]);
-    if (blockIdx.x == (unsigned)nsl && threadIdx.x == 0) pnorm[i + 1] = sqrt(pp);
+    if (bid == nsl && threadIdx.x == 0) pnorm[i + 1] = sqrt(pp);
     __syncthreads();
     red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : 0.0;
     __syncthreads();
     if (q == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
+}
+
+__global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
+                                            const double* __restrict__ u, const double* __restrict__ pn,
+                                            double* __restrict__ Wc, double* __restrict__ Wr,
+                                            const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
+                                            const double* __restrict__ pdb, double* __restrict__ X,
+                                            double* __restrict__ uh, double* __restrict__ pnorm,
+                                            const double* __restrict__ tau_a, const double* __restrict__ beta_a) {
+    extern __shared__ double dyn[];  // [3 (i + 2)]
+    qd_body(k, i, nsl, v, u, pn, Wc, Wr, Vc, mcap, pd, pdb, X, uh, pnorm, tau_a, beta_a, blockIdx.x, dyn);
+}
+
+// ---------------------------------------------------------------------------
+// Batched column steps: workgroup -> (factorisation, local block) through map.
+// Every factorisation in the map is at column i.  pnext is P(:, i+1) when the
+// factorisation has a column i+1, and nothing otherwise.
+// ---------------------------------------------------------------------------
+template <typename PT>
+__global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                             int i) {
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    const bool from_p = (i == 0 && !it.defer);
+    qa_body<PT>(static_cast<const PT*>(it.part), it.nproj, it.sketch_scale, from_p ? it.P : nullptr, a.k, i, a.Wr,
+                a.mcap, a.sp, a.pd, bm.y);
+}
+
+__global__ __launch_bounds__(kGW) void kb_qb(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                             int i) {
+    extern __shared__ double c1[];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    qb_body(a.k, i, it.nsl, a.sp, a.Vc, a.mcap, a.pd, a.u, a.pd2, it.S, it.lds, it.R, it.ldr, a.rr, a.invr,
+            a.pnorm, a.status, bm.y, c1);
+}
+
+__global__ __launch_bounds__(kGW) void kb_qc(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                             int i) {
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    const double* pn = (i + 1 < it.m) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
+    qc_body(a.k, i, it.nsl, a.u, a.pd2, pn, a.v, a.Vc, a.Vr, a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status,
+            bm.y);
+}
+
+__global__ __launch_bounds__(kGW) void kb_qd(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                             int i) {
+    extern __shared__ double dyn[];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    const double* pn = (i + 1 < it.m) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
+    qd_body(a.k, i, it.nsl, a.v, a.u, pn, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
+            a.beta, bm.y, dyn);
+}
+
+template <typename TW>
+__global__ __launch_bounds__(kGW) void kb_ls3(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                              int i) {
+    extern __shared__ double us[];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    ls3_body<TW>(i + 1, i + 1, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<TW*>(it.coef),
+                 it.defer ? a.invr : nullptr, bm.y, us);
 }
 
 __global__ void k_zero_mat(double* __restrict__ A, int64_t rows, int64_t cols, int64_t lda) {
@@ -674,23 +849,23 @@ bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, 
     return true;
 }
 
-template <typename T, typename PT>
-bool launch_project(hipStream_t st, const T* w, T* Q, int64_t ldq, int64_t n, int j, const T* coef,
+template <typename TW, typename TQ, bool DEFER>
+bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
                     const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
-                    PT* partials, const int* status) {
+                    TW* partials, const int* status) {
     const unsigned nblk = nblocks(n, kProjRows);
     const dim3 thr(kProjWaves * kWave);
     switch (sk.sketch) {
         case SK_SRHT:
-            hipLaunchKernelGGL((k_project<T, PT, SK_SRHT>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j, coef,
-                               invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
             break;
         case SK_GAUSS:
-            hipLaunchKernelGGL((k_project<T, PT, SK_GAUSS>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
                                coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
             break;
         default:
-            hipLaunchKernelGGL((k_project<T, PT, SK_IDENT>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_IDENT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
                                coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
     }
     RGS_LAUNCH_CHECK();
@@ -700,6 +875,13 @@ bool launch_project(hipStream_t st, const T* w, T* Q, int64_t ldq, int64_t n, in
 template <typename T>
 bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const int* status) {
     hipLaunchKernelGGL(k_scale_col<T>, dim3(nblocks(n, 256)), dim3(256), 0, st, q, n, invr, status);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr,
+                            const int* status) {
+    hipLaunchKernelGGL(k_scale_cols_bf16, dim3(nblocks(n, 256)), dim3(256), 0, st, Q, ldq, n, m, invr, status);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -714,14 +896,14 @@ bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, doubl
                        a.pd, a.uh, a.pnorm);
     RGS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, a.X, a.mcap, a.uh, R,
-                       ldr, coef);
+                       ldr, coef, (const double*)nullptr);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
 template <typename T, typename PT>
 bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
-                        double* R, int64_t ldr, T* coef) {
+                        double* R, int64_t ldr, T* coef, const double* cscale) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, (const double*)nullptr, a.k, i,
                        a.Wr, a.mcap, a.pbuf, a.pd);
@@ -731,7 +913,7 @@ bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, 
                        a.mcap, a.pd, a.uh, a.pnorm);
     RGS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, a.X, a.mcap, a.uh, R,
-                       ldr, coef);
+                       ldr, coef, cscale);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -739,7 +921,7 @@ bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, 
 template <typename T, typename PT>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
-                   const double* pnext, T* coef) {
+                   const double* pnext, T* coef, const double* cscale) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap, a.sp,
                        a.pd);
@@ -756,9 +938,59 @@ bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G
     RGS_LAUNCH_CHECK();
     if (pnext) {
         hipLaunchKernelGGL(k_ls3<T>, dim3(nblocks(i + 1, 64)), dim3(kGW), (i + 1) * sizeof(double), st, i + 1,
-                           i + 1, a.X, a.mcap, a.uh, R, ldr, coef);
+                           i + 1, a.X, a.mcap, a.uh, R, ldr, coef, cscale);
         RGS_LAUNCH_CHECK();
     }
+    return true;
+}
+
+// ---- batched launchers: one launch per column step for every factorisation in the map ----
+bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64_t max_m2) {
+    hipLaunchKernelGGL(kb_init, dim3(nblocks(std::max<int64_t>(max_m2, 4), 256), nitems), dim3(256), 0, st, items,
+                       nitems);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TW, typename TQ, bool DEFER>
+bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const int2* map, int count, int i) {
+    if (count == 0) return true;
+    const dim3 thr(kProjWaves * kWave);
+    if (sketch == SK_SRHT)
+        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(count), thr, 0, st, items, map, i);
+    else
+        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(count), thr, 0, st, items, map, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TW>
+bool launch_batch_column(hipStream_t st, const BatchItem* items, const int2* map_sl, int n_sl, const int2* map_qd,
+                         int n_qd, const int2* map_ls, int n_ls, int i) {
+    if (n_sl > 0) {
+        hipLaunchKernelGGL(kb_qa<TW>, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
+        RGS_LAUNCH_CHECK();
+        hipLaunchKernelGGL(kb_qb, dim3(n_sl), dim3(kGW), (i + 1) * sizeof(double), st, items, map_sl, i);
+        RGS_LAUNCH_CHECK();
+        hipLaunchKernelGGL(kb_qc, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
+        RGS_LAUNCH_CHECK();
+    }
+    if (n_qd > 0) {
+        hipLaunchKernelGGL(kb_qd, dim3(n_qd), dim3(kGW), 3 * (i + 2) * sizeof(double), st, items, map_qd, i);
+        RGS_LAUNCH_CHECK();
+    }
+    if (n_ls > 0) {
+        hipLaunchKernelGGL(kb_ls3<TW>, dim3(n_ls), dim3(kGW), (i + 1) * sizeof(double), st, items, map_ls, i);
+        RGS_LAUNCH_CHECK();
+    }
+    return true;
+}
+
+template <typename TQ, bool DEFER>
+bool launch_batch_scale(hipStream_t st, const BatchItem* items, const int2* map, int count) {
+    if (count == 0) return true;
+    hipLaunchKernelGGL((kb_scale<TQ, DEFER>), dim3(count), dim3(256), 0, st, items, map);
+    RGS_LAUNCH_CHECK();
     return true;
 }
 
@@ -801,25 +1033,35 @@ template bool launch_sketch_cols<double, double>(hipStream_t, const double*, int
                                                  const SketchArgs&, double*);
 template bool launch_reduce<float>(hipStream_t, const float*, int, int, int, double, double*, int64_t);
 template bool launch_reduce<double>(hipStream_t, const double*, int, int, int, double, double*, int64_t);
-template bool launch_project<float, float>(hipStream_t, const float*, float*, int64_t, int64_t, int,
-                                           const float*, const double*, int, int, int, const SketchArgs&,
-                                           float*, const int*);
-template bool launch_project<double, double>(hipStream_t, const double*, double*, int64_t, int64_t, int,
-                                             const double*, const double*, int, int, int, const SketchArgs&,
-                                             double*, const int*);
+template bool launch_project<float, float, false>(hipStream_t, const float*, float*, int64_t, int64_t, int,
+                                                  const float*, const double*, int, int, int, const SketchArgs&,
+                                                  float*, const int*);
+template bool launch_project<double, double, false>(hipStream_t, const double*, double*, int64_t, int64_t, int,
+                                                    const double*, const double*, int, int, int,
+                                                    const SketchArgs&, double*, const int*);
+template bool launch_project<float, bf16, true>(hipStream_t, const float*, bf16*, int64_t, int64_t, int,
+                                                const float*, const double*, int, int, int, const SketchArgs&,
+                                                float*, const int*);
 template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double*, const int*);
 template bool launch_scale_col<double>(hipStream_t, double*, int64_t, const double*, const int*);
 template bool launch_ls<float>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, float*);
 template bool launch_ls<double>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, double*);
 template bool launch_ls_partials<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, int,
-                                               double*, int64_t, float*);
+                                               double*, int64_t, float*, const double*);
 template bool launch_ls_partials<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double, int,
-                                                 double*, int64_t, double*);
+                                                 double*, int64_t, double*, const double*);
 template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, const double*,
-                                          int, double*, int64_t, double*, int64_t, const double*, float*);
+                                          int, double*, int64_t, double*, int64_t, const double*, float*,
+                                          const double*);
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
-                                            double*);
+                                            double*, const double*);
+template bool launch_batch_project<float, float, false>(hipStream_t, int, const BatchItem*, const int2*, int, int);
+template bool launch_batch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const int2*, int, int);
+template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,
+                                         const int2*, int, int);
+template bool launch_batch_scale<float, false>(hipStream_t, const BatchItem*, const int2*, int);
+template bool launch_batch_scale<bf16, true>(hipStream_t, const BatchItem*, const int2*, int);
 template bool launch_materialize<float>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,
                                         double, double*, int64_t);
 template bool launch_materialize<double>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,
