@@ -52,20 +52,72 @@ def measured_traffic(n, m, k):
     """HBM bytes per launch of the projection kernel from the committed counter
     record, or None when the record is for another size or the kernel sources
     have changed since the counters were taken."""
-    import hashlib
     try:
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
     if (n, m, k) != (1 << 22, 512, 2048):
         return None
-    h = hashlib.sha256()
-    for f in rec["source_files"]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec["source_sha256"]:
+    if sources_sha256(rec["source_files"]) != rec["source_sha256"]:
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+TRAFFIC_SOURCES = ["paper_2011_05090_amd/csrc/rgs_kernels.hip", "paper_2011_05090_amd/csrc/rgs_block.hpp",
+                   "paper_2011_05090_amd/csrc/rgs_device.hpp"]
+PROJECT_KERNEL = "k_project<float, float, float, 1, false>"      # fp32 basis, P-SRHT, normalised storage
+
+
+def sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def write_traffic_record(fetch_db, write_db, n=1 << 22, m=512, k=2048):
+    """Turn two rocprofv3 --pmc databases (FETCH_SIZE, then WRITE_SIZE, of
+    ``bench.py --steps 1 --warmup 0 --no-extra --no-cpu-baseline --no-gmres
+    --calibrate-copy``) into the HBM-traffic record read by ``measured_traffic``.
+    The counters are scaled by what they read for the closing 1 GiB device copy."""
+    import sqlite3
+
+    def rows(db, counter):
+        con = sqlite3.connect(db)
+        out = list(con.execute("select dispatch_id, kernel_name, value from counters_collection "
+                               "where counter_name=? order by dispatch_id", (counter,)))
+        con.close()
+        return out
+
+    rec = {"kernel": "rgs::" + PROJECT_KERNEL,
+           "workload": "RGS QR fp32/fp64-LS, P-SRHT, n=%d, m=%d, k=%d (one factorisation = %d launches)" % (n, m, k, m)}
+    per = {}
+    for name, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        r = rows(db, counter)
+        proj = [v for _, kn, v in r if PROJECT_KERNEL in kn]
+        copies = [v for _, kn, v in r if "copyBuffer" in kn]
+        if len(proj) != m or not copies:
+            raise SystemExit("%s: expected %d projection dispatches and a closing copy, found %d and %d" %
+                             (db, m, len(proj), len(copies)))
+        cal_kib = copies[-1]
+        factor = cal_kib * 1024.0 / (1 << 30)       # counter KiB per byte moved, from the 1 GiB copy
+        per[name] = (sum(proj) / m, cal_kib, factor)
+    fetch_kib, fcal, ff = per["fetch"]
+    write_kib, wcal, wf = per["write"]
+    traffic = fetch_kib * 1024.0 / ff + write_kib * 1024.0 / wf
+    alg = project_bytes(n, m, 4) / m
+    rec.update({"launches": m, "fetch_size_kib_per_launch_raw": fetch_kib, "write_size_kib_per_launch_raw": write_kib,
+                "copy_calibration": {"kernel": "__amd_rocclr_copyBuffer", "bytes_read": 1 << 30,
+                                     "bytes_written": 1 << 30, "fetch_size_kib": fcal, "write_size_kib": wcal,
+                                     "fetch_factor": ff, "write_factor": wf},
+                "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": alg,
+                "source_files": TRAFFIC_SOURCES, "source_sha256": sources_sha256(TRAFFIC_SOURCES),
+                "traffic_over_algorithmic": traffic / alg})
+    with open(TRAFFIC_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def run_steps(rgs, torch, h, desc, W, Q, R, S, steps, warmup):
@@ -116,6 +168,84 @@ def cpu_baseline(n=1 << 21, m=48, k=2048):
             "sample": "oracle fp32-model RGS, P-SRHT k=%d, W %dx%d (sigma 1..1e-8), %.1f s wall" % (k, n, m, dt)}
 
 
+def small_fp64_leg(rgs, torch, synth, h, n=16384, m=64, k=256, steps=20, warmup=3):
+    """Plain fp64 RGS with the Gaussian sketch at n = 16384, m = 64, k = 256: a
+    latency-bound size (64 dependent column steps), reported in us per column."""
+    W = rgs.colmajor(n, m, torch.float64)
+    W.copy_(torch.from_numpy(synth.svd_matrix(n, m, 1e-6, tag=0)))
+    Q = rgs.colmajor(n, m, torch.float64)
+    R = rgs.colmajor(m, m, torch.float64)
+    S = rgs.colmajor(k, m, torch.float64)
+    d = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp64")
+    ms, _, rep = run_steps(rgs, torch, h, d, W, Q, R, S, steps, warmup)
+    res, d2, o2 = quality(torch, W, Q, R, S)
+    out = {"n": n, "m": m, "k": k, "sketch": "gaussian", "ms_per_qr": ms, "us_per_column": 1000.0 * ms / m,
+           "gbs": qr_bytes(n, m, 8) / (ms / 1000.0) / 1e9, "status": rep.status, "backward_error": res,
+           "norm2_I_minus_StS": d2}
+    log("  fp64 RGS n=%d m=%d k=%d Gaussian: %.3f ms/QR (%.1f us/column), ||W-QR||/||W|| %.2e" %
+        (n, m, k, ms, 1000.0 * ms / m, res))
+    return out
+
+
+def batched_qr_bytes(n, m):
+    """Algorithmic bytes of one bf16-stored factorisation (fp32 W, bf16 Q):
+    P = Theta W reads W (4nm), the projections read w_i (4nm) and Q_{i-1}
+    (2n i per column, 2n m(m-1)/2 in all) and write q'_i (2nm), and the closing
+    scale pass reads and writes Q (4nm)."""
+    return n * (m * (m - 1) + 14 * m)
+
+
+def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian"), steps=2, warmup=1,
+                   gaussian_batch=256):
+    """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
+    m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and bf16-stored Q, all in
+    one rgs_qr_batched call.  The Gaussian sketch regenerates its entries per
+    factorisation, so it runs on the first ``gaussian_batch`` items only."""
+    ns, ms_ = synth.batch_qr_sizes(batch)
+    items = []
+    t0 = time.perf_counter()
+    for b in range(batch):
+        n, m = int(ns[b]), int(ms_[b])
+        k = 4 * m
+        W64 = synth.svd_matrix_torch(n, m, 1e-6, tag=1000 + b)
+        W = rgs.colmajor(n, m, torch.float32)
+        W.copy_(W64)
+        del W64
+        items.append((W, rgs.colmajor(n, m, torch.bfloat16), rgs.colmajor(m, m, torch.float64),
+                      rgs.colmajor(k, m, torch.float64), k))
+    torch.cuda.synchronize()
+    log("  generated %d inputs in %.1f s" % (batch, time.perf_counter() - t0))
+    out = {"batch": batch, "n_range": [4096, 262144], "m_range": [16, 128], "k": "4m", "q_dtype": "bf16",
+           "sigma_min": 1e-6}
+    for sketch in sketches:
+        its = items if sketch == "srht" else items[:gaussian_batch]
+        B = sum(batched_qr_bytes(W.shape[0], W.shape[1]) for W, *_ in its)
+        for _ in range(warmup):
+            rgs.rgs_qr_batched(h, its, sketch=sketch, prec="bf16q")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rep, stat, _ = rgs.rgs_qr_batched(h, its, sketch=sketch, prec="bf16q")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        bad = sum(1 for v in stat if v != 0)
+        # quality on a few items (fp64 on the device, spectral norms on the host)
+        import numpy as np
+        worst_be, worst_d2 = 0.0, 0.0
+        for W, Q, R, S, _ in its[:: max(1, len(its) // 8)]:
+            be, d2, _ = quality(torch, W, Q.float(), R, S)
+            worst_be, worst_d2 = max(worst_be, be), max(worst_d2, d2)
+        out[sketch] = {"items": len(its), "seconds": dt, "algorithmic_bytes": B, "gbs": B / dt / 1e9,
+                       "pct_hbm_peak": 100.0 * B / dt / 1e9 / HBM_PEAK_GBS, "failed_items": bad,
+                       "status": rep.status, "sampled_max_backward_error": worst_be,
+                       "sampled_max_norm2_I_minus_StS": worst_d2}
+        log("  batched %s x%d: %.3f s, %.1f GB/s algorithmic, max sampled ||W-QR||/||W|| %.2e, "
+            "||I-S^TS||_2 %.2e, failed %d" % (sketch, len(its), dt, B / dt / 1e9, worst_be, worst_d2, bad))
+    del items
+    torch.cuda.empty_cache()
+    return out
+
+
 def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6):
     """Time-to-1e-6 of restarted randomized GMRES on the 7-point convection-diffusion
     system (N^3 unknowns, b ~ N(0,1)), fp32 basis vs plain fp64, Gaussian and SRHT."""
@@ -153,9 +283,16 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the fp64 / Gaussian / companion QR legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true", help="skip the randomized GMRES leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched and small fp64 QR legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
+                         "databases (no GPU needed) and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(rows would be sharded by blocks with one all-reduce of the sketch per column); "
@@ -239,8 +376,14 @@ def main():
                                          "norm2_I_minus_QtQ": co2}
         log("  companion sigma->1e-3: ||W-QR||/||W|| %.2e  ||I-S^TS||_2 %.2e" % (cres, cd2))
         out["extra"] = extra
+    if not args.no_batched:
+        log("plain fp64 RGS, small size (latency-bound)")
+        out.setdefault("extra", {})["fp64_rgs_n16384_m64"] = small_fp64_leg(rgs, torch, synth, h)
     if not args.no_gmres:
         out.setdefault("extra", {})["rgmres_convdiff_192"] = gmres_leg(rgs, torch, synth, h)
+    if not args.no_batched:
+        log("batched RGS QR (bf16 Q)")
+        out["extra"]["batched_qr_2048"] = batched_qr_leg(rgs, torch, synth, h)
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -71,6 +71,8 @@ typedef enum {
 /* Flags for rgs_qr_desc.flags / rgs_gmres_desc.flags */
 #define RGS_FLAG_DIAGNOSTICS 1u  /* compute step 8 of Algorithm 2 (Delta_m, tilde Delta_m) */
 #define RGS_FLAG_TIME_KERNELS 2u /* time every projection+sketch launch with events */
+#define RGS_FLAG_GRAPH 4u        /* rgs_gmres_batched: capture a restart cycle once as a HIP graph
+                                    and replay it while the set of running systems is unchanged */
 
 /* Describes one RGS factorisation and its sketch Theta (k x n).
  * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
@@ -108,7 +110,7 @@ typedef struct {
     int32_t sketch;     /* rgs_sketch (GAUSSIAN or SRHT) */
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
-    uint32_t flags;
+    uint32_t flags;     /* rgs_gmres: ignored; rgs_gmres_batched: 0 or RGS_FLAG_GRAPH */
 } rgs_gmres_desc;
 
 typedef struct {
@@ -136,6 +138,15 @@ typedef struct {
     double *S;            /* k x m, lds >= k */
     int64_t lds;
 } rgs_qr_item;
+
+/* One system of a batched GMRES call (b and x device memory, res_hist host). */
+typedef struct {
+    rgs_stencil7 A;       /* operator of this system (its own grid and coefficients) */
+    const double *b;      /* [n], n = nx*ny*nz */
+    double *x;            /* [n] output, x0 = 0 */
+    double *res_hist;     /* host, hist_cap entries, may be NULL when hist_cap == 0 */
+    int64_t hist_cap;
+} rgs_gmres_item;
 
 /* Library version of this header (RGS_ABI_VERSION). */
 int rgs_abi_version(void);
@@ -209,10 +220,32 @@ rgs_status rgs_sketch_materialize(rgs_handle *h, const rgs_qr_desc *desc, int64_
  *   res_hist (host, may be NULL) receives |g_i|/||b||_2 after each inner step,
  *      up to hist_cap entries (the sketched residual ||Theta(b - A x_i)||, Sec. 4.2).
  *   rep (host, may be NULL).
+ * desc->prec: FP64, FP32_LS64 or BF16Q_FP32_LS64 (basis stored unnormalised in
+ * bf16 with fp64 scales; the mat-vec input is fl32(stored column / r_ii)).
  * Returns OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE or ENOCONV. */
 rgs_status rgs_gmres(rgs_handle *h, const rgs_stencil7 *A, const rgs_gmres_desc *desc,
                      const double *b, double *x, double *res_hist, int64_t hist_cap,
                      rgs_report *rep);
+
+/* A batch of independent restarted randomized GMRES solves (Sec. 4.2, on
+ * RGS-Arnoldi, Algorithm 3) of uneven sizes, sharing one descriptor (restart,
+ * k, tol, max_iters, sketch, precision).  The systems advance in lockstep, one
+ * restart cycle at a time: each inner step is one launch of each kernel over
+ * every system still running; a system stops itself on the device when its
+ * sketched residual reaches tol (or at a lucky breakdown), and drops out of
+ * later cycles once its true residual ||b - A x||/||b|| <= tol (fp64).
+ *   items (host array of `batch` <= 65535 entries); every system's sketch is
+ *   the one a separate rgs_gmres call with the same descriptor would use
+ *   (instance 0, its own n), so each system's x, history and counts equal
+ *   those of a separate call.
+ *   desc->sketch: GAUSSIAN or SRHT.  desc->flags: 0 or RGS_FLAG_GRAPH.
+ *   item_status (host, `batch` entries, may be NULL): RGS_OK, RGS_ENONFINITE or
+ *   RGS_ENOCONV per system; reps (host, `batch` entries, may be NULL): per
+ *   system iters, cycles, true_relres (seconds = the whole call).
+ * Returns RGS_OK when every system converged, the first failing system's
+ * status otherwise, or EINVAL / ENOMEM / EDEVICE. */
+rgs_status rgs_gmres_batched(rgs_handle *h, int64_t batch, const rgs_gmres_item *items,
+                             const rgs_gmres_desc *desc, int32_t *item_status, rgs_report *reps);
 
 /* w = A u for the 7-point operator (the mat-vec of Algorithm 3, step 3), in
  * the working precision of `prec` (u, w: float for FP32_LS64, double for FP64).

@@ -18,12 +18,17 @@ Readings (the paper runs a single unrestarted Arnoldi process):
   * iteration count = total number of inner steps (mat-vecs A q).
 Precision 'fp32' follows the multi-precision model: basis, mat-vec and the
 projection in float32, sketches / least squares / Givens / x in fp64.
+Precision 'bf16q' is 'fp32' with the basis stored in bfloat16, as in the
+'bf16q' model of ``oracle.rgs``: column i is kept unnormalised as
+qb_i = bf16(q'_i) with the fp64 scale 1/r_ii, its sketch is taken of qb_i, the
+mat-vec input is fl32(qb_{i-1} / r_{i-1,i-1}), the projection uses the stored
+columns with coefficients fl32(y_c / r_cc), and x += sum_c qb_c (y_c / r_cc).
 """
 
 import numpy as np
 import scipy.linalg
 
-from .rgs import _ls, BREAKDOWN_RATIO
+from .rgs import _ls, bf16_round, BREAKDOWN_RATIO
 
 
 def _givens(a, b):
@@ -42,7 +47,10 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
     Returns dict(x, hist, iters, cycles, true_relres, converged, cond_info).
     hist[t] = |g| / ||b|| after global inner step t.
     """
+    if precision not in ("fp64", "fp32", "bf16q"):
+        raise ValueError(precision)
     store = np.float64 if precision == "fp64" else np.float32
+    bf16 = precision == "bf16q"
     b = np.asarray(b, dtype=np.float64)
     n = b.size
     bnorm = np.linalg.norm(b)
@@ -57,37 +65,57 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
         theta = make_theta(0 if reuse_theta else cycle)
         k = theta.k
         mmax = restart + 1
-        Q = np.zeros((n, mmax), dtype=store)
+        Q = np.zeros((n, mmax), dtype=store)     # bf16q: the stored, unnormalised columns
+        scale = np.zeros(mmax)                   # bf16q: 1 / r_ii of each stored column
         S = np.zeros((k, mmax))
         R = np.zeros((mmax, mmax))
         # step 1-2 of Algorithm 3: w_1 = r_0, first RGS iteration
         w = r0.astype(store)
-        p = theta.apply(w.astype(np.float64))
+        if bf16:
+            Q[:, 0] = bf16_round(w)
+            p = theta.apply(Q[:, 0].astype(np.float64))
+        else:
+            p = theta.apply(w.astype(np.float64))
         r11 = np.linalg.norm(p)
         if r11 == 0.0:
             converged = True
             break
         R[0, 0] = r11
         S[:, 0] = p / r11
-        Q[:, 0] = (w.astype(np.float64) / r11).astype(store)
+        if bf16:
+            scale[0] = 1.0 / r11
+        else:
+            Q[:, 0] = (w.astype(np.float64) / r11).astype(store)
         g = np.zeros(mmax)
         g[0] = r11
         cs = np.zeros(mmax)
         sn = np.zeros(mmax)
         used = 0                                    # columns of H (= inner steps)
         for i in range(1, mmax):                    # 0-based index of the new column
-            w = apply_A(Q[:, i - 1], store)         # step 3 of Algorithm 3
+            if bf16:
+                q_prev = (Q[:, i - 1].astype(np.float64) * scale[i - 1]).astype(store)
+            else:
+                q_prev = Q[:, i - 1]
+            w = apply_A(q_prev, store)              # step 3 of Algorithm 3
             p = theta.apply(w.astype(np.float64))   # RGS step 1
             r = _ls(S[:, :i], p, ls)                # RGS step 2
             R[:i, i] = r
-            qp = w - Q[:, :i] @ r.astype(store)     # RGS step 3
-            sp = theta.apply(qp.astype(np.float64))  # RGS step 4
+            if bf16:
+                qp = w - Q[:, :i] @ (r * scale[:i]).astype(store)   # RGS step 3 on the stored columns
+                Q[:, i] = bf16_round(qp)
+                sp = theta.apply(Q[:, i].astype(np.float64))        # RGS step 4 of the stored column
+            else:
+                qp = w - Q[:, :i] @ r.astype(store)     # RGS step 3
+                sp = theta.apply(qp.astype(np.float64))  # RGS step 4
             rii = np.linalg.norm(sp)                # RGS step 5
             lucky = rii == 0.0 or rii <= BREAKDOWN_RATIO * np.linalg.norm(p)
             R[i, i] = 0.0 if lucky else rii
             if not lucky:
                 S[:, i] = sp / rii                  # RGS step 6
-                Q[:, i] = (qp.astype(np.float64) / rii).astype(store)  # RGS step 7
+                if bf16:
+                    scale[i] = 1.0 / rii            # RGS step 7, kept as a scale
+                else:
+                    Q[:, i] = (qp.astype(np.float64) / rii).astype(store)  # RGS step 7
             # Hessenberg column i-1 (0-based) = R(0:i+1, i); Givens in fp64
             h = R[: i + 1, i].copy()
             for t in range(i - 1):
@@ -108,6 +136,8 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
         # y = argmin || H z - r11 e1 ||: back substitution on the rotated H
         Hr = R[:used, 1:used + 1]
         y = scipy.linalg.solve_triangular(Hr, g[:used], lower=False)
+        if bf16:
+            y = y * scale[:used]
         x = x + Q[:, :used].astype(np.float64) @ y
         r0 = b - apply_A(x, np.float64)
         true_relres = np.linalg.norm(r0) / bnorm

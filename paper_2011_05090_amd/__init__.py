@@ -22,6 +22,7 @@ SKETCH = {"gaussian": 0, "srht": 1, "identity": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16q": 2}
 FLAG_DIAGNOSTICS = 1
 FLAG_TIME_KERNELS = 2
+FLAG_GRAPH = 4
 
 
 class RgsError(RuntimeError):
@@ -54,6 +55,11 @@ class QrItem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("W", ctypes.c_void_p), ("ldw", ctypes.c_int64), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64),
                 ("R", ctypes.c_void_p), ("ldr", ctypes.c_int64), ("S", ctypes.c_void_p), ("lds", ctypes.c_int64)]
+
+
+class GmresItem(ctypes.Structure):
+    _fields_ = [("A", Stencil7), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("res_hist", ctypes.c_void_p),
+                ("hist_cap", ctypes.c_int64)]
 
 
 class Report(ctypes.Structure):
@@ -89,6 +95,8 @@ SIGNATURES = {
     "rgs_qr_batched": (ctypes.c_int, [_P, _I64, ctypes.POINTER(QrItem), ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Report)]),
+    "rgs_gmres_batched": (ctypes.c_int, [_P, _I64, ctypes.POINTER(GmresItem), ctypes.POINTER(GmresDesc),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Report)]),
 }
 
 _lib = None
@@ -289,6 +297,33 @@ def rgs_gmres(handle, A, desc, b, x, res_hist=None, allow=(RGS_ENOCONV,)):
     rep.status = st
     used = min(cap, rep.iters)
     return rep, [hist[i] for i in range(used)]
+
+
+def rgs_gmres_batched(handle, systems, desc, hist_cap=0, allow=(RGS_ENOCONV, RGS_ENONFINITE)):
+    """Batched randomized GMRES.  systems: list of (Stencil7, b, x) with b, x
+    float64 device tensors of nx*ny*nz entries.  Returns (status, per-system
+    statuses, per-system Reports, per-system histories)."""
+    import torch
+    B = len(systems)
+    arr = (GmresItem * B)()
+    hists = []
+    for i, (A, b, x) in enumerate(systems):
+        n = A.nx * A.ny * A.nz
+        if b.numel() != n or x.numel() != n:
+            raise ValueError("system %d: b and x must have nx*ny*nz entries" % i)
+        h = (ctypes.c_double * max(int(hist_cap), 1))()
+        hists.append(h)
+        arr[i] = GmresItem(A=A, b=_dev(b, "b", torch.float64), x=_dev(x, "x", torch.float64),
+                           res_hist=ctypes.cast(h, ctypes.c_void_p) if hist_cap else None, hist_cap=int(hist_cap))
+    stat = (ctypes.c_int32 * B)()
+    reps = (Report * B)()
+    st = lib().rgs_gmres_batched(handle.ptr, B, arr, ctypes.byref(desc), stat, reps)
+    _check(st, "rgs_gmres_batched", allow)
+    out = []
+    for i in range(B):
+        reps[i].status = stat[i]
+        out.append(reps[i])
+    return st, list(stat), out, [[hists[i][t] for t in range(min(int(hist_cap), out[i].iters))] for i in range(B)]
 
 
 def rgs_stencil_apply(handle, A, prec, u, w):

@@ -23,6 +23,7 @@ using namespace rgs;
 struct rgs_handle {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;   // created on first use: graph capture needs a non-null stream
     char* arena = nullptr;
     size_t arena_bytes = 0;
     std::vector<hipEvent_t> events;
@@ -47,7 +48,7 @@ rgs_status ensure_arena(rgs_handle* h, size_t bytes) {
     if (h->arena_bytes >= bytes) return RGS_OK;
     if (h->arena) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) return RGS_EDEVICE;
-        hipFree(h->arena);
+        (void)hipFree(h->arena);
         h->arena = nullptr;
         h->arena_bytes = 0;
     }
@@ -376,7 +377,7 @@ StencilArgs stencil_args(const rgs_stencil7* A) {
 // Restarted randomized GMRES (Sec. 4.2) driven from the host: one restart
 // cycle is enqueued in full (its inner steps stop themselves on the device
 // once converged), then the host synchronises once to read the true residual.
-template <typename T>
+template <typename T, typename TQ, bool DEFER>
 rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc* d, const double* b, double* x,
                      double* res_hist, int64_t hist_cap, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -386,7 +387,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T));
     Carver c;
     c.off = pl.total;
-    const size_t oQ = c.take<T>((size_t)n * mcap), oW = c.take<T>(n), oR = c.take<double>(mcap * mcap);
+    const size_t oQ = c.take<TQ>((size_t)n * mcap), oW = c.take<T>(n), oR = c.take<double>(mcap * mcap);
     const size_t oS = c.take<double>(k * mcap), oHr = c.take<double>(mcap * mcap), ocs = c.take<double>(mcap);
     const size_t osn = c.take<double>(mcap), ogv = c.take<double>(mcap + 1), oy = c.take<double>(mcap);
     const size_t ohist = c.take<double>(mcap), oused = c.take<int>(4), or_ = c.take<double>(n);
@@ -395,7 +396,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     if (st != RGS_OK) return st;
     char* Ar = h->arena;
     SpaceArgs sa = space_args(Ar, pl, k, mcap);
-    T* Q = reinterpret_cast<T*>(Ar + oQ);
+    TQ* Q = reinterpret_cast<TQ*>(Ar + oQ);
     T* wbuf = reinterpret_cast<T*>(Ar + oW);
     double* R = reinterpret_cast<double*>(Ar + oR);
     double* S = reinterpret_cast<double*>(Ar + oS);
@@ -438,7 +439,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
         // RGS step 1 of Algorithm 3: w_1 = r_0
         if (!launch_cast<T>(s, r, wbuf, n)) return RGS_EDEVICE;
-        if (!launch_project<T, T, false>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, 1, vec_ok ? 1 : 0, sk, part, sa.status))
+        if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, 1, vec_ok ? 1 : 0, sk, part,
+                                          sa.status))
             return RGS_EDEVICE;
         if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, 0, S, k, R, mcap, nullptr, coef, nullptr))
             return RGS_EDEVICE;
@@ -447,19 +449,22 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         for (int64_t ci = 1; ci <= steps; ++ci) {
             const int i = (int)ci;
             // w_i = A q_{i-1}, sketched: p_i (step 3 of Algorithm 3, step 1 of Algorithm 2)
-            if (!launch_stencil_sketch<T, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
-                                             sa.status))
+            if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
+                                              sa.status))
                 return RGS_EDEVICE;
-            if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, nullptr)) return RGS_EDEVICE;
-            if (!launch_project<T, T, false>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), 1, 1, vec_ok ? 1 : 0, sk,
-                                             part, sa.status))
+            if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr))
+                return RGS_EDEVICE;
+            if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
+                                              vec_ok ? 1 : 0, sk, part, sa.status))
                 return RGS_EDEVICE;
             if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef, nullptr))
                 return RGS_EDEVICE;
-            if (!launch_givens(s, i, R, (int)mcap, Hr, cs, sn, gv, bnorm, d->tol, hist, sa.status, used))
+            if (!launch_givens(s, i, R, (int)mcap, Hr, cs, sn, gv, bnorm, d->tol, hist, sa.status, used,
+                               (int)steps))
                 return RGS_EDEVICE;
         }
-        if (!launch_update_x<T>(s, Hr, (int)mcap, gv, used, y, x, Q, n, n)) return RGS_EDEVICE;
+        if (!launch_update_x<TQ>(s, Hr, (int)mcap, gv, used, y, x, Q, n, n, DEFER ? sa.invr : nullptr))
+            return RGS_EDEVICE;
         if (!launch_residual(s, A, b, x, r, rpart, norm)) return RGS_EDEVICE;
         int stat[4] = {0, 0, 0, 0};
         int u = 0;
@@ -716,6 +721,387 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     return result;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched randomized GMRES.  The systems advance in lockstep, one restart
+// cycle at a time: a cycle is one launch sequence over the systems still
+// running (optionally captured once as a HIP graph and replayed while that set
+// does not change).  Inside a cycle each system stops itself on the device
+// (converged, lucky breakdown, or its step limit); between cycles the host
+// reads every system's status, step count and true residual.  Every system
+// uses the sketch instance 0 with its own n, exactly as a separate rgs_gmres
+// call on it, so the batched solve reproduces separate solves bit for bit.
+// ---------------------------------------------------------------------------
+bool grid_size(const rgs_stencil7& A, int64_t* n) {
+    if (A.nx < 1 || A.ny < 1 || A.nz < 1) return false;
+    const double nd = (double)A.nx * (double)A.ny * (double)A.nz;
+    if (!(nd <= (double)(((int64_t)1 << 31) - 1))) return false;
+    *n = A.nx * A.ny * A.nz;
+    return true;
+}
+
+bool valid_gmres_desc(const rgs_gmres_desc* d) {
+    if (!d) return false;
+    if (d->restart < 1 || d->restart + 1 > d->k || d->restart > 4000 || d->max_iters < 1 || !(d->tol >= 0))
+        return false;
+    return d->prec == RGS_P_FP64 || d->prec == RGS_P_FP32_LS64 || d->prec == RGS_P_BF16Q_FP32_LS64;
+}
+
+struct GmresMaps {
+    std::vector<int2> m;
+    size_t sys, row, proj, sl;
+    int nsys, nrow, nproj, nsl;
+    std::vector<size_t> qd, rb;
+    std::vector<int> nqd, nrb;
+};
+
+void build_gmres_maps(GmresMaps& g, const std::vector<int64_t>& active, const std::vector<int64_t>& ns, int64_t k,
+                      int64_t restart) {
+    g.m.clear();
+    const int64_t nsl = (k + kSlice - 1) / kSlice;
+    auto add = [&](int64_t per_sys_fn_tag, size_t& at, int& cnt, int64_t extra) {
+        at = g.m.size();
+        for (int64_t b : active) {
+            int64_t blocks = 0;
+            switch (per_sys_fn_tag) {
+                case 0: blocks = 1; break;
+                case 1: blocks = (ns[b] + 255) / 256; break;
+                case 2: blocks = (ns[b] + kProjRows - 1) / kProjRows; break;
+                case 3: blocks = nsl + extra; break;
+                default: blocks = extra; break;
+            }
+            for (int64_t q = 0; q < blocks; ++q) g.m.push_back({(int)b, (int)q});
+        }
+        cnt = (int)(g.m.size() - at);
+    };
+    add(0, g.sys, g.nsys, 0);
+    add(1, g.row, g.nrow, 0);
+    add(2, g.proj, g.nproj, 0);
+    add(3, g.sl, g.nsl, 0);
+    g.qd.assign((size_t)restart + 1, 0);
+    g.nqd.assign((size_t)restart + 1, 0);
+    g.rb.assign((size_t)restart + 1, 0);
+    g.nrb.assign((size_t)restart + 1, 0);
+    for (int64_t i = 0; i <= restart; ++i) add(3, g.qd[i], g.nqd[i], (i + 1 + 63) / 64);
+    for (int64_t i = 1; i <= restart; ++i) add(4, g.rb[i], g.nrb[i], (i + 63) / 64);
+}
+
+template <typename T, typename TQ, bool DEFER>
+rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,
+                             int32_t* item_status, rgs_report* reps) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = h->stream;
+    const int sk_kind = sketch_kind(d->sketch);
+    const int64_t restart = d->restart, mcap = restart + 1, k = d->k;
+    const int64_t nsl = (k + kSlice - 1) / kSlice;
+    const bool use_graph = (d->flags & RGS_FLAG_GRAPH) != 0;
+    std::vector<int64_t> ns((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) grid_size(items[b].A, &ns[b]);
+
+    // scratch of every system, carved from the handle's arena
+    struct Off {
+        size_t Q, w, r, rpart, R, S, part, coef, Vc, Vr, Wc, Wr, X, sp, u, v, pbuf, uh, pd, pdb, pd2, rr, invr, pnorm,
+            tau, beta, Hr, cs, sn, gv, y, signs;
+    };
+    std::vector<Off> off((size_t)batch);
+    Carver c;
+    for (int64_t b = 0; b < batch; ++b) {
+        const int64_t n = ns[b], nproj = (n + kProjRows - 1) / kProjRows;
+        Off& o = off[b];
+        o.Q = c.take<TQ>((size_t)n * mcap);
+        o.w = c.take<T>(n);
+        o.r = c.take<double>(n);
+        o.rpart = c.take<double>((n + 255) / 256);
+        o.R = c.take<double>(mcap * mcap);
+        o.S = c.take<double>(k * mcap);
+        o.part = c.take<T>(nproj * k);
+        o.coef = c.take<T>(mcap);
+        o.Vc = c.take<double>(k * mcap);
+        o.Vr = c.take<double>(k * mcap);
+        o.Wc = c.take<double>(k * mcap);
+        o.Wr = c.take<double>(k * mcap);
+        o.X = c.take<double>(mcap * mcap);
+        o.sp = c.take<double>(k);
+        o.u = c.take<double>(k);
+        o.v = c.take<double>(k);
+        o.pbuf = c.take<double>(k);
+        o.uh = c.take<double>(mcap + 1);
+        o.pd = c.take<double>(nsl * (mcap + 1));
+        o.pdb = c.take<double>(nsl * (mcap + 2));
+        o.pd2 = c.take<double>(nsl);
+        o.rr = c.take<double>(mcap);
+        o.invr = c.take<double>(mcap);
+        o.pnorm = c.take<double>(mcap);
+        o.tau = c.take<double>(mcap);
+        o.beta = c.take<double>(mcap);
+        o.Hr = c.take<double>(mcap * mcap);
+        o.cs = c.take<double>(mcap);
+        o.sn = c.take<double>(mcap);
+        o.gv = c.take<double>(mcap + 1);
+        o.y = c.take<double>(mcap);
+        o.signs = sk_kind == SK_SRHT ? c.take<uint32_t>((n + 31) / 32 + 4) : 0;
+    }
+    const size_t o_rows = c.take<int>(sk_kind == SK_SRHT ? k * batch : 1);
+    const size_t o_status = c.take<int>(4 * batch), o_used = c.take<int>(batch), o_limit = c.take<int>(batch);
+    const size_t o_norm = c.take<double>(batch), o_hist = c.take<double>(batch * mcap);
+    const size_t o_items = c.take<BatchItem>(batch), o_gitems = c.take<GmresItem>(batch);
+    std::vector<int64_t> all((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) all[b] = b;
+    GmresMaps gm;
+    build_gmres_maps(gm, all, ns, k, restart);
+    const size_t o_maps = c.take<int2>(gm.m.size());
+    rgs_status st = ensure_arena(h, c.off + kAlign);
+    if (st != RGS_OK) return st;
+    char* A = h->arena;
+
+    std::vector<BatchItem> bi((size_t)batch);
+    std::vector<GmresItem> gi((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) {
+        const Off& o = off[b];
+        const int64_t n = ns[b];
+        BatchItem& x = bi[b];
+        x = BatchItem{};
+        x.n = n;
+        x.m = (int)mcap;
+        x.k = (int)k;
+        x.nproj = (int)((n + kProjRows - 1) / kProjRows);
+        x.nsl = (int)nsl;
+        x.Q = A + o.Q;
+        x.ldq = n;
+        x.R = reinterpret_cast<double*>(A + o.R);
+        x.ldr = mcap;
+        x.S = reinterpret_cast<double*>(A + o.S);
+        x.lds = k;
+        x.P = nullptr;
+        x.part = A + o.part;
+        x.coef = A + o.coef;
+        x.sketch_scale = 1.0 / std::sqrt((double)k);
+        x.vec_ok = (n % 4 == 0) ? 1 : 0;
+        x.defer = DEFER ? 1 : 0;
+        SpaceArgs& a = x.sa;
+        a.k = (int)k;
+        a.mcap = (int)mcap;
+        a.Vc = reinterpret_cast<double*>(A + o.Vc);
+        a.Vr = reinterpret_cast<double*>(A + o.Vr);
+        a.Wc = reinterpret_cast<double*>(A + o.Wc);
+        a.Wr = reinterpret_cast<double*>(A + o.Wr);
+        a.X = reinterpret_cast<double*>(A + o.X);
+        a.sp = reinterpret_cast<double*>(A + o.sp);
+        a.u = reinterpret_cast<double*>(A + o.u);
+        a.v = reinterpret_cast<double*>(A + o.v);
+        a.pbuf = reinterpret_cast<double*>(A + o.pbuf);
+        a.uh = reinterpret_cast<double*>(A + o.uh);
+        a.pd = reinterpret_cast<double*>(A + o.pd);
+        a.pdb = reinterpret_cast<double*>(A + o.pdb);
+        a.pd2 = reinterpret_cast<double*>(A + o.pd2);
+        a.rr = reinterpret_cast<double*>(A + o.rr);
+        a.invr = reinterpret_cast<double*>(A + o.invr);
+        a.pnorm = reinterpret_cast<double*>(A + o.pnorm);
+        a.tau = reinterpret_cast<double*>(A + o.tau);
+        a.beta = reinterpret_cast<double*>(A + o.beta);
+        a.status = reinterpret_cast<int*>(A + o_status) + 4 * b;
+        x.sk = make_sketch(sk_kind, k, d->seed, 2, 0);
+        if (sk_kind == SK_SRHT) {
+            x.sk.signs = reinterpret_cast<uint32_t*>(A + o.signs);
+            x.sk.rows = reinterpret_cast<int*>(A + o_rows) + b * k;
+        }
+        GmresItem& g = gi[b];
+        g = GmresItem{};
+        g.n = n;
+        g.A = stencil_args(&items[b].A);
+        g.b = items[b].b;
+        g.x = items[b].x;
+        g.r = reinterpret_cast<double*>(A + o.r);
+        g.w = A + o.w;
+        g.rpart = reinterpret_cast<double*>(A + o.rpart);
+        g.norm = reinterpret_cast<double*>(A + o_norm) + b;
+        g.tol = d->tol;
+        g.Hr = reinterpret_cast<double*>(A + o.Hr);
+        g.cs = reinterpret_cast<double*>(A + o.cs);
+        g.sn = reinterpret_cast<double*>(A + o.sn);
+        g.gv = reinterpret_cast<double*>(A + o.gv);
+        g.y = reinterpret_cast<double*>(A + o.y);
+        g.hist = reinterpret_cast<double*>(A + o_hist) + b * mcap;
+        g.used = reinterpret_cast<int*>(A + o_used) + b;
+        g.limit = reinterpret_cast<int*>(A + o_limit) + b;
+    }
+    BatchItem* itd = reinterpret_cast<BatchItem*>(A + o_items);
+    GmresItem* gid = reinterpret_cast<GmresItem*>(A + o_gitems);
+    const int2* mp = reinterpret_cast<const int2*>(A + o_maps);
+    if (hipMemcpyAsync(A + o_gitems, gi.data(), gi.size() * sizeof(GmresItem), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(A + o_maps, gm.m.data(), gm.m.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        return RGS_EDEVICE;
+    // x0 = 0, r0 = b, ||b|| of every system
+    if (!launch_gbatch_zero_x(s, gid, mp + gm.row, gm.nrow) ||
+        !launch_gbatch_residual(s, gid, mp + gm.sys, gm.nsys, mp + gm.row, gm.nrow))
+        return RGS_EDEVICE;
+    std::vector<double> bn((size_t)batch), rn((size_t)batch), hh((size_t)(batch * mcap));
+    if (hipMemcpyAsync(bn.data(), A + o_norm, batch * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return RGS_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // host vectors above stay alive till here
+    for (int64_t b = 0; b < batch; ++b) gi[b].bnorm = bn[b];
+    if (hipMemcpyAsync(A + o_gitems, gi.data(), gi.size() * sizeof(GmresItem), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return RGS_EDEVICE;
+
+    std::vector<int64_t> iters((size_t)batch, 0), cycles((size_t)batch, 0), nhist((size_t)batch, 0);
+    std::vector<double> relres((size_t)batch, 1.0);
+    std::vector<rgs_status> res((size_t)batch, RGS_OK);
+    std::vector<char> done((size_t)batch, 0);
+    for (int64_t b = 0; b < batch; ++b) {
+        if (!std::isfinite(bn[b])) {
+            res[b] = RGS_ENONFINITE;
+            done[b] = 1;
+        } else if (!(bn[b] > 0)) {
+            relres[b] = 0.0;
+            done[b] = 1;
+        }
+    }
+    std::vector<int> lim((size_t)batch, 0), stat((size_t)(4 * batch)), usedh((size_t)batch);
+    std::vector<int> rows_all;
+    std::vector<int64_t> active, prev_active;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto drop_graph = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto enqueue_cycle = [&](hipStream_t q) -> bool {
+        if (!launch_gbatch_reset(q, itd, mp + gm.sys, gm.nsys)) return false;
+        if (!launch_gbatch_cast<T>(q, gid, mp + gm.row, gm.nrow)) return false;
+        if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, 0)) return false;
+        if (!launch_batch_column<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.qd[0], gm.nqd[0], nullptr, 0, 0))
+            return false;
+        if (!launch_gbatch_givens_init(q, itd, gid, mp + gm.sys, gm.nsys)) return false;
+        for (int64_t i = 1; i <= restart; ++i) {
+            const int ii = (int)i;
+            if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii)) return false;
+            if (!launch_gbatch_ls<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.rb[i], gm.nrb[i], ii)) return false;
+            if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii)) return false;
+            if (!launch_batch_column<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.qd[i], gm.nqd[i], nullptr, 0, ii))
+                return false;
+            if (!launch_gbatch_givens(q, itd, gid, mp + gm.sys, gm.nsys, ii)) return false;
+        }
+        return launch_gbatch_finish<TQ>(q, itd, gid, mp + gm.sys, gm.nsys, mp + gm.row, gm.nrow);
+    };
+    rgs_status fail = RGS_OK;
+    for (int64_t cycle = 0;; ++cycle) {
+        active.clear();
+        for (int64_t b = 0; b < batch; ++b) {
+            if (done[b]) continue;
+            if (iters[b] >= d->max_iters) {
+                res[b] = RGS_ENOCONV;
+                done[b] = 1;
+                continue;
+            }
+            active.push_back(b);
+        }
+        if (active.empty()) break;
+        for (int64_t b : active) lim[b] = (int)std::min<int64_t>(restart, d->max_iters - iters[b]);
+        // the cycle's sketch: sketch_id 2 (+ cycle unless reused), instance 0, per-system n
+        if (cycle == 0 || !d->reuse_theta) {
+            const uint32_t sid = d->reuse_theta ? 2u : (uint32_t)(2 + cycle);
+            if (sk_kind == SK_SRHT) rows_all.assign((size_t)(k * batch), 0);
+            for (int64_t b : active) {
+                bi[b].sk.sid = sid;
+                if (sk_kind == SK_SRHT) {
+                    if (!launch_srht_signs(s, const_cast<uint32_t*>(bi[b].sk.signs), (ns[b] + 31) / 32, bi[b].sk))
+                        return RGS_EDEVICE;
+                    std::vector<int> rows;
+                    srht_rows_host(srht_order(ns[b]), (int)k, bi[b].sk, rows);
+                    std::copy(rows.begin(), rows.end(), rows_all.begin() + b * k);
+                }
+            }
+            if (sk_kind == SK_SRHT && hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int),
+                                                     hipMemcpyHostToDevice, s) != hipSuccess)
+                return RGS_EDEVICE;
+            if (hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+                return RGS_EDEVICE;
+        }
+        if (active != prev_active) {
+            build_gmres_maps(gm, active, ns, k, restart);
+            if (hipMemcpyAsync(A + o_maps, gm.m.data(), gm.m.size() * sizeof(int2), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+                return RGS_EDEVICE;
+            drop_graph();
+            prev_active = active;
+        }
+        if (hipMemcpyAsync(A + o_limit, lim.data(), batch * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
+            return RGS_EDEVICE;
+        if (use_graph) {
+            if (!exec) {
+                if (!h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
+                    return RGS_EDEVICE;
+                if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return RGS_EDEVICE;
+                const bool ok = enqueue_cycle(h->capture);
+                const bool ended = hipStreamEndCapture(h->capture, &graph) == hipSuccess;
+                if (!ok || !ended || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                    drop_graph();
+                    return RGS_EDEVICE;
+                }
+            }
+            if (hipGraphLaunch(exec, s) != hipSuccess) {
+                drop_graph();
+                return RGS_EDEVICE;
+            }
+        } else if (!enqueue_cycle(s)) {
+            return RGS_EDEVICE;
+        }
+        if (hipMemcpyAsync(stat.data(), A + o_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(usedh.data(), A + o_used, batch * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(rn.data(), A + o_norm, batch * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hh.data(), A + o_hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) {
+            drop_graph();
+            return RGS_EDEVICE;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            drop_graph();
+            return RGS_EDEVICE;
+        }
+        for (int64_t b : active) {
+            const int u = usedh[b];
+            ++cycles[b];
+            iters[b] += u;
+            const rgs_gmres_item& it = items[b];
+            for (int t = 0; t < u && nhist[b] < it.hist_cap && it.res_hist; ++t)
+                it.res_hist[nhist[b]++] = hh[b * mcap + t];
+            relres[b] = rn[b] / bn[b];
+            if (stat[4 * b] == kStatusNonfinite || !std::isfinite(rn[b])) {
+                res[b] = RGS_ENONFINITE;
+                done[b] = 1;
+            } else if (relres[b] <= d->tol) {
+                done[b] = 1;
+            } else if (u == 0) {   // no inner step could run: breakdown of the very first column
+                res[b] = RGS_ENOCONV;
+                done[b] = 1;
+            }
+        }
+    }
+    drop_graph();
+    const auto t1 = std::chrono::steady_clock::now();
+    for (int64_t b = 0; b < batch; ++b) {
+        if (item_status) item_status[b] = res[b];
+        if (res[b] != RGS_OK && fail == RGS_OK) fail = res[b];
+        if (reps) {
+            rgs_report& r = reps[b];
+            r.failed_column = -1;
+            r.iters = iters[b];
+            r.cycles = cycles[b];
+            r.delta_F = NAN;
+            r.delta_tilde_F = NAN;
+            r.true_relres = relres[b];
+            r.seconds = std::chrono::duration<double>(t1 - t0).count();
+            r.proj_kernel_ms = 0.0;
+            r.proj_launches = iters[b];
+        }
+    }
+    return fail;
+}
 }  // namespace
 
 extern "C" {
@@ -754,10 +1140,11 @@ rgs_status rgs_create(rgs_handle** h, int device, rgs_stream stream) {
 
 rgs_status rgs_destroy(rgs_handle* h) {
     if (!h) return RGS_EINVAL;
-    hipSetDevice(h->device);
-    hipStreamSynchronize(h->stream);
-    for (hipEvent_t e : h->events) hipEventDestroy(e);
-    if (h->arena) hipFree(h->arena);
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    if (h->arena) (void)hipFree(h->arena);
     delete h;
     return RGS_OK;
 }
@@ -832,13 +1219,10 @@ rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j
 
 rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc* d, const double* b, double* x,
                      double* res_hist, int64_t hist_cap, rgs_report* rep) {
-    if (!h || !A || !d || !b || !x || hist_cap < 0) return RGS_EINVAL;
-    if (A->nx < 1 || A->ny < 1 || A->nz < 1) return RGS_EINVAL;
-    const int64_t n = A->nx * A->ny * A->nz;
-    if (n > ((int64_t)1 << 31) - 1) return RGS_EINVAL;
-    if (d->restart < 1 || d->restart + 1 > d->k || d->restart > 4000 || d->max_iters < 1 || !(d->tol >= 0))
+    if (!h || !A || !b || !x || hist_cap < 0 || (hist_cap > 0 && !res_hist) || !valid_gmres_desc(d))
         return RGS_EINVAL;
-    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64) return RGS_EINVAL;
+    int64_t n = 0;
+    if (!grid_size(*A, &n)) return RGS_EINVAL;
     rgs_qr_desc q{};
     q.n = n;
     q.m = d->restart + 1;
@@ -847,8 +1231,9 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     q.prec = d->prec;
     if (!valid_desc(&q, true)) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
-    if (d->prec == RGS_P_FP64) return run_gmres<double>(h, A, d, b, x, res_hist, hist_cap, rep);
-    return run_gmres<float>(h, A, d, b, x, res_hist, hist_cap, rep);
+    if (d->prec == RGS_P_FP64) return run_gmres<double, double, false>(h, A, d, b, x, res_hist, hist_cap, rep);
+    if (d->prec == RGS_P_BF16Q_FP32_LS64) return run_gmres<float, bf16, true>(h, A, d, b, x, res_hist, hist_cap, rep);
+    return run_gmres<float, float, false>(h, A, d, b, x, res_hist, hist_cap, rep);
 }
 
 rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec, const void* u, void* w) {
@@ -887,6 +1272,31 @@ rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (prec == RGS_P_BF16Q_FP32_LS64)
         return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
     return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
+}
+
+rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,
+                             int32_t* item_status, rgs_report* reps) {
+    if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
+    if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
+    if ((d->flags & ~RGS_FLAG_GRAPH) != 0) return RGS_EINVAL;
+    for (int64_t b = 0; b < batch; ++b) {
+        const rgs_gmres_item& it = items[b];
+        int64_t n = 0;
+        if (!it.b || !it.x || it.hist_cap < 0 || (it.hist_cap > 0 && !it.res_hist)) return RGS_EINVAL;
+        if (!grid_size(it.A, &n)) return RGS_EINVAL;
+        rgs_qr_desc q{};
+        q.n = n;
+        q.m = d->restart + 1;
+        q.k = d->k;
+        q.sketch = d->sketch;
+        q.prec = d->prec;
+        if (!valid_desc(&q, true)) return RGS_EINVAL;
+    }
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    if (d->prec == RGS_P_FP64) return run_gmres_batched<double, double, false>(h, batch, items, d, item_status, reps);
+    if (d->prec == RGS_P_BF16Q_FP32_LS64)
+        return run_gmres_batched<float, bf16, true>(h, batch, items, d, item_status, reps);
+    return run_gmres_batched<float, float, false>(h, batch, items, d, item_status, reps);
 }
 
 }  // extern "C"

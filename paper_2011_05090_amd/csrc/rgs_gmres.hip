@@ -9,13 +9,19 @@
 // (Sec. 4.2), with |g_{i+1}| the sketched residual ||Theta (b - A x_i)||.
 // x and the restart residual b - A x are kept in fp64.
 //
+// Every kernel is a thin wrapper around a device body.  The single-system
+// wrappers take explicit arguments; the batched ("kg_") wrappers map their
+// workgroup to (system, local block) through a host-built table and read the
+// system's pointers from its BatchItem (column-step state) and GmresItem
+// (operator, x, residual, Givens state).  Both call the same bodies, so a
+// batched solve reproduces separate solves bit for bit.
+//
 // Status word (shared with the QR kernels): [0] breakdown / non-finite,
-// [1] failed column, [2] "cycle done" (converged or lucky breakdown): once it
-// is set the remaining launches of the cycle return immediately.
+// [1] failed column, [2] "cycle done" (converged, lucky breakdown or the
+// cycle's step limit): once it is set the remaining launches of the cycle
+// return immediately.
 
-#include "rgs_block.hpp"
-#include "rgs_device.hpp"
-#include "rgs_internal.hpp"
+#include "rgs_step.hpp"
 
 namespace rgs {
 
@@ -35,6 +41,25 @@ struct Grid3 {
     int nx, ny, nz;
     double c0, cxm, cxp, cym, cyp, czm, czp;
 };
+
+__host__ __device__ inline Grid3 grid3(const StencilArgs& a) {
+    Grid3 g;
+    g.nx = (int)a.nx;
+    g.ny = (int)a.ny;
+    g.nz = (int)a.nz;
+    g.c0 = a.c[0];
+    g.cxm = a.c[1];
+    g.cxp = a.c[2];
+    g.cym = a.c[3];
+    g.cyp = a.c[4];
+    g.czm = a.c[5];
+    g.czp = a.c[6];
+    return g;
+}
+
+__device__ __forceinline__ double to_double(float v) { return (double)v; }
+__device__ __forceinline__ double to_double(double v) { return v; }
+__device__ __forceinline__ double to_double(bf16 v) { return (double)bf16_to_float(v.bits); }
 
 // (A u)_l for one row l, u read through `ld` (a functor giving u at an index).
 template <typename T, typename Load>
@@ -56,23 +81,24 @@ __device__ __forceinline__ T stencil_row(const Grid3& g, int64_t l, const Load& 
     return acc;
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// Device bodies
+// ---------------------------------------------------------------------------
 
-// Step 3 of Algorithm 3 (+ step 1 of Algorithm 2): w = A q with q = q' / r
-// normalised on the fly (fp64 reciprocal, rounded to T, exactly as the next
-// projection pass will store it), then the block's sketch partials of w.
-// Block layout identical to k_project (kProjWaves wave tiles of 1024 rows).
-template <typename T, typename PT, int SK>
-__global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
-    const T* __restrict__ qp, const double* __restrict__ invr, Grid3 g, int64_t n, T* __restrict__ w,
-    int do_sketch, SketchArgs sk, PT* __restrict__ partials, const int* __restrict__ status) {
+// Step 3 of Algorithm 3 (+ step 1 of Algorithm 2): w = A q with q = qs * invr
+// (qs the stored column, invr its fp64 reciprocal scale; the product rounded
+// to T exactly as a normalising projection pass stores it), then the block's
+// sketch partials of w.  Block layout identical to the projection kernel
+// (kProjWaves wave tiles of 1024 rows).
+template <typename TQ, typename T, typename PT, int SK>
+__device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, const double* __restrict__ invr,
+                                                    const Grid3& g, int64_t n, T* __restrict__ w, int do_sketch,
+                                                    const SketchArgs& sk, PT* __restrict__ partials, int64_t blk,
+                                                    T* __restrict__ lds) {
     constexpr int NW = kProjWaves;
-    __shared__ T lds[NW * kTile];
-    RGS_EXIT_IF_STOPPED(status);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t blk = blockIdx.x;
     const double ir = invr ? invr[0] : 1.0;
-    auto ld = [&](int64_t idx) -> T { return invr ? (T)((double)qp[idx] * ir) : qp[idx]; };
+    auto ld = [&](int64_t idx) -> T { return invr ? (T)(to_double(qs[idx]) * ir) : (T)to_double(qs[idx]); };
     T v[16];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -85,9 +111,6 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
         }
     }
     if (!do_sketch) return;
-    PT acc[kKptMax];
-#pragma unroll
-    for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
     if constexpr (SK == SK_IDENT) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -97,6 +120,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
                 if (r0 + r < n) partials[r0 + r] = (PT)v[4 * e + r];
         }
     } else {
+        PT acc[kKptMax];
+#pragma unroll
+        for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
         block_sketch<T, PT, SK, NW>(v, blk, n, sk, acc, lds);
         constexpr int NT = NW * kWave;
         const int kpt = (sk.k + NT - 1) / NT;
@@ -109,12 +135,13 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
     }
 }
 
-// r = b - A x in fp64, and per-block partial sums of ||r||^2 (one per workgroup of 256 rows).
-__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
-                                                  Grid3 g, int64_t n, double* __restrict__ r,
-                                                  double* __restrict__ part) {
+// r = b - A x in fp64 for the 256 rows of block blk (256 threads), and the
+// block's partial sum of ||r||^2.
+__device__ __forceinline__ void residual_body(const double* __restrict__ b, const double* __restrict__ x,
+                                              const Grid3& g, int64_t n, double* __restrict__ r,
+                                              double* __restrict__ part, int64_t blk) {
     __shared__ double red[256];
-    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t l = blk * 256 + threadIdx.x;
     double val = 0.0;
     if (l < n) {
         auto ld = [&](int64_t idx) -> double { return x[idx]; };
@@ -127,12 +154,12 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, 
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) part[blk] = red[0];
 }
 
-// out[0] = sqrt(sum of G partials), fixed order (one workgroup).
-__global__ __launch_bounds__(256) void k_norm_finish(const double* __restrict__ part, int64_t G,
-                                                     double* __restrict__ out) {
+// out[0] = sqrt(sum of G partials), fixed order (one workgroup of 256).
+__device__ __forceinline__ void norm_finish_body(const double* __restrict__ part, int64_t G,
+                                                 double* __restrict__ out) {
     __shared__ double red[256];
     double acc = 0.0;
     const int64_t per = (G + 255) / 256;
@@ -147,23 +174,17 @@ __global__ __launch_bounds__(256) void k_norm_finish(const double* __restrict__ 
     if (threadIdx.x == 0) out[0] = sqrt(red[0]);
 }
 
-template <typename T>
-__global__ void k_cast(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < n) dst[l] = (T)src[l];
-}
-
 // One Givens step for Hessenberg column c-1 (0-based basis column c >= 1):
 // h = R(0:c, c) (RGS R column, h_c = r_cc), apply the c-1 previous rotations,
 // form rotation c-1 that zeroes h_c, update g; record |g_c| / ||b|| in the
-// history and stop the cycle when it is <= tol or at a lucky breakdown
-// (status[0] = breakdown at column c: h_c = 0).  One thread: at most
-// `restart` rotations of 2-vectors.
-__global__ void k_givens(int c, const double* __restrict__ R, int mcap, double* __restrict__ Hr,
-                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ gv,
-                         double bnorm, double tol, double* __restrict__ hist, int* __restrict__ status,
-                         int* __restrict__ used) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// history and stop the cycle when it is <= tol, at a lucky breakdown
+// (status[0] = breakdown at column c: h_c = 0) or once c reaches `limit`.
+// Run by one thread: at most `restart` rotations of 2-vectors.
+__device__ __forceinline__ void givens_body(int c, const double* __restrict__ R, int mcap,
+                                            double* __restrict__ Hr, double* __restrict__ cs,
+                                            double* __restrict__ sn, double* __restrict__ gv, double bnorm,
+                                            double tol, double* __restrict__ hist, int* __restrict__ status,
+                                            int* __restrict__ used, int limit) {
     if (status[2] != 0) return;
     bool lucky = false;
     if (status[0] != 0) {
@@ -198,7 +219,74 @@ __global__ void k_givens(int c, const double* __restrict__ R, int mcap, double* 
     hist[c - 1] = est;
     used[0] = c;
     if (lucky) status[0] = 0;       // a lucky breakdown is not an error in GMRES
-    if (lucky || est <= tol) status[2] = 1;
+    if (lucky || est <= tol || c >= limit) status[2] = 1;
+}
+
+// y = Hr(0:u, 0:u)^{-1} g(0:u), u = used[0]: back substitution (one thread).
+// With an unnormalised stored basis (invr given) y_c is then scaled by 1/r_cc
+// so that x += sum_c qs_c y_c.
+__device__ __forceinline__ void backsub_body(const double* __restrict__ Hr, int mcap, const double* __restrict__ gv,
+                                             const int* __restrict__ used, double* __restrict__ y,
+                                             const double* __restrict__ invr) {
+    const int u = used[0];
+    for (int r = u - 1; r >= 0; --r) {
+        double acc = gv[r];
+        for (int c = r + 1; c < u; ++c) acc -= Hr[r + (int64_t)c * mcap] * y[c];
+        y[r] = acc / Hr[r + (int64_t)r * mcap];
+    }
+    if (invr)
+        for (int r = 0; r < u; ++r) y[r] = y[r] * invr[r];
+}
+
+// x_l += sum_{c < u} Q(l, c) y_c in fp64, columns in ascending order.
+template <typename TQ>
+__device__ __forceinline__ void xupdate_body(double* __restrict__ x, const TQ* __restrict__ Q, int64_t ldq,
+                                             int64_t n, const int* __restrict__ used, const double* __restrict__ y,
+                                             int64_t l) {
+    if (l >= n) return;
+    const int u = used[0];
+    double acc = x[l];
+    for (int c = 0; c < u; ++c) acc += to_double(Q[l + (int64_t)c * ldq]) * y[c];
+    x[l] = acc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single-system kernels
+// ---------------------------------------------------------------------------
+template <typename TQ, typename T, typename PT, int SK>
+__global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
+    const TQ* __restrict__ qs, const double* __restrict__ invr, Grid3 g, int64_t n, T* __restrict__ w,
+    int do_sketch, SketchArgs sk, PT* __restrict__ partials, const int* __restrict__ status) {
+    __shared__ T lds[kProjWaves * kTile];
+    RGS_EXIT_IF_STOPPED(status);
+    stencil_sketch_body<TQ, T, PT, SK>(qs, invr, g, n, w, do_sketch, sk, partials, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
+                                                  Grid3 g, int64_t n, double* __restrict__ r,
+                                                  double* __restrict__ part) {
+    residual_body(b, x, g, n, r, part, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_norm_finish(const double* __restrict__ part, int64_t G,
+                                                     double* __restrict__ out) {
+    norm_finish_body(part, G, out);
+}
+
+template <typename T>
+__global__ void k_cast(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n) dst[l] = (T)src[l];
+}
+
+__global__ void k_givens(int c, const double* __restrict__ R, int mcap, double* __restrict__ Hr,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ gv,
+                         double bnorm, double tol, double* __restrict__ hist, int* __restrict__ status,
+                         int* __restrict__ used, int limit) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    givens_body(c, R, mcap, Hr, cs, sn, gv, bnorm, tol, hist, status, used, limit);
 }
 
 // g(0) = r_11 = R(0, 0) at the start of a cycle.
@@ -209,29 +297,156 @@ __global__ void k_givens_init(const double* __restrict__ R, double* __restrict__
     }
 }
 
-// y = Hr(0:u, 0:u)^{-1} g(0:u), u = used[0]: back substitution (one thread).
 __global__ void k_backsub(const double* __restrict__ Hr, int mcap, const double* __restrict__ gv,
-                          const int* __restrict__ used, double* __restrict__ y) {
+                          const int* __restrict__ used, double* __restrict__ y, const double* __restrict__ invr) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int u = used[0];
-    for (int r = u - 1; r >= 0; --r) {
-        double acc = gv[r];
-        for (int c = r + 1; c < u; ++c) acc -= Hr[r + (int64_t)c * mcap] * y[c];
-        y[r] = acc / Hr[r + (int64_t)r * mcap];
-    }
+    backsub_body(Hr, mcap, gv, used, y, invr);
 }
 
-// x += Q(:, 0:u) y in fp64 (u = used[0]; columns in ascending order).
-template <typename T>
-__global__ __launch_bounds__(256) void k_xupdate(double* __restrict__ x, const T* __restrict__ Q, int64_t ldq,
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_xupdate(double* __restrict__ x, const TQ* __restrict__ Q, int64_t ldq,
                                                  int64_t n, const int* __restrict__ used,
                                                  const double* __restrict__ y) {
-    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (l >= n) return;
-    const int u = used[0];
-    double acc = x[l];
-    for (int c = 0; c < u; ++c) acc += (double)Q[l + (int64_t)c * ldq] * y[c];
-    x[l] = acc;
+    xupdate_body<TQ>(x, Q, ldq, n, used, y, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernels: workgroup -> (system, local block) through map.
+// ---------------------------------------------------------------------------
+
+// Start of a cycle: clear the status word (a kernel, not a memset, so that the
+// cycle can be captured in a graph).
+__global__ void kg_reset(const BatchItem* __restrict__ items, const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    if (threadIdx.x < 3) items[bm.x].sa.status[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void kg_zero_x(const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    const GmresItem& g = gi[bm.x];
+    const int64_t l = (int64_t)bm.y * 256 + threadIdx.x;
+    if (l < g.n) g.x[l] = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kg_cast(const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    const GmresItem& g = gi[bm.x];
+    const int64_t l = (int64_t)bm.y * 256 + threadIdx.x;
+    if (l < g.n) static_cast<T*>(g.w)[l] = (T)g.r[l];
+}
+
+template <typename TQ, typename T, int SK>
+__global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem* __restrict__ items,
+                                                                 const GmresItem* __restrict__ gi,
+                                                                 const int2* __restrict__ map, int i) {
+    __shared__ T lds[kProjWaves * kTile];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_STOPPED(it.sa.status);
+    const GmresItem& g = gi[bm.x];
+    stencil_sketch_body<TQ, T, T, SK>(static_cast<const TQ*>(it.Q) + (int64_t)(i - 1) * it.ldq,
+                                      it.sa.invr + (i - 1), grid3(g.A), it.n, static_cast<T*>(g.w), 1, it.sk,
+                                      static_cast<T*>(it.part), bm.y, lds);
+}
+
+template <typename T, typename TQ, int SK, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem* __restrict__ items,
+                                                                 const GmresItem* __restrict__ gi,
+                                                                 const int2* __restrict__ map, int i) {
+    __shared__ T lds[kProjWaves * kTile];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_STOPPED(it.sa.status);
+    const GmresItem& g = gi[bm.x];
+    project_body<T, TQ, T, SK, DEFER>(static_cast<const T*>(g.w), static_cast<TQ*>(it.Q), it.ldq, it.n, i,
+                                      static_cast<const T*>(it.coef), i > 0 ? it.sa.invr + (i - 1) : nullptr,
+                                      (!DEFER && i > 0) ? 1 : 0, 1, it.vec_ok, it.sk, static_cast<T*>(it.part),
+                                      bm.y, lds);
+}
+
+// Step 2 for the Arnoldi right-hand side p_i (block partials of the mat-vec
+// kernel): reduce to pbuf with the per-slice partials of Wm^T p, then the head
+// of U^T p, then y = R_S^{-1} uh -> R(0:i, i) and the projection coefficients.
+template <typename PT>
+__global__ __launch_bounds__(kGW) void kg_lsa(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                              int i) {
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    qa_body<PT>(static_cast<const PT*>(it.part), it.nproj, it.sketch_scale, nullptr, a.k, i, a.Wr, a.mcap, a.pbuf,
+                a.pd, bm.y);
+}
+
+__global__ __launch_bounds__(kGW) void kg_ls2(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                              int i) {
+    extern __shared__ double cp[];  // [i + 1]
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    ls2_body(a.pbuf, a.k, i, it.nsl, a.Vc, a.mcap, a.pd, a.uh, a.pnorm, bm.y, cp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGW) void kg_ls3(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+                                              int i) {
+    extern __shared__ double us[];  // [i]
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    ls3_body<T>(i, i, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<T*>(it.coef), it.defer ? a.invr : nullptr, bm.y,
+                us);
+}
+
+__global__ void kg_givens_init(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
+                               const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const GmresItem& g = gi[bm.x];
+    g.gv[0] = items[bm.x].R[0];
+    g.used[0] = 0;
+}
+
+__global__ void kg_givens(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
+                          const int2* __restrict__ map, int c) {
+    const int2 bm = map[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const BatchItem& it = items[bm.x];
+    const GmresItem& g = gi[bm.x];
+    givens_body(c, it.R, it.sa.mcap, g.Hr, g.cs, g.sn, g.gv, g.bnorm, g.tol, g.hist, it.sa.status, g.used,
+                g.limit[0]);
+}
+
+__global__ void kg_backsub(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
+                           const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const BatchItem& it = items[bm.x];
+    const GmresItem& g = gi[bm.x];
+    backsub_body(g.Hr, it.sa.mcap, g.gv, g.used, g.y, it.defer ? it.sa.invr : nullptr);
+}
+
+template <typename TQ>
+__global__ __launch_bounds__(256) void kg_xupdate(const BatchItem* __restrict__ items,
+                                                  const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    const GmresItem& g = gi[bm.x];
+    xupdate_body<TQ>(g.x, static_cast<const TQ*>(it.Q), it.ldq, g.n, g.used, g.y,
+                     (int64_t)bm.y * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void kg_residual(const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    const GmresItem& g = gi[bm.x];
+    residual_body(g.b, g.x, grid3(g.A), g.n, g.r, g.rpart, bm.y);
+}
+
+__global__ __launch_bounds__(256) void kg_norm_finish(const GmresItem* __restrict__ gi,
+                                                      const int2* __restrict__ map) {
+    const int2 bm = map[blockIdx.x];
+    const GmresItem& g = gi[bm.x];
+    norm_finish_body(g.rpart, (g.n + 255) / 256, g.norm);
 }
 
 // ---------------------------------------------------------------------------
@@ -244,35 +459,20 @@ __global__ __launch_bounds__(256) void k_xupdate(double* __restrict__ x, const T
 
 static inline unsigned nblk_of(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
 
-static Grid3 grid3(const StencilArgs& a) {
-    Grid3 g;
-    g.nx = (int)a.nx;
-    g.ny = (int)a.ny;
-    g.nz = (int)a.nz;
-    g.c0 = a.c[0];
-    g.cxm = a.c[1];
-    g.cxp = a.c[2];
-    g.cym = a.c[3];
-    g.cyp = a.c[4];
-    g.czm = a.c[5];
-    g.czp = a.c[6];
-    return g;
-}
-
-template <typename T, typename PT>
-bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const T* qp, const double* invr, T* w,
-                           int do_sketch, const SketchArgs& sk, PT* partials, const int* status) {
+template <typename TQ, typename T>
+bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, const double* invr, T* w,
+                           int do_sketch, const SketchArgs& sk, T* partials, const int* status) {
     const int64_t n = A.nx * A.ny * A.nz;
     const Grid3 g = grid3(A);
     const dim3 grid(nblk_of(n, kProjRows)), thr(kProjWaves * kWave);
     if (sk.sketch == SK_SRHT)
-        hipLaunchKernelGGL((k_stencil_sketch<T, PT, SK_SRHT>), grid, thr, 0, st, qp, invr, g, n, w, do_sketch, sk,
-                           partials, status);
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_SRHT>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
+                           sk, partials, status);
     else if (sk.sketch == SK_GAUSS)
-        hipLaunchKernelGGL((k_stencil_sketch<T, PT, SK_GAUSS>), grid, thr, 0, st, qp, invr, g, n, w, do_sketch,
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_GAUSS>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
     else
-        hipLaunchKernelGGL((k_stencil_sketch<T, PT, SK_IDENT>), grid, thr, 0, st, qp, invr, g, n, w, do_sketch,
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_IDENT>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
     RGS_LAUNCH_CHECK();
     return true;
@@ -303,19 +503,121 @@ bool launch_givens_init(hipStream_t st, const double* R, double* gv, int* used) 
 }
 
 bool launch_givens(hipStream_t st, int c, const double* R, int mcap, double* Hr, double* cs, double* sn,
-                   double* gv, double bnorm, double tol, double* hist, int* status, int* used) {
+                   double* gv, double bnorm, double tol, double* hist, int* status, int* used, int limit) {
     hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, c, R, mcap, Hr, cs, sn, gv, bnorm, tol, hist, status,
-                       used);
+                       used, limit);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TQ>
+bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* gv, const int* used, double* y,
+                     double* x, const TQ* Q, int64_t ldq, int64_t n, const double* invr) {
+    hipLaunchKernelGGL(k_backsub, dim3(1), dim3(64), 0, st, Hr, mcap, gv, used, y, invr);
+    RGS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_xupdate<TQ>, dim3(nblk_of(n, 256)), dim3(256), 0, st, x, Q, ldq, n, used, y);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+// ---- batched ----
+bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const int2* map_sys, int nsys) {
+    if (nsys == 0) return true;
+    hipLaunchKernelGGL(kg_reset, dim3(nsys), dim3(64), 0, st, items, map_sys);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow) {
+    if (nrow == 0) return true;
+    hipLaunchKernelGGL(kg_zero_x, dim3(nrow), dim3(256), 0, st, gi, map_row);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
 template <typename T>
-bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* gv, const int* used, double* y,
-                     double* x, const T* Q, int64_t ldq, int64_t n) {
-    hipLaunchKernelGGL(k_backsub, dim3(1), dim3(64), 0, st, Hr, mcap, gv, used, y);
+bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow) {
+    if (nrow == 0) return true;
+    hipLaunchKernelGGL(kg_cast<T>, dim3(nrow), dim3(256), 0, st, gi, map_row);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_xupdate<T>, dim3(nblk_of(n, 256)), dim3(256), 0, st, x, Q, ldq, n, used, y);
+    return true;
+}
+
+template <typename T, typename TQ>
+bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
+                           const int2* map_proj, int nproj, int i) {
+    if (nproj == 0) return true;
+    const dim3 thr(kProjWaves * kWave);
+    if (sketch == SK_SRHT)
+        hipLaunchKernelGGL((kg_stencil<TQ, T, SK_SRHT>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
+    else
+        hipLaunchKernelGGL((kg_stencil<TQ, T, SK_GAUSS>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename T, typename TQ, bool DEFER>
+bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
+                           const int2* map_proj, int nproj, int i) {
+    if (nproj == 0) return true;
+    const dim3 thr(kProjWaves * kWave);
+    if (sketch == SK_SRHT)
+        hipLaunchKernelGGL((kg_project<T, TQ, SK_SRHT, DEFER>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
+    else
+        hipLaunchKernelGGL((kg_project<T, TQ, SK_GAUSS, DEFER>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename T>
+bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const int2* map_sl, int nsl, const int2* map_rb,
+                      int nrb, int i) {
+    if (nsl > 0) {
+        hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i);
+        RGS_LAUNCH_CHECK();
+    }
+    if (nrb > 0) {
+        hipLaunchKernelGGL(kg_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, items, map_rb, i);
+        RGS_LAUNCH_CHECK();
+        hipLaunchKernelGGL(kg_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, items, map_rb, i);
+        RGS_LAUNCH_CHECK();
+    }
+    return true;
+}
+
+bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
+                               int nsys) {
+    if (nsys == 0) return true;
+    hipLaunchKernelGGL(kg_givens_init, dim3(nsys), dim3(64), 0, st, items, gi, map_sys);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
+                          int nsys, int c) {
+    if (nsys == 0) return true;
+    hipLaunchKernelGGL(kg_givens, dim3(nsys), dim3(64), 0, st, items, gi, map_sys, c);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TQ>
+bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
+                          int nsys, const int2* map_row, int nrow) {
+    if (nsys == 0) return true;
+    hipLaunchKernelGGL(kg_backsub, dim3(nsys), dim3(64), 0, st, items, gi, map_sys);
+    RGS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kg_xupdate<TQ>, dim3(nrow), dim3(256), 0, st, items, gi, map_row);
+    RGS_LAUNCH_CHECK();
+    return launch_gbatch_residual(st, gi, map_sys, nsys, map_row, nrow);
+}
+
+bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const int2* map_sys, int nsys,
+                            const int2* map_row, int nrow) {
+    if (nsys == 0) return true;
+    hipLaunchKernelGGL(kg_residual, dim3(nrow), dim3(256), 0, st, gi, map_row);
+    RGS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kg_norm_finish, dim3(nsys), dim3(256), 0, st, gi, map_sys);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -324,11 +626,37 @@ template bool launch_stencil_sketch<float, float>(hipStream_t, const StencilArgs
                                                   float*, int, const SketchArgs&, float*, const int*);
 template bool launch_stencil_sketch<double, double>(hipStream_t, const StencilArgs&, const double*, const double*,
                                                     double*, int, const SketchArgs&, double*, const int*);
+template bool launch_stencil_sketch<bf16, float>(hipStream_t, const StencilArgs&, const bf16*, const double*,
+                                                 float*, int, const SketchArgs&, float*, const int*);
 template bool launch_cast<float>(hipStream_t, const double*, float*, int64_t);
 template bool launch_cast<double>(hipStream_t, const double*, double*, int64_t);
 template bool launch_update_x<float>(hipStream_t, const double*, int, const double*, const int*, double*, double*,
-                                     const float*, int64_t, int64_t);
+                                     const float*, int64_t, int64_t, const double*);
 template bool launch_update_x<double>(hipStream_t, const double*, int, const double*, const int*, double*,
-                                      double*, const double*, int64_t, int64_t);
+                                      double*, const double*, int64_t, int64_t, const double*);
+template bool launch_update_x<bf16>(hipStream_t, const double*, int, const double*, const int*, double*, double*,
+                                    const bf16*, int64_t, int64_t, const double*);
+template bool launch_gbatch_cast<float>(hipStream_t, const GmresItem*, const int2*, int);
+template bool launch_gbatch_cast<double>(hipStream_t, const GmresItem*, const int2*, int);
+template bool launch_gbatch_stencil<float, float>(hipStream_t, int, const BatchItem*, const GmresItem*, const int2*,
+                                                  int, int);
+template bool launch_gbatch_stencil<double, double>(hipStream_t, int, const BatchItem*, const GmresItem*,
+                                                    const int2*, int, int);
+template bool launch_gbatch_stencil<float, bf16>(hipStream_t, int, const BatchItem*, const GmresItem*, const int2*,
+                                                 int, int);
+template bool launch_gbatch_project<float, float, false>(hipStream_t, int, const BatchItem*, const GmresItem*,
+                                                         const int2*, int, int);
+template bool launch_gbatch_project<double, double, false>(hipStream_t, int, const BatchItem*, const GmresItem*,
+                                                           const int2*, int, int);
+template bool launch_gbatch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const GmresItem*,
+                                                       const int2*, int, int);
+template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int);
+template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int);
+template bool launch_gbatch_finish<float>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
+                                          const int2*, int);
+template bool launch_gbatch_finish<double>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
+                                           const int2*, int);
+template bool launch_gbatch_finish<bf16>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
+                                         const int2*, int);
 
 }  // namespace rgs

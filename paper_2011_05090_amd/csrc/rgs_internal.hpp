@@ -68,6 +68,23 @@ struct BatchItem {
     SketchArgs sk;
 };
 
+// One system of a batched GMRES call, beside its BatchItem (the column-step
+// view: basis, sketch-space state, R, S).
+struct GmresItem {
+    int64_t n;
+    StencilArgs A;
+    const double* b;
+    double* x;
+    double* r;            // n: restart residual b - A x (fp64)
+    void* w;              // n: the current Arnoldi vector (working precision)
+    double* rpart;        // per 256-row block partial sums of ||r||^2
+    double* norm;         // [0] = ||r||
+    double bnorm, tol;
+    double *Hr, *cs, *sn, *gv, *y, *hist;   // Givens state (mcap each; gv mcap + 1)
+    int* used;            // inner steps done in the current cycle
+    const int* limit;     // inner steps allowed in the current cycle
+};
+
 bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const SketchArgs& sk);
 template <typename T, typename PT>
 bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int ncols, int G,
@@ -104,23 +121,50 @@ bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_
 bool launch_diagnostics(hipStream_t st, const double* P, int64_t ldp, const double* S, int64_t lds,
                         const double* R, int64_t ldr, int k, int m, double* gram_out, double* resid_out);
 
-template <typename T, typename PT>
-bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const T* qp, const double* invr, T* w,
-                           int do_sketch, const SketchArgs& sk, PT* partials, const int* status);
+template <typename TQ, typename T>
+bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, const double* invr, T* w,
+                           int do_sketch, const SketchArgs& sk, T* partials, const int* status);
 bool launch_residual(hipStream_t st, const StencilArgs& A, const double* b, const double* x, double* r,
                      double* part, double* norm_out);
 template <typename T>
 bool launch_cast(hipStream_t st, const double* src, T* dst, int64_t n);
 bool launch_givens_init(hipStream_t st, const double* R, double* gv, int* used);
 bool launch_givens(hipStream_t st, int c, const double* R, int mcap, double* Hr, double* cs, double* sn,
-                   double* gv, double bnorm, double tol, double* hist, int* status, int* used);
-template <typename T>
+                   double* gv, double bnorm, double tol, double* hist, int* status, int* used, int limit);
+template <typename TQ>
 bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* gv, const int* used, double* y,
-                     double* x, const T* Q, int64_t ldq, int64_t n);
+                     double* x, const TQ* Q, int64_t ldq, int64_t n, const double* invr);
 // Step 2 when the right-hand side arrives as block partials (Arnoldi): reduce to
 // a.pbuf, then the least-squares solve of column i (R(0:i, i) and coef).
 template <typename T, typename PT>
 bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
                         double* R, int64_t ldr, T* coef, const double* cscale);
+
+// Batched GMRES: every launch covers the systems listed in its map
+// (map_sys: one entry per system, map_row: 256-row blocks, map_proj: blocks
+// of kProjRows rows, map_sl: 64-row sketch slices, map_rb: 64-row blocks of
+// the i x i least-squares solve).
+bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const int2* map_sys, int nsys);
+bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow);
+template <typename T>
+bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow);
+template <typename T, typename TQ>
+bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
+                           const int2* map_proj, int nproj, int i);
+template <typename T, typename TQ, bool DEFER>
+bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
+                           const int2* map_proj, int nproj, int i);
+template <typename T>
+bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const int2* map_sl, int nsl, const int2* map_rb,
+                      int nrb, int i);
+bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
+                               int nsys);
+bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
+                          int nsys, int c);
+template <typename TQ>
+bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
+                          int nsys, const int2* map_row, int nrow);
+bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const int2* map_sys, int nsys,
+                            const int2* map_row, int nrow);
 
 }  // namespace rgs

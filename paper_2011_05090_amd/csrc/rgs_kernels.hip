@@ -21,21 +21,9 @@
 
 #include <algorithm>
 
-#include "rgs_block.hpp"
-#include "rgs_device.hpp"
-#include "rgs_internal.hpp"
+#include "rgs_step.hpp"
 
 namespace rgs {
-
-// Workgroup-uniform early exit once an earlier step has flagged a breakdown:
-// one thread reads the status word, the whole workgroup takes the same branch.
-#define RGS_EXIT_IF_FAILED(status)                      \
-    do {                                                \
-        __shared__ int rgs_stop_;                       \
-        if (threadIdx.x == 0) rgs_stop_ = (status)[0] | (status)[2]; \
-        __syncthreads();                                \
-        if (rgs_stop_ != 0) return;                     \
-    } while (0)
 
 // SRHT diagonal D as a bit table: bit b of word w is set iff d_{32w+b} = -1.
 // Word w comes from word (w mod 4) of Philox(w/4, 0xFFFFFFFF, sketch_id, instance).
@@ -102,70 +90,6 @@ __global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials,
 #pragma unroll
         for (int t = 0; t < 8; ++t) tot += red[t][jl];
         out[j + (int64_t)col * ldo] = tot * scale;
-    }
-}
-
-// Step 3 (+ step 4 partials, + step 7 of the previous column), for row block
-// blk of kProjWaves * 1024 rows:
-//   q'_i = w_i - sum_{c<j} coef[c] q_c        (working precision TW, fma chain in c order)
-// If normalize_last, column j-1 still holds q'_{i-1} and is first scaled to
-// q_{i-1} = q'_{i-1} / r_{i-1,i-1} (fp64 multiply by the reciprocal, rounded
-// to the storage type) and written back.  q'_i is stored in column j, then the
-// block's sketch partials of the stored q'_i are written (or q'_i itself for
-// Theta = I).  DEFER (bf16 storage): columns stay unnormalised, the
-// coefficients already carry 1/r_cc, and the sketch is taken of the rounded,
-// stored q'_i.
-template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
-__device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n,
-                                             int j, const TW* __restrict__ coef, const double* __restrict__ invr,
-                                             int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
-                                             PT* __restrict__ partials, int64_t blk, TW* __restrict__ lds) {
-    constexpr int NW = kProjWaves;
-    int64_t row0[4];
-    lane_rows<NW>(blk, row0);
-    const bool full = vec_ok && (blk + 1) * (NW * kTile) <= n;
-    TW v[16];
-    load16(w, row0, n, full, v);
-    const int jl = (!DEFER && normalize_last) ? j - 1 : j;
-    for (int c = 0; c < jl; ++c) {
-        const TW a = coef[c];
-        TW q[16];
-        load16(Q + (int64_t)c * ldq, row0, n, full, q);
-#pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
-    }
-    if constexpr (!DEFER) {
-        if (normalize_last) {
-            const int c = j - 1;
-            const TW a = coef[c];
-            const double ir = invr[0];
-            TW q[16];
-            TQ* qc = Q + (int64_t)c * ldq;
-            load16(qc, row0, n, full, q);
-#pragma unroll
-            for (int t = 0; t < 16; ++t) q[t] = (TW)((double)q[t] * ir);
-            store16(qc, row0, n, full, q);
-#pragma unroll
-            for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
-        }
-    }
-    store16(Q + (int64_t)j * ldq, row0, n, full, v);   // bf16: v becomes the stored value
-    if (!do_sketch) return;
-    if constexpr (SK == SK_IDENT) {
-        store16(partials, row0, n, false, v);   // Theta = I: the "sketch" is q' itself
-    } else {
-        PT acc[kKptMax];
-#pragma unroll
-        for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
-        block_sketch<TW, PT, SK, NW>(v, blk, n, sk, acc, lds);
-        PT* out = partials + blk * sk.k;
-        constexpr int NT = NW * kWave;
-        const int kpt = (sk.k + NT - 1) / NT;
-#pragma unroll
-        for (int u = 0; u < kKptMax; ++u) {
-            const int jj = threadIdx.x + NT * u;
-            if (u < kpt && jj < sk.k) out[jj] = acc[u];
-        }
     }
 }
 
@@ -246,94 +170,6 @@ __global__ void kb_init(const BatchItem* __restrict__ items, int nitems) {
     if (idx < 4) it.sa.status[idx] = 0;
 }
 
-// ---------------------------------------------------------------------------
-// Sketch-space kernels (fp64).  i = 0-based index of the current column;
-// i columns are already factorised.  A "slice" is 64 consecutive sketch rows
-// (one workgroup); pd buffers hold per-slice partial dot products.  These
-// kernels are latency-bound, so every loop over global memory issues its
-// loads in batches (independent loads first, then the fixed-order sums) to
-// keep the number of dependent round trips per kernel at two or three.
-// Column-parallel dot products run one thread per column over a slice;
-// row-parallel products run 64 rows x 16 column groups (1024 threads).
-// ---------------------------------------------------------------------------
-constexpr int kGW = 1024;   // threads of the sketch-space kernels
-constexpr int kGQ = 16;     // column groups of the row-parallel products
-constexpr int kBatch = 16;  // loads issued back to back per thread
-
-// sum_{s < nsl} pd[s * stride + c] (fixed order in s)
-__device__ __forceinline__ double sum_col(const double* __restrict__ pd, int nsl, int stride, int c) {
-    double acc = 0.0;
-    for (int s0 = 0; s0 < nsl; s0 += kBatch) {
-        double t[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) t[u] = (s0 + u < nsl) ? pd[(int64_t)(s0 + u) * stride + c] : 0.0;
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) acc += t[u];
-    }
-    return acc;
-}
-
-__device__ __forceinline__ void sum_slices(const double* __restrict__ pd, int nsl, int stride, int cnt,
-                                           double* __restrict__ out) {
-    for (int c = threadIdx.x; c < cnt; c += blockDim.x) out[c] = sum_col(pd, nsl, stride, c);
-}
-
-// sum_{rr < 64} M[row(rr), c] * xs[rr], M row-major with row stride mcap; rows
-// past k are clamped (xs is 0 there).
-__device__ __forceinline__ double slice_dot(const double* __restrict__ Mr, int mcap, int r0, int k,
-                                            const double* __restrict__ xs, int c) {
-    double acc = 0.0;
-#pragma unroll 1
-    for (int b = 0; b < kSlice; b += kBatch) {
-        double t[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) t[u] = Mr[(int64_t)min(r0 + b + u, k - 1) * mcap + c];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) acc = fma(t[u], xs[b + u], acc);
-    }
-    return acc;
-}
-
-__device__ __forceinline__ double slice_sq(const double* __restrict__ xs) {
-    double acc = 0.0;
-    for (int rr = 0; rr < kSlice; ++rr) acc = fma(xs[rr], xs[rr], acc);
-    return acc;
-}
-
-__device__ __forceinline__ double slice_xy(const double* __restrict__ xs, const double* __restrict__ ys) {
-    double acc = 0.0;
-    for (int rr = 0; rr < kSlice; ++rr) acc = fma(xs[rr], ys[rr], acc);
-    return acc;
-}
-
-// Row-parallel partial: sum over c in [c0, c1) with c = q (mod kGQ), ascending,
-// of M[r, c] * xl[c]; M column-major with leading dimension ld.
-__device__ __forceinline__ double row_part(const double* __restrict__ Mc, int64_t ld, int r, int c0, int c1,
-                                           const double* __restrict__ xl, int q) {
-    double acc = 0.0;
-    for (int c = c0 + ((q - c0) % kGQ + kGQ) % kGQ; c < c1; c += kGQ * kBatch) {
-        double t[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int cc = c + kGQ * u;
-            t[u] = (cc < c1) ? Mc[r + (int64_t)cc * ld] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int cc = c + kGQ * u;
-            if (cc < c1) acc = fma(t[u], xl[cc], acc);
-        }
-    }
-    return acc;
-}
-
-__device__ __forceinline__ double combine16(double (*red)[64], int rl) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < kGQ; ++q) t += red[q][rl];
-    return t;
-}
-
 // Step 2 for a right-hand side p known only now (Arnoldi): part 1, per-slice
 // partials of c = Wm_i^T p (c < i) and of ||p||^2 (slot i).
 __global__ __launch_bounds__(kGW) void k_ls1(const double* __restrict__ p, int k, int i,
@@ -346,45 +182,12 @@ __global__ __launch_bounds__(kGW) void k_ls1(const double* __restrict__ p, int k
     for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
-// Step 2, part 2: c = sum of slice partials; head of U_i^T p:
-//   uh[r] = p[r] - sum_{c <= r} V[r, c] c[c],  r < i.
 __global__ __launch_bounds__(kGW) void k_ls2(const double* __restrict__ p, int k, int i, int nsl,
                                              const double* __restrict__ Vc, int mcap,
                                              const double* __restrict__ pd, double* __restrict__ uh,
                                              double* __restrict__ pnorm) {
     extern __shared__ double cp[];  // [i + 1]
-    __shared__ double red[kGQ][64];
-    sum_slices(pd, nsl, mcap + 1, i + 1, cp);
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) pnorm[i] = sqrt(cp[i]);
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int r = blockIdx.x * 64 + rl;
-    red[q][rl] = (r < i) ? row_part(Vc, k, r, 0, min(r, i - 1) + 1, cp, q) : 0.0;
-    __syncthreads();
-    if (q == 0 && r < i) uh[r] = p[r] - combine16(red, rl);
-}
-
-// Step 2, last part: y = R_S^{-1} uh with X = R_S^{-1} (upper triangular, nr x nr):
-//   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:nr, col) and the working-
-// precision coefficients coef[r] = y[r] (times cscale[r] = 1/r_rr when the
-// basis is kept unnormalised).  bid = row block of 64.
-template <typename T>
-__device__ __forceinline__ void ls3_body(int nr, int col, const double* __restrict__ X, int mcap,
-                                         const double* __restrict__ uh, double* __restrict__ R, int64_t ldr,
-                                         T* __restrict__ coef, const double* __restrict__ cscale, int bid,
-                                         double* __restrict__ us) {
-    __shared__ double red[kGQ][64];
-    for (int c = threadIdx.x; c < nr; c += kGW) us[c] = uh[c];
-    __syncthreads();
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int r = bid * 64 + rl;
-    red[q][rl] = (r < nr) ? row_part(X, mcap, r, r, nr, us, q) : 0.0;
-    __syncthreads();
-    if (q == 0 && r < nr) {
-        const double y = combine16(red, rl);
-        R[r + (int64_t)col * ldr] = y;
-        coef[r] = (T)(cscale ? y * cscale[r] : y);
-    }
+    ls2_body(p, k, i, nsl, Vc, mcap, pd, uh, pnorm, blockIdx.x, cp);
 }
 
 template <typename T>
@@ -395,107 +198,12 @@ __global__ __launch_bounds__(kGW) void k_ls3(int nr, int col, const double* __re
     ls3_body<T>(nr, col, X, mcap, uh, R, ldr, coef, cscale, blockIdx.x, us);
 }
 
-// Column step A: s' = scale * (sum of the projection kernel's block partials)
-// for slice bid (or a copy of src), stored in sp; per-slice partials of
-// c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
-template <typename PT>
-__device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, double scale,
-                                        const double* __restrict__ src, int k, int i,
-                                        const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                        double* __restrict__ pd, int bid) {
-    __shared__ double red[kGQ][64];
-    __shared__ double xs[kSlice];
-    const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int r = r0 + rl;
-    if (src) {
-        if (q == 0) {
-            const double val = (r < k) ? src[r] : 0.0;
-            xs[rl] = val;
-            if (r < k) sp[r] = val;
-        }
-    } else {
-        // group q sums the block partials g in [G q / 16, G (q+1) / 16), in order
-        const int g0 = (int)((int64_t)G * q / kGQ), g1 = (int)((int64_t)G * (q + 1) / kGQ);
-        double acc = 0.0;
-        if (r < k) {
-            for (int g = g0; g < g1; g += 32) {
-                PT t[32];
-#pragma unroll
-                for (int u = 0; u < 32; ++u) t[u] = (g + u < g1) ? partials[(int64_t)(g + u) * k + r] : PT(0);
-#pragma unroll
-                for (int u = 0; u < 32; ++u) acc += (double)t[u];
-            }
-        }
-        red[q][rl] = acc;
-        __syncthreads();
-        if (q == 0) {
-            const double val = (r < k) ? combine16(red, rl) * scale : 0.0;
-            xs[rl] = val;
-            if (r < k) sp[r] = val;
-        }
-    }
-    __syncthreads();
-    double* out = pd + (int64_t)s * (mcap + 1);
-    for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
-}
-
 template <typename PT>
 __global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int G, double scale,
                                             const double* __restrict__ src, int k, int i,
                                             const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
                                             double* __restrict__ pd) {
     qa_body<PT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x);
-}
-
-// Column step B (steps 5-6): r_ii = ||s'||, S(:, i) = s'/r_ii, breakdown test,
-// u = U_i^T s_i = (s' - V c1) / r_ii, per-slice partials of ||u(i+1:k)||^2.
-__device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __restrict__ sp,
-                                        const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                        double* __restrict__ u, double* __restrict__ pd2, double* __restrict__ S,
-                                        int64_t lds, double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
-                                        double* __restrict__ invr, const double* __restrict__ pnorm,
-                                        int* __restrict__ status, int bid, double* __restrict__ c1) {
-    __shared__ double red[kGQ][64];
-    __shared__ double tl[64];
-    sum_slices(pd, nsl, mcap + 1, i + 1, c1);
-    __syncthreads();
-    const double rii = sqrt(c1[i]);
-    if (bid == 0 && threadIdx.x == 0) {
-        rr[i] = rii;
-        invr[i] = 1.0 / rii;
-        R[i + (int64_t)i * ldr] = rii;
-        const double pn = (i == 0) ? rii : pnorm[i];
-        if (status[0] == 0 && status[2] == 0) {
-            if (!isfinite(rii) || !isfinite(pn)) {
-                status[1] = i;
-                status[0] = kStatusNonfinite;
-            } else if (rii == 0.0 || rii <= 0x1p-50 * pn) {
-                status[1] = i;
-                status[0] = kStatusBreakdown;
-            }
-        }
-    }
-    const int s = bid, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int r = s * kSlice + rl;
-    red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : 0.0;
-    __syncthreads();
-    if (q == 0) {
-        double t2 = 0.0;
-        if (r < k) {
-            const double spr = sp[r];
-            const double val = (spr - combine16(red, rl)) / rii;
-            u[r] = val;
-            S[r + (int64_t)i * lds] = spr / rii;
-            if (r > i) t2 = val * val;
-        }
-        tl[rl] = t2;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double acc = 0.0;
-        for (int t = 0; t < 64; ++t) acc += tl[t];
-        pd2[s] = acc;
-    }
 }
 
 __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
@@ -509,77 +217,6 @@ __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double*
     qb_body(k, i, nsl, sp, Vc, mcap, pd, u, pd2, S, lds, R, ldr, rr, invr, pnorm, status, blockIdx.x, c1);
 }
 
-// Column step C: Householder reflector of u(i:k) (dlarfg convention):
-// beta = -sign(u_i) ||u(i:k)||, tau = (beta - u_i)/beta, v = [0; 1; u(i+1:k)/(u_i - beta)],
-// stored as column i of V (both layouts).  Per-slice partials of d = V_i^T v
-// (pd, stride mcap+1) and, when the next right-hand side pn = p_{i+1} is given,
-// of e = Wm_i^T pn, v.pn and ||pn||^2 (pdb, stride mcap+2, slots [0,i), i, i+1).
-__device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __restrict__ u,
-                                        const double* __restrict__ pd2, const double* __restrict__ pn,
-                                        double* __restrict__ v, double* __restrict__ Vc, double* __restrict__ Vr,
-                                        const double* __restrict__ Wr, int mcap, double* __restrict__ pd,
-                                        double* __restrict__ pdb, double* __restrict__ tau_a,
-                                        double* __restrict__ beta_a, int* __restrict__ status, int bid) {
-    __shared__ double vs[kSlice], ps[kSlice];
-    __shared__ double hh[3];
-    if (threadIdx.x == 0) {
-        double tail2 = 0.0;
-        for (int s = 0; s < nsl; ++s) tail2 += pd2[s];
-        const double x1 = u[i];
-        double beta, tau, scal;
-        if (tail2 == 0.0) {
-            beta = x1;
-            tau = 0.0;
-            scal = 0.0;
-        } else {
-            beta = -copysign(sqrt(x1 * x1 + tail2), x1);
-            tau = (beta - x1) / beta;
-            scal = 1.0 / (x1 - beta);
-        }
-        hh[0] = beta;
-        hh[1] = tau;
-        hh[2] = scal;
-        if (bid == 0) {
-            tau_a[i] = tau;
-            beta_a[i] = beta;
-            if (status[0] == 0 && status[2] == 0 && !(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1})
-                status[1] = i;
-                status[0] = kStatusBreakdown;
-            }
-        }
-    }
-    __syncthreads();
-    const int s = bid, r0 = s * kSlice;
-    if (threadIdx.x < kSlice) {
-        const int r = r0 + threadIdx.x;
-        double val = 0.0;
-        if (r < k) {
-            val = (r < i) ? 0.0 : (r == i ? 1.0 : u[r] * hh[2]);
-            v[r] = val;
-            Vc[r + (int64_t)i * k] = val;
-            Vr[(int64_t)r * mcap + i] = val;
-        }
-        vs[threadIdx.x] = val;
-        ps[threadIdx.x] = (pn && r < k) ? pn[r] : 0.0;
-    }
-    __syncthreads();
-    const int ntot = pn ? 2 * i + 2 : i;
-    double* outd = pd + (int64_t)s * (mcap + 1);
-    double* oute = pdb + (int64_t)s * (mcap + 2);
-    for (int c = threadIdx.x; c < ntot; c += kGW) {
-        const bool isd = c < i;
-        const int ce = isd ? c : c - i;
-        double val;
-        if (isd || ce < i) {
-            val = slice_dot(isd ? Vr : Wr, mcap, r0, k, isd ? vs : ps, ce);
-        } else {
-            val = (ce == i) ? slice_xy(vs, ps) : slice_sq(ps);
-        }
-        if (isd) outd[c] = val;
-        else oute[ce] = val;
-    }
-}
-
 __global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
                                             const double* __restrict__ pd2, const double* __restrict__ pn,
                                             double* __restrict__ v, double* __restrict__ Vc,
@@ -588,74 +225,6 @@ __global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double*
                                             double* __restrict__ tau_a, double* __restrict__ beta_a,
                                             int* __restrict__ status) {
     qc_body(k, i, nsl, u, pd2, pn, v, Vc, Vr, Wr, mcap, pd, pdb, tau_a, beta_a, status, blockIdx.x);
-}
-
-// Column step D.  Blocks [0, nsl): Wm(:, i) = tau (v - Wm_i d), d = sum of the slice partials.
-// Blocks [nsl, ...), rows r of [64 b, 64 b + 64):
-//   column i of X = R_S^{-1}: X(r, i) = -(sum_{c=r}^{i-1} X(r, c) u(c)) / beta for r < i
-//   (u(0:i) is R_S(0:i, i)), X(i, i) = 1/beta;
-//   when pn is given, the head of U_{i+1}^T pn for the next column's least squares:
-//   cp = Wm_{i+1}^T pn = [e; tau (v.pn - d.e)],  uh(r) = pn(r) - sum_{c <= min(r,i)} V(r, c) cp(c), r <= i.
-__device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __restrict__ v,
-                                        const double* __restrict__ u, const double* __restrict__ pn,
-                                        double* __restrict__ Wc, double* __restrict__ Wr,
-                                        const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                        const double* __restrict__ pdb, double* __restrict__ X,
-                                        double* __restrict__ uh, double* __restrict__ pnorm,
-                                        const double* __restrict__ tau_a, const double* __restrict__ beta_a,
-                                        int bid, double* __restrict__ dyn) {
-    __shared__ double red[kGQ][64];
-    __shared__ double tree[kGW];
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const double tau = tau_a[i];
-    if (bid < nsl) {
-        double* dsh = dyn;
-        sum_slices(pd, nsl, mcap + 1, i, dsh);
-        __syncthreads();
-        const int r = bid * kSlice + rl;
-        red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : 0.0;
-        __syncthreads();
-        if (q == 0 && r < k) {
-            const double val = tau * (v[r] - combine16(red, rl));
-            Wc[r + (int64_t)i * k] = val;
-            Wr[(int64_t)r * mcap + i] = val;
-        }
-        if (bid == 0 && threadIdx.x == 0) X[i + (int64_t)i * mcap] = 1.0 / beta_a[i];
-        return;
-    }
-    double* ush = dyn;            // u(0:i)
-    double* dsh = dyn + (i + 1);  // d
-    double* csh = dsh + (i + 1);  // cp
-    for (int c = threadIdx.x; c < i; c += kGW) ush[c] = u[c];
-    if (pn) {
-        for (int c = threadIdx.x; c < 2 * i + 2; c += kGW) {
-            if (c < i) dsh[c] = sum_col(pd, nsl, mcap + 1, c);
-            else csh[c - i] = sum_col(pdb, nsl, mcap + 2, c - i);   // e, then v.pn at i, ||pn||^2 at i+1
-        }
-    }
-    __syncthreads();
-    const int r = (bid - nsl) * 64 + rl;
-    red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : 0.0;
-    __syncthreads();
-    if (q == 0 && r < i) X[r + (int64_t)i * mcap] = -combine16(red, rl) / beta_a[i];
-    if (!pn) return;
-    // d.e by a fixed-shape tree, then cp(i) = tau (v.pn - d.e)
-    double part = 0.0;
-    for (int c = threadIdx.x; c < i; c += kGW) part = fma(dsh[c], csh[c], part);
-    tree[threadIdx.x] = part;
-    __syncthreads();
-    for (int w = kGW / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double vp = csh[i], pp = csh[i + 1];
-    __syncthreads();
-    if (threadIdx.x == 0) csh[i] = tau * (vp - tree[0]);
-    if (bid == nsl && threadIdx.x == 0) pnorm[i + 1] = sqrt(pp);
-    __syncthreads();
-    red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : 0.0;
-    __syncthreads();
-    if (q == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
 }
 
 __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
@@ -680,7 +249,7 @@ __global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items
     const int2 bm = map[blockIdx.x];
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    const bool from_p = (i == 0 && !it.defer);
+    const bool from_p = (i == 0 && !it.defer && it.P != nullptr);   // GMRES systems carry no P
     qa_body<PT>(static_cast<const PT*>(it.part), it.nproj, it.sketch_scale, from_p ? it.P : nullptr, a.k, i, a.Wr,
                 a.mcap, a.sp, a.pd, bm.y);
 }
@@ -700,7 +269,7 @@ __global__ __launch_bounds__(kGW) void kb_qc(const BatchItem* __restrict__ items
     const int2 bm = map[blockIdx.x];
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    const double* pn = (i + 1 < it.m) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
+    const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
     qc_body(a.k, i, it.nsl, a.u, a.pd2, pn, a.v, a.Vc, a.Vr, a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status,
             bm.y);
 }
@@ -711,7 +280,7 @@ __global__ __launch_bounds__(kGW) void kb_qd(const BatchItem* __restrict__ items
     const int2 bm = map[blockIdx.x];
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    const double* pn = (i + 1 < it.m) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
+    const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
     qd_body(a.k, i, it.nsl, a.v, a.u, pn, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
             a.beta, bm.y, dyn);
 }
@@ -1060,6 +629,8 @@ template bool launch_batch_project<float, float, false>(hipStream_t, int, const 
 template bool launch_batch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const int2*, int, int);
 template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,
                                          const int2*, int, int);
+template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,
+                                          const int2*, int, int);
 template bool launch_batch_scale<float, false>(hipStream_t, const BatchItem*, const int2*, int);
 template bool launch_batch_scale<bf16, true>(hipStream_t, const BatchItem*, const int2*, int);
 template bool launch_materialize<float>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,

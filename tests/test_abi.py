@@ -70,3 +70,4 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(rgs.GmresDesc) == 8 * 5 + 4 * 4
     assert ctypes.sizeof(rgs.Report) == 8 * 9
     assert ctypes.sizeof(rgs.QrItem) == 8 * 11
+    assert ctypes.sizeof(rgs.GmresItem) == ctypes.sizeof(rgs.Stencil7) + 8 * 4

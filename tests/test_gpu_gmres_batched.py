@@ -1,0 +1,168 @@
+"""GPU parity of the batched randomized GMRES (rgs_gmres_batched) and of the
+bf16-basis RGMRES.
+
+* every system of a batched solve equals a separate rgs_gmres call on it bit
+  for bit (x, residual history, iteration and cycle counts), for both
+  sketches and the fp64 / fp32 / bf16 bases, with a fresh sketch per cycle;
+* the graph-replayed cycles equal the eagerly launched ones bit for bit (the
+  graph is replayed once per cycle, and re-captured when systems drop out);
+* against the oracle: fp64 and fp32 bases converge within +-2 iterations of
+  the fp64 oracle's count, the bf16 basis within +-2 of the oracle's bf16
+  model; every true residual (recomputed with the oracle's operator in fp64)
+  is <= tol;
+* per-system failure handling: a non-finite right-hand side and the
+  max_iters cap are reported for that system only.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gmres as ogm, sketch as osk, stencil as ost
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RESTART, K, TOL = 20, 96, 1e-6
+
+
+def _rgs():
+    import paper_2011_05090_amd as rgs
+    return rgs
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=torch.float64, device="cuda")
+
+
+def _systems(count, tag, n_lo=6, n_hi=22):
+    """Grids N^3 with N ~ U{n_lo..n_hi} (some rows ragged, a few spanning
+    several 8192-row blocks) and Pe ~ U[1, 100] (the recipe of the batched
+    convection-diffusion workload, at sizes the oracle redoes in seconds)."""
+    Ns, Pes = synth.batch_gmres_sizes(count, N_lo=n_lo, N_hi=n_hi, tag=tag)
+    out = []
+    for i, (N, Pe) in enumerate(zip(Ns, Pes)):
+        dims, coeffs = synth.convdiff_coeffs(int(N), float(Pe))
+        out.append((dims, coeffs, synth.rhs(int(N) ** 3, tag=100 * tag + i)))
+    return out
+
+
+def _batched(h, systems, desc, hist_cap=4000):
+    rgs = _rgs()
+    xs = [torch.full((b.size,), np.nan, dtype=torch.float64, device="cuda") for _, _, b in systems]
+    sy = [(rgs.stencil7(d, c), dev(b), x) for (d, c, b), x in zip(systems, xs)]
+    st, stat, reps, hists = rgs.rgs_gmres_batched(h, sy, desc, hist_cap=hist_cap)
+    torch.cuda.synchronize()
+    return st, stat, reps, hists, xs
+
+
+def _single(h, system, desc, hist_cap=4000):
+    rgs = _rgs()
+    dims, coeffs, b = system
+    x = torch.full((b.size,), np.nan, dtype=torch.float64, device="cuda")
+    rep, hist = rgs.rgs_gmres(h, rgs.stencil7(dims, coeffs), desc, dev(b), x, res_hist=hist_cap)
+    torch.cuda.synchronize()
+    return rep, hist, x
+
+
+@pytest.mark.parametrize("sketch,prec", [("srht", "fp32"), ("gaussian", "fp32"), ("srht", "bf16q"),
+                                         ("gaussian", "bf16q"), ("srht", "fp64")])
+def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec):
+    rgs = _rgs()
+    systems = _systems(6, tag=1)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec)
+    st, stat, reps, hists, xs = _batched(gpu_handle, systems, desc)
+    assert st == 0 and stat == [0] * len(systems)
+    for sysm, rep, hist, x in zip(systems, reps, hists, xs):
+        rep1, hist1, x1 = _single(gpu_handle, sysm, desc)
+        assert rep1.status == 0
+        assert (rep.iters, rep.cycles) == (rep1.iters, rep1.cycles)
+        assert rep.true_relres == rep1.true_relres
+        assert hist == hist1
+        assert torch.equal(x, x1)
+
+
+@pytest.mark.parametrize("sketch,prec", [("srht", "fp32"), ("gaussian", "bf16q")])
+def test_graph_replay_equals_eager(gpu_handle, sketch, prec):
+    rgs = _rgs()
+    systems = _systems(7, tag=2)
+    d_eager = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec)
+    d_graph = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, flags=rgs.FLAG_GRAPH)
+    a = _batched(gpu_handle, systems, d_eager)
+    # host work between the runs, as an application would do
+    torch.cuda.synchronize()
+    b_ = _batched(gpu_handle, systems, d_graph)
+    cyc = [r.cycles for r in a[2]]
+    assert max(cyc) > min(cyc)          # systems drop out at different cycles: the graph is re-captured
+    assert a[0] == b_[0] == 0
+    for ra, rb, ha, hb, xa, xb in zip(a[2], b_[2], a[3], b_[3], a[4], b_[4]):
+        assert (ra.iters, ra.cycles, ra.true_relres) == (rb.iters, rb.cycles, rb.true_relres)
+        assert ha == hb
+        assert torch.equal(xa, xb)
+
+
+@pytest.mark.parametrize("sketch,prec,model", [("gaussian", "fp64", "fp64"), ("srht", "fp32", "fp64"),
+                                               ("gaussian", "fp32", "fp64"), ("srht", "bf16q", "bf16q"),
+                                               ("gaussian", "bf16q", "bf16q")])
+def test_batched_matches_oracle(gpu_handle, sketch, prec, model):
+    rgs = _rgs()
+    systems = _systems(5, tag=3)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, flags=rgs.FLAG_GRAPH)
+    st, stat, reps, hists, xs = _batched(gpu_handle, systems, desc)
+    assert st == 0
+    for (dims, coeffs, b), rep, hist, x in zip(systems, reps, hists, xs):
+        n = b.size
+        ref = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b,
+                         lambda c: osk.make(sketch, n, K, seed=42, sketch_id=2 + c),
+                         restart=RESTART, tol=TOL, precision=model, max_iters=3000)
+        assert ref["converged"]
+        assert abs(rep.iters - ref["iters"]) <= 2, (dims, rep.iters, ref["iters"])
+        r = b - ost.apply(x.cpu().numpy(), dims, coeffs, np.float64)
+        relres = np.linalg.norm(r) / np.linalg.norm(b)
+        assert relres <= TOL and abs(relres - rep.true_relres) <= 1e-6 * relres
+        # the sketched residual history tracks the oracle's while both run the same cycle
+        m = min(len(hist), len(ref["hist"]), RESTART)
+        np.testing.assert_allclose(hist[:m], ref["hist"][:m], rtol=1e-2 if prec == "bf16q" else 1e-4)
+
+
+def test_batched_per_system_failures(gpu_handle):
+    rgs = _rgs()
+    systems = _systems(4, tag=4)
+    dims, coeffs, b = systems[1]
+    b = b.copy()
+    b[5] = np.nan
+    systems[1] = (dims, coeffs, b)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch="srht", prec="fp32", flags=rgs.FLAG_GRAPH)
+    st, stat, reps, hists, xs = _batched(gpu_handle, systems, desc)
+    assert st == rgs.RGS_ENONFINITE and stat == [0, rgs.RGS_ENONFINITE, 0, 0]
+    for i in (0, 2, 3):
+        assert reps[i].true_relres <= TOL
+    # the iteration cap: a system that needs more steps than allowed ends with ENOCONV
+    need = max(r.iters for i, r in enumerate(reps) if i != 1)
+    cap = need - 3
+    desc2 = rgs.gmres_desc(RESTART, K, TOL, max_iters=cap, sketch="srht", prec="fp32")
+    ok = [s for i, s in enumerate(systems) if i != 1]
+    st2, stat2, reps2, _, _ = _batched(gpu_handle, ok, desc2)
+    assert st2 == rgs.RGS_ENOCONV
+    for r, s2, r_full in zip(reps2, stat2, [reps[0], reps[2], reps[3]]):
+        if r_full.iters > cap:
+            assert s2 == rgs.RGS_ENOCONV and r.iters == cap
+        else:
+            assert s2 == 0 and r.iters == r_full.iters
+
+
+def test_bf16_single_matches_oracle_model(gpu_handle):
+    """rgs_gmres with the bf16 basis on one system spanning several blocks."""
+    rgs = _rgs()
+    N, Pe = 24, 50.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    b = synth.rhs(N ** 3, tag=5)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch="srht", prec="bf16q")
+    rep, hist, x = _single(gpu_handle, (dims, coeffs, b), desc)
+    ref = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b,
+                     lambda c: osk.make("srht", N ** 3, K, seed=42, sketch_id=2 + c),
+                     restart=RESTART, tol=TOL, precision="bf16q", max_iters=3000)
+    assert rep.status == 0 and ref["converged"]
+    assert abs(rep.iters - ref["iters"]) <= 2
+    r = b - ost.apply(x.cpu().numpy(), dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= TOL
