@@ -63,8 +63,10 @@ def measured_traffic(n, m, k):
     return rec["traffic_bytes_per_launch"]
 
 
-TRAFFIC_SOURCES = ["paper_2011_05090_amd/csrc/rgs_kernels.hip", "paper_2011_05090_amd/csrc/rgs_block.hpp",
-                   "paper_2011_05090_amd/csrc/rgs_device.hpp"]
+# the projection kernel and everything its code is built from
+TRAFFIC_SOURCES = ["paper_2011_05090_amd/csrc/rgs_project.hip", "paper_2011_05090_amd/csrc/rgs_proj.hpp",
+                   "paper_2011_05090_amd/csrc/rgs_block.hpp", "paper_2011_05090_amd/csrc/rgs_device.hpp",
+                   "paper_2011_05090_amd/csrc/rgs_types.hpp"]
 PROJECT_KERNEL = "k_project<float, float, float, 1, false>"      # fp32 basis, P-SRHT, normalised storage
 
 
@@ -246,6 +248,49 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
     return out
 
 
+def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e-6, gaussian_batch=32):
+    """Batched randomized GMRES: ``batch`` convection-diffusion systems on grids
+    N^3, N ~ U{32..96}, Pe ~ U[1, 100], b ~ N(0, 1), restart 50, k = 200,
+    tol 1e-6, one rgs_gmres_batched call with graph-replayed cycles.  The bf16
+    and fp32 bases are compared with plain fp64 on the same GPU (iteration
+    counts per system).  The Gaussian sketch regenerates its entries per
+    system, so it runs on the first ``gaussian_batch`` systems only."""
+    Ns, Pes = synth.batch_gmres_sizes(batch)
+    systems = []
+    for i, (N, Pe) in enumerate(zip(Ns, Pes)):
+        dims, coeffs = synth.convdiff_coeffs(int(N), float(Pe))
+        b = torch.from_numpy(synth.rhs(int(N) ** 3, tag=1000 + i)).to("cuda")
+        systems.append((rgs.stencil7(dims, coeffs), b, torch.empty_like(b)))
+    n_tot = int(sum(int(N) ** 3 for N in Ns))
+    out = {"batch": batch, "N_range": [32, 96], "Pe_range": [1.0, 100.0], "restart": restart, "k": k, "tol": tol,
+           "unknowns": n_tot}
+    for sketch in ("srht", "gaussian"):
+        sy = systems if sketch == "srht" else systems[:gaussian_batch]
+        res = {"systems": len(sy)}
+        iters = {}
+        for prec in ("bf16q", "fp32", "fp64"):
+            d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch=sketch, prec=prec, flags=rgs.FLAG_GRAPH)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, stat, reps, _ = rgs.rgs_gmres_batched(h, sy, d)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            iters[prec] = [r.iters for r in reps]
+            res[prec] = {"seconds_to_tol": dt, "status": st, "converged": sum(1 for v in stat if v == 0),
+                         "total_iters": int(sum(iters[prec])), "max_cycles": max(r.cycles for r in reps),
+                         "max_true_relres": max(r.true_relres for r in reps)}
+            log("  batched rgmres %s/%s x%d: %.3f s, %d converged, max cycles %d, max relres %.2e" %
+                (sketch, prec, len(sy), dt, res[prec]["converged"], res[prec]["max_cycles"],
+                 res[prec]["max_true_relres"]))
+        for prec in ("bf16q", "fp32"):
+            diff = [a - b for a, b in zip(iters[prec], iters["fp64"])]
+            res[prec]["iters_minus_fp64"] = {"min": min(diff), "max": max(diff),
+                                             "within_2": sum(1 for v in diff if abs(v) <= 2)}
+            res[prec]["speedup_vs_fp64"] = res["fp64"]["seconds_to_tol"] / res[prec]["seconds_to_tol"]
+        out[sketch] = res
+    return out
+
+
 def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6):
     """Time-to-1e-6 of restarted randomized GMRES on the 7-point convection-diffusion
     system (N^3 unknowns, b ~ N(0,1)), fp32 basis vs plain fp64, Gaussian and SRHT."""
@@ -339,7 +384,7 @@ def main():
                    "pct_hbm_peak": 100 * value / HBM_PEAK_GBS, "bytes_per_step": B},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n, m, k),
-                     "kernel": "k_project<float,float,SRHT>",
+                     "kernel": "rgs::" + PROJECT_KERNEL,
                      "avg_launch_ms": avg_launch_ms, "avg_launch_bytes": avg_launch_bytes},
         "quality": {"backward_error": res, "norm2_I_minus_StS": d2, "norm2_I_minus_QtQ": o2},
     }
@@ -384,6 +429,8 @@ def main():
     if not args.no_batched:
         log("batched RGS QR (bf16 Q)")
         out["extra"]["batched_qr_2048"] = batched_qr_leg(rgs, torch, synth, h)
+        log("batched randomized GMRES")
+        out["extra"]["batched_rgmres_256"] = batched_gmres_leg(rgs, torch, synth, h)
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

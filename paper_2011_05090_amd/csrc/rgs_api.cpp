@@ -160,9 +160,14 @@ struct QrPlan {
     size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2, pdb, pbuf;
     size_t rr, invr, pnorm, tau, beta, status, coef, diag;
     size_t total;
-    int G_P, cc;
+    int G_P, G_col, cc;
     int64_t nblk, nproj;
 };
+
+// Below this many rows the fused projection + Gaussian sketch has too few row
+// blocks to fill the device, so the column's sketch gets a launch of its own
+// spread over up to 256 row groups x k/256 row chunks of Theta.
+constexpr int64_t kSplitRows = (int64_t)128 * kProjRows;
 
 QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     QrPlan p{};
@@ -170,12 +175,17 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     p.nblk = (n + kBlock - 1) / kBlock;
     p.nproj = (n + kProjRows - 1) / kProjRows;
     const int64_t nsl = (k + kSlice - 1) / kSlice;
-    p.G_P = (int)std::min<int64_t>(p.nblk, 64);
+    const int64_t nsub = (n + 255) / 256;
+    // row groups of P = Theta W: 4096-row blocks (SRHT), 256-row sub-blocks (Gaussian)
+    p.G_P = (int)std::min<int64_t>(sketch == SK_GAUSS ? nsub : p.nblk, 64);
+    // Gaussian sketch of a single column in its own launch (below kSplitRows rows)
+    p.G_col = (sketch == SK_GAUSS && n < kSplitRows) ? (int)std::min<int64_t>(nsub, 256) : 0;
     const size_t per_col = (size_t)p.G_P * k * tsize;
     p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
     p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
     p.rows = c.take<int>(k);
-    p.part_proj = c.take<char>((sketch == SK_IDENT ? (size_t)n : (size_t)p.nproj * k) * tsize);
+    p.part_proj = c.take<char>(
+        (sketch == SK_IDENT ? (size_t)n : (size_t)std::max<int64_t>(p.nproj, p.G_col) * k) * tsize);
     p.part_P = c.take<char>(per_col * p.cc);
     p.P = c.take<double>(k * m);
     p.Vc = c.take<double>(k * m);
@@ -242,7 +252,11 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const T* X, int64_
                     return RGS_EDEVICE;
             continue;
         }
-        if (!launch_sketch_cols<T, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
+        if (sk.sketch == SK_GAUSS) {
+            if (!launch_gauss_cols<T, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
+        } else if (!launch_sketch_cols<T, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
+            return RGS_EDEVICE;
+        }
         if (!launch_reduce<T>(h->stream, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
     }
     return RGS_OK;
@@ -281,16 +295,20 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const bool vec_ok = (ldq % 4 == 0) && (ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) &&
                         ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
     const double scale = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)k);
-    const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nproj;
+    const bool split = pl.G_col > 0;
+    const int Gp = sk_kind == SK_IDENT ? 1 : (split ? pl.G_col : (int)pl.nproj);
 
     for (int64_t i = 0; i < m; ++i) {
         // column i: step 3 (+4, + step 7 of column i-1) with the coefficients solved at the end
         // of column i-1, then steps 5-6, the Householder append of s_i and step 2 for column i+1
         const double* pnext = (i + 1 < m) ? P + (i + 1) * k : nullptr;
         if (timed) (void)hipEventRecord(h->events[2 * i], s);
+        const bool sketch_col = DEFER || i > 0;
         if (!launch_project<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
                                           i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
-                                          (DEFER || i > 0) ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
+                                          (sketch_col && !split) ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
+            return RGS_EDEVICE;
+        if (split && sketch_col && !launch_gauss_cols<TQ, T>(s, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
         if (!launch_column<T, T>(s, sa, part, Gp, scale, (i == 0 && !DEFER) ? P : nullptr, (int)i, S, lds, R, ldr,
@@ -392,9 +410,14 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const size_t osn = c.take<double>(mcap), ogv = c.take<double>(mcap + 1), oy = c.take<double>(mcap);
     const size_t ohist = c.take<double>(mcap), oused = c.take<int>(4), or_ = c.take<double>(n);
     const size_t opart = c.take<double>((n + 255) / 256), onorm = c.take<double>(4);
+    // Gaussian: the two sketches of an Arnoldi step share their draws (the
+    // mat-vec kernel sketches q'_i and A q'_i together), second partials buffer
+    const bool dual = sk_kind == SK_GAUSS;
+    const size_t opart2 = c.take<T>(dual ? pl.nproj * k : 1);
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* Ar = h->arena;
+    T* part2 = reinterpret_cast<T*>(Ar + opart2);
     SpaceArgs sa = space_args(Ar, pl, k, mcap);
     TQ* Q = reinterpret_cast<TQ*>(Ar + oQ);
     T* wbuf = reinterpret_cast<T*>(Ar + oW);
@@ -439,24 +462,39 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
         // RGS step 1 of Algorithm 3: w_1 = r_0
         if (!launch_cast<T>(s, r, wbuf, n)) return RGS_EDEVICE;
-        if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, 1, vec_ok ? 1 : 0, sk, part,
-                                          sa.status))
+        if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, dual ? 0 : 1, vec_ok ? 1 : 0, sk,
+                                          part, sa.status))
             return RGS_EDEVICE;
+        // dual: t_1 = A q'_0 with the sketches of q'_0 (part) and t_1 (part2)
+        if (dual && !launch_stencil_dual<TQ, T>(s, A, Q, wbuf, sk, part, part2, sa.status)) return RGS_EDEVICE;
         if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, 0, S, k, R, mcap, nullptr, coef, nullptr))
             return RGS_EDEVICE;
         if (!launch_givens_init(s, R, gv, used)) return RGS_EDEVICE;
         const int64_t steps = std::min<int64_t>(d->restart, d->max_iters - iters);
         for (int64_t ci = 1; ci <= steps; ++ci) {
             const int i = (int)ci;
-            // w_i = A q_{i-1}, sketched: p_i (step 3 of Algorithm 3, step 1 of Algorithm 2)
-            if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
-                                              sa.status))
-                return RGS_EDEVICE;
-            if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr))
-                return RGS_EDEVICE;
-            if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
-                                              vec_ok ? 1 : 0, sk, part, sa.status))
-                return RGS_EDEVICE;
+            if (dual) {
+                // p_i = Theta (A q'_{i-1}) / r_{i-1,i-1} and w_i = (A q'_{i-1}) / r_{i-1,i-1}
+                if (!launch_ls_partials<T, T>(s, sa, part2, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr,
+                                              sa.invr + (i - 1)))
+                    return RGS_EDEVICE;
+                if (!launch_project_ws<T, TQ, DEFER>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1,
+                                                     vec_ok ? 1 : 0, sa.invr + (i - 1), sa.status))
+                    return RGS_EDEVICE;
+                if (!launch_stencil_dual<TQ, T>(s, A, Q + i * n, wbuf, sk, part, part2, sa.status))
+                    return RGS_EDEVICE;
+            } else {
+                // w_i = A q_{i-1}, sketched: p_i (step 3 of Algorithm 3, step 1 of Algorithm 2)
+                if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
+                                                  sa.status))
+                    return RGS_EDEVICE;
+                if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr,
+                                              nullptr))
+                    return RGS_EDEVICE;
+                if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
+                                                  vec_ok ? 1 : 0, sk, part, sa.status))
+                    return RGS_EDEVICE;
+            }
             if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef, nullptr))
                 return RGS_EDEVICE;
             if (!launch_givens(s, i, R, (int)mcap, Hr, cs, sn, gv, bnorm, d->tol, hist, sa.status, used,
@@ -800,7 +838,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
 
     // scratch of every system, carved from the handle's arena
     struct Off {
-        size_t Q, w, r, rpart, R, S, part, coef, Vc, Vr, Wc, Wr, X, sp, u, v, pbuf, uh, pd, pdb, pd2, rr, invr, pnorm,
+        size_t Q, w, r, rpart, R, S, part, part2, coef, Vc, Vr, Wc, Wr, X, sp, u, v, pbuf, uh, pd, pdb, pd2, rr, invr, pnorm,
             tau, beta, Hr, cs, sn, gv, y, signs;
     };
     std::vector<Off> off((size_t)batch);
@@ -815,6 +853,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         o.R = c.take<double>(mcap * mcap);
         o.S = c.take<double>(k * mcap);
         o.part = c.take<T>(nproj * k);
+        o.part2 = c.take<T>(sk_kind == SK_GAUSS ? nproj * k : 1);
         o.coef = c.take<T>(mcap);
         o.Vc = c.take<double>(k * mcap);
         o.Vr = c.take<double>(k * mcap);
@@ -874,6 +913,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         x.lds = k;
         x.P = nullptr;
         x.part = A + o.part;
+        x.part2 = A + o.part2;
         x.coef = A + o.coef;
         x.sketch_scale = 1.0 / std::sqrt((double)k);
         x.vec_ok = (n % 4 == 0) ? 1 : 0;
@@ -969,18 +1009,33 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         exec = nullptr;
         graph = nullptr;
     };
+    const bool dual = sk_kind == SK_GAUSS;   // the two sketches of an Arnoldi step share their draws
     auto enqueue_cycle = [&](hipStream_t q) -> bool {
         if (!launch_gbatch_reset(q, itd, mp + gm.sys, gm.nsys)) return false;
         if (!launch_gbatch_cast<T>(q, gid, mp + gm.row, gm.nrow)) return false;
-        if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, 0)) return false;
+        if (dual) {
+            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, mp + gm.proj, gm.nproj, 0) ||
+                !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, mp + gm.proj, gm.nproj, 0))
+                return false;
+        } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, 0)) {
+            return false;
+        }
         if (!launch_batch_column<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.qd[0], gm.nqd[0], nullptr, 0, 0))
             return false;
         if (!launch_gbatch_givens_init(q, itd, gid, mp + gm.sys, gm.nsys)) return false;
         for (int64_t i = 1; i <= restart; ++i) {
             const int ii = (int)i;
-            if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii)) return false;
-            if (!launch_gbatch_ls<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.rb[i], gm.nrb[i], ii)) return false;
-            if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii)) return false;
+            if (dual) {
+                if (!launch_gbatch_ls<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.rb[i], gm.nrb[i], ii, 1) ||
+                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, mp + gm.proj, gm.nproj, ii) ||
+                    !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, mp + gm.proj, gm.nproj, ii))
+                    return false;
+            } else {
+                if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii)) return false;
+                if (!launch_gbatch_ls<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.rb[i], gm.nrb[i], ii, 0)) return false;
+                if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii))
+                    return false;
+            }
             if (!launch_batch_column<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.qd[i], gm.nqd[i], nullptr, 0, ii))
                 return false;
             if (!launch_gbatch_givens(q, itd, gid, mp + gm.sys, gm.nsys, ii)) return false;

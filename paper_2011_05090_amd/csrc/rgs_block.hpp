@@ -5,7 +5,7 @@
 #pragma once
 
 #include "rgs_device.hpp"
-#include "rgs_internal.hpp"
+#include "rgs_types.hpp"
 
 namespace rgs {
 

@@ -135,6 +135,69 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
     }
 }
 
+// Gaussian sketch only.  For the stored column x (unscaled): t = A x, stored
+// in t_out, and the block's sketch partials of both x and t from one
+// generation of Theta's entries (the two sketches of an Arnoldi step, s'_i of
+// q'_i and p_{i+1} of A q'_i, share every draw; the normalisation 1/r_ii is
+// applied to both later, when it is known).  Same row mapping and summation
+// order per vector as stencil_sketch_body.
+template <typename TQ, typename T>
+__device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
+                                                  T* __restrict__ t_out, const SketchArgs& sk,
+                                                  T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
+                                                  T* __restrict__ lds) {
+    constexpr int NW = kProjWaves, NT = NW * kWave, RB = NW * kTile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto ld = [&](int64_t idx) -> T { return (T)to_double(xs[idx]); };
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int local = wave * kTile + 256 * e + 4 * lane;
+        const int64_t r0 = blk * RB + local;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t l = r0 + r;
+            T tv = T(0), xv = T(0);
+            if (l < n) {
+                tv = stencil_row<T>(g, l, ld);
+                xv = ld(l);
+                t_out[l] = tv;
+            }
+            lds[local + r] = xv;
+            lds[RB + local + r] = tv;
+        }
+    }
+    __syncthreads();
+    const int kpt = (sk.k + NT - 1) / NT;
+    T ax[kKptMax], at[kKptMax];
+#pragma unroll
+    for (int u = 0; u < kKptMax; ++u) ax[u] = at[u] = T(0);
+    const int64_t rem = n - blk * RB;
+    const int nq = rem >= RB ? RB / 4 : (int)((rem + 3) / 4);
+    const uint32_t q0 = (uint32_t)(blk * (RB / 4));
+    for (int q = 0; q < nq; ++q) {
+        const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
+        const T t0 = lds[RB + 4 * q], t1 = lds[RB + 4 * q + 1], t2 = lds[RB + 4 * q + 2], t3 = lds[RB + 4 * q + 3];
+#pragma unroll
+        for (int u = 0; u < kKptMax; ++u) {
+            const int j = threadIdx.x + NT * u;
+            if (u < kpt && j < sk.k) {
+                T z[4];
+                gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+                ax[u] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
+                at[u] += z[0] * t0 + z[1] * t1 + z[2] * t2 + z[3] * t3;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kKptMax; ++u) {
+        const int j = threadIdx.x + NT * u;
+        if (u < kpt && j < sk.k) {
+            part_x[blk * sk.k + j] = ax[u];
+            part_t[blk * sk.k + j] = at[u];
+        }
+    }
+}
+
 // r = b - A x in fp64 for the 256 rows of block blk (256 threads), and the
 // block's partial sum of ||r||^2.
 __device__ __forceinline__ void residual_body(const double* __restrict__ b, const double* __restrict__ x,
@@ -264,6 +327,15 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
     stencil_sketch_body<TQ, T, PT, SK>(qs, invr, g, n, w, do_sketch, sk, partials, blockIdx.x, lds);
 }
 
+template <typename TQ, typename T>
+__global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
+    const TQ* __restrict__ xs, Grid3 g, int64_t n, T* __restrict__ t_out, SketchArgs sk, T* __restrict__ part_x,
+    T* __restrict__ part_t, const int* __restrict__ status) {
+    __shared__ T lds[2 * kProjWaves * kTile];
+    RGS_EXIT_IF_STOPPED(status);
+    stencil_dual_body<TQ, T>(xs, g, n, t_out, sk, part_x, part_t, blockIdx.x, lds);
+}
+
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
                                                   Grid3 g, int64_t n, double* __restrict__ r,
                                                   double* __restrict__ part) {
@@ -350,6 +422,39 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem
                                       static_cast<T*>(it.part), bm.y, lds);
 }
 
+template <typename TQ, typename T>
+__global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const BatchItem* __restrict__ items,
+                                                                      const GmresItem* __restrict__ gi,
+                                                                      const int2* __restrict__ map, int i) {
+    __shared__ T lds[2 * kProjWaves * kTile];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_STOPPED(it.sa.status);
+    const GmresItem& g = gi[bm.x];
+    stencil_dual_body<TQ, T>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+                             static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part), static_cast<T*>(it.part2), bm.y,
+                             lds);
+}
+
+// The projection of the fused-sketch Gaussian step: w_i = (A q'_{i-1}) / r_{i-1,i-1}
+// scaled on load, no sketch (taken by kg_stencil_dual afterwards).
+template <typename T, typename TQ, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void kg_project_ws(const BatchItem* __restrict__ items,
+                                                                    const GmresItem* __restrict__ gi,
+                                                                    const int2* __restrict__ map, int i) {
+    __shared__ T lds[kProjWaves * kTile];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_STOPPED(it.sa.status);
+    const GmresItem& g = gi[bm.x];
+    SketchArgs none{};
+    project_body<T, TQ, T, SK_GAUSS, DEFER, true>(static_cast<const T*>(g.w), static_cast<TQ*>(it.Q), it.ldq, it.n,
+                                                  i, static_cast<const T*>(it.coef),
+                                                  i > 0 ? it.sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
+                                                  0, it.vec_ok, none, nullptr, bm.y, lds,
+                                                  i > 0 ? it.sa.invr + (i - 1) : nullptr);
+}
+
 template <typename T, typename TQ, int SK, bool DEFER>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem* __restrict__ items,
                                                                  const GmresItem* __restrict__ gi,
@@ -370,12 +475,13 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem
 // of U^T p, then y = R_S^{-1} uh -> R(0:i, i) and the projection coefficients.
 template <typename PT>
 __global__ __launch_bounds__(kGW) void kg_lsa(const BatchItem* __restrict__ items, const int2* __restrict__ map,
-                                              int i) {
+                                              int i, int dual) {
     const int2 bm = map[blockIdx.x];
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    qa_body<PT>(static_cast<const PT*>(it.part), it.nproj, it.sketch_scale, nullptr, a.k, i, a.Wr, a.mcap, a.pbuf,
-                a.pd, bm.y);
+    // dual: p_i arrives as the sketch of A q'_{i-1} (part2), scaled by 1/r_{i-1,i-1} here
+    qa_body<PT>(static_cast<const PT*>(dual ? it.part2 : it.part), it.nproj, it.sketch_scale, nullptr, a.k, i, a.Wr,
+                a.mcap, a.pbuf, a.pd, bm.y, dual ? a.invr + (i - 1) : nullptr);
 }
 
 __global__ __launch_bounds__(kGW) void kg_ls2(const BatchItem* __restrict__ items, const int2* __restrict__ map,
@@ -478,6 +584,16 @@ bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, c
     return true;
 }
 
+template <typename TQ, typename T>
+bool launch_stencil_dual(hipStream_t st, const StencilArgs& A, const TQ* xs, T* t_out, const SketchArgs& sk,
+                         T* part_x, T* part_t, const int* status) {
+    const int64_t n = A.nx * A.ny * A.nz;
+    hipLaunchKernelGGL((k_stencil_dual<TQ, T>), dim3(nblk_of(n, kProjRows)), dim3(kProjWaves * kWave), 0, st, xs,
+                       grid3(A), n, t_out, sk, part_x, part_t, status);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 bool launch_residual(hipStream_t st, const StencilArgs& A, const double* b, const double* x, double* r,
                      double* part, double* norm_out) {
     const int64_t n = A.nx * A.ny * A.nz;
@@ -556,6 +672,25 @@ bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, c
     return true;
 }
 
+template <typename T, typename TQ>
+bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_proj,
+                                int nproj, int i) {
+    if (nproj == 0) return true;
+    hipLaunchKernelGGL((kg_stencil_dual<TQ, T>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi, map_proj, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename T, typename TQ, bool DEFER>
+bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_proj,
+                              int nproj, int i) {
+    if (nproj == 0) return true;
+    hipLaunchKernelGGL((kg_project_ws<T, TQ, DEFER>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
+                       map_proj, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
                            const int2* map_proj, int nproj, int i) {
@@ -571,9 +706,9 @@ bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, c
 
 template <typename T>
 bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const int2* map_sl, int nsl, const int2* map_rb,
-                      int nrb, int i) {
+                      int nrb, int i, int dual) {
     if (nsl > 0) {
-        hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i);
+        hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i, dual);
         RGS_LAUNCH_CHECK();
     }
     if (nrb > 0) {
@@ -650,8 +785,26 @@ template bool launch_gbatch_project<double, double, false>(hipStream_t, int, con
                                                            const int2*, int, int);
 template bool launch_gbatch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const GmresItem*,
                                                        const int2*, int, int);
-template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int);
-template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int);
+template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int, int);
+template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int, int);
+template bool launch_stencil_dual<float, float>(hipStream_t, const StencilArgs&, const float*, float*,
+                                                const SketchArgs&, float*, float*, const int*);
+template bool launch_stencil_dual<double, double>(hipStream_t, const StencilArgs&, const double*, double*,
+                                                  const SketchArgs&, double*, double*, const int*);
+template bool launch_stencil_dual<bf16, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
+                                               const SketchArgs&, float*, float*, const int*);
+template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const int2*,
+                                                       int, int);
+template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                         const int2*, int, int);
+template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const int2*,
+                                                      int, int);
+template bool launch_gbatch_project_ws<float, float, false>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                            const int2*, int, int);
+template bool launch_gbatch_project_ws<double, double, false>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                              const int2*, int, int);
+template bool launch_gbatch_project_ws<float, bf16, true>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                          const int2*, int, int);
 template bool launch_gbatch_finish<float>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
                                           const int2*, int);
 template bool launch_gbatch_finish<double>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,

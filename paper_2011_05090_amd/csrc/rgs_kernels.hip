@@ -2,12 +2,14 @@
 //
 // Randomized Gram-Schmidt, Algorithm 2 of Balabanov & Grigori (Sec. 2.3), one
 // column i at a time:
-//   step 1  p_i = Theta w_i                 -> k_sketch_cols + k_reduce (all columns at once)
+//   step 1  p_i = Theta w_i                 -> k_sketch_cols (SRHT) / k_gauss_cols (Gaussian)
+//                                              + k_reduce, all columns at once
 //   step 2  y = argmin ||S_{i-1} y - p_i||  -> k_ls1, k_ls2, k_ls3 (Householder, compact WY)
-//   step 3  q'_i = w_i - Q_{i-1} y          -> k_project (one coalesced pass over Q_{i-1})
+//   step 3  q'_i = w_i - Q_{i-1} y          -> k_project (rgs_project.hip): one coalesced pass
 //   step 4  s'_i = Theta q'_i               -> fused into k_project as per-block partials
+//                                              (k_gauss_cols on the stored column for small n)
 //   steps 5-6  r_ii = ||s'_i||, s_i = s'_i / r_ii, and the Householder append of s_i
-//                                           -> k_ap1 .. k_ap4
+//                                           -> k_qa .. k_qd
 //   step 7  q_i = q'_i / r_ii               -> done in the next column's k_project pass
 //                                              (k_scale_col for the last column)
 //
@@ -68,6 +70,62 @@ __global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, in
     }
 }
 
+// Gaussian sketch of ncols columns with every entry of Theta generated once
+// per workgroup and applied to C columns (instead of once per column).
+// Workgroup (g, jc, cc): sketch rows j = 256 jc + threadIdx.x, columns
+// [C cc, C cc + C), row sub-blocks sb = g, g + G, ... of kGSub rows.  The
+// sub-block of the C columns is staged in LDS column by column, so rows
+// 4q..4q+3 of a column are one vector read; z(j, 4q..4q+3) comes from one
+// Philox call.  Writes partials[(col * G + g) * k + j] (the k_reduce layout).
+// TX: element type of X (float, double or bf16); T: arithmetic type.
+constexpr int kGSub = 256;
+
+__device__ __forceinline__ float elem_real(float v) { return v; }
+__device__ __forceinline__ double elem_real(double v) { return v; }
+__device__ __forceinline__ float elem_real(bf16 v) { return bf16_to_float(v.bits); }
+
+template <typename TX, typename T, int C>
+__global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
+                                                    int G, SketchArgs sk, T* __restrict__ partials) {
+    __shared__ __attribute__((aligned(16))) T w[C][kGSub];
+    const int g = blockIdx.x;
+    const int j = blockIdx.y * kWG + threadIdx.x;
+    const int c0 = blockIdx.z * C;
+    const int nc = min(C, ncols - c0);
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    const int64_t nsub = (n + kGSub - 1) / kGSub;
+    for (int64_t sb = g; sb < nsub; sb += G) {
+        const int64_t r0 = sb * kGSub;
+        const int64_t l = r0 + threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            w[c][threadIdx.x] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+        __syncthreads();
+        if (j < sk.k) {
+            const int64_t rem = n - r0;
+            const int nq = rem >= kGSub ? kGSub / 4 : (int)((rem + 3) / 4);
+            const uint32_t q0 = (uint32_t)(r0 / 4);
+            for (int q = 0; q < nq; ++q) {
+                T z[4];
+                gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const T x0 = w[c][4 * q], x1 = w[c][4 * q + 1], x2 = w[c][4 * q + 2], x3 = w[c][4 * q + 3];
+                    acc[c] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (j < sk.k) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c < nc) partials[((int64_t)(c0 + c) * G + g) * sk.k + j] = acc[c];
+    }
+}
+
 // out[j + col*ldo] = scale * sum_{g=0}^{G-1} partials[(col*G + g)*k + j], in fp64 and
 // in a fixed order: 8 contiguous g-ranges summed by 8 threads, then combined in order.
 template <typename PT>
@@ -91,33 +149,6 @@ __global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials,
         for (int t = 0; t < 8; ++t) tot += red[t][jl];
         out[j + (int64_t)col * ldo] = tot * scale;
     }
-}
-
-template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
-__global__ __launch_bounds__(kProjWaves * kWave) void k_project(
-    const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n, int j, const TW* __restrict__ coef,
-    const double* __restrict__ invr, int normalize_last, int do_sketch, int vec_ok, SketchArgs sk,
-    PT* __restrict__ partials, const int* __restrict__ status) {
-    __shared__ TW lds[kProjWaves * kTile];
-    RGS_EXIT_IF_FAILED(status);
-    project_body<TW, TQ, PT, SK, DEFER>(w, Q, ldq, n, j, coef, invr, normalize_last, do_sketch, vec_ok, sk,
-                                        partials, blockIdx.x, lds);
-}
-
-// Batched: workgroup -> (factorisation, row block) through map; column i of
-// every factorisation listed in the map.
-template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
-__global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem* __restrict__ items,
-                                                                 const int2* __restrict__ map, int i) {
-    __shared__ TW lds[kProjWaves * kTile];
-    const int2 bm = map[blockIdx.x];
-    const BatchItem& it = items[bm.x];
-    RGS_EXIT_IF_FAILED(it.sa.status);
-    const TW* W = static_cast<const TW*>(it.W);
-    project_body<TW, TQ, PT, SK, DEFER>(W + (int64_t)i * it.ldw, static_cast<TQ*>(it.Q), it.ldq, it.n, i,
-                                        static_cast<const TW*>(it.coef), i > 0 ? it.sa.invr + (i - 1) : nullptr,
-                                        (!DEFER && i > 0) ? 1 : 0, (DEFER || i > 0) ? 1 : 0, it.vec_ok, it.sk,
-                                        static_cast<PT*>(it.part), bm.y, lds);
 }
 
 // Final step 7 for the last column: q = q' / r (fp64 reciprocal, rounded to T).
@@ -202,8 +233,8 @@ template <typename PT>
 __global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int G, double scale,
                                             const double* __restrict__ src, int k, int i,
                                             const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                            double* __restrict__ pd) {
-    qa_body<PT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x);
+                                            double* __restrict__ pd, const double* __restrict__ scale2) {
+    qa_body<PT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2);
 }
 
 __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
@@ -409,34 +440,26 @@ bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int 
     return true;
 }
 
+template <typename TX, typename T>
+bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
+                       T* partials) {
+    const unsigned jc = nblocks(sk.k, kWG);
+    if (ncols == 1) {
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, 1>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
+                           partials);
+    } else {
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, kGaussCols>), dim3(G, jc, nblocks(ncols, kGaussCols)), dim3(kWG), 0,
+                           st, X, ldx, n, ncols, G, sk, partials);
+    }
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 template <typename PT>
 bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
                    int64_t ldo) {
     hipLaunchKernelGGL(k_reduce<PT>, dim3(nblocks(k, 32), ncols), dim3(kWG), 0, st, partials, G, k, scale,
                        out, ldo);
-    RGS_LAUNCH_CHECK();
-    return true;
-}
-
-template <typename TW, typename TQ, bool DEFER>
-bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
-                    const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
-                    TW* partials, const int* status) {
-    const unsigned nblk = nblocks(n, kProjRows);
-    const dim3 thr(kProjWaves * kWave);
-    switch (sk.sketch) {
-        case SK_SRHT:
-            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
-                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
-            break;
-        case SK_GAUSS:
-            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
-                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
-            break;
-        default:
-            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_IDENT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
-                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
-    }
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -472,10 +495,10 @@ bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, doubl
 
 template <typename T, typename PT>
 bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
-                        double* R, int64_t ldr, T* coef, const double* cscale) {
+                        double* R, int64_t ldr, T* coef, const double* cscale, const double* scale2) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, (const double*)nullptr, a.k, i,
-                       a.Wr, a.mcap, a.pbuf, a.pd);
+                       a.Wr, a.mcap, a.pbuf, a.pd, scale2);
     RGS_LAUNCH_CHECK();
     const unsigned nrb = nblocks(i, 64);
     hipLaunchKernelGGL(k_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, a.pbuf, a.k, i, nsl, a.Vc,
@@ -493,7 +516,7 @@ bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G
                    const double* pnext, T* coef, const double* cscale) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap, a.sp,
-                       a.pd);
+                       a.pd, (const double*)nullptr);
     RGS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_qb, dim3(nsl), dim3(kGW), (i + 1) * sizeof(double), st, a.k, i, nsl, a.sp, a.Vc, a.mcap,
                        a.pd, a.u, a.pd2, S, lds, R, ldr, a.rr, a.invr, a.pnorm, a.status);
@@ -517,18 +540,6 @@ bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G
 bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64_t max_m2) {
     hipLaunchKernelGGL(kb_init, dim3(nblocks(std::max<int64_t>(max_m2, 4), 256), nitems), dim3(256), 0, st, items,
                        nitems);
-    RGS_LAUNCH_CHECK();
-    return true;
-}
-
-template <typename TW, typename TQ, bool DEFER>
-bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const int2* map, int count, int i) {
-    if (count == 0) return true;
-    const dim3 thr(kProjWaves * kWave);
-    if (sketch == SK_SRHT)
-        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(count), thr, 0, st, items, map, i);
-    else
-        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(count), thr, 0, st, items, map, i);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -602,31 +613,26 @@ template bool launch_sketch_cols<double, double>(hipStream_t, const double*, int
                                                  const SketchArgs&, double*);
 template bool launch_reduce<float>(hipStream_t, const float*, int, int, int, double, double*, int64_t);
 template bool launch_reduce<double>(hipStream_t, const double*, int, int, int, double, double*, int64_t);
-template bool launch_project<float, float, false>(hipStream_t, const float*, float*, int64_t, int64_t, int,
-                                                  const float*, const double*, int, int, int, const SketchArgs&,
-                                                  float*, const int*);
-template bool launch_project<double, double, false>(hipStream_t, const double*, double*, int64_t, int64_t, int,
-                                                    const double*, const double*, int, int, int,
-                                                    const SketchArgs&, double*, const int*);
-template bool launch_project<float, bf16, true>(hipStream_t, const float*, bf16*, int64_t, int64_t, int,
-                                                const float*, const double*, int, int, int, const SketchArgs&,
-                                                float*, const int*);
 template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double*, const int*);
 template bool launch_scale_col<double>(hipStream_t, double*, int64_t, const double*, const int*);
 template bool launch_ls<float>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, float*);
 template bool launch_ls<double>(hipStream_t, const SpaceArgs&, const double*, int, double*, int64_t, double*);
 template bool launch_ls_partials<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, int,
-                                               double*, int64_t, float*, const double*);
+                                               double*, int64_t, float*, const double*, const double*);
 template bool launch_ls_partials<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double, int,
-                                                 double*, int64_t, double*, const double*);
+                                                 double*, int64_t, double*, const double*, const double*);
 template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, const double*,
                                           int, double*, int64_t, double*, int64_t, const double*, float*,
                                           const double*);
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
                                             double*, const double*);
-template bool launch_batch_project<float, float, false>(hipStream_t, int, const BatchItem*, const int2*, int, int);
-template bool launch_batch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const int2*, int, int);
+template bool launch_gauss_cols<float, float>(hipStream_t, const float*, int64_t, int64_t, int, int,
+                                              const SketchArgs&, float*);
+template bool launch_gauss_cols<double, double>(hipStream_t, const double*, int64_t, int64_t, int, int,
+                                                const SketchArgs&, double*);
+template bool launch_gauss_cols<bf16, float>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
+                                             const SketchArgs&, float*);
 template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,
                                          const int2*, int, int);
 template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,

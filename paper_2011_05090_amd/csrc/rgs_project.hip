@@ -1,0 +1,127 @@
+// The fused projection + sketch kernel of librgs for gfx950 (MI355X): steps
+// 3, 4 and 7 of Algorithm 2 (Sec. 2.3 of Balabanov & Grigori) in one
+// coalesced pass over the basis, for one factorisation (k_project) or for
+// every factorisation of a batched call at the same column (kb_project).  It
+// is the kernel that bounds the factorisation (one read of Q_{i-1} per
+// column), so it sits in a translation unit of its own.
+
+#include "rgs_internal.hpp"
+#include "rgs_proj.hpp"
+
+namespace rgs {
+
+template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void k_project(
+    const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n, int j, const TW* __restrict__ coef,
+    const double* __restrict__ invr, int normalize_last, int do_sketch, int vec_ok, SketchArgs sk,
+    PT* __restrict__ partials, const int* __restrict__ status) {
+    __shared__ TW lds[kProjWaves * kTile];
+    RGS_EXIT_IF_FAILED(status);
+    project_body<TW, TQ, PT, SK, DEFER>(w, Q, ldq, n, j, coef, invr, normalize_last, do_sketch, vec_ok, sk,
+                                        partials, blockIdx.x, lds);
+}
+
+// The same pass with w_i scaled by wscale[0] on load (fused-sketch GMRES step;
+// the sketch of q'_i is taken elsewhere, so none here).
+template <typename TW, typename TQ, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void k_project_ws(
+    const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n, int j, const TW* __restrict__ coef,
+    const double* __restrict__ invr, int normalize_last, int vec_ok, const double* __restrict__ wscale,
+    const int* __restrict__ status) {
+    __shared__ TW lds[kProjWaves * kTile];
+    RGS_EXIT_IF_FAILED(status);
+    SketchArgs none{};
+    project_body<TW, TQ, TW, SK_GAUSS, DEFER, true>(w, Q, ldq, n, j, coef, invr, normalize_last, 0, vec_ok, none,
+                                                    nullptr, blockIdx.x, lds, wscale);
+}
+
+// Batched: workgroup -> (factorisation, row block) through map; column i of
+// every factorisation listed in the map.
+template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
+__global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem* __restrict__ items,
+                                                                 const int2* __restrict__ map, int i) {
+    __shared__ TW lds[kProjWaves * kTile];
+    const int2 bm = map[blockIdx.x];
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_FAILED(it.sa.status);
+    const TW* W = static_cast<const TW*>(it.W);
+    project_body<TW, TQ, PT, SK, DEFER>(W + (int64_t)i * it.ldw, static_cast<TQ*>(it.Q), it.ldq, it.n, i,
+                                        static_cast<const TW*>(it.coef), i > 0 ? it.sa.invr + (i - 1) : nullptr,
+                                        (!DEFER && i > 0) ? 1 : 0, (DEFER || i > 0) ? 1 : 0, it.vec_ok, it.sk,
+                                        static_cast<PT*>(it.part), bm.y, lds);
+}
+
+#define RGS_LAUNCH_CHECK()                                   \
+    do {                                                     \
+        if (hipGetLastError() != hipSuccess) return false;   \
+    } while (0)
+
+static inline unsigned nblocks(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
+
+template <typename TW, typename TQ, bool DEFER>
+bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
+                    const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
+                    TW* partials, const int* status) {
+    const unsigned nblk = nblocks(n, kProjRows);
+    const dim3 thr(kProjWaves * kWave);
+    switch (sk.sketch) {
+        case SK_SRHT:
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
+            break;
+        case SK_GAUSS:
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
+            break;
+        default:
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_IDENT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
+    }
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TW, typename TQ, bool DEFER>
+bool launch_project_ws(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
+                       const double* invr, int normalize_last, int vec_ok, const double* wscale, const int* status) {
+    hipLaunchKernelGGL((k_project_ws<TW, TQ, DEFER>), dim3(nblocks(n, kProjRows)), dim3(kProjWaves * kWave), 0, st,
+                       w, Q, ldq, n, j, coef, invr, normalize_last, vec_ok, wscale, status);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TW, typename TQ, bool DEFER>
+bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const int2* map, int count, int i) {
+    if (count == 0) return true;
+    const dim3 thr(kProjWaves * kWave);
+    if (sketch == SK_SRHT)
+        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(count), thr, 0, st, items, map, i);
+    else
+        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(count), thr, 0, st, items, map, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+// explicit instantiations
+template bool launch_project_ws<float, float, false>(hipStream_t, const float*, float*, int64_t, int64_t, int,
+                                                     const float*, const double*, int, int, const double*,
+                                                     const int*);
+template bool launch_project_ws<double, double, false>(hipStream_t, const double*, double*, int64_t, int64_t, int,
+                                                       const double*, const double*, int, int, const double*,
+                                                       const int*);
+template bool launch_project_ws<float, bf16, true>(hipStream_t, const float*, bf16*, int64_t, int64_t, int,
+                                                   const float*, const double*, int, int, const double*,
+                                                   const int*);
+template bool launch_project<float, float, false>(hipStream_t, const float*, float*, int64_t, int64_t, int,
+                                                  const float*, const double*, int, int, int, const SketchArgs&,
+                                                  float*, const int*);
+template bool launch_project<double, double, false>(hipStream_t, const double*, double*, int64_t, int64_t, int,
+                                                    const double*, const double*, int, int, int,
+                                                    const SketchArgs&, double*, const int*);
+template bool launch_project<float, bf16, true>(hipStream_t, const float*, bf16*, int64_t, int64_t, int,
+                                                const float*, const double*, int, int, int, const SketchArgs&,
+                                                float*, const int*);
+template bool launch_batch_project<float, float, false>(hipStream_t, int, const BatchItem*, const int2*, int, int);
+template bool launch_batch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const int2*, int, int);
+
+}  // namespace rgs

@@ -1,91 +1,15 @@
 // Device bodies of the RGS column step shared by the QR kernels
 // (rgs_kernels.hip) and the randomized GMRES kernels (rgs_gmres.hip): the
-// fused projection + sketch pass over a row block, and the fp64 sketch-space
-// work of one column (least squares on the compact-WY Householder
+// fp64 sketch-space work of one column (least squares on the compact-WY Householder
 // factorisation of S, r_ii, and the append of s_i).  Each __global__ wrapper
 // passes its block index; single-factorisation and batched wrappers call the
 // same bodies, so both produce the same bits.
 #pragma once
 
-#include "rgs_block.hpp"
-#include "rgs_device.hpp"
 #include "rgs_internal.hpp"
+#include "rgs_proj.hpp"
 
 namespace rgs {
-
-// Workgroup-uniform early exit once an earlier step has flagged a breakdown:
-// one thread reads the status word, the whole workgroup takes the same branch.
-#define RGS_EXIT_IF_FAILED(status)                      \
-    do {                                                \
-        __shared__ int rgs_stop_;                       \
-        if (threadIdx.x == 0) rgs_stop_ = (status)[0] | (status)[2]; \
-        __syncthreads();                                \
-        if (rgs_stop_ != 0) return;                     \
-    } while (0)
-
-// Step 3 (+ step 4 partials, + step 7 of the previous column), for row block
-// blk of kProjWaves * 1024 rows:
-//   q'_i = w_i - sum_{c<j} coef[c] q_c        (working precision TW, fma chain in c order)
-// If normalize_last, column j-1 still holds q'_{i-1} and is first scaled to
-// q_{i-1} = q'_{i-1} / r_{i-1,i-1} (fp64 multiply by the reciprocal, rounded
-// to the storage type) and written back.  q'_i is stored in column j, then the
-// block's sketch partials of the stored q'_i are written (or q'_i itself for
-// Theta = I).  DEFER (bf16 storage): columns stay unnormalised, the
-// coefficients already carry 1/r_cc, and the sketch is taken of the rounded,
-// stored q'_i.
-template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
-__device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n,
-                                             int j, const TW* __restrict__ coef, const double* __restrict__ invr,
-                                             int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
-                                             PT* __restrict__ partials, int64_t blk, TW* __restrict__ lds) {
-    constexpr int NW = kProjWaves;
-    int64_t row0[4];
-    lane_rows<NW>(blk, row0);
-    const bool full = vec_ok && (blk + 1) * (NW * kTile) <= n;
-    TW v[16];
-    load16(w, row0, n, full, v);
-    const int jl = (!DEFER && normalize_last) ? j - 1 : j;
-    for (int c = 0; c < jl; ++c) {
-        const TW a = coef[c];
-        TW q[16];
-        load16(Q + (int64_t)c * ldq, row0, n, full, q);
-#pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
-    }
-    if constexpr (!DEFER) {
-        if (normalize_last) {
-            const int c = j - 1;
-            const TW a = coef[c];
-            const double ir = invr[0];
-            TW q[16];
-            TQ* qc = Q + (int64_t)c * ldq;
-            load16(qc, row0, n, full, q);
-#pragma unroll
-            for (int t = 0; t < 16; ++t) q[t] = (TW)((double)q[t] * ir);
-            store16(qc, row0, n, full, q);
-#pragma unroll
-            for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
-        }
-    }
-    store16(Q + (int64_t)j * ldq, row0, n, full, v);   // bf16: v becomes the stored value
-    if (!do_sketch) return;
-    if constexpr (SK == SK_IDENT) {
-        store16(partials, row0, n, false, v);   // Theta = I: the "sketch" is q' itself
-    } else {
-        PT acc[kKptMax];
-#pragma unroll
-        for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
-        block_sketch<TW, PT, SK, NW>(v, blk, n, sk, acc, lds);
-        PT* out = partials + blk * sk.k;
-        constexpr int NT = NW * kWave;
-        const int kpt = (sk.k + NT - 1) / NT;
-#pragma unroll
-        for (int u = 0; u < kKptMax; ++u) {
-            const int jj = threadIdx.x + NT * u;
-            if (u < kpt && jj < sk.k) out[jj] = acc[u];
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Sketch-space kernels (fp64).  i = 0-based index of the current column;
@@ -216,13 +140,15 @@ __device__ __forceinline__ void ls3_body(int nr, int col, const double* __restri
 }
 
 // Column step A: s' = scale * (sum of the projection kernel's block partials)
-// for slice bid (or a copy of src), stored in sp; per-slice partials of
-// c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
+// (times scale2[0] when given: the 1/r_ii of an Arnoldi vector sketched before
+// its normalisation was known) for slice bid (or a copy of src), stored in sp;
+// per-slice partials of c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
 template <typename PT>
 __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, double scale,
                                         const double* __restrict__ src, int k, int i,
                                         const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                        double* __restrict__ pd, int bid) {
+                                        double* __restrict__ pd, int bid,
+                                        const double* __restrict__ scale2 = nullptr) {
     __shared__ double red[kGQ][64];
     __shared__ double xs[kSlice];
     const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -249,7 +175,8 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
         red[q][rl] = acc;
         __syncthreads();
         if (q == 0) {
-            const double val = (r < k) ? combine16(red, rl) * scale : 0.0;
+            double val = (r < k) ? combine16(red, rl) * scale : 0.0;
+            if (scale2) val *= scale2[0];
             xs[rl] = val;
             if (r < k) sp[r] = val;
         }

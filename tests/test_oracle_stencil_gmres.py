@@ -118,3 +118,36 @@ def test_convdiff_converges_restarted(precision):
     r = b - applyA(out["x"], np.float64)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
     assert out["cycles"] >= 2                  # restarts really happened
+
+
+def test_bf16_model_without_rounding_is_the_fp32_model(monkeypatch):
+    """The bf16 basis model keeps columns unnormalised and folds 1/r_cc into the
+    projection coefficients, the mat-vec input and the x update.  With the bf16
+    rounding replaced by the identity on float32 it must reproduce the fp32
+    model up to rounding (a wrong or missing scale anywhere fails this)."""
+    N, Pe = 9, 30.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=6)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    mk = lambda c: sketch.SRHT(n, 64, seed=42, sketch_id=2 + c)
+    ref = gmres.rgmres(applyA, b, mk, restart=15, tol=1e-6, precision="fp32")
+    monkeypatch.setattr(gmres, "bf16_round", lambda x: np.asarray(x, dtype=np.float32).copy())
+    out = gmres.rgmres(applyA, b, mk, restart=15, tol=1e-6, precision="bf16q")
+    assert out["iters"] == ref["iters"] and out["cycles"] == ref["cycles"]
+    np.testing.assert_allclose(out["hist"], ref["hist"], rtol=1e-4)
+    assert np.linalg.norm(out["x"] - ref["x"]) <= 1e-5 * np.linalg.norm(ref["x"])
+
+
+def test_bf16_model_converges_with_rounding():
+    """With the bf16 rounding on, restarts still drive the fp64 true residual to tol."""
+    N, Pe = 9, 30.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=6)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    out = gmres.rgmres(applyA, b, lambda c: sketch.SRHT(n, 64, seed=42, sketch_id=2 + c),
+                       restart=15, tol=1e-6, precision="bf16q")
+    assert out["converged"]
+    r = b - applyA(out["x"], np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
