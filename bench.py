@@ -331,6 +331,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched and small fp64 QR legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--only", choices=["small", "batched-qr", "batched-gmres", "gmres"],
+                    help="profiling aid: run only this leg and print its JSON (not the benchmark line)")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
                          "databases (no GPU needed) and exit")
@@ -348,6 +350,14 @@ def main():
     import synth
     import paper_2011_05090_amd as rgs
 
+    if args.only:
+        h = rgs.Handle(0)
+        leg = {"small": small_fp64_leg, "batched-qr": batched_qr_leg, "batched-gmres": batched_gmres_leg,
+               "gmres": gmres_leg}[args.only]
+        res = leg(rgs, torch, synth, h)
+        h.close()
+        print(json.dumps({"only": args.only, "result": res}), flush=True)
+        return
     n, m, k = args.n, args.m, args.k
     dev = torch.device("cuda:0")
     log("generating W (%d x %d, sigma 1..1e-8) on the device" % (n, m))

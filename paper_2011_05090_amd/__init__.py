@@ -137,10 +137,13 @@ def _check(status, where, allow=()):
     return status
 
 
-def colmajor(n, m, dtype, device="cuda"):
-    """Uninitialised column-major n x m tensor (shape (n, m), stride (1, n))."""
+def colmajor(n, m, dtype, device="cuda", pad=True):
+    """Uninitialised column-major n x m tensor (shape (n, m), stride (1, ld)).
+    With pad, ld = n rounded up to a multiple of 4: every column then starts
+    16-byte aligned (8-byte for bf16), which the library's vectorised loads need."""
     import torch
-    return torch.empty((m, n), dtype=dtype, device=device).t()
+    ld = (n + 3) // 4 * 4 if pad else n
+    return torch.empty((m, ld), dtype=dtype, device=device).t()[:n]
 
 
 def _ld(t, rows):

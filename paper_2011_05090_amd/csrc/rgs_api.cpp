@@ -405,7 +405,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T));
     Carver c;
     c.off = pl.total;
-    const size_t oQ = c.take<TQ>((size_t)n * mcap), oW = c.take<T>(n), oR = c.take<double>(mcap * mcap);
+    const int64_t ldq = (n + 3) / 4 * 4;   // 16-byte aligned columns: every full block takes vector loads
+    const size_t oQ = c.take<TQ>((size_t)ldq * mcap), oW = c.take<T>(n), oR = c.take<double>(mcap * mcap);
     const size_t oS = c.take<double>(k * mcap), oHr = c.take<double>(mcap * mcap), ocs = c.take<double>(mcap);
     const size_t osn = c.take<double>(mcap), ogv = c.take<double>(mcap + 1), oy = c.take<double>(mcap);
     const size_t ohist = c.take<double>(mcap), oused = c.take<int>(4), or_ = c.take<double>(n);
@@ -438,7 +439,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     hipStream_t s = h->stream;
     const double scale = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)k);
     const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nproj;
-    const bool vec_ok = (n % 4 == 0);
+    const bool vec_ok = true;   // ldq % 4 == 0 and the arena is 256-byte aligned
 
     // x0 = 0, r0 = b, ||b||
     if (hipMemsetAsync(x, 0, n * sizeof(double), s) != hipSuccess) return RGS_EDEVICE;
@@ -462,7 +463,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
         // RGS step 1 of Algorithm 3: w_1 = r_0
         if (!launch_cast<T>(s, r, wbuf, n)) return RGS_EDEVICE;
-        if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, 0, coef, nullptr, 0, dual ? 0 : 1, vec_ok ? 1 : 0, sk,
+        if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, ldq, n, 0, coef, nullptr, 0, dual ? 0 : 1, vec_ok ? 1 : 0, sk,
                                           part, sa.status))
             return RGS_EDEVICE;
         // dual: t_1 = A q'_0 with the sketches of q'_0 (part) and t_1 (part2)
@@ -478,20 +479,20 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
                 if (!launch_ls_partials<T, T>(s, sa, part2, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr,
                                               sa.invr + (i - 1)))
                     return RGS_EDEVICE;
-                if (!launch_project_ws<T, TQ, DEFER>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1,
+                if (!launch_project_ws<T, TQ, DEFER>(s, wbuf, Q, ldq, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1,
                                                      vec_ok ? 1 : 0, sa.invr + (i - 1), sa.status))
                     return RGS_EDEVICE;
-                if (!launch_stencil_dual<TQ, T>(s, A, Q + i * n, wbuf, sk, part, part2, sa.status))
+                if (!launch_stencil_dual<TQ, T>(s, A, Q + i * ldq, wbuf, sk, part, part2, sa.status))
                     return RGS_EDEVICE;
             } else {
                 // w_i = A q_{i-1}, sketched: p_i (step 3 of Algorithm 3, step 1 of Algorithm 2)
-                if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * n, sa.invr + (i - 1), wbuf, 1, sk, part,
+                if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * ldq, sa.invr + (i - 1), wbuf, 1, sk, part,
                                                   sa.status))
                     return RGS_EDEVICE;
                 if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr,
                                               nullptr))
                     return RGS_EDEVICE;
-                if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, n, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
+                if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, ldq, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
                                                   vec_ok ? 1 : 0, sk, part, sa.status))
                     return RGS_EDEVICE;
             }
@@ -501,7 +502,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
                                (int)steps))
                 return RGS_EDEVICE;
         }
-        if (!launch_update_x<TQ>(s, Hr, (int)mcap, gv, used, y, x, Q, n, n, DEFER ? sa.invr : nullptr))
+        if (!launch_update_x<TQ>(s, Hr, (int)mcap, gv, used, y, x, Q, ldq, n, DEFER ? sa.invr : nullptr))
             return RGS_EDEVICE;
         if (!launch_residual(s, A, b, x, r, rpart, norm)) return RGS_EDEVICE;
         int stat[4] = {0, 0, 0, 0};
@@ -846,7 +847,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     for (int64_t b = 0; b < batch; ++b) {
         const int64_t n = ns[b], nproj = (n + kProjRows - 1) / kProjRows;
         Off& o = off[b];
-        o.Q = c.take<TQ>((size_t)n * mcap);
+        o.Q = c.take<TQ>((size_t)((n + 3) / 4 * 4) * mcap);
         o.w = c.take<T>(n);
         o.r = c.take<double>(n);
         o.rpart = c.take<double>((n + 255) / 256);
@@ -906,7 +907,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         x.nproj = (int)((n + kProjRows - 1) / kProjRows);
         x.nsl = (int)nsl;
         x.Q = A + o.Q;
-        x.ldq = n;
+        x.ldq = (n + 3) / 4 * 4;   // 16-byte aligned columns
         x.R = reinterpret_cast<double*>(A + o.R);
         x.ldr = mcap;
         x.S = reinterpret_cast<double*>(A + o.S);
@@ -916,7 +917,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         x.part2 = A + o.part2;
         x.coef = A + o.coef;
         x.sketch_scale = 1.0 / std::sqrt((double)k);
-        x.vec_ok = (n % 4 == 0) ? 1 : 0;
+        x.vec_ok = 1;
         x.defer = DEFER ? 1 : 0;
         SpaceArgs& a = x.sa;
         a.k = (int)k;
