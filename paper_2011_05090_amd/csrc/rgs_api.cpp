@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -558,97 +559,116 @@ bool valid_item(const rgs_qr_item& it, int sk_kind) {
     return true;
 }
 
+// Prefix sums (count + 1 entries) of per-position block counts.
+template <typename F>
+std::vector<int64_t> prefix_of(int64_t count, F blocks) {
+    std::vector<int64_t> p((size_t)count + 1, 0);
+    for (int64_t q = 0; q < count; ++q) p[q + 1] = p[q] + blocks(q);
+    return p;
+}
+
+// Runs f(b) for b in [0, count) on a few host threads (independent items).
+template <typename F>
+void parallel_for(int64_t count, F f) {
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(16, std::min<int64_t>(count / 64 + 1,
+                                                                 (int64_t)std::thread::hardware_concurrency())));
+    if (nt <= 1) {
+        for (int64_t b = 0; b < count; ++b) f(b);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int64_t b = t; b < count; b += nt) f(b);
+        });
+    for (auto& x : th) x.join();
+}
+
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
                           uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     typedef float T;
     hipStream_t s = h->stream;
-    std::vector<BatchItem> bi((size_t)batch);
-    std::vector<size_t> o_signs(batch), o_part(batch), o_P(batch), o_Vc(batch), o_Vr(batch), o_Wc(batch),
-        o_Wr(batch), o_X(batch), o_sp(batch), o_u(batch), o_v(batch), o_pbuf(batch), o_uh(batch), o_pd(batch),
-        o_pdb(batch), o_pd2(batch), o_rr(batch), o_invr(batch), o_pnorm(batch), o_tau(batch), o_beta(batch),
-        o_coef(batch);
+    // Launch order: by m descending, so the factorisations that still have a
+    // column i are a prefix of the order and every launch map is implicit.
+    std::vector<int64_t> order((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return items[a].m > items[b].m; });
+    const int64_t max_m = items[order[0]].m;
+    std::vector<int> active((size_t)max_m + 1, 0);   // active[i]: factorisations with a column i
+    for (int64_t i = 0; i <= max_m; ++i)
+        active[i] = (int)(std::upper_bound(order.begin(), order.end(), i,
+                                           [&](int64_t v, int64_t b) { return v >= items[b].m; }) -
+                          order.begin());
+    auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[order[q]]; };
+    auto gp_of = [&](int64_t q) -> int64_t {
+        const int64_t n = it_of(q).n;
+        return std::min<int64_t>(sk_kind == SK_GAUSS ? (n + 255) / 256 : (n + kBlock - 1) / kBlock, 16);
+    };
+    const std::vector<int64_t> pre_proj = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + kProjRows - 1) / kProjRows; });
+    const std::vector<int64_t> pre_sl = prefix_of(batch, [&](int64_t q) { return (it_of(q).k + kSlice - 1) / kSlice; });
+    const std::vector<int64_t> pre_row = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + 255) / 256; });
+    const std::vector<int64_t> pre_sign = prefix_of(batch, [&](int64_t q) { return ((it_of(q).n + 31) / 32 + 1023) / 1024; });
+    const std::vector<int64_t> pre_part = prefix_of(batch, [&](int64_t q) {
+        const rgs_qr_item& it = it_of(q);
+        return sk_kind == SK_GAUSS ? gp_of(q) * ((it.k + kWG - 1) / kWG) * ((it.m + kGaussCols - 1) / kGaussCols)
+                                   : gp_of(q) * it.m;
+    });
+    const std::vector<int64_t> pre_red = prefix_of(batch, [&](int64_t q) { return ((it_of(q).k + 31) / 32) * it_of(q).m; });
+
+    struct Off {
+        size_t signs, part, partP, P, Vc, Vr, Wc, Wr, X, sp, u, v, pbuf, uh, pd, pdb, pd2, rr, invr, pnorm, tau, beta,
+            coef;
+    };
+    std::vector<Off> off((size_t)batch);
     Carver c;
-    int64_t max_m = 0, ktot = 0;
-    size_t max_partP = 0;
-    for (int64_t b = 0; b < batch; ++b) {
-        const rgs_qr_item& it = items[b];
+    int64_t ktot = 0;
+    for (int64_t q = 0; q < batch; ++q) {
+        const rgs_qr_item& it = it_of(q);
         const int64_t n = it.n, m = it.m, k = it.k;
         const int64_t nproj = (n + kProjRows - 1) / kProjRows, nsl = (k + kSlice - 1) / kSlice;
-        max_m = std::max(max_m, m);
+        Off& o = off[q];
+        o.signs = c.take<uint32_t>(sk_kind == SK_SRHT ? (n + 31) / 32 + 4 : 1);
+        o.part = c.take<T>(nproj * k);
+        o.partP = c.take<T>(gp_of(q) * k * m);
+        o.P = c.take<double>(k * m);
+        o.Vc = c.take<double>(k * m);
+        o.Vr = c.take<double>(k * m);
+        o.Wc = c.take<double>(k * m);
+        o.Wr = c.take<double>(k * m);
+        o.X = c.take<double>(m * m);
+        o.sp = c.take<double>(k);
+        o.u = c.take<double>(k);
+        o.v = c.take<double>(k);
+        o.pbuf = c.take<double>(k);
+        o.uh = c.take<double>(m + 1);
+        o.pd = c.take<double>(nsl * (m + 1));
+        o.pdb = c.take<double>(nsl * (m + 2));
+        o.pd2 = c.take<double>(nsl);
+        o.rr = c.take<double>(m);
+        o.invr = c.take<double>(m);
+        o.pnorm = c.take<double>(m);
+        o.tau = c.take<double>(m);
+        o.beta = c.take<double>(m);
+        o.coef = c.take<T>(m);
         ktot += k;
-        const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T));
-        max_partP = std::max(max_partP, (size_t)pl.G_P * k * sizeof(T) * pl.cc);
-        o_signs[b] = c.take<uint32_t>((n + 31) / 32 + 4);
-        o_part[b] = c.take<T>(nproj * k);
-        o_P[b] = c.take<double>(k * m);
-        o_Vc[b] = c.take<double>(k * m);
-        o_Vr[b] = c.take<double>(k * m);
-        o_Wc[b] = c.take<double>(k * m);
-        o_Wr[b] = c.take<double>(k * m);
-        o_X[b] = c.take<double>(m * m);
-        o_sp[b] = c.take<double>(k);
-        o_u[b] = c.take<double>(k);
-        o_v[b] = c.take<double>(k);
-        o_pbuf[b] = c.take<double>(k);
-        o_uh[b] = c.take<double>(m + 1);
-        o_pd[b] = c.take<double>(nsl * (m + 1));
-        o_pdb[b] = c.take<double>(nsl * (m + 2));
-        o_pd2[b] = c.take<double>(nsl);
-        o_rr[b] = c.take<double>(m);
-        o_invr[b] = c.take<double>(m);
-        o_pnorm[b] = c.take<double>(m);
-        o_tau[b] = c.take<double>(m);
-        o_beta[b] = c.take<double>(m);
-        o_coef[b] = c.take<T>(m);
     }
-    const size_t o_rows = c.take<int>(ktot), o_status = c.take<int>(4 * batch), o_items = c.take<BatchItem>(batch);
-    const size_t o_partP = c.take<char>(max_partP);
-    // launch maps, column by column
-    std::vector<int2> maps;
-    struct ColMaps {
-        size_t proj, sl, qd, ls;
-        int nproj, nsl, nqd, nls;
-    };
-    std::vector<ColMaps> cm((size_t)max_m);
-    for (int64_t i = 0; i < max_m; ++i) {
-        ColMaps& x = cm[i];
-        const int64_t rb = (i + 1 + 63) / 64;
-        x.proj = maps.size();
-        for (int64_t b = 0; b < batch; ++b)
-            if (items[b].m > i)
-                for (int64_t g = 0; g < (items[b].n + kProjRows - 1) / kProjRows; ++g) maps.push_back({(int)b, (int)g});
-        x.nproj = (int)(maps.size() - x.proj);
-        x.sl = maps.size();
-        for (int64_t b = 0; b < batch; ++b)
-            if (items[b].m > i)
-                for (int64_t g = 0; g < (items[b].k + kSlice - 1) / kSlice; ++g) maps.push_back({(int)b, (int)g});
-        x.nsl = (int)(maps.size() - x.sl);
-        x.qd = maps.size();
-        for (int64_t b = 0; b < batch; ++b)
-            if (items[b].m > i)
-                for (int64_t g = 0; g < (items[b].k + kSlice - 1) / kSlice + rb; ++g) maps.push_back({(int)b, (int)g});
-        x.nqd = (int)(maps.size() - x.qd);
-        x.ls = maps.size();
-        for (int64_t b = 0; b < batch; ++b)
-            if (items[b].m > i + 1)
-                for (int64_t g = 0; g < rb; ++g) maps.push_back({(int)b, (int)g});
-        x.nls = (int)(maps.size() - x.ls);
-    }
-    const size_t scale_at = maps.size();
-    for (int64_t b = 0; b < batch; ++b)
-        for (int64_t g = 0; g < (items[b].n + 255) / 256; ++g) maps.push_back({(int)b, (int)g});
-    const int nscale = (int)(maps.size() - scale_at);
-    const size_t o_maps = c.take<int2>(maps.size());
+    const size_t o_rows = c.take<int>(sk_kind == SK_SRHT ? ktot : 1), o_status = c.take<int>(4 * batch);
+    const size_t o_items = c.take<BatchItem>(batch);
+    const size_t o_pre = c.take<int64_t>(6 * (batch + 1));
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* A = h->arena;
-    std::vector<int> rows_all((size_t)ktot);
-    int64_t rpos = 0;
-    for (int64_t b = 0; b < batch; ++b) {
-        const rgs_qr_item& it = items[b];
-        BatchItem& x = bi[b];
+    std::vector<BatchItem> bi((size_t)batch);
+    std::vector<int64_t> rpos((size_t)batch + 1, 0);
+    for (int64_t q = 0; q < batch; ++q) rpos[q + 1] = rpos[q] + it_of(q).k;
+    std::vector<int> rows_all(sk_kind == SK_SRHT ? (size_t)ktot : 0);
+    parallel_for(batch, [&](int64_t q) {
+        const rgs_qr_item& it = it_of(q);
+        const Off& o = off[q];
+        BatchItem& x = bi[q];
+        x = BatchItem{};
         x.n = it.n;
         x.m = (int)it.m;
         x.k = (int)it.k;
@@ -662,9 +682,11 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         x.ldr = it.ldr;
         x.S = it.S;
         x.lds = it.lds;
-        x.P = reinterpret_cast<double*>(A + o_P[b]);
-        x.part = A + o_part[b];
-        x.coef = A + o_coef[b];
+        x.P = reinterpret_cast<double*>(A + o.P);
+        x.partP = A + o.partP;
+        x.G_P = (int)gp_of(q);
+        x.part = A + o.part;
+        x.coef = A + o.coef;
         x.sketch_scale = 1.0 / std::sqrt((double)it.k);
         x.vec_ok = (it.ldq % 4 == 0) && (it.ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.Q) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(it.W) & 15) == 0);
@@ -672,78 +694,88 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         SpaceArgs& a = x.sa;
         a.k = (int)it.k;
         a.mcap = (int)it.m;
-        a.Vc = reinterpret_cast<double*>(A + o_Vc[b]);
-        a.Vr = reinterpret_cast<double*>(A + o_Vr[b]);
-        a.Wc = reinterpret_cast<double*>(A + o_Wc[b]);
-        a.Wr = reinterpret_cast<double*>(A + o_Wr[b]);
-        a.X = reinterpret_cast<double*>(A + o_X[b]);
-        a.sp = reinterpret_cast<double*>(A + o_sp[b]);
-        a.u = reinterpret_cast<double*>(A + o_u[b]);
-        a.v = reinterpret_cast<double*>(A + o_v[b]);
-        a.pbuf = reinterpret_cast<double*>(A + o_pbuf[b]);
-        a.uh = reinterpret_cast<double*>(A + o_uh[b]);
-        a.pd = reinterpret_cast<double*>(A + o_pd[b]);
-        a.pdb = reinterpret_cast<double*>(A + o_pdb[b]);
-        a.pd2 = reinterpret_cast<double*>(A + o_pd2[b]);
-        a.rr = reinterpret_cast<double*>(A + o_rr[b]);
-        a.invr = reinterpret_cast<double*>(A + o_invr[b]);
-        a.pnorm = reinterpret_cast<double*>(A + o_pnorm[b]);
-        a.tau = reinterpret_cast<double*>(A + o_tau[b]);
-        a.beta = reinterpret_cast<double*>(A + o_beta[b]);
-        a.status = reinterpret_cast<int*>(A + o_status) + 4 * b;
+        a.Vc = reinterpret_cast<double*>(A + o.Vc);
+        a.Vr = reinterpret_cast<double*>(A + o.Vr);
+        a.Wc = reinterpret_cast<double*>(A + o.Wc);
+        a.Wr = reinterpret_cast<double*>(A + o.Wr);
+        a.X = reinterpret_cast<double*>(A + o.X);
+        a.sp = reinterpret_cast<double*>(A + o.sp);
+        a.u = reinterpret_cast<double*>(A + o.u);
+        a.v = reinterpret_cast<double*>(A + o.v);
+        a.pbuf = reinterpret_cast<double*>(A + o.pbuf);
+        a.uh = reinterpret_cast<double*>(A + o.uh);
+        a.pd = reinterpret_cast<double*>(A + o.pd);
+        a.pdb = reinterpret_cast<double*>(A + o.pdb);
+        a.pd2 = reinterpret_cast<double*>(A + o.pd2);
+        a.rr = reinterpret_cast<double*>(A + o.rr);
+        a.invr = reinterpret_cast<double*>(A + o.invr);
+        a.pnorm = reinterpret_cast<double*>(A + o.pnorm);
+        a.tau = reinterpret_cast<double*>(A + o.tau);
+        a.beta = reinterpret_cast<double*>(A + o.beta);
+        a.status = reinterpret_cast<int*>(A + o_status) + 4 * q;
         // Theta of factorisation b: SRHT per factorisation (instance b); Gaussian: the
         // leading k_b x n_b block of one master matrix (instance 0)
-        x.sk = make_sketch(sk_kind, it.k, seed, sid, sk_kind == SK_SRHT ? (uint32_t)b : 0u);
+        x.sk = make_sketch(sk_kind, it.k, seed, sid, sk_kind == SK_SRHT ? (uint32_t)order[q] : 0u);
         if (sk_kind == SK_SRHT) {
-            uint32_t* signs = reinterpret_cast<uint32_t*>(A + o_signs[b]);
-            if (!launch_srht_signs(s, signs, (it.n + 31) / 32, x.sk)) return RGS_EDEVICE;
             std::vector<int> rows;
             srht_rows_host(srht_order(it.n), (int)it.k, x.sk, rows);
-            std::copy(rows.begin(), rows.end(), rows_all.begin() + rpos);
-            x.sk.signs = signs;
-            x.sk.rows = reinterpret_cast<int*>(A + o_rows) + rpos;
+            std::copy(rows.begin(), rows.end(), rows_all.begin() + rpos[q]);
+            x.sk.signs = reinterpret_cast<uint32_t*>(A + o.signs);
+            x.sk.rows = reinterpret_cast<int*>(A + o_rows) + rpos[q];
         }
-        rpos += it.k;
-    }
-    if (hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
+    });
+    int64_t* pre_dev = reinterpret_cast<int64_t*>(A + o_pre);
+    std::vector<int64_t> pre_all;
+    pre_all.reserve(6 * (batch + 1));
+    for (const auto* v : {&pre_proj, &pre_sl, &pre_row, &pre_sign, &pre_part, &pre_red}) pre_all.insert(pre_all.end(), v->begin(), v->end());
+    if ((sk_kind == SK_SRHT && hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int),
+                                              hipMemcpyHostToDevice, s) != hipSuccess) ||
         hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipMemcpyAsync(A + o_maps, maps.data(), maps.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(pre_dev, pre_all.data(), pre_all.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
         return RGS_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // host staging vectors stay alive till here
     const BatchItem* itd = reinterpret_cast<const BatchItem*>(A + o_items);
-    const int2* mp = reinterpret_cast<const int2*>(A + o_maps);
-    if (!launch_batch_init(s, itd, (int)batch, max_m * max_m)) return RGS_EDEVICE;
-    // step 1 for every column of every factorisation: P_b = Theta_b W_b
-    T* partP = reinterpret_cast<T*>(A + o_partP);
-    for (int64_t b = 0; b < batch; ++b) {
-        const rgs_qr_item& it = items[b];
-        const QrPlan pl = plan_qr(it.n, it.m, it.k, sk_kind, sizeof(T));
-        st = sketch_matrix<T>(h, bi[b].sk, static_cast<const T*>(it.W), it.ldw, it.n, it.m, pl.G_P, pl.cc, partP,
-                              bi[b].P, it.k);
-        if (st != RGS_OK) return st;
-    }
+    const int64_t* d_proj = pre_dev;
+    const int64_t* d_sl = pre_dev + (batch + 1);
+    const int64_t* d_row = pre_dev + 2 * (batch + 1);
+    const int64_t* d_sign = pre_dev + 3 * (batch + 1);
+    const int64_t* d_part = pre_dev + 4 * (batch + 1);
+    const int64_t* d_red = pre_dev + 5 * (batch + 1);
+    const int nb = (int)batch;
+    if (!launch_batch_init(s, itd, nb, max_m * max_m)) return RGS_EDEVICE;
+    // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
+    if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, pre_sign[batch],
+                                  BlockMap{d_part, nullptr, nb, 0}, pre_part[batch], BlockMap{d_red, nullptr, nb, 0},
+                                  pre_red[batch]))
+        return RGS_EDEVICE;
     for (int64_t i = 0; i < max_m; ++i) {
-        const ColMaps& x = cm[i];
-        if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, mp + x.proj, x.nproj, (int)i)) return RGS_EDEVICE;
-        if (!launch_batch_column<T>(s, itd, mp + x.sl, x.nsl, mp + x.qd, x.nqd, mp + x.ls, x.nls, (int)i))
+        const int a = active[i], a1 = active[i + 1];
+        const int rb = (int)((i + 1 + 63) / 64);
+        if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, BlockMap{d_proj, nullptr, a, 0}, pre_proj[a], (int)i))
+            return RGS_EDEVICE;
+        if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, pre_sl[a], BlockMap{d_sl, nullptr, a, rb},
+                                    pre_sl[a] + (int64_t)rb * a, BlockMap{nullptr, nullptr, a1, rb},
+                                    (int64_t)rb * a1, (int)i))
             return RGS_EDEVICE;
     }
-    if (!launch_batch_scale<TQ, DEFER>(s, itd, mp + scale_at, nscale)) return RGS_EDEVICE;
+    if (!launch_batch_scale<TQ, DEFER>(s, itd, BlockMap{d_row, nullptr, nb, 0}, pre_row[batch])) return RGS_EDEVICE;
     std::vector<int> stat((size_t)(4 * batch));
     if (hipMemcpyAsync(stat.data(), A + o_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
         return RGS_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // host staging vectors stay alive till here
+    std::vector<rgs_status> sb((size_t)batch, RGS_OK);
+    std::vector<int64_t> fc((size_t)batch, -1);
+    for (int64_t q = 0; q < batch; ++q) {
+        const int code = stat[4 * q];
+        sb[order[q]] = code == kStatusBreakdown ? RGS_EBREAKDOWN : code == kStatusNonfinite ? RGS_ENONFINITE : RGS_OK;
+        if (code) fc[order[q]] = stat[4 * q + 1];
+    }
     rgs_status result = RGS_OK;
     for (int64_t b = 0; b < batch; ++b) {
-        const int code = stat[4 * b];
-        const rgs_status sb = code == kStatusBreakdown ? RGS_EBREAKDOWN
-                              : code == kStatusNonfinite ? RGS_ENONFINITE
-                                                         : RGS_OK;
-        if (item_status) item_status[b] = sb;
-        if (failed_column) failed_column[b] = code ? stat[4 * b + 1] : -1;
-        if (sb != RGS_OK && result == RGS_OK) result = sb;
+        if (item_status) item_status[b] = sb[b];
+        if (failed_column) failed_column[b] = fc[b];
+        if (sb[b] != RGS_OK && result == RGS_OK) result = sb[b];
     }
     const auto t1 = std::chrono::steady_clock::now();
     if (rep) {
@@ -759,7 +791,6 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     }
     return result;
 }
-
 
 // ---------------------------------------------------------------------------
 // Batched randomized GMRES.  The systems advance in lockstep, one restart
@@ -786,43 +817,21 @@ bool valid_gmres_desc(const rgs_gmres_desc* d) {
     return d->prec == RGS_P_FP64 || d->prec == RGS_P_FP32_LS64 || d->prec == RGS_P_BF16Q_FP32_LS64;
 }
 
+// Implicit launch maps of the systems still running (ids = their indices):
+// per-system 256-row blocks and projection blocks as prefix sums; the other
+// launches have the same number of blocks for every system.
 struct GmresMaps {
-    std::vector<int2> m;
-    size_t sys, row, proj, sl;
-    int nsys, nrow, nproj, nsl;
-    std::vector<size_t> qd, rb;
-    std::vector<int> nqd, nrb;
+    std::vector<int> ids;
+    std::vector<int64_t> row, proj;   // prefix sums over the listed systems
+    int nsl = 0;
+    int count() const { return (int)ids.size(); }
 };
 
-void build_gmres_maps(GmresMaps& g, const std::vector<int64_t>& active, const std::vector<int64_t>& ns, int64_t k,
-                      int64_t restart) {
-    g.m.clear();
-    const int64_t nsl = (k + kSlice - 1) / kSlice;
-    auto add = [&](int64_t per_sys_fn_tag, size_t& at, int& cnt, int64_t extra) {
-        at = g.m.size();
-        for (int64_t b : active) {
-            int64_t blocks = 0;
-            switch (per_sys_fn_tag) {
-                case 0: blocks = 1; break;
-                case 1: blocks = (ns[b] + 255) / 256; break;
-                case 2: blocks = (ns[b] + kProjRows - 1) / kProjRows; break;
-                case 3: blocks = nsl + extra; break;
-                default: blocks = extra; break;
-            }
-            for (int64_t q = 0; q < blocks; ++q) g.m.push_back({(int)b, (int)q});
-        }
-        cnt = (int)(g.m.size() - at);
-    };
-    add(0, g.sys, g.nsys, 0);
-    add(1, g.row, g.nrow, 0);
-    add(2, g.proj, g.nproj, 0);
-    add(3, g.sl, g.nsl, 0);
-    g.qd.assign((size_t)restart + 1, 0);
-    g.nqd.assign((size_t)restart + 1, 0);
-    g.rb.assign((size_t)restart + 1, 0);
-    g.nrb.assign((size_t)restart + 1, 0);
-    for (int64_t i = 0; i <= restart; ++i) add(3, g.qd[i], g.nqd[i], (i + 1 + 63) / 64);
-    for (int64_t i = 1; i <= restart; ++i) add(4, g.rb[i], g.nrb[i], (i + 63) / 64);
+void build_gmres_maps(GmresMaps& g, const std::vector<int64_t>& active, const std::vector<int64_t>& ns, int64_t k) {
+    g.ids.assign(active.begin(), active.end());
+    g.row = prefix_of((int64_t)active.size(), [&](int64_t p) { return (ns[active[p]] + 255) / 256; });
+    g.proj = prefix_of((int64_t)active.size(), [&](int64_t p) { return (ns[active[p]] + kProjRows - 1) / kProjRows; });
+    g.nsl = (int)((k + kSlice - 1) / kSlice);
 }
 
 template <typename T, typename TQ, bool DEFER>
@@ -888,8 +897,9 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     std::vector<int64_t> all((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) all[b] = b;
     GmresMaps gm;
-    build_gmres_maps(gm, all, ns, k, restart);
-    const size_t o_maps = c.take<int2>(gm.m.size());
+    build_gmres_maps(gm, all, ns, k);
+    const size_t o_ids = c.take<int>(batch), o_mrow = c.take<int64_t>(batch + 1);
+    const size_t o_mproj = c.take<int64_t>(batch + 1);
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -968,14 +978,33 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     }
     BatchItem* itd = reinterpret_cast<BatchItem*>(A + o_items);
     GmresItem* gid = reinterpret_cast<GmresItem*>(A + o_gitems);
-    const int2* mp = reinterpret_cast<const int2*>(A + o_maps);
+    const int* d_ids = reinterpret_cast<const int*>(A + o_ids);
+    const int64_t* d_row = reinterpret_cast<const int64_t*>(A + o_mrow);
+    const int64_t* d_proj = reinterpret_cast<const int64_t*>(A + o_mproj);
+    auto upload_maps = [&]() -> bool {
+        return hipMemcpyAsync(A + o_ids, gm.ids.data(), gm.ids.size() * sizeof(int), hipMemcpyHostToDevice, s) ==
+                   hipSuccess &&
+               hipMemcpyAsync(A + o_mrow, gm.row.data(), gm.row.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                              s) == hipSuccess &&
+               hipMemcpyAsync(A + o_mproj, gm.proj.data(), gm.proj.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                              s) == hipSuccess;
+    };
+    // launch maps over the running systems: one block per system, 256-row blocks,
+    // projection blocks, sketch slices (+ rb row blocks of the least squares)
+    auto m_sys = [&]() { return BlockMap{nullptr, d_ids, gm.count(), 1}; };
+    auto m_row = [&]() { return BlockMap{d_row, d_ids, gm.count(), 0}; };
+    auto m_proj = [&]() { return BlockMap{d_proj, d_ids, gm.count(), 0}; };
+    auto m_uni = [&](int per) { return BlockMap{nullptr, d_ids, gm.count(), per}; };
+    auto n_row = [&]() { return gm.row[gm.count()]; };
+    auto n_proj = [&]() { return gm.proj[gm.count()]; };
+    auto n_uni = [&](int per) { return (int64_t)per * gm.count(); };
     if (hipMemcpyAsync(A + o_gitems, gi.data(), gi.size() * sizeof(GmresItem), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipMemcpyAsync(A + o_maps, gm.m.data(), gm.m.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        !upload_maps())
         return RGS_EDEVICE;
     // x0 = 0, r0 = b, ||b|| of every system
-    if (!launch_gbatch_zero_x(s, gid, mp + gm.row, gm.nrow) ||
-        !launch_gbatch_residual(s, gid, mp + gm.sys, gm.nsys, mp + gm.row, gm.nrow))
+    if (!launch_gbatch_zero_x(s, gid, m_row(), n_row()) ||
+        !launch_gbatch_residual(s, gid, m_sys(), gm.count(), m_row(), n_row()))
         return RGS_EDEVICE;
     std::vector<double> bn((size_t)batch), rn((size_t)batch), hh((size_t)(batch * mcap));
     if (hipMemcpyAsync(bn.data(), A + o_norm, batch * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -1012,36 +1041,41 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     };
     const bool dual = sk_kind == SK_GAUSS;   // the two sketches of an Arnoldi step share their draws
     auto enqueue_cycle = [&](hipStream_t q) -> bool {
-        if (!launch_gbatch_reset(q, itd, mp + gm.sys, gm.nsys)) return false;
-        if (!launch_gbatch_cast<T>(q, gid, mp + gm.row, gm.nrow)) return false;
+        const int nsl = gm.nsl;
+        const BlockMap none{nullptr, nullptr, 0, 0};
+        if (!launch_gbatch_reset(q, itd, m_sys(), gm.count())) return false;
+        if (!launch_gbatch_cast<T>(q, gid, m_row(), n_row())) return false;
         if (dual) {
-            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, mp + gm.proj, gm.nproj, 0) ||
-                !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, mp + gm.proj, gm.nproj, 0))
+            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), 0) ||
+                !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), 0))
                 return false;
-        } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, 0)) {
+        } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(), n_proj(), 0)) {
             return false;
         }
-        if (!launch_batch_column<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.qd[0], gm.nqd[0], nullptr, 0, 0))
+        if (!launch_batch_column<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(nsl + 1), n_uni(nsl + 1), none, 0, 0))
             return false;
-        if (!launch_gbatch_givens_init(q, itd, gid, mp + gm.sys, gm.nsys)) return false;
+        if (!launch_gbatch_givens_init(q, itd, gid, m_sys(), gm.count())) return false;
         for (int64_t i = 1; i <= restart; ++i) {
             const int ii = (int)i;
+            const int rbl = (int)((i + 63) / 64);       // row blocks of the i x i solve
+            const int rbq = (int)((i + 1 + 63) / 64);   // column-step blocks beyond the slices
             if (dual) {
-                if (!launch_gbatch_ls<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.rb[i], gm.nrb[i], ii, 1) ||
-                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, mp + gm.proj, gm.nproj, ii) ||
-                    !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, mp + gm.proj, gm.nproj, ii))
+                if (!launch_gbatch_ls<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(rbl), n_uni(rbl), ii, 1) ||
+                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), ii) ||
+                    !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), ii))
                     return false;
             } else {
-                if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii)) return false;
-                if (!launch_gbatch_ls<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.rb[i], gm.nrb[i], ii, 0)) return false;
-                if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, mp + gm.proj, gm.nproj, ii))
+                if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(), n_proj(), ii)) return false;
+                if (!launch_gbatch_ls<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(rbl), n_uni(rbl), ii, 0)) return false;
+                if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(), n_proj(), ii))
                     return false;
             }
-            if (!launch_batch_column<T>(q, itd, mp + gm.sl, gm.nsl, mp + gm.qd[i], gm.nqd[i], nullptr, 0, ii))
+            if (!launch_batch_column<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(nsl + rbq), n_uni(nsl + rbq), none, 0,
+                                        ii))
                 return false;
-            if (!launch_gbatch_givens(q, itd, gid, mp + gm.sys, gm.nsys, ii)) return false;
+            if (!launch_gbatch_givens(q, itd, gid, m_sys(), gm.count(), ii)) return false;
         }
-        return launch_gbatch_finish<TQ>(q, itd, gid, mp + gm.sys, gm.nsys, mp + gm.row, gm.nrow);
+        return launch_gbatch_finish<TQ>(q, itd, gid, m_sys(), gm.count(), m_row(), n_row());
     };
     rgs_status fail = RGS_OK;
     for (int64_t cycle = 0;; ++cycle) {
@@ -1079,10 +1113,8 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
                 return RGS_EDEVICE;
         }
         if (active != prev_active) {
-            build_gmres_maps(gm, active, ns, k, restart);
-            if (hipMemcpyAsync(A + o_maps, gm.m.data(), gm.m.size() * sizeof(int2), hipMemcpyHostToDevice, s) !=
-                hipSuccess)
-                return RGS_EDEVICE;
+            build_gmres_maps(gm, active, ns, k);
+            if (!upload_maps()) return RGS_EDEVICE;
             drop_graph();
             prev_active = active;
         }

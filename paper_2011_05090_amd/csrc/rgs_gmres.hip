@@ -21,6 +21,7 @@
 // cycle's step limit): once it is set the remaining launches of the cycle
 // return immediately.
 
+#include "rgs_map.hpp"
 #include "rgs_step.hpp"
 
 namespace rgs {
@@ -388,21 +389,21 @@ __global__ __launch_bounds__(256) void k_xupdate(double* __restrict__ x, const T
 
 // Start of a cycle: clear the status word (a kernel, not a memset, so that the
 // cycle can be captured in a graph).
-__global__ void kg_reset(const BatchItem* __restrict__ items, const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+__global__ void kg_reset(const BatchItem* __restrict__ items, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     if (threadIdx.x < 3) items[bm.x].sa.status[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(256) void kg_zero_x(const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+__global__ __launch_bounds__(256) void kg_zero_x(const GmresItem* __restrict__ gi, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     const GmresItem& g = gi[bm.x];
     const int64_t l = (int64_t)bm.y * 256 + threadIdx.x;
     if (l < g.n) g.x[l] = 0.0;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void kg_cast(const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+__global__ __launch_bounds__(256) void kg_cast(const GmresItem* __restrict__ gi, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     const GmresItem& g = gi[bm.x];
     const int64_t l = (int64_t)bm.y * 256 + threadIdx.x;
     if (l < g.n) static_cast<T*>(g.w)[l] = (T)g.r[l];
@@ -411,9 +412,9 @@ __global__ __launch_bounds__(256) void kg_cast(const GmresItem* __restrict__ gi,
 template <typename TQ, typename T, int SK>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem* __restrict__ items,
                                                                  const GmresItem* __restrict__ gi,
-                                                                 const int2* __restrict__ map, int i) {
+                                                                 BlockMap map, int i) {
     __shared__ T lds[kProjWaves * kTile];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
@@ -425,9 +426,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem
 template <typename TQ, typename T>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const BatchItem* __restrict__ items,
                                                                       const GmresItem* __restrict__ gi,
-                                                                      const int2* __restrict__ map, int i) {
+                                                                      BlockMap map, int i) {
     __shared__ T lds[2 * kProjWaves * kTile];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
@@ -441,9 +442,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const Batc
 template <typename T, typename TQ, bool DEFER>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_project_ws(const BatchItem* __restrict__ items,
                                                                     const GmresItem* __restrict__ gi,
-                                                                    const int2* __restrict__ map, int i) {
+                                                                    BlockMap map, int i) {
     __shared__ T lds[kProjWaves * kTile];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
@@ -458,9 +459,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_project_ws(const BatchI
 template <typename T, typename TQ, int SK, bool DEFER>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem* __restrict__ items,
                                                                  const GmresItem* __restrict__ gi,
-                                                                 const int2* __restrict__ map, int i) {
+                                                                 BlockMap map, int i) {
     __shared__ T lds[kProjWaves * kTile];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
@@ -474,9 +475,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem
 // kernel): reduce to pbuf with the per-slice partials of Wm^T p, then the head
 // of U^T p, then y = R_S^{-1} uh -> R(0:i, i) and the projection coefficients.
 template <typename PT>
-__global__ __launch_bounds__(kGW) void kg_lsa(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+__global__ __launch_bounds__(kGW) void kg_lsa(const BatchItem* __restrict__ items, BlockMap map,
                                               int i, int dual) {
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     // dual: p_i arrives as the sketch of A q'_{i-1} (part2), scaled by 1/r_{i-1,i-1} here
@@ -484,20 +485,20 @@ __global__ __launch_bounds__(kGW) void kg_lsa(const BatchItem* __restrict__ item
                 a.mcap, a.pbuf, a.pd, bm.y, dual ? a.invr + (i - 1) : nullptr);
 }
 
-__global__ __launch_bounds__(kGW) void kg_ls2(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+__global__ __launch_bounds__(kGW) void kg_ls2(const BatchItem* __restrict__ items, BlockMap map,
                                               int i) {
     extern __shared__ double cp[];  // [i + 1]
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     ls2_body(a.pbuf, a.k, i, it.nsl, a.Vc, a.mcap, a.pd, a.uh, a.pnorm, bm.y, cp);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kGW) void kg_ls3(const BatchItem* __restrict__ items, const int2* __restrict__ map,
+__global__ __launch_bounds__(kGW) void kg_ls3(const BatchItem* __restrict__ items, BlockMap map,
                                               int i) {
     extern __shared__ double us[];  // [i]
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     ls3_body<T>(i, i, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<T*>(it.coef), it.defer ? a.invr : nullptr, bm.y,
@@ -505,8 +506,8 @@ __global__ __launch_bounds__(kGW) void kg_ls3(const BatchItem* __restrict__ item
 }
 
 __global__ void kg_givens_init(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
-                               const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+                               BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     if (threadIdx.x != 0) return;
     const GmresItem& g = gi[bm.x];
     g.gv[0] = items[bm.x].R[0];
@@ -514,8 +515,8 @@ __global__ void kg_givens_init(const BatchItem* __restrict__ items, const GmresI
 }
 
 __global__ void kg_givens(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
-                          const int2* __restrict__ map, int c) {
-    const int2 bm = map[blockIdx.x];
+                          BlockMap map, int c) {
+    const int2 bm = locate(map, blockIdx.x);
     if (threadIdx.x != 0) return;
     const BatchItem& it = items[bm.x];
     const GmresItem& g = gi[bm.x];
@@ -524,8 +525,8 @@ __global__ void kg_givens(const BatchItem* __restrict__ items, const GmresItem* 
 }
 
 __global__ void kg_backsub(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
-                           const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+                           BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     if (threadIdx.x != 0) return;
     const BatchItem& it = items[bm.x];
     const GmresItem& g = gi[bm.x];
@@ -534,23 +535,23 @@ __global__ void kg_backsub(const BatchItem* __restrict__ items, const GmresItem*
 
 template <typename TQ>
 __global__ __launch_bounds__(256) void kg_xupdate(const BatchItem* __restrict__ items,
-                                                  const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+                                                  const GmresItem* __restrict__ gi, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const GmresItem& g = gi[bm.x];
     xupdate_body<TQ>(g.x, static_cast<const TQ*>(it.Q), it.ldq, g.n, g.used, g.y,
                      (int64_t)bm.y * 256 + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void kg_residual(const GmresItem* __restrict__ gi, const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+__global__ __launch_bounds__(256) void kg_residual(const GmresItem* __restrict__ gi, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     const GmresItem& g = gi[bm.x];
     residual_body(g.b, g.x, grid3(g.A), g.n, g.r, g.rpart, bm.y);
 }
 
 __global__ __launch_bounds__(256) void kg_norm_finish(const GmresItem* __restrict__ gi,
-                                                      const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+                                                      BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     const GmresItem& g = gi[bm.x];
     norm_finish_body(g.rpart, (g.n + 255) / 256, g.norm);
 }
@@ -637,14 +638,14 @@ bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* g
 }
 
 // ---- batched ----
-bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const int2* map_sys, int nsys) {
+bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const BlockMap& map_sys, int64_t nsys) {
     if (nsys == 0) return true;
     hipLaunchKernelGGL(kg_reset, dim3(nsys), dim3(64), 0, st, items, map_sys);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow) {
+bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const BlockMap& map_row, int64_t nrow) {
     if (nrow == 0) return true;
     hipLaunchKernelGGL(kg_zero_x, dim3(nrow), dim3(256), 0, st, gi, map_row);
     RGS_LAUNCH_CHECK();
@@ -652,7 +653,7 @@ bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const int2* map_r
 }
 
 template <typename T>
-bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow) {
+bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const BlockMap& map_row, int64_t nrow) {
     if (nrow == 0) return true;
     hipLaunchKernelGGL(kg_cast<T>, dim3(nrow), dim3(256), 0, st, gi, map_row);
     RGS_LAUNCH_CHECK();
@@ -661,7 +662,7 @@ bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const int2* map_row
 
 template <typename T, typename TQ>
 bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
-                           const int2* map_proj, int nproj, int i) {
+                           const BlockMap& map_proj, int64_t nproj, int i) {
     if (nproj == 0) return true;
     const dim3 thr(kProjWaves * kWave);
     if (sketch == SK_SRHT)
@@ -673,8 +674,8 @@ bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, c
 }
 
 template <typename T, typename TQ>
-bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_proj,
-                                int nproj, int i) {
+bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
+                                int64_t nproj, int i) {
     if (nproj == 0) return true;
     hipLaunchKernelGGL((kg_stencil_dual<TQ, T>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi, map_proj, i);
     RGS_LAUNCH_CHECK();
@@ -682,8 +683,8 @@ bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const Gm
 }
 
 template <typename T, typename TQ, bool DEFER>
-bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_proj,
-                              int nproj, int i) {
+bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
+                              int64_t nproj, int i) {
     if (nproj == 0) return true;
     hipLaunchKernelGGL((kg_project_ws<T, TQ, DEFER>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
                        map_proj, i);
@@ -693,7 +694,7 @@ bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const Gmre
 
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
-                           const int2* map_proj, int nproj, int i) {
+                           const BlockMap& map_proj, int64_t nproj, int i) {
     if (nproj == 0) return true;
     const dim3 thr(kProjWaves * kWave);
     if (sketch == SK_SRHT)
@@ -705,8 +706,8 @@ bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, c
 }
 
 template <typename T>
-bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const int2* map_sl, int nsl, const int2* map_rb,
-                      int nrb, int i, int dual) {
+bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl, const BlockMap& map_rb,
+                      int64_t nrb, int i, int dual) {
     if (nsl > 0) {
         hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i, dual);
         RGS_LAUNCH_CHECK();
@@ -720,16 +721,16 @@ bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const int2* map_sl
     return true;
 }
 
-bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
-                               int nsys) {
+bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
+                               int64_t nsys) {
     if (nsys == 0) return true;
     hipLaunchKernelGGL(kg_givens_init, dim3(nsys), dim3(64), 0, st, items, gi, map_sys);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
-                          int nsys, int c) {
+bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
+                          int64_t nsys, int c) {
     if (nsys == 0) return true;
     hipLaunchKernelGGL(kg_givens, dim3(nsys), dim3(64), 0, st, items, gi, map_sys, c);
     RGS_LAUNCH_CHECK();
@@ -737,8 +738,8 @@ bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresIte
 }
 
 template <typename TQ>
-bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
-                          int nsys, const int2* map_row, int nrow) {
+bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
+                          int64_t nsys, const BlockMap& map_row, int64_t nrow) {
     if (nsys == 0) return true;
     hipLaunchKernelGGL(kg_backsub, dim3(nsys), dim3(64), 0, st, items, gi, map_sys);
     RGS_LAUNCH_CHECK();
@@ -747,8 +748,8 @@ bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresIte
     return launch_gbatch_residual(st, gi, map_sys, nsys, map_row, nrow);
 }
 
-bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const int2* map_sys, int nsys,
-                            const int2* map_row, int nrow) {
+bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const BlockMap& map_sys, int64_t nsys,
+                            const BlockMap& map_row, int64_t nrow) {
     if (nsys == 0) return true;
     hipLaunchKernelGGL(kg_residual, dim3(nrow), dim3(256), 0, st, gi, map_row);
     RGS_LAUNCH_CHECK();
@@ -771,45 +772,41 @@ template bool launch_update_x<double>(hipStream_t, const double*, int, const dou
                                       double*, const double*, int64_t, int64_t, const double*);
 template bool launch_update_x<bf16>(hipStream_t, const double*, int, const double*, const int*, double*, double*,
                                     const bf16*, int64_t, int64_t, const double*);
-template bool launch_gbatch_cast<float>(hipStream_t, const GmresItem*, const int2*, int);
-template bool launch_gbatch_cast<double>(hipStream_t, const GmresItem*, const int2*, int);
-template bool launch_gbatch_stencil<float, float>(hipStream_t, int, const BatchItem*, const GmresItem*, const int2*,
-                                                  int, int);
+template bool launch_gbatch_cast<float>(hipStream_t, const GmresItem*, const BlockMap&, int64_t);
+template bool launch_gbatch_cast<double>(hipStream_t, const GmresItem*, const BlockMap&, int64_t);
+template bool launch_gbatch_stencil<float, float>(hipStream_t, int, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
 template bool launch_gbatch_stencil<double, double>(hipStream_t, int, const BatchItem*, const GmresItem*,
-                                                    const int2*, int, int);
-template bool launch_gbatch_stencil<float, bf16>(hipStream_t, int, const BatchItem*, const GmresItem*, const int2*,
-                                                 int, int);
+                                                    const BlockMap&, int64_t, int);
+template bool launch_gbatch_stencil<float, bf16>(hipStream_t, int, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
 template bool launch_gbatch_project<float, float, false>(hipStream_t, int, const BatchItem*, const GmresItem*,
-                                                         const int2*, int, int);
+                                                         const BlockMap&, int64_t, int);
 template bool launch_gbatch_project<double, double, false>(hipStream_t, int, const BatchItem*, const GmresItem*,
-                                                           const int2*, int, int);
+                                                           const BlockMap&, int64_t, int);
 template bool launch_gbatch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const GmresItem*,
-                                                       const int2*, int, int);
-template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int, int);
-template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int, int, int);
+                                                       const BlockMap&, int64_t, int);
+template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
+template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
 template bool launch_stencil_dual<float, float>(hipStream_t, const StencilArgs&, const float*, float*,
                                                 const SketchArgs&, float*, float*, const int*);
 template bool launch_stencil_dual<double, double>(hipStream_t, const StencilArgs&, const double*, double*,
                                                   const SketchArgs&, double*, double*, const int*);
 template bool launch_stencil_dual<bf16, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
                                                const SketchArgs&, float*, float*, const int*);
-template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const int2*,
-                                                       int, int);
+template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
 template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
-                                                         const int2*, int, int);
-template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const int2*,
-                                                      int, int);
+                                                         const BlockMap&, int64_t, int);
+template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
 template bool launch_gbatch_project_ws<float, float, false>(hipStream_t, const BatchItem*, const GmresItem*,
-                                                            const int2*, int, int);
+                                                            const BlockMap&, int64_t, int);
 template bool launch_gbatch_project_ws<double, double, false>(hipStream_t, const BatchItem*, const GmresItem*,
-                                                              const int2*, int, int);
+                                                              const BlockMap&, int64_t, int);
 template bool launch_gbatch_project_ws<float, bf16, true>(hipStream_t, const BatchItem*, const GmresItem*,
-                                                          const int2*, int, int);
-template bool launch_gbatch_finish<float>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
-                                          const int2*, int);
-template bool launch_gbatch_finish<double>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
-                                           const int2*, int);
-template bool launch_gbatch_finish<bf16>(hipStream_t, const BatchItem*, const GmresItem*, const int2*, int,
-                                         const int2*, int);
+                                                          const BlockMap&, int64_t, int);
+template bool launch_gbatch_finish<float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t,
+                                          const BlockMap&, int64_t);
+template bool launch_gbatch_finish<double>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t,
+                                           const BlockMap&, int64_t);
+template bool launch_gbatch_finish<bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t,
+                                         const BlockMap&, int64_t);
 
 }  // namespace rgs

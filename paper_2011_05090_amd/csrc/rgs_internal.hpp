@@ -43,13 +43,18 @@ bool launch_zero_mat(hipStream_t st, double* A, int64_t rows, int64_t cols, int6
 bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr,
                             const int* status);
 bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64_t max_m2);
+template <typename T>
+bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map_signs,
+                           int64_t n_signs, const BlockMap& map_part, int64_t n_part, const BlockMap& map_red,
+                           int64_t n_red);
 template <typename TW, typename TQ, bool DEFER>
-bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const int2* map, int count, int i);
+bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map, int64_t nblk,
+                          int i);
 template <typename TW>
-bool launch_batch_column(hipStream_t st, const BatchItem* items, const int2* map_sl, int n_sl, const int2* map_qd,
-                         int n_qd, const int2* map_ls, int n_ls, int i);
+bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
+                         const BlockMap& map_qd, int64_t n_qd, const BlockMap& map_ls, int64_t n_ls, int i);
 template <typename TQ, bool DEFER>
-bool launch_batch_scale(hipStream_t st, const BatchItem* items, const int2* map, int count);
+bool launch_batch_scale(hipStream_t st, const BatchItem* items, const BlockMap& map, int64_t nblk);
 template <typename T>
 bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_t j1, int64_t l0, int64_t l1,
                         double rsk, double* out, int64_t ldo);
@@ -84,33 +89,33 @@ bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, 
 // (map_sys: one entry per system, map_row: 256-row blocks, map_proj: blocks
 // of kProjRows rows, map_sl: 64-row sketch slices, map_rb: 64-row blocks of
 // the i x i least-squares solve).
-bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const int2* map_sys, int nsys);
-bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow);
+bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const BlockMap& map_sys, int64_t nsys);
+bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const BlockMap& map_row, int64_t nrow);
 template <typename T>
-bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const int2* map_row, int nrow);
+bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const BlockMap& map_row, int64_t nrow);
 template <typename T, typename TQ>
 bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
-                           const int2* map_proj, int nproj, int i);
+                           const BlockMap& map_proj, int64_t nproj, int i);
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
-                           const int2* map_proj, int nproj, int i);
+                           const BlockMap& map_proj, int64_t nproj, int i);
 template <typename T>
-bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const int2* map_sl, int nsl, const int2* map_rb,
-                      int nrb, int i, int dual);
+bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl, const BlockMap& map_rb,
+                      int64_t nrb, int i, int dual);
 template <typename T, typename TQ>
-bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_proj,
-                                int nproj, int i);
+bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
+                                int64_t nproj, int i);
 template <typename T, typename TQ, bool DEFER>
-bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_proj,
-                              int nproj, int i);
-bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
-                               int nsys);
-bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
-                          int nsys, int c);
+bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
+                              int64_t nproj, int i);
+bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
+                               int64_t nsys);
+bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
+                          int64_t nsys, int c);
 template <typename TQ>
-bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* map_sys,
-                          int nsys, const int2* map_row, int nrow);
-bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const int2* map_sys, int nsys,
-                            const int2* map_row, int nrow);
+bool launch_gbatch_finish(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
+                          int64_t nsys, const BlockMap& map_row, int64_t nrow);
+bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const BlockMap& map_sys, int64_t nsys,
+                            const BlockMap& map_row, int64_t nrow);
 
 }  // namespace rgs

@@ -23,15 +23,15 @@
 
 #include <algorithm>
 
+#include "rgs_map.hpp"
 #include "rgs_step.hpp"
 
 namespace rgs {
 
 // SRHT diagonal D as a bit table: bit b of word w is set iff d_{32w+b} = -1.
 // Word w comes from word (w mod 4) of Philox(w/4, 0xFFFFFFFF, sketch_id, instance).
-__global__ void k_srht_signs(uint32_t* __restrict__ signs, int64_t nwords, uint32_t k0, uint32_t k1,
-                             uint32_t sid, uint32_t inst) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void srht_signs_body(uint32_t* __restrict__ signs, int64_t nwords, uint32_t k0,
+                                                uint32_t k1, uint32_t sid, uint32_t inst, int64_t b) {
     if (4 * b >= nwords) return;
     uint32_t x[4];
     philox4x32_10((uint32_t)b, kTagSigns, sid, inst, k0, k1, x);
@@ -40,14 +40,25 @@ __global__ void k_srht_signs(uint32_t* __restrict__ signs, int64_t nwords, uint3
         if (4 * b + t < nwords) signs[4 * b + t] = x[t];
 }
 
+__global__ void k_srht_signs(uint32_t* __restrict__ signs, int64_t nwords, uint32_t k0, uint32_t k1,
+                             uint32_t sid, uint32_t inst) {
+    srht_signs_body(signs, nwords, k0, k1, sid, inst, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched: map blocks are (factorisation, 256 groups of 4 sign words).
+__global__ void kb_srht_signs(const BatchItem* __restrict__ items, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    srht_signs_body(const_cast<uint32_t*>(it.sk.signs), (it.n + 31) / 32, it.sk.k0, it.sk.k1, it.sk.sid,
+                    it.sk.inst, (int64_t)bm.y * blockDim.x + threadIdx.x);
+}
+
 // Partial sketches of ncols columns of X: workgroup (g, col) covers row blocks
 // g, g + G, ... (4096 rows each) and writes partials[(col * G + g) * k + j].
 template <typename T, typename PT, int SK>
-__global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, int64_t ldx, int64_t n,
-                                                     int64_t nblk, int G, SketchArgs sk,
-                                                     PT* __restrict__ partials) {
-    __shared__ T lds[kBlock];
-    const int g = blockIdx.x, col = blockIdx.y;
+__device__ __forceinline__ void sketch_cols_body(const T* __restrict__ X, int64_t ldx, int64_t n, int64_t nblk,
+                                                 int G, const SketchArgs& sk, PT* __restrict__ partials, int g,
+                                                 int col, T* __restrict__ lds) {
     const T* x = X + (int64_t)col * ldx;
     PT acc[kKptMax];
 #pragma unroll
@@ -70,6 +81,24 @@ __global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, in
     }
 }
 
+template <typename T, typename PT, int SK>
+__global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, int64_t ldx, int64_t n,
+                                                     int64_t nblk, int G, SketchArgs sk,
+                                                     PT* __restrict__ partials) {
+    __shared__ T lds[kBlock];
+    sketch_cols_body<T, PT, SK>(X, ldx, n, nblk, G, sk, partials, blockIdx.x, blockIdx.y, lds);
+}
+
+// Batched step 1 (SRHT): map blocks are (factorisation, g + G_P * column).
+template <typename T, int SK>
+__global__ __launch_bounds__(kWG) void kb_sketch_cols(const BatchItem* __restrict__ items, BlockMap map) {
+    __shared__ T lds[kBlock];
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    sketch_cols_body<T, T, SK>(static_cast<const T*>(it.W), it.ldw, it.n, (it.n + kBlock - 1) / kBlock, it.G_P,
+                               it.sk, static_cast<T*>(it.partP), bm.y % it.G_P, bm.y / it.G_P, lds);
+}
+
 // Gaussian sketch of ncols columns with every entry of Theta generated once
 // per workgroup and applied to C columns (instead of once per column).
 // Workgroup (g, jc, cc): sketch rows j = 256 jc + threadIdx.x, columns
@@ -85,12 +114,11 @@ __device__ __forceinline__ double elem_real(double v) { return v; }
 __device__ __forceinline__ float elem_real(bf16 v) { return bf16_to_float(v.bits); }
 
 template <typename TX, typename T, int C>
-__global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
-                                                    int G, SketchArgs sk, T* __restrict__ partials) {
-    __shared__ __attribute__((aligned(16))) T w[C][kGSub];
-    const int g = blockIdx.x;
-    const int j = blockIdx.y * kWG + threadIdx.x;
-    const int c0 = blockIdx.z * C;
+__device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
+                                                const SketchArgs& sk, T* __restrict__ partials, int g, int jc,
+                                                int cc, T (*w)[kGSub]) {
+    const int j = jc * kWG + threadIdx.x;
+    const int c0 = cc * C;
     const int nc = min(C, ncols - c0);
     T acc[C];
 #pragma unroll
@@ -126,15 +154,33 @@ __global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, in
     }
 }
 
+template <typename TX, typename T, int C>
+__global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
+                                                    int G, SketchArgs sk, T* __restrict__ partials) {
+    __shared__ __attribute__((aligned(16))) T w[C][kGSub];
+    gauss_cols_body<TX, T, C>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+}
+
+// Batched step 1 (Gaussian): map blocks are (factorisation, g + G_P (jc + njc cc)).
+template <typename T>
+__global__ __launch_bounds__(kWG) void kb_gauss_cols(const BatchItem* __restrict__ items, BlockMap map) {
+    __shared__ __attribute__((aligned(16))) T w[kGaussCols][kGSub];
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const int njc = (it.k + kWG - 1) / kWG;
+    const int rest = bm.y / it.G_P;
+    gauss_cols_body<T, T, kGaussCols>(static_cast<const T*>(it.W), it.ldw, it.n, it.m, it.G_P, it.sk,
+                                      static_cast<T*>(it.partP), bm.y % it.G_P, rest % njc, rest / njc, w);
+}
+
 // out[j + col*ldo] = scale * sum_{g=0}^{G-1} partials[(col*G + g)*k + j], in fp64 and
 // in a fixed order: 8 contiguous g-ranges summed by 8 threads, then combined in order.
 template <typename PT>
-__global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials, int G, int k,
-                                                double scale, double* __restrict__ out, int64_t ldo) {
+__device__ __forceinline__ void reduce_body(const PT* __restrict__ partials, int G, int k, double scale,
+                                            double* __restrict__ out, int64_t ldo, int jb, int col) {
     __shared__ double red[8][32];
-    const int col = blockIdx.y;
     const int jl = threadIdx.x & 31, part = threadIdx.x >> 5;
-    const int j = blockIdx.x * 32 + jl;
+    const int j = jb * 32 + jl;
     const int g0 = (int)((int64_t)G * part / 8), g1 = (int)((int64_t)G * (part + 1) / 8);
     double s = 0.0;
     if (j < k) {
@@ -149,6 +195,22 @@ __global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials,
         for (int t = 0; t < 8; ++t) tot += red[t][jl];
         out[j + (int64_t)col * ldo] = tot * scale;
     }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials, int G, int k,
+                                                double scale, double* __restrict__ out, int64_t ldo) {
+    reduce_body<PT>(partials, G, k, scale, out, ldo, blockIdx.x, blockIdx.y);
+}
+
+// Batched: map blocks are (factorisation, 32-row chunk + ceil(k/32) * column) of P.
+template <typename PT>
+__global__ __launch_bounds__(kWG) void kb_reduce(const BatchItem* __restrict__ items, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const int nj = (it.k + 31) / 32;
+    reduce_body<PT>(static_cast<const PT*>(it.partP), it.G_P, it.k, it.sketch_scale, it.P, it.k, bm.y % nj,
+                    bm.y / nj);
 }
 
 // Final step 7 for the last column: q = q' / r (fp64 reciprocal, rounded to T).
@@ -176,10 +238,10 @@ __global__ void k_scale_cols_bf16(bf16* __restrict__ Q, int64_t ldq, int64_t n, 
     scale_cols_bf16_body(Q, ldq, n, m, invr, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Batched end of step 7: map entries (factorisation, block of 256 rows).
+// Batched end of step 7: map blocks are (factorisation, block of 256 rows).
 template <typename TQ, bool DEFER>
-__global__ void kb_scale(const BatchItem* __restrict__ items, const int2* __restrict__ map) {
-    const int2 bm = map[blockIdx.x];
+__global__ void kb_scale(const BatchItem* __restrict__ items, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_FAILED(it.sa.status);
     const int64_t l = (int64_t)bm.y * blockDim.x + threadIdx.x;
@@ -275,9 +337,8 @@ __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double*
 // factorisation has a column i+1, and nothing otherwise.
 // ---------------------------------------------------------------------------
 template <typename PT>
-__global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items, const int2* __restrict__ map,
-                                             int i) {
-    const int2 bm = map[blockIdx.x];
+__global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const bool from_p = (i == 0 && !it.defer && it.P != nullptr);   // GMRES systems carry no P
@@ -285,19 +346,17 @@ __global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items
                 a.mcap, a.sp, a.pd, bm.y);
 }
 
-__global__ __launch_bounds__(kGW) void kb_qb(const BatchItem* __restrict__ items, const int2* __restrict__ map,
-                                             int i) {
+__global__ __launch_bounds__(kGW) void kb_qb(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double c1[];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     qb_body(a.k, i, it.nsl, a.sp, a.Vc, a.mcap, a.pd, a.u, a.pd2, it.S, it.lds, it.R, it.ldr, a.rr, a.invr,
             a.pnorm, a.status, bm.y, c1);
 }
 
-__global__ __launch_bounds__(kGW) void kb_qc(const BatchItem* __restrict__ items, const int2* __restrict__ map,
-                                             int i) {
-    const int2 bm = map[blockIdx.x];
+__global__ __launch_bounds__(kGW) void kb_qc(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
@@ -305,10 +364,9 @@ __global__ __launch_bounds__(kGW) void kb_qc(const BatchItem* __restrict__ items
             bm.y);
 }
 
-__global__ __launch_bounds__(kGW) void kb_qd(const BatchItem* __restrict__ items, const int2* __restrict__ map,
-                                             int i) {
+__global__ __launch_bounds__(kGW) void kb_qd(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double dyn[];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
@@ -317,10 +375,9 @@ __global__ __launch_bounds__(kGW) void kb_qd(const BatchItem* __restrict__ items
 }
 
 template <typename TW>
-__global__ __launch_bounds__(kGW) void kb_ls3(const BatchItem* __restrict__ items, const int2* __restrict__ map,
-                                              int i) {
+__global__ __launch_bounds__(kGW) void kb_ls3(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double us[];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     ls3_body<TW>(i + 1, i + 1, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<TW*>(it.coef),
@@ -455,6 +512,26 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
     return true;
 }
 
+// Step 1 for every factorisation of a batch: sign tables (SRHT), block
+// partials of P_b = Theta_b W_b, and their reduction into P_b.
+template <typename T>
+bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map_signs,
+                           int64_t n_signs, const BlockMap& map_part, int64_t n_part, const BlockMap& map_red,
+                           int64_t n_red) {
+    if (sketch == SK_SRHT) {
+        if (n_signs > 0) hipLaunchKernelGGL(kb_srht_signs, dim3(n_signs), dim3(256), 0, st, items, map_signs);
+        RGS_LAUNCH_CHECK();
+        if (n_part > 0)
+            hipLaunchKernelGGL((kb_sketch_cols<T, SK_SRHT>), dim3(n_part), dim3(kWG), 0, st, items, map_part);
+    } else if (n_part > 0) {
+        hipLaunchKernelGGL(kb_gauss_cols<T>, dim3(n_part), dim3(kWG), 0, st, items, map_part);
+    }
+    RGS_LAUNCH_CHECK();
+    if (n_red > 0) hipLaunchKernelGGL(kb_reduce<T>, dim3(n_red), dim3(kWG), 0, st, items, map_red);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 template <typename PT>
 bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
                    int64_t ldo) {
@@ -545,8 +622,8 @@ bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64
 }
 
 template <typename TW>
-bool launch_batch_column(hipStream_t st, const BatchItem* items, const int2* map_sl, int n_sl, const int2* map_qd,
-                         int n_qd, const int2* map_ls, int n_ls, int i) {
+bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
+                         const BlockMap& map_qd, int64_t n_qd, const BlockMap& map_ls, int64_t n_ls, int i) {
     if (n_sl > 0) {
         hipLaunchKernelGGL(kb_qa<TW>, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
@@ -567,9 +644,9 @@ bool launch_batch_column(hipStream_t st, const BatchItem* items, const int2* map
 }
 
 template <typename TQ, bool DEFER>
-bool launch_batch_scale(hipStream_t st, const BatchItem* items, const int2* map, int count) {
-    if (count == 0) return true;
-    hipLaunchKernelGGL((kb_scale<TQ, DEFER>), dim3(count), dim3(256), 0, st, items, map);
+bool launch_batch_scale(hipStream_t st, const BatchItem* items, const BlockMap& map, int64_t nblk) {
+    if (nblk == 0) return true;
+    hipLaunchKernelGGL((kb_scale<TQ, DEFER>), dim3(nblk), dim3(256), 0, st, items, map);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -627,18 +704,20 @@ template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const f
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
                                             double*, const double*);
+template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
+                                          const BlockMap&, int64_t, const BlockMap&, int64_t);
 template bool launch_gauss_cols<float, float>(hipStream_t, const float*, int64_t, int64_t, int, int,
                                               const SketchArgs&, float*);
 template bool launch_gauss_cols<double, double>(hipStream_t, const double*, int64_t, int64_t, int, int,
                                                 const SketchArgs&, double*);
 template bool launch_gauss_cols<bf16, float>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
                                              const SketchArgs&, float*);
-template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,
-                                         const int2*, int, int);
-template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const int2*, int, const int2*, int,
-                                          const int2*, int, int);
-template bool launch_batch_scale<float, false>(hipStream_t, const BatchItem*, const int2*, int);
-template bool launch_batch_scale<bf16, true>(hipStream_t, const BatchItem*, const int2*, int);
+template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
+                                         int64_t, const BlockMap&, int64_t, int);
+template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
+                                         int64_t, const BlockMap&, int64_t, int);
+template bool launch_batch_scale<float, false>(hipStream_t, const BatchItem*, const BlockMap&, int64_t);
+template bool launch_batch_scale<bf16, true>(hipStream_t, const BatchItem*, const BlockMap&, int64_t);
 template bool launch_materialize<float>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,
                                         double, double*, int64_t);
 template bool launch_materialize<double>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,

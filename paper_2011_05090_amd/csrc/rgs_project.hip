@@ -6,6 +6,7 @@
 // column), so it sits in a translation unit of its own.
 
 #include "rgs_internal.hpp"
+#include "rgs_map.hpp"
 #include "rgs_proj.hpp"
 
 namespace rgs {
@@ -35,13 +36,13 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_project_ws(
                                                     nullptr, blockIdx.x, lds, wscale);
 }
 
-// Batched: workgroup -> (factorisation, row block) through map; column i of
-// every factorisation listed in the map.
+// Batched: workgroup -> (factorisation, row block) through the implicit map;
+// column i of every factorisation listed in it.
 template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
-__global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem* __restrict__ items,
-                                                                 const int2* __restrict__ map, int i) {
+__global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem* __restrict__ items, BlockMap map,
+                                                                 int i) {
     __shared__ TW lds[kProjWaves * kTile];
-    const int2 bm = map[blockIdx.x];
+    const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_FAILED(it.sa.status);
     const TW* W = static_cast<const TW*>(it.W);
@@ -91,13 +92,14 @@ bool launch_project_ws(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t 
 }
 
 template <typename TW, typename TQ, bool DEFER>
-bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const int2* map, int count, int i) {
-    if (count == 0) return true;
+bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map, int64_t nblk,
+                          int i) {
+    if (nblk == 0) return true;
     const dim3 thr(kProjWaves * kWave);
     if (sketch == SK_SRHT)
-        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(count), thr, 0, st, items, map, i);
+        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_SRHT, DEFER>), dim3(nblk), thr, 0, st, items, map, i);
     else
-        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(count), thr, 0, st, items, map, i);
+        hipLaunchKernelGGL((kb_project<TW, TQ, TW, SK_GAUSS, DEFER>), dim3(nblk), thr, 0, st, items, map, i);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -121,7 +123,8 @@ template bool launch_project<double, double, false>(hipStream_t, const double*, 
 template bool launch_project<float, bf16, true>(hipStream_t, const float*, bf16*, int64_t, int64_t, int,
                                                 const float*, const double*, int, int, int, const SketchArgs&,
                                                 float*, const int*);
-template bool launch_batch_project<float, float, false>(hipStream_t, int, const BatchItem*, const int2*, int, int);
-template bool launch_batch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const int2*, int, int);
+template bool launch_batch_project<float, float, false>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
+                                                        int);
+template bool launch_batch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t, int);
 
 }  // namespace rgs

@@ -61,6 +61,8 @@ struct BatchItem {
     double* S;
     int64_t lds;
     double* P;            // k x m: sketches of the columns of W
+    void* partP;          // batched step 1: G_P x k x m block partials of P
+    int G_P;              // row groups of step 1
     void* part;           // nproj x k block partials (working precision)
     void* part2;          // GMRES, Gaussian: block partials of the next Arnoldi vector's sketch
     void* coef;           // m coefficients of the projection (working precision)
@@ -85,6 +87,17 @@ struct GmresItem {
     double *Hr, *cs, *sn, *gv, *y, *hist;   // Givens state (mcap each; gv mcap + 1)
     int* used;            // inner steps done in the current cycle
     const int* limit;     // inner steps allowed in the current cycle
+};
+
+// Implicit launch map of a batched call: the grid is the concatenation of the
+// block ranges of the listed items.  Listed position p owns blocks
+// [first(p), first(p + 1)), first(p) = base[p] + uniform * p (base: prefix sums
+// of per-item block counts, or none), and names item ids[p] (or item p).
+struct BlockMap {
+    const int64_t* base;
+    const int* ids;
+    int count;
+    int uniform;
 };
 
 }  // namespace rgs
