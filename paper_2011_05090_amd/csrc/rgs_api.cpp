@@ -317,7 +317,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
             return RGS_EDEVICE;
     }
     if constexpr (DEFER) {
-        if (!launch_scale_cols_bf16(s, Q, ldq, n, (int)m, sa.invr, sa.status)) return RGS_EDEVICE;
+        if (!launch_scale_cols_bf16(s, Q, ldq, n, (int)m, sa.invr, vec_ok ? 1 : 0, sa.status)) return RGS_EDEVICE;
     } else {
         if (!launch_scale_col<T>(s, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;
     }
@@ -608,7 +608,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     };
     const std::vector<int64_t> pre_proj = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + kProjRows - 1) / kProjRows; });
     const std::vector<int64_t> pre_sl = prefix_of(batch, [&](int64_t q) { return (it_of(q).k + kSlice - 1) / kSlice; });
-    const std::vector<int64_t> pre_row = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + 255) / 256; });
+    const std::vector<int64_t> pre_row = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + 1023) / 1024; });
     const std::vector<int64_t> pre_sign = prefix_of(batch, [&](int64_t q) { return ((it_of(q).n + 31) / 32 + 1023) / 1024; });
     const std::vector<int64_t> pre_part = prefix_of(batch, [&](int64_t q) {
         const rgs_qr_item& it = it_of(q);

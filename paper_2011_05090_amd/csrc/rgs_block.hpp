@@ -18,9 +18,41 @@ namespace rgs {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+// `vec` (aligned columns) lets a partial tile still load its complete 4-row
+// groups as vectors; the group that straddles n is read element by element.
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ p, T v[4]) {
+    if constexpr (sizeof(T) == 4) {
+        const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    } else {
+        const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+        const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void load16(const T* __restrict__ p, const int64_t row0[4], int64_t n,
-                                       bool full, T v[16]) {
+                                       bool full, T v[16], bool vec = false) {
+    if (!full && vec) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (row0[e] + 4 <= n) {
+                load4(p + row0[e], v + 4 * e);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[4 * e + r] = (row0[e] + r < n) ? p[row0[e] + r] : T(0);
+            }
+        }
+        return;
+    }
     if (full) {
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
@@ -91,7 +123,24 @@ __device__ __forceinline__ uint16_t float_to_bf16(float f) {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void load16(const bf16* __restrict__ p, const int64_t row0[4], int64_t n, bool full,
-                                       float v[16]) {
+                                       float v[16], bool vec = false) {
+    if (!full && vec) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (row0[e] + 4 <= n) {
+                const u32x2 t = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p + row0[e]));
+                v[4 * e] = __uint_as_float(t.x << 16);
+                v[4 * e + 1] = __uint_as_float(t.x & 0xFFFF0000u);
+                v[4 * e + 2] = __uint_as_float(t.y << 16);
+                v[4 * e + 3] = __uint_as_float(t.y & 0xFFFF0000u);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    v[4 * e + r] = (row0[e] + r < n) ? bf16_to_float(p[row0[e] + r].bits) : 0.f;
+            }
+        }
+        return;
+    }
     if (full) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {

@@ -40,7 +40,7 @@ bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
                    const double* pnext, T* coef, const double* cscale);
 bool launch_zero_mat(hipStream_t st, double* A, int64_t rows, int64_t cols, int64_t lda);
-bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr,
+bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr, int vec,
                             const int* status);
 bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64_t max_m2);
 template <typename T>

@@ -223,33 +223,53 @@ __global__ void k_scale_col(T* __restrict__ q, int64_t n, const double* __restri
 }
 
 // Step 7 for bf16 storage, all columns at the end: q_c = fl_bf16(fl32(q'_c / r_cc)).
+// Rows l0 .. l0+3 (l0 a multiple of 4) of every column; one 8-byte access per
+// column when the columns are aligned (vec) and the 4 rows are all below n.
 __device__ __forceinline__ void scale_cols_bf16_body(bf16* __restrict__ Q, int64_t ldq, int64_t n, int m,
-                                                     const double* __restrict__ invr, int64_t l) {
-    if (l >= n) return;
-    for (int c = 0; c < m; ++c) {
-        bf16* p = Q + l + (int64_t)c * ldq;
-        p->bits = float_to_bf16((float)((double)bf16_to_float(p->bits) * invr[c]));
+                                                     const double* __restrict__ invr, int64_t l0, bool vec) {
+    if (l0 >= n) return;
+    auto scale = [](uint32_t h, double ir) -> uint32_t {
+        return float_to_bf16((float)((double)bf16_to_float((uint16_t)h) * ir));
+    };
+    if (vec && l0 + 4 <= n) {
+        for (int c = 0; c < m; ++c) {
+            u32x2* p = reinterpret_cast<u32x2*>(Q + l0 + (int64_t)c * ldq);
+            const double ir = invr[c];
+            const u32x2 t = *p;
+            u32x2 o;
+            o.x = scale(t.x & 0xFFFFu, ir) | (scale(t.x >> 16, ir) << 16);
+            o.y = scale(t.y & 0xFFFFu, ir) | (scale(t.y >> 16, ir) << 16);
+            *p = o;
+        }
+        return;
     }
+    for (int c = 0; c < m; ++c)
+        for (int r = 0; r < 4 && l0 + r < n; ++r) {
+            bf16* p = Q + l0 + r + (int64_t)c * ldq;
+            p->bits = (uint16_t)scale(p->bits, invr[c]);
+        }
 }
 
 __global__ void k_scale_cols_bf16(bf16* __restrict__ Q, int64_t ldq, int64_t n, int m,
-                                  const double* __restrict__ invr, const int* __restrict__ status) {
+                                  const double* __restrict__ invr, int vec, const int* __restrict__ status) {
     RGS_EXIT_IF_FAILED(status);
-    scale_cols_bf16_body(Q, ldq, n, m, invr, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    scale_cols_bf16_body(Q, ldq, n, m, invr, 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x), vec != 0);
 }
 
-// Batched end of step 7: map blocks are (factorisation, block of 256 rows).
+// Batched end of step 7: map blocks are (factorisation, block of 1024 rows),
+// 4 rows per thread.
 template <typename TQ, bool DEFER>
 __global__ void kb_scale(const BatchItem* __restrict__ items, BlockMap map) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_FAILED(it.sa.status);
-    const int64_t l = (int64_t)bm.y * blockDim.x + threadIdx.x;
+    const int64_t l0 = 4 * ((int64_t)bm.y * blockDim.x + threadIdx.x);
     if constexpr (DEFER) {
-        scale_cols_bf16_body(static_cast<bf16*>(it.Q), it.ldq, it.n, it.m, it.sa.invr, l);
+        scale_cols_bf16_body(static_cast<bf16*>(it.Q), it.ldq, it.n, it.m, it.sa.invr, l0, it.vec_ok != 0);
     } else {
         TQ* q = static_cast<TQ*>(it.Q) + (int64_t)(it.m - 1) * it.ldq;
-        if (l < it.n) q[l] = (TQ)((double)q[l] * it.sa.invr[it.m - 1]);
+        for (int r = 0; r < 4; ++r)
+            if (l0 + r < it.n) q[l0 + r] = (TQ)((double)q[l0 + r] * it.sa.invr[it.m - 1]);
     }
 }
 
@@ -548,9 +568,9 @@ bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const
     return true;
 }
 
-bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr,
+bool launch_scale_cols_bf16(hipStream_t st, bf16* Q, int64_t ldq, int64_t n, int m, const double* invr, int vec,
                             const int* status) {
-    hipLaunchKernelGGL(k_scale_cols_bf16, dim3(nblocks(n, 256)), dim3(256), 0, st, Q, ldq, n, m, invr, status);
+    hipLaunchKernelGGL(k_scale_cols_bf16, dim3(nblocks(n, 1024)), dim3(256), 0, st, Q, ldq, n, m, invr, vec, status);
     RGS_LAUNCH_CHECK();
     return true;
 }

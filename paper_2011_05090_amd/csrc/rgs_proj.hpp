@@ -43,7 +43,7 @@ __device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __res
     lane_rows<NW>(blk, row0);
     const bool full = vec_ok && (blk + 1) * (NW * kTile) <= n;
     TW v[16];
-    load16(w, row0, n, full, v);
+    load16(w, row0, n, full, v, vec_ok);
     if constexpr (WSCALE) {
         if (wscale) {   // none at the first column of a cycle (w_1 = r_0)
             const double ws = wscale[0];
@@ -55,7 +55,7 @@ __device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __res
     for (int c = 0; c < jl; ++c) {
         const TW a = coef[c];
         TW q[16];
-        load16(Q + (int64_t)c * ldq, row0, n, full, q);
+        load16(Q + (int64_t)c * ldq, row0, n, full, q, vec_ok);
 #pragma unroll
         for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
     }
