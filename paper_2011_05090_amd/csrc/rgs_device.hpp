@@ -54,6 +54,7 @@ __host__ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1,
 // (q, j, sketch_id, instance).  Uniforms: u1 = ((x_a >> 9) + 1/2) 2^-23 in (0,1),
 // u2 = (x_b >> 8) 2^-24 in [0,1), both exact in fp32 and fp64;
 // z_a = sqrt(-2 ln u1) cos(2 pi u2), z_b = sqrt(-2 ln u1) sin(2 pi u2).
+// fp64: libm log and sincospi in double.
 __device__ __forceinline__ void gauss4(uint32_t q, uint32_t j, uint32_t sid, uint32_t inst,
                                        uint32_t k0, uint32_t k1, double z[4]) {
     uint32_t x[4];
@@ -70,6 +71,8 @@ __device__ __forceinline__ void gauss4(uint32_t q, uint32_t j, uint32_t sid, uin
     }
 }
 
+// fp32: hardware log2, sqrt, and sine/cosine (whose argument is in revolutions,
+// so cos(2 pi u2) is the instruction applied to u2 itself).
 __device__ __forceinline__ void gauss4(uint32_t q, uint32_t j, uint32_t sid, uint32_t inst,
                                        uint32_t k0, uint32_t k1, float z[4]) {
     uint32_t x[4];
@@ -80,10 +83,8 @@ __device__ __forceinline__ void gauss4(uint32_t q, uint32_t j, uint32_t sid, uin
         const float u2 = (float)(x[2 * h + 1] >> 8) * 0x1p-24f;
         // -2 ln u1 = -2 ln(2) log2(u1)
         const float rho = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
-        float s, c;
-        sincospif(2.0f * u2, &s, &c);
-        z[2 * h] = rho * c;
-        z[2 * h + 1] = rho * s;
+        z[2 * h] = rho * __builtin_amdgcn_cosf(u2);
+        z[2 * h + 1] = rho * __builtin_amdgcn_sinf(u2);
     }
 }
 
