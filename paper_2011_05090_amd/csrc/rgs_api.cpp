@@ -180,7 +180,8 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     // row groups of P = Theta W: 4096-row blocks (SRHT), 256-row sub-blocks (Gaussian)
     p.G_P = (int)std::min<int64_t>(sketch == SK_GAUSS ? nsub : p.nblk, 64);
     // Gaussian sketch of a single column in its own launch (below kSplitRows rows)
-    p.G_col = (sketch == SK_GAUSS && n < kSplitRows) ? (int)std::min<int64_t>(nsub, 256) : 0;
+    p.G_col = (sketch == SK_GAUSS && n < kSplitRows) ? (int)std::min<int64_t>((n + kGSubCol - 1) / kGSubCol, 256)
+                                                     : 0;
     const size_t per_col = (size_t)p.G_P * k * tsize;
     p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
     p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
@@ -305,10 +306,16 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
         const double* pnext = (i + 1 < m) ? P + (i + 1) * k : nullptr;
         if (timed) (void)hipEventRecord(h->events[2 * i], s);
         const bool sketch_col = DEFER || i > 0;
-        if (!launch_project<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
-                                          i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
-                                          (sketch_col && !split) ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status))
+        if (split) {
+            if (!launch_project_rows<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
+                                                   i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
+                                                   sa.status))
+                return RGS_EDEVICE;
+        } else if (!launch_project<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
+                                                 i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
+                                                 sketch_col ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status)) {
             return RGS_EDEVICE;
+        }
         if (split && sketch_col && !launch_gauss_cols<TQ, T>(s, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);

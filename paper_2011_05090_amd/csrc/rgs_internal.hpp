@@ -16,6 +16,7 @@ bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int 
 // Gaussian sketch partials of ncols columns (k_reduce layout, G row groups of
 // 256-row sub-blocks), each entry of Theta generated once per kGaussCols columns.
 constexpr int kGaussCols = 32;
+constexpr int kGSubCol = 64;   // rows per sub-block of the single-column Gaussian sketch
 template <typename TX, typename T>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
                        T* partials);
@@ -26,6 +27,11 @@ template <typename TW, typename TQ, bool DEFER>
 bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
                     const double* invr, int normalize_last, int do_sketch, int vec_ok, const SketchArgs& sk,
                     TW* partials, const int* status);
+// launch_project without a sketch, on small row blocks (small factorisations
+// whose column sketch is launched separately).
+template <typename TW, typename TQ, bool DEFER>
+bool launch_project_rows(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
+                         const double* invr, int normalize_last, const int* status);
 // launch_project with w_i multiplied by wscale[0] on load and no sketch (the
 // fused-sketch GMRES step).
 template <typename TW, typename TQ, bool DEFER>

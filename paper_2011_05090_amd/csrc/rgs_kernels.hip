@@ -113,27 +113,29 @@ __device__ __forceinline__ float elem_real(float v) { return v; }
 __device__ __forceinline__ double elem_real(double v) { return v; }
 __device__ __forceinline__ float elem_real(bf16 v) { return bf16_to_float(v.bits); }
 
-template <typename TX, typename T, int C>
+template <typename TX, typename T, int C, int SUB = kGSub>
 __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
                                                 const SketchArgs& sk, T* __restrict__ partials, int g, int jc,
-                                                int cc, T (*w)[kGSub]) {
+                                                int cc, T (*w)[SUB]) {
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
     const int nc = min(C, ncols - c0);
     T acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = T(0);
-    const int64_t nsub = (n + kGSub - 1) / kGSub;
+    const int64_t nsub = (n + SUB - 1) / SUB;
     for (int64_t sb = g; sb < nsub; sb += G) {
-        const int64_t r0 = sb * kGSub;
-        const int64_t l = r0 + threadIdx.x;
+        const int64_t r0 = sb * SUB;
+        for (int t = threadIdx.x; t < SUB; t += kWG) {
+            const int64_t l = r0 + t;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            w[c][threadIdx.x] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+            for (int c = 0; c < C; ++c)
+                w[c][t] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+        }
         __syncthreads();
         if (j < sk.k) {
             const int64_t rem = n - r0;
-            const int nq = rem >= kGSub ? kGSub / 4 : (int)((rem + 3) / 4);
+            const int nq = rem >= SUB ? SUB / 4 : (int)((rem + 3) / 4);
             const uint32_t q0 = (uint32_t)(r0 / 4);
             for (int q = 0; q < nq; ++q) {
                 T z[4];
@@ -154,11 +156,11 @@ __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_
     }
 }
 
-template <typename TX, typename T, int C>
+template <typename TX, typename T, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
                                                     int G, SketchArgs sk, T* __restrict__ partials) {
-    __shared__ __attribute__((aligned(16))) T w[C][kGSub];
-    gauss_cols_body<TX, T, C>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+    __shared__ __attribute__((aligned(16))) T w[C][SUB];
+    gauss_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
 // Batched step 1 (Gaussian): map blocks are (factorisation, g + G_P (jc + njc cc)).
@@ -521,12 +523,12 @@ template <typename TX, typename T>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
                        T* partials) {
     const unsigned jc = nblocks(sk.k, kWG);
-    if (ncols == 1) {
-        hipLaunchKernelGGL((k_gauss_cols<TX, T, 1>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
-                           partials);
+    if (ncols == 1) {   // the single-column sketch of a small-n step: 64-row sub-blocks
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, 1, kGSubCol>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G,
+                           sk, partials);
     } else {
-        hipLaunchKernelGGL((k_gauss_cols<TX, T, kGaussCols>), dim3(G, jc, nblocks(ncols, kGaussCols)), dim3(kWG), 0,
-                           st, X, ldx, n, ncols, G, sk, partials);
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
+                           dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
     }
     RGS_LAUNCH_CHECK();
     return true;

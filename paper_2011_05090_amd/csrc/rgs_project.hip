@@ -52,6 +52,65 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem
                                         static_cast<PT*>(it.part), bm.y, lds);
 }
 
+// The same step 3 (+ step 7 of the previous column) without a sketch, 4 rows
+// per lane and one wave per workgroup (256 rows), for factorisations too
+// small to fill the device with kProjWaves-tile blocks; their column sketch is
+// a launch of its own.  Per-element arithmetic as in project_body, so the
+// stored q'_i is the same.
+template <typename TW, typename TQ, bool DEFER>
+__global__ __launch_bounds__(64) void k_project_rows(const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq,
+                                                     int64_t n, int j, const TW* __restrict__ coef,
+                                                     const double* __restrict__ invr, int normalize_last,
+                                                     const int* __restrict__ status) {
+    RGS_EXIT_IF_FAILED(status);
+    const int64_t r0 = ((int64_t)blockIdx.x * 64 + threadIdx.x) * 4;
+    if (r0 >= n) return;
+    auto load = [&](const auto* p, TW v[4]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if constexpr (sizeof(*p) == 2)
+                v[r] = (r0 + r < n) ? (TW)bf16_to_float(p[r0 + r].bits) : TW(0);
+            else
+                v[r] = (r0 + r < n) ? (TW)p[r0 + r] : TW(0);
+        }
+    };
+    TW v[4];
+    load(w, v);
+    const int jl = (!DEFER && normalize_last) ? j - 1 : j;
+    for (int c = 0; c < jl; ++c) {
+        const TW a = coef[c];
+        TW q[4];
+        load(Q + (int64_t)c * ldq, q);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = fma(-a, q[t], v[t]);
+    }
+    if constexpr (!DEFER) {
+        if (normalize_last) {
+            const int c = j - 1;
+            const TW a = coef[c];
+            const double ir = invr[0];
+            TQ* qc = Q + (int64_t)c * ldq;
+            TW q[4];
+            load(qc, q);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                q[t] = (TW)((double)q[t] * ir);
+                if (r0 + t < n) qc[r0 + t] = q[t];
+                v[t] = fma(-a, q[t], v[t]);
+            }
+        }
+    }
+    TQ* qj = Q + (int64_t)j * ldq;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (r0 + t >= n) break;
+        if constexpr (sizeof(TQ) == 2)
+            qj[r0 + t].bits = float_to_bf16((float)v[t]);
+        else
+            qj[r0 + t] = v[t];
+    }
+}
+
 #define RGS_LAUNCH_CHECK()                                   \
     do {                                                     \
         if (hipGetLastError() != hipSuccess) return false;   \
@@ -83,6 +142,15 @@ bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, 
 }
 
 template <typename TW, typename TQ, bool DEFER>
+bool launch_project_rows(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
+                         const double* invr, int normalize_last, const int* status) {
+    hipLaunchKernelGGL((k_project_rows<TW, TQ, DEFER>), dim3(nblocks(n, 256)), dim3(64), 0, st, w, Q, ldq, n, j, coef,
+                       invr, normalize_last, status);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TW, typename TQ, bool DEFER>
 bool launch_project_ws(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, int j, const TW* coef,
                        const double* invr, int normalize_last, int vec_ok, const double* wscale, const int* status) {
     hipLaunchKernelGGL((k_project_ws<TW, TQ, DEFER>), dim3(nblocks(n, kProjRows)), dim3(kProjWaves * kWave), 0, st,
@@ -105,6 +173,12 @@ bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, co
 }
 
 // explicit instantiations
+template bool launch_project_rows<float, float, false>(hipStream_t, const float*, float*, int64_t, int64_t, int,
+                                                       const float*, const double*, int, const int*);
+template bool launch_project_rows<double, double, false>(hipStream_t, const double*, double*, int64_t, int64_t, int,
+                                                         const double*, const double*, int, const int*);
+template bool launch_project_rows<float, bf16, true>(hipStream_t, const float*, bf16*, int64_t, int64_t, int,
+                                                     const float*, const double*, int, const int*);
 template bool launch_project_ws<float, float, false>(hipStream_t, const float*, float*, int64_t, int64_t, int,
                                                      const float*, const double*, int, int, const double*,
                                                      const int*);
