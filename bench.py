@@ -198,11 +198,11 @@ def batched_qr_bytes(n, m):
 
 
 def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian"), steps=2, warmup=1,
-                   gaussian_batch=256):
+                   gaussian_batch=2048):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
     m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and bf16-stored Q, all in
-    one rgs_qr_batched call.  The Gaussian sketch regenerates its entries per
-    factorisation, so it runs on the first ``gaussian_batch`` items only."""
+    one rgs_qr_batched call, with the P-SRHT and with the Gaussian sketch (the
+    factorisations share one master Gaussian matrix)."""
     ns, ms_ = synth.batch_qr_sizes(batch)
     items = []
     t0 = time.perf_counter()

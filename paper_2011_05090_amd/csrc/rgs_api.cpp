@@ -609,19 +609,23 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
                                            [&](int64_t v, int64_t b) { return v >= items[b].m; }) -
                           order.begin());
     auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[order[q]]; };
+    // step-1 row groups: 4096-row blocks (SRHT, at most 16 groups), 16384-row chunks of the
+    // Gaussian product
     auto gp_of = [&](int64_t q) -> int64_t {
         const int64_t n = it_of(q).n;
-        return std::min<int64_t>(sk_kind == SK_GAUSS ? (n + 255) / 256 : (n + kBlock - 1) / kBlock, 16);
+        return sk_kind == SK_GAUSS ? (n + kGemmRowsP - 1) / kGemmRowsP
+                                   : std::min<int64_t>((n + kBlock - 1) / kBlock, 16);
+    };
+    auto npart_of = [&](int64_t q) -> int64_t {   // step-4 partials per column
+        const int64_t n = it_of(q).n;
+        return sk_kind == SK_GAUSS ? (n + kGemmRows - 1) / kGemmRows : (n + kProjRows - 1) / kProjRows;
     };
     const std::vector<int64_t> pre_proj = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + kProjRows - 1) / kProjRows; });
     const std::vector<int64_t> pre_sl = prefix_of(batch, [&](int64_t q) { return (it_of(q).k + kSlice - 1) / kSlice; });
     const std::vector<int64_t> pre_row = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + 1023) / 1024; });
     const std::vector<int64_t> pre_sign = prefix_of(batch, [&](int64_t q) { return ((it_of(q).n + 31) / 32 + 1023) / 1024; });
-    const std::vector<int64_t> pre_part = prefix_of(batch, [&](int64_t q) {
-        const rgs_qr_item& it = it_of(q);
-        return sk_kind == SK_GAUSS ? gp_of(q) * ((it.k + kWG - 1) / kWG) * ((it.m + kGaussCols - 1) / kGaussCols)
-                                   : gp_of(q) * it.m;
-    });
+    const std::vector<int64_t> pre_part =
+        prefix_of(batch, [&](int64_t q) { return sk_kind == SK_GAUSS ? 0 : gp_of(q) * it_of(q).m; });
     const std::vector<int64_t> pre_red = prefix_of(batch, [&](int64_t q) { return ((it_of(q).k + 31) / 32) * it_of(q).m; });
 
     struct Off {
@@ -637,7 +641,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         const int64_t nproj = (n + kProjRows - 1) / kProjRows, nsl = (k + kSlice - 1) / kSlice;
         Off& o = off[q];
         o.signs = c.take<uint32_t>(sk_kind == SK_SRHT ? (n + 31) / 32 + 4 : 1);
-        o.part = c.take<T>(nproj * k);
+        o.part = c.take<T>(std::max<int64_t>(nproj, npart_of(q)) * k);
         o.partP = c.take<T>(gp_of(q) * k * m);
         o.P = c.take<double>(k * m);
         o.Vc = c.take<double>(k * m);
@@ -664,6 +668,46 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     const size_t o_rows = c.take<int>(sk_kind == SK_SRHT ? ktot : 1), o_status = c.take<int>(4 * batch);
     const size_t o_items = c.take<BatchItem>(batch);
     const size_t o_pre = c.take<int64_t>(6 * (batch + 1));
+    // Gaussian: the step-1 product over (item, column) tiles, and per column the
+    // active items ordered by n (descending) in tiles of 64; each tile is split
+    // into work units of one row chunk and 128 sketch rows
+    const bool gemm = sk_kind == SK_GAUSS;
+    std::vector<int2> g_cols;
+    std::vector<GemmUnit> g_units;
+    std::vector<size_t> g_units_at((size_t)max_m + 2, 0);
+    auto add_tile = [&](int first, int cnt, int64_t rows) {
+        int64_t nmax = 0, kmax = 0;
+        for (int c2 = 0; c2 < cnt; ++c2) {
+            const rgs_qr_item& it = it_of(g_cols[first + c2].x);
+            nmax = std::max<int64_t>(nmax, it.n);
+            kmax = std::max<int64_t>(kmax, it.k);
+        }
+        for (int64_t blk = 0; blk < (nmax + rows - 1) / rows; ++blk)
+            for (int64_t jt = 0; jt < (kmax + 127) / 128; ++jt) g_units.push_back(GemmUnit{first, cnt, (int)blk, (int)jt});
+    };
+    if (gemm) {
+        for (int64_t q = 0; q < batch; ++q)   // step 1: 64-column tiles of each item's W
+            for (int64_t c0 = 0; c0 < it_of(q).m; c0 += 64) {
+                const int first = (int)g_cols.size(), cnt = (int)std::min<int64_t>(64, it_of(q).m - c0);
+                for (int c2 = 0; c2 < cnt; ++c2) g_cols.push_back(make_int2((int)q, (int)(c0 + c2)));
+                add_tile(first, cnt, kGemmRowsP);
+            }
+        g_units_at[0] = g_units.size();
+        std::vector<int> act;
+        for (int64_t i = 0; i < max_m; ++i) {   // step 4 of column i
+            act.resize((size_t)active[i]);
+            for (int q = 0; q < active[i]; ++q) act[q] = q;
+            std::stable_sort(act.begin(), act.end(), [&](int a, int b) { return it_of(a).n > it_of(b).n; });
+            for (int t0 = 0; t0 < active[i]; t0 += 64) {
+                const int first = (int)g_cols.size(), cnt = std::min(64, active[i] - t0);
+                for (int c2 = 0; c2 < cnt; ++c2) g_cols.push_back(make_int2(act[t0 + c2], (int)i));
+                add_tile(first, cnt, kGemmRows);
+            }
+            g_units_at[i + 1] = g_units.size();
+        }
+    }
+    const size_t o_gcols = c.take<int2>(std::max<size_t>(g_cols.size(), 1));
+    const size_t o_gunits = c.take<GemmUnit>(std::max<size_t>(g_units.size(), 1));
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -680,6 +724,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         x.m = (int)it.m;
         x.k = (int)it.k;
         x.nproj = (int)((it.n + kProjRows - 1) / kProjRows);
+        x.npart = (int)npart_of(q);
         x.nsl = (int)((it.k + kSlice - 1) / kSlice);
         x.W = it.W;
         x.ldw = it.ldw;
@@ -698,6 +743,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         x.vec_ok = (it.ldq % 4 == 0) && (it.ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.Q) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(it.W) & 15) == 0);
         x.defer = DEFER ? 1 : 0;
+        x.gemm_sketch = gemm ? 1 : 0;
         SpaceArgs& a = x.sa;
         a.k = (int)it.k;
         a.mcap = (int)it.m;
@@ -740,7 +786,11 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipMemcpyAsync(pre_dev, pre_all.data(), pre_all.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
+            hipSuccess ||
+        (gemm && (hipMemcpyAsync(A + o_gcols, g_cols.data(), g_cols.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                 s) != hipSuccess ||
+                  hipMemcpyAsync(A + o_gunits, g_units.data(), g_units.size() * sizeof(GemmUnit),
+                                 hipMemcpyHostToDevice, s) != hipSuccess)))
         return RGS_EDEVICE;
     const BatchItem* itd = reinterpret_cast<const BatchItem*>(A + o_items);
     const int64_t* d_proj = pre_dev;
@@ -751,7 +801,11 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     const int64_t* d_red = pre_dev + 5 * (batch + 1);
     const int nb = (int)batch;
     if (!launch_batch_init(s, itd, nb, max_m * max_m)) return RGS_EDEVICE;
+    const GemmUnit* d_units = reinterpret_cast<const GemmUnit*>(A + o_gunits);
+    const int2* d_cols = reinterpret_cast<const int2*>(A + o_gcols);
     // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
+    if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, d_units, (int)g_units_at[0], d_cols, (int)kGemmRowsP))
+        return RGS_EDEVICE;
     if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, pre_sign[batch],
                                   BlockMap{d_part, nullptr, nb, 0}, pre_part[batch], BlockMap{d_red, nullptr, nb, 0},
                                   pre_red[batch]))
@@ -760,6 +814,10 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         const int a = active[i], a1 = active[i + 1];
         const int rb = (int)((i + 1 + 63) / 64);
         if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, BlockMap{d_proj, nullptr, a, 0}, pre_proj[a], (int)i))
+            return RGS_EDEVICE;
+        if (gemm && (DEFER || i > 0) &&
+            !launch_batch_gauss_gemm<TQ, true>(s, itd, d_units + g_units_at[i], (int)(g_units_at[i + 1] - g_units_at[i]),
+                                               d_cols, (int)kGemmRows))
             return RGS_EDEVICE;
         if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, pre_sl[a], BlockMap{d_sl, nullptr, a, rb},
                                     pre_sl[a] + (int64_t)rb * a, BlockMap{nullptr, nullptr, a1, rb},
@@ -922,6 +980,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         x.m = (int)mcap;
         x.k = (int)k;
         x.nproj = (int)((n + kProjRows - 1) / kProjRows);
+        x.npart = x.nproj;
         x.nsl = (int)nsl;
         x.Q = A + o.Q;
         x.ldq = (n + 3) / 4 * 4;   // 16-byte aligned columns

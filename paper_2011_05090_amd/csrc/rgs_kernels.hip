@@ -175,6 +175,135 @@ __global__ __launch_bounds__(kWG) void kb_gauss_cols(const BatchItem* __restrict
                                       static_cast<T*>(it.partP), bm.y % it.G_P, rest % njc, rest / njc, w);
 }
 
+// ---------------------------------------------------------------------------
+// The batched Gaussian sketch as dense products with the shared master matrix
+// Z (instance 0; item b uses Z[0:k_b, 0:n_b] / sqrt(k_b)): for a tile of up to
+// 64 operand columns x (each a column of some item's W or Q) and a chunk of
+// `rows` rows, partial[x, j] = sum over the chunk's rows l of Z[j, l] x[l] --
+// a (sketch rows) x (rows) times (rows) x (columns) product, done with fp32
+// MFMA 32x32x2 (fp32 inputs: Z exact in fp32, x exact from bf16 or fp32;
+// fp32 accumulation, as the VALU sketches).  Z is generated in registers, each
+// entry once per work unit: wave w owns sketch rows 128 jt + 32 w + (0..31);
+// lane L (jr = L % 32, kk = L / 32) draws the Philox quad of rows r + 4 kk ..
+// r + 4 kk + 3 for sketch row jr, which is exactly its A operand for the four
+// k-steps over rows r .. r + 7 (k-slot kk of step t is row r + 4 kk + t).  Its
+// B operand for column x = L % 32 of each 32-column sub-tile is the same 4 rows
+// of that column; the next 8 rows are loaded while the current ones are used.
+// Accumulator t of the 32x32 result is sketch row 8 (t / 4) + 4 kk + t % 4 of
+// column L % 32.
+//   STEP4: the columns are column i of the listed items' Q (step 4 of the
+//   column step; partial of chunk blk -> part[blk k_b + j]);
+//   otherwise columns of W (step 1; partial of chunk blk of column c ->
+//   partP[(c G_P + blk) k_b + j]).
+// ---------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Rows r .. r+3 of a column (zeros past n); one 8-byte (bf16) or 16-byte
+// (fp32) load when they are all present and the column is aligned.
+template <typename TB>
+__device__ __forceinline__ void ld4_rows(const TB* __restrict__ col, int64_t r, int64_t n, bool vec, float v[4]) {
+    if constexpr (sizeof(TB) == 2) {
+        const bf16* c = reinterpret_cast<const bf16*>(col);
+        if (vec && r + 4 <= n) {
+            const u32x2 t = *reinterpret_cast<const u32x2*>(c + r);
+            v[0] = __uint_as_float(t.x << 16);
+            v[1] = __uint_as_float(t.x & 0xFFFF0000u);
+            v[2] = __uint_as_float(t.y << 16);
+            v[3] = __uint_as_float(t.y & 0xFFFF0000u);
+            return;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = (r + t < n) ? bf16_to_float(c[r + t].bits) : 0.f;
+    } else {
+        if (vec && r + 4 <= n) {
+            const f32x4 t = *reinterpret_cast<const f32x4*>(col + r);
+            v[0] = t.x;
+            v[1] = t.y;
+            v[2] = t.z;
+            v[3] = t.w;
+            return;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = (r + t < n) ? (float)col[r + t] : 0.f;
+    }
+}
+
+template <typename TB, bool STEP4>
+__global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict__ items,
+                                                     const GemmUnit* __restrict__ units, const int2* __restrict__ cols,
+                                                     int rows) {
+    const GemmUnit un = units[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int jr = lane & 31, kk = lane >> 5;
+    const int j = un.jt * 128 + wave * 32 + jr;   // this lane's sketch row (A operand)
+    const TB* col[2];
+    int64_t nb[2];
+    bool vec[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {   // B operand: column x = lane % 32 of each sub-tile
+        const int c = s2 * 32 + jr;
+        col[s2] = nullptr;
+        nb[s2] = 0;
+        vec[s2] = false;
+        if (c < un.count) {
+            const int2 ic = cols[un.first + c];
+            const BatchItem& it = items[ic.x];
+            col[s2] = STEP4 ? static_cast<const TB*>(it.Q) + (int64_t)ic.y * it.ldq
+                            : static_cast<const TB*>(it.W) + (int64_t)ic.y * it.ldw;
+            nb[s2] = it.n;
+            vec[s2] = it.vec_ok != 0;
+        }
+    }
+    int kmax = 0;
+    int64_t nmax = 0;
+    for (int c = 0; c < un.count; ++c) {
+        const BatchItem& it = items[cols[un.first + c].x];
+        kmax = max(kmax, it.k);
+        nmax = max(nmax, it.n);
+    }
+    const SketchArgs& sk = items[cols[un.first].x].sk;   // seed, sketch id, instance: shared
+    const int64_t r_begin = (int64_t)un.blk * rows;
+    const int64_t r_end = min(r_begin + (int64_t)rows, nmax);
+    f32x16 acc0 = {0}, acc1 = {0};
+    float b0[4], b1[4];
+    ld4_rows(col[0], r_begin + 4 * kk, col[0] ? nb[0] : 0, vec[0], b0);
+    ld4_rows(col[1], r_begin + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
+    for (int64_t r = r_begin; r < r_end; r += 8) {
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        if (j < kmax) gauss4((uint32_t)(r / 4 + kk), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+        float c0[4], c1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            c0[t] = b0[t];
+            c1[t] = b1[t];
+        }
+        if (r + 8 < r_end) {   // next 8 rows while these are used
+            ld4_rows(col[0], r + 8 + 4 * kk, col[0] ? nb[0] : 0, vec[0], b0);
+            ld4_rows(col[1], r + 8 + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c0[t], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c1[t], acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const int c = s2 * 32 + jr;
+        if (c >= un.count) continue;
+        const int2 ic = cols[un.first + c];
+        const BatchItem& it = items[ic.x];
+        if (r_begin >= it.n) continue;
+        float* out = STEP4 ? static_cast<float*>(it.part) + (int64_t)un.blk * it.k
+                           : static_cast<float*>(it.partP) + ((int64_t)ic.y * it.G_P + un.blk) * it.k;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int jj = un.jt * 128 + wave * 32 + 8 * (t / 4) + 4 * kk + (t % 4);
+            if (jj < it.k) out[jj] = s2 ? acc1[t] : acc0[t];
+        }
+    }
+}
+
 // out[j + col*ldo] = scale * sum_{g=0}^{G-1} partials[(col*G + g)*k + j], in fp64 and
 // in a fixed order: 8 contiguous g-ranges summed by 8 threads, then combined in order.
 template <typename PT>
@@ -364,7 +493,7 @@ __global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const bool from_p = (i == 0 && !it.defer && it.P != nullptr);   // GMRES systems carry no P
-    qa_body<PT>(static_cast<const PT*>(it.part), it.nproj, it.sketch_scale, from_p ? it.P : nullptr, a.k, i, a.Wr,
+    qa_body<PT>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, from_p ? it.P : nullptr, a.k, i, a.Wr,
                 a.mcap, a.sp, a.pd, bm.y);
 }
 
@@ -530,6 +659,15 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
         hipLaunchKernelGGL((k_gauss_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
                            dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
     }
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TB, bool STEP4>
+bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
+                             const int2* cols, int rows) {
+    if (nunits == 0) return true;
+    hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -726,6 +864,11 @@ template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const f
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
                                             double*, const double*);
+template bool launch_batch_gauss_gemm<float, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
+                                                   int);
+template bool launch_batch_gauss_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*, int);
+template bool launch_batch_gauss_gemm<float, false>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
+                                                    int);
 template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
                                           const BlockMap&, int64_t, const BlockMap&, int64_t);
 template bool launch_gauss_cols<float, float>(hipStream_t, const float*, int64_t, int64_t, int, int,

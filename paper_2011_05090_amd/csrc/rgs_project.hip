@@ -48,7 +48,8 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem
     const TW* W = static_cast<const TW*>(it.W);
     project_body<TW, TQ, PT, SK, DEFER>(W + (int64_t)i * it.ldw, static_cast<TQ*>(it.Q), it.ldq, it.n, i,
                                         static_cast<const TW*>(it.coef), i > 0 ? it.sa.invr + (i - 1) : nullptr,
-                                        (!DEFER && i > 0) ? 1 : 0, (DEFER || i > 0) ? 1 : 0, it.vec_ok, it.sk,
+                                        (!DEFER && i > 0) ? 1 : 0, ((DEFER || i > 0) && !it.gemm_sketch) ? 1 : 0,
+                                        it.vec_ok, it.sk,
                                         static_cast<PT*>(it.part), bm.y, lds);
 }
 

@@ -52,6 +52,8 @@ struct SpaceArgs {
 struct BatchItem {
     int64_t n;
     int m, k, nproj, nsl;
+    int npart;            // block partials of step 4 reduced by the column step (nproj, or the
+                          // 2048-row chunks of the batched Gaussian sketch product)
     const void* W;
     int64_t ldw;
     void* Q;
@@ -68,6 +70,7 @@ struct BatchItem {
     void* coef;           // m coefficients of the projection (working precision)
     double sketch_scale;  // 1 / sqrt(k)
     int vec_ok, defer;
+    int gemm_sketch;      // batched Gaussian: step 4 by the shared-Theta MFMA kernel, not in the projection
     SpaceArgs sa;
     SketchArgs sk;
 };
@@ -98,6 +101,13 @@ struct BlockMap {
     const int* ids;
     int count;
     int uniform;
+};
+
+// One work unit of the batched Gaussian sketch product: the operand columns
+// at positions [first, first + count) of the launch's (item, column) list (at
+// most 64), row chunk blk, sketch rows [128 jt, 128 jt + 128).
+struct GemmUnit {
+    int first, count, blk, jt;
 };
 
 }  // namespace rgs
