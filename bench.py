@@ -237,6 +237,8 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
         for W, Q, R, S, _ in its[:: max(1, len(its) // 8)]:
             be, d2, _ = quality(torch, W, Q.float(), R, S)
             worst_be, worst_d2 = max(worst_be, be), max(worst_d2, d2)
+        if sketch == "gaussian":
+            out["gaussian_schedule"] = rgs.rgs_last_tuning(h)   # autotuned sketch-product schedule (1..4)
         out[sketch] = {"items": len(its), "seconds": dt, "algorithmic_bytes": B, "gbs": B / dt / 1e9,
                        "pct_hbm_peak": 100.0 * B / dt / 1e9 / HBM_PEAK_GBS, "failed_items": bad,
                        "status": rep.status, "sampled_max_backward_error": worst_be,

@@ -165,6 +165,18 @@ rgs_status rgs_destroy(rgs_handle *h);
 /* Re-bind the handle to another stream of the same device. */
 rgs_status rgs_set_stream(rgs_handle *h, rgs_stream stream);
 
+/* Autotuner of the batched Gaussian sketch product (rgs_qr_batched with the
+ * Gaussian sketch).  Its schedules -- 64 or 32 operand columns per work unit,
+ * units in plain or XCD-grouped order -- give identical results; with
+ * mode 0 (default) the handle times the four on the first column step of the
+ * first call for a batch signature (precision and every (n, m, k)) and keeps
+ * the fastest for later calls with that signature; mode 1..4 always uses that
+ * schedule (1: 64/plain, 2: 64/XCD, 3: 32/plain, 4: 32/XCD).  EINVAL otherwise. */
+rgs_status rgs_set_tuning(rgs_handle *h, int32_t mode);
+
+/* The schedule (1..4) the last batched Gaussian QR on this handle used, 0 if none. */
+int32_t rgs_last_tuning(const rgs_handle *h);
+
 /* RGS QR factorisation, Algorithm 2 (Sec. 2.3), W = Q R.
  *   W  [n x m, ldw >= n] input, element type per desc->prec.
  *   Q  [n x m, ldq >= n] output, same element type; Q = W R^-1 is orthonormal

@@ -86,6 +86,8 @@ SIGNATURES = {
     "rgs_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
     "rgs_destroy": (ctypes.c_int, [_P]),
     "rgs_set_stream": (ctypes.c_int, [_P, _P]),
+    "rgs_set_tuning": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "rgs_last_tuning": (ctypes.c_int32, [_P]),
     "rgs_qr": (ctypes.c_int, [_P, _DESCP, _P, _I64, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(Report)]),
     "rgs_sketch_apply": (ctypes.c_int, [_P, _DESCP, _P, _I64, _I64, _P, _I64]),
     "rgs_sketch_materialize": (ctypes.c_int, [_P, _DESCP, _I64, _I64, _I64, _I64, _P, _I64]),
@@ -252,6 +254,15 @@ def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id
     _check(st, "rgs_qr_batched", allow)
     rep.status = st
     return rep, list(stat), list(fcol)
+
+
+def rgs_set_tuning(handle, mode):
+    """0: autotune the batched Gaussian sketch product per batch signature; 1..4: force a schedule."""
+    _check(lib().rgs_set_tuning(handle.ptr, int(mode)), "rgs_set_tuning")
+
+
+def rgs_last_tuning(handle):
+    return int(lib().rgs_last_tuning(handle.ptr))
 
 
 def rgs_sketch_apply(handle, desc, X, Y):

@@ -28,6 +28,11 @@ struct rgs_handle {
     char* arena = nullptr;
     size_t arena_bytes = 0;
     std::vector<hipEvent_t> events;
+    // autotuner of the batched Gaussian sketch product: schedule chosen per
+    // batch signature (1-based index into kGemmSchedules), tuning mode
+    std::unordered_map<uint64_t, int> gemm_tuned;
+    int tune_mode = 0;        // 0: tune on first use, s > 0: always schedule s
+    int last_schedule = 0;    // schedule used by the last batched Gaussian call
 };
 
 namespace {
@@ -591,6 +596,38 @@ void parallel_for(int64_t count, F f) {
     for (auto& x : th) x.join();
 }
 
+// Schedules of the batched Gaussian sketch product that the autotuner picks
+// from: columns per work unit, and the order of the units in the launch --
+// plain, or XCD-grouped (the units of one (column tile, row chunk) pair, which
+// read the same operand columns, are placed 8 apart so that the round-robin
+// dispatch over the 8 XCDs puts them on the same L2).  Every schedule gives
+// the same bits: each partial is one unit's fixed-order sum.
+struct GemmSchedule {
+    int tile, xcd;
+};
+constexpr GemmSchedule kGemmSchedules[4] = {{64, 0}, {64, 1}, {32, 0}, {32, 1}};
+
+void order_units(const std::vector<GemmUnit>& in, size_t a, size_t b, int xcd, std::vector<GemmUnit>& out) {
+    if (!xcd) {
+        out.insert(out.end(), in.begin() + a, in.begin() + b);
+        return;
+    }
+    // group = consecutive units with the same (first, blk); queue = group index mod 8
+    std::vector<std::vector<GemmUnit>> q(8);
+    int g = -1;
+    for (size_t u = a; u < b; ++u) {
+        if (u == a || in[u].first != in[u - 1].first || in[u].blk != in[u - 1].blk) ++g;
+        q[g % 8].push_back(in[u]);
+    }
+    std::vector<size_t> pos(8, 0);
+    for (size_t done = 0; done < b - a;)
+        for (int x = 0; x < 8; ++x)
+            if (pos[x] < q[x].size()) {
+                out.push_back(q[x][pos[x]++]);
+                ++done;
+            }
+}
+
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
                           uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
@@ -673,9 +710,10 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     // into work units of one row chunk and 128 sketch rows
     const bool gemm = sk_kind == SK_GAUSS;
     std::vector<int2> g_cols;
-    std::vector<GemmUnit> g_units;
-    std::vector<size_t> g_units_at((size_t)max_m + 2, 0);
-    auto add_tile = [&](int first, int cnt, int64_t rows) {
+    std::vector<GemmUnit> g_units_p;                    // step 1
+    std::vector<GemmUnit> g_units[2];                   // step 4, tile widths 64 and 32, all columns
+    std::vector<size_t> g_at[2];                        // per column offsets into g_units[w]
+    auto add_tile = [&](std::vector<GemmUnit>& out, int first, int cnt, int64_t rows) {
         int64_t nmax = 0, kmax = 0;
         for (int c2 = 0; c2 < cnt; ++c2) {
             const rgs_qr_item& it = it_of(g_cols[first + c2].x);
@@ -683,31 +721,47 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
             kmax = std::max<int64_t>(kmax, it.k);
         }
         for (int64_t blk = 0; blk < (nmax + rows - 1) / rows; ++blk)
-            for (int64_t jt = 0; jt < (kmax + 127) / 128; ++jt) g_units.push_back(GemmUnit{first, cnt, (int)blk, (int)jt});
+            for (int64_t jt = 0; jt < (kmax + 127) / 128; ++jt) out.push_back(GemmUnit{first, cnt, (int)blk, (int)jt});
     };
     if (gemm) {
         for (int64_t q = 0; q < batch; ++q)   // step 1: 64-column tiles of each item's W
             for (int64_t c0 = 0; c0 < it_of(q).m; c0 += 64) {
                 const int first = (int)g_cols.size(), cnt = (int)std::min<int64_t>(64, it_of(q).m - c0);
                 for (int c2 = 0; c2 < cnt; ++c2) g_cols.push_back(make_int2((int)q, (int)(c0 + c2)));
-                add_tile(first, cnt, kGemmRowsP);
+                add_tile(g_units_p, first, cnt, kGemmRowsP);
             }
-        g_units_at[0] = g_units.size();
         std::vector<int> act;
-        for (int64_t i = 0; i < max_m; ++i) {   // step 4 of column i
+        for (int w = 0; w < 2; ++w) g_at[w].assign((size_t)max_m + 1, 0);
+        for (int64_t i = 0; i < max_m; ++i) {   // step 4 of column i: active items ordered by n
             act.resize((size_t)active[i]);
             for (int q = 0; q < active[i]; ++q) act[q] = q;
             std::stable_sort(act.begin(), act.end(), [&](int a, int b) { return it_of(a).n > it_of(b).n; });
-            for (int t0 = 0; t0 < active[i]; t0 += 64) {
-                const int first = (int)g_cols.size(), cnt = std::min(64, active[i] - t0);
-                for (int c2 = 0; c2 < cnt; ++c2) g_cols.push_back(make_int2(act[t0 + c2], (int)i));
-                add_tile(first, cnt, kGemmRows);
+            const int base = (int)g_cols.size();
+            for (int q = 0; q < active[i]; ++q) g_cols.push_back(make_int2(act[q], (int)i));
+            for (int w = 0; w < 2; ++w) {
+                const int tile = kGemmSchedules[2 * w].tile;
+                for (int t0 = 0; t0 < active[i]; t0 += tile)
+                    add_tile(g_units[w], base + t0, std::min(tile, active[i] - t0), kGemmRows);
+                g_at[w][i + 1] = g_units[w].size();
             }
-            g_units_at[i + 1] = g_units.size();
         }
     }
+    const size_t n_units_max = std::max(g_units[0].size(), g_units[1].size());
     const size_t o_gcols = c.take<int2>(std::max<size_t>(g_cols.size(), 1));
-    const size_t o_gunits = c.take<GemmUnit>(std::max<size_t>(g_units.size(), 1));
+    const size_t o_gunits_p = c.take<GemmUnit>(std::max<size_t>(g_units_p.size(), 1));
+    const size_t o_gunits = c.take<GemmUnit>(std::max<size_t>(n_units_max, 1));
+    const size_t o_gtune = c.take<GemmUnit>(gemm ? 4 * std::max<size_t>(1, std::max(g_at[0].size() > 2 ? g_at[0][2] : 0,
+                                                                                      g_at[1].size() > 2 ? g_at[1][2] : 0))
+                                                 : 1);
+    // the batch signature of the tuning cache: precision and every (n, m, k)
+    uint64_t sig = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+    mix((uint64_t)DEFER);
+    for (int64_t q = 0; q < batch; ++q) {
+        mix((uint64_t)it_of(q).n);
+        mix((uint64_t)it_of(q).m);
+        mix((uint64_t)it_of(q).k);
+    }
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -789,7 +843,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
             hipSuccess ||
         (gemm && (hipMemcpyAsync(A + o_gcols, g_cols.data(), g_cols.size() * sizeof(int2), hipMemcpyHostToDevice,
                                  s) != hipSuccess ||
-                  hipMemcpyAsync(A + o_gunits, g_units.data(), g_units.size() * sizeof(GemmUnit),
+                  hipMemcpyAsync(A + o_gunits_p, g_units_p.data(), g_units_p.size() * sizeof(GemmUnit),
                                  hipMemcpyHostToDevice, s) != hipSuccess)))
         return RGS_EDEVICE;
     const BatchItem* itd = reinterpret_cast<const BatchItem*>(A + o_items);
@@ -801,11 +855,32 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     const int64_t* d_red = pre_dev + 5 * (batch + 1);
     const int nb = (int)batch;
     if (!launch_batch_init(s, itd, nb, max_m * max_m)) return RGS_EDEVICE;
-    const GemmUnit* d_units = reinterpret_cast<const GemmUnit*>(A + o_gunits);
+    GemmUnit* d_units = reinterpret_cast<GemmUnit*>(A + o_gunits);
+    GemmUnit* d_tune = reinterpret_cast<GemmUnit*>(A + o_gtune);
     const int2* d_cols = reinterpret_cast<const int2*>(A + o_gcols);
     // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
-    if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, d_units, (int)g_units_at[0], d_cols, (int)kGemmRowsP))
+    if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, reinterpret_cast<const GemmUnit*>(A + o_gunits_p),
+                                                   (int)g_units_p.size(), d_cols, (int)kGemmRowsP, 64))
         return RGS_EDEVICE;
+    // step-4 schedule: cached for this batch signature, forced, or tuned at the first
+    // column that needs the product (the schedules give the same bits, so the
+    // timing launches leave nothing behind)
+    int sched = 0;
+    std::vector<GemmUnit> sched_units;   // stays alive until the final synchronisation
+    if (gemm) {
+        if (h->tune_mode > 0) sched = h->tune_mode;
+        else if (h->gemm_tuned.count(sig)) sched = h->gemm_tuned[sig];
+    }
+    auto upload_schedule = [&](int sc) -> bool {
+        const int w = kGemmSchedules[sc - 1].tile == 64 ? 0 : 1;
+        sched_units.clear();
+        for (int64_t i = 0; i < max_m; ++i)
+            order_units(g_units[w], g_at[w][i], g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, sched_units);
+        return hipMemcpyAsync(d_units, sched_units.data(), sched_units.size() * sizeof(GemmUnit),
+                              hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    if (gemm && sched > 0 && !upload_schedule(sched)) return RGS_EDEVICE;
+    const int64_t i_tune = DEFER ? 0 : 1;
     if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, pre_sign[batch],
                                   BlockMap{d_part, nullptr, nb, 0}, pre_part[batch], BlockMap{d_red, nullptr, nb, 0},
                                   pre_red[batch]))
@@ -815,10 +890,46 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         const int rb = (int)((i + 1 + 63) / 64);
         if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, BlockMap{d_proj, nullptr, a, 0}, pre_proj[a], (int)i))
             return RGS_EDEVICE;
-        if (gemm && (DEFER || i > 0) &&
-            !launch_batch_gauss_gemm<TQ, true>(s, itd, d_units + g_units_at[i], (int)(g_units_at[i + 1] - g_units_at[i]),
-                                               d_cols, (int)kGemmRows))
-            return RGS_EDEVICE;
+        if (gemm && sched == 0 && i == i_tune) {
+            // time the four schedules on this column's product, keep the fastest
+            std::vector<GemmUnit> tu[4];
+            size_t off_t[5] = {0, 0, 0, 0, 0};
+            for (int sc = 1; sc <= 4; ++sc) {
+                const int w = kGemmSchedules[sc - 1].tile == 64 ? 0 : 1;
+                order_units(g_units[w], g_at[w][i], g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, tu[sc - 1]);
+                off_t[sc] = off_t[sc - 1] + tu[sc - 1].size();
+                if (hipMemcpyAsync(d_tune + off_t[sc - 1], tu[sc - 1].data(), tu[sc - 1].size() * sizeof(GemmUnit),
+                                   hipMemcpyHostToDevice, s) != hipSuccess)
+                    return RGS_EDEVICE;
+            }
+            if (ensure_events(h, 10) != RGS_OK) return RGS_EDEVICE;
+            for (int rep2 = 0; rep2 < 2; ++rep2)   // the first round warms the caches
+                for (int sc = 1; sc <= 4; ++sc) {
+                    (void)hipEventRecord(h->events[2 * sc - 2], s);
+                    if (!launch_batch_gauss_gemm<TQ, true>(s, itd, d_tune + off_t[sc - 1], (int)tu[sc - 1].size(),
+                                                           d_cols, (int)kGemmRows, kGemmSchedules[sc - 1].tile))
+                        return RGS_EDEVICE;
+                    (void)hipEventRecord(h->events[2 * sc - 1], s);
+                }
+            if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+            float best = 0.f;
+            for (int sc = 1; sc <= 4; ++sc) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, h->events[2 * sc - 2], h->events[2 * sc - 1]);
+                if (sched == 0 || ms < best) {
+                    best = ms;
+                    sched = sc;
+                }
+            }
+            h->gemm_tuned[sig] = sched;
+            if (!upload_schedule(sched)) return RGS_EDEVICE;
+        }
+        if (gemm && (DEFER || i > 0)) {
+            const int w = kGemmSchedules[sched - 1].tile == 64 ? 0 : 1;
+            if (!launch_batch_gauss_gemm<TQ, true>(s, itd, d_units + g_at[w][i], (int)(g_at[w][i + 1] - g_at[w][i]),
+                                                   d_cols, (int)kGemmRows, kGemmSchedules[sched - 1].tile))
+                return RGS_EDEVICE;
+        }
         if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, pre_sl[a], BlockMap{d_sl, nullptr, a, rb},
                                     pre_sl[a] + (int64_t)rb * a, BlockMap{nullptr, nullptr, a1, rb},
                                     (int64_t)rb * a1, (int)i))
@@ -842,6 +953,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         if (failed_column) failed_column[b] = fc[b];
         if (sb[b] != RGS_OK && result == RGS_OK) result = sb[b];
     }
+    if (gemm) h->last_schedule = sched;
     const auto t1 = std::chrono::steady_clock::now();
     if (rep) {
         rep->failed_column = -1;
@@ -1302,6 +1414,14 @@ rgs_status rgs_destroy(rgs_handle* h) {
     delete h;
     return RGS_OK;
 }
+
+rgs_status rgs_set_tuning(rgs_handle* h, int32_t mode) {
+    if (!h || mode < 0 || mode > 4) return RGS_EINVAL;
+    h->tune_mode = mode;
+    return RGS_OK;
+}
+
+int32_t rgs_last_tuning(const rgs_handle* h) { return h ? h->last_schedule : 0; }
 
 rgs_status rgs_set_stream(rgs_handle* h, rgs_stream stream) {
     if (!h) return RGS_EINVAL;

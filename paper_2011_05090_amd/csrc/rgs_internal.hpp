@@ -54,14 +54,15 @@ bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, c
                            int64_t n_signs, const BlockMap& map_part, int64_t n_part, const BlockMap& map_red,
                            int64_t n_red);
 // Batched Gaussian sketch products with the shared master matrix, one
-// workgroup per GemmUnit over the (item, column) list `cols`: STEP4, column i
+// workgroup per GemmUnit over the (item, column) list `cols` (tile: 32 or 64
+// columns per unit, as the units were built): STEP4, column i
 // of Q (partials per `rows`-row chunk into part); otherwise columns of W
 // (partials per chunk into partP, G_P chunks per column).
 constexpr int kGemmRows = 2048;      // row chunk of the step-4 product
 constexpr int kGemmRowsP = 16384;    // row chunk of the step-1 product
 template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
-                             const int2* cols, int rows);
+                             const int2* cols, int rows, int tile);
 template <typename TW, typename TQ, bool DEFER>
 bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map, int64_t nblk,
                           int i);

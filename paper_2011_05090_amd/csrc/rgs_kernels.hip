@@ -228,7 +228,7 @@ __device__ __forceinline__ void ld4_rows(const TB* __restrict__ col, int64_t r, 
     }
 }
 
-template <typename TB, bool STEP4>
+template <typename TB, bool STEP4, int NSUB>
 __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict__ items,
                                                      const GemmUnit* __restrict__ units, const int2* __restrict__ cols,
                                                      int rows) {
@@ -240,12 +240,12 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
     int64_t nb[2];
     bool vec[2];
 #pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {   // B operand: column x = lane % 32 of each sub-tile
+    for (int s2 = 0; s2 < 2; ++s2) {   // B operand: column x = lane % 32 of each sub-tile (NSUB of them)
         const int c = s2 * 32 + jr;
         col[s2] = nullptr;
         nb[s2] = 0;
         vec[s2] = false;
-        if (c < un.count) {
+        if (s2 < NSUB && c < un.count) {
             const int2 ic = cols[un.first + c];
             const BatchItem& it = items[ic.x];
             col[s2] = STEP4 ? static_cast<const TB*>(it.Q) + (int64_t)ic.y * it.ldq
@@ -265,13 +265,13 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
     const int64_t r_begin = (int64_t)un.blk * rows;
     const int64_t r_end = min(r_begin + (int64_t)rows, nmax);
     f32x16 acc0 = {0}, acc1 = {0};
-    float b0[4], b1[4];
+    float b0[4], b1[4] = {0.f, 0.f, 0.f, 0.f};
     ld4_rows(col[0], r_begin + 4 * kk, col[0] ? nb[0] : 0, vec[0], b0);
-    ld4_rows(col[1], r_begin + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
+    if (NSUB > 1) ld4_rows(col[1], r_begin + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
     for (int64_t r = r_begin; r < r_end; r += 8) {
         float z[4] = {0.f, 0.f, 0.f, 0.f};
         if (j < kmax) gauss4((uint32_t)(r / 4 + kk), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
-        float c0[4], c1[4];
+        float c0[4], c1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             c0[t] = b0[t];
@@ -279,16 +279,16 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
         }
         if (r + 8 < r_end) {   // next 8 rows while these are used
             ld4_rows(col[0], r + 8 + 4 * kk, col[0] ? nb[0] : 0, vec[0], b0);
-            ld4_rows(col[1], r + 8 + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
+            if (NSUB > 1) ld4_rows(col[1], r + 8 + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c0[t], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c1[t], acc1, 0, 0, 0);
+            if (NSUB > 1) acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c1[t], acc1, 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
+    for (int s2 = 0; s2 < NSUB; ++s2) {
         const int c = s2 * 32 + jr;
         if (c >= un.count) continue;
         const int2 ic = cols[un.first + c];
@@ -665,9 +665,12 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
 
 template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
-                             const int2* cols, int rows) {
+                             const int2* cols, int rows, int tile) {
     if (nunits == 0) return true;
-    hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
+    if (tile <= 32)
+        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 1>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
+    else
+        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -865,10 +868,11 @@ template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
                                             double*, const double*);
 template bool launch_batch_gauss_gemm<float, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
-                                                   int);
-template bool launch_batch_gauss_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*, int);
+                                                   int, int);
+template bool launch_batch_gauss_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*, int,
+                                                  int);
 template bool launch_batch_gauss_gemm<float, false>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
-                                                    int);
+                                                    int, int);
 template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
                                           const BlockMap&, int64_t, const BlockMap&, int64_t);
 template bool launch_gauss_cols<float, float>(hipStream_t, const float*, int64_t, int64_t, int, int,

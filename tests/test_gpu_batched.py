@@ -199,3 +199,34 @@ def test_batched_gaussian_many_items_matches_oracle(gpu_handle):
             # two runs round differently: Delta is compared as a distribution over items
             # (no bias: median near 1; single items within a few times).
             assert np.median(ratios) <= 1.5 and max(ratios) <= 4.0, ratios
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16q"])
+def test_gaussian_schedules_give_identical_bits(gpu_handle, prec):
+    """The autotuner's four schedules of the batched Gaussian sketch product
+    (32 / 64 columns per unit, plain / XCD-grouped order) produce the same
+    bits; the automatic mode picks one of them and keeps it for the signature."""
+    rgs = _rgs()
+    qd = torch.bfloat16 if prec == "bf16q" else torch.float32
+    data = _batch_inputs(40, seed=7, nmax=30000, mmax=24)
+    outs = []
+    try:
+        for mode in (1, 2, 3, 4, 0, 0):
+            rgs.rgs_set_tuning(gpu_handle, mode)
+            items = []
+            for W, k in data:
+                n, m = W.shape
+                Q, R, S = alloc(n, m, k, qd)
+                items.append((to_dev(W, torch.float32), Q, R, S, k))
+            rep, stat, _ = rgs.rgs_qr_batched(gpu_handle, items, sketch="gaussian", prec=prec)
+            torch.cuda.synchronize()
+            assert rep.status == 0
+            used = rgs.rgs_last_tuning(gpu_handle)
+            assert used == mode if mode else used in (1, 2, 3, 4)
+            outs.append(items)
+    finally:
+        rgs.rgs_set_tuning(gpu_handle, 0)
+    ref = outs[0]
+    for other in outs[1:]:
+        for (_, Q, R, S, _), (_, Q1, R1, S1, _) in zip(ref, other):
+            assert torch.equal(Q, Q1) and torch.equal(R, R1) and torch.equal(S, S1)
