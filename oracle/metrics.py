@@ -6,7 +6,8 @@
 * cond(Q), cond(S): Corollary 2.2 and the plots of Sec. 5.
 * omega = ||I - (Theta V)^T Theta V||_2 for an orthonormal basis V of range(V):
   the smallest epsilon in the definition of an epsilon-embedding (Sec. 2.1).
-* omega_bar: the probabilistic upper bound of Prop. 3.7 from two sketches.
+* omega_bar: the probabilistic upper bound of Prop. 3.7 from two sketches
+  (cert_extremes gives the two singular values it is built from).
 """
 
 import numpy as np
@@ -53,10 +54,22 @@ def omega(theta_V, V):
     return np.linalg.norm(np.eye(V.shape[1]) - TU.T @ TU, 2)
 
 
-def omega_bar(theta_V, phi_V, eps_star):
-    """Prop. 3.7: with X such that (Phi V) X is orthonormal,
-    omega_bar = max(1 - (1-eps*) smin^2(Theta V X), (1+eps*) smax^2(Theta V X) - 1)."""
+def cert_extremes(theta_V, phi_V):
+    """Extreme singular values (smin, smax) of Theta V X, where X makes Phi V
+    orthonormal (Prop. 3.7).  X = T^-1 from a QR  Phi V = U T; any other
+    choice gives the same singular values."""
     _, T = np.linalg.qr(np.asarray(phi_V, dtype=np.float64))
     Y = np.linalg.solve(T.T, np.asarray(theta_V, dtype=np.float64).T).T   # Theta V T^-1
     sv = np.linalg.svd(Y, compute_uv=False)
-    return max(1.0 - (1.0 - eps_star) * sv[-1] ** 2, (1.0 + eps_star) * sv[0] ** 2 - 1.0)
+    return float(sv[-1]), float(sv[0])
+
+
+def omega_bar_from(smin, smax, eps_star):
+    """Prop. 3.7: max(1 - (1-eps*) smin^2, (1+eps*) smax^2 - 1)."""
+    return max(1.0 - (1.0 - eps_star) * smin ** 2, (1.0 + eps_star) * smax ** 2 - 1.0)
+
+
+def omega_bar(theta_V, phi_V, eps_star):
+    """Prop. 3.7: the a-posteriori bound on the embedding distortion of Theta
+    for range(V) from the sketches Theta V and Phi V (Phi independent of V)."""
+    return omega_bar_from(*cert_extremes(theta_V, phi_V), eps_star)
