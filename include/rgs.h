@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 1
+#define RGS_ABI_VERSION 2
 
 typedef struct rgs_handle rgs_handle;  /* opaque */
 typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
@@ -73,6 +73,12 @@ typedef enum {
 #define RGS_FLAG_TIME_KERNELS 2u /* time every projection+sketch launch with events */
 #define RGS_FLAG_GRAPH 4u        /* rgs_gmres_batched: capture a restart cycle once as a HIP graph
                                     and replay it while the set of running systems is unchanged */
+#define RGS_FLAG_CERTIFY 8u      /* rgs_qr: a-posteriori certification of Theta (Prop. 3.7, Sec. 3)
+                                    for V = Q and V = W with a second sketch Phi of the same kind and
+                                    size, independent of Theta (counter word 2 = sketch_id + 1) and
+                                    used for nothing else; results in rgs_report.cert_*.  Costs three
+                                    sketches of n x m matrices (Theta Q, Phi Q, Phi W), a few k x m x m
+                                    fp64 products and O(m^3) host work.  Not with IDENTITY (EINVAL). */
 
 /* Describes one RGS factorisation and its sketch Theta (k x n).
  * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
@@ -124,6 +130,14 @@ typedef struct {
     double proj_kernel_ms;  /* with RGS_FLAG_TIME_KERNELS: summed duration of the
                                projection+sketch launches, else 0 */
     int64_t proj_launches;  /* number of projection+sketch launches */
+    /* RGS_FLAG_CERTIFY (Prop. 3.7): for V = Q (the returned basis) and V = W, the smallest and
+     * largest singular values of (Theta V) X, X any matrix with (Phi V) X orthonormal; NaN when
+     * not requested, when the factorisation failed, or when Phi V is numerically rank deficient.
+     * rgs_omega_bar turns a pair into the bound omega_bar. */
+    double cert_smin_q, cert_smax_q;
+    double cert_smin_w, cert_smax_w;
+    double cert_cond_phi_q; /* cond_2(Phi Q); u_crs times it bounds the rounding error of the
+                               computed omega_bar for V = Q (Prop. 3.9) */
 } rgs_report;
 
 /* One factorisation of a batched call (all pointers device memory, as in rgs_qr). */
@@ -150,6 +164,12 @@ typedef struct {
 
 /* Library version of this header (RGS_ABI_VERSION). */
 int rgs_abi_version(void);
+
+/* Prop. 3.7: omega_bar = max(1 - (1 - eps_star) smin^2, (1 + eps_star) smax^2 - 1), from the
+ * rgs_report.cert_* pair of one V.  If omega_bar < 1 and Phi is an (eps_star, delta*, 1)
+ * oblivious subspace embedding, Theta is an omega_bar-embedding of range(V) with probability at
+ * least 1 - delta*.  NaN if smin or smax is NaN.  Pure host function. */
+double rgs_omega_bar(double smin, double smax, double eps_star);
 
 /* Static English description of a status code.  Never NULL. */
 const char *rgs_status_string(rgs_status s);

@@ -23,6 +23,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16q": 2}
 FLAG_DIAGNOSTICS = 1
 FLAG_TIME_KERNELS = 2
 FLAG_GRAPH = 4
+FLAG_CERTIFY = 8
 
 
 class RgsError(RuntimeError):
@@ -66,7 +67,10 @@ class Report(ctypes.Structure):
     _fields_ = [("failed_column", ctypes.c_int64), ("iters", ctypes.c_int64), ("cycles", ctypes.c_int64),
                 ("delta_F", ctypes.c_double), ("delta_tilde_F", ctypes.c_double),
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("proj_kernel_ms", ctypes.c_double), ("proj_launches", ctypes.c_int64)]
+                ("proj_kernel_ms", ctypes.c_double), ("proj_launches", ctypes.c_int64),
+                ("cert_smin_q", ctypes.c_double), ("cert_smax_q", ctypes.c_double),
+                ("cert_smin_w", ctypes.c_double), ("cert_smax_w", ctypes.c_double),
+                ("cert_cond_phi_q", ctypes.c_double)]
 
     status = RGS_OK
 
@@ -82,6 +86,7 @@ _I64 = ctypes.c_int64
 _DESCP = ctypes.POINTER(QrDesc)
 SIGNATURES = {
     "rgs_abi_version": (ctypes.c_int, []),
+    "rgs_omega_bar": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "rgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rgs_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
     "rgs_destroy": (ctypes.c_int, [_P]),
@@ -131,6 +136,11 @@ def status_string(status):
 
 def rgs_abi_version():
     return lib().rgs_abi_version()
+
+
+def rgs_omega_bar(smin, smax, eps_star):
+    """Prop. 3.7 bound from one pair of rgs_report.cert_* values."""
+    return lib().rgs_omega_bar(smin, smax, eps_star)
 
 
 def _check(status, where, allow=()):

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librgs.so")
 
-SOURCES = ["rgs_project.hip", "rgs_kernels.hip", "rgs_gmres.hip", "rgs_api.cpp"]
+SOURCES = ["rgs_project.hip", "rgs_kernels.hip", "rgs_gmres.hip", "rgs_dense.cpp", "rgs_api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

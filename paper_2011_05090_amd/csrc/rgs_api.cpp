@@ -12,10 +12,12 @@
 #include <cmath>
 #include <cstring>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
 #include "rgs.h"
+#include "rgs_dense.hpp"
 #include "rgs_device.hpp"
 #include "rgs_internal.hpp"
 
@@ -164,7 +166,7 @@ rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* sign
 // Layout of the scratch arena for one factorisation.
 struct QrPlan {
     size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2, pdb, pbuf;
-    size_t rr, invr, pnorm, tau, beta, status, coef, diag;
+    size_t rr, invr, pnorm, tau, beta, status, coef, diag, cert;
     size_t total;
     int G_P, G_col, cc;
     int64_t nblk, nproj;
@@ -175,7 +177,7 @@ struct QrPlan {
 // spread over up to 256 row groups x k/256 row chunks of Theta.
 constexpr int64_t kSplitRows = (int64_t)128 * kProjRows;
 
-QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
+QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool certify = false) {
     QrPlan p{};
     Carver c;
     p.nblk = (n + kBlock - 1) / kBlock;
@@ -216,6 +218,8 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize) {
     p.status = c.take<int>(4);
     p.coef = c.take<char>(m * tsize);
     p.diag = c.take<double>(3 * m);
+    // certification (Prop. 3.7): six k x m and four m x m fp64 matrices
+    p.cert = certify ? c.take<double>(6 * k * m + 4 * m * m) : 0;
     p.total = c.off + kAlign;
     return p;
 }
@@ -246,25 +250,159 @@ SpaceArgs space_args(char* A, const QrPlan& pl, int64_t k, int64_t m) {
     return sa;
 }
 
-template <typename T>
-rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const T* X, int64_t ldx, int64_t n, int64_t ncols,
+// Y = Theta X for ncols columns of X (element type TX, arithmetic and
+// partials in T, reduction in fp64), cc columns per pass.
+template <typename TX, typename T>
+rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64_t ldx, int64_t n, int64_t ncols,
                          int G, int cc, T* part, double* out, int64_t ldo) {
     const double scale = sk.sketch == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)sk.k);
     for (int64_t c0 = 0; c0 < ncols; c0 += cc) {
         const int nc = (int)std::min<int64_t>(cc, ncols - c0);
         if (sk.sketch == SK_IDENT) {
-            // Theta = I: the sketch of a column is the column (reduce over G = 1 partial)
-            for (int c = 0; c < nc; ++c)
-                if (!launch_reduce<T>(h->stream, X + (c0 + c) * ldx, 1, (int)n, 1, 1.0, out + (c0 + c) * ldo, ldo))
-                    return RGS_EDEVICE;
-            continue;
+            if constexpr (std::is_same<TX, T>::value) {
+                // Theta = I: the sketch of a column is the column (reduce over G = 1 partial)
+                for (int c = 0; c < nc; ++c)
+                    if (!launch_reduce<T>(h->stream, X + (c0 + c) * ldx, 1, (int)n, 1, 1.0, out + (c0 + c) * ldo,
+                                          ldo))
+                        return RGS_EDEVICE;
+                continue;
+            } else {
+                return RGS_EINVAL;
+            }
         }
         if (sk.sketch == SK_GAUSS) {
-            if (!launch_gauss_cols<T, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
-        } else if (!launch_sketch_cols<T, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
+            if (!launch_gauss_cols<TX, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
+        } else if (!launch_sketch_cols<TX, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
             return RGS_EDEVICE;
         }
         if (!launch_reduce<T>(h->stream, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
+    }
+    return RGS_OK;
+}
+
+void report_defaults(rgs_report* r) {
+    r->failed_column = -1;
+    r->iters = 0;
+    r->cycles = 0;
+    r->delta_F = NAN;
+    r->delta_tilde_F = NAN;
+    r->true_relres = NAN;
+    r->seconds = 0.0;
+    r->proj_kernel_ms = 0.0;
+    r->proj_launches = 0;
+    r->cert_smin_q = r->cert_smax_q = NAN;
+    r->cert_smin_w = r->cert_smax_w = NAN;
+    r->cert_cond_phi_q = NAN;
+}
+
+// A-posteriori certification of Theta (Prop. 3.7) for V = Q (the returned
+// basis) and V = W: the extreme singular values of (Theta V) X with X such
+// that (Phi V) X is orthonormal.  Phi is a second sketch of the same kind and
+// size, independent of Theta (counter word 2 = sketch_id + 1); as the paper
+// suggests, it is used for nothing else.  Theta Q is a fresh sketch of the
+// returned Q, Theta W is P from step 1.  For V = W both sketches are first
+// multiplied by R^-1: the range, hence the singular values, is unchanged, and
+// the Gram matrices formed next stay well conditioned however ill-conditioned
+// W is.  With Z_Phi = (Phi V) M, Z_Theta = (Theta V) M (M = I or R^-1):
+// Z_Phi^T Z_Phi = T^T T (Cholesky), X = M T^-1, and the squared singular
+// values are the eigenvalues of Y^T Y with Y = Z_Theta T^-1.  The k x m
+// products run on the device, the m x m factorisations, inverses and
+// eigenvalue extremes on the host, all in fp64.
+template <typename T, typename TQ>
+rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const SketchArgs& theta, const T* W,
+                   int64_t ldw, const TQ* Q, int64_t ldq, const double* R, int64_t ldr, rgs_report* rep) {
+    const int64_t n = d->n, m = d->m, k = d->k;
+    const int mi = (int)m, ki = (int)k;
+    hipStream_t s = h->stream;
+    char* A = h->arena;
+    const double* P = reinterpret_cast<const double*>(A + pl.P);
+    double* thQ = reinterpret_cast<double*>(A + pl.cert);
+    double* phQ = thQ + k * m;
+    double* phW = phQ + k * m;
+    double* Z1 = phW + k * m;   // P R^-1
+    double* Z2 = Z1 + k * m;    // (Phi W) R^-1
+    double* Y = Z2 + k * m;
+    double* Md = Y + k * m;     // two m x m right factors
+    double* Gd = Md + 2 * m * m;   // two m x m Gram matrices
+    T* part = reinterpret_cast<T*>(A + pl.part_P);
+    const size_t mm = (size_t)m * m;
+    auto both = [](auto f) {   // f(0) and f(1) on two host threads
+        std::thread t1([&]() { f(1); });
+        f(0);
+        t1.join();
+    };
+
+    std::vector<double> Rh(mm);
+    if (hipMemcpy2DAsync(Rh.data(), m * sizeof(double), R, ldr * sizeof(double), m * sizeof(double), m,
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return RGS_EDEVICE;
+    rgs_status st = sketch_matrix<TQ, T>(h, theta, Q, ldq, n, m, pl.G_P, pl.cc, part, thQ, k);
+    if (st != RGS_OK) return st;
+    SketchArgs phi = make_sketch(theta.sketch, k, d->seed, d->sketch_id + 1u, d->instance);
+    // Theta's tables are no longer read: Phi's overwrite them in stream order
+    st = setup_sketch(h, phi, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
+    if (st != RGS_OK) return st;
+    st = sketch_matrix<TQ, T>(h, phi, Q, ldq, n, m, pl.G_P, pl.cc, part, phQ, k);
+    if (st != RGS_OK) return st;
+    st = sketch_matrix<T, T>(h, phi, W, ldw, n, m, pl.G_P, pl.cc, part, phW, k);
+    if (st != RGS_OK) return st;
+    const std::vector<double> Rinv = dense::upper_inverse(Rh, mi);   // overlaps the sketches
+    if (hipMemcpyAsync(Md, Rinv.data(), mm * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return RGS_EDEVICE;
+    if (!launch_dgemm(s, false, ki, mi, mi, P, k, Md, m, Z1, k) ||
+        !launch_dgemm(s, false, ki, mi, mi, phW, k, Md, m, Z2, k) ||
+        !launch_dgemm(s, true, mi, mi, ki, phQ, k, phQ, k, Gd, m) ||
+        !launch_dgemm(s, true, mi, mi, ki, Z2, k, Z2, k, Gd + mm, m))
+        return RGS_EDEVICE;
+    std::vector<double> Gh(2 * mm);
+    if (hipMemcpyAsync(Gh.data(), Gd, 2 * mm * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return RGS_EDEVICE;
+
+    // host: Cholesky factors of both Gram matrices and their inverses; cond(Phi Q) alongside
+    std::vector<double> Tq(Gh.begin(), Gh.begin() + mm), Tw(Gh.begin() + mm, Gh.end());
+    bool ok[2] = {false, false}, ok_c = false;
+    double gq_min = NAN, gq_max = NAN;
+    std::vector<double> Tinv(2 * mm);
+    std::thread tc([&]() {
+        ok_c = dense::sym_eig_extremes(std::vector<double>(Gh.begin(), Gh.begin() + mm), mi, gq_min, gq_max);
+    });
+    both([&](int b) {
+        std::vector<double>& Tm = b == 0 ? Tq : Tw;
+        ok[b] = dense::cholesky_upper(Tm, mi);
+        if (ok[b]) {
+            const std::vector<double> inv = dense::upper_inverse(Tm, mi);
+            std::copy(inv.begin(), inv.end(), Tinv.begin() + b * mm);
+        }
+    });
+    tc.join();
+    if (ok_c && gq_min > 0) rep->cert_cond_phi_q = std::sqrt(gq_max / gq_min);
+    if (hipMemcpyAsync(Md, Tinv.data(), 2 * mm * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return RGS_EDEVICE;
+    if (!launch_dgemm(s, false, ki, mi, mi, thQ, k, Md, m, Y, k) ||
+        !launch_dgemm(s, true, mi, mi, ki, Y, k, Y, k, Gd, m) ||
+        !launch_dgemm(s, false, ki, mi, mi, Z1, k, Md + mm, m, Y, k) ||
+        !launch_dgemm(s, true, mi, mi, ki, Y, k, Y, k, Gd + mm, m))
+        return RGS_EDEVICE;
+    std::vector<double> Ch(2 * mm);
+    if (hipMemcpyAsync(Ch.data(), Gd, 2 * mm * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return RGS_EDEVICE;
+    double lo[2] = {NAN, NAN}, hi[2] = {NAN, NAN};
+    bool ok_e[2] = {false, false};
+    both([&](int b) {
+        if (!ok[b]) return;
+        ok_e[b] = dense::sym_eig_extremes(std::vector<double>(Ch.begin() + b * mm, Ch.begin() + (b + 1) * mm), mi,
+                                          lo[b], hi[b]);
+    });
+    if (ok_e[0]) {
+        rep->cert_smin_q = std::sqrt(std::max(lo[0], 0.0));
+        rep->cert_smax_q = std::sqrt(std::max(hi[0], 0.0));
+    }
+    if (ok_e[1]) {
+        rep->cert_smin_w = std::sqrt(std::max(lo[1], 0.0));
+        rep->cert_smax_w = std::sqrt(std::max(hi[1], 0.0));
     }
     return RGS_OK;
 }
@@ -275,7 +413,8 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = d->n, m = d->m, k = d->k;
     const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
-    const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T));
+    const bool want_cert = (d->flags & RGS_FLAG_CERTIFY) != 0 && rep != nullptr;
+    const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert);
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -294,7 +433,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
 
     // Step 1 for every column at once: P = Theta W.
-    st = sketch_matrix<T>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
+    st = sketch_matrix<T, T>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
     if (st != RGS_OK) return st;
 
     const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;
@@ -349,14 +488,15 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
             return RGS_EDEVICE;
     }
     if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+    if (rep) report_defaults(rep);
+    if (want_cert && status[0] == 0) {
+        const rgs_status cs = certify<T, TQ>(h, d, pl, sk, W, ldw, Q, ldq, R, ldr, rep);
+        if (cs != RGS_OK) return cs;
+    }
     const auto t1 = std::chrono::steady_clock::now();
     if (rep) {
         rep->failed_column = status[0] ? status[1] : -1;
         rep->iters = status[0] ? status[1] : m;
-        rep->cycles = 0;
-        rep->delta_F = NAN;
-        rep->delta_tilde_F = NAN;
-        rep->true_relres = NAN;
         if (want_diag && status[0] == 0) {
             double g = 0, e = 0, p2 = 0;
             for (int64_t c = 0; c < m; ++c) {
@@ -545,6 +685,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     if (!std::isfinite(bnorm)) result = RGS_ENONFINITE;
     const auto t1 = std::chrono::steady_clock::now();
     if (rep) {
+        report_defaults(rep);
         rep->failed_column = -1;
         rep->iters = iters;
         rep->cycles = cycles;
@@ -956,6 +1097,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (gemm) h->last_schedule = sched;
     const auto t1 = std::chrono::steady_clock::now();
     if (rep) {
+        report_defaults(rep);
         rep->failed_column = -1;
         rep->iters = max_m;
         rep->cycles = 0;
@@ -1355,6 +1497,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         if (res[b] != RGS_OK && fail == RGS_OK) fail = res[b];
         if (reps) {
             rgs_report& r = reps[b];
+            report_defaults(&r);
             r.failed_column = -1;
             r.iters = iters[b];
             r.cycles = cycles[b];
@@ -1373,6 +1516,12 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
 extern "C" {
 
 int rgs_abi_version(void) { return RGS_ABI_VERSION; }
+
+double rgs_omega_bar(double smin, double smax, double eps_star) {
+    const double lo = 1.0 - (1.0 - eps_star) * smin * smin, hi = (1.0 + eps_star) * smax * smax - 1.0;
+    if (std::isnan(lo) || std::isnan(hi)) return NAN;
+    return lo > hi ? lo : hi;
+}
 
 const char* rgs_status_string(rgs_status s) {
     switch (s) {
@@ -1433,7 +1582,9 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
                   double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
     if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
     if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
-    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS)) != 0) return RGS_EINVAL;
+    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY)) != 0) return RGS_EINVAL;
+    // Phi = Theta = I would certify nothing
+    if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;
     if (d->m > 4096) return RGS_EINVAL;   // dynamic LDS of the sketch-space kernels
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64)
@@ -1460,10 +1611,10 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     st = setup_sketch(h, sk, d->n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
     if (d->prec == RGS_P_FP64)
-        st = sketch_matrix<double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
+        st = sketch_matrix<double, double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
                                    reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
     else
-        st = sketch_matrix<float>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
+        st = sketch_matrix<float, float>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
                                   reinterpret_cast<float*>(A + pl.part_P), Y, ldy);
     if (st != RGS_OK) return st;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;

@@ -76,6 +76,9 @@ bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_
                         double rsk, double* out, int64_t ldo);
 bool launch_diagnostics(hipStream_t st, const double* P, int64_t ldp, const double* S, int64_t lds,
                         const double* R, int64_t ldr, int k, int m, double* gram_out, double* resid_out);
+// C = op(A) B in fp64 (op(A) = A^T when transA), the small products of the certification.
+bool launch_dgemm(hipStream_t st, bool transA, int M, int N, int K, const double* A, int64_t lda, const double* B,
+                  int64_t ldb, double* C, int64_t ldc);
 
 template <typename TQ, typename T>
 bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, const double* invr, T* w,

@@ -55,14 +55,15 @@ __global__ void kb_srht_signs(const BatchItem* __restrict__ items, BlockMap map)
 
 // Partial sketches of ncols columns of X: workgroup (g, col) covers row blocks
 // g, g + G, ... (4096 rows each) and writes partials[(col * G + g) * k + j].
-template <typename T, typename PT, int SK>
-__device__ __forceinline__ void sketch_cols_body(const T* __restrict__ X, int64_t ldx, int64_t n, int64_t nblk,
-                                                 int G, const SketchArgs& sk, PT* __restrict__ partials, int g,
+// TX: element type of X (float, double or bf16); T: arithmetic and partial type.
+template <typename TX, typename T, int SK>
+__device__ __forceinline__ void sketch_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t nblk,
+                                                 int G, const SketchArgs& sk, T* __restrict__ partials, int g,
                                                  int col, T* __restrict__ lds) {
-    const T* x = X + (int64_t)col * ldx;
-    PT acc[kKptMax];
+    const TX* x = X + (int64_t)col * ldx;
+    T acc[kKptMax];
 #pragma unroll
-    for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
+    for (int u = 0; u < kKptMax; ++u) acc[u] = T(0);
     const bool vec_ok = ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
     for (int64_t blk = g; blk < nblk; blk += G) {
         int64_t row0[4];
@@ -70,9 +71,9 @@ __device__ __forceinline__ void sketch_cols_body(const T* __restrict__ X, int64_
         const bool full = vec_ok && (blk + 1) * kBlock <= n;
         T v[16];
         load16(x, row0, n, full, v);
-        block_sketch<T, PT, SK, 4>(v, blk, n, sk, acc, lds);
+        block_sketch<T, T, SK, 4>(v, blk, n, sk, acc, lds);
     }
-    PT* out = partials + ((int64_t)col * G + g) * sk.k;
+    T* out = partials + ((int64_t)col * G + g) * sk.k;
     const int kpt = (sk.k + kWG - 1) / kWG;
 #pragma unroll
     for (int u = 0; u < kKptMax; ++u) {
@@ -81,12 +82,12 @@ __device__ __forceinline__ void sketch_cols_body(const T* __restrict__ X, int64_
     }
 }
 
-template <typename T, typename PT, int SK>
-__global__ __launch_bounds__(kWG) void k_sketch_cols(const T* __restrict__ X, int64_t ldx, int64_t n,
+template <typename TX, typename T, int SK>
+__global__ __launch_bounds__(kWG) void k_sketch_cols(const TX* __restrict__ X, int64_t ldx, int64_t n,
                                                      int64_t nblk, int G, SketchArgs sk,
-                                                     PT* __restrict__ partials) {
+                                                     T* __restrict__ partials) {
     __shared__ T lds[kBlock];
-    sketch_cols_body<T, PT, SK>(X, ldx, n, nblk, G, sk, partials, blockIdx.x, blockIdx.y, lds);
+    sketch_cols_body<TX, T, SK>(X, ldx, n, nblk, G, sk, partials, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched step 1 (SRHT): map blocks are (factorisation, g + G_P * column).
@@ -567,6 +568,62 @@ __global__ void k_materialize(SketchArgs sk, int64_t j0, int64_t j1, int64_t l0,
     out[jj + ll * ldo] = val;
 }
 
+// Small fp64 product of the certification (Prop. 3.7): C = op(A) B with
+// op(A) = A (M x K, column-major, lda) or A^T (A stored K x M), B K x N (ldb),
+// C M x N (ldc).  64 x 64 output tile per workgroup, 16-deep slices of both
+// operands staged in LDS; each thread owns a 4 x 4 block of the tile.
+template <bool TA>
+__global__ __launch_bounds__(kWG) void k_dgemm(int M, int N, int K, const double* __restrict__ A, int64_t lda,
+                                               const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                                               int64_t ldc) {
+    constexpr int TM = 64, TN = 64, TK = 16;
+    __shared__ double As[TK][TM + 1];
+    __shared__ double Bs[TK][TN + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        for (int e = threadIdx.x; e < TK * TM; e += kWG) {
+            // consecutive threads walk the contiguous index of A
+            const int kk = TA ? e % TK : e / TM, mm = TA ? e / TK : e % TM;
+            const int gm = m0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < M && gk < K) v = TA ? A[gk + (int64_t)gm * lda] : A[gm + (int64_t)gk * lda];
+            As[kk][mm] = v;
+        }
+        for (int e = threadIdx.x; e < TK * TN; e += kWG) {
+            const int kk = e % TK, nn = e / TK;
+            const int gn = n0 + nn, gk = k0 + kk;
+            Bs[kk][nn] = (gn < N && gk < K) ? B[gk + (int64_t)gn * ldb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
+            if (gm < M && gn < N) C[gm + (int64_t)gn * ldc] = acc[i][j];
+        }
+}
+
 // Step 8 diagnostics: per column a of S, sum_b (S^T S - I)_{ab}^2.
 __global__ void k_diag_gram(const double* __restrict__ S, int64_t lds, int k, int m,
                             double* __restrict__ outcol) {
@@ -837,6 +894,18 @@ bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_
     return true;
 }
 
+bool launch_dgemm(hipStream_t st, bool transA, int M, int N, int K, const double* A, int64_t lda, const double* B,
+                  int64_t ldb, double* C, int64_t ldc) {
+    if (M <= 0 || N <= 0) return true;
+    const dim3 grid(nblocks(M, 64), nblocks(N, 64));
+    if (transA)
+        hipLaunchKernelGGL(k_dgemm<true>, grid, dim3(kWG), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    else
+        hipLaunchKernelGGL(k_dgemm<false>, grid, dim3(kWG), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 bool launch_diagnostics(hipStream_t st, const double* P, int64_t ldp, const double* S, int64_t lds,
                         const double* R, int64_t ldr, int k, int m, double* gram_out, double* resid_out) {
     hipLaunchKernelGGL(k_diag_gram, dim3(m), dim3(kWG), 0, st, S, lds, k, m, gram_out);
@@ -851,6 +920,8 @@ template bool launch_sketch_cols<float, float>(hipStream_t, const float*, int64_
                                                const SketchArgs&, float*);
 template bool launch_sketch_cols<double, double>(hipStream_t, const double*, int64_t, int64_t, int, int,
                                                  const SketchArgs&, double*);
+template bool launch_sketch_cols<bf16, float>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
+                                              const SketchArgs&, float*);
 template bool launch_reduce<float>(hipStream_t, const float*, int, int, int, double, double*, int64_t);
 template bool launch_reduce<double>(hipStream_t, const double*, int, int, int, double, double*, int64_t);
 template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double*, const int*);

@@ -45,7 +45,7 @@ def test_binding_signatures_cover_the_header():
 
 
 def test_abi_version_and_status_strings(lib):
-    assert rgs.rgs_abi_version() == 1
+    assert rgs.rgs_abi_version() == 2
     for code in (0, -1, -2, -3, -4, -5, -6):
         s = rgs.status_string(code)
         assert s and "unknown" not in s
@@ -68,6 +68,18 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(rgs.QrDesc) == 8 * 4 + 4 * 6
     assert ctypes.sizeof(rgs.Stencil7) == 8 * 3 + 8 * 7
     assert ctypes.sizeof(rgs.GmresDesc) == 8 * 5 + 4 * 4
-    assert ctypes.sizeof(rgs.Report) == 8 * 9
+    assert ctypes.sizeof(rgs.Report) == 8 * 14
     assert ctypes.sizeof(rgs.QrItem) == 8 * 11
     assert ctypes.sizeof(rgs.GmresItem) == ctypes.sizeof(rgs.Stencil7) + 8 * 4
+
+
+def test_omega_bar_helper_matches_the_oracle(lib):
+    """rgs_omega_bar is a host function: Prop. 3.7's formula, checked against
+    the oracle's, both branches of the maximum, and NaN propagation."""
+    import math
+    from oracle import metrics
+    for smin, smax, eps in ((0.9, 1.05, 0.05), (0.99, 1.2, 0.25), (1.0, 1.0, 0.0), (0.5, 0.6, 0.1)):
+        assert rgs.rgs_omega_bar(smin, smax, eps) == pytest.approx(metrics.omega_bar_from(smin, smax, eps),
+                                                                   rel=1e-15, abs=1e-15)
+    assert math.isnan(rgs.rgs_omega_bar(float("nan"), 1.0, 0.05))
+    assert math.isnan(rgs.rgs_omega_bar(1.0, float("nan"), 0.05))
