@@ -420,6 +420,19 @@ def main():
         extra["fp32_rgs_gaussian"] = {"ms_per_qr": msg, "gbs": B / (msg / 1000) / 1e9, "status": repg.status,
                                       "gaussian_draws_per_s": draws / (msg / 1000)}
         log("  %.2f ms/QR" % msg)
+        # the same factorisation with the a-posteriori certification of Theta (Prop. 3.7)
+        dcert = rgs.qr_desc(n, m, k, sketch="srht", prec="fp32", flags=rgs.FLAG_CERTIFY)
+        log("fp32 RGS, SRHT, with certification: 1 warmup, 2 steps")
+        msc, _, repc = run_steps(rgs, torch, h, dcert, W32, Q, R, S, 2, 1)
+        extra["certified_qr_srht"] = {
+            "ms_per_qr": msc, "overhead_ms": msc - ms, "status": repc.status,
+            "sigma_q": [repc.cert_smin_q, repc.cert_smax_q], "sigma_w": [repc.cert_smin_w, repc.cert_smax_w],
+            "omega_bar_q_eps0.05": rgs.rgs_omega_bar(repc.cert_smin_q, repc.cert_smax_q, 0.05),
+            "omega_bar_w_eps0.05": rgs.rgs_omega_bar(repc.cert_smin_w, repc.cert_smax_w, 0.05),
+            "cond_phi_q": repc.cert_cond_phi_q}
+        log("  %.2f ms/QR (+%.2f ms), omega_bar(Q) %.4f, omega_bar(W) %.4f (eps* = 0.05)" %
+            (msc, msc - ms, extra["certified_qr_srht"]["omega_bar_q_eps0.05"],
+             extra["certified_qr_srht"]["omega_bar_w_eps0.05"]))
         # companion input, sigma 1 -> 1e-3: the 1e-4 gate on ||I - S^T S||_2
         del W64
         Wc64 = synth.svd_matrix_torch(n, m, 1e-3, tag=1, device=dev)
