@@ -16,6 +16,11 @@ Gaussian (Sec. 2.1; entries N(0, 1/k)):
     (both exactly representable in float32 and fp64),
     rho = sqrt(-2 ln u1),  z_a = rho cos(2 pi u2),  z_b = rho sin(2 pi u2).
 
+Rademacher (Sec. 2.1; entries +-1/sqrt(k) with equal probability):
+    theta[j, l] = -1/sqrt(k) iff bit (l % 32) of word ((l % 128) // 32) of
+    Philox(floor(l/128), j, sketch_id, instance) is set, else +1/sqrt(k)
+    (one Philox call gives the signs of 128 consecutive columns of a row).
+
 P-SRHT (Sec. 2.1): with s = 2**ceil(log2 n), n <= s < 2n,
     Theta = k**-1/2 * Rows_rho * H_s * D, restricted to its first n columns
     (equivalently: zero-pad x to length s).  H_s is the unnormalised
@@ -70,6 +75,29 @@ def gaussian_block(k, seed, sketch_id, instance, j0, j1, l0, l1):
     z = z.reshape(js.size, -1)
     off = l0 - 4 * b0
     return z[:, off:off + (l1 - l0)] / math.sqrt(k)
+
+
+# ----------------------------------------------------------------------------
+# Rademacher
+# ----------------------------------------------------------------------------
+
+def rademacher_block(k, seed, sketch_id, instance, j0, j1, l0, l1):
+    """Entries theta[j0:j1, l0:l1] of the Rademacher sketch, fp64."""
+    key = seed_key(seed)
+    js = np.arange(j0, j1, dtype=np.uint64)
+    b0, b1 = l0 // 128, (l1 + 127) // 128
+    blocks = np.arange(b0, b1, dtype=np.uint64)
+    ctr = np.empty((js.size, blocks.size, 4), dtype=np.uint64)
+    ctr[..., 0] = blocks[None, :]
+    ctr[..., 1] = js[:, None]
+    ctr[..., 2] = sketch_id
+    ctr[..., 3] = instance
+    words = philox4x32(ctr, key).astype(np.uint64)        # (J, B, 4)
+    l = np.arange(l0, l1, dtype=np.uint64)
+    w = words[:, (l // np.uint64(128) - np.uint64(b0)).astype(np.int64),
+              ((l % np.uint64(128)) // np.uint64(32)).astype(np.int64)]
+    bit = (w >> (l % np.uint64(32))[None, :]) & np.uint64(1)
+    return np.where(bit == 1, -1.0, 1.0) / math.sqrt(k)
 
 
 # ----------------------------------------------------------------------------
@@ -196,6 +224,17 @@ class Gaussian(Sketch):
         return Y[:, 0] if vec else Y
 
 
+class Rademacher(Gaussian):
+    """Rademacher sketch, entries +-1/sqrt(k), generated block by block."""
+
+    kind = "rademacher"
+
+    def materialize(self, j0=0, j1=None, l0=0, l1=None):
+        j1 = self.k if j1 is None else j1
+        l1 = self.n if l1 is None else l1
+        return rademacher_block(self.k, self.seed, self.sketch_id, self.instance, j0, j1, l0, l1)
+
+
 class SRHT(Sketch):
     """P-SRHT: k**-1/2 * Rows_rho * H_s * D on the zero-padded input."""
 
@@ -247,9 +286,11 @@ class Identity(Sketch):
 
 
 def make(kind, n, k, seed=42, sketch_id=0, instance=0):
-    """Factory by name: 'gaussian', 'srht' or 'identity'."""
+    """Factory by name: 'gaussian', 'rademacher', 'srht' or 'identity'."""
     if kind == "gaussian":
         return Gaussian(n, k, seed, sketch_id, instance)
+    if kind == "rademacher":
+        return Rademacher(n, k, seed, sketch_id, instance)
     if kind == "srht":
         return SRHT(n, k, seed, sketch_id, instance)
     if kind == "identity":

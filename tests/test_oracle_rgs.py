@@ -30,7 +30,7 @@ def _wellcond(n, m, smin=1e-2, tag=0):
     return synth.svd_matrix(n, m, smin, tag=tag)
 
 
-@pytest.mark.parametrize("kind,n,m,k", [("gaussian", 512, 8, 64), ("srht", 1000, 12, 96),
+@pytest.mark.parametrize("kind,n,m,k", [("gaussian", 512, 8, 64), ("srht", 1000, 12, 96), ("rademacher", 700, 10, 80),
                                          ("gaussian", 300, 20, 20)])
 def test_closed_form_R_from_qr_of_sketch(kind, n, m, k):
     W = _wellcond(n, m, tag=1)
@@ -72,7 +72,7 @@ def test_full_srht_matches_householder_qr():
     assert metrics.orth_loss_2(out["Q"]) <= 1e-12
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher"])
 def test_output_invariants_fp64(kind):
     n, m, k = 2048, 32, 512
     W = synth.svd_matrix(n, m, 1e-6, tag=5)

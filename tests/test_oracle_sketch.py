@@ -3,6 +3,7 @@
 Each check is tied to something outside the code under test: the textbook
 Sylvester-Hadamard matrix (scipy), the exact column norms of an SRHT, the
 isometry of a fully sampled SRHT, the N(0, 1/k) law of the Gaussian entries,
+the fair, independent +-1/sqrt(k) signs of the Rademacher entries,
 the uniformity of a Fisher-Yates draw, and the definition of an
 epsilon-embedding (Sec. 2.1, Definition 2.1) checked by brute force.
 """
@@ -110,7 +111,54 @@ def test_gaussian_expected_gram_is_identity():
     assert np.max(np.abs(acc - np.eye(n))) < 6 * math.sqrt(2.0 / (k * reps))
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+def test_rademacher_entries_and_frobenius_norm():
+    # entries are exactly +-1/sqrt(k), so ||Theta||_F^2 = n exactly
+    for n, k in ((1000, 64), (37, 16), (4099, 300)):
+        T = sketch.make("rademacher", n, k, seed=3).materialize()
+        assert np.all(np.abs(T) == 1.0 / math.sqrt(k))
+        assert abs((T ** 2).sum() - n) < 1e-9 * n
+
+
+def test_rademacher_signs_are_fair_independent_coins():
+    k, n = 64, 8192
+    S = sketch.rademacher_block(k, 42, 0, 0, 0, k, 0, n) * math.sqrt(k)
+    b = (S.reshape(-1) < 0).astype(np.float64)
+    assert abs(b.mean() - 0.5) < 5 * 0.5 / math.sqrt(b.size)
+    # neighbours inside one 32-bit word, across words and across Philox calls
+    for lag in (1, 31, 32, 127, 128):
+        c = np.mean(S[:, lag:] * S[:, :-lag])
+        assert abs(c) < 5 / math.sqrt(k * (n - lag))
+    # rows and sketch ids are independent
+    assert abs(np.mean(S[1:] * S[:-1])) < 5 / math.sqrt((k - 1) * n)
+    S2 = sketch.rademacher_block(k, 42, 1, 0, 0, k, 0, n) * math.sqrt(k)
+    assert abs(np.mean(S * S2)) < 5 / math.sqrt(k * n)
+    # runs test on one long row: number of sign changes of a fair coin sequence
+    row = sketch.rademacher_block(1, 7, 0, 0, 0, 1, 0, 1 << 16)[0]
+    changes = np.count_nonzero(row[1:] != row[:-1])
+    assert abs(changes - (row.size - 1) / 2) < 5 * math.sqrt((row.size - 1) / 4)
+
+
+def test_rademacher_block_views_and_apply_agree():
+    k, n = 24, 1000
+    full = sketch.rademacher_block(k, 9, 1, 2, 0, k, 0, n)
+    assert np.array_equal(full[3:11, 129:517], sketch.rademacher_block(k, 9, 1, 2, 3, 11, 129, 517))
+    th = sketch.Rademacher(n, k, seed=9, sketch_id=1, instance=2, cache_limit=0)
+    X = np.random.Generator(np.random.PCG64(2)).standard_normal((n, 3))
+    np.testing.assert_allclose(th.apply(X), full @ X, rtol=1e-13, atol=1e-13)
+
+
+def test_rademacher_expected_gram_is_identity():
+    n, k, reps = 8, 32, 400
+    acc = np.zeros((n, n))
+    for t in range(reps):
+        T = sketch.rademacher_block(k, 42, 10 + t, 0, 0, k, 0, n)
+        acc += T.T @ T
+    acc /= reps
+    assert np.allclose(np.diag(acc), 1.0, rtol=0, atol=1e-15)    # exactly 1: entries are +-1/sqrt(k)
+    assert np.max(np.abs(acc - np.eye(n))) < 6 * math.sqrt(1.0 / (k * reps))
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher"])
 def test_omega_equals_bruteforce_embedding_distortion(kind):
     # Definition 2.1: omega is the smallest eps with
     # |<x,y> - <Theta x, Theta y>| <= eps ||x|| ||y|| for all x, y in range(V).

@@ -81,7 +81,7 @@ def test_identity_sketch_rgmres_is_gmres():
         np.testing.assert_allclose(out["x"], xref, rtol=1e-9, atol=1e-9 * np.abs(xref).max())
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher"])
 def test_residual_estimate_is_sketched_residual(kind):
     N, Pe = 6, 30.0
     dims, coeffs = synth.convdiff_coeffs(N, Pe)
