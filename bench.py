@@ -420,6 +420,16 @@ def main():
         extra["fp32_rgs_gaussian"] = {"ms_per_qr": msg, "gbs": B / (msg / 1000) / 1e9, "status": repg.status,
                                       "gaussian_draws_per_s": draws / (msg / 1000)}
         log("  %.2f ms/QR" % msg)
+        # Rademacher sketch, fp32 path: dense like the Gaussian, 128 signs per Philox call
+        dr = rgs.qr_desc(n, m, k, sketch="rademacher", prec="fp32", flags=rgs.FLAG_TIME_KERNELS)
+        log("fp32 RGS, Rademacher sketch: 1 warmup, 2 steps")
+        msr, kern_r, repr_ = run_steps(rgs, torch, h, dr, W32, Q, R, S, 2, 1)
+        rres, rd2, _ = quality(torch, W32, Q, R, S)
+        extra["fp32_rgs_rademacher"] = {"ms_per_qr": msr, "gbs": B / (msr / 1000) / 1e9, "status": repr_.status,
+                                        "projection_gbs": project_bytes(n, m, 4) / (kern_r / 2 / 1000) / 1e9,
+                                        "backward_error": rres, "norm2_I_minus_StS": rd2}
+        log("  %.2f ms/QR (%.1f GB/s), projection+sketch kernel %.1f GB/s, ||W-QR||/||W|| %.2e" %
+            (msr, B / (msr / 1000) / 1e9, extra["fp32_rgs_rademacher"]["projection_gbs"], rres))
         # the same factorisation with the a-posteriori certification of Theta (Prop. 3.7)
         dcert = rgs.qr_desc(n, m, k, sketch="srht", prec="fp32", flags=rgs.FLAG_CERTIFY)
         log("fp32 RGS, SRHT, with certification: 1 warmup, 2 steps")

@@ -6,7 +6,7 @@
  * application to GMRES", arXiv:2011.05090.
  *   - RGS column step: Algorithm 2 (Sec. 2.3).
  *   - RGS-Arnoldi: Algorithm 3 (Sec. 4.1); randomized GMRES: Sec. 4.2.
- *   - Sketching operators (Gaussian, P-SRHT) and seeded generation: Sec. 2.1.
+ *   - Sketching operators (Gaussian, Rademacher, P-SRHT) and seeded generation: Sec. 2.1.
  *
  * Conventions shared by every entry point
  *   - Matrices are column-major with an explicit leading dimension (in
@@ -56,7 +56,12 @@ typedef enum {
 typedef enum {
     RGS_SKETCH_GAUSSIAN = 0, /* entries N(0,1/k), Philox4x32-10 + Box-Muller, generated on the fly */
     RGS_SKETCH_SRHT = 1,     /* P-SRHT: k^-1/2 Rows H_s D on the zero-padded input */
-    RGS_SKETCH_IDENTITY = 2  /* test sketch: k = n, Theta = I */
+    RGS_SKETCH_IDENTITY = 2, /* test sketch: k = n, Theta = I */
+    RGS_SKETCH_RADEMACHER = 3 /* entries +-1/sqrt(k) (Sec. 2.1), generated on the fly: the signs of
+                                 columns 128b..128b+127 of row j are the 128 bits of one Philox4x32-10
+                                 call at counter (b, j, sketch_id, instance), bit l%32 of word
+                                 (l%128)/32 set meaning -1.  rgs_qr, rgs_gmres, rgs_sketch_apply and
+                                 rgs_sketch_materialize; not the batched calls */
 } rgs_sketch;
 
 typedef enum {
@@ -113,7 +118,7 @@ typedef struct {
     int64_t k;          /* sketch rows */
     double tol;         /* stop when ||b - A x||_2 / ||b||_2 <= tol (fp64) */
     uint64_t seed;
-    int32_t sketch;     /* rgs_sketch (GAUSSIAN or SRHT) */
+    int32_t sketch;     /* rgs_sketch (GAUSSIAN, SRHT or RADEMACHER; batched: GAUSSIAN or SRHT) */
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
     uint32_t flags;     /* rgs_gmres: ignored; rgs_gmres_batched: 0 or RGS_FLAG_GRAPH */

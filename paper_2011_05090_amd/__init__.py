@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librgs.so")
 
 RGS_OK, RGS_EINVAL, RGS_ENOMEM, RGS_EDEVICE, RGS_EBREAKDOWN, RGS_ENONFINITE, RGS_ENOCONV = 0, -1, -2, -3, -4, -5, -6
-SKETCH = {"gaussian": 0, "srht": 1, "identity": 2}
+SKETCH = {"gaussian": 0, "srht": 1, "identity": 2, "rademacher": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16q": 2}
 FLAG_DIAGNOSTICS = 1
 FLAG_TIME_KERNELS = 2

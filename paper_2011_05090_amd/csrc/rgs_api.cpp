@@ -120,6 +120,18 @@ SketchArgs make_sketch(int sketch, int64_t k, uint64_t seed, uint32_t sid, uint3
     return sk;
 }
 
+int sketch_kind(int32_t sketch) {
+    switch (sketch) {
+        case RGS_SKETCH_GAUSSIAN: return SK_GAUSS;
+        case RGS_SKETCH_SRHT: return SK_SRHT;
+        case RGS_SKETCH_RADEMACHER: return SK_RADEM;
+        default: return SK_IDENT;
+    }
+}
+
+// Sketches generated entry by entry from Philox (no transform).
+bool dense_sketch(int sk_kind) { return sk_kind == SK_GAUSS || sk_kind == SK_RADEM; }
+
 bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (!d) return false;
     if (d->n < 1 || d->k < 1) return false;
@@ -130,6 +142,10 @@ bool valid_desc(const rgs_qr_desc* d, bool need_m) {
         case RGS_SKETCH_GAUSSIAN:
             if (d->k > (int64_t)kKptMax * kWG) return false;
             if (d->n > ((int64_t)1 << 34)) return false;   // counter word 0 holds l/4
+            break;
+        case RGS_SKETCH_RADEMACHER:
+            if (d->k > (int64_t)kKptMax * kWG) return false;
+            if (d->n > ((int64_t)1 << 38)) return false;   // counter word 0 holds l/128
             break;
         case RGS_SKETCH_SRHT:
             if (d->k > (int64_t)kKptMax * kWG) return false;
@@ -185,10 +201,11 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool c
     const int64_t nsl = (k + kSlice - 1) / kSlice;
     const int64_t nsub = (n + 255) / 256;
     // row groups of P = Theta W: 4096-row blocks (SRHT), 256-row sub-blocks (Gaussian)
-    p.G_P = (int)std::min<int64_t>(sketch == SK_GAUSS ? nsub : p.nblk, 64);
-    // Gaussian sketch of a single column in its own launch (below kSplitRows rows)
-    p.G_col = (sketch == SK_GAUSS && n < kSplitRows) ? (int)std::min<int64_t>((n + kGSubCol - 1) / kGSubCol, 256)
-                                                     : 0;
+    p.G_P = (int)std::min<int64_t>(dense_sketch(sketch) ? nsub : p.nblk, 64);
+    // Gaussian / Rademacher sketch of a single column in its own launch (below kSplitRows rows)
+    p.G_col = (dense_sketch(sketch) && n < kSplitRows)
+                  ? (int)std::min<int64_t>((n + kGSubCol - 1) / kGSubCol, 256)
+                  : 0;
     const size_t per_col = (size_t)p.G_P * k * tsize;
     p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
     p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
@@ -270,7 +287,7 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64
                 return RGS_EINVAL;
             }
         }
-        if (sk.sketch == SK_GAUSS) {
+        if (dense_sketch(sk.sketch)) {
             if (!launch_gauss_cols<TX, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
         } else if (!launch_sketch_cols<TX, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
             return RGS_EDEVICE;
@@ -412,7 +429,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
                   int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = d->n, m = d->m, k = d->k;
-    const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+    const int sk_kind = sketch_kind(d->sketch);
     const bool want_cert = (d->flags & RGS_FLAG_CERTIFY) != 0 && rep != nullptr;
     const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert);
     rgs_status st = ensure_arena(h, pl.total);
@@ -525,10 +542,6 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     return RGS_OK;
 }
 
-
-int sketch_kind(int32_t sketch) {
-    return sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
-}
 
 StencilArgs stencil_args(const rgs_stencil7* A) {
     StencilArgs s{};
@@ -1601,7 +1614,7 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
                             double* Y, int64_t ldy) {
     if (!h || !valid_desc(d, false) || !X || !Y || ncols < 1 || ldx < d->n || ldy < d->k) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
-    const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+    const int sk_kind = sketch_kind(d->sketch);
     const size_t tsize = d->prec == RGS_P_FP64 ? sizeof(double) : sizeof(float);
     const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize);   // W and X are float on the bf16 path
     rgs_status st = ensure_arena(h, pl.total);
@@ -1626,7 +1639,7 @@ rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j
     if (j0 < 0 || j1 < j0 || j1 > d->k || l0 < 0 || l1 < l0 || l1 > d->n || ldo < std::max<int64_t>(1, j1 - j0))
         return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
-    const int sk_kind = d->sketch == RGS_SKETCH_GAUSSIAN ? SK_GAUSS : (d->sketch == RGS_SKETCH_SRHT ? SK_SRHT : SK_IDENT);
+    const int sk_kind = sketch_kind(d->sketch);
     const QrPlan pl = plan_qr(d->n, 1, d->k, sk_kind, sizeof(double));
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;

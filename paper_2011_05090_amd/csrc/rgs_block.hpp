@@ -204,6 +204,8 @@ __device__ __forceinline__ void lane_rows(int64_t blk, int64_t row0[4]) {
 // combined per sampled row through LDS (tile t = NW blk + w, and since the
 // bits of w and NW blk are disjoint the sign factors into both parts).
 // Gaussian: theta_{j,l} generated on the fly, 4 entries per Philox call.
+// Rademacher: the signs of 128 entries of a row per Philox call, applied as
+// fma(+-1, x, acc).
 // ---------------------------------------------------------------------------
 template <typename T, typename PT, int SK, int NW>
 __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, const SketchArgs& sk,
@@ -266,6 +268,35 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
                     T z[4];
                     gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
                     acc[u] += (PT)(z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3);
+                }
+            }
+        }
+        __syncthreads();
+    } else if constexpr (SK == SK_RADEM) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
+        __syncthreads();
+        // rows past n hold zeros, so only whole 128-row groups up to n are visited
+        const int64_t rem = n - blk * (NW * kTile);
+        const int ng = rem >= NW * kTile ? NW * kTile / 128 : (int)((rem + 127) / 128);
+        const uint32_t g0 = (uint32_t)(blk * (NW * kTile / 128));
+        for (int g = 0; g < ng; ++g) {
+#pragma unroll
+            for (int u = 0; u < kKptMax; ++u) {
+                const int j = t + NT * u;
+                if (u < kpt && j < sk.k) {
+                    uint32_t wd[4];
+                    rad_words(g0 + (uint32_t)g, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, wd);
+                    PT a = acc[u];
+#pragma unroll
+                    for (int c4 = 0; c4 < 4; ++c4) {
+                        const T* xs = lds + 128 * g + 32 * c4;
+#pragma unroll
+                        for (int r = 0; r < 32; ++r) a = fma((PT)rad_sign<T>(wd[c4], r), (PT)xs[r], a);
+                    }
+                    acc[u] = a;
                 }
             }
         }

@@ -50,6 +50,26 @@ __host__ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1,
     out[3] = c3;
 }
 
+// Rademacher sketch (entries +-1/sqrt(k)): the signs of row j at the 128
+// columns 128 b .. 128 b + 127 are the bits of one Philox call at counter
+// (b, j, sketch_id, instance); bit l % 32 of word (l % 128) / 32 set means -1.
+__device__ __forceinline__ void rad_words(uint32_t b, uint32_t j, uint32_t sid, uint32_t inst, uint32_t k0,
+                                          uint32_t k1, uint32_t w[4]) {
+    philox4x32_10(b, j, sid, inst, k0, k1, w);
+}
+
+// +1 or -1 (bit r of wd set) in T, built from the bit without a branch.
+template <typename T>
+__device__ __forceinline__ T rad_sign(uint32_t wd, int r);
+template <>
+__device__ __forceinline__ float rad_sign<float>(uint32_t wd, int r) {
+    return __uint_as_float(0x3F800000u | ((wd << (31 - r)) & 0x80000000u));
+}
+template <>
+__device__ __forceinline__ double rad_sign<double>(uint32_t wd, int r) {
+    return __hiloint2double((int)(0x3FF00000u | ((wd << (31 - r)) & 0x80000000u)), 0);
+}
+
 // Four standard normals z(j, 4q .. 4q+3) from one Philox call at counter
 // (q, j, sketch_id, instance).  Uniforms: u1 = ((x_a >> 9) + 1/2) 2^-23 in (0,1),
 // u2 = (x_b >> 8) 2^-24 in [0,1), both exact in fp32 and fp64;

@@ -578,6 +578,9 @@ bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, c
     else if (sk.sketch == SK_GAUSS)
         hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_GAUSS>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
+    else if (sk.sketch == SK_RADEM)
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_RADEM>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
+                           sk, partials, status);
     else
         hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_IDENT>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);

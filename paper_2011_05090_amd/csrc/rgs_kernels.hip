@@ -164,6 +164,64 @@ __global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, in
     gauss_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
+// Rademacher counterpart of gauss_cols_body (same workgroup and partials
+// layout): each Philox call gives the signs of 128 rows of sketch row j,
+// applied to the C staged columns.  SUB is a multiple of 128.
+template <typename TX, typename T, int C, int SUB>
+__device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
+                                              const SketchArgs& sk, T* __restrict__ partials, int g, int jc, int cc,
+                                              T (*w)[SUB]) {
+    static_assert(SUB % 128 == 0, "whole 128-row sign groups per sub-block");
+    const int j = jc * kWG + threadIdx.x;
+    const int c0 = cc * C;
+    const int nc = min(C, ncols - c0);
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    const int64_t nsub = (n + SUB - 1) / SUB;
+    for (int64_t sb = g; sb < nsub; sb += G) {
+        const int64_t r0 = sb * SUB;
+        for (int t = threadIdx.x; t < SUB; t += kWG) {
+            const int64_t l = r0 + t;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                w[c][t] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+        }
+        __syncthreads();
+        if (j < sk.k) {
+            const int64_t rem = n - r0;
+            const int ng = rem >= SUB ? SUB / 128 : (int)((rem + 127) / 128);
+            const uint32_t b0 = (uint32_t)(r0 / 128);
+            for (int q = 0; q < ng; ++q) {
+                uint32_t wd[4];
+                rad_words(b0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, wd);
+#pragma unroll
+                for (int c4 = 0; c4 < 4; ++c4)
+#pragma unroll 8
+                    for (int r = 0; r < 32; ++r) {
+                        const T sg = rad_sign<T>(wd[c4], r);
+                        const int t = 128 * q + 32 * c4 + r;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) acc[c] = fma(sg, w[c][t], acc[c]);
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    if (j < sk.k) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c < nc) partials[((int64_t)(c0 + c) * G + g) * sk.k + j] = acc[c];
+    }
+}
+
+template <typename TX, typename T, int C, int SUB>
+__global__ __launch_bounds__(kWG) void k_rad_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
+                                                  int G, SketchArgs sk, T* __restrict__ partials) {
+    __shared__ __attribute__((aligned(16))) T w[C][SUB];
+    rad_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+}
+
 // Batched step 1 (Gaussian): map blocks are (factorisation, g + G_P (jc + njc cc)).
 template <typename T>
 __global__ __launch_bounds__(kWG) void kb_gauss_cols(const BatchItem* __restrict__ items, BlockMap map) {
@@ -557,6 +615,10 @@ __global__ void k_materialize(SketchArgs sk, int64_t j0, int64_t j1, int64_t l0,
         T z[4];
         gauss4((uint32_t)(l >> 2), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
         val = (double)z[l & 3] * rsk;
+    } else if constexpr (SK == SK_RADEM) {
+        uint32_t wd[4];
+        rad_words((uint32_t)(l >> 7), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, wd);
+        val = ((wd[(l >> 5) & 3] >> (l & 31)) & 1u) ? -rsk : rsk;
     } else if constexpr (SK == SK_SRHT) {
         const uint32_t rho = (uint32_t)sk.rows[j];
         const int par = __popcll((uint64_t)rho & (uint64_t)l) & 1;
@@ -709,6 +771,16 @@ template <typename TX, typename T>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
                        T* partials) {
     const unsigned jc = nblocks(sk.k, kWG);
+    if (sk.sketch == SK_RADEM) {
+        if (ncols == 1)
+            hipLaunchKernelGGL((k_rad_cols<TX, T, 1, 128>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
+                               partials);
+        else
+            hipLaunchKernelGGL((k_rad_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
+                               dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
+        RGS_LAUNCH_CHECK();
+        return true;
+    }
     if (ncols == 1) {   // the single-column sketch of a small-n step: 64-row sub-blocks
         hipLaunchKernelGGL((k_gauss_cols<TX, T, 1, kGSubCol>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G,
                            sk, partials);
@@ -886,6 +958,8 @@ bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_
     const dim3 g(nblocks(cnt, 256)), b(256);
     if (sk.sketch == SK_GAUSS)
         hipLaunchKernelGGL((k_materialize<T, SK_GAUSS>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
+    else if (sk.sketch == SK_RADEM)
+        hipLaunchKernelGGL((k_materialize<T, SK_RADEM>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
     else if (sk.sketch == SK_SRHT)
         hipLaunchKernelGGL((k_materialize<T, SK_SRHT>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
     else

@@ -8,7 +8,7 @@
 
 namespace rgs {
 
-enum { SK_GAUSS = 0, SK_SRHT = 1, SK_IDENT = 2 };
+enum { SK_GAUSS = 0, SK_SRHT = 1, SK_IDENT = 2, SK_RADEM = 3 };
 enum { kStatusOk = 0, kStatusBreakdown = 1, kStatusNonfinite = 2 };
 
 // Everything a kernel needs to regenerate Theta (k x n) on the fly.

@@ -68,7 +68,7 @@ def _check_against_oracle(rep, W64, Qh, sketch, k, prec, seed=42, sketch_id=0):
     assert abs(rep.cert_cond_phi_q - c) <= 64 * U[prec] * c * c
 
 
-@pytest.mark.parametrize("sketch", ["gaussian", "srht"])
+@pytest.mark.parametrize("sketch", ["gaussian", "srht", "rademacher"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16q"])
 def test_certificate_matches_oracle(gpu_handle, sketch, prec):
     rgs = _rgs()

@@ -68,7 +68,7 @@ def _gpu(h, dims, coeffs, b, restart, k, tol, sketch, prec, max_iters=100000):
     return rep, np.array(hist), x.cpu().numpy()
 
 
-@pytest.mark.parametrize("sketch", ["gaussian", "srht"])
+@pytest.mark.parametrize("sketch", ["gaussian", "srht", "rademacher"])
 def test_rgmres_fp64_matches_oracle(gpu_handle, sketch):
     N, Pe, restart, k, tol = 24, 50.0, 20, 96, 1e-6        # n = 13824: 2 blocks, ragged
     dims, coeffs, b, ref = _oracle(N, Pe, restart, k, tol, sketch, "fp64", tag=1)

@@ -95,7 +95,7 @@ def test_srht_materialize_is_bit_exact(gpu_handle):
 
 
 @pytest.mark.parametrize("sketch,n,k", [("srht", 10000, 256), ("srht", 300, 64), ("gaussian", 9000, 96),
-                                        ("identity", 777, 777)])
+                                        ("identity", 777, 777), ("rademacher", 9000, 96), ("rademacher", 1000, 40)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_sketch_apply_matches_oracle(gpu_handle, sketch, n, k, prec):
     rgs = _rgs()
@@ -113,12 +113,42 @@ def test_sketch_apply_matches_oracle(gpu_handle, sketch, n, k, prec):
     assert np.abs(to_host(Y) - ref).max() <= tol * scale
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rademacher_materialize_is_exact(gpu_handle, prec):
+    """Entries are +-1/sqrt(k) from Philox bits: bit for bit equal to the oracle's."""
+    rgs = _rgs()
+    n, k = 1000, 40
+    d = rgs.qr_desc(n, 1, k, sketch="rademacher", prec=prec, seed=123, sketch_id=3, instance=5)
+    out = rgs.colmajor(k, n, torch.float64)
+    rgs.rgs_sketch_materialize(gpu_handle, d, 0, k, 0, n, out)
+    ref = osk.rademacher_block(k, 123, 3, 5, 0, k, 0, n)
+    assert np.array_equal(to_host(out), ref)
+    sub = rgs.colmajor(7, 300, torch.float64)
+    rgs.rgs_sketch_materialize(gpu_handle, d, 5, 12, 129, 429, sub)
+    assert np.array_equal(to_host(sub), ref[5:12, 129:429])
+
+
+def test_rademacher_fused_sketch_large_n(gpu_handle):
+    """n above the split threshold: the Rademacher sketch runs inside the
+    projection kernel (8192-row blocks, ragged tail)."""
+    n, m, k = (1 << 20) + 333, 6, 64
+    W = synth.svd_matrix(n, m, 1e-2, tag=19)
+    rep, Q, R, S = run_qr(gpu_handle, W, k, "rademacher", "fp64")
+    assert rep.status == 0
+    th = osk.make("rademacher", n, k, seed=42)
+    ref = orgs.rgs_qr(W, th)
+    assert np.linalg.norm(R - ref["R"]) / np.linalg.norm(ref["R"]) <= 1e-12
+    assert np.linalg.norm(S - ref["S"]) / np.linalg.norm(ref["S"]) <= 1e-12
+    assert np.linalg.norm(S - th.apply(Q)) <= 1e-12 * np.linalg.norm(S)
+    assert metrics.backward_error(W, Q, R) <= 1e-12
+
+
 # ---------------------------------------------------------------------------
 # fp64 factorisation
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("sketch,n,m,k", [("gaussian", 16384, 64, 256), ("srht", 10000, 40, 256),
-                                          ("srht", 4096 * 3 + 17, 24, 128)])
+                                          ("srht", 4096 * 3 + 17, 24, 128), ("rademacher", 4096 * 3 + 17, 24, 128)])
 def test_fp64_qr_wellconditioned_forward_parity(gpu_handle, sketch, n, m, k):
     W = synth.svd_matrix(n, m, 1e-2, tag=11)
     rep, Q, R, S = run_qr(gpu_handle, W, k, sketch, "fp64")
@@ -164,7 +194,7 @@ def test_identity_sketch_reproduces_householder_R(gpu_handle):
 # fp32 projection / fp64 least squares
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("sketch", ["srht", "gaussian"])
+@pytest.mark.parametrize("sketch", ["srht", "gaussian", "rademacher"])
 def test_fp32_qr_matches_oracle_fp32_model(gpu_handle, sketch):
     n, m, k = 4096 * 5 + 100, 48, 192
     W = synth.svd_matrix(n, m, 1e-3, tag=13).astype(np.float32).astype(np.float64)
@@ -238,7 +268,7 @@ def test_invalid_arguments_rejected(gpu_handle):
                    rgs.colmajor(200, 4, dt))
 
 
-@pytest.mark.parametrize("sketch", ["srht", "gaussian"])
+@pytest.mark.parametrize("sketch", ["srht", "gaussian", "rademacher"])
 def test_bitwise_deterministic(gpu_handle, sketch):
     W = synth.svd_matrix(20000, 32, 1e-4, tag=18)
     a = run_qr(gpu_handle, W, 128, sketch, "fp32")
