@@ -16,6 +16,11 @@ Gaussian (Sec. 2.1; entries N(0, 1/k)):
     (both exactly representable in float32 and fp64),
     rho = sqrt(-2 ln u1),  z_a = rho cos(2 pi u2),  z_b = rho sin(2 pi u2).
 
+Gaussian with bf16 entries (a stored variant of the Gaussian sketch):
+    theta[j, l] = bf16(z(j, l)) / sqrt(k), z as above in fp64, rounded once
+    to the nearest bfloat16 (ties to even).  Still an i.i.d. sketch whose
+    entries differ from the N(0, 1/k) ones by at most 2**-8 relative.
+
 Rademacher (Sec. 2.1; entries +-1/sqrt(k) with equal probability):
     theta[j, l] = -1/sqrt(k) iff bit (l % 32) of word ((l % 128) // 32) of
     Philox(floor(l/128), j, sketch_id, instance) is set, else +1/sqrt(k)
@@ -75,6 +80,23 @@ def gaussian_block(k, seed, sketch_id, instance, j0, j1, l0, l1):
     z = z.reshape(js.size, -1)
     off = l0 - 4 * b0
     return z[:, off:off + (l1 - l0)] / math.sqrt(k)
+
+
+def bf16_round_f64(x):
+    """Round fp64 values to the nearest bfloat16 (ties to even) in one step,
+    returned as fp64.  Finite values within the float32 normal range."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    u = x.view(np.uint64)
+    # bfloat16 keeps 7 of the 52 fraction bits: round at bit 45
+    lsb = (u >> np.uint64(45)) & np.uint64(1)
+    r = ((u + np.uint64((1 << 44) - 1) + lsb) >> np.uint64(45)) << np.uint64(45)
+    return r.view(np.float64).reshape(x.shape)
+
+
+def gaussian_bf16_block(k, seed, sketch_id, instance, j0, j1, l0, l1):
+    """Entries theta[j0:j1, l0:l1] of the Gaussian sketch with bf16 entries."""
+    z = gaussian_block(1, seed, sketch_id, instance, j0, j1, l0, l1)   # k = 1: z itself, unscaled
+    return bf16_round_f64(z) / math.sqrt(k)
 
 
 # ----------------------------------------------------------------------------
@@ -224,6 +246,17 @@ class Gaussian(Sketch):
         return Y[:, 0] if vec else Y
 
 
+class GaussianBF16(Gaussian):
+    """Gaussian sketch with entries rounded to bfloat16."""
+
+    kind = "gaussian_bf16"
+
+    def materialize(self, j0=0, j1=None, l0=0, l1=None):
+        j1 = self.k if j1 is None else j1
+        l1 = self.n if l1 is None else l1
+        return gaussian_bf16_block(self.k, self.seed, self.sketch_id, self.instance, j0, j1, l0, l1)
+
+
 class Rademacher(Gaussian):
     """Rademacher sketch, entries +-1/sqrt(k), generated block by block."""
 
@@ -286,11 +319,13 @@ class Identity(Sketch):
 
 
 def make(kind, n, k, seed=42, sketch_id=0, instance=0):
-    """Factory by name: 'gaussian', 'rademacher', 'srht' or 'identity'."""
+    """Factory by name: 'gaussian', 'gaussian_bf16', 'rademacher', 'srht' or 'identity'."""
     if kind == "gaussian":
         return Gaussian(n, k, seed, sketch_id, instance)
     if kind == "rademacher":
         return Rademacher(n, k, seed, sketch_id, instance)
+    if kind == "gaussian_bf16":
+        return GaussianBF16(n, k, seed, sketch_id, instance)
     if kind == "srht":
         return SRHT(n, k, seed, sketch_id, instance)
     if kind == "identity":

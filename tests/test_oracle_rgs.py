@@ -72,7 +72,7 @@ def test_full_srht_matches_householder_qr():
     assert metrics.orth_loss_2(out["Q"]) <= 1e-12
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher"])
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher", "gaussian_bf16"])
 def test_output_invariants_fp64(kind):
     n, m, k = 2048, 32, 512
     W = synth.svd_matrix(n, m, 1e-6, tag=5)

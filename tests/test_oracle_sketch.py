@@ -158,7 +158,44 @@ def test_rademacher_expected_gram_is_identity():
     assert np.max(np.abs(acc - np.eye(n))) < 6 * math.sqrt(1.0 / (k * reps))
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher"])
+def _bf16_nearest_even_bruteforce(x):
+    """Nearest bfloat16 to the double x by exact integer arithmetic on its
+    significand: the two grid neighbours, then the nearer (even on a tie)."""
+    m, e = math.frexp(abs(x))                 # x = m 2^e, 0.5 <= m < 1
+    sig = int(m * (1 << 53))                  # exact 53-bit significand
+    lo, rem = divmod(sig, 1 << 45)            # 8 significant bits kept (1 implicit + 7)
+    half = 1 << 44
+    up = rem > half or (rem == half and (lo & 1))
+    q = (lo + (1 if up else 0)) * (1 << 45)
+    return math.copysign(math.ldexp(q / float(1 << 53), e), x)
+
+
+def test_bf16_round_f64_is_nearest_even():
+    g = np.random.Generator(np.random.PCG64(5))
+    x = g.standard_normal(20000) * np.exp(g.uniform(-20, 20, 20000))
+    # exact ties and near-ties in both directions
+    base = sketch.bf16_round_f64(x)
+    ulp = np.ldexp(1.0, np.frexp(base)[1] - 8)          # bf16 spacing at base
+    x = np.concatenate([x, base + ulp / 2, base - ulp / 2, base + ulp / 2 * (1 + 2 ** -40)])
+    got = sketch.bf16_round_f64(x)
+    ref = np.array([_bf16_nearest_even_bruteforce(float(v)) for v in x])
+    assert np.array_equal(got, ref)
+    assert np.all((got.view(np.uint64) & np.uint64((1 << 45) - 1)) == 0)
+
+
+def test_gaussian_bf16_entries_are_rounded_gaussians():
+    k, n = 48, 3000
+    G = sketch.gaussian_block(k, 42, 0, 0, 0, k, 0, n)
+    B = sketch.make("gaussian_bf16", n, k, seed=42).materialize()
+    assert np.all(np.abs(B - G) <= 2.0 ** -8 * np.abs(G) + 1e-300)
+    Z = sketch.gaussian_bf16_block(1, 42, 0, 0, 0, k, 0, n)              # unscaled (k = 1)
+    assert np.all((Z.view(np.uint64) & np.uint64((1 << 45) - 1)) == 0)   # on the bf16 grid before the scale
+    assert np.array_equal(B, Z / math.sqrt(k))
+    z = Z.reshape(-1)
+    assert abs(z.mean()) < 5 / math.sqrt(z.size) and abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / z.size)
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "rademacher", "gaussian_bf16"])
 def test_omega_equals_bruteforce_embedding_distortion(kind):
     # Definition 2.1: omega is the smallest eps with
     # |<x,y> - <Theta x, Theta y>| <= eps ||x|| ||y|| for all x, y in range(V).
