@@ -316,6 +316,18 @@ def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6
                 (sketch, prec, rep.iters, rep.cycles, rep.true_relres, dt))
         res["%s_speedup_fp32_vs_fp64" % sketch] = (res["%s_fp64" % sketch]["seconds_to_tol"] /
                                                    res["%s_fp32" % sketch]["seconds_to_tol"])
+    # the Gaussian sketch with bf16 entries, made once per cycle into a table (RGS_FLAG_THETA_BF16)
+    d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="gaussian", prec="fp32", flags=rgs.FLAG_THETA_BF16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep, _ = rgs.rgs_gmres(h, A, d, b, x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["gaussian_bf16_table_fp32"] = {"seconds_to_tol": dt, "iters": rep.iters, "cycles": rep.cycles,
+                                       "true_relres": rep.true_relres, "status": rep.status,
+                                       "speedup_vs_fp64_gaussian": res["gaussian_fp64"]["seconds_to_tol"] / dt}
+    log("  rgmres gaussian(bf16 table)/fp32: %d iters, %d cycles, relres %.2e, %.3f s" %
+        (rep.iters, rep.cycles, rep.true_relres, dt))
     return res
 
 
@@ -420,6 +432,13 @@ def main():
         extra["fp32_rgs_gaussian"] = {"ms_per_qr": msg, "gbs": B / (msg / 1000) / 1e9, "status": repg.status,
                                       "gaussian_draws_per_s": draws / (msg / 1000)}
         log("  %.2f ms/QR" % msg)
+        # Gaussian sketch with bf16 entries, made once into a table and read by every column
+        dgt = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32", flags=rgs.FLAG_THETA_BF16)
+        log("fp32 RGS, Gaussian sketch with bf16 entries (table): 1 warmup, 2 steps")
+        msgt, _, repgt = run_steps(rgs, torch, h, dgt, W32, Q, R, S, 2, 1)
+        extra["fp32_rgs_gaussian_bf16_table"] = {"ms_per_qr": msgt, "gbs": B / (msgt / 1000) / 1e9,
+                                                 "status": repgt.status, "table_bytes": 2 * k * n}
+        log("  %.2f ms/QR" % msgt)
         # Rademacher sketch, fp32 path: dense like the Gaussian, 128 signs per Philox call
         dr = rgs.qr_desc(n, m, k, sketch="rademacher", prec="fp32", flags=rgs.FLAG_TIME_KERNELS)
         log("fp32 RGS, Rademacher sketch: 1 warmup, 2 steps")

@@ -83,11 +83,22 @@ typedef enum {
                                     size, independent of Theta (counter word 2 = sketch_id + 1) and
                                     used for nothing else; results in rgs_report.cert_*.  Costs three
                                     sketches of n x m matrices (Theta Q, Phi Q, Phi W), a few k x m x m
-                                    fp64 products and O(m^3) host work.  Not with IDENTITY (EINVAL). */
+                                    fp64 products and O(m^3) host work.  Not with IDENTITY (EINVAL).
+                                    With RGS_FLAG_THETA_BF16, Phi is the Gaussian sketch (not its
+                                    bf16 variant). */
+#define RGS_FLAG_THETA_BF16 16u  /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_sketch_apply,
+                                    rgs_sketch_materialize): the Gaussian sketch with bf16 entries,
+                                    theta = bf16(z)/sqrt(k), z the fp64 Box-Muller value of the
+                                    Gaussian sketch rounded once to nearest even; the entries are
+                                    made once per Theta into a table of 2 k ceil(n/8)*8 bytes in the
+                                    handle's scratch and read by every later sketch instead of being
+                                    drawn again.  A different (still i.i.d., entries within 2^-8
+                                    relative of N(0,1/k)) sketch from the GAUSSIAN one */
 
 /* Describes one RGS factorisation and its sketch Theta (k x n).
  * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
- * regenerated on demand and never stored (Sec. 2.1, seeded generation). */
+ * regenerated on demand and not stored (Sec. 2.1, seeded generation), except
+ * for the bf16 table that RGS_FLAG_THETA_BF16 asks for. */
 typedef struct {
     int64_t n;           /* rows of W (high dimension), n >= 1 */
     int64_t m;           /* columns of W, 1 <= m <= k */
@@ -121,7 +132,8 @@ typedef struct {
     int32_t sketch;     /* rgs_sketch (GAUSSIAN, SRHT or RADEMACHER; batched: GAUSSIAN or SRHT) */
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
-    uint32_t flags;     /* rgs_gmres: ignored; rgs_gmres_batched: 0 or RGS_FLAG_GRAPH */
+    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16 is honoured, other bits ignored;
+                           rgs_gmres_batched: 0 or RGS_FLAG_GRAPH */
 } rgs_gmres_desc;
 
 typedef struct {

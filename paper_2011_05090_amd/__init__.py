@@ -24,6 +24,7 @@ FLAG_DIAGNOSTICS = 1
 FLAG_TIME_KERNELS = 2
 FLAG_GRAPH = 4
 FLAG_CERTIFY = 8
+FLAG_THETA_BF16 = 16
 
 
 class RgsError(RuntimeError):

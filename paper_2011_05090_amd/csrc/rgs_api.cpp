@@ -130,7 +130,7 @@ int sketch_kind(int32_t sketch) {
 }
 
 // Sketches generated entry by entry from Philox (no transform).
-bool dense_sketch(int sk_kind) { return sk_kind == SK_GAUSS || sk_kind == SK_RADEM; }
+bool dense_sketch(int sk_kind) { return sk_kind == SK_GAUSS || sk_kind == SK_RADEM || sk_kind == SK_TABLE; }
 
 bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (!d) return false;
@@ -182,7 +182,7 @@ rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* sign
 // Layout of the scratch arena for one factorisation.
 struct QrPlan {
     size_t signs, rows, part_proj, part_P, P, Vc, Vr, Wc, Wr, X, sp, u, v, uh, pd, pd2, pdb, pbuf;
-    size_t rr, invr, pnorm, tau, beta, status, coef, diag, cert;
+    size_t rr, invr, pnorm, tau, beta, status, coef, diag, cert, table;
     size_t total;
     int G_P, G_col, cc;
     int64_t nblk, nproj;
@@ -193,7 +193,8 @@ struct QrPlan {
 // spread over up to 256 row groups x k/256 row chunks of Theta.
 constexpr int64_t kSplitRows = (int64_t)128 * kProjRows;
 
-QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool certify = false) {
+QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool certify = false,
+               bool table = false) {
     QrPlan p{};
     Carver c;
     p.nblk = (n + kBlock - 1) / kBlock;
@@ -237,6 +238,8 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool c
     p.diag = c.take<double>(3 * m);
     // certification (Prop. 3.7): six k x m and four m x m fp64 matrices
     p.cert = certify ? c.take<double>(6 * k * m + 4 * m * m) : 0;
+    // Gaussian sketch with bf16 entries: (n + 7) / 8 groups of 8 entries per sketch row
+    p.table = table ? c.take<uint16_t>((size_t)((n + 7) / 8) * 8 * k) : 0;
     p.total = c.off + kAlign;
     return p;
 }
@@ -265,6 +268,15 @@ SpaceArgs space_args(char* A, const QrPlan& pl, int64_t k, int64_t m) {
     sa.beta = reinterpret_cast<double*>(A + pl.beta);
     sa.status = reinterpret_cast<int*>(A + pl.status);
     return sa;
+}
+
+// RGS_FLAG_THETA_BF16: fills the bf16 table of the Gaussian sketch sk (in
+// stream order) and switches sk to read it.
+rgs_status use_table(rgs_handle* h, SketchArgs& sk, int64_t n, uint16_t* table) {
+    if (!launch_theta_table(h->stream, sk, n, table)) return RGS_EDEVICE;
+    sk.sketch = SK_TABLE;
+    sk.table = table;
+    return RGS_OK;
 }
 
 // Y = Theta X for ncols columns of X (element type TX, arithmetic and
@@ -356,7 +368,9 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
         return RGS_EDEVICE;
     rgs_status st = sketch_matrix<TQ, T>(h, theta, Q, ldq, n, m, pl.G_P, pl.cc, part, thQ, k);
     if (st != RGS_OK) return st;
-    SketchArgs phi = make_sketch(theta.sketch, k, d->seed, d->sketch_id + 1u, d->instance);
+    // Phi of a bf16-table Theta is the Gaussian sketch generated on the fly
+    const int phi_kind = theta.sketch == SK_TABLE ? SK_GAUSS : theta.sketch;
+    SketchArgs phi = make_sketch(phi_kind, k, d->seed, d->sketch_id + 1u, d->instance);
     // Theta's tables are no longer read: Phi's overwrite them in stream order
     st = setup_sketch(h, phi, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
@@ -431,13 +445,15 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const int64_t n = d->n, m = d->m, k = d->k;
     const int sk_kind = sketch_kind(d->sketch);
     const bool want_cert = (d->flags & RGS_FLAG_CERTIFY) != 0 && rep != nullptr;
-    const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert);
+    const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
+    const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert, tab);
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
     SketchArgs sk = make_sketch(sk_kind, k, d->seed, d->sketch_id, d->instance);
     st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
+    if (tab && (st = use_table(h, sk, n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
 
     SpaceArgs sa = space_args(A, pl, k, m);
     double* P = reinterpret_cast<double*>(A + pl.P);
@@ -568,7 +584,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const StencilArgs A = stencil_args(Ad);
     const int64_t n = A.nx * A.ny * A.nz, mcap = d->restart + 1, k = d->k;
     const int sk_kind = sketch_kind(d->sketch);
-    const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T));
+    const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
+    const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T), false, tab);
     Carver c;
     c.off = pl.total;
     const int64_t ldq = (n + 3) / 4 * 4;   // 16-byte aligned columns: every full block takes vector loads
@@ -626,6 +643,15 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         SketchArgs sk = make_sketch(sk_kind, k, d->seed, sid, 0);
         st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(Ar + pl.signs), reinterpret_cast<int*>(Ar + pl.rows));
         if (st != RGS_OK) return st;
+        if (tab) {   // a fresh table per cycle, unless the cycles share Theta
+            uint16_t* table = reinterpret_cast<uint16_t*>(Ar + pl.table);
+            if (cycles == 0 || !d->reuse_theta) {
+                if ((st = use_table(h, sk, n, table)) != RGS_OK) return st;
+            } else {
+                sk.sketch = SK_TABLE;
+                sk.table = table;
+            }
+        }
         if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
         // RGS step 1 of Algorithm 3: w_1 = r_0
         if (!launch_cast<T>(s, r, wbuf, n)) return RGS_EDEVICE;
@@ -1595,9 +1621,11 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
                   double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
     if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
     if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
-    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY)) != 0) return RGS_EINVAL;
+    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY | RGS_FLAG_THETA_BF16)) != 0)
+        return RGS_EINVAL;
     // Phi = Theta = I would certify nothing
     if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;
+    if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     if (d->m > 4096) return RGS_EINVAL;   // dynamic LDS of the sketch-space kernels
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64)
@@ -1615,14 +1643,18 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     if (!h || !valid_desc(d, false) || !X || !Y || ncols < 1 || ldx < d->n || ldy < d->k) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     const int sk_kind = sketch_kind(d->sketch);
+    const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
+    if (tab && sk_kind != SK_GAUSS) return RGS_EINVAL;
     const size_t tsize = d->prec == RGS_P_FP64 ? sizeof(double) : sizeof(float);
-    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize);   // W and X are float on the bf16 path
+    // W and X are float on the bf16 path
+    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize, false, tab);
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
     SketchArgs sk = make_sketch(sk_kind, d->k, d->seed, d->sketch_id, d->instance);
     st = setup_sketch(h, sk, d->n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
+    if (tab && (st = use_table(h, sk, d->n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
     if (d->prec == RGS_P_FP64)
         st = sketch_matrix<double, double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
                                    reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
@@ -1640,13 +1672,16 @@ rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j
         return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     const int sk_kind = sketch_kind(d->sketch);
-    const QrPlan pl = plan_qr(d->n, 1, d->k, sk_kind, sizeof(double));
+    const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
+    if (tab && sk_kind != SK_GAUSS) return RGS_EINVAL;
+    const QrPlan pl = plan_qr(d->n, 1, d->k, sk_kind, sizeof(double), false, tab);
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
     SketchArgs sk = make_sketch(sk_kind, d->k, d->seed, d->sketch_id, d->instance);
     st = setup_sketch(h, sk, d->n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
+    if (tab && (st = use_table(h, sk, d->n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
     const double rsk = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)d->k);
     const bool ok = d->prec == RGS_P_FP64
                         ? launch_materialize<double>(h->stream, sk, j0, j1, l0, l1, rsk, out, ldo)
@@ -1668,6 +1703,7 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     q.sketch = d->sketch;
     q.prec = d->prec;
     if (!valid_desc(&q, true)) return RGS_EINVAL;
+    if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64) return run_gmres<double, double, false>(h, A, d, b, x, res_hist, hist_cap, rep);
     if (d->prec == RGS_P_BF16Q_FP32_LS64) return run_gmres<float, bf16, true>(h, A, d, b, x, res_hist, hist_cap, rep);

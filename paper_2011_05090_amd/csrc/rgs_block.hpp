@@ -205,7 +205,7 @@ __device__ __forceinline__ void lane_rows(int64_t blk, int64_t row0[4]) {
 // bits of w and NW blk are disjoint the sign factors into both parts).
 // Gaussian: theta_{j,l} generated on the fly, 4 entries per Philox call.
 // Rademacher: the signs of 128 entries of a row per Philox call, applied as
-// fma(+-1, x, acc).
+// fma(+-1, x, acc).  Table (bf16 Gaussian): 8 entries per 16-byte load.
 // ---------------------------------------------------------------------------
 template <typename T, typename PT, int SK, int NW>
 __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, const SketchArgs& sk,
@@ -269,6 +269,42 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
                     gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
                     acc[u] += (PT)(z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3);
                 }
+            }
+        }
+        __syncthreads();
+    } else if constexpr (SK == SK_TABLE) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
+        __syncthreads();
+        const int64_t rem = n - blk * (NW * kTile);
+        const int no = rem >= NW * kTile ? NW * kTile / 8 : (int)((rem + 7) / 8);
+        const int64_t o0 = blk * (NW * kTile / 8);
+        // each thread streams its sketch rows through the block's table groups,
+        // kTabDepth 16-byte loads in flight; x comes from LDS (broadcast reads)
+#pragma unroll
+        for (int u = 0; u < kKptMax; ++u) {
+            const int j = t + NT * u;
+            if (u < kpt && j < sk.k) {
+                PT a = acc[u];
+                for (int o = 0; o < no; o += kTabDepth) {
+                    tabw_t w[kTabDepth];
+#pragma unroll
+                    for (int d = 0; d < kTabDepth; ++d)
+                        if (o + d < no) w[d] = tab_load(sk.table, sk.k, o0 + o + d, j);
+#pragma unroll
+                    for (int d = 0; d < kTabDepth; ++d) {
+                        if (o + d < no) {
+                            T z[8];
+                            tab_unpack<T>(w[d], z);
+                            const T* x = lds + 8 * (o + d);
+                            a += (PT)(z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3]);
+                            a += (PT)(z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7]);
+                        }
+                    }
+                }
+                acc[u] = a;
             }
         }
         __syncthreads();

@@ -50,6 +50,39 @@ __host__ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1,
     out[3] = c3;
 }
 
+// fp64 -> bfloat16 bits, rounded to nearest (ties to even) in one step.
+// For finite values in the float range (the rounded value, 8 significant
+// bits with a float exponent, converts to float exactly).
+__device__ __forceinline__ uint32_t bf16_rne_f64(double x) {
+    uint64_t u = (uint64_t)__double_as_longlong(x);
+    u = ((u + ((1ull << 44) - 1) + ((u >> 45) & 1ull)) >> 45) << 45;
+    return __float_as_uint((float)__longlong_as_double((long long)u)) >> 16;
+}
+
+// The bf16 Gaussian table (unscaled entries): group o of sketch row j holds
+// z(j, 8o .. 8o+7) as one 16-byte word.
+typedef uint32_t tabw_t __attribute__((ext_vector_type(4)));
+constexpr int kTabDepth = 4;   // table groups a thread keeps in flight
+
+__device__ __forceinline__ tabw_t tab_load(const uint16_t* __restrict__ table, int k, int64_t o, int j) {
+    return __builtin_nontemporal_load(reinterpret_cast<const tabw_t*>(table + (o * k + j) * 8));
+}
+
+template <typename T>
+__device__ __forceinline__ void tab_unpack(const tabw_t w, T z[8]) {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        z[2 * t] = (T)__uint_as_float(ws[t] << 16);
+        z[2 * t + 1] = (T)__uint_as_float(ws[t] & 0xFFFF0000u);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tab8(const uint16_t* __restrict__ table, int k, int64_t o, int j, T z[8]) {
+    tab_unpack<T>(tab_load(table, k, o, j), z);
+}
+
 // Rademacher sketch (entries +-1/sqrt(k)): the signs of row j at the 128
 // columns 128 b .. 128 b + 127 are the bits of one Philox call at counter
 // (b, j, sketch_id, instance); bit l % 32 of word (l % 128) / 32 set means -1.

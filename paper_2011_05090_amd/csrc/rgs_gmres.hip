@@ -142,7 +142,8 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
 // q'_i and p_{i+1} of A q'_i, share every draw; the normalisation 1/r_ii is
 // applied to both later, when it is known).  Same row mapping and summation
 // order per vector as stencil_sketch_body.
-template <typename TQ, typename T>
+// TAB: the entries come from the bf16 table (SK_TABLE), 8 rows per load.
+template <typename TQ, typename T, bool TAB = false>
 __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
                                                   T* __restrict__ t_out, const SketchArgs& sk,
                                                   T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
@@ -173,19 +174,54 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
 #pragma unroll
     for (int u = 0; u < kKptMax; ++u) ax[u] = at[u] = T(0);
     const int64_t rem = n - blk * RB;
-    const int nq = rem >= RB ? RB / 4 : (int)((rem + 3) / 4);
-    const uint32_t q0 = (uint32_t)(blk * (RB / 4));
-    for (int q = 0; q < nq; ++q) {
-        const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
-        const T t0 = lds[RB + 4 * q], t1 = lds[RB + 4 * q + 1], t2 = lds[RB + 4 * q + 2], t3 = lds[RB + 4 * q + 3];
+    if constexpr (TAB) {
+        const int no = rem >= RB ? RB / 8 : (int)((rem + 7) / 8);
+        const int64_t o0 = blk * (RB / 8);
+        // per sketch row, the block's table groups with kTabDepth loads in flight
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) {
             const int j = threadIdx.x + NT * u;
             if (u < kpt && j < sk.k) {
-                T z[4];
-                gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
-                ax[u] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
-                at[u] += z[0] * t0 + z[1] * t1 + z[2] * t2 + z[3] * t3;
+                T sx = ax[u], st = at[u];
+                for (int o = 0; o < no; o += kTabDepth) {
+                    tabw_t w[kTabDepth];
+#pragma unroll
+                    for (int d = 0; d < kTabDepth; ++d)
+                        if (o + d < no) w[d] = tab_load(sk.table, sk.k, o0 + o + d, j);
+#pragma unroll
+                    for (int d = 0; d < kTabDepth; ++d) {
+                        if (o + d < no) {
+                            T z[8];
+                            tab_unpack<T>(w[d], z);
+                            const T* x = lds + 8 * (o + d);
+                            const T* tt = lds + RB + 8 * (o + d);
+                            sx += z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3];
+                            sx += z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7];
+                            st += z[0] * tt[0] + z[1] * tt[1] + z[2] * tt[2] + z[3] * tt[3];
+                            st += z[4] * tt[4] + z[5] * tt[5] + z[6] * tt[6] + z[7] * tt[7];
+                        }
+                    }
+                }
+                ax[u] = sx;
+                at[u] = st;
+            }
+        }
+    } else {
+        const int nq = rem >= RB ? RB / 4 : (int)((rem + 3) / 4);
+        const uint32_t q0 = (uint32_t)(blk * (RB / 4));
+        for (int q = 0; q < nq; ++q) {
+            const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
+            const T t0 = lds[RB + 4 * q], t1 = lds[RB + 4 * q + 1], t2 = lds[RB + 4 * q + 2],
+                    t3 = lds[RB + 4 * q + 3];
+#pragma unroll
+            for (int u = 0; u < kKptMax; ++u) {
+                const int j = threadIdx.x + NT * u;
+                if (u < kpt && j < sk.k) {
+                    T z[4];
+                    gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+                    ax[u] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
+                    at[u] += z[0] * t0 + z[1] * t1 + z[2] * t2 + z[3] * t3;
+                }
             }
         }
     }
@@ -328,13 +364,13 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
     stencil_sketch_body<TQ, T, PT, SK>(qs, invr, g, n, w, do_sketch, sk, partials, blockIdx.x, lds);
 }
 
-template <typename TQ, typename T>
+template <typename TQ, typename T, bool TAB>
 __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     const TQ* __restrict__ xs, Grid3 g, int64_t n, T* __restrict__ t_out, SketchArgs sk, T* __restrict__ part_x,
     T* __restrict__ part_t, const int* __restrict__ status) {
     __shared__ T lds[2 * kProjWaves * kTile];
     RGS_EXIT_IF_STOPPED(status);
-    stencil_dual_body<TQ, T>(xs, g, n, t_out, sk, part_x, part_t, blockIdx.x, lds);
+    stencil_dual_body<TQ, T, TAB>(xs, g, n, t_out, sk, part_x, part_t, blockIdx.x, lds);
 }
 
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
@@ -592,8 +628,12 @@ template <typename TQ, typename T>
 bool launch_stencil_dual(hipStream_t st, const StencilArgs& A, const TQ* xs, T* t_out, const SketchArgs& sk,
                          T* part_x, T* part_t, const int* status) {
     const int64_t n = A.nx * A.ny * A.nz;
-    hipLaunchKernelGGL((k_stencil_dual<TQ, T>), dim3(nblk_of(n, kProjRows)), dim3(kProjWaves * kWave), 0, st, xs,
-                       grid3(A), n, t_out, sk, part_x, part_t, status);
+    if (sk.sketch == SK_TABLE)
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true>), dim3(nblk_of(n, kProjRows)), dim3(kProjWaves * kWave), 0,
+                           st, xs, grid3(A), n, t_out, sk, part_x, part_t, status);
+    else
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, false>), dim3(nblk_of(n, kProjRows)), dim3(kProjWaves * kWave), 0,
+                           st, xs, grid3(A), n, t_out, sk, part_x, part_t, status);
     RGS_LAUNCH_CHECK();
     return true;
 }

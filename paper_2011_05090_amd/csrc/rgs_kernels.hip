@@ -222,6 +222,90 @@ __global__ __launch_bounds__(kWG) void k_rad_cols(const TX* __restrict__ X, int6
     rad_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
+// Table of the Gaussian sketch with bf16 entries: thread (o, j) draws
+// z(j, 8o .. 8o+7) with the fp64 Box-Muller of two Philox quads, rounds each
+// once to bf16 and writes the group as one 16-byte store at (o k + j) 8
+// (rows past n hold 0).
+__global__ void k_theta_table(SketchArgs sk, int64_t n, int64_t ngroups, uint16_t* __restrict__ table) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ngroups * sk.k) return;
+    const int64_t o = idx / sk.k;
+    const int j = (int)(idx - o * sk.k);
+    double z[8];
+    gauss4((uint32_t)(2 * o), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+    gauss4((uint32_t)(2 * o + 1), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z + 4);
+    uint32_t w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t l = 8 * o + 2 * t;
+        const uint32_t lo = l < n ? bf16_rne_f64(z[2 * t]) : 0u;
+        const uint32_t hi = l + 1 < n ? bf16_rne_f64(z[2 * t + 1]) : 0u;
+        w[t] = lo | (hi << 16);
+    }
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    u32x4_t v;
+    v.x = w[0];
+    v.y = w[1];
+    v.z = w[2];
+    v.w = w[3];
+    *reinterpret_cast<u32x4_t*>(table + idx * 8) = v;
+}
+
+// Table counterpart of gauss_cols_body (same workgroup and partials layout):
+// each 16-byte table load serves 8 rows of sketch row j for the C staged
+// columns.  SUB is a multiple of 8.
+template <typename TX, typename T, int C, int SUB>
+__device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
+                                                const SketchArgs& sk, T* __restrict__ partials, int g, int jc,
+                                                int cc, T (*w)[SUB]) {
+    static_assert(SUB % 8 == 0, "whole 8-row table groups per sub-block");
+    const int j = jc * kWG + threadIdx.x;
+    const int c0 = cc * C;
+    const int nc = min(C, ncols - c0);
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    const int64_t nsub = (n + SUB - 1) / SUB;
+    for (int64_t sb = g; sb < nsub; sb += G) {
+        const int64_t r0 = sb * SUB;
+        for (int t = threadIdx.x; t < SUB; t += kWG) {
+            const int64_t l = r0 + t;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                w[c][t] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+        }
+        __syncthreads();
+        if (j < sk.k) {
+            const int64_t rem = n - r0;
+            const int no = rem >= SUB ? SUB / 8 : (int)((rem + 7) / 8);
+            const int64_t o0 = r0 / 8;
+            for (int o = 0; o < no; ++o) {
+                T z[8];
+                tab8<T>(sk.table, sk.k, o0 + o, j, z);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const T* x = w[c] + 8 * o;
+                    acc[c] += z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3];
+                    acc[c] += z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (j < sk.k) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c < nc) partials[((int64_t)(c0 + c) * G + g) * sk.k + j] = acc[c];
+    }
+}
+
+template <typename TX, typename T, int C, int SUB>
+__global__ __launch_bounds__(kWG) void k_table_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
+                                                    int G, SketchArgs sk, T* __restrict__ partials) {
+    __shared__ __attribute__((aligned(16))) T w[C][SUB];
+    table_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+}
+
 // Batched step 1 (Gaussian): map blocks are (factorisation, g + G_P (jc + njc cc)).
 template <typename T>
 __global__ __launch_bounds__(kWG) void kb_gauss_cols(const BatchItem* __restrict__ items, BlockMap map) {
@@ -615,6 +699,10 @@ __global__ void k_materialize(SketchArgs sk, int64_t j0, int64_t j1, int64_t l0,
         T z[4];
         gauss4((uint32_t)(l >> 2), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
         val = (double)z[l & 3] * rsk;
+    } else if constexpr (SK == SK_TABLE) {
+        T z[8];
+        tab8<T>(sk.table, sk.k, l >> 3, (int)j, z);
+        val = (double)z[l & 7] * rsk;
     } else if constexpr (SK == SK_RADEM) {
         uint32_t wd[4];
         rad_words((uint32_t)(l >> 7), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, wd);
@@ -771,6 +859,16 @@ template <typename TX, typename T>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
                        T* partials) {
     const unsigned jc = nblocks(sk.k, kWG);
+    if (sk.sketch == SK_TABLE) {
+        if (ncols == 1)
+            hipLaunchKernelGGL((k_table_cols<TX, T, 1, kGSubCol>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G,
+                               sk, partials);
+        else
+            hipLaunchKernelGGL((k_table_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
+                               dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
+        RGS_LAUNCH_CHECK();
+        return true;
+    }
     if (sk.sketch == SK_RADEM) {
         if (ncols == 1)
             hipLaunchKernelGGL((k_rad_cols<TX, T, 1, 128>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
@@ -960,10 +1058,20 @@ bool launch_materialize(hipStream_t st, const SketchArgs& sk, int64_t j0, int64_
         hipLaunchKernelGGL((k_materialize<T, SK_GAUSS>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
     else if (sk.sketch == SK_RADEM)
         hipLaunchKernelGGL((k_materialize<T, SK_RADEM>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
+    else if (sk.sketch == SK_TABLE)
+        hipLaunchKernelGGL((k_materialize<T, SK_TABLE>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
     else if (sk.sketch == SK_SRHT)
         hipLaunchKernelGGL((k_materialize<T, SK_SRHT>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
     else
         hipLaunchKernelGGL((k_materialize<T, SK_IDENT>), g, b, 0, st, sk, j0, j1, l0, l1, rsk, out, ldo);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+bool launch_theta_table(hipStream_t st, const SketchArgs& sk, int64_t n, uint16_t* table) {
+    const int64_t ngroups = (n + 7) / 8;
+    const int64_t work = ngroups * sk.k;
+    hipLaunchKernelGGL(k_theta_table, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, sk, n, ngroups, table);
     RGS_LAUNCH_CHECK();
     return true;
 }
