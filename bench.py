@@ -255,8 +255,10 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
     N^3, N ~ U{32..96}, Pe ~ U[1, 100], b ~ N(0, 1), restart 50, k = 200,
     tol 1e-6, one rgs_gmres_batched call with graph-replayed cycles.  The bf16
     and fp32 bases are compared with plain fp64 on the same GPU (iteration
-    counts per system).  The Gaussian sketch regenerates its entries per
-    system, so it runs on the first ``gaussian_batch`` systems only."""
+    counts per system).  The Gaussian sketch drawn on the fly regenerates its
+    entries per system, so it runs on the first ``gaussian_batch`` systems
+    only; the Gaussian sketch with bf16 entries (one table per cycle shared by
+    all systems) runs on the whole batch."""
     Ns, Pes = synth.batch_gmres_sizes(batch)
     systems = []
     for i, (N, Pe) in enumerate(zip(Ns, Pes)):
@@ -266,12 +268,14 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
     n_tot = int(sum(int(N) ** 3 for N in Ns))
     out = {"batch": batch, "N_range": [32, 96], "Pe_range": [1.0, 100.0], "restart": restart, "k": k, "tol": tol,
            "unknowns": n_tot}
-    for sketch in ("srht", "gaussian"):
-        sy = systems if sketch == "srht" else systems[:gaussian_batch]
+    for variant in ("srht", "gaussian", "gaussian_bf16_table"):
+        sketch = "srht" if variant == "srht" else "gaussian"
+        flags = rgs.FLAG_GRAPH | (rgs.FLAG_THETA_BF16 if variant == "gaussian_bf16_table" else 0)
+        sy = systems[:gaussian_batch] if variant == "gaussian" else systems
         res = {"systems": len(sy)}
         iters = {}
         for prec in ("bf16q", "fp32", "fp64"):
-            d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch=sketch, prec=prec, flags=rgs.FLAG_GRAPH)
+            d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch=sketch, prec=prec, flags=flags)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st, stat, reps, _ = rgs.rgs_gmres_batched(h, sy, d)
@@ -282,14 +286,14 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
                          "total_iters": int(sum(iters[prec])), "max_cycles": max(r.cycles for r in reps),
                          "max_true_relres": max(r.true_relres for r in reps)}
             log("  batched rgmres %s/%s x%d: %.3f s, %d converged, max cycles %d, max relres %.2e" %
-                (sketch, prec, len(sy), dt, res[prec]["converged"], res[prec]["max_cycles"],
+                (variant, prec, len(sy), dt, res[prec]["converged"], res[prec]["max_cycles"],
                  res[prec]["max_true_relres"]))
         for prec in ("bf16q", "fp32"):
             diff = [a - b for a, b in zip(iters[prec], iters["fp64"])]
             res[prec]["iters_minus_fp64"] = {"min": min(diff), "max": max(diff),
                                              "within_2": sum(1 for v in diff if abs(v) <= 2)}
             res[prec]["speedup_vs_fp64"] = res["fp64"]["seconds_to_tol"] / res[prec]["seconds_to_tol"]
-        out[sketch] = res
+        out[variant] = res
     return out
 
 

@@ -86,8 +86,9 @@ typedef enum {
                                     fp64 products and O(m^3) host work.  Not with IDENTITY (EINVAL).
                                     With RGS_FLAG_THETA_BF16, Phi is the Gaussian sketch (not its
                                     bf16 variant). */
-#define RGS_FLAG_THETA_BF16 16u  /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_sketch_apply,
-                                    rgs_sketch_materialize): the Gaussian sketch with bf16 entries,
+#define RGS_FLAG_THETA_BF16 16u  /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_gmres_batched,
+                                    rgs_sketch_apply, rgs_sketch_materialize): the Gaussian sketch
+                                    with bf16 entries,
                                     theta = bf16(z)/sqrt(k), z the fp64 Box-Muller value of the
                                     Gaussian sketch rounded once to nearest even; the entries are
                                     made once per Theta into a table of 2 k ceil(n/8)*8 bytes in the
@@ -133,7 +134,7 @@ typedef struct {
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
     uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16 is honoured, other bits ignored;
-                           rgs_gmres_batched: 0 or RGS_FLAG_GRAPH */
+                           rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
 } rgs_gmres_desc;
 
 typedef struct {
@@ -287,7 +288,8 @@ rgs_status rgs_gmres(rgs_handle *h, const rgs_stencil7 *A, const rgs_gmres_desc 
  *   the one a separate rgs_gmres call with the same descriptor would use
  *   (instance 0, its own n), so each system's x, history and counts equal
  *   those of a separate call.
- *   desc->sketch: GAUSSIAN or SRHT.  desc->flags: 0 or RGS_FLAG_GRAPH.
+ *   desc->sketch: GAUSSIAN or SRHT.  desc->flags: RGS_FLAG_GRAPH, RGS_FLAG_THETA_BF16 (one
+ *   table over the largest n per cycle serves every system).
  *   item_status (host, `batch` entries, may be NULL): RGS_OK, RGS_ENONFINITE or
  *   RGS_ENOCONV per system; reps (host, `batch` entries, may be NULL): per
  *   system iters, cycles, true_relres (seconds = the whole call).

@@ -1201,8 +1201,12 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     const int64_t restart = d->restart, mcap = restart + 1, k = d->k;
     const int64_t nsl = (k + kSlice - 1) / kSlice;
     const bool use_graph = (d->flags & RGS_FLAG_GRAPH) != 0;
+    // Gaussian sketch with bf16 entries: entry (j, l) does not depend on n, so
+    // one table over the largest n serves every system of the cycle
+    const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
     std::vector<int64_t> ns((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) grid_size(items[b].A, &ns[b]);
+    const int64_t nmax = *std::max_element(ns.begin(), ns.end());
 
     // scratch of every system, carved from the handle's arena
     struct Off {
@@ -1252,6 +1256,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     const size_t o_status = c.take<int>(4 * batch), o_used = c.take<int>(batch), o_limit = c.take<int>(batch);
     const size_t o_norm = c.take<double>(batch), o_hist = c.take<double>(batch * mcap);
     const size_t o_items = c.take<BatchItem>(batch), o_gitems = c.take<GmresItem>(batch);
+    const size_t o_table = c.take<uint16_t>(tab ? (size_t)((nmax + 7) / 8) * 8 * k : 1);
     std::vector<int64_t> all((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) all[b] = b;
     GmresMaps gm;
@@ -1311,6 +1316,10 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         a.beta = reinterpret_cast<double*>(A + o.beta);
         a.status = reinterpret_cast<int*>(A + o_status) + 4 * b;
         x.sk = make_sketch(sk_kind, k, d->seed, 2, 0);
+        if (tab) {
+            x.sk.sketch = SK_TABLE;
+            x.sk.table = reinterpret_cast<uint16_t*>(A + o_table);
+        }
         if (sk_kind == SK_SRHT) {
             x.sk.signs = reinterpret_cast<uint32_t*>(A + o.signs);
             x.sk.rows = reinterpret_cast<int*>(A + o_rows) + b * k;
@@ -1406,7 +1415,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         if (!launch_gbatch_cast<T>(q, gid, m_row(), n_row())) return false;
         if (dual) {
             if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), 0) ||
-                !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), 0))
+                !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), 0, tab))
                 return false;
         } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(), n_proj(), 0)) {
             return false;
@@ -1421,7 +1430,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
             if (dual) {
                 if (!launch_gbatch_ls<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(rbl), n_uni(rbl), ii, 1) ||
                     !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), ii) ||
-                    !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), ii))
+                    !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), ii, tab))
                     return false;
             } else {
                 if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(), n_proj(), ii)) return false;
@@ -1466,6 +1475,9 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
             }
             if (sk_kind == SK_SRHT && hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int),
                                                      hipMemcpyHostToDevice, s) != hipSuccess)
+                return RGS_EDEVICE;
+            if (tab && !launch_theta_table(s, make_sketch(SK_GAUSS, k, d->seed, sid, 0), nmax,
+                                           reinterpret_cast<uint16_t*>(A + o_table)))
                 return RGS_EDEVICE;
             if (hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
                 hipSuccess)
@@ -1752,7 +1764,8 @@ rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
                              int32_t* item_status, rgs_report* reps) {
     if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
-    if ((d->flags & ~RGS_FLAG_GRAPH) != 0) return RGS_EINVAL;
+    if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16)) != 0) return RGS_EINVAL;
+    if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     for (int64_t b = 0; b < batch; ++b) {
         const rgs_gmres_item& it = items[b];
         int64_t n = 0;

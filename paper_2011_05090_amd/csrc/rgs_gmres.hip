@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem
                                       static_cast<T*>(it.part), bm.y, lds);
 }
 
-template <typename TQ, typename T>
+template <typename TQ, typename T, bool TAB>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const BatchItem* __restrict__ items,
                                                                       const GmresItem* __restrict__ gi,
                                                                       BlockMap map, int i) {
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const Batc
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
-    stencil_dual_body<TQ, T>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+    stencil_dual_body<TQ, T, TAB>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
                              static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part), static_cast<T*>(it.part2), bm.y,
                              lds);
 }
@@ -718,9 +718,14 @@ bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, c
 
 template <typename T, typename TQ>
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
-                                int64_t nproj, int i) {
+                                int64_t nproj, int i, bool table) {
     if (nproj == 0) return true;
-    hipLaunchKernelGGL((kg_stencil_dual<TQ, T>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi, map_proj, i);
+    if (table)
+        hipLaunchKernelGGL((kg_stencil_dual<TQ, T, true>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
+                           map_proj, i);
+    else
+        hipLaunchKernelGGL((kg_stencil_dual<TQ, T, false>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
+                           map_proj, i);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -835,10 +840,10 @@ template bool launch_stencil_dual<double, double>(hipStream_t, const StencilArgs
                                                   const SketchArgs&, double*, double*, const int*);
 template bool launch_stencil_dual<bf16, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
                                                const SketchArgs&, float*, float*, const int*);
-template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
+template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool);
 template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
-                                                         const BlockMap&, int64_t, int);
-template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
+                                                         const BlockMap&, int64_t, int, bool);
+template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool);
 template bool launch_gbatch_project_ws<float, float, false>(hipStream_t, const BatchItem*, const GmresItem*,
                                                             const BlockMap&, int64_t, int);
 template bool launch_gbatch_project_ws<double, double, false>(hipStream_t, const BatchItem*, const GmresItem*,

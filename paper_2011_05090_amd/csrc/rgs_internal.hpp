@@ -125,7 +125,7 @@ bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& ma
                       int64_t nrb, int i, int dual);
 template <typename T, typename TQ>
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
-                                int64_t nproj, int i);
+                                int64_t nproj, int i, bool table);
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                               int64_t nproj, int i);

@@ -65,12 +65,17 @@ def _single(h, system, desc, hist_cap=4000):
     return rep, hist, x
 
 
-@pytest.mark.parametrize("sketch,prec", [("srht", "fp32"), ("gaussian", "fp32"), ("srht", "bf16q"),
-                                         ("gaussian", "bf16q"), ("srht", "fp64")])
-def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec):
+@pytest.mark.parametrize("sketch,prec,table", [("srht", "fp32", False), ("gaussian", "fp32", False),
+                                               ("srht", "bf16q", False), ("gaussian", "bf16q", False),
+                                               ("srht", "fp64", False), ("gaussian", "fp32", True),
+                                               ("gaussian", "bf16q", True)])
+def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec, table):
+    """table: the Gaussian sketch with bf16 entries; the batched call's one
+    table over the largest n gives every system the entries of its own."""
     rgs = _rgs()
     systems = _systems(6, tag=1)
-    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec,
+                          flags=rgs.FLAG_THETA_BF16 if table else 0)
     st, stat, reps, hists, xs = _batched(gpu_handle, systems, desc)
     assert st == 0 and stat == [0] * len(systems)
     for sysm, rep, hist, x in zip(systems, reps, hists, xs):
@@ -82,12 +87,14 @@ def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec):
         assert torch.equal(x, x1)
 
 
-@pytest.mark.parametrize("sketch,prec", [("srht", "fp32"), ("gaussian", "bf16q")])
-def test_graph_replay_equals_eager(gpu_handle, sketch, prec):
+@pytest.mark.parametrize("sketch,prec,table", [("srht", "fp32", False), ("gaussian", "bf16q", False),
+                                               ("gaussian", "fp32", True)])
+def test_graph_replay_equals_eager(gpu_handle, sketch, prec, table):
     rgs = _rgs()
     systems = _systems(7, tag=2)
-    d_eager = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec)
-    d_graph = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, flags=rgs.FLAG_GRAPH)
+    tf = rgs.FLAG_THETA_BF16 if table else 0
+    d_eager = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, flags=tf)
+    d_graph = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, flags=rgs.FLAG_GRAPH | tf)
     a = _batched(gpu_handle, systems, d_eager)
     # host work between the runs, as an application would do
     torch.cuda.synchronize()
