@@ -55,6 +55,23 @@ def test_identity_sketch_with_richardson1_is_cgs_bitwise():
     assert np.array_equal(out["R"], Rc)
 
 
+def test_identity_sketch_with_richardson2_is_cgs2():
+    """Two Richardson sweeps with Theta = I are CGS with one re-orthogonalisation
+    (the same two sets of coefficients; RGS subtracts their sum in one pass,
+    CGS2 in two, so the columns agree to O(u kappa))."""
+    n, m = 300, 20
+    W = _wellcond(n, m, smin=1e-4, tag=3)
+    uk = U64 * metrics.cond(W)
+    out = rgs.rgs_qr(W, sketch.Identity(n), ls="richardson2")
+    Qc, Rc = rgs.cgs2(W)
+    assert np.linalg.norm(out["R"] - Rc) <= 1e-13 * np.linalg.norm(Rc)
+    assert np.linalg.norm(out["Q"] - Qc) <= 100 * uk * np.linalg.norm(Qc)
+    assert metrics.orth_loss_2(out["Q"]) <= 100 * uk
+    # one sweep (CGS) loses orthogonality at O(u kappa^2): the second sweep is what restores it
+    q1 = rgs.rgs_qr(W, sketch.Identity(n), ls="richardson1")["Q"]
+    assert metrics.orth_loss_2(q1) > 100 * metrics.orth_loss_2(out["Q"])
+
+
 def test_identity_sketch_householder_matches_householder_qr():
     n, m = 400, 24
     W = _wellcond(n, m, smin=1e-2, tag=3)
