@@ -453,6 +453,14 @@ def main():
                                         "backward_error": rres, "norm2_I_minus_StS": rd2}
         log("  %.2f ms/QR (%.1f GB/s), projection+sketch kernel %.1f GB/s, ||W-QR||/||W|| %.2e" %
             (msr, B / (msr / 1000) / 1e9, extra["fp32_rgs_rademacher"]["projection_gbs"], rres))
+        # step 2 by two Richardson sweeps on the normal equations instead of Householder
+        drich = rgs.qr_desc(n, m, k, sketch="srht", prec="fp32", ls_sweeps=2)
+        log("fp32 RGS, SRHT, Richardson least squares (2 sweeps): 1 warmup, 2 steps")
+        msr2, _, repr2 = run_steps(rgs, torch, h, drich, W32, Q, R, S, 2, 1)
+        r2res, r2d2, _ = quality(torch, W32, Q, R, S)
+        extra["fp32_rgs_srht_richardson2"] = {"ms_per_qr": msr2, "status": repr2.status, "backward_error": r2res,
+                                              "norm2_I_minus_StS": r2d2}
+        log("  %.2f ms/QR, ||W-QR||/||W|| %.2e, ||I-S^TS||_2 %.2e" % (msr2, r2res, r2d2))
         # the same factorisation with the a-posteriori certification of Theta (Prop. 3.7)
         dcert = rgs.qr_desc(n, m, k, sketch="srht", prec="fp32", flags=rgs.FLAG_CERTIFY)
         log("fp32 RGS, SRHT, with certification: 1 warmup, 2 steps")

@@ -110,7 +110,11 @@ typedef struct {
     int32_t sketch;      /* rgs_sketch */
     int32_t prec;        /* rgs_precision */
     uint32_t flags;      /* RGS_FLAG_* */
-    uint32_t reserved;   /* must be 0 */
+    uint32_t ls_sweeps;  /* step 2 solver of rgs_qr (ignored by the sketch hooks): 0 = Householder QR of S in
+                            compact-WY form; 1..8 = that many Richardson iterations on the normal
+                            equations, y = S^T p then y += S^T (p - S y) (remark on the least-squares
+                            solver, Sec. 2.3): 1 is the sketched classical Gram-Schmidt, 2 its
+                            re-orthogonalised form; EINVAL above 8 */
 } rgs_qr_desc;
 
 /* Constant-coefficient 7-point operator on an nx*ny*nz box, Dirichlet 0,

@@ -37,7 +37,7 @@ class QrDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("sketch_id", ctypes.c_uint32), ("instance", ctypes.c_uint32),
                 ("sketch", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("ls_sweeps", ctypes.c_uint32)]
 
 
 class Stencil7(ctypes.Structure):
@@ -222,10 +222,11 @@ class Handle:
             pass
 
 
-def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=0, flags=0):
-    """prec: 'fp64', 'fp32' (fp32 projection, fp64 least squares) or 'bf16q' (bf16 basis)."""
+def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=0, flags=0, ls_sweeps=0):
+    """prec: 'fp64', 'fp32' (fp32 projection, fp64 least squares) or 'bf16q' (bf16 basis).
+    ls_sweeps: 0 = Householder least squares, s > 0 = s Richardson sweeps."""
     return QrDesc(n=n, m=m, k=k, seed=seed, sketch_id=sketch_id, instance=instance,
-                  sketch=SKETCH[sketch], prec=PREC[prec], flags=flags, reserved=0)
+                  sketch=SKETCH[sketch], prec=PREC[prec], flags=flags, ls_sweeps=ls_sweeps)
 
 
 def rgs_qr(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):

@@ -120,6 +120,8 @@ SketchArgs make_sketch(int sketch, int64_t k, uint64_t seed, uint32_t sid, uint3
     return sk;
 }
 
+constexpr uint32_t kMaxSweeps = 8;   // Richardson sweeps of step 2 accepted by rgs_qr
+
 int sketch_kind(int32_t sketch) {
     switch (sketch) {
         case RGS_SKETCH_GAUSSIAN: return SK_GAUSS;
@@ -137,7 +139,7 @@ bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (d->n < 1 || d->k < 1) return false;
     if (need_m && (d->m < 1 || d->m > d->k)) return false;
     if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64 && d->prec != RGS_P_BF16Q_FP32_LS64) return false;
-    if (d->reserved != 0) return false;
+    if (d->ls_sweeps > kMaxSweeps) return false;
     switch (d->sketch) {
         case RGS_SKETCH_GAUSSIAN:
             if (d->k > (int64_t)kKptMax * kWG) return false;
@@ -496,9 +498,13 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
         if (split && sketch_col && !launch_gauss_cols<TQ, T>(s, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
-        if (!launch_column<T, T>(s, sa, part, Gp, scale, (i == 0 && !DEFER) ? P : nullptr, (int)i, S, lds, R, ldr,
-                                 pnext, coef, DEFER ? sa.invr : nullptr))
-            return RGS_EDEVICE;
+        const double* src0 = (i == 0 && !DEFER) ? P : nullptr;
+        const bool ok = d->ls_sweeps > 0
+                            ? launch_column_richardson<T, T>(s, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr,
+                                                             pnext, coef, DEFER ? sa.invr : nullptr, (int)d->ls_sweeps)
+                            : launch_column<T, T>(s, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr, pnext, coef,
+                                                  DEFER ? sa.invr : nullptr);
+        if (!ok) return RGS_EDEVICE;
     }
     if constexpr (DEFER) {
         if (!launch_scale_cols_bf16(s, Q, ldq, n, (int)m, sa.invr, vec_ok ? 1 : 0, sa.status)) return RGS_EDEVICE;

@@ -41,6 +41,11 @@ template <typename T>
 bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const int* status);
 template <typename T>
 bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, double* R, int64_t ldr, T* coef);
+// The column step with step 2 by `sweeps` Richardson iterations on the normal equations.
+template <typename T, typename PT>
+bool launch_column_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
+                              const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
+                              const double* pnext, T* coef, const double* cscale, int sweeps);
 template <typename T, typename PT>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,

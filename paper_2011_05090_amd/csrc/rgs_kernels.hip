@@ -977,6 +977,57 @@ bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, 
     return true;
 }
 
+__global__ __launch_bounds__(kGW) void k_rb(int k, int i, int nsl, const double* __restrict__ sp,
+                                            const double* __restrict__ pd, int mcap, double* __restrict__ S,
+                                            int64_t lds, double* __restrict__ Sr, double* __restrict__ R, int64_t ldr,
+                                            double* __restrict__ rr, double* __restrict__ invr,
+                                            const double* __restrict__ pnorm, int* __restrict__ status,
+                                            const double* __restrict__ pn, double* __restrict__ pdb) {
+    rb_body(k, i, nsl, sp, pd, mcap, S, lds, Sr, R, ldr, rr, invr, pnorm, status, pn, pdb, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGW) void k_rsum(int i, int nsl, int mcap, const double* __restrict__ pdb,
+                                              double* __restrict__ y, int accumulate, int last,
+                                              double* __restrict__ pnorm, double* __restrict__ R, int64_t ldr,
+                                              T* __restrict__ coef, const double* __restrict__ cscale) {
+    rsum_body<T>(i, nsl, mcap, pdb, y, accumulate, last, pnorm, R, ldr, coef, cscale, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kGW) void k_rres(int k, int i, int mcap, const double* __restrict__ Sc, int64_t lds,
+                                              const double* __restrict__ Sr, const double* __restrict__ pn,
+                                              const double* __restrict__ y, double* __restrict__ pdb) {
+    rres_body(k, i, mcap, Sc, lds, Sr, pn, y, pdb, blockIdx.x);
+}
+
+// The column step with step 2 by `sweeps` Richardson iterations (sweeps >= 1).
+template <typename T, typename PT>
+bool launch_column_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
+                              const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
+                              const double* pnext, T* coef, const double* cscale, int sweeps) {
+    const int nsl = (a.k + kSlice - 1) / kSlice;
+    // s' and the slice partials of ||s'||^2 (slot 0)
+    hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, src, a.k, 0, a.Wr, a.mcap, a.sp,
+                       a.pd, (const double*)nullptr);
+    RGS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rb, dim3(nsl), dim3(kGW), 0, st, a.k, i, nsl, a.sp, a.pd, a.mcap, S, lds, a.Wr, R, ldr, a.rr,
+                       a.invr, a.pnorm, a.status, pnext, a.pdb);
+    RGS_LAUNCH_CHECK();
+    if (!pnext) return true;
+    const unsigned nb = nblocks(i + 1, kGW);
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const int last = sw + 1 == sweeps;
+        hipLaunchKernelGGL(k_rsum<T>, dim3(nb), dim3(kGW), 0, st, i, nsl, a.mcap, a.pdb, a.uh, sw > 0 ? 1 : 0, last,
+                           a.pnorm, R, ldr, coef, cscale);
+        RGS_LAUNCH_CHECK();
+        if (!last) {
+            hipLaunchKernelGGL(k_rres, dim3(nsl), dim3(kGW), 0, st, a.k, i, a.mcap, S, lds, a.Wr, pnext, a.uh, a.pdb);
+            RGS_LAUNCH_CHECK();
+        }
+    }
+    return true;
+}
+
 template <typename T, typename PT>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
@@ -1114,6 +1165,12 @@ template bool launch_ls_partials<float, float>(hipStream_t, const SpaceArgs&, co
                                                double*, int64_t, float*, const double*, const double*);
 template bool launch_ls_partials<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double, int,
                                                  double*, int64_t, double*, const double*, const double*);
+template bool launch_column_richardson<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double,
+                                                     const double*, int, double*, int64_t, double*, int64_t,
+                                                     const double*, float*, const double*, int);
+template bool launch_column_richardson<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
+                                                       const double*, int, double*, int64_t, double*, int64_t,
+                                                       const double*, double*, const double*, int);
 template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, const double*,
                                           int, double*, int64_t, double*, int64_t, const double*, float*,
                                           const double*);

@@ -376,4 +376,103 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
     if (q == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
 }
 
+// ---------------------------------------------------------------------------
+// Step 2 by Richardson iterations on the normal equations (remark on the
+// least-squares solver in Sec. 2.3): y = S^T p, then y <- y + S^T (p - S y)
+// per further sweep; one sweep is the sketched classical Gram-Schmidt.  S is
+// kept row-major as well (stride mcap, in the Wr buffer, unused by this
+// solver otherwise) for the column-parallel dot products.  Steps 5-6 are as
+// in the Householder chain (qa_body run with i = 0 gives s' and the slice
+// partials of ||s'||^2).
+// ---------------------------------------------------------------------------
+
+// Column step B (Richardson): r_ii = ||s'||, S(:, i) = s'/r_ii in both
+// layouts, breakdown test as qb_body (without the Householder beta test), and,
+// when the next right-hand side pn is given, the slice partials of S_{i+1}^T pn
+// (slots 0..i) and ||pn||^2 (slot i+1), stride mcap + 2.
+__device__ __forceinline__ void rb_body(int k, int i, int nsl, const double* __restrict__ sp,
+                                        const double* __restrict__ pd, int mcap, double* __restrict__ S, int64_t lds,
+                                        double* __restrict__ Sr, double* __restrict__ R, int64_t ldr,
+                                        double* __restrict__ rr, double* __restrict__ invr,
+                                        const double* __restrict__ pnorm, int* __restrict__ status,
+                                        const double* __restrict__ pn, double* __restrict__ pdb, int bid) {
+    __shared__ double ss[kSlice], ps[kSlice];
+    __shared__ double rii_s;
+    if (threadIdx.x == 0) rii_s = sqrt(sum_col(pd, nsl, mcap + 1, 0));
+    __syncthreads();
+    const double rii = rii_s;
+    if (bid == 0 && threadIdx.x == 0) {
+        rr[i] = rii;
+        invr[i] = 1.0 / rii;
+        R[i + (int64_t)i * ldr] = rii;
+        const double pnv = (i == 0) ? rii : pnorm[i];
+        if (status[0] == 0 && status[2] == 0) {
+            if (!isfinite(rii) || !isfinite(pnv)) {
+                status[1] = i;
+                status[0] = kStatusNonfinite;
+            } else if (rii == 0.0 || rii <= 0x1p-50 * pnv) {
+                status[1] = i;
+                status[0] = kStatusBreakdown;
+            }
+        }
+    }
+    const int r0 = bid * kSlice;
+    if (threadIdx.x < kSlice) {
+        const int r = r0 + threadIdx.x;
+        double sv = 0.0, pv = 0.0;
+        if (r < k) {
+            sv = sp[r] / rii;
+            S[r + (int64_t)i * lds] = sv;
+            Sr[(int64_t)r * mcap + i] = sv;
+            if (pn) pv = pn[r];
+        }
+        ss[threadIdx.x] = sv;
+        ps[threadIdx.x] = pv;
+    }
+    __syncthreads();
+    if (!pn) return;
+    double* out = pdb + (int64_t)bid * (mcap + 2);
+    // column i from shared memory: this workgroup's own writes of Sr are not read back
+    for (int c = threadIdx.x; c <= i + 1; c += kGW)
+        out[c] = (c < i) ? slice_dot(Sr, mcap, r0, k, ps, c) : (c == i ? slice_xy(ss, ps) : slice_sq(ps));
+}
+
+// Richardson: y[c] = (y[c] +) sum of the slice partials (c <= i); the first
+// sweep also sets pnorm[i+1] from slot i+1; the last writes R(0:i+1, i+1) = y
+// and the working-precision coefficients (times cscale[c] when given).
+template <typename T>
+__device__ __forceinline__ void rsum_body(int i, int nsl, int mcap, const double* __restrict__ pdb,
+                                          double* __restrict__ y, int accumulate, int last,
+                                          double* __restrict__ pnorm, double* __restrict__ R, int64_t ldr,
+                                          T* __restrict__ coef, const double* __restrict__ cscale, int bid) {
+    const int c = bid * kGW + threadIdx.x;
+    if (c <= i) {
+        double v = sum_col(pdb, nsl, mcap + 2, c);
+        if (accumulate) v += y[c];
+        y[c] = v;
+        if (last) {
+            R[c + (int64_t)(i + 1) * ldr] = v;
+            coef[c] = (T)(cscale ? v * cscale[c] : v);
+        }
+    }
+    if (!accumulate && bid == 0 && threadIdx.x == 0) pnorm[i + 1] = sqrt(sum_col(pdb, nsl, mcap + 2, i + 1));
+}
+
+// Richardson, one more sweep: t = pn - S y on the slice's rows (row-parallel),
+// then the slice partials of S^T t (slots 0..i, stride mcap + 2).
+__device__ __forceinline__ void rres_body(int k, int i, int mcap, const double* __restrict__ Sc, int64_t lds,
+                                          const double* __restrict__ Sr, const double* __restrict__ pn,
+                                          const double* __restrict__ y, double* __restrict__ pdb, int bid) {
+    __shared__ double red[kGQ][64];
+    __shared__ double ts[kSlice];
+    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int r = bid * kSlice + rl;
+    red[q][rl] = (r < k) ? row_part(Sc, lds, r, 0, i + 1, y, q) : 0.0;
+    __syncthreads();
+    if (q == 0) ts[rl] = (r < k) ? pn[r] - combine16(red, rl) : 0.0;
+    __syncthreads();
+    double* out = pdb + (int64_t)bid * (mcap + 2);
+    for (int c = threadIdx.x; c <= i; c += kGW) out[c] = slice_dot(Sr, mcap, bid * kSlice, k, ts, c);
+}
+
 }  // namespace rgs
