@@ -82,6 +82,152 @@ __device__ __forceinline__ T stencil_row(const Grid3& g, int64_t l, const Load& 
     return acc;
 }
 
+// Four stored values at rows l .. l+3 (l % 4 == 0, 16-byte aligned fp32 /
+// 8-byte bf16 / 2 x 16-byte fp64 vector loads), widened to double.
+__device__ __forceinline__ void ld4_raw(const float* __restrict__ p, int64_t l, double o[4]) {
+    const f32x4 t = *reinterpret_cast<const f32x4*>(p + l);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+}
+__device__ __forceinline__ void ld4_raw(const double* __restrict__ p, int64_t l, double o[4]) {
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const f64x2 a = *reinterpret_cast<const f64x2*>(p + l), b = *reinterpret_cast<const f64x2*>(p + l + 2);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ __forceinline__ void ld4_raw(const bf16* __restrict__ p, int64_t l, double o[4]) {
+    const u32x2 t = *reinterpret_cast<const u32x2*>(p + l);
+    o[0] = __uint_as_float(t.x << 16);
+    o[1] = __uint_as_float(t.x & 0xFFFF0000u);
+    o[2] = __uint_as_float(t.y << 16);
+    o[3] = __uint_as_float(t.y & 0xFFFF0000u);
+}
+
+// Rows l0 .. l0+3 (l0 % 4 == 0) of w = A u, u = (T)(stored * ir) when scale,
+// else (T)stored; out[r] = 0 past n, cen[r] = u at row l0 + r.  Same per-row
+// association as stencil_row, so the same bits.  With vec (nx % 4 == 0 and an
+// aligned column) the four rows share y and z: the centre and each of the
+// four y/z neighbour planes are one vector load, plus the two x neighbours
+// outside the group.  Otherwise the rows are stepped from one coordinate
+// division and read element by element.
+template <typename T, typename TQ>
+__device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ qs, bool scale, double ir,
+                                         bool vec, int64_t l0, int64_t n, T out[4], T cen[4]) {
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz, nxy = nx * ny;
+    const uint32_t lu = (uint32_t)l0;
+    uint32_t z = lu / nxy;
+    const uint32_t rem = lu - z * nxy;
+    uint32_t y = rem / nx;
+    uint32_t x = rem - y * nx;
+    auto cv = [&](double d) -> T { return scale ? (T)(d * ir) : (T)d; };
+    auto ld1 = [&](int64_t idx) -> T { return cv(to_double(qs[idx])); };
+    if (vec) {
+        if (l0 >= n) {   // n is a multiple of 4 here: whole groups only
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[r] = cen[r] = T(0);
+            return;
+        }
+        double a[4];
+        T u[4], ym[4], yp[4], zm[4], zp[4];
+        ld4_raw(qs, l0, a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u[r] = cv(a[r]);
+        const T xm = x > 0 ? ld1(l0 - 1) : T(0);
+        const T xp = x + 4 < nx ? ld1(l0 + 4) : T(0);
+        auto plane = [&](bool ok, int64_t at, T o[4]) {
+            if (ok) {
+                ld4_raw(qs, at, a);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = cv(a[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = T(0);
+            }
+        };
+        plane(y > 0, l0 - nx, ym);
+        plane(y + 1 < ny, l0 + nx, yp);
+        plane(z > 0, l0 - (int64_t)nxy, zm);
+        plane(z + 1 < nz, l0 + (int64_t)nxy, zp);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T acc = (T)g.c0 * u[r];
+            acc = acc + (x + r > 0 ? (T)g.cxm * (r > 0 ? u[r - 1] : xm) : T(0));
+            acc = acc + (x + r + 1 < nx ? (T)g.cxp * (r < 3 ? u[r + 1] : xp) : T(0));
+            acc = acc + (y > 0 ? (T)g.cym * ym[r] : T(0));
+            acc = acc + (y + 1 < ny ? (T)g.cyp * yp[r] : T(0));
+            acc = acc + (z > 0 ? (T)g.czm * zm[r] : T(0));
+            acc = acc + (z + 1 < nz ? (T)g.czp * zp[r] : T(0));
+            out[r] = acc;
+            cen[r] = u[r];
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t l = l0 + r;
+        if (l < n) {
+            const T c = ld1(l);
+            T acc = (T)g.c0 * c;
+            acc = acc + (x > 0 ? (T)g.cxm * ld1(l - 1) : T(0));
+            acc = acc + (x + 1 < nx ? (T)g.cxp * ld1(l + 1) : T(0));
+            acc = acc + (y > 0 ? (T)g.cym * ld1(l - nx) : T(0));
+            acc = acc + (y + 1 < ny ? (T)g.cyp * ld1(l + nx) : T(0));
+            acc = acc + (z > 0 ? (T)g.czm * ld1(l - (int64_t)nxy) : T(0));
+            acc = acc + (z + 1 < nz ? (T)g.czp * ld1(l + (int64_t)nxy) : T(0));
+            out[r] = acc;
+            cen[r] = c;
+        } else {
+            out[r] = cen[r] = T(0);
+        }
+        if (++x == nx) {
+            x = 0;
+            if (++y == ny) {
+                y = 0;
+                ++z;
+            }
+        }
+    }
+}
+
+// Stores 4 values at rows l0 .. l0+3 (rows past n skipped): one vector store
+// when the group is whole and aligned.
+template <typename T>
+__device__ __forceinline__ void st4(T* __restrict__ w, int64_t l0, int64_t n, bool vec, const T v[4]) {
+    if (vec && l0 + 4 <= n) {
+        if constexpr (sizeof(T) == 4) {
+            f32x4 t;
+            t.x = v[0];
+            t.y = v[1];
+            t.z = v[2];
+            t.w = v[3];
+            *reinterpret_cast<f32x4*>(w + l0) = t;
+        } else {
+            typedef double f64x2 __attribute__((ext_vector_type(2)));
+            f64x2 a, b;
+            a.x = v[0];
+            a.y = v[1];
+            b.x = v[2];
+            b.y = v[3];
+            *reinterpret_cast<f64x2*>(w + l0) = a;
+            *reinterpret_cast<f64x2*>(w + l0 + 2) = b;
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (l0 + r < n) w[l0 + r] = v[r];
+}
+
+template <typename TQ, typename T>
+__device__ __forceinline__ bool stencil_vec_ok(const Grid3& g, const TQ* qs, const T* w) {
+    return (g.nx % 4 == 0) && ((reinterpret_cast<uintptr_t>(qs) & (4 * sizeof(TQ) - 1)) == 0) &&
+           ((reinterpret_cast<uintptr_t>(w) & (4 * sizeof(T) - 1)) == 0);
+}
+
 // ---------------------------------------------------------------------------
 // Device bodies
 // ---------------------------------------------------------------------------
@@ -99,17 +245,14 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
     constexpr int NW = kProjWaves;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double ir = invr ? invr[0] : 1.0;
-    auto ld = [&](int64_t idx) -> T { return invr ? (T)(to_double(qs[idx]) * ir) : (T)to_double(qs[idx]); };
+    const bool vec = stencil_vec_ok(g, qs, w);
     T v[16];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t l = r0 + r;
-            v[4 * e + r] = (l < n) ? stencil_row<T>(g, l, ld) : T(0);
-            if (l < n) w[l] = v[4 * e + r];
-        }
+        T c[4];
+        stencil4<T, TQ>(g, qs, invr != nullptr, ir, vec, r0, n, v + 4 * e, c);
+        st4<T>(w, r0, n, vec, v + 4 * e);
     }
     if (!do_sketch) return;
     if constexpr (SK == SK_IDENT) {
@@ -150,22 +293,18 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
                                                   T* __restrict__ lds) {
     constexpr int NW = kProjWaves, NT = NW * kWave, RB = NW * kTile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    auto ld = [&](int64_t idx) -> T { return (T)to_double(xs[idx]); };
+    const bool vec = stencil_vec_ok(g, xs, t_out);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int local = wave * kTile + 256 * e + 4 * lane;
         const int64_t r0 = blk * RB + local;
+        T tv[4], xv[4];
+        stencil4<T, TQ>(g, xs, false, 1.0, vec, r0, n, tv, xv);
+        st4<T>(t_out, r0, n, vec, tv);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t l = r0 + r;
-            T tv = T(0), xv = T(0);
-            if (l < n) {
-                tv = stencil_row<T>(g, l, ld);
-                xv = ld(l);
-                t_out[l] = tv;
-            }
-            lds[local + r] = xv;
-            lds[RB + local + r] = tv;
+            lds[local + r] = xv[r];
+            lds[RB + local + r] = tv[r];
         }
     }
     __syncthreads();
