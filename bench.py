@@ -297,6 +297,59 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
     return out
 
 
+def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=(25, 50, 100, 150, 200, 250, 300),
+              eps_star=0.05):
+    """The synthetic-function experiment of Sec. 5.1 at the paper's size: W_ij =
+    f_mu_j(x_i) = sin(10 (mu_j + x_i)) / (cos(100 (mu_j - x_i)) + 1.1) on n = 10^6
+    evenly spaced x in [0, 1] and m = 300 evenly spaced mu in [0, 1], fp32 W,
+    multi-precision RGS (fp32 projection, fp64 least squares) with P-SRHT
+    k in {1500, 5000}.  For prefixes W_i (factorised with the a-posteriori
+    certificate, Phi of Theta's size, eps* = 0.05) it reports what the paper
+    plots: cond(Q_i), cond(S_i), ||W_i - Q_i R_i|| / ||W_i||, the embedding
+    distortion omega of Theta on range(Q_i) and its bound omega_bar.  The
+    paper's classical comparison methods and its unique-precision RGS are not
+    run.  Metrics are computed in fp64 on the device (measurement code)."""
+    import numpy as np
+    W = rgs.colmajor(n, m, torch.float32)
+    W.copy_(torch.from_numpy(synth.f_mu_matrix(n, m, np.float64)).to("cuda"))
+    W64 = W.double()
+    out = {"n": n, "m": m, "eps_star": eps_star, "precision": "fp32 projection, fp64 LS", "sketch": "srht"}
+    for k in ks:
+        rows = []
+        for i in prefixes:
+            Wi = W[:, :i]
+            Q = rgs.colmajor(n, i, torch.float32)
+            R = rgs.colmajor(i, i, torch.float64)
+            S = rgs.colmajor(k, i, torch.float64)
+            d = rgs.qr_desc(n, i, k, sketch="srht", prec="fp32", flags=rgs.FLAG_CERTIFY)
+            rep = rgs.rgs_qr(h, d, Wi, Q, R, S)
+            torch.cuda.synchronize()
+            Q64 = Q.double()
+            G = Q64.T @ Q64
+            ev = torch.linalg.eigvalsh(G)
+            cond_q = float(torch.sqrt(ev[-1] / ev[0]))
+            sv = torch.linalg.svdvals(S)
+            cond_s = float(sv[0] / sv[-1])
+            err = float(torch.linalg.norm(W64[:, :i] - Q64 @ R) / torch.linalg.norm(W64[:, :i]))
+            # omega: distortion of Theta on range(Q_i), from an l2-orthonormal basis U = Q C^-1
+            C = torch.linalg.cholesky(G, upper=True)
+            U = Q64 @ torch.linalg.inv(C)          # i x i inverse: cond(Q_i) is O(1)
+            TU = rgs.colmajor(k, i, torch.float64)
+            rgs.rgs_sketch_apply(h, rgs.qr_desc(n, i, k, sketch="srht", prec="fp64"), U.contiguous().T.contiguous().T,
+                                 TU)
+            torch.cuda.synchronize()
+            omega = float(torch.linalg.matrix_norm(torch.eye(i, dtype=torch.float64, device="cuda") - TU.T @ TU, 2))
+            obar = rgs.rgs_omega_bar(rep.cert_smin_q, rep.cert_smax_q, eps_star)
+            rows.append({"i": i, "status": rep.status, "cond_Q": cond_q, "cond_S": cond_s, "error": err,
+                         "omega": omega, "omega_bar": obar, "seconds": rep.seconds})
+            log("  sec5.1 k=%d i=%d: cond(Q) %.3f cond(S) %.3f err %.2e omega %.3f omega_bar %.3f (%.1f ms)" %
+                (k, i, cond_q, cond_s, err, omega, obar, 1000 * rep.seconds))
+            del Q, R, S, Q64, G, C, U, TU
+        out["k%d" % k] = rows
+    del W, W64
+    return out
+
+
 def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6):
     """Time-to-1e-6 of restarted randomized GMRES on the 7-point convection-diffusion
     system (N^3 unknowns, b ~ N(0,1)), fp32 basis vs plain fp64, Gaussian and SRHT."""
@@ -349,7 +402,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched and small fp64 QR legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--only", choices=["small", "batched-qr", "batched-gmres", "gmres"],
+    ap.add_argument("--only", choices=["small", "batched-qr", "batched-gmres", "gmres", "sec51"],
                     help="profiling aid: run only this leg and print its JSON (not the benchmark line)")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
@@ -371,7 +424,7 @@ def main():
     if args.only:
         h = rgs.Handle(0)
         leg = {"small": small_fp64_leg, "batched-qr": batched_qr_leg, "batched-gmres": batched_gmres_leg,
-               "gmres": gmres_leg}[args.only]
+               "gmres": gmres_leg, "sec51": sec51_leg}[args.only]
         res = leg(rgs, torch, synth, h)
         h.close()
         print(json.dumps({"only": args.only, "result": res}), flush=True)
@@ -492,6 +545,9 @@ def main():
         out.setdefault("extra", {})["fp64_rgs_n16384_m64"] = small_fp64_leg(rgs, torch, synth, h)
     if not args.no_gmres:
         out.setdefault("extra", {})["rgmres_convdiff_192"] = gmres_leg(rgs, torch, synth, h)
+    if not args.no_extra:
+        log("Sec. 5.1 synthetic functions, n = 10^6, m = 300")
+        out.setdefault("extra", {})["sec51_functions"] = sec51_leg(rgs, torch, synth, h)
     if not args.no_batched:
         log("batched RGS QR (bf16 Q)")
         out["extra"]["batched_qr_2048"] = batched_qr_leg(rgs, torch, synth, h)

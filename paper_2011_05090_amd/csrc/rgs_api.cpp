@@ -121,6 +121,9 @@ SketchArgs make_sketch(int sketch, int64_t k, uint64_t seed, uint32_t sid, uint3
 }
 
 constexpr uint32_t kMaxSweeps = 8;   // Richardson sweeps of step 2 accepted by rgs_qr
+// Sketch rows of a single call: kKptMax rows per thread of a 512-thread
+// workgroup (the batched calls keep 256-thread kernels: kKptMax * kWG).
+constexpr int64_t kMaxK = (int64_t)kKptMax * kProjWaves * kWave;
 
 int sketch_kind(int32_t sketch) {
     switch (sketch) {
@@ -142,15 +145,15 @@ bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (d->ls_sweeps > kMaxSweeps) return false;
     switch (d->sketch) {
         case RGS_SKETCH_GAUSSIAN:
-            if (d->k > (int64_t)kKptMax * kWG) return false;
+            if (d->k > kMaxK) return false;
             if (d->n > ((int64_t)1 << 34)) return false;   // counter word 0 holds l/4
             break;
         case RGS_SKETCH_RADEMACHER:
-            if (d->k > (int64_t)kKptMax * kWG) return false;
+            if (d->k > kMaxK) return false;
             if (d->n > ((int64_t)1 << 38)) return false;   // counter word 0 holds l/128
             break;
         case RGS_SKETCH_SRHT:
-            if (d->k > (int64_t)kKptMax * kWG) return false;
+            if (d->k > kMaxK) return false;
             if (d->k > srht_order(d->n)) return false;
             if (d->n > ((int64_t)1 << 31)) return false;
             break;
@@ -209,7 +212,7 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool c
     p.G_col = (dense_sketch(sketch) && n < kSplitRows)
                   ? (int)std::min<int64_t>((n + kGSubCol - 1) / kGSubCol, 256)
                   : 0;
-    const size_t per_col = (size_t)p.G_P * k * tsize;
+    const size_t per_col = (size_t)p.G_P * k * sizeof(double);   // step-1 partials accumulate in fp64
     p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
     p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
     p.rows = c.take<int>(k);
@@ -281,11 +284,13 @@ rgs_status use_table(rgs_handle* h, SketchArgs& sk, int64_t n, uint16_t* table) 
     return RGS_OK;
 }
 
-// Y = Theta X for ncols columns of X (element type TX, arithmetic and
-// partials in T, reduction in fp64), cc columns per pass.
-template <typename TX, typename T>
+// Y = Theta X for ncols columns of X (element type TX; Theta's entries and
+// the staging in T; accumulation and block partials in TA, fp64 for step 1 and
+// the certificate, as the paper's multi-precision model computes sketches at
+// u_fine; reduction in fp64), cc columns per pass.
+template <typename TX, typename T, typename TA>
 rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64_t ldx, int64_t n, int64_t ncols,
-                         int G, int cc, T* part, double* out, int64_t ldo) {
+                         int G, int cc, TA* part, double* out, int64_t ldo) {
     const double scale = sk.sketch == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)sk.k);
     for (int64_t c0 = 0; c0 < ncols; c0 += cc) {
         const int nc = (int)std::min<int64_t>(cc, ncols - c0);
@@ -302,11 +307,11 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64
             }
         }
         if (dense_sketch(sk.sketch)) {
-            if (!launch_gauss_cols<TX, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
-        } else if (!launch_sketch_cols<TX, T>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
+            if (!launch_gauss_cols<TX, T, TA>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
+        } else if (!launch_sketch_cols<TX, TA>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
             return RGS_EDEVICE;
         }
-        if (!launch_reduce<T>(h->stream, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
+        if (!launch_reduce<TA>(h->stream, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
     }
     return RGS_OK;
 }
@@ -355,7 +360,7 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     double* Y = Z2 + k * m;
     double* Md = Y + k * m;     // two m x m right factors
     double* Gd = Md + 2 * m * m;   // two m x m Gram matrices
-    T* part = reinterpret_cast<T*>(A + pl.part_P);
+    double* part = reinterpret_cast<double*>(A + pl.part_P);
     const size_t mm = (size_t)m * m;
     auto both = [](auto f) {   // f(0) and f(1) on two host threads
         std::thread t1([&]() { f(1); });
@@ -368,7 +373,7 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
                          hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return RGS_EDEVICE;
-    rgs_status st = sketch_matrix<TQ, T>(h, theta, Q, ldq, n, m, pl.G_P, pl.cc, part, thQ, k);
+    rgs_status st = sketch_matrix<TQ, T, double>(h, theta, Q, ldq, n, m, pl.G_P, pl.cc, part, thQ, k);
     if (st != RGS_OK) return st;
     // Phi of a bf16-table Theta is the Gaussian sketch generated on the fly
     const int phi_kind = theta.sketch == SK_TABLE ? SK_GAUSS : theta.sketch;
@@ -376,9 +381,9 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     // Theta's tables are no longer read: Phi's overwrite them in stream order
     st = setup_sketch(h, phi, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
-    st = sketch_matrix<TQ, T>(h, phi, Q, ldq, n, m, pl.G_P, pl.cc, part, phQ, k);
+    st = sketch_matrix<TQ, T, double>(h, phi, Q, ldq, n, m, pl.G_P, pl.cc, part, phQ, k);
     if (st != RGS_OK) return st;
-    st = sketch_matrix<T, T>(h, phi, W, ldw, n, m, pl.G_P, pl.cc, part, phW, k);
+    st = sketch_matrix<T, T, double>(h, phi, W, ldw, n, m, pl.G_P, pl.cc, part, phW, k);
     if (st != RGS_OK) return st;
     const std::vector<double> Rinv = dense::upper_inverse(Rh, mi);   // overlaps the sketches
     if (hipMemcpyAsync(Md, Rinv.data(), mm * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -461,14 +466,14 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     double* P = reinterpret_cast<double*>(A + pl.P);
     T* coef = reinterpret_cast<T*>(A + pl.coef);
     T* part = reinterpret_cast<T*>(A + pl.part_proj);
-    T* partP = reinterpret_cast<T*>(A + pl.part_P);
+    double* partP = reinterpret_cast<double*>(A + pl.part_P);
 
     hipStream_t s = h->stream;
     if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
     if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
 
     // Step 1 for every column at once: P = Theta W.
-    st = sketch_matrix<T, T>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
+    st = sketch_matrix<T, T, double>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
     if (st != RGS_OK) return st;
 
     const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;
@@ -865,7 +870,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         Off& o = off[q];
         o.signs = c.take<uint32_t>(sk_kind == SK_SRHT ? (n + 31) / 32 + 4 : 1);
         o.part = c.take<T>(std::max<int64_t>(nproj, npart_of(q)) * k);
-        o.partP = c.take<T>(gp_of(q) * k * m);
+        o.partP = c.take<double>(gp_of(q) * k * m);   // fp64 for SRHT, T for the Gaussian sketch
         o.P = c.take<double>(k * m);
         o.Vc = c.take<double>(k * m);
         o.Vr = c.take<double>(k * m);
@@ -1674,11 +1679,11 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     if (st != RGS_OK) return st;
     if (tab && (st = use_table(h, sk, d->n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
     if (d->prec == RGS_P_FP64)
-        st = sketch_matrix<double, double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
-                                   reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
+        st = sketch_matrix<double, double, double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P,
+                                                   pl.cc, reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
     else
-        st = sketch_matrix<float, float>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols, pl.G_P, pl.cc,
-                                  reinterpret_cast<float*>(A + pl.part_P), Y, ldy);
+        st = sketch_matrix<float, float, double>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols, pl.G_P,
+                                                 pl.cc, reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
     if (st != RGS_OK) return st;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
 }

@@ -21,6 +21,10 @@ constexpr int kBlock = 4096;   // rows per workgroup block (4 wave tiles)
 constexpr int kSlice = 64;     // sketch-space rows per workgroup
 constexpr int kKptMax = 16;    // sketch rows per thread: k <= 16 * 256
 constexpr int kProjWaves = 8;  // wave tiles per workgroup of the projection kernel
+// Step 3 sums the terms coef_c q_c of kProjGroup consecutive columns in a fresh
+// accumulator before subtracting them from w: fewer roundings of the large
+// running vector (fp32 accumulation throughout).
+constexpr int kProjGroup = 8;
 constexpr int kProjRows = kProjWaves * kTile;
 
 constexpr uint32_t kTagSigns = 0xFFFFFFFFu;  // counter word 1 of the SRHT sign draws

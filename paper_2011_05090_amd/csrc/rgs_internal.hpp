@@ -2,6 +2,8 @@
 // called by the host C ABI (rgs_api.cpp).  Not part of the public interface.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -17,9 +19,11 @@ bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int 
 // 256-row sub-blocks), each entry of Theta generated once per kGaussCols columns.
 constexpr int kGaussCols = 32;
 constexpr int kGSubCol = 64;   // rows per sub-block of the single-column Gaussian sketch
-template <typename TX, typename T>
+// Gaussian (drawn or bf16 table) / Rademacher sketches of ncols columns: T the
+// entry and staging type, TA the accumulation and partials type.
+template <typename TX, typename T, typename TA = T>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
-                       T* partials);
+                       TA* partials);
 template <typename PT>
 bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
                    int64_t ldo);

@@ -53,13 +53,30 @@ __global__ void kb_srht_signs(const BatchItem* __restrict__ items, BlockMap map)
                     it.sk.inst, (int64_t)bm.y * blockDim.x + threadIdx.x);
 }
 
+// 16 rows of a lane loaded as T (a float or bf16 column widened to double: the
+// step-1 sketches of the fp32 paths accumulate in fp64).
+template <typename T, typename TX>
+__device__ __forceinline__ void load16_as(const TX* __restrict__ p, const int64_t row0[4], int64_t n, bool full,
+                                          T v[16]) {
+    if constexpr (std::is_same<TX, T>::value) {
+        load16(p, row0, n, full, v);
+    } else {
+        float t[16];   // TX is float or bf16 here
+        load16(p, row0, n, full, t);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = (T)t[e];
+    }
+}
+
 // Partial sketches of ncols columns of X: workgroup (g, col) covers row blocks
-// g, g + G, ... (4096 rows each) and writes partials[(col * G + g) * k + j].
+// g, g + G, ... (NW * 1024 rows each) and writes partials[(col * G + g) * k + j].
 // TX: element type of X (float, double or bf16); T: arithmetic and partial type.
-template <typename TX, typename T, int SK>
+// NW = 4 (256 threads) for k <= 4096, NW = 8 (512 threads) for k <= 8192.
+template <typename TX, typename T, int SK, int NW = 4>
 __device__ __forceinline__ void sketch_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t nblk,
                                                  int G, const SketchArgs& sk, T* __restrict__ partials, int g,
                                                  int col, T* __restrict__ lds) {
+    constexpr int NT = NW * kWave;
     const TX* x = X + (int64_t)col * ldx;
     T acc[kKptMax];
 #pragma unroll
@@ -67,37 +84,38 @@ __device__ __forceinline__ void sketch_cols_body(const TX* __restrict__ X, int64
     const bool vec_ok = ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
     for (int64_t blk = g; blk < nblk; blk += G) {
         int64_t row0[4];
-        lane_rows<4>(blk, row0);
-        const bool full = vec_ok && (blk + 1) * kBlock <= n;
+        lane_rows<NW>(blk, row0);
+        const bool full = vec_ok && (blk + 1) * (NW * kTile) <= n;
         T v[16];
-        load16(x, row0, n, full, v);
-        block_sketch<T, T, SK, 4>(v, blk, n, sk, acc, lds);
+        load16_as<T>(x, row0, n, full, v);
+        block_sketch<T, T, SK, NW>(v, blk, n, sk, acc, lds);
     }
     T* out = partials + ((int64_t)col * G + g) * sk.k;
-    const int kpt = (sk.k + kWG - 1) / kWG;
+    const int kpt = (sk.k + NT - 1) / NT;
 #pragma unroll
     for (int u = 0; u < kKptMax; ++u) {
-        const int j = threadIdx.x + kWG * u;
+        const int j = threadIdx.x + NT * u;
         if (u < kpt && j < sk.k) out[j] = acc[u];
     }
 }
 
-template <typename TX, typename T, int SK>
-__global__ __launch_bounds__(kWG) void k_sketch_cols(const TX* __restrict__ X, int64_t ldx, int64_t n,
-                                                     int64_t nblk, int G, SketchArgs sk,
-                                                     T* __restrict__ partials) {
-    __shared__ T lds[kBlock];
-    sketch_cols_body<TX, T, SK>(X, ldx, n, nblk, G, sk, partials, blockIdx.x, blockIdx.y, lds);
+template <typename TX, typename T, int SK, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_sketch_cols(const TX* __restrict__ X, int64_t ldx, int64_t n,
+                                                            int64_t nblk, int G, SketchArgs sk,
+                                                            T* __restrict__ partials) {
+    __shared__ T lds[NW * kTile];
+    sketch_cols_body<TX, T, SK, NW>(X, ldx, n, nblk, G, sk, partials, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched step 1 (SRHT): map blocks are (factorisation, g + G_P * column).
 template <typename T, int SK>
 __global__ __launch_bounds__(kWG) void kb_sketch_cols(const BatchItem* __restrict__ items, BlockMap map) {
-    __shared__ T lds[kBlock];
+    __shared__ double lds[kBlock];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
-    sketch_cols_body<T, T, SK>(static_cast<const T*>(it.W), it.ldw, it.n, (it.n + kBlock - 1) / kBlock, it.G_P,
-                               it.sk, static_cast<T*>(it.partP), bm.y % it.G_P, bm.y / it.G_P, lds);
+    // fp64 accumulation, as the single-factorisation step 1
+    sketch_cols_body<T, double, SK>(static_cast<const T*>(it.W), it.ldw, it.n, (it.n + kBlock - 1) / kBlock, it.G_P,
+                                    it.sk, static_cast<double*>(it.partP), bm.y % it.G_P, bm.y / it.G_P, lds);
 }
 
 // Gaussian sketch of ncols columns with every entry of Theta generated once
@@ -114,16 +132,16 @@ __device__ __forceinline__ float elem_real(float v) { return v; }
 __device__ __forceinline__ double elem_real(double v) { return v; }
 __device__ __forceinline__ float elem_real(bf16 v) { return bf16_to_float(v.bits); }
 
-template <typename TX, typename T, int C, int SUB = kGSub>
+template <typename TX, typename T, typename TA, int C, int SUB = kGSub>
 __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
-                                                const SketchArgs& sk, T* __restrict__ partials, int g, int jc,
+                                                const SketchArgs& sk, TA* __restrict__ partials, int g, int jc,
                                                 int cc, T (*w)[SUB]) {
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
     const int nc = min(C, ncols - c0);
-    T acc[C];
+    TA acc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    for (int c = 0; c < C; ++c) acc[c] = TA(0);
     const int64_t nsub = (n + SUB - 1) / SUB;
     for (int64_t sb = g; sb < nsub; sb += G) {
         const int64_t r0 = sb * SUB;
@@ -143,8 +161,8 @@ __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_
                 gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const T x0 = w[c][4 * q], x1 = w[c][4 * q + 1], x2 = w[c][4 * q + 2], x3 = w[c][4 * q + 3];
-                    acc[c] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
+                    const TA x0 = w[c][4 * q], x1 = w[c][4 * q + 1], x2 = w[c][4 * q + 2], x3 = w[c][4 * q + 3];
+                    acc[c] += (TA)z[0] * x0 + (TA)z[1] * x1 + (TA)z[2] * x2 + (TA)z[3] * x3;
                 }
             }
         }
@@ -157,27 +175,27 @@ __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_
     }
 }
 
-template <typename TX, typename T, int C, int SUB>
+template <typename TX, typename T, typename TA, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
-                                                    int G, SketchArgs sk, T* __restrict__ partials) {
+                                                    int G, SketchArgs sk, TA* __restrict__ partials) {
     __shared__ __attribute__((aligned(16))) T w[C][SUB];
-    gauss_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+    gauss_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
 // Rademacher counterpart of gauss_cols_body (same workgroup and partials
 // layout): each Philox call gives the signs of 128 rows of sketch row j,
 // applied to the C staged columns.  SUB is a multiple of 128.
-template <typename TX, typename T, int C, int SUB>
+template <typename TX, typename T, typename TA, int C, int SUB>
 __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
-                                              const SketchArgs& sk, T* __restrict__ partials, int g, int jc, int cc,
+                                              const SketchArgs& sk, TA* __restrict__ partials, int g, int jc, int cc,
                                               T (*w)[SUB]) {
     static_assert(SUB % 128 == 0, "whole 128-row sign groups per sub-block");
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
     const int nc = min(C, ncols - c0);
-    T acc[C];
+    TA acc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    for (int c = 0; c < C; ++c) acc[c] = TA(0);
     const int64_t nsub = (n + SUB - 1) / SUB;
     for (int64_t sb = g; sb < nsub; sb += G) {
         const int64_t r0 = sb * SUB;
@@ -199,10 +217,10 @@ __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t 
                 for (int c4 = 0; c4 < 4; ++c4)
 #pragma unroll 8
                     for (int r = 0; r < 32; ++r) {
-                        const T sg = rad_sign<T>(wd[c4], r);
+                        const TA sg = rad_sign<TA>(wd[c4], r);
                         const int t = 128 * q + 32 * c4 + r;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) acc[c] = fma(sg, w[c][t], acc[c]);
+                        for (int c = 0; c < C; ++c) acc[c] = fma(sg, (TA)w[c][t], acc[c]);
                     }
             }
         }
@@ -215,11 +233,11 @@ __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t 
     }
 }
 
-template <typename TX, typename T, int C, int SUB>
+template <typename TX, typename T, typename TA, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_rad_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
-                                                  int G, SketchArgs sk, T* __restrict__ partials) {
+                                                  int G, SketchArgs sk, TA* __restrict__ partials) {
     __shared__ __attribute__((aligned(16))) T w[C][SUB];
-    rad_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+    rad_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
 // Table of the Gaussian sketch with bf16 entries: thread (o, j) draws
@@ -254,17 +272,17 @@ __global__ void k_theta_table(SketchArgs sk, int64_t n, int64_t ngroups, uint16_
 // Table counterpart of gauss_cols_body (same workgroup and partials layout):
 // each 16-byte table load serves 8 rows of sketch row j for the C staged
 // columns.  SUB is a multiple of 8.
-template <typename TX, typename T, int C, int SUB>
+template <typename TX, typename T, typename TA, int C, int SUB>
 __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
-                                                const SketchArgs& sk, T* __restrict__ partials, int g, int jc,
+                                                const SketchArgs& sk, TA* __restrict__ partials, int g, int jc,
                                                 int cc, T (*w)[SUB]) {
     static_assert(SUB % 8 == 0, "whole 8-row table groups per sub-block");
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
     const int nc = min(C, ncols - c0);
-    T acc[C];
+    TA acc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    for (int c = 0; c < C; ++c) acc[c] = TA(0);
     const int64_t nsub = (n + SUB - 1) / SUB;
     for (int64_t sb = g; sb < nsub; sb += G) {
         const int64_t r0 = sb * SUB;
@@ -280,13 +298,13 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
             const int no = rem >= SUB ? SUB / 8 : (int)((rem + 7) / 8);
             const int64_t o0 = r0 / 8;
             for (int o = 0; o < no; ++o) {
-                T z[8];
-                tab8<T>(sk.table, sk.k, o0 + o, j, z);
+                TA z[8];
+                tab8<TA>(sk.table, sk.k, o0 + o, j, z);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const T* x = w[c] + 8 * o;
-                    acc[c] += z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3];
-                    acc[c] += z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7];
+                    acc[c] += z[0] * (TA)x[0] + z[1] * (TA)x[1] + z[2] * (TA)x[2] + z[3] * (TA)x[3];
+                    acc[c] += z[4] * (TA)x[4] + z[5] * (TA)x[5] + z[6] * (TA)x[6] + z[7] * (TA)x[7];
                 }
             }
         }
@@ -299,11 +317,11 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
     }
 }
 
-template <typename TX, typename T, int C, int SUB>
+template <typename TX, typename T, typename TA, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_table_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
-                                                    int G, SketchArgs sk, T* __restrict__ partials) {
+                                                    int G, SketchArgs sk, TA* __restrict__ partials) {
     __shared__ __attribute__((aligned(16))) T w[C][SUB];
-    table_cols_body<TX, T, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+    table_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
 // Batched step 1 (Gaussian): map blocks are (factorisation, g + G_P (jc + njc cc)).
@@ -314,7 +332,7 @@ __global__ __launch_bounds__(kWG) void kb_gauss_cols(const BatchItem* __restrict
     const BatchItem& it = items[bm.x];
     const int njc = (it.k + kWG - 1) / kWG;
     const int rest = bm.y / it.G_P;
-    gauss_cols_body<T, T, kGaussCols>(static_cast<const T*>(it.W), it.ldw, it.n, it.m, it.G_P, it.sk,
+    gauss_cols_body<T, T, T, kGaussCols>(static_cast<const T*>(it.W), it.ldw, it.n, it.m, it.G_P, it.sk,
                                       static_cast<T*>(it.partP), bm.y % it.G_P, rest % njc, rest / njc, w);
 }
 
@@ -843,48 +861,52 @@ bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const Sk
 template <typename T, typename PT>
 bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int ncols, int G,
                         const SketchArgs& sk, PT* partials) {
-    const int64_t nblk = (n + kBlock - 1) / kBlock;
     dim3 grid(G, ncols);
-    if (sk.sketch == SK_SRHT)
-        hipLaunchKernelGGL((k_sketch_cols<T, PT, SK_SRHT>), grid, dim3(kWG), 0, st, X, ldx, n, nblk, G, sk,
-                           partials);
-    else
-        hipLaunchKernelGGL((k_sketch_cols<T, PT, SK_GAUSS>), grid, dim3(kWG), 0, st, X, ldx, n, nblk, G, sk,
-                           partials);
+    if (sk.k > kKptMax * kWG) {   // 512 threads, 8192-row blocks
+        const int64_t nblk = (n + kProjRows - 1) / kProjRows;
+        if (sk.sketch == SK_SRHT)
+            hipLaunchKernelGGL((k_sketch_cols<T, PT, SK_SRHT, kProjWaves>), grid, dim3(kProjWaves * kWave), 0, st, X,
+                               ldx, n, nblk, G, sk, partials);
+        else
+            hipLaunchKernelGGL((k_sketch_cols<T, PT, SK_GAUSS, kProjWaves>), grid, dim3(kProjWaves * kWave), 0, st,
+                               X, ldx, n, nblk, G, sk, partials);
+    } else {
+        const int64_t nblk = (n + kBlock - 1) / kBlock;
+        if (sk.sketch == SK_SRHT)
+            hipLaunchKernelGGL((k_sketch_cols<T, PT, SK_SRHT, 4>), grid, dim3(kWG), 0, st, X, ldx, n, nblk, G, sk,
+                               partials);
+        else
+            hipLaunchKernelGGL((k_sketch_cols<T, PT, SK_GAUSS, 4>), grid, dim3(kWG), 0, st, X, ldx, n, nblk, G, sk,
+                               partials);
+    }
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-template <typename TX, typename T>
+template <typename TX, typename T, typename TA>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
-                       T* partials) {
+                       TA* partials) {
     const unsigned jc = nblocks(sk.k, kWG);
+    const dim3 g1(G, jc, 1), gc(G, jc, nblocks(ncols, kGaussCols));
     if (sk.sketch == SK_TABLE) {
         if (ncols == 1)
-            hipLaunchKernelGGL((k_table_cols<TX, T, 1, kGSubCol>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G,
-                               sk, partials);
-        else
-            hipLaunchKernelGGL((k_table_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
-                               dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
-        RGS_LAUNCH_CHECK();
-        return true;
-    }
-    if (sk.sketch == SK_RADEM) {
-        if (ncols == 1)
-            hipLaunchKernelGGL((k_rad_cols<TX, T, 1, 128>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
+            hipLaunchKernelGGL((k_table_cols<TX, T, TA, 1, kGSubCol>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
                                partials);
         else
-            hipLaunchKernelGGL((k_rad_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
-                               dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
-        RGS_LAUNCH_CHECK();
-        return true;
-    }
-    if (ncols == 1) {   // the single-column sketch of a small-n step: 64-row sub-blocks
-        hipLaunchKernelGGL((k_gauss_cols<TX, T, 1, kGSubCol>), dim3(G, jc, 1), dim3(kWG), 0, st, X, ldx, n, 1, G,
-                           sk, partials);
+            hipLaunchKernelGGL((k_table_cols<TX, T, TA, kGaussCols, kGSub>), gc, dim3(kWG), 0, st, X, ldx, n, ncols,
+                               G, sk, partials);
+    } else if (sk.sketch == SK_RADEM) {
+        if (ncols == 1)
+            hipLaunchKernelGGL((k_rad_cols<TX, T, TA, 1, 128>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk, partials);
+        else
+            hipLaunchKernelGGL((k_rad_cols<TX, T, TA, kGaussCols, kGSub>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
+                               sk, partials);
+    } else if (ncols == 1) {   // the single-column sketch of a small-n step: 64-row sub-blocks
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, TA, 1, kGSubCol>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
+                           partials);
     } else {
-        hipLaunchKernelGGL((k_gauss_cols<TX, T, kGaussCols, kGSub>), dim3(G, jc, nblocks(ncols, kGaussCols)),
-                           dim3(kWG), 0, st, X, ldx, n, ncols, G, sk, partials);
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, TA, kGaussCols, kGSub>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
+                           sk, partials);
     }
     RGS_LAUNCH_CHECK();
     return true;
@@ -917,7 +939,12 @@ bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, c
         hipLaunchKernelGGL(kb_gauss_cols<T>, dim3(n_part), dim3(kWG), 0, st, items, map_part);
     }
     RGS_LAUNCH_CHECK();
-    if (n_red > 0) hipLaunchKernelGGL(kb_reduce<T>, dim3(n_red), dim3(kWG), 0, st, items, map_red);
+    if (n_red > 0) {
+        if (sketch == SK_SRHT)
+            hipLaunchKernelGGL(kb_reduce<double>, dim3(n_red), dim3(kWG), 0, st, items, map_red);
+        else
+            hipLaunchKernelGGL(kb_reduce<T>, dim3(n_red), dim3(kWG), 0, st, items, map_red);
+    }
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -1155,6 +1182,20 @@ template bool launch_sketch_cols<double, double>(hipStream_t, const double*, int
                                                  const SketchArgs&, double*);
 template bool launch_sketch_cols<bf16, float>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
                                               const SketchArgs&, float*);
+template bool launch_sketch_cols<float, double>(hipStream_t, const float*, int64_t, int64_t, int, int,
+                                                const SketchArgs&, double*);
+template bool launch_sketch_cols<bf16, double>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
+                                               const SketchArgs&, double*);
+template bool launch_gauss_cols<float, float, float>(hipStream_t, const float*, int64_t, int64_t, int, int,
+                                                     const SketchArgs&, float*);
+template bool launch_gauss_cols<double, double, double>(hipStream_t, const double*, int64_t, int64_t, int, int,
+                                                        const SketchArgs&, double*);
+template bool launch_gauss_cols<bf16, float, float>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
+                                                    const SketchArgs&, float*);
+template bool launch_gauss_cols<float, float, double>(hipStream_t, const float*, int64_t, int64_t, int, int,
+                                                      const SketchArgs&, double*);
+template bool launch_gauss_cols<bf16, float, double>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
+                                                     const SketchArgs&, double*);
 template bool launch_reduce<float>(hipStream_t, const float*, int, int, int, double, double*, int64_t);
 template bool launch_reduce<double>(hipStream_t, const double*, int, int, int, double, double*, int64_t);
 template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double*, const int*);
@@ -1185,12 +1226,6 @@ template bool launch_batch_gauss_gemm<float, false>(hipStream_t, const BatchItem
                                                     int, int);
 template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
                                           const BlockMap&, int64_t, const BlockMap&, int64_t);
-template bool launch_gauss_cols<float, float>(hipStream_t, const float*, int64_t, int64_t, int, int,
-                                              const SketchArgs&, float*);
-template bool launch_gauss_cols<double, double>(hipStream_t, const double*, int64_t, int64_t, int, int,
-                                                const SketchArgs&, double*);
-template bool launch_gauss_cols<bf16, float>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
-                                             const SketchArgs&, float*);
 template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
                                          int64_t, const BlockMap&, int64_t, int);
 template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,

@@ -21,7 +21,9 @@ namespace rgs {
 
 // Step 3 (+ step 4 partials, + step 7 of the previous column), for row block
 // blk of kProjWaves * 1024 rows:
-//   q'_i = w_i - sum_{c<j} coef[c] q_c        (working precision TW, fma chain in c order)
+//   q'_i = w_i - sum_{c<j} coef[c] q_c        (working precision TW; the terms of
+//   each group of kProjGroup columns are summed by an fma chain in c order, then
+//   subtracted)
 // If normalize_last, column j-1 still holds q'_{i-1} and is first scaled to
 // q_{i-1} = q'_{i-1} / r_{i-1,i-1} (fp64 multiply by the reciprocal, rounded
 // to the storage type) and written back.  q'_i is stored in column j, then the
@@ -52,12 +54,20 @@ __device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __res
         }
     }
     const int jl = (!DEFER && normalize_last) ? j - 1 : j;
-    for (int c = 0; c < jl; ++c) {
-        const TW a = coef[c];
-        TW q[16];
-        load16(Q + (int64_t)c * ldq, row0, n, full, q, vec_ok);
+    for (int c0 = 0; c0 < jl; c0 += kProjGroup) {
+        const int c1 = min(c0 + kProjGroup, jl);
+        TW g[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = fma(-a, q[t], v[t]);
+        for (int t = 0; t < 16; ++t) g[t] = TW(0);
+        for (int c = c0; c < c1; ++c) {
+            const TW a = coef[c];
+            TW q[16];
+            load16(Q + (int64_t)c * ldq, row0, n, full, q, vec_ok);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) g[t] = fma(a, q[t], g[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] -= g[t];
     }
     if constexpr (!DEFER) {
         if (normalize_last) {

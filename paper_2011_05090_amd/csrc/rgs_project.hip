@@ -78,12 +78,18 @@ __global__ __launch_bounds__(64) void k_project_rows(const TW* __restrict__ w, T
     TW v[4];
     load(w, v);
     const int jl = (!DEFER && normalize_last) ? j - 1 : j;
-    for (int c = 0; c < jl; ++c) {
-        const TW a = coef[c];
-        TW q[4];
-        load(Q + (int64_t)c * ldq, q);
+    for (int c0 = 0; c0 < jl; c0 += kProjGroup) {
+        const int c1 = min(c0 + kProjGroup, jl);
+        TW g[4] = {TW(0), TW(0), TW(0), TW(0)};
+        for (int c = c0; c < c1; ++c) {
+            const TW a = coef[c];
+            TW q[4];
+            load(Q + (int64_t)c * ldq, q);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = fma(-a, q[t], v[t]);
+            for (int t = 0; t < 4; ++t) g[t] = fma(a, q[t], g[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] -= g[t];
     }
     if constexpr (!DEFER) {
         if (normalize_last) {

@@ -95,7 +95,8 @@ def test_srht_materialize_is_bit_exact(gpu_handle):
 
 
 @pytest.mark.parametrize("sketch,n,k", [("srht", 10000, 256), ("srht", 300, 64), ("gaussian", 9000, 96),
-                                        ("identity", 777, 777), ("rademacher", 9000, 96), ("rademacher", 1000, 40)])
+                                        ("identity", 777, 777), ("rademacher", 9000, 96), ("rademacher", 1000, 40),
+                                        ("srht", 20000, 5000)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_sketch_apply_matches_oracle(gpu_handle, sketch, n, k, prec):
     rgs = _rgs()
@@ -148,7 +149,8 @@ def test_rademacher_fused_sketch_large_n(gpu_handle):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("sketch,n,m,k", [("gaussian", 16384, 64, 256), ("srht", 10000, 40, 256),
-                                          ("srht", 4096 * 3 + 17, 24, 128), ("rademacher", 4096 * 3 + 17, 24, 128)])
+                                          ("srht", 4096 * 3 + 17, 24, 128), ("rademacher", 4096 * 3 + 17, 24, 128),
+                                          ("srht", 8192 * 3 + 17, 24, 5000), ("gaussian", 9000, 12, 4500)])
 def test_fp64_qr_wellconditioned_forward_parity(gpu_handle, sketch, n, m, k):
     W = synth.svd_matrix(n, m, 1e-2, tag=11)
     rep, Q, R, S = run_qr(gpu_handle, W, k, sketch, "fp64")
