@@ -418,47 +418,73 @@ __device__ __forceinline__ void norm_finish_body(const double* __restrict__ part
 // form rotation c-1 that zeroes h_c, update g; record |g_c| / ||b|| in the
 // history and stop the cycle when it is <= tol, at a lucky breakdown
 // (status[0] = breakdown at column c: h_c = 0) or once c reaches `limit`.
-// Run by one thread: at most `restart` rotations of 2-vectors.
+// Called by every thread of one wave: the column is loaded into LDS (hs, at
+// least c + 1 doubles) in parallel, one thread runs the chain of rotations
+// with the running entry in a register and the rotations read 16 at a time,
+// and the rotated column is written back in parallel.
 __device__ __forceinline__ void givens_body(int c, const double* __restrict__ R, int mcap,
                                             double* __restrict__ Hr, double* __restrict__ cs,
                                             double* __restrict__ sn, double* __restrict__ gv, double bnorm,
                                             double tol, double* __restrict__ hist, int* __restrict__ status,
-                                            int* __restrict__ used, int limit) {
-    if (status[2] != 0) return;
-    bool lucky = false;
-    if (status[0] != 0) {
-        if (status[0] == kStatusBreakdown && status[1] == c) {
-            lucky = true;          // w_c numerically in span(Q_c): exact Krylov space reached
-        } else {
-            return;                // non-finite data: the host reports it
+                                            int* __restrict__ used, int limit, double* __restrict__ hs) {
+    __shared__ int mode;   // 0: skip, 1: normal step, 2: lucky breakdown
+    if (threadIdx.x == 0) {
+        int md = 1;
+        if (status[2] != 0) {
+            md = 0;
+        } else if (status[0] != 0) {
+            // w_c numerically in span(Q_c): exact Krylov space reached; otherwise non-finite data
+            md = (status[0] == kStatusBreakdown && status[1] == c) ? 2 : 0;
         }
+        mode = md;
     }
+    __syncthreads();
+    if (mode == 0) return;
+    const bool lucky = mode == 2;
+    for (int t = threadIdx.x; t <= c; t += blockDim.x)
+        hs[t] = (t == c && lucky) ? 0.0 : R[t + (int64_t)c * mcap];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double cur = hs[0];   // entry t of the column, already rotated by rotations < t
+        for (int t0 = 0; t0 < c - 1; t0 += 16) {
+            double cv[16], sv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                cv[u] = (t0 + u < c - 1) ? cs[t0 + u] : 0.0;
+                sv[u] = (t0 + u < c - 1) ? sn[t0 + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int t = t0 + u;
+                if (t < c - 1) {
+                    const double a = cur, bb = hs[t + 1];
+                    hs[t] = cv[u] * a + sv[u] * bb;
+                    cur = -sv[u] * a + cv[u] * bb;
+                }
+            }
+        }
+        const double a = cur, bb = hs[c];
+        double co = 1.0, si = 0.0, rho = a;
+        if (bb != 0.0) {
+            rho = hypot(a, bb);
+            co = a / rho;
+            si = bb / rho;
+        }
+        cs[c - 1] = co;
+        sn[c - 1] = si;
+        hs[c - 1] = rho;
+        hs[c] = 0.0;
+        gv[c] = -si * gv[c - 1];
+        gv[c - 1] = co * gv[c - 1];
+        const double est = fabs(gv[c]) / bnorm;
+        hist[c - 1] = est;
+        used[0] = c;
+        if (lucky) status[0] = 0;       // a lucky breakdown is not an error in GMRES
+        if (lucky || est <= tol || c >= limit) status[2] = 1;
+    }
+    __syncthreads();
     double* h = Hr + (int64_t)(c - 1) * mcap;   // rotated column c-1 of H
-    for (int t = 0; t < c; ++t) h[t] = R[t + (int64_t)c * mcap];
-    h[c] = lucky ? 0.0 : R[c + (int64_t)c * mcap];
-    for (int t = 0; t < c - 1; ++t) {
-        const double a = h[t], bb = h[t + 1];
-        h[t] = cs[t] * a + sn[t] * bb;
-        h[t + 1] = -sn[t] * a + cs[t] * bb;
-    }
-    const double a = h[c - 1], bb = h[c];
-    double co = 1.0, si = 0.0, rho = a;
-    if (bb != 0.0) {
-        rho = hypot(a, bb);
-        co = a / rho;
-        si = bb / rho;
-    }
-    cs[c - 1] = co;
-    sn[c - 1] = si;
-    h[c - 1] = rho;
-    h[c] = 0.0;
-    gv[c] = -si * gv[c - 1];
-    gv[c - 1] = co * gv[c - 1];
-    const double est = fabs(gv[c]) / bnorm;
-    hist[c - 1] = est;
-    used[0] = c;
-    if (lucky) status[0] = 0;       // a lucky breakdown is not an error in GMRES
-    if (lucky || est <= tol || c >= limit) status[2] = 1;
+    for (int t = threadIdx.x; t <= c; t += blockDim.x) h[t] = hs[t];
 }
 
 // y = Hr(0:u, 0:u)^{-1} g(0:u), u = used[0]: back substitution (one thread).
@@ -529,12 +555,13 @@ __global__ void k_cast(const double* __restrict__ src, T* __restrict__ dst, int6
     if (l < n) dst[l] = (T)src[l];
 }
 
-__global__ void k_givens(int c, const double* __restrict__ R, int mcap, double* __restrict__ Hr,
-                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ gv,
-                         double bnorm, double tol, double* __restrict__ hist, int* __restrict__ status,
-                         int* __restrict__ used, int limit) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    givens_body(c, R, mcap, Hr, cs, sn, gv, bnorm, tol, hist, status, used, limit);
+__global__ __launch_bounds__(64) void k_givens(int c, const double* __restrict__ R, int mcap,
+                                               double* __restrict__ Hr, double* __restrict__ cs,
+                                               double* __restrict__ sn, double* __restrict__ gv, double bnorm,
+                                               double tol, double* __restrict__ hist, int* __restrict__ status,
+                                               int* __restrict__ used, int limit) {
+    extern __shared__ double hs_dyn[];
+    givens_body(c, R, mcap, Hr, cs, sn, gv, bnorm, tol, hist, status, used, limit, hs_dyn);
 }
 
 // g(0) = r_11 = R(0, 0) at the start of a cycle.
@@ -689,14 +716,14 @@ __global__ void kg_givens_init(const BatchItem* __restrict__ items, const GmresI
     g.used[0] = 0;
 }
 
-__global__ void kg_givens(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
-                          BlockMap map, int c) {
+__global__ __launch_bounds__(64) void kg_givens(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
+                                                BlockMap map, int c) {
+    extern __shared__ double hs_dyn[];
     const int2 bm = locate(map, blockIdx.x);
-    if (threadIdx.x != 0) return;
     const BatchItem& it = items[bm.x];
     const GmresItem& g = gi[bm.x];
     givens_body(c, it.R, it.sa.mcap, g.Hr, g.cs, g.sn, g.gv, g.bnorm, g.tol, g.hist, it.sa.status, g.used,
-                g.limit[0]);
+                g.limit[0], hs_dyn);
 }
 
 __global__ void kg_backsub(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
@@ -803,8 +830,8 @@ bool launch_givens_init(hipStream_t st, const double* R, double* gv, int* used) 
 
 bool launch_givens(hipStream_t st, int c, const double* R, int mcap, double* Hr, double* cs, double* sn,
                    double* gv, double bnorm, double tol, double* hist, int* status, int* used, int limit) {
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, c, R, mcap, Hr, cs, sn, gv, bnorm, tol, hist, status,
-                       used, limit);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), (c + 1) * sizeof(double), st, c, R, mcap, Hr, cs, sn, gv,
+                       bnorm, tol, hist, status, used, limit);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -919,7 +946,7 @@ bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const Gmr
 bool launch_gbatch_givens(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
                           int64_t nsys, int c) {
     if (nsys == 0) return true;
-    hipLaunchKernelGGL(kg_givens, dim3(nsys), dim3(64), 0, st, items, gi, map_sys, c);
+    hipLaunchKernelGGL(kg_givens, dim3(nsys), dim3(64), (c + 1) * sizeof(double), st, items, gi, map_sys, c);
     RGS_LAUNCH_CHECK();
     return true;
 }
