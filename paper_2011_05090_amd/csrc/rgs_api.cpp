@@ -466,14 +466,16 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     double* P = reinterpret_cast<double*>(A + pl.P);
     T* coef = reinterpret_cast<T*>(A + pl.coef);
     T* part = reinterpret_cast<T*>(A + pl.part_proj);
-    double* partP = reinterpret_cast<double*>(A + pl.part_P);
+    // step 1 accumulates in fp64 (R-2), except on the bf16-basis path whose rounding dominates
+    using TP = typename std::conditional<DEFER, T, double>::type;
+    TP* partP = reinterpret_cast<TP*>(A + pl.part_P);
 
     hipStream_t s = h->stream;
     if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
     if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
 
     // Step 1 for every column at once: P = Theta W.
-    st = sketch_matrix<T, T, double>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
+    st = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
     if (st != RGS_OK) return st;
 
     const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;
@@ -1074,7 +1076,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     const int64_t i_tune = DEFER ? 0 : 1;
     if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, pre_sign[batch],
                                   BlockMap{d_part, nullptr, nb, 0}, pre_part[batch], BlockMap{d_red, nullptr, nb, 0},
-                                  pre_red[batch]))
+                                  pre_red[batch], !DEFER))
         return RGS_EDEVICE;
     for (int64_t i = 0; i < max_m; ++i) {
         const int a = active[i], a1 = active[i + 1];

@@ -61,7 +61,7 @@ bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64
 template <typename T>
 bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map_signs,
                            int64_t n_signs, const BlockMap& map_part, int64_t n_part, const BlockMap& map_red,
-                           int64_t n_red);
+                           int64_t n_red, bool acc64);
 // Batched Gaussian sketch products with the shared master matrix, one
 // workgroup per GemmUnit over the (item, column) list `cols` (tile: 32 or 64
 // columns per unit, as the units were built): STEP4, column i

@@ -108,14 +108,15 @@ __global__ __launch_bounds__(NW * kWave) void k_sketch_cols(const TX* __restrict
 }
 
 // Batched step 1 (SRHT): map blocks are (factorisation, g + G_P * column).
-template <typename T, int SK>
+// TA: accumulation type (fp64 on the fp32 path, as its single-factorisation
+// step 1; the working precision on the bf16-basis path).
+template <typename T, typename TA, int SK>
 __global__ __launch_bounds__(kWG) void kb_sketch_cols(const BatchItem* __restrict__ items, BlockMap map) {
-    __shared__ double lds[kBlock];
+    __shared__ TA lds[kBlock];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
-    // fp64 accumulation, as the single-factorisation step 1
-    sketch_cols_body<T, double, SK>(static_cast<const T*>(it.W), it.ldw, it.n, (it.n + kBlock - 1) / kBlock, it.G_P,
-                                    it.sk, static_cast<double*>(it.partP), bm.y % it.G_P, bm.y / it.G_P, lds);
+    sketch_cols_body<T, TA, SK>(static_cast<const T*>(it.W), it.ldw, it.n, (it.n + kBlock - 1) / kBlock, it.G_P,
+                                it.sk, static_cast<TA*>(it.partP), bm.y % it.G_P, bm.y / it.G_P, lds);
 }
 
 // Gaussian sketch of ncols columns with every entry of Theta generated once
@@ -929,18 +930,21 @@ bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmU
 template <typename T>
 bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map_signs,
                            int64_t n_signs, const BlockMap& map_part, int64_t n_part, const BlockMap& map_red,
-                           int64_t n_red) {
+                           int64_t n_red, bool acc64) {
+    const bool srht64 = sketch == SK_SRHT && acc64;
     if (sketch == SK_SRHT) {
         if (n_signs > 0) hipLaunchKernelGGL(kb_srht_signs, dim3(n_signs), dim3(256), 0, st, items, map_signs);
         RGS_LAUNCH_CHECK();
-        if (n_part > 0)
-            hipLaunchKernelGGL((kb_sketch_cols<T, SK_SRHT>), dim3(n_part), dim3(kWG), 0, st, items, map_part);
+        if (n_part > 0 && srht64)
+            hipLaunchKernelGGL((kb_sketch_cols<T, double, SK_SRHT>), dim3(n_part), dim3(kWG), 0, st, items, map_part);
+        else if (n_part > 0)
+            hipLaunchKernelGGL((kb_sketch_cols<T, T, SK_SRHT>), dim3(n_part), dim3(kWG), 0, st, items, map_part);
     } else if (n_part > 0) {
         hipLaunchKernelGGL(kb_gauss_cols<T>, dim3(n_part), dim3(kWG), 0, st, items, map_part);
     }
     RGS_LAUNCH_CHECK();
     if (n_red > 0) {
-        if (sketch == SK_SRHT)
+        if (srht64)
             hipLaunchKernelGGL(kb_reduce<double>, dim3(n_red), dim3(kWG), 0, st, items, map_red);
         else
             hipLaunchKernelGGL(kb_reduce<T>, dim3(n_red), dim3(kWG), 0, st, items, map_red);
@@ -1225,7 +1229,7 @@ template bool launch_batch_gauss_gemm<bf16, true>(hipStream_t, const BatchItem*,
 template bool launch_batch_gauss_gemm<float, false>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
                                                     int, int);
 template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
-                                          const BlockMap&, int64_t, const BlockMap&, int64_t);
+                                          const BlockMap&, int64_t, const BlockMap&, int64_t, bool);
 template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
                                          int64_t, const BlockMap&, int64_t, int);
 template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
