@@ -136,7 +136,7 @@ __device__ __forceinline__ float elem_real(bf16 v) { return bf16_to_float(v.bits
 template <typename TX, typename T, typename TA, int C, int SUB = kGSub>
 __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
                                                 const SketchArgs& sk, TA* __restrict__ partials, int g, int jc,
-                                                int cc, T (*w)[SUB]) {
+                                                int cc, TA (*w)[SUB]) {
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
     const int nc = min(C, ncols - c0);
@@ -150,7 +150,7 @@ __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_
             const int64_t l = r0 + t;
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                w[c][t] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+                w[c][t] = (c < nc && l < n) ? (TA)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : TA(0);
         }
         __syncthreads();
         if (j < sk.k) {
@@ -179,7 +179,7 @@ __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_
 template <typename TX, typename T, typename TA, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
                                                     int G, SketchArgs sk, TA* __restrict__ partials) {
-    __shared__ __attribute__((aligned(16))) T w[C][SUB];
+    __shared__ __attribute__((aligned(16))) TA w[C][SUB];
     gauss_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kWG) void k_gauss_cols(const TX* __restrict__ X, in
 template <typename TX, typename T, typename TA, int C, int SUB>
 __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
                                               const SketchArgs& sk, TA* __restrict__ partials, int g, int jc, int cc,
-                                              T (*w)[SUB]) {
+                                              TA (*w)[SUB]) {
     static_assert(SUB % 128 == 0, "whole 128-row sign groups per sub-block");
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t 
             const int64_t l = r0 + t;
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                w[c][t] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+                w[c][t] = (c < nc && l < n) ? (TA)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : TA(0);
         }
         __syncthreads();
         if (j < sk.k) {
@@ -221,7 +221,7 @@ __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t 
                         const TA sg = rad_sign<TA>(wd[c4], r);
                         const int t = 128 * q + 32 * c4 + r;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) acc[c] = fma(sg, (TA)w[c][t], acc[c]);
+                        for (int c = 0; c < C; ++c) acc[c] = fma(sg, w[c][t], acc[c]);
                     }
             }
         }
@@ -237,7 +237,7 @@ __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t 
 template <typename TX, typename T, typename TA, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_rad_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
                                                   int G, SketchArgs sk, TA* __restrict__ partials) {
-    __shared__ __attribute__((aligned(16))) T w[C][SUB];
+    __shared__ __attribute__((aligned(16))) TA w[C][SUB];
     rad_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
@@ -276,7 +276,7 @@ __global__ void k_theta_table(SketchArgs sk, int64_t n, int64_t ngroups, uint16_
 template <typename TX, typename T, typename TA, int C, int SUB>
 __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
                                                 const SketchArgs& sk, TA* __restrict__ partials, int g, int jc,
-                                                int cc, T (*w)[SUB]) {
+                                                int cc, TA (*w)[SUB]) {
     static_assert(SUB % 8 == 0, "whole 8-row table groups per sub-block");
     const int j = jc * kWG + threadIdx.x;
     const int c0 = cc * C;
@@ -291,7 +291,7 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
             const int64_t l = r0 + t;
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                w[c][t] = (c < nc && l < n) ? (T)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : T(0);
+                w[c][t] = (c < nc && l < n) ? (TA)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : TA(0);
         }
         __syncthreads();
         if (j < sk.k) {
@@ -303,9 +303,9 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
                 tab8<TA>(sk.table, sk.k, o0 + o, j, z);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const T* x = w[c] + 8 * o;
-                    acc[c] += z[0] * (TA)x[0] + z[1] * (TA)x[1] + z[2] * (TA)x[2] + z[3] * (TA)x[3];
-                    acc[c] += z[4] * (TA)x[4] + z[5] * (TA)x[5] + z[6] * (TA)x[6] + z[7] * (TA)x[7];
+                    const TA* x = w[c] + 8 * o;
+                    acc[c] += z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3];
+                    acc[c] += z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7];
                 }
             }
         }
@@ -321,7 +321,7 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
 template <typename TX, typename T, typename TA, int C, int SUB>
 __global__ __launch_bounds__(kWG) void k_table_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
                                                     int G, SketchArgs sk, TA* __restrict__ partials) {
-    __shared__ __attribute__((aligned(16))) T w[C][SUB];
+    __shared__ __attribute__((aligned(16))) TA w[C][SUB];
     table_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
@@ -889,24 +889,26 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
                        TA* partials) {
     const unsigned jc = nblocks(sk.k, kWG);
     const dim3 g1(G, jc, 1), gc(G, jc, nblocks(ncols, kGaussCols));
+    // columns staged in LDS in TA: 32 x kGSub fp32 or 32 x kGSub/2 fp64 (32 KB)
+    constexpr int SUBC = sizeof(TA) > sizeof(float) && sizeof(T) == sizeof(float) ? kGSub / 2 : kGSub;
     if (sk.sketch == SK_TABLE) {
         if (ncols == 1)
             hipLaunchKernelGGL((k_table_cols<TX, T, TA, 1, kGSubCol>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
                                partials);
         else
-            hipLaunchKernelGGL((k_table_cols<TX, T, TA, kGaussCols, kGSub>), gc, dim3(kWG), 0, st, X, ldx, n, ncols,
+            hipLaunchKernelGGL((k_table_cols<TX, T, TA, kGaussCols, SUBC>), gc, dim3(kWG), 0, st, X, ldx, n, ncols,
                                G, sk, partials);
     } else if (sk.sketch == SK_RADEM) {
         if (ncols == 1)
             hipLaunchKernelGGL((k_rad_cols<TX, T, TA, 1, 128>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk, partials);
         else
-            hipLaunchKernelGGL((k_rad_cols<TX, T, TA, kGaussCols, kGSub>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
+            hipLaunchKernelGGL((k_rad_cols<TX, T, TA, kGaussCols, SUBC>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
                                sk, partials);
     } else if (ncols == 1) {   // the single-column sketch of a small-n step: 64-row sub-blocks
         hipLaunchKernelGGL((k_gauss_cols<TX, T, TA, 1, kGSubCol>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
                            partials);
     } else {
-        hipLaunchKernelGGL((k_gauss_cols<TX, T, TA, kGaussCols, kGSub>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
+        hipLaunchKernelGGL((k_gauss_cols<TX, T, TA, kGaussCols, SUBC>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
                            sk, partials);
     }
     RGS_LAUNCH_CHECK();
