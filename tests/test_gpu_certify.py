@@ -7,9 +7,10 @@ cond(Phi Q).  The oracle recomputes them from its own Theta and Phi applied
 in fp64 to the same V (the device's returned Q, the input W).
 
 Tolerance: Prop. 3.9 bounds the change of the certificate under rounding of
-the two sketches by u cond(Phi V); the device sketches fp32 data in fp32
-partial sums (fp64 data in fp64), so the tests allow 64 u cond(Phi V) on the
-singular values, u the unit roundoff of the sketch arithmetic.
+the two sketches by u cond(Phi V); the device accumulates the sketches in fp64
+but its fp32 paths use Theta's fp32 entries (the Gaussian ones differ from the
+oracle's fp64 entries by a few fp32 ulps), so the tests allow 64 u cond(Phi V)
+on the singular values, u the unit roundoff of the working precision.
 """
 
 import math
