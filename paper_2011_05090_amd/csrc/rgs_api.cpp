@@ -27,6 +27,8 @@ struct rgs_handle {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;   // created on first use: graph capture needs a non-null stream
+    hipStream_t aux = nullptr;       // created on first use: the second share of a batched QR call
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     char* arena = nullptr;
     size_t arena_bytes = 0;
     std::vector<hipEvent_t> events;
@@ -56,6 +58,7 @@ rgs_status ensure_arena(rgs_handle* h, size_t bytes) {
     if (h->arena_bytes >= bytes) return RGS_OK;
     if (h->arena) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) return RGS_EDEVICE;
+        if (h->aux && hipStreamSynchronize(h->aux) != hipSuccess) return RGS_EDEVICE;
         (void)hipFree(h->arena);
         h->arena = nullptr;
         h->arena_bytes = 0;
@@ -800,6 +803,9 @@ struct GemmSchedule {
 };
 constexpr GemmSchedule kGemmSchedules[4] = {{64, 0}, {64, 1}, {32, 0}, {32, 1}};
 
+// Streams a batched QR call spreads its factorisations over.
+constexpr int kQrShares = 2;
+
 void order_units(const std::vector<GemmUnit>& in, size_t a, size_t b, int xcd, std::vector<GemmUnit>& out) {
     if (!xcd) {
         out.insert(out.end(), in.begin() + a, in.begin() + b);
@@ -821,58 +827,80 @@ void order_units(const std::vector<GemmUnit>& in, size_t a, size_t b, int xcd, s
             }
 }
 
-template <typename TQ, bool DEFER>
-rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
-                          uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
-    const auto t0 = std::chrono::steady_clock::now();
-    typedef float T;
-    hipStream_t s = h->stream;
-    // Launch order: by m descending, so the factorisations that still have a
-    // column i are a prefix of the order and every launch map is implicit.
-    std::vector<int64_t> order((size_t)batch);
-    for (int64_t b = 0; b < batch; ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return items[a].m > items[b].m; });
-    const int64_t max_m = items[order[0]].m;
-    std::vector<int> active((size_t)max_m + 1, 0);   // active[i]: factorisations with a column i
-    for (int64_t i = 0; i <= max_m; ++i)
-        active[i] = (int)(std::upper_bound(order.begin(), order.end(), i,
-                                           [&](int64_t v, int64_t b) { return v >= items[b].m; }) -
-                          order.begin());
-    auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[order[q]]; };
-    // step-1 row groups: 4096-row blocks (SRHT, at most 16 groups), 16384-row chunks of the
-    // Gaussian product
-    auto gp_of = [&](int64_t q) -> int64_t {
-        const int64_t n = it_of(q).n;
-        return sk_kind == SK_GAUSS ? (n + kGemmRowsP - 1) / kGemmRowsP
-                                   : std::min<int64_t>((n + kBlock - 1) / kBlock, 16);
-    };
-    auto npart_of = [&](int64_t q) -> int64_t {   // step-4 partials per column
-        const int64_t n = it_of(q).n;
-        return sk_kind == SK_GAUSS ? (n + kGemmRows - 1) / kGemmRows : (n + kProjRows - 1) / kProjRows;
-    };
-    const std::vector<int64_t> pre_proj = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + kProjRows - 1) / kProjRows; });
-    const std::vector<int64_t> pre_sl = prefix_of(batch, [&](int64_t q) { return (it_of(q).k + kSlice - 1) / kSlice; });
-    const std::vector<int64_t> pre_row = prefix_of(batch, [&](int64_t q) { return (it_of(q).n + 1023) / 1024; });
-    const std::vector<int64_t> pre_sign = prefix_of(batch, [&](int64_t q) { return ((it_of(q).n + 31) / 32 + 1023) / 1024; });
-    const std::vector<int64_t> pre_part =
-        prefix_of(batch, [&](int64_t q) { return sk_kind == SK_GAUSS ? 0 : gp_of(q) * it_of(q).m; });
-    const std::vector<int64_t> pre_red = prefix_of(batch, [&](int64_t q) { return ((it_of(q).k + 31) / 32) * it_of(q).m; });
+// Workspace offsets of one factorisation of a batched QR call.
+struct QrItemOff {
+    size_t signs, part, partP, P, Vc, Vr, Wc, Wr, X, sp, u, v, pbuf, uh, pd, pdb, pd2, rr, invr, pnorm, tau, beta,
+        coef;
+};
 
-    struct Off {
-        size_t signs, part, partP, P, Vc, Vr, Wc, Wr, X, sp, u, v, pbuf, uh, pd, pdb, pd2, rr, invr, pnorm, tau, beta,
-            coef;
-    };
-    std::vector<Off> off((size_t)batch);
-    Carver c;
+// One stream's share of a batched QR call.  The call's factorisations are
+// ordered by m (descending) and dealt out round-robin, so each share is in
+// that order too: the factorisations of a share that still have a column i
+// are a prefix of it, and every launch map is implicit.  The shares run the
+// same per-column launch sequence on their own streams, so the latency-bound
+// sketch-space kernels of one share overlap the HBM-bound projection of the
+// other; each factorisation's arithmetic does not depend on the split.
+struct QrGroup {
+    std::vector<int64_t> order;   // indices into the caller's items
+    int64_t max_m = 0;
+    std::vector<int> active;      // active[i]: factorisations with a column i
+    std::vector<int64_t> pre_proj, pre_sl, pre_row, pre_sign, pre_part, pre_red;
+    std::vector<QrItemOff> off;
+    size_t o_rows = 0, o_status = 0, o_items = 0, o_pre = 0, o_gcols = 0, o_gunits_p = 0, o_gunits = 0,
+           o_gtune = 0;
+    // Gaussian: the step-1 product over (item, column) tiles, and per column the
+    // active items ordered by n (descending) in tiles of 64 or 32; each tile is
+    // split into work units of one row chunk and 128 sketch rows
+    std::vector<int2> g_cols;
+    std::vector<GemmUnit> g_units_p;   // step 1
+    std::vector<GemmUnit> g_units[2];  // step 4, tile widths 64 and 32, all columns
+    std::vector<size_t> g_at[2];       // per column offsets into g_units[w]
+    std::vector<BatchItem> bi;
+    std::vector<int> rows_all;
+    std::vector<int64_t> pre_all;
+    std::vector<GemmUnit> sched_units;  // staged for an asynchronous copy: alive until the final synchronisation
+    std::vector<int> stat;              // 4 status words per factorisation, read back at the end
+};
+
+// step-1 row groups: 4096-row blocks (SRHT, at most 16 groups), 16384-row
+// chunks of the Gaussian product
+int64_t qr_group_gp(int64_t n, int sk_kind) {
+    return sk_kind == SK_GAUSS ? (n + kGemmRowsP - 1) / kGemmRowsP : std::min<int64_t>((n + kBlock - 1) / kBlock, 16);
+}
+
+// step-4 block partials per column
+int64_t qr_group_npart(int64_t n, int sk_kind) {
+    return sk_kind == SK_GAUSS ? (n + kGemmRows - 1) / kGemmRows : (n + kProjRows - 1) / kProjRows;
+}
+
+// Launch tables and workspace layout of one share (g.order already set).
+void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c) {
+    typedef float T;
+    const int64_t cnt = (int64_t)g.order.size();
+    auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[g.order[q]]; };
+    g.max_m = it_of(0).m;
+    g.active.assign((size_t)g.max_m + 1, 0);
+    for (int64_t i = 0; i <= g.max_m; ++i)
+        g.active[i] = (int)(std::upper_bound(g.order.begin(), g.order.end(), i,
+                                             [&](int64_t v, int64_t b) { return v >= items[b].m; }) -
+                            g.order.begin());
+    g.pre_proj = prefix_of(cnt, [&](int64_t q) { return (it_of(q).n + kProjRows - 1) / kProjRows; });
+    g.pre_sl = prefix_of(cnt, [&](int64_t q) { return (it_of(q).k + kSlice - 1) / kSlice; });
+    g.pre_row = prefix_of(cnt, [&](int64_t q) { return (it_of(q).n + 1023) / 1024; });
+    g.pre_sign = prefix_of(cnt, [&](int64_t q) { return ((it_of(q).n + 31) / 32 + 1023) / 1024; });
+    g.pre_part = prefix_of(
+        cnt, [&](int64_t q) { return sk_kind == SK_GAUSS ? 0 : qr_group_gp(it_of(q).n, sk_kind) * it_of(q).m; });
+    g.pre_red = prefix_of(cnt, [&](int64_t q) { return ((it_of(q).k + 31) / 32) * it_of(q).m; });
+    g.off.resize((size_t)cnt);
     int64_t ktot = 0;
-    for (int64_t q = 0; q < batch; ++q) {
+    for (int64_t q = 0; q < cnt; ++q) {
         const rgs_qr_item& it = it_of(q);
         const int64_t n = it.n, m = it.m, k = it.k;
         const int64_t nproj = (n + kProjRows - 1) / kProjRows, nsl = (k + kSlice - 1) / kSlice;
-        Off& o = off[q];
+        QrItemOff& o = g.off[q];
         o.signs = c.take<uint32_t>(sk_kind == SK_SRHT ? (n + 31) / 32 + 4 : 1);
-        o.part = c.take<T>(std::max<int64_t>(nproj, npart_of(q)) * k);
-        o.partP = c.take<double>(gp_of(q) * k * m);   // fp64 for SRHT, T for the Gaussian sketch
+        o.part = c.take<T>(std::max<int64_t>(nproj, qr_group_npart(n, sk_kind)) * k);
+        o.partP = c.take<double>(qr_group_gp(n, sk_kind) * k * m);   // fp64 for SRHT, T for the Gaussian sketch
         o.P = c.take<double>(k * m);
         o.Vc = c.take<double>(k * m);
         o.Vr = c.take<double>(k * m);
@@ -895,83 +923,73 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         o.coef = c.take<T>(m);
         ktot += k;
     }
-    const size_t o_rows = c.take<int>(sk_kind == SK_SRHT ? ktot : 1), o_status = c.take<int>(4 * batch);
-    const size_t o_items = c.take<BatchItem>(batch);
-    const size_t o_pre = c.take<int64_t>(6 * (batch + 1));
-    // Gaussian: the step-1 product over (item, column) tiles, and per column the
-    // active items ordered by n (descending) in tiles of 64; each tile is split
-    // into work units of one row chunk and 128 sketch rows
-    const bool gemm = sk_kind == SK_GAUSS;
-    std::vector<int2> g_cols;
-    std::vector<GemmUnit> g_units_p;                    // step 1
-    std::vector<GemmUnit> g_units[2];                   // step 4, tile widths 64 and 32, all columns
-    std::vector<size_t> g_at[2];                        // per column offsets into g_units[w]
-    auto add_tile = [&](std::vector<GemmUnit>& out, int first, int cnt, int64_t rows) {
-        int64_t nmax = 0, kmax = 0;
-        for (int c2 = 0; c2 < cnt; ++c2) {
-            const rgs_qr_item& it = it_of(g_cols[first + c2].x);
-            nmax = std::max<int64_t>(nmax, it.n);
-            kmax = std::max<int64_t>(kmax, it.k);
-        }
-        for (int64_t blk = 0; blk < (nmax + rows - 1) / rows; ++blk)
-            for (int64_t jt = 0; jt < (kmax + 127) / 128; ++jt) out.push_back(GemmUnit{first, cnt, (int)blk, (int)jt});
-    };
-    if (gemm) {
-        for (int64_t q = 0; q < batch; ++q)   // step 1: 64-column tiles of each item's W
+    g.o_rows = c.take<int>(sk_kind == SK_SRHT ? ktot : 1);
+    g.o_status = c.take<int>(4 * cnt);
+    g.o_items = c.take<BatchItem>(cnt);
+    g.o_pre = c.take<int64_t>(6 * (cnt + 1));
+    if (sk_kind == SK_GAUSS) {
+        auto add_tile = [&](std::vector<GemmUnit>& out, int first, int tcnt, int64_t rows) {
+            int64_t nmax = 0, kmax = 0;
+            for (int c2 = 0; c2 < tcnt; ++c2) {
+                const rgs_qr_item& it = it_of(g.g_cols[first + c2].x);
+                nmax = std::max<int64_t>(nmax, it.n);
+                kmax = std::max<int64_t>(kmax, it.k);
+            }
+            for (int64_t blk = 0; blk < (nmax + rows - 1) / rows; ++blk)
+                for (int64_t jt = 0; jt < (kmax + 127) / 128; ++jt)
+                    out.push_back(GemmUnit{first, tcnt, (int)blk, (int)jt});
+        };
+        for (int64_t q = 0; q < cnt; ++q)   // step 1: 64-column tiles of each item's W
             for (int64_t c0 = 0; c0 < it_of(q).m; c0 += 64) {
-                const int first = (int)g_cols.size(), cnt = (int)std::min<int64_t>(64, it_of(q).m - c0);
-                for (int c2 = 0; c2 < cnt; ++c2) g_cols.push_back(make_int2((int)q, (int)(c0 + c2)));
-                add_tile(g_units_p, first, cnt, kGemmRowsP);
+                const int first = (int)g.g_cols.size(), tcnt = (int)std::min<int64_t>(64, it_of(q).m - c0);
+                for (int c2 = 0; c2 < tcnt; ++c2) g.g_cols.push_back(make_int2((int)q, (int)(c0 + c2)));
+                add_tile(g.g_units_p, first, tcnt, kGemmRowsP);
             }
         std::vector<int> act;
-        for (int w = 0; w < 2; ++w) g_at[w].assign((size_t)max_m + 1, 0);
-        for (int64_t i = 0; i < max_m; ++i) {   // step 4 of column i: active items ordered by n
-            act.resize((size_t)active[i]);
-            for (int q = 0; q < active[i]; ++q) act[q] = q;
-            std::stable_sort(act.begin(), act.end(), [&](int a, int b) { return it_of(a).n > it_of(b).n; });
-            const int base = (int)g_cols.size();
-            for (int q = 0; q < active[i]; ++q) g_cols.push_back(make_int2(act[q], (int)i));
+        for (int w = 0; w < 2; ++w) g.g_at[w].assign((size_t)g.max_m + 1, 0);
+        for (int64_t i = 0; i < g.max_m; ++i) {   // step 4 of column i: active items ordered by n
+            const int a = g.active[i];
+            act.resize((size_t)a);
+            for (int q = 0; q < a; ++q) act[q] = q;
+            std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return it_of(x).n > it_of(y).n; });
+            const int base = (int)g.g_cols.size();
+            for (int q = 0; q < a; ++q) g.g_cols.push_back(make_int2(act[q], (int)i));
             for (int w = 0; w < 2; ++w) {
                 const int tile = kGemmSchedules[2 * w].tile;
-                for (int t0 = 0; t0 < active[i]; t0 += tile)
-                    add_tile(g_units[w], base + t0, std::min(tile, active[i] - t0), kGemmRows);
-                g_at[w][i + 1] = g_units[w].size();
+                for (int t0 = 0; t0 < a; t0 += tile) add_tile(g.g_units[w], base + t0, std::min(tile, a - t0), kGemmRows);
+                g.g_at[w][i + 1] = g.g_units[w].size();
             }
         }
     }
-    const size_t n_units_max = std::max(g_units[0].size(), g_units[1].size());
-    const size_t o_gcols = c.take<int2>(std::max<size_t>(g_cols.size(), 1));
-    const size_t o_gunits_p = c.take<GemmUnit>(std::max<size_t>(g_units_p.size(), 1));
-    const size_t o_gunits = c.take<GemmUnit>(std::max<size_t>(n_units_max, 1));
-    const size_t o_gtune = c.take<GemmUnit>(gemm ? 4 * std::max<size_t>(1, std::max(g_at[0].size() > 2 ? g_at[0][2] : 0,
-                                                                                      g_at[1].size() > 2 ? g_at[1][2] : 0))
-                                                 : 1);
-    // the batch signature of the tuning cache: precision and every (n, m, k)
-    uint64_t sig = 1469598103934665603ull;
-    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
-    mix((uint64_t)DEFER);
-    for (int64_t q = 0; q < batch; ++q) {
-        mix((uint64_t)it_of(q).n);
-        mix((uint64_t)it_of(q).m);
-        mix((uint64_t)it_of(q).k);
-    }
-    rgs_status st = ensure_arena(h, c.off + kAlign);
-    if (st != RGS_OK) return st;
-    char* A = h->arena;
-    std::vector<BatchItem> bi((size_t)batch);
-    std::vector<int64_t> rpos((size_t)batch + 1, 0);
-    for (int64_t q = 0; q < batch; ++q) rpos[q + 1] = rpos[q] + it_of(q).k;
-    std::vector<int> rows_all(sk_kind == SK_SRHT ? (size_t)ktot : 0);
-    parallel_for(batch, [&](int64_t q) {
-        const rgs_qr_item& it = it_of(q);
-        const Off& o = off[q];
-        BatchItem& x = bi[q];
-        x = BatchItem{};
+    const size_t n_units_max = std::max(g.g_units[0].size(), g.g_units[1].size());
+    g.o_gcols = c.take<int2>(std::max<size_t>(g.g_cols.size(), 1));
+    g.o_gunits_p = c.take<GemmUnit>(std::max<size_t>(g.g_units_p.size(), 1));
+    g.o_gunits = c.take<GemmUnit>(std::max<size_t>(n_units_max, 1));
+    size_t tune_units = 1;
+    if (sk_kind == SK_GAUSS)
+        tune_units = 4 * std::max<size_t>(1, std::max(g.g_at[0].size() > 2 ? g.g_at[0][2] : 0,
+                                                      g.g_at[1].size() > 2 ? g.g_at[1][2] : 0));
+    g.o_gtune = c.take<GemmUnit>(tune_units);
+}
+
+// Device-side descriptors of one share's factorisations (arena at A).
+template <bool DEFER>
+void bind_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, uint64_t seed, uint32_t sid, char* A) {
+    const int64_t cnt = (int64_t)g.order.size();
+    const bool gemm = sk_kind == SK_GAUSS;
+    g.bi.assign((size_t)cnt, BatchItem{});
+    std::vector<int64_t> rpos((size_t)cnt + 1, 0);
+    for (int64_t q = 0; q < cnt; ++q) rpos[q + 1] = rpos[q] + items[g.order[q]].k;
+    g.rows_all.assign(sk_kind == SK_SRHT ? (size_t)rpos[cnt] : 0, 0);
+    parallel_for(cnt, [&](int64_t q) {
+        const rgs_qr_item& it = items[g.order[q]];
+        const QrItemOff& o = g.off[q];
+        BatchItem& x = g.bi[q];
         x.n = it.n;
         x.m = (int)it.m;
         x.k = (int)it.k;
         x.nproj = (int)((it.n + kProjRows - 1) / kProjRows);
-        x.npart = (int)npart_of(q);
+        x.npart = (int)qr_group_npart(it.n, sk_kind);
         x.nsl = (int)((it.k + kSlice - 1) / kSlice);
         x.W = it.W;
         x.ldw = it.ldw;
@@ -983,7 +1001,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         x.lds = it.lds;
         x.P = reinterpret_cast<double*>(A + o.P);
         x.partP = A + o.partP;
-        x.G_P = (int)gp_of(q);
+        x.G_P = (int)qr_group_gp(it.n, sk_kind);
         x.part = A + o.part;
         x.coef = A + o.coef;
         x.sketch_scale = 1.0 / std::sqrt((double)it.k);
@@ -1012,84 +1030,117 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         a.pnorm = reinterpret_cast<double*>(A + o.pnorm);
         a.tau = reinterpret_cast<double*>(A + o.tau);
         a.beta = reinterpret_cast<double*>(A + o.beta);
-        a.status = reinterpret_cast<int*>(A + o_status) + 4 * q;
-        // Theta of factorisation b: SRHT per factorisation (instance b); Gaussian: the
-        // leading k_b x n_b block of one master matrix (instance 0)
-        x.sk = make_sketch(sk_kind, it.k, seed, sid, sk_kind == SK_SRHT ? (uint32_t)order[q] : 0u);
+        a.status = reinterpret_cast<int*>(A + g.o_status) + 4 * q;
+        // Theta of factorisation b: SRHT per factorisation (instance b, the
+        // caller's index); Gaussian: the leading k_b x n_b block of one master
+        // matrix (instance 0)
+        x.sk = make_sketch(sk_kind, it.k, seed, sid, sk_kind == SK_SRHT ? (uint32_t)g.order[q] : 0u);
         if (sk_kind == SK_SRHT) {
             std::vector<int> rows;
             srht_rows_host(srht_order(it.n), (int)it.k, x.sk, rows);
-            std::copy(rows.begin(), rows.end(), rows_all.begin() + rpos[q]);
+            std::copy(rows.begin(), rows.end(), g.rows_all.begin() + rpos[q]);
             x.sk.signs = reinterpret_cast<uint32_t*>(A + o.signs);
-            x.sk.rows = reinterpret_cast<int*>(A + o_rows) + rpos[q];
+            x.sk.rows = reinterpret_cast<int*>(A + g.o_rows) + rpos[q];
         }
     });
-    int64_t* pre_dev = reinterpret_cast<int64_t*>(A + o_pre);
-    std::vector<int64_t> pre_all;
-    pre_all.reserve(6 * (batch + 1));
-    for (const auto* v : {&pre_proj, &pre_sl, &pre_row, &pre_sign, &pre_part, &pre_red}) pre_all.insert(pre_all.end(), v->begin(), v->end());
-    if ((sk_kind == SK_SRHT && hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int),
-                                              hipMemcpyHostToDevice, s) != hipSuccess) ||
-        hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(pre_dev, pre_all.data(), pre_all.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        (gemm && (hipMemcpyAsync(A + o_gcols, g_cols.data(), g_cols.size() * sizeof(int2), hipMemcpyHostToDevice,
-                                 s) != hipSuccess ||
-                  hipMemcpyAsync(A + o_gunits_p, g_units_p.data(), g_units_p.size() * sizeof(GemmUnit),
-                                 hipMemcpyHostToDevice, s) != hipSuccess)))
-        return RGS_EDEVICE;
-    const BatchItem* itd = reinterpret_cast<const BatchItem*>(A + o_items);
-    const int64_t* d_proj = pre_dev;
-    const int64_t* d_sl = pre_dev + (batch + 1);
-    const int64_t* d_row = pre_dev + 2 * (batch + 1);
-    const int64_t* d_sign = pre_dev + 3 * (batch + 1);
-    const int64_t* d_part = pre_dev + 4 * (batch + 1);
-    const int64_t* d_red = pre_dev + 5 * (batch + 1);
-    const int nb = (int)batch;
-    if (!launch_batch_init(s, itd, nb, max_m * max_m)) return RGS_EDEVICE;
-    GemmUnit* d_units = reinterpret_cast<GemmUnit*>(A + o_gunits);
-    GemmUnit* d_tune = reinterpret_cast<GemmUnit*>(A + o_gtune);
-    const int2* d_cols = reinterpret_cast<const int2*>(A + o_gcols);
-    // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
-    if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, reinterpret_cast<const GemmUnit*>(A + o_gunits_p),
-                                                   (int)g_units_p.size(), d_cols, (int)kGemmRowsP, 64))
-        return RGS_EDEVICE;
-    // step-4 schedule: cached for this batch signature, forced, or tuned at the first
-    // column that needs the product (the schedules give the same bits, so the
-    // timing launches leave nothing behind)
-    int sched = 0;
-    std::vector<GemmUnit> sched_units;   // stays alive until the final synchronisation
-    if (gemm) {
-        if (h->tune_mode > 0) sched = h->tune_mode;
-        else if (h->gemm_tuned.count(sig)) sched = h->gemm_tuned[sig];
-    }
-    auto upload_schedule = [&](int sc) -> bool {
+    g.pre_all.clear();
+    g.pre_all.reserve(6 * (cnt + 1));
+    for (const auto* v : {&g.pre_proj, &g.pre_sl, &g.pre_row, &g.pre_sign, &g.pre_part, &g.pre_red})
+        g.pre_all.insert(g.pre_all.end(), v->begin(), v->end());
+}
+
+// Enqueues one share's factorisations on its stream: begin() uploads the
+// tables and runs step 1, step(i) the launches of column i, end() the final
+// scaling.  The caller interleaves the shares column by column, so both
+// streams are fed from the start; nothing here waits for the device (a copy
+// into pageable host memory would), except the schedule timing of the
+// Gaussian product.
+template <typename TQ, bool DEFER>
+struct QrGroupLauncher {
+    typedef float T;
+    rgs_handle* h;
+    QrGroup& g;
+    int sk_kind;
+    char* A;
+    hipStream_t s;
+    bool gemm = false;
+    int nb = 0;
+    int uploaded = 0;   // schedule whose unit order sits in d_units
+    const BatchItem* itd = nullptr;
+    const int64_t *d_proj = nullptr, *d_sl = nullptr, *d_row = nullptr, *d_sign = nullptr, *d_part = nullptr,
+                  *d_red = nullptr;
+    GemmUnit *d_units = nullptr, *d_tune = nullptr;
+    const int2* d_cols = nullptr;
+
+    QrGroupLauncher(rgs_handle* h_, QrGroup& g_, int sk, char* A_, hipStream_t s_)
+        : h(h_), g(g_), sk_kind(sk), A(A_), s(s_) {}
+
+    bool upload_schedule(int sc) {
         const int w = kGemmSchedules[sc - 1].tile == 64 ? 0 : 1;
-        sched_units.clear();
-        for (int64_t i = 0; i < max_m; ++i)
-            order_units(g_units[w], g_at[w][i], g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, sched_units);
-        return hipMemcpyAsync(d_units, sched_units.data(), sched_units.size() * sizeof(GemmUnit),
+        g.sched_units.clear();
+        for (int64_t i = 0; i < g.max_m; ++i)
+            order_units(g.g_units[w], g.g_at[w][i], g.g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, g.sched_units);
+        uploaded = sc;
+        return hipMemcpyAsync(d_units, g.sched_units.data(), g.sched_units.size() * sizeof(GemmUnit),
                               hipMemcpyHostToDevice, s) == hipSuccess;
-    };
-    if (gemm && sched > 0 && !upload_schedule(sched)) return RGS_EDEVICE;
-    const int64_t i_tune = DEFER ? 0 : 1;
-    if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, pre_sign[batch],
-                                  BlockMap{d_part, nullptr, nb, 0}, pre_part[batch], BlockMap{d_red, nullptr, nb, 0},
-                                  pre_red[batch], !DEFER))
-        return RGS_EDEVICE;
-    for (int64_t i = 0; i < max_m; ++i) {
-        const int a = active[i], a1 = active[i + 1];
+    }
+
+    rgs_status begin(int sched) {
+        gemm = sk_kind == SK_GAUSS;
+        nb = (int)g.order.size();
+        if ((sk_kind == SK_SRHT && hipMemcpyAsync(A + g.o_rows, g.rows_all.data(), g.rows_all.size() * sizeof(int),
+                                                  hipMemcpyHostToDevice, s) != hipSuccess) ||
+            hipMemcpyAsync(A + g.o_items, g.bi.data(), g.bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(A + g.o_pre, g.pre_all.data(), g.pre_all.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            (gemm && (hipMemcpyAsync(A + g.o_gcols, g.g_cols.data(), g.g_cols.size() * sizeof(int2),
+                                     hipMemcpyHostToDevice, s) != hipSuccess ||
+                      hipMemcpyAsync(A + g.o_gunits_p, g.g_units_p.data(), g.g_units_p.size() * sizeof(GemmUnit),
+                                     hipMemcpyHostToDevice, s) != hipSuccess)))
+            return RGS_EDEVICE;
+        itd = reinterpret_cast<const BatchItem*>(A + g.o_items);
+        const int64_t* pre_dev = reinterpret_cast<const int64_t*>(A + g.o_pre);
+        d_proj = pre_dev;
+        d_sl = pre_dev + (nb + 1);
+        d_row = pre_dev + 2 * (nb + 1);
+        d_sign = pre_dev + 3 * (nb + 1);
+        d_part = pre_dev + 4 * (nb + 1);
+        d_red = pre_dev + 5 * (nb + 1);
+        d_units = reinterpret_cast<GemmUnit*>(A + g.o_gunits);
+        d_tune = reinterpret_cast<GemmUnit*>(A + g.o_gtune);
+        d_cols = reinterpret_cast<const int2*>(A + g.o_gcols);
+        // the copies come before the first launch: a copy from pageable host
+        // memory can hold the host until the stream has drained
+        if (gemm && sched > 0 && !upload_schedule(sched)) return RGS_EDEVICE;
+        if (!launch_batch_init(s, itd, nb, g.max_m * g.max_m)) return RGS_EDEVICE;
+        // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
+        if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, reinterpret_cast<const GemmUnit*>(A + g.o_gunits_p),
+                                                       (int)g.g_units_p.size(), d_cols, (int)kGemmRowsP, 64))
+            return RGS_EDEVICE;
+        if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, g.pre_sign[nb],
+                                      BlockMap{d_part, nullptr, nb, 0}, g.pre_part[nb],
+                                      BlockMap{d_red, nullptr, nb, 0}, g.pre_red[nb], !DEFER))
+            return RGS_EDEVICE;
+        return RGS_OK;
+    }
+
+    // Column i (i < g.max_m).  sched: the Gaussian step-4 schedule; 0 = time
+    // the four on this column's product (the first column that needs it),
+    // keep the fastest and record it under sig.
+    rgs_status step(int64_t i, int& sched, uint64_t sig) {
+        const int a = g.active[i], a1 = g.active[i + 1];
         const int rb = (int)((i + 1 + 63) / 64);
-        if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, BlockMap{d_proj, nullptr, a, 0}, pre_proj[a], (int)i))
+        const int64_t i_tune = DEFER ? 0 : 1;
+        if (!launch_batch_project<T, TQ, DEFER>(s, sk_kind, itd, BlockMap{d_proj, nullptr, a, 0}, g.pre_proj[a],
+                                                (int)i))
             return RGS_EDEVICE;
         if (gemm && sched == 0 && i == i_tune) {
-            // time the four schedules on this column's product, keep the fastest
             std::vector<GemmUnit> tu[4];
             size_t off_t[5] = {0, 0, 0, 0, 0};
             for (int sc = 1; sc <= 4; ++sc) {
                 const int w = kGemmSchedules[sc - 1].tile == 64 ? 0 : 1;
-                order_units(g_units[w], g_at[w][i], g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, tu[sc - 1]);
+                order_units(g.g_units[w], g.g_at[w][i], g.g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, tu[sc - 1]);
                 off_t[sc] = off_t[sc - 1] + tu[sc - 1].size();
                 if (hipMemcpyAsync(d_tune + off_t[sc - 1], tu[sc - 1].data(), tu[sc - 1].size() * sizeof(GemmUnit),
                                    hipMemcpyHostToDevice, s) != hipSuccess)
@@ -1104,7 +1155,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
                         return RGS_EDEVICE;
                     (void)hipEventRecord(h->events[2 * sc - 1], s);
                 }
-            if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
+            if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // tu stays alive till here
             float best = 0.f;
             for (int sc = 1; sc <= 4; ++sc) {
                 float ms = 0.f;
@@ -1115,31 +1166,119 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
                 }
             }
             h->gemm_tuned[sig] = sched;
-            if (!upload_schedule(sched)) return RGS_EDEVICE;
         }
         if (gemm && (DEFER || i > 0)) {
+            if (uploaded != sched && !upload_schedule(sched)) return RGS_EDEVICE;
             const int w = kGemmSchedules[sched - 1].tile == 64 ? 0 : 1;
-            if (!launch_batch_gauss_gemm<TQ, true>(s, itd, d_units + g_at[w][i], (int)(g_at[w][i + 1] - g_at[w][i]),
-                                                   d_cols, (int)kGemmRows, kGemmSchedules[sched - 1].tile))
+            if (!launch_batch_gauss_gemm<TQ, true>(s, itd, d_units + g.g_at[w][i],
+                                                   (int)(g.g_at[w][i + 1] - g.g_at[w][i]), d_cols, (int)kGemmRows,
+                                                   kGemmSchedules[sched - 1].tile))
                 return RGS_EDEVICE;
         }
-        if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, pre_sl[a], BlockMap{d_sl, nullptr, a, rb},
-                                    pre_sl[a] + (int64_t)rb * a, BlockMap{nullptr, nullptr, a1, rb},
-                                    (int64_t)rb * a1, (int)i))
+        if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, g.pre_sl[a],
+                                    BlockMap{d_sl, nullptr, a, rb}, g.pre_sl[a] + (int64_t)rb * a,
+                                    BlockMap{nullptr, nullptr, a1, rb}, (int64_t)rb * a1, (int)i))
+            return RGS_EDEVICE;
+        return RGS_OK;
+    }
+
+    rgs_status end() {
+        return launch_batch_scale<TQ, DEFER>(s, itd, BlockMap{d_row, nullptr, nb, 0}, g.pre_row[nb]) ? RGS_OK
+                                                                                                     : RGS_EDEVICE;
+    }
+};
+
+// Streams of a batched QR call: the handle's stream and, for a second share,
+// the handle's auxiliary stream, forked from and joined back into the
+// handle's stream with events (so the call stays ordered on that stream).
+rgs_status ensure_aux(rgs_handle* h) {
+    if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return RGS_EDEVICE;
+    for (hipEvent_t* e : {&h->fork_ev, &h->join_ev})
+        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return RGS_EDEVICE;
+    return RGS_OK;
+}
+
+template <typename TQ, bool DEFER>
+rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
+                          uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<int64_t> order((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return items[a].m > items[b].m; });
+    const int ng = batch >= 2 ? kQrShares : 1;
+    std::vector<QrGroup> grp((size_t)ng);
+    for (int64_t q = 0; q < batch; ++q) grp[q % ng].order.push_back(order[q]);
+    Carver c;
+    for (QrGroup& g : grp) plan_qr_group(g, items, sk_kind, c);
+    // the batch signature of the tuning cache: precision, shares and every (n, m, k)
+    uint64_t sig = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+    mix((uint64_t)DEFER);
+    mix((uint64_t)ng);
+    for (int64_t q = 0; q < batch; ++q) {
+        mix((uint64_t)items[order[q]].n);
+        mix((uint64_t)items[order[q]].m);
+        mix((uint64_t)items[order[q]].k);
+    }
+    rgs_status st = ensure_arena(h, c.off + kAlign);
+    if (st != RGS_OK) return st;
+    char* A = h->arena;
+    for (QrGroup& g : grp) bind_qr_group<DEFER>(g, items, sk_kind, seed, sid, A);
+    const bool gemm = sk_kind == SK_GAUSS;
+    // step-4 schedule: forced, cached for this batch signature, or tuned by the
+    // first share at the first column that needs the product (the schedules
+    // give the same bits, so the timing launches leave nothing behind)
+    int sched = 0;
+    if (gemm) {
+        if (h->tune_mode > 0) sched = h->tune_mode;
+        else if (h->gemm_tuned.count(sig)) sched = h->gemm_tuned[sig];
+    }
+    static_assert(kQrShares == 2, "the shares past the first run on the one auxiliary stream");
+    hipStream_t ss[kQrShares] = {h->stream, h->stream};
+    if (ng > 1) {
+        if (ensure_aux(h) != RGS_OK) return RGS_EDEVICE;
+        ss[1] = h->aux;
+        if (hipEventRecord(h->fork_ev, h->stream) != hipSuccess || hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)
             return RGS_EDEVICE;
     }
-    if (!launch_batch_scale<TQ, DEFER>(s, itd, BlockMap{d_row, nullptr, nb, 0}, pre_row[batch])) return RGS_EDEVICE;
-    std::vector<int> stat((size_t)(4 * batch));
-    if (hipMemcpyAsync(stat.data(), A + o_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return RGS_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // host staging vectors stay alive till here
+    std::vector<QrGroupLauncher<TQ, DEFER>> run;
+    for (int gi = 0; gi < ng; ++gi) run.emplace_back(h, grp[gi], sk_kind, A, ss[gi]);
+    rgs_status est = run[0].begin(sched);
+    // an untuned Gaussian product: share 0 (it holds the largest m) runs alone
+    // up to the column whose product it times, so the timing sees no other work
+    int64_t done0 = 0;
+    if (gemm && sched == 0)
+        for (const int64_t i_tune = DEFER ? 0 : 1; done0 <= i_tune && done0 < grp[0].max_m && est == RGS_OK; ++done0)
+            est = run[0].step(done0, sched, sig);
+    for (int gi = 1; gi < ng && est == RGS_OK; ++gi) est = run[gi].begin(sched);
+    // then column by column over the shares
+    for (int64_t i = 0; i < grp[0].max_m && est == RGS_OK; ++i)
+        for (int gi = 0; gi < ng && est == RGS_OK; ++gi)
+            if (i < grp[gi].max_m && (gi > 0 || i >= done0)) est = run[gi].step(i, sched, sig);
+    for (int gi = 0; gi < ng && est == RGS_OK; ++gi) est = run[gi].end();
+    if (ng > 1) {   // join (also after a failed enqueue, so no work is left behind unordered)
+        if (hipEventRecord(h->join_ev, h->aux) != hipSuccess || hipStreamWaitEvent(h->stream, h->join_ev, 0) != hipSuccess)
+            est = RGS_EDEVICE;
+    }
+    for (QrGroup& g : grp) {   // the status words, once every share has finished
+        g.stat.assign(4 * g.order.size(), 0);
+        if (est == RGS_OK && hipMemcpyAsync(g.stat.data(), A + g.o_status, g.stat.size() * sizeof(int),
+                                            hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+            est = RGS_EDEVICE;
+    }
+    // host staging vectors stay alive till here
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return RGS_EDEVICE;
+    if (est != RGS_OK) return est;
     std::vector<rgs_status> sb((size_t)batch, RGS_OK);
     std::vector<int64_t> fc((size_t)batch, -1);
-    for (int64_t q = 0; q < batch; ++q) {
-        const int code = stat[4 * q];
-        sb[order[q]] = code == kStatusBreakdown ? RGS_EBREAKDOWN : code == kStatusNonfinite ? RGS_ENONFINITE : RGS_OK;
-        if (code) fc[order[q]] = stat[4 * q + 1];
-    }
+    for (const QrGroup& g : grp)
+        for (size_t q = 0; q < g.order.size(); ++q) {
+            const int code = g.stat[4 * q];
+            sb[g.order[q]] = code == kStatusBreakdown   ? RGS_EBREAKDOWN
+                             : code == kStatusNonfinite ? RGS_ENONFINITE
+                                                        : RGS_OK;
+            if (code) fc[g.order[q]] = g.stat[4 * q + 1];
+        }
     rgs_status result = RGS_OK;
     for (int64_t b = 0; b < batch; ++b) {
         if (item_status) item_status[b] = sb[b];
@@ -1151,14 +1290,14 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (rep) {
         report_defaults(rep);
         rep->failed_column = -1;
-        rep->iters = max_m;
+        rep->iters = items[order[0]].m;
         rep->cycles = 0;
         rep->delta_F = NAN;
         rep->delta_tilde_F = NAN;
         rep->true_relres = NAN;
         rep->seconds = std::chrono::duration<double>(t1 - t0).count();
         rep->proj_kernel_ms = 0.0;
-        rep->proj_launches = max_m;
+        rep->proj_launches = items[order[0]].m;
     }
     return result;
 }
@@ -1622,7 +1761,11 @@ rgs_status rgs_destroy(rgs_handle* h) {
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->aux) (void)hipStreamSynchronize(h->aux);
+    for (hipEvent_t e : {h->fork_ev, h->join_ev})
+        if (e) (void)hipEventDestroy(e);
     if (h->capture) (void)hipStreamDestroy(h->capture);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->arena) (void)hipFree(h->arena);
     delete h;
     return RGS_OK;

@@ -677,34 +677,34 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem
 // kernel): reduce to pbuf with the per-slice partials of Wm^T p, then the head
 // of U^T p, then y = R_S^{-1} uh -> R(0:i, i) and the projection coefficients.
 template <typename PT>
-__global__ __launch_bounds__(kGW) void kg_lsa(const BatchItem* __restrict__ items, BlockMap map,
+__global__ __launch_bounds__(kGWB) void kg_lsa(const BatchItem* __restrict__ items, BlockMap map,
                                               int i, int dual) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     // dual: p_i arrives as the sketch of A q'_{i-1} (part2), scaled by 1/r_{i-1,i-1} here
-    qa_body<PT>(static_cast<const PT*>(dual ? it.part2 : it.part), it.nproj, it.sketch_scale, nullptr, a.k, i, a.Wr,
-                a.mcap, a.pbuf, a.pd, bm.y, dual ? a.invr + (i - 1) : nullptr);
+    qa_body<PT, kGWB>(static_cast<const PT*>(dual ? it.part2 : it.part), it.nproj, it.sketch_scale, nullptr, a.k, i,
+                      a.Wr, a.mcap, a.pbuf, a.pd, bm.y, dual ? a.invr + (i - 1) : nullptr);
 }
 
-__global__ __launch_bounds__(kGW) void kg_ls2(const BatchItem* __restrict__ items, BlockMap map,
+__global__ __launch_bounds__(kGWB) void kg_ls2(const BatchItem* __restrict__ items, BlockMap map,
                                               int i) {
     extern __shared__ double cp[];  // [i + 1]
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    ls2_body(a.pbuf, a.k, i, it.nsl, a.Vc, a.mcap, a.pd, a.uh, a.pnorm, bm.y, cp);
+    ls2_body<kGWB>(a.pbuf, a.k, i, it.nsl, a.Vc, a.mcap, a.pd, a.uh, a.pnorm, bm.y, cp);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kGW) void kg_ls3(const BatchItem* __restrict__ items, BlockMap map,
+__global__ __launch_bounds__(kGWB) void kg_ls3(const BatchItem* __restrict__ items, BlockMap map,
                                               int i) {
     extern __shared__ double us[];  // [i]
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    ls3_body<T>(i, i, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<T*>(it.coef), it.defer ? a.invr : nullptr, bm.y,
-                us);
+    ls3_body<T, kGWB>(i, i, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<T*>(it.coef), it.defer ? a.invr : nullptr,
+                      bm.y, us);
 }
 
 __global__ void kg_givens_init(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
@@ -923,13 +923,13 @@ template <typename T>
 bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl, const BlockMap& map_rb,
                       int64_t nrb, int i, int dual) {
     if (nsl > 0) {
-        hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i, dual);
+        hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGWB), 0, st, items, map_sl, i, dual);
         RGS_LAUNCH_CHECK();
     }
     if (nrb > 0) {
-        hipLaunchKernelGGL(kg_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, items, map_rb, i);
+        hipLaunchKernelGGL(kg_ls2, dim3(nrb), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_rb, i);
         RGS_LAUNCH_CHECK();
-        hipLaunchKernelGGL(kg_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, items, map_rb, i);
+        hipLaunchKernelGGL(kg_ls3<T>, dim3(nrb), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_rb, i);
         RGS_LAUNCH_CHECK();
     }
     return true;

@@ -650,51 +650,51 @@ __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double*
 // factorisation has a column i+1, and nothing otherwise.
 // ---------------------------------------------------------------------------
 template <typename PT>
-__global__ __launch_bounds__(kGW) void kb_qa(const BatchItem* __restrict__ items, BlockMap map, int i) {
+__global__ __launch_bounds__(kGWB) void kb_qa(const BatchItem* __restrict__ items, BlockMap map, int i) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const bool from_p = (i == 0 && !it.defer && it.P != nullptr);   // GMRES systems carry no P
-    qa_body<PT>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, from_p ? it.P : nullptr, a.k, i, a.Wr,
-                a.mcap, a.sp, a.pd, bm.y);
+    qa_body<PT, kGWB>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, from_p ? it.P : nullptr, a.k, i,
+                      a.Wr, a.mcap, a.sp, a.pd, bm.y);
 }
 
-__global__ __launch_bounds__(kGW) void kb_qb(const BatchItem* __restrict__ items, BlockMap map, int i) {
+__global__ __launch_bounds__(kGWB) void kb_qb(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double c1[];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    qb_body(a.k, i, it.nsl, a.sp, a.Vc, a.mcap, a.pd, a.u, a.pd2, it.S, it.lds, it.R, it.ldr, a.rr, a.invr,
-            a.pnorm, a.status, bm.y, c1);
+    qb_body<kGWB>(a.k, i, it.nsl, a.sp, a.Vc, a.mcap, a.pd, a.u, a.pd2, it.S, it.lds, it.R, it.ldr, a.rr, a.invr,
+                  a.pnorm, a.status, bm.y, c1);
 }
 
-__global__ __launch_bounds__(kGW) void kb_qc(const BatchItem* __restrict__ items, BlockMap map, int i) {
+__global__ __launch_bounds__(kGWB) void kb_qc(const BatchItem* __restrict__ items, BlockMap map, int i) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
-    qc_body(a.k, i, it.nsl, a.u, a.pd2, pn, a.v, a.Vc, a.Vr, a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status,
-            bm.y);
+    qc_body<kGWB>(a.k, i, it.nsl, a.u, a.pd2, pn, a.v, a.Vc, a.Vr, a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta,
+                  a.status, bm.y);
 }
 
-__global__ __launch_bounds__(kGW) void kb_qd(const BatchItem* __restrict__ items, BlockMap map, int i) {
+__global__ __launch_bounds__(kGWB) void kb_qd(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double dyn[];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
-    qd_body(a.k, i, it.nsl, a.v, a.u, pn, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
-            a.beta, bm.y, dyn);
+    qd_body<kGWB>(a.k, i, it.nsl, a.v, a.u, pn, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
+                  a.beta, bm.y, dyn);
 }
 
 template <typename TW>
-__global__ __launch_bounds__(kGW) void kb_ls3(const BatchItem* __restrict__ items, BlockMap map, int i) {
+__global__ __launch_bounds__(kGWB) void kb_ls3(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double us[];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    ls3_body<TW>(i + 1, i + 1, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<TW*>(it.coef),
-                 it.defer ? a.invr : nullptr, bm.y, us);
+    ls3_body<TW, kGWB>(i + 1, i + 1, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<TW*>(it.coef),
+                       it.defer ? a.invr : nullptr, bm.y, us);
 }
 
 __global__ void k_zero_mat(double* __restrict__ A, int64_t rows, int64_t cols, int64_t lda) {
@@ -1099,19 +1099,19 @@ template <typename TW>
 bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
                          const BlockMap& map_qd, int64_t n_qd, const BlockMap& map_ls, int64_t n_ls, int i) {
     if (n_sl > 0) {
-        hipLaunchKernelGGL(kb_qa<TW>, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
+        hipLaunchKernelGGL(kb_qa<TW>, dim3(n_sl), dim3(kGWB), 0, st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
-        hipLaunchKernelGGL(kb_qb, dim3(n_sl), dim3(kGW), (i + 1) * sizeof(double), st, items, map_sl, i);
+        hipLaunchKernelGGL(kb_qb, dim3(n_sl), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
-        hipLaunchKernelGGL(kb_qc, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
+        hipLaunchKernelGGL(kb_qc, dim3(n_sl), dim3(kGWB), 0, st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
     }
     if (n_qd > 0) {
-        hipLaunchKernelGGL(kb_qd, dim3(n_qd), dim3(kGW), 3 * (i + 2) * sizeof(double), st, items, map_qd, i);
+        hipLaunchKernelGGL(kb_qd, dim3(n_qd), dim3(kGWB), 3 * (i + 2) * sizeof(double), st, items, map_qd, i);
         RGS_LAUNCH_CHECK();
     }
     if (n_ls > 0) {
-        hipLaunchKernelGGL(kb_ls3<TW>, dim3(n_ls), dim3(kGW), (i + 1) * sizeof(double), st, items, map_ls, i);
+        hipLaunchKernelGGL(kb_ls3<TW>, dim3(n_ls), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_ls, i);
         RGS_LAUNCH_CHECK();
     }
     return true;

@@ -19,9 +19,15 @@ namespace rgs {
 // loads in batches (independent loads first, then the fixed-order sums) to
 // keep the number of dependent round trips per kernel at two or three.
 // Column-parallel dot products run one thread per column over a slice;
-// row-parallel products run 64 rows x 16 column groups (1024 threads).
+// row-parallel products run 64 rows x 16 column groups.  The bodies are
+// written for NT threads per workgroup (kGW, or kGWB in the batched kernels,
+// which share the GPU with other launches and so use smaller workgroups);
+// with NT < kGW a thread takes the column groups q, q + NT/64, ... and the
+// fixed-shape reductions keep the kGW-thread shape, so every NT gives the
+// same bits.
 // ---------------------------------------------------------------------------
 constexpr int kGW = 1024;   // threads of the sketch-space kernels
+constexpr int kGWB = 256;   // threads of the batched sketch-space kernels
 constexpr int kGQ = 16;     // column groups of the row-parallel products
 constexpr int kBatch = 16;  // loads issued back to back per thread
 
@@ -101,6 +107,7 @@ __device__ __forceinline__ double combine16(double (*red)[64], int rl) {
 
 // Step 2, part 2: c = sum of slice partials; head of U_i^T p:
 //   uh[r] = p[r] - sum_{c <= r} V[r, c] c[c],  r < i.
+template <int NT = kGW>
 __device__ __forceinline__ void ls2_body(const double* __restrict__ p, int k, int i, int nsl,
                                          const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
                                          double* __restrict__ uh, double* __restrict__ pnorm, int bid,
@@ -109,30 +116,30 @@ __device__ __forceinline__ void ls2_body(const double* __restrict__ p, int k, in
     sum_slices(pd, nsl, mcap + 1, i + 1, cp);
     __syncthreads();
     if (bid == 0 && threadIdx.x == 0) pnorm[i] = sqrt(cp[i]);
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = bid * 64 + rl;
-    red[q][rl] = (r < i) ? row_part(Vc, k, r, 0, min(r, i - 1) + 1, cp, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < i) ? row_part(Vc, k, r, 0, min(r, i - 1) + 1, cp, q) : 0.0;
     __syncthreads();
-    if (q == 0 && r < i) uh[r] = p[r] - combine16(red, rl);
+    if (q0 == 0 && r < i) uh[r] = p[r] - combine16(red, rl);
 }
 
 // Step 2, last part: y = R_S^{-1} uh with X = R_S^{-1} (upper triangular, nr x nr):
 //   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:nr, col) and the working-
 // precision coefficients coef[r] = y[r] (times cscale[r] = 1/r_rr when the
 // basis is kept unnormalised).  bid = row block of 64.
-template <typename T>
+template <typename T, int NT = kGW>
 __device__ __forceinline__ void ls3_body(int nr, int col, const double* __restrict__ X, int mcap,
                                          const double* __restrict__ uh, double* __restrict__ R, int64_t ldr,
                                          T* __restrict__ coef, const double* __restrict__ cscale, int bid,
                                          double* __restrict__ us) {
     __shared__ double red[kGQ][64];
-    for (int c = threadIdx.x; c < nr; c += kGW) us[c] = uh[c];
+    for (int c = threadIdx.x; c < nr; c += NT) us[c] = uh[c];
     __syncthreads();
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = bid * 64 + rl;
-    red[q][rl] = (r < nr) ? row_part(X, mcap, r, r, nr, us, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < nr) ? row_part(X, mcap, r, r, nr, us, q) : 0.0;
     __syncthreads();
-    if (q == 0 && r < nr) {
+    if (q0 == 0 && r < nr) {
         const double y = combine16(red, rl);
         R[r + (int64_t)col * ldr] = y;
         coef[r] = (T)(cscale ? y * cscale[r] : y);
@@ -143,7 +150,7 @@ __device__ __forceinline__ void ls3_body(int nr, int col, const double* __restri
 // (times scale2[0] when given: the 1/r_ii of an Arnoldi vector sketched before
 // its normalisation was known) for slice bid (or a copy of src), stored in sp;
 // per-slice partials of c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
-template <typename PT>
+template <typename PT, int NT = kGW>
 __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, double scale,
                                         const double* __restrict__ src, int k, int i,
                                         const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
@@ -151,30 +158,32 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
                                         const double* __restrict__ scale2 = nullptr) {
     __shared__ double red[kGQ][64];
     __shared__ double xs[kSlice];
-    const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = r0 + rl;
     if (src) {
-        if (q == 0) {
+        if (q0 == 0) {
             const double val = (r < k) ? src[r] : 0.0;
             xs[rl] = val;
             if (r < k) sp[r] = val;
         }
     } else {
         // group q sums the block partials g in [G q / 16, G (q+1) / 16), in order
-        const int g0 = (int)((int64_t)G * q / kGQ), g1 = (int)((int64_t)G * (q + 1) / kGQ);
-        double acc = 0.0;
-        if (r < k) {
-            for (int g = g0; g < g1; g += 32) {
-                PT t[32];
+        for (int q = q0; q < kGQ; q += NT / 64) {
+            const int g0 = (int)((int64_t)G * q / kGQ), g1 = (int)((int64_t)G * (q + 1) / kGQ);
+            double acc = 0.0;
+            if (r < k) {
+                for (int g = g0; g < g1; g += 32) {
+                    PT t[32];
 #pragma unroll
-                for (int u = 0; u < 32; ++u) t[u] = (g + u < g1) ? partials[(int64_t)(g + u) * k + r] : PT(0);
+                    for (int u = 0; u < 32; ++u) t[u] = (g + u < g1) ? partials[(int64_t)(g + u) * k + r] : PT(0);
 #pragma unroll
-                for (int u = 0; u < 32; ++u) acc += (double)t[u];
+                    for (int u = 0; u < 32; ++u) acc += (double)t[u];
+                }
             }
+            red[q][rl] = acc;
         }
-        red[q][rl] = acc;
         __syncthreads();
-        if (q == 0) {
+        if (q0 == 0) {
             double val = (r < k) ? combine16(red, rl) * scale : 0.0;
             if (scale2) val *= scale2[0];
             xs[rl] = val;
@@ -183,11 +192,12 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
     }
     __syncthreads();
     double* out = pd + (int64_t)s * (mcap + 1);
-    for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
+    for (int c = threadIdx.x; c <= i; c += NT) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
 // Column step B (steps 5-6): r_ii = ||s'||, S(:, i) = s'/r_ii, breakdown test,
 // u = U_i^T s_i = (s' - V c1) / r_ii, per-slice partials of ||u(i+1:k)||^2.
+template <int NT = kGW>
 __device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __restrict__ sp,
                                         const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
                                         double* __restrict__ u, double* __restrict__ pd2, double* __restrict__ S,
@@ -214,11 +224,11 @@ __device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __r
             }
         }
     }
-    const int s = bid, rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int s = bid, rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = s * kSlice + rl;
-    red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : 0.0;
     __syncthreads();
-    if (q == 0) {
+    if (q0 == 0) {
         double t2 = 0.0;
         if (r < k) {
             const double spr = sp[r];
@@ -242,6 +252,7 @@ __device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __r
 // stored as column i of V (both layouts).  Per-slice partials of d = V_i^T v
 // (pd, stride mcap+1) and, when the next right-hand side pn = p_{i+1} is given,
 // of e = Wm_i^T pn, v.pn and ||pn||^2 (pdb, stride mcap+2, slots [0,i), i, i+1).
+template <int NT = kGW>
 __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __restrict__ u,
                                         const double* __restrict__ pd2, const double* __restrict__ pn,
                                         double* __restrict__ v, double* __restrict__ Vc, double* __restrict__ Vr,
@@ -294,7 +305,7 @@ __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __r
     const int ntot = pn ? 2 * i + 2 : i;
     double* outd = pd + (int64_t)s * (mcap + 1);
     double* oute = pdb + (int64_t)s * (mcap + 2);
-    for (int c = threadIdx.x; c < ntot; c += kGW) {
+    for (int c = threadIdx.x; c < ntot; c += NT) {
         const bool isd = c < i;
         const int ce = isd ? c : c - i;
         double val;
@@ -314,6 +325,7 @@ __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __r
 //   (u(0:i) is R_S(0:i, i)), X(i, i) = 1/beta;
 //   when pn is given, the head of U_{i+1}^T pn for the next column's least squares:
 //   cp = Wm_{i+1}^T pn = [e; tau (v.pn - d.e)],  uh(r) = pn(r) - sum_{c <= min(r,i)} V(r, c) cp(c), r <= i.
+template <int NT = kGW>
 __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __restrict__ v,
                                         const double* __restrict__ u, const double* __restrict__ pn,
                                         double* __restrict__ Wc, double* __restrict__ Wr,
@@ -323,17 +335,17 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
                                         const double* __restrict__ tau_a, const double* __restrict__ beta_a,
                                         int bid, double* __restrict__ dyn) {
     __shared__ double red[kGQ][64];
-    __shared__ double tree[kGW];
-    const int rl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    __shared__ double tree[NT];
+    const int rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const double tau = tau_a[i];
     if (bid < nsl) {
         double* dsh = dyn;
         sum_slices(pd, nsl, mcap + 1, i, dsh);
         __syncthreads();
         const int r = bid * kSlice + rl;
-        red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : 0.0;
+        for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : 0.0;
         __syncthreads();
-        if (q == 0 && r < k) {
+        if (q0 == 0 && r < k) {
             const double val = tau * (v[r] - combine16(red, rl));
             Wc[r + (int64_t)i * k] = val;
             Wr[(int64_t)r * mcap + i] = val;
@@ -344,25 +356,37 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
     double* ush = dyn;            // u(0:i)
     double* dsh = dyn + (i + 1);  // d
     double* csh = dsh + (i + 1);  // cp
-    for (int c = threadIdx.x; c < i; c += kGW) ush[c] = u[c];
+    for (int c = threadIdx.x; c < i; c += NT) ush[c] = u[c];
     if (pn) {
-        for (int c = threadIdx.x; c < 2 * i + 2; c += kGW) {
+        for (int c = threadIdx.x; c < 2 * i + 2; c += NT) {
             if (c < i) dsh[c] = sum_col(pd, nsl, mcap + 1, c);
             else csh[c - i] = sum_col(pdb, nsl, mcap + 2, c - i);   // e, then v.pn at i, ||pn||^2 at i+1
         }
     }
     __syncthreads();
     const int r = (bid - nsl) * 64 + rl;
-    red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : 0.0;
     __syncthreads();
-    if (q == 0 && r < i) X[r + (int64_t)i * mcap] = -combine16(red, rl) / beta_a[i];
+    if (q0 == 0 && r < i) X[r + (int64_t)i * mcap] = -combine16(red, rl) / beta_a[i];
     if (!pn) return;
-    // d.e by a fixed-shape tree, then cp(i) = tau (v.pn - d.e)
-    double part = 0.0;
-    for (int c = threadIdx.x; c < i; c += kGW) part = fma(dsh[c], csh[c], part);
-    tree[threadIdx.x] = part;
+    // d.e by a fixed-shape tree over kGW leaves (leaf t: the products c = t
+    // (mod kGW), ascending), then cp(i) = tau (v.pn - d.e).  A thread holds
+    // the leaves threadIdx.x + NT j; the levels wider than NT are summed in
+    // its registers, the rest in LDS.
+    constexpr int V = kGW / NT;
+    double part[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        part[j] = 0.0;
+        for (int c = threadIdx.x + NT * j; c < i; c += kGW) part[j] = fma(dsh[c], csh[c], part[j]);
+    }
+#pragma unroll
+    for (int w = kGW / 2; w >= NT; w >>= 1)
+#pragma unroll
+        for (int j = 0; j < w / NT; ++j) part[j] += part[j + w / NT];
+    tree[threadIdx.x] = part[0];
     __syncthreads();
-    for (int w = kGW / 2; w > 0; w >>= 1) {
+    for (int w = NT / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
         __syncthreads();
     }
@@ -371,9 +395,9 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
     if (threadIdx.x == 0) csh[i] = tau * (vp - tree[0]);
     if (bid == nsl && threadIdx.x == 0) pnorm[i + 1] = sqrt(pp);
     __syncthreads();
-    red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : 0.0;
     __syncthreads();
-    if (q == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
+    if (q0 == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
 }
 
 // ---------------------------------------------------------------------------
