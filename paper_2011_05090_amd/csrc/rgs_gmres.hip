@@ -125,71 +125,79 @@ __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ 
     uint32_t x = rem - y * nx;
     auto cv = [&](double d) -> T { return scale ? (T)(d * ir) : (T)d; };
     auto ld1 = [&](int64_t idx) -> T { return cv(to_double(qs[idx])); };
+    // results in local arrays with one store sequence at the end: stores
+    // through out/cen on several paths keep the caller's array out of registers
+    T ro[4], rc[4];
     if (vec) {
         if (l0 >= n) {   // n is a multiple of 4 here: whole groups only
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[r] = cen[r] = T(0);
-            return;
-        }
-        double a[4];
-        T u[4], ym[4], yp[4], zm[4], zp[4];
-        ld4_raw(qs, l0, a);
+            for (int r = 0; r < 4; ++r) ro[r] = rc[r] = T(0);
+        } else {
+            double a[4];
+            T u[4], ym[4], yp[4], zm[4], zp[4];
+            ld4_raw(qs, l0, a);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) u[r] = cv(a[r]);
-        const T xm = x > 0 ? ld1(l0 - 1) : T(0);
-        const T xp = x + 4 < nx ? ld1(l0 + 4) : T(0);
-        auto plane = [&](bool ok, int64_t at, T o[4]) {
-            if (ok) {
-                ld4_raw(qs, at, a);
+            for (int r = 0; r < 4; ++r) u[r] = cv(a[r]);
+            const T xm = x > 0 ? ld1(l0 - 1) : T(0);
+            const T xp = x + 4 < nx ? ld1(l0 + 4) : T(0);
+            auto plane = [&](bool ok, int64_t at, T o[4]) {
+                if (ok) {
+                    ld4_raw(qs, at, a);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = cv(a[r]);
-            } else {
+                    for (int r = 0; r < 4; ++r) o[r] = cv(a[r]);
+                } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = T(0);
+                    for (int r = 0; r < 4; ++r) o[r] = T(0);
+                }
+            };
+            plane(y > 0, l0 - nx, ym);
+            plane(y + 1 < ny, l0 + nx, yp);
+            plane(z > 0, l0 - (int64_t)nxy, zm);
+            plane(z + 1 < nz, l0 + (int64_t)nxy, zp);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T acc = (T)g.c0 * u[r];
+                acc = acc + (x + r > 0 ? (T)g.cxm * (r > 0 ? u[r - 1] : xm) : T(0));
+                acc = acc + (x + r + 1 < nx ? (T)g.cxp * (r < 3 ? u[r + 1] : xp) : T(0));
+                acc = acc + (y > 0 ? (T)g.cym * ym[r] : T(0));
+                acc = acc + (y + 1 < ny ? (T)g.cyp * yp[r] : T(0));
+                acc = acc + (z > 0 ? (T)g.czm * zm[r] : T(0));
+                acc = acc + (z + 1 < nz ? (T)g.czp * zp[r] : T(0));
+                ro[r] = acc;
+                rc[r] = u[r];
             }
-        };
-        plane(y > 0, l0 - nx, ym);
-        plane(y + 1 < ny, l0 + nx, yp);
-        plane(z > 0, l0 - (int64_t)nxy, zm);
-        plane(z + 1 < nz, l0 + (int64_t)nxy, zp);
+        }
+    } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            T acc = (T)g.c0 * u[r];
-            acc = acc + (x + r > 0 ? (T)g.cxm * (r > 0 ? u[r - 1] : xm) : T(0));
-            acc = acc + (x + r + 1 < nx ? (T)g.cxp * (r < 3 ? u[r + 1] : xp) : T(0));
-            acc = acc + (y > 0 ? (T)g.cym * ym[r] : T(0));
-            acc = acc + (y + 1 < ny ? (T)g.cyp * yp[r] : T(0));
-            acc = acc + (z > 0 ? (T)g.czm * zm[r] : T(0));
-            acc = acc + (z + 1 < nz ? (T)g.czp * zp[r] : T(0));
-            out[r] = acc;
-            cen[r] = u[r];
+            const int64_t l = l0 + r;
+            if (l < n) {
+                const T c = ld1(l);
+                T acc = (T)g.c0 * c;
+                acc = acc + (x > 0 ? (T)g.cxm * ld1(l - 1) : T(0));
+                acc = acc + (x + 1 < nx ? (T)g.cxp * ld1(l + 1) : T(0));
+                acc = acc + (y > 0 ? (T)g.cym * ld1(l - nx) : T(0));
+                acc = acc + (y + 1 < ny ? (T)g.cyp * ld1(l + nx) : T(0));
+                acc = acc + (z > 0 ? (T)g.czm * ld1(l - (int64_t)nxy) : T(0));
+                acc = acc + (z + 1 < nz ? (T)g.czp * ld1(l + (int64_t)nxy) : T(0));
+                ro[r] = acc;
+                rc[r] = c;
+            } else {
+                ro[r] = rc[r] = T(0);
+            }
+            if (++x == nx) {
+                x = 0;
+                if (++y == ny) {
+                    y = 0;
+                    ++z;
+                }
+            }
         }
-        return;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int64_t l = l0 + r;
-        if (l < n) {
-            const T c = ld1(l);
-            T acc = (T)g.c0 * c;
-            acc = acc + (x > 0 ? (T)g.cxm * ld1(l - 1) : T(0));
-            acc = acc + (x + 1 < nx ? (T)g.cxp * ld1(l + 1) : T(0));
-            acc = acc + (y > 0 ? (T)g.cym * ld1(l - nx) : T(0));
-            acc = acc + (y + 1 < ny ? (T)g.cyp * ld1(l + nx) : T(0));
-            acc = acc + (z > 0 ? (T)g.czm * ld1(l - (int64_t)nxy) : T(0));
-            acc = acc + (z + 1 < nz ? (T)g.czp * ld1(l + (int64_t)nxy) : T(0));
-            out[r] = acc;
-            cen[r] = c;
-        } else {
-            out[r] = cen[r] = T(0);
-        }
-        if (++x == nx) {
-            x = 0;
-            if (++y == ny) {
-                y = 0;
-                ++z;
-            }
-        }
+        out[r] = ro[r];
+        cen[r] = rc[r];
     }
 }
 

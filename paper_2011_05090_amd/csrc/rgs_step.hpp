@@ -30,6 +30,7 @@ constexpr int kGW = 1024;   // threads of the sketch-space kernels
 constexpr int kGWB = 256;   // threads of the batched sketch-space kernels
 constexpr int kGQ = 16;     // column groups of the row-parallel products
 constexpr int kBatch = 16;  // loads issued back to back per thread
+constexpr int kSliceBatch = 32;   // the same in the column-parallel slice products
 
 // sum_{s < nsl} pd[s * stride + c] (fixed order in s)
 __device__ __forceinline__ double sum_col(const double* __restrict__ pd, int nsl, int stride, int c) {
@@ -55,12 +56,12 @@ __device__ __forceinline__ double slice_dot(const double* __restrict__ Mr, int m
                                             const double* __restrict__ xs, int c) {
     double acc = 0.0;
 #pragma unroll 1
-    for (int b = 0; b < kSlice; b += kBatch) {
-        double t[kBatch];
+    for (int b = 0; b < kSlice; b += kSliceBatch) {
+        double t[kSliceBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) t[u] = Mr[(int64_t)min(r0 + b + u, k - 1) * mcap + c];
+        for (int u = 0; u < kSliceBatch; ++u) t[u] = Mr[(int64_t)min(r0 + b + u, k - 1) * mcap + c];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) acc = fma(t[u], xs[b + u], acc);
+        for (int u = 0; u < kSliceBatch; ++u) acc = fma(t[u], xs[b + u], acc);
     }
     return acc;
 }
