@@ -806,6 +806,10 @@ constexpr GemmSchedule kGemmSchedules[4] = {{64, 0}, {64, 1}, {32, 0}, {32, 1}};
 // Streams a batched QR call spreads its factorisations over.
 constexpr int kQrShares = 2;
 
+// XCDs of the device: the dispatcher sends workgroup b of a launch to XCD
+// b mod kXcds (a launch order built on it only affects cache reuse).
+constexpr int kXcds = 8;
+
 void order_units(const std::vector<GemmUnit>& in, size_t a, size_t b, int xcd, std::vector<GemmUnit>& out) {
     if (!xcd) {
         out.insert(out.end(), in.begin() + a, in.begin() + b);
@@ -1333,6 +1337,11 @@ bool valid_gmres_desc(const rgs_gmres_desc* d) {
 struct GmresMaps {
     std::vector<int> ids;
     std::vector<int64_t> row, proj;   // prefix sums over the listed systems
+    // the (row block, system) pairs of the projection blocks, for the launch
+    // whose systems share a row block's data: pairs[j kXcds + x] is the j-th
+    // pair, in r order, of the row blocks r with r mod kXcds = x, so each row
+    // block stays on one XCD; (-1, -1) marks an idle slot
+    std::vector<int2> pairs;
     int nsl = 0;
     int count() const { return (int)ids.size(); }
 };
@@ -1341,6 +1350,21 @@ void build_gmres_maps(GmresMaps& g, const std::vector<int64_t>& active, const st
     g.ids.assign(active.begin(), active.end());
     g.row = prefix_of((int64_t)active.size(), [&](int64_t p) { return (ns[active[p]] + 255) / 256; });
     g.proj = prefix_of((int64_t)active.size(), [&](int64_t p) { return (ns[active[p]] + kProjRows - 1) / kProjRows; });
+    std::vector<std::vector<int2>> lane((size_t)kXcds);
+    for (int64_t r = 0;; ++r) {
+        bool any = false;
+        for (int64_t b : active)
+            if (r * kProjRows < ns[b]) {
+                lane[r % kXcds].push_back(make_int2((int)r, (int)b));
+                any = true;
+            }
+        if (!any) break;
+    }
+    size_t len = 0;
+    for (const auto& l : lane) len = std::max(len, l.size());
+    g.pairs.assign(len * kXcds, make_int2(-1, -1));
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t j = 0; j < lane[x].size(); ++j) g.pairs[j * kXcds + x] = lane[x][j];
     g.nsl = (int)((k + kSlice - 1) / kSlice);
 }
 
@@ -1415,6 +1439,8 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     build_gmres_maps(gm, all, ns, k);
     const size_t o_ids = c.take<int>(batch), o_mrow = c.take<int64_t>(batch + 1);
     const size_t o_mproj = c.take<int64_t>(batch + 1);
+    // pair list: at most kXcds x (the blocks of the XCD with the most)
+    const size_t o_pairs = c.take<int2>((size_t)kXcds * (gm.proj[gm.count()] + (nmax + kProjRows - 1) / kProjRows));
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -1501,9 +1527,12 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     const int* d_ids = reinterpret_cast<const int*>(A + o_ids);
     const int64_t* d_row = reinterpret_cast<const int64_t*>(A + o_mrow);
     const int64_t* d_proj = reinterpret_cast<const int64_t*>(A + o_mproj);
+    const int2* d_pairs = reinterpret_cast<const int2*>(A + o_pairs);
     auto upload_maps = [&]() -> bool {
         return hipMemcpyAsync(A + o_ids, gm.ids.data(), gm.ids.size() * sizeof(int), hipMemcpyHostToDevice, s) ==
                    hipSuccess &&
+               hipMemcpyAsync(A + o_pairs, gm.pairs.data(), gm.pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
+                              s) == hipSuccess &&
                hipMemcpyAsync(A + o_mrow, gm.row.data(), gm.row.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                               s) == hipSuccess &&
                hipMemcpyAsync(A + o_mproj, gm.proj.data(), gm.proj.size() * sizeof(int64_t), hipMemcpyHostToDevice,
@@ -1560,14 +1589,19 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         graph = nullptr;
     };
     const bool dual = sk_kind == SK_GAUSS;   // the two sketches of an Arnoldi step share their draws
+    // the dual mat-vec + sketch step: with the bf16 table in row-block-major
+    // order (the systems share the table's entries), else system by system
+    auto dual_step = [&](hipStream_t q, int ii) -> bool {
+        return tab ? launch_gbatch_stencil_dual_rows<T, TQ>(q, itd, gid, d_pairs, (int64_t)gm.pairs.size(), ii)
+                   : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), ii, false);
+    };
     auto enqueue_cycle = [&](hipStream_t q) -> bool {
         const int nsl = gm.nsl;
         const BlockMap none{nullptr, nullptr, 0, 0};
         if (!launch_gbatch_reset(q, itd, m_sys(), gm.count())) return false;
         if (!launch_gbatch_cast<T>(q, gid, m_row(), n_row())) return false;
         if (dual) {
-            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), 0) ||
-                !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), 0, tab))
+            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), 0) || !dual_step(q, 0))
                 return false;
         } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(), n_proj(), 0)) {
             return false;
@@ -1581,8 +1615,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
             const int rbq = (int)((i + 1 + 63) / 64);   // column-step blocks beyond the slices
             if (dual) {
                 if (!launch_gbatch_ls<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(rbl), n_uni(rbl), ii, 1) ||
-                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), ii) ||
-                    !launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), ii, tab))
+                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), ii) || !dual_step(q, ii))
                     return false;
             } else {
                 if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(), n_proj(), ii)) return false;

@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t bf16_rne_f64(double x) {
 // The bf16 Gaussian table (unscaled entries): group o of sketch row j holds
 // z(j, 8o .. 8o+7) as one 16-byte word.
 typedef uint32_t tabw_t __attribute__((ext_vector_type(4)));
-constexpr int kTabDepth = 4;   // table groups a thread keeps in flight
+constexpr int kTabDepth = 16;   // table groups a thread keeps in flight
 
 __device__ __forceinline__ tabw_t tab_load(const uint16_t* __restrict__ table, int k, int64_t o, int j) {
     return __builtin_nontemporal_load(reinterpret_cast<const tabw_t*>(table + (o * k + j) * 8));

@@ -647,6 +647,29 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const Batc
                              lds);
 }
 
+// The bf16-table variant with the L2 in mind: workgroup b -> (row block r,
+// system) from a host-built list.  The table's entries do not depend on the
+// system, so every system with a row block r reads the same k x kProjRows
+// slice of it; the list gives the pairs of row block r to the workgroups that
+// the round-robin dispatch sends to XCD r mod 8, in r order, so the workgroups
+// resident on one XCD share one slice, which its L2 then serves after one read
+// from HBM.  An entry with r < 0 is an idle slot.  Same body per (system,
+// block) as kg_stencil_dual, so the same bits.
+template <typename TQ, typename T>
+__global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_rows(const BatchItem* __restrict__ items,
+                                                                           const GmresItem* __restrict__ gi,
+                                                                           const int2* __restrict__ pairs, int i) {
+    __shared__ T lds[2 * kProjWaves * kTile];
+    const int2 p = pairs[blockIdx.x];   // (row block, system)
+    if (p.x < 0) return;
+    const BatchItem& it = items[p.y];
+    RGS_EXIT_IF_STOPPED(it.sa.status);
+    const GmresItem& g = gi[p.y];
+    stencil_dual_body<TQ, T, true>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+                                   static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part), static_cast<T*>(it.part2),
+                                   p.x, lds);
+}
+
 // The projection of the fused-sketch Gaussian step: w_i = (A q'_{i-1}) / r_{i-1,i-1}
 // scaled on load, no sketch (taken by kg_stencil_dual afterwards).
 template <typename T, typename TQ, bool DEFER>
@@ -904,6 +927,16 @@ bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const Gm
     return true;
 }
 
+template <typename T, typename TQ>
+bool launch_gbatch_stencil_dual_rows(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* pairs,
+                                     int64_t npairs, int i) {
+    if (npairs == 0) return true;
+    hipLaunchKernelGGL((kg_stencil_dual_rows<TQ, T>), dim3(npairs), dim3(kProjWaves * kWave), 0, st, items, gi,
+                       pairs, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                               int64_t nproj, int i) {
@@ -1018,6 +1051,12 @@ template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchI
 template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
                                                          const BlockMap&, int64_t, int, bool);
 template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool);
+template bool launch_gbatch_stencil_dual_rows<float, float>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                            const int2*, int64_t, int);
+template bool launch_gbatch_stencil_dual_rows<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                              const int2*, int64_t, int);
+template bool launch_gbatch_stencil_dual_rows<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                           const int2*, int64_t, int);
 template bool launch_gbatch_project_ws<float, float, false>(hipStream_t, const BatchItem*, const GmresItem*,
                                                             const BlockMap&, int64_t, int);
 template bool launch_gbatch_project_ws<double, double, false>(hipStream_t, const BatchItem*, const GmresItem*,

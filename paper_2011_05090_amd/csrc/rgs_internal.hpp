@@ -135,6 +135,9 @@ bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& ma
 template <typename T, typename TQ>
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                                 int64_t nproj, int i, bool table);
+template <typename T, typename TQ>
+bool launch_gbatch_stencil_dual_rows(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* pairs,
+                                     int64_t npairs, int i);
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project_ws(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                               int64_t nproj, int i);
