@@ -27,6 +27,17 @@ constexpr int kProjWaves = 8;  // wave tiles per workgroup of the projection ker
 constexpr int kProjGroup = 8;
 constexpr int kProjRows = kProjWaves * kTile;
 
+// The dispatcher sends workgroup b of a launch to XCD b mod kXcd, each XCD
+// with its own L2.  xcd_block maps b to a logical block so that every XCD
+// gets one contiguous range of the G blocks: blocks that read each other's
+// rows (the neighbour planes of a stencil) then share an L2.  A bijection of
+// [0, G); only cache reuse depends on it.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+    const int64_t x = b % kXcd, slot = b / kXcd, q = G / kXcd, r = G % kXcd;
+    return x * q + (x < r ? x : r) + slot;
+}
+
 constexpr uint32_t kTagSigns = 0xFFFFFFFFu;  // counter word 1 of the SRHT sign draws
 constexpr uint32_t kTagRows = 0xFFFFFFFEu;   // counter word 1 of the SRHT row draws
 

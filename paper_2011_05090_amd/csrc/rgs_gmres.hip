@@ -534,7 +534,8 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
     int do_sketch, SketchArgs sk, PT* __restrict__ partials, const int* __restrict__ status) {
     __shared__ T lds[kProjWaves * kTile];
     RGS_EXIT_IF_STOPPED(status);
-    stencil_sketch_body<TQ, T, PT, SK>(qs, invr, g, n, w, do_sketch, sk, partials, blockIdx.x, lds);
+    stencil_sketch_body<TQ, T, PT, SK>(qs, invr, g, n, w, do_sketch, sk, partials, xcd_block(blockIdx.x, gridDim.x),
+                                       lds);
 }
 
 template <typename TQ, typename T, bool TAB>
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     T* __restrict__ part_t, const int* __restrict__ status) {
     __shared__ T lds[2 * kProjWaves * kTile];
     RGS_EXIT_IF_STOPPED(status);
-    stencil_dual_body<TQ, T, TAB>(xs, g, n, t_out, sk, part_x, part_t, blockIdx.x, lds);
+    stencil_dual_body<TQ, T, TAB>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
@@ -624,7 +625,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem
                                                                  const GmresItem* __restrict__ gi,
                                                                  BlockMap map, int i) {
     __shared__ T lds[kProjWaves * kTile];
-    const int2 bm = locate(map, blockIdx.x);
+    const int2 bm = locate(map, xcd_block(blockIdx.x, gridDim.x));
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
@@ -638,7 +639,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const Batc
                                                                       const GmresItem* __restrict__ gi,
                                                                       BlockMap map, int i) {
     __shared__ T lds[2 * kProjWaves * kTile];
-    const int2 bm = locate(map, blockIdx.x);
+    const int2 bm = locate(map, xcd_block(blockIdx.x, gridDim.x));
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
