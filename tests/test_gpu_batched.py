@@ -111,6 +111,30 @@ def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec):
                 assert be <= 2 * be1 and be1 <= 2 * be
 
 
+@pytest.mark.parametrize("count", [1, 2, 3])
+def test_small_batches_equal_single_calls_bitwise(gpu_handle, count):
+    """A call spreads its factorisations over two streams (ordered by m, dealt
+    out alternately); one factorisation runs alone, two or three split
+    unevenly.  Every result is still the single call's, bit for bit."""
+    rgs = _rgs()
+    data = _batch_inputs(count, seed=7)
+    items, singles = [], []
+    for b, (W, k) in enumerate(data):
+        n, m = W.shape
+        Wd = to_dev(W, torch.float32)
+        Q, R, S = alloc(n, m, k, torch.float32)
+        items.append((Wd, Q, R, S, k))
+        Q1, R1, S1 = alloc(n, m, k, torch.float32)
+        rep1 = rgs.rgs_qr(gpu_handle, rgs.qr_desc(n, m, k, sketch="srht", prec="fp32", instance=b), Wd, Q1, R1, S1)
+        assert rep1.status == 0
+        singles.append((Q1, R1, S1))
+    rep, stat, fcol = rgs.rgs_qr_batched(gpu_handle, items, sketch="srht", prec="fp32")
+    torch.cuda.synchronize()
+    assert rep.status == 0 and stat == [0] * count
+    for (Wd, Q, R, S, k), (Q1, R1, S1) in zip(items, singles):
+        assert torch.equal(Q, Q1) and torch.equal(R, R1) and torch.equal(S, S1)
+
+
 def test_batched_matches_oracle(gpu_handle):
     rgs = _rgs()
     data = _batch_inputs(5, seed=2, nmax=20000, mmax=24)
