@@ -149,8 +149,10 @@ __device__ __forceinline__ void gauss_cols_body(const TX* __restrict__ X, int64_
         for (int t = threadIdx.x; t < SUB; t += kWG) {
             const int64_t l = r0 + t;
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                w[c][t] = (c < nc && l < n) ? (TA)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : TA(0);
+            for (int c = 0; c < C; ++c) {   // clamped loads, masked after: no branch per load
+                const TA x = (TA)elem_real(X[(int64_t)(c0 + min(c, nc - 1)) * ldx + min(l, n - 1)]);
+                w[c][t] = (c < nc && l < n) ? x : TA(0);
+            }
         }
         __syncthreads();
         if (j < sk.k) {
@@ -203,8 +205,10 @@ __device__ __forceinline__ void rad_cols_body(const TX* __restrict__ X, int64_t 
         for (int t = threadIdx.x; t < SUB; t += kWG) {
             const int64_t l = r0 + t;
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                w[c][t] = (c < nc && l < n) ? (TA)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : TA(0);
+            for (int c = 0; c < C; ++c) {   // clamped loads, masked after: no branch per load
+                const TA x = (TA)elem_real(X[(int64_t)(c0 + min(c, nc - 1)) * ldx + min(l, n - 1)]);
+                w[c][t] = (c < nc && l < n) ? x : TA(0);
+            }
         }
         __syncthreads();
         if (j < sk.k) {
@@ -290,8 +294,10 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
         for (int t = threadIdx.x; t < SUB; t += kWG) {
             const int64_t l = r0 + t;
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                w[c][t] = (c < nc && l < n) ? (TA)elem_real(X[(int64_t)(c0 + c) * ldx + l]) : TA(0);
+            for (int c = 0; c < C; ++c) {   // clamped loads, masked after: no branch per load
+                const TA x = (TA)elem_real(X[(int64_t)(c0 + min(c, nc - 1)) * ldx + min(l, n - 1)]);
+                w[c][t] = (c < nc && l < n) ? x : TA(0);
+            }
         }
         __syncthreads();
         if (j < sk.k) {
