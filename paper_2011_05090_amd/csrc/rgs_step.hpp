@@ -32,19 +32,15 @@ constexpr int kGQ = 16;     // column groups of the row-parallel products
 constexpr int kBatch = 16;  // loads issued back to back per thread
 constexpr int kSliceBatch = 32;   // the same in the column-parallel slice products
 
-// The batched loads below read clamped (always valid) addresses and mask the
-// values afterwards: a load under a per-element condition becomes a branch
-// around each load with a wait after it, one round trip per element.
-
 // sum_{s < nsl} pd[s * stride + c] (fixed order in s)
 __device__ __forceinline__ double sum_col(const double* __restrict__ pd, int nsl, int stride, int c) {
     double acc = 0.0;
     for (int s0 = 0; s0 < nsl; s0 += kBatch) {
         double t[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) t[u] = pd[(int64_t)min(s0 + u, nsl - 1) * stride + c];
+        for (int u = 0; u < kBatch; ++u) t[u] = (s0 + u < nsl) ? pd[(int64_t)(s0 + u) * stride + c] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) acc += (s0 + u < nsl) ? t[u] : 0.0;
+        for (int u = 0; u < kBatch; ++u) acc += t[u];
     }
     return acc;
 }
@@ -90,7 +86,10 @@ __device__ __forceinline__ double row_part(const double* __restrict__ Mc, int64_
     for (int c = c0 + ((q - c0) % kGQ + kGQ) % kGQ; c < c1; c += kGQ * kBatch) {
         double t[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) t[u] = Mc[r + (int64_t)min(c + kGQ * u, c1 - 1) * ld];
+        for (int u = 0; u < kBatch; ++u) {
+            const int cc = c + kGQ * u;
+            t[u] = (cc < c1) ? Mc[r + (int64_t)cc * ld] : 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int cc = c + kGQ * u;
@@ -175,6 +174,8 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
             double acc = 0.0;
             if (r < k) {
                 for (int g = g0; g < g1; g += 32) {
+                    // clamped addresses, masked after: loads under a per-element
+                    // condition came out as a branch and a wait per element
                     PT t[32];
 #pragma unroll
                     for (int u = 0; u < 32; ++u) t[u] = partials[(int64_t)min(g + u, g1 - 1) * k + r];
@@ -264,8 +265,7 @@ __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __r
     __shared__ double vs[kSlice], ps[kSlice];
     __shared__ double hh[3];
     if (threadIdx.x == 0) {
-        double tail2 = 0.0;
-        for (int s = 0; s < nsl; ++s) tail2 += pd2[s];
+        const double tail2 = sum_col(pd2, nsl, 1, 0);   // ascending s, loads in batches
         const double x1 = u[i];
         double beta, tau, scal;
         if (tail2 == 0.0) {
