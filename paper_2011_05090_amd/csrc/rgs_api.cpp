@@ -29,6 +29,7 @@ struct rgs_handle {
     hipStream_t capture = nullptr;   // created on first use: graph capture needs a non-null stream
     hipStream_t aux = nullptr;       // created on first use: the second share of a batched QR call
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    std::vector<hipEvent_t> chunk_ev;   // step-1 chunks of a QR on the auxiliary stream
     char* arena = nullptr;
     size_t arena_bytes = 0;
     std::vector<hipEvent_t> events;
@@ -78,6 +79,26 @@ rgs_status ensure_events(rgs_handle* h, size_t count) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return RGS_EDEVICE;
         h->events.push_back(e);
+    }
+    return RGS_OK;
+}
+
+// The handle's auxiliary stream (default priority) and its fork / join
+// events: work put on it is forked from the handle's stream and joined back
+// into it with events, so every call stays ordered on the handle's stream.
+rgs_status ensure_aux(rgs_handle* h) {
+    if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return RGS_EDEVICE;
+    for (hipEvent_t* e : {&h->fork_ev, &h->join_ev})
+        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return RGS_EDEVICE;
+    return RGS_OK;
+}
+
+// Untimed events that mark the step-1 chunks done on the auxiliary stream.
+rgs_status ensure_chunk_events(rgs_handle* h, size_t count) {
+    while (h->chunk_ev.size() < count) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return RGS_EDEVICE;
+        h->chunk_ev.push_back(e);
     }
     return RGS_OK;
 }
@@ -293,7 +314,8 @@ rgs_status use_table(rgs_handle* h, SketchArgs& sk, int64_t n, uint16_t* table) 
 // u_fine; reduction in fp64), cc columns per pass.
 template <typename TX, typename T, typename TA>
 rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64_t ldx, int64_t n, int64_t ncols,
-                         int G, int cc, TA* part, double* out, int64_t ldo) {
+                         int G, int cc, TA* part, double* out, int64_t ldo, hipStream_t stream = nullptr) {
+    hipStream_t st = stream ? stream : h->stream;
     const double scale = sk.sketch == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)sk.k);
     for (int64_t c0 = 0; c0 < ncols; c0 += cc) {
         const int nc = (int)std::min<int64_t>(cc, ncols - c0);
@@ -301,7 +323,7 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64
             if constexpr (std::is_same<TX, T>::value) {
                 // Theta = I: the sketch of a column is the column (reduce over G = 1 partial)
                 for (int c = 0; c < nc; ++c)
-                    if (!launch_reduce<T>(h->stream, X + (c0 + c) * ldx, 1, (int)n, 1, 1.0, out + (c0 + c) * ldo,
+                    if (!launch_reduce<T>(st, X + (c0 + c) * ldx, 1, (int)n, 1, 1.0, out + (c0 + c) * ldo,
                                           ldo))
                         return RGS_EDEVICE;
                 continue;
@@ -310,11 +332,11 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64
             }
         }
         if (dense_sketch(sk.sketch)) {
-            if (!launch_gauss_cols<TX, T, TA>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
-        } else if (!launch_sketch_cols<TX, TA>(h->stream, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
+            if (!launch_gauss_cols<TX, T, TA>(st, X + c0 * ldx, ldx, n, nc, G, sk, part)) return RGS_EDEVICE;
+        } else if (!launch_sketch_cols<TX, TA>(st, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
             return RGS_EDEVICE;
         }
-        if (!launch_reduce<TA>(h->stream, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
+        if (!launch_reduce<TA>(st, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
     }
     return RGS_OK;
 }
@@ -474,12 +496,34 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     TP* partP = reinterpret_cast<TP*>(A + pl.part_P);
 
     hipStream_t s = h->stream;
+    if (h->aux &&   // anything a failed call left on the auxiliary stream comes first
+        (hipEventRecord(h->join_ev, h->aux) != hipSuccess || hipStreamWaitEvent(s, h->join_ev, 0) != hipSuccess))
+        return RGS_EDEVICE;
     if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
     if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
 
-    // Step 1 for every column at once: P = Theta W.
-    st = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, m, pl.G_P, pl.cc, partP, P, k);
+    // Step 1 for every column at once: P = Theta W, in chunks of pl.cc columns.
+    // The first chunk runs on the handle's stream; the others run on the
+    // auxiliary stream beside the first columns' steps, whose latency-bound
+    // sketch-space chains leave the device mostly idle.  Chunk c signals
+    // chunk_ev[c], which the column loop waits for before the least squares
+    // that first reads one of its columns.  The chunks share one partials
+    // buffer, so the auxiliary stream starts after the first chunk.
+    const int64_t nchunk = (m + pl.cc - 1) / pl.cc;
+    st = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, std::min<int64_t>(m, pl.cc), pl.G_P, pl.cc, partP, P, k);
     if (st != RGS_OK) return st;
+    if (nchunk > 1) {
+        if (ensure_aux(h) != RGS_OK || ensure_chunk_events(h, (size_t)nchunk) != RGS_OK ||
+            hipEventRecord(h->fork_ev, s) != hipSuccess || hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)
+            return RGS_EDEVICE;
+        for (int64_t c = 1; c < nchunk; ++c) {
+            const int64_t c0 = c * pl.cc;
+            st = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P, pl.cc,
+                                         partP, P + c0 * k, k, h->aux);
+            if (st != RGS_OK) return st;
+            if (hipEventRecord(h->chunk_ev[c], h->aux) != hipSuccess) return RGS_EDEVICE;
+        }
+    }
 
     const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;
     if (timed && ensure_events(h, 2 * (size_t)m) != RGS_OK) return RGS_EDEVICE;
@@ -508,6 +552,9 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
         if (split && sketch_col && !launch_gauss_cols<TQ, T>(s, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
+        if (i + 1 < m && (i + 1) % pl.cc == 0 &&   // the next column opens a chunk of P
+            hipStreamWaitEvent(s, h->chunk_ev[(i + 1) / pl.cc], 0) != hipSuccess)
+            return RGS_EDEVICE;
         const double* src0 = (i == 0 && !DEFER) ? P : nullptr;
         const bool ok = d->ls_sweeps > 0
                             ? launch_column_richardson<T, T>(s, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr,
@@ -1192,16 +1239,6 @@ struct QrGroupLauncher {
     }
 };
 
-// Streams of a batched QR call: the handle's stream and, for a second share,
-// the handle's auxiliary stream, forked from and joined back into the
-// handle's stream with events (so the call stays ordered on that stream).
-rgs_status ensure_aux(rgs_handle* h) {
-    if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return RGS_EDEVICE;
-    for (hipEvent_t* e : {&h->fork_ev, &h->join_ev})
-        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return RGS_EDEVICE;
-    return RGS_OK;
-}
-
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
                           uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
@@ -1797,6 +1834,7 @@ rgs_status rgs_destroy(rgs_handle* h) {
     if (h->aux) (void)hipStreamSynchronize(h->aux);
     for (hipEvent_t e : {h->fork_ev, h->join_ev})
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->chunk_ev) (void)hipEventDestroy(e);
     if (h->capture) (void)hipStreamDestroy(h->capture);
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->arena) (void)hipFree(h->arena);

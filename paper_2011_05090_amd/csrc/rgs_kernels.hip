@@ -602,23 +602,24 @@ __global__ __launch_bounds__(kGW) void k_ls2(const double* __restrict__ p, int k
     ls2_body(p, k, i, nsl, Vc, mcap, pd, uh, pnorm, blockIdx.x, cp);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kGW) void k_ls3(int nr, int col, const double* __restrict__ X, int mcap,
-                                             const double* __restrict__ uh, double* __restrict__ R,
-                                             int64_t ldr, T* __restrict__ coef, const double* __restrict__ cscale) {
+template <typename T, int NT = kGW>
+__global__ __launch_bounds__(NT) void k_ls3(int nr, int col, const double* __restrict__ X, int mcap,
+                                            const double* __restrict__ uh, double* __restrict__ R,
+                                            int64_t ldr, T* __restrict__ coef, const double* __restrict__ cscale) {
     extern __shared__ double us[];  // [nr]
-    ls3_body<T>(nr, col, X, mcap, uh, R, ldr, coef, cscale, blockIdx.x, us);
+    ls3_body<T, NT>(nr, col, X, mcap, uh, R, ldr, coef, cscale, blockIdx.x, us);
 }
 
-template <typename PT>
-__global__ __launch_bounds__(kGW) void k_qa(const PT* __restrict__ partials, int G, double scale,
-                                            const double* __restrict__ src, int k, int i,
-                                            const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                            double* __restrict__ pd, const double* __restrict__ scale2) {
-    qa_body<PT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2);
+template <typename PT, int NT = kGW>
+__global__ __launch_bounds__(NT) void k_qa(const PT* __restrict__ partials, int G, double scale,
+                                           const double* __restrict__ src, int k, int i,
+                                           const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
+                                           double* __restrict__ pd, const double* __restrict__ scale2) {
+    qa_body<PT, NT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2);
 }
 
-__global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
+template <int NT = kGW>
+__global__ __launch_bounds__(NT) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
                                             const double* __restrict__ Vc, int mcap,
                                             const double* __restrict__ pd, double* __restrict__ u,
                                             double* __restrict__ pd2, double* __restrict__ S, int64_t lds,
@@ -626,20 +627,22 @@ __global__ __launch_bounds__(kGW) void k_qb(int k, int i, int nsl, const double*
                                             double* __restrict__ invr, const double* __restrict__ pnorm,
                                             int* __restrict__ status) {
     extern __shared__ double c1[];  // [i + 1]
-    qb_body(k, i, nsl, sp, Vc, mcap, pd, u, pd2, S, lds, R, ldr, rr, invr, pnorm, status, blockIdx.x, c1);
+    qb_body<NT>(k, i, nsl, sp, Vc, mcap, pd, u, pd2, S, lds, R, ldr, rr, invr, pnorm, status, blockIdx.x, c1);
 }
 
-__global__ __launch_bounds__(kGW) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
+template <int NT = kGW>
+__global__ __launch_bounds__(NT) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
                                             const double* __restrict__ pd2, const double* __restrict__ pn,
                                             double* __restrict__ v, double* __restrict__ Vc,
                                             double* __restrict__ Vr, const double* __restrict__ Wr, int mcap,
                                             double* __restrict__ pd, double* __restrict__ pdb,
                                             double* __restrict__ tau_a, double* __restrict__ beta_a,
                                             int* __restrict__ status) {
-    qc_body(k, i, nsl, u, pd2, pn, v, Vc, Vr, Wr, mcap, pd, pdb, tau_a, beta_a, status, blockIdx.x);
+    qc_body<NT>(k, i, nsl, u, pd2, pn, v, Vc, Vr, Wr, mcap, pd, pdb, tau_a, beta_a, status, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
+template <int NT = kGW>
+__global__ __launch_bounds__(NT) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
                                             const double* __restrict__ u, const double* __restrict__ pn,
                                             double* __restrict__ Wc, double* __restrict__ Wr,
                                             const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
@@ -647,7 +650,7 @@ __global__ __launch_bounds__(kGW) void k_qd(int k, int i, int nsl, const double*
                                             double* __restrict__ uh, double* __restrict__ pnorm,
                                             const double* __restrict__ tau_a, const double* __restrict__ beta_a) {
     extern __shared__ double dyn[];  // [3 (i + 2)]
-    qd_body(k, i, nsl, v, u, pn, Wc, Wr, Vc, mcap, pd, pdb, X, uh, pnorm, tau_a, beta_a, blockIdx.x, dyn);
+    qd_body<NT>(k, i, nsl, v, u, pn, Wc, Wr, Vc, mcap, pd, pdb, X, uh, pnorm, tau_a, beta_a, blockIdx.x, dyn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1072,21 +1075,22 @@ bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
                    const double* pnext, T* coef, const double* cscale) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap, a.sp,
-                       a.pd, (const double*)nullptr);
+    constexpr int NT = kGWS;
+    hipLaunchKernelGGL((k_qa<PT, NT>), dim3(nsl), dim3(NT), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap,
+                       a.sp, a.pd, (const double*)nullptr);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_qb, dim3(nsl), dim3(kGW), (i + 1) * sizeof(double), st, a.k, i, nsl, a.sp, a.Vc, a.mcap,
+    hipLaunchKernelGGL(k_qb<NT>, dim3(nsl), dim3(NT), (i + 1) * sizeof(double), st, a.k, i, nsl, a.sp, a.Vc, a.mcap,
                        a.pd, a.u, a.pd2, S, lds, R, ldr, a.rr, a.invr, a.pnorm, a.status);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_qc, dim3(nsl), dim3(kGW), 0, st, a.k, i, nsl, a.u, a.pd2, pnext, a.v, a.Vc, a.Vr, a.Wr,
-                       a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status);
+    hipLaunchKernelGGL(k_qc<NT>, dim3(nsl), dim3(NT), 0, st, a.k, i, nsl, a.u, a.pd2, pnext, a.v, a.Vc, a.Vr,
+                       a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_qd, dim3(nsl + nblocks(i + 1, 64)), dim3(kGW), 3 * (i + 2) * sizeof(double), st, a.k, i,
-                       nsl, a.v, a.u, pnext, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
+    hipLaunchKernelGGL(k_qd<NT>, dim3(nsl + nblocks(i + 1, 64)), dim3(NT), 3 * (i + 2) * sizeof(double), st, a.k,
+                       i, nsl, a.v, a.u, pnext, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
                        a.beta);
     RGS_LAUNCH_CHECK();
     if (pnext) {
-        hipLaunchKernelGGL(k_ls3<T>, dim3(nblocks(i + 1, 64)), dim3(kGW), (i + 1) * sizeof(double), st, i + 1,
+        hipLaunchKernelGGL((k_ls3<T, NT>), dim3(nblocks(i + 1, 64)), dim3(NT), (i + 1) * sizeof(double), st, i + 1,
                            i + 1, a.X, a.mcap, a.uh, R, ldr, coef, cscale);
         RGS_LAUNCH_CHECK();
     }

@@ -28,6 +28,10 @@ namespace rgs {
 // ---------------------------------------------------------------------------
 constexpr int kGW = 1024;   // threads of the sketch-space kernels
 constexpr int kGWB = 256;   // threads of the batched sketch-space kernels
+// threads of the single-factorisation column-step kernels: alone on the device
+// the 1024-thread shape is faster (each thread one column group); 256 threads
+// cost ≈ 8 µs per column at k = 2048
+constexpr int kGWS = kGW;
 constexpr int kGQ = 16;     // column groups of the row-parallel products
 constexpr int kBatch = 16;  // loads issued back to back per thread
 constexpr int kSliceBatch = 32;   // the same in the column-parallel slice products

@@ -227,6 +227,31 @@ def test_fp32_qr_srht_ragged_small(gpu_handle):
 # Edge cases
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("sketch,prec", [("srht", "fp64"), ("srht", "fp32"), ("gaussian", "fp32")])
+def test_step1_chunks_on_second_stream(gpu_handle, sketch, prec):
+    """Step 1 (P = Theta W) runs in chunks of columns (64 here: 64 row groups x
+    k = 2048 fp64 partials per column), all after the first on a second stream
+    beside the first columns' steps, each column waiting for its chunk.  RGS
+    column i depends on columns <= i only, so the first chunk's columns equal
+    a call on those columns alone bit for bit; and S R = Theta W holds for
+    every column (a column read from an unfinished chunk would break it)."""
+    rgs = _rgs()
+    n, m, k = (1 << 18) + 123, 150, 2048
+    W = synth.svd_matrix(n, m, 1e-2, tag=71)
+    if prec == "fp32":
+        W = W.astype(np.float32).astype(np.float64)
+    rep, Q, R, S = run_qr(gpu_handle, W, k, sketch, prec, seed=5)
+    rep1, Q1, R1, S1 = run_qr(gpu_handle, W[:, :64], k, sketch, prec, seed=5)
+    assert rep.status == 0 and rep1.status == 0
+    assert np.array_equal(Q[:, :64], Q1) and np.array_equal(R[:64, :64], R1) and np.array_equal(S[:, :64], S1)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    P = rgs.colmajor(k, m, torch.float64)
+    rgs.rgs_sketch_apply(gpu_handle, rgs.qr_desc(n, m, k, sketch=sketch, prec=prec, seed=5), to_dev(W, dt), P)
+    P = to_host(P)
+    err = np.linalg.norm(S @ R - P, axis=0) / np.linalg.norm(P, axis=0)
+    assert err.max() <= (1e-11 if prec == "fp64" else 1e-5), err.max()   # fp32: rounding of q' in step 3
+
+
 def test_breakdown_reports_column(gpu_handle):
     rgs = _rgs()
     n, m, k = 8192, 10, 64
