@@ -197,6 +197,27 @@ def batched_qr_bytes(n, m):
     return n * (m * (m - 1) + 14 * m)
 
 
+def copy_ceiling(torch, dev, reps=7):
+    """Measured HBM ceiling of a plain device copy: (bytes read + written) / time,
+    median over reps of a 1 GiB fp32 copy, timed with events on the current stream."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1000.0)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / sorted(times)[len(times) // 2] / 1e9
+
+
 def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian"), steps=2, warmup=1,
                    gaussian_batch=2048):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
@@ -451,6 +472,8 @@ def main():
     avg_launch_bytes = project_bytes(n, m, 4) / m
     achieved = avg_launch_bytes / (avg_launch_ms / 1000.0) / 1e9
     res, d2, o2 = quality(torch, W32, Q, R, S)
+    copy_gbs = copy_ceiling(torch, dev)
+    log("  device copy ceiling: %.1f GB/s (read + write bytes)" % copy_gbs)
     log("  %.2f ms/QR  %.1f GB/s  (%.1f%% of HBM peak); projection kernel %.1f GB/s; "
         "||W-QR||/||W|| %.2e  ||I-S^TS||_2 %.2e  ||I-Q^TQ||_2 %.2e" %
         (ms, value, 100 * value / HBM_PEAK_GBS, achieved, res, d2, o2))
@@ -466,7 +489,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n, m, k),
                      "kernel": "rgs::" + PROJECT_KERNEL,
-                     "avg_launch_ms": avg_launch_ms, "avg_launch_bytes": avg_launch_bytes},
+                     "avg_launch_ms": avg_launch_ms, "avg_launch_bytes": avg_launch_bytes,
+                     "copy_ceiling": {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+                                      "how": "torch copy_ of 1 GiB fp32, (read + write bytes) / time, median of 7"}},
         "quality": {"backward_error": res, "norm2_I_minus_StS": d2, "norm2_I_minus_QtQ": o2},
     }
     if not args.no_extra:
