@@ -133,27 +133,27 @@ __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ 
 #pragma unroll
             for (int r = 0; r < 4; ++r) ro[r] = rc[r] = T(0);
         } else {
-            double a[4];
+            // every load reads a valid address (a missing neighbour reads the
+            // centre group) and the value is dropped afterwards: loads under a
+            // condition would each be a branch and a wait
+            double a[4], am[4], ap[4], bm[4], bp[4];
             T u[4], ym[4], yp[4], zm[4], zp[4];
+            const bool hxm = x > 0, hxp = x + 4 < nx, hym = y > 0, hyp = y + 1 < ny, hzm = z > 0, hzp = z + 1 < nz;
             ld4_raw(qs, l0, a);
+            ld4_raw(qs, hym ? l0 - nx : l0, am);
+            ld4_raw(qs, hyp ? l0 + nx : l0, ap);
+            ld4_raw(qs, hzm ? l0 - (int64_t)nxy : l0, bm);
+            ld4_raw(qs, hzp ? l0 + (int64_t)nxy : l0, bp);
+            const T xm0 = ld1(hxm ? l0 - 1 : l0), xp0 = ld1(hxp ? l0 + 4 : l0);
+            const T xm = hxm ? xm0 : T(0), xp = hxp ? xp0 : T(0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) u[r] = cv(a[r]);
-            const T xm = x > 0 ? ld1(l0 - 1) : T(0);
-            const T xp = x + 4 < nx ? ld1(l0 + 4) : T(0);
-            auto plane = [&](bool ok, int64_t at, T o[4]) {
-                if (ok) {
-                    ld4_raw(qs, at, a);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) o[r] = cv(a[r]);
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) o[r] = T(0);
-                }
-            };
-            plane(y > 0, l0 - nx, ym);
-            plane(y + 1 < ny, l0 + nx, yp);
-            plane(z > 0, l0 - (int64_t)nxy, zm);
-            plane(z + 1 < nz, l0 + (int64_t)nxy, zp);
+            for (int r = 0; r < 4; ++r) {
+                u[r] = cv(a[r]);
+                ym[r] = hym ? cv(am[r]) : T(0);
+                yp[r] = hyp ? cv(ap[r]) : T(0);
+                zm[r] = hzm ? cv(bm[r]) : T(0);
+                zp[r] = hzp ? cv(bp[r]) : T(0);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 T acc = (T)g.c0 * u[r];
@@ -170,21 +170,26 @@ __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ 
     } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            // as in the vector path: valid addresses always (a row past n reads
+            // row n - 1, a missing neighbour the row itself), values dropped after
             const int64_t l = l0 + r;
-            if (l < n) {
-                const T c = ld1(l);
-                T acc = (T)g.c0 * c;
-                acc = acc + (x > 0 ? (T)g.cxm * ld1(l - 1) : T(0));
-                acc = acc + (x + 1 < nx ? (T)g.cxp * ld1(l + 1) : T(0));
-                acc = acc + (y > 0 ? (T)g.cym * ld1(l - nx) : T(0));
-                acc = acc + (y + 1 < ny ? (T)g.cyp * ld1(l + nx) : T(0));
-                acc = acc + (z > 0 ? (T)g.czm * ld1(l - (int64_t)nxy) : T(0));
-                acc = acc + (z + 1 < nz ? (T)g.czp * ld1(l + (int64_t)nxy) : T(0));
-                ro[r] = acc;
-                rc[r] = c;
-            } else {
-                ro[r] = rc[r] = T(0);
-            }
+            const bool live = l < n;
+            const int64_t lc = live ? l : n - 1;
+            const bool hxm = live && x > 0, hxp = live && x + 1 < nx, hym = live && y > 0,
+                       hyp = live && y + 1 < ny, hzm = live && z > 0, hzp = live && z + 1 < nz;
+            const T c = ld1(lc);
+            const T vxm = ld1(hxm ? lc - 1 : lc), vxp = ld1(hxp ? lc + 1 : lc);
+            const T vym = ld1(hym ? lc - nx : lc), vyp = ld1(hyp ? lc + nx : lc);
+            const T vzm = ld1(hzm ? lc - (int64_t)nxy : lc), vzp = ld1(hzp ? lc + (int64_t)nxy : lc);
+            T acc = (T)g.c0 * c;
+            acc = acc + (hxm ? (T)g.cxm * vxm : T(0));
+            acc = acc + (hxp ? (T)g.cxp * vxp : T(0));
+            acc = acc + (hym ? (T)g.cym * vym : T(0));
+            acc = acc + (hyp ? (T)g.cyp * vyp : T(0));
+            acc = acc + (hzm ? (T)g.czm * vzm : T(0));
+            acc = acc + (hzp ? (T)g.czp * vzp : T(0));
+            ro[r] = live ? acc : T(0);
+            rc[r] = live ? c : T(0);
             if (++x == nx) {
                 x = 0;
                 if (++y == ny) {
