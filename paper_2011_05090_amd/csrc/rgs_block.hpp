@@ -216,14 +216,19 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
     if constexpr (SK == SK_SRHT) {
         int64_t row0[4];
         lane_rows<NW>(blk, row0);
+        // the sign words and the sampled rows are read from valid (clamped)
+        // addresses without a condition, so the loads issue together; a load
+        // under a condition would be a branch and a wait each
+        uint32_t words[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) words[e] = sk.signs[min(row0[e], n - 1) >> 5];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (row0[e] < n) {
-                const uint32_t word = sk.signs[row0[e] >> 5];
                 const int sh = (int)(row0[e] & 31);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if ((word >> (sh + r)) & 1u) v[4 * e + r] = -v[4 * e + r];
+                    if ((words[e] >> (sh + r)) & 1u) v[4 * e + r] = -v[4 * e + r];
             }
         }
         fwht1024_wave<T>(v, lane);
@@ -234,19 +239,25 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
         __syncthreads();
         const uint32_t tb = (uint32_t)(blk * NW);  // tile index of wave 0
 #pragma unroll
-        for (int u = 0; u < kKptMax; ++u) {
-            const int j = t + NT * u;
-            if (u < kpt && j < sk.k) {
-                const uint32_t rho = (uint32_t)sk.rows[j];
-                const uint32_t alpha = rho >> 10, beta = rho & 1023u;
-                T tot = T(0);
+        for (int u0 = 0; u0 < kKptMax; u0 += 4) {
+            if (u0 >= kpt) break;
+            uint32_t rows[4];   // four sampled rows per round trip
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const T z = lds[w * kTile + beta];
-                    tot = (__popc(alpha & (uint32_t)w) & 1) ? tot - z : tot + z;
+            for (int d = 0; d < 4; ++d) rows[d] = (uint32_t)sk.rows[min(t + NT * (u0 + d), sk.k - 1)];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int u = u0 + d, j = t + NT * u;
+                if (u < kpt && j < sk.k) {
+                    const uint32_t alpha = rows[d] >> 10, beta = rows[d] & 1023u;
+                    T tot = T(0);
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        const T z = lds[w * kTile + beta];
+                        tot = (__popc(alpha & (uint32_t)w) & 1) ? tot - z : tot + z;
+                    }
+                    if (__popc(alpha & tb) & 1) tot = -tot;
+                    acc[u] += (PT)tot;
                 }
-                if (__popc(alpha & tb) & 1) tot = -tot;
-                acc[u] += (PT)tot;
             }
         }
         __syncthreads();
