@@ -850,8 +850,10 @@ struct GemmSchedule {
 };
 constexpr GemmSchedule kGemmSchedules[4] = {{64, 0}, {64, 1}, {32, 0}, {32, 1}};
 
-// Streams a batched QR call spreads its factorisations over.
+// Streams a batched QR call spreads its factorisations over, and a batched
+// GMRES call its systems.
 constexpr int kQrShares = 2;
+constexpr int kGmresShares = 2;
 
 // XCDs of the device: the dispatcher sends workgroup b of a launch to XCD
 // b mod kXcds (a launch order built on it only affects cache reuse).
@@ -1478,6 +1480,25 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     const size_t o_mproj = c.take<int64_t>(batch + 1);
     // pair list: at most kXcds x (the blocks of the XCD with the most)
     const size_t o_pairs = c.take<int2>((size_t)kXcds * (gm.proj[gm.count()] + (nmax + kProjRows - 1) / kProjRows));
+    // the running systems of a cycle are dealt out, by n, into two shares that
+    // run their launch sequences on two streams (the handle's and the
+    // auxiliary one): one share's latency-bound sketch-space kernels then run
+    // beside the other's HBM-bound passes.  Each system's arithmetic does not
+    // depend on the split.
+    struct GShare {
+        GmresMaps gm;
+        size_t o_ids = 0, o_mrow = 0, o_mproj = 0, o_pairs = 0;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::vector<int64_t> active;
+    };
+    GShare sh[kGmresShares];
+    for (GShare& g : sh) {
+        g.o_ids = c.take<int>(batch);
+        g.o_mrow = c.take<int64_t>(batch + 1);
+        g.o_mproj = c.take<int64_t>(batch + 1);
+        g.o_pairs = c.take<int2>((size_t)kXcds * (gm.proj[gm.count()] + (nmax + kProjRows - 1) / kProjRows));
+    }
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -1561,36 +1582,45 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     }
     BatchItem* itd = reinterpret_cast<BatchItem*>(A + o_items);
     GmresItem* gid = reinterpret_cast<GmresItem*>(A + o_gitems);
-    const int* d_ids = reinterpret_cast<const int*>(A + o_ids);
-    const int64_t* d_row = reinterpret_cast<const int64_t*>(A + o_mrow);
-    const int64_t* d_proj = reinterpret_cast<const int64_t*>(A + o_mproj);
-    const int2* d_pairs = reinterpret_cast<const int2*>(A + o_pairs);
-    auto upload_maps = [&]() -> bool {
-        return hipMemcpyAsync(A + o_ids, gm.ids.data(), gm.ids.size() * sizeof(int), hipMemcpyHostToDevice, s) ==
-                   hipSuccess &&
-               hipMemcpyAsync(A + o_pairs, gm.pairs.data(), gm.pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
-                              s) == hipSuccess &&
-               hipMemcpyAsync(A + o_mrow, gm.row.data(), gm.row.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                              s) == hipSuccess &&
-               hipMemcpyAsync(A + o_mproj, gm.proj.data(), gm.proj.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                              s) == hipSuccess;
+    // maps of a set of systems (gm at arena offsets o): their ids, 256-row
+    // blocks, projection blocks and (row block, system) pairs
+    struct MapAt {
+        const GmresMaps& gm;
+        const int* ids;
+        const int64_t *row, *proj;
+        const int2* pairs;
     };
-    // launch maps over the running systems: one block per system, 256-row blocks,
+    auto map_at = [&](const GmresMaps& m, size_t oi, size_t orow, size_t oproj, size_t opairs) {
+        return MapAt{m, reinterpret_cast<const int*>(A + oi), reinterpret_cast<const int64_t*>(A + orow),
+                     reinterpret_cast<const int64_t*>(A + oproj), reinterpret_cast<const int2*>(A + opairs)};
+    };
+    auto upload = [&](const GmresMaps& m, size_t oi, size_t orow, size_t oproj, size_t opairs) -> bool {
+        return hipMemcpyAsync(A + oi, m.ids.data(), m.ids.size() * sizeof(int), hipMemcpyHostToDevice, s) ==
+                   hipSuccess &&
+               hipMemcpyAsync(A + opairs, m.pairs.data(), m.pairs.size() * sizeof(int2), hipMemcpyHostToDevice, s) ==
+                   hipSuccess &&
+               hipMemcpyAsync(A + orow, m.row.data(), m.row.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) ==
+                   hipSuccess &&
+               hipMemcpyAsync(A + oproj, m.proj.data(), m.proj.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) ==
+                   hipSuccess;
+    };
+    // launch maps over a set of systems: one block per system, 256-row blocks,
     // projection blocks, sketch slices (+ rb row blocks of the least squares)
-    auto m_sys = [&]() { return BlockMap{nullptr, d_ids, gm.count(), 1}; };
-    auto m_row = [&]() { return BlockMap{d_row, d_ids, gm.count(), 0}; };
-    auto m_proj = [&]() { return BlockMap{d_proj, d_ids, gm.count(), 0}; };
-    auto m_uni = [&](int per) { return BlockMap{nullptr, d_ids, gm.count(), per}; };
-    auto n_row = [&]() { return gm.row[gm.count()]; };
-    auto n_proj = [&]() { return gm.proj[gm.count()]; };
-    auto n_uni = [&](int per) { return (int64_t)per * gm.count(); };
+    auto m_sys = [](const MapAt& M) { return BlockMap{nullptr, M.ids, M.gm.count(), 1}; };
+    auto m_row = [](const MapAt& M) { return BlockMap{M.row, M.ids, M.gm.count(), 0}; };
+    auto m_proj = [](const MapAt& M) { return BlockMap{M.proj, M.ids, M.gm.count(), 0}; };
+    auto m_uni = [](const MapAt& M, int per) { return BlockMap{nullptr, M.ids, M.gm.count(), per}; };
+    auto n_row = [](const MapAt& M) { return M.gm.row[M.gm.count()]; };
+    auto n_proj = [](const MapAt& M) { return M.gm.proj[M.gm.count()]; };
+    auto n_uni = [](const MapAt& M, int per) { return (int64_t)per * M.gm.count(); };
+    const MapAt every = map_at(gm, o_ids, o_mrow, o_mproj, o_pairs);
     if (hipMemcpyAsync(A + o_gitems, gi.data(), gi.size() * sizeof(GmresItem), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        !upload_maps())
+        !upload(gm, o_ids, o_mrow, o_mproj, o_pairs))
         return RGS_EDEVICE;
     // x0 = 0, r0 = b, ||b|| of every system
-    if (!launch_gbatch_zero_x(s, gid, m_row(), n_row()) ||
-        !launch_gbatch_residual(s, gid, m_sys(), gm.count(), m_row(), n_row()))
+    if (!launch_gbatch_zero_x(s, gid, m_row(every), n_row(every)) ||
+        !launch_gbatch_residual(s, gid, m_sys(every), gm.count(), m_row(every), n_row(every)))
         return RGS_EDEVICE;
     std::vector<double> bn((size_t)batch), rn((size_t)batch), hh((size_t)(batch * mcap));
     if (hipMemcpyAsync(bn.data(), A + o_norm, batch * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -1617,55 +1647,59 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     std::vector<int> lim((size_t)batch, 0), stat((size_t)(4 * batch)), usedh((size_t)batch);
     std::vector<int> rows_all;
     std::vector<int64_t> active, prev_active;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    auto drop_graph = [&]() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
+    auto drop_graph = [](GShare& g) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g.exec = nullptr;
+        g.graph = nullptr;
+    };
+    auto drop_graphs = [&]() {
+        for (GShare& g : sh) drop_graph(g);
     };
     const bool dual = sk_kind == SK_GAUSS;   // the two sketches of an Arnoldi step share their draws
     // the dual mat-vec + sketch step: with the bf16 table in row-block-major
     // order (the systems share the table's entries), else system by system
-    auto dual_step = [&](hipStream_t q, int ii) -> bool {
-        return tab ? launch_gbatch_stencil_dual_rows<T, TQ>(q, itd, gid, d_pairs, (int64_t)gm.pairs.size(), ii)
-                   : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(), n_proj(), ii, false);
+    auto dual_step = [&](hipStream_t q, const MapAt& M, int ii) -> bool {
+        return tab ? launch_gbatch_stencil_dual_rows<T, TQ>(q, itd, gid, M.pairs, (int64_t)M.gm.pairs.size(), ii)
+                   : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(M), n_proj(M), ii, false);
     };
-    auto enqueue_cycle = [&](hipStream_t q) -> bool {
-        const int nsl = gm.nsl;
+    auto enqueue_cycle = [&](hipStream_t q, const MapAt& M) -> bool {
+        const int nsl = M.gm.nsl, cnt = M.gm.count();
         const BlockMap none{nullptr, nullptr, 0, 0};
-        if (!launch_gbatch_reset(q, itd, m_sys(), gm.count())) return false;
-        if (!launch_gbatch_cast<T>(q, gid, m_row(), n_row())) return false;
+        if (!launch_gbatch_reset(q, itd, m_sys(M), cnt)) return false;
+        if (!launch_gbatch_cast<T>(q, gid, m_row(M), n_row(M))) return false;
         if (dual) {
-            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), 0) || !dual_step(q, 0))
+            if (!launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(M), n_proj(M), 0) || !dual_step(q, M, 0))
                 return false;
-        } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(), n_proj(), 0)) {
+        } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), 0)) {
             return false;
         }
-        if (!launch_batch_column<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(nsl + 1), n_uni(nsl + 1), none, 0, 0))
+        if (!launch_batch_column<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + 1), n_uni(M, nsl + 1), none,
+                                    0, 0))
             return false;
-        if (!launch_gbatch_givens_init(q, itd, gid, m_sys(), gm.count())) return false;
+        if (!launch_gbatch_givens_init(q, itd, gid, m_sys(M), cnt)) return false;
         for (int64_t i = 1; i <= restart; ++i) {
             const int ii = (int)i;
             const int rbl = (int)((i + 63) / 64);       // row blocks of the i x i solve
             const int rbq = (int)((i + 1 + 63) / 64);   // column-step blocks beyond the slices
             if (dual) {
-                if (!launch_gbatch_ls<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(rbl), n_uni(rbl), ii, 1) ||
-                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(), n_proj(), ii) || !dual_step(q, ii))
+                if (!launch_gbatch_ls<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl), n_uni(M, rbl), ii, 1) ||
+                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(M), n_proj(M), ii) ||
+                    !dual_step(q, M, ii))
                     return false;
             } else {
-                if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(), n_proj(), ii)) return false;
-                if (!launch_gbatch_ls<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(rbl), n_uni(rbl), ii, 0)) return false;
-                if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(), n_proj(), ii))
+                if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii)) return false;
+                if (!launch_gbatch_ls<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl), n_uni(M, rbl), ii, 0))
+                    return false;
+                if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii))
                     return false;
             }
-            if (!launch_batch_column<T>(q, itd, m_uni(nsl), n_uni(nsl), m_uni(nsl + rbq), n_uni(nsl + rbq), none, 0,
-                                        ii))
+            if (!launch_batch_column<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + rbq),
+                                        n_uni(M, nsl + rbq), none, 0, ii))
                 return false;
-            if (!launch_gbatch_givens(q, itd, gid, m_sys(), gm.count(), ii)) return false;
+            if (!launch_gbatch_givens(q, itd, gid, m_sys(M), cnt, ii)) return false;
         }
-        return launch_gbatch_finish<TQ>(q, itd, gid, m_sys(), gm.count(), m_row(), n_row());
+        return launch_gbatch_finish<TQ>(q, itd, gid, m_sys(M), cnt, m_row(M), n_row(M));
     };
     rgs_status fail = RGS_OK;
     for (int64_t cycle = 0;; ++cycle) {
@@ -1684,64 +1718,101 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         // the cycle's sketch: sketch_id 2 (+ cycle unless reused), instance 0, per-system n
         if (cycle == 0 || !d->reuse_theta) {
             const uint32_t sid = d->reuse_theta ? 2u : (uint32_t)(2 + cycle);
+            bool ok = true;
             if (sk_kind == SK_SRHT) rows_all.assign((size_t)(k * batch), 0);
             for (int64_t b : active) {
                 bi[b].sk.sid = sid;
                 if (sk_kind == SK_SRHT) {
-                    if (!launch_srht_signs(s, const_cast<uint32_t*>(bi[b].sk.signs), (ns[b] + 31) / 32, bi[b].sk))
-                        return RGS_EDEVICE;
+                    ok = ok && launch_srht_signs(s, const_cast<uint32_t*>(bi[b].sk.signs), (ns[b] + 31) / 32,
+                                                 bi[b].sk);
                     std::vector<int> rows;
                     srht_rows_host(srht_order(ns[b]), (int)k, bi[b].sk, rows);
                     std::copy(rows.begin(), rows.end(), rows_all.begin() + b * k);
                 }
             }
-            if (sk_kind == SK_SRHT && hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int),
-                                                     hipMemcpyHostToDevice, s) != hipSuccess)
+            ok = ok && (sk_kind != SK_SRHT || hipMemcpyAsync(A + o_rows, rows_all.data(), rows_all.size() * sizeof(int),
+                                                             hipMemcpyHostToDevice, s) == hipSuccess);
+            ok = ok && (!tab || launch_theta_table(s, make_sketch(SK_GAUSS, k, d->seed, sid, 0), nmax,
+                                                   reinterpret_cast<uint16_t*>(A + o_table)));
+            ok = ok && hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
+                                      s) == hipSuccess;
+            if (!ok) {
+                drop_graphs();
                 return RGS_EDEVICE;
-            if (tab && !launch_theta_table(s, make_sketch(SK_GAUSS, k, d->seed, sid, 0), nmax,
-                                           reinterpret_cast<uint16_t*>(A + o_table)))
-                return RGS_EDEVICE;
-            if (hipMemcpyAsync(A + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s) !=
-                hipSuccess)
-                return RGS_EDEVICE;
+            }
         }
         if (active != prev_active) {
-            build_gmres_maps(gm, active, ns, k);
-            if (!upload_maps()) return RGS_EDEVICE;
-            drop_graph();
-            prev_active = active;
-        }
-        if (hipMemcpyAsync(A + o_limit, lim.data(), batch * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
-            return RGS_EDEVICE;
-        if (use_graph) {
-            if (!exec) {
-                if (!h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
-                    return RGS_EDEVICE;
-                if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return RGS_EDEVICE;
-                const bool ok = enqueue_cycle(h->capture);
-                const bool ended = hipStreamEndCapture(h->capture, &graph) == hipSuccess;
-                if (!ok || !ended || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-                    drop_graph();
+            // deal the running systems, by n (descending), into the shares
+            std::vector<int64_t> by_n(active);
+            std::stable_sort(by_n.begin(), by_n.end(), [&](int64_t a, int64_t b) { return ns[a] > ns[b]; });
+            for (GShare& g : sh) g.active.clear();
+            for (size_t q = 0; q < by_n.size(); ++q) sh[q % kGmresShares].active.push_back(by_n[q]);
+            for (GShare& g : sh) {
+                std::sort(g.active.begin(), g.active.end());
+                drop_graph(g);
+                if (g.active.empty()) continue;
+                build_gmres_maps(g.gm, g.active, ns, k);
+                if (!upload(g.gm, g.o_ids, g.o_mrow, g.o_mproj, g.o_pairs)) {
+                    drop_graphs();
                     return RGS_EDEVICE;
                 }
             }
-            if (hipGraphLaunch(exec, s) != hipSuccess) {
-                drop_graph();
-                return RGS_EDEVICE;
-            }
-        } else if (!enqueue_cycle(s)) {
+            prev_active = active;
+        }
+        if (hipMemcpyAsync(A + o_limit, lim.data(), batch * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) {
+            drop_graphs();
             return RGS_EDEVICE;
         }
-        if (hipMemcpyAsync(stat.data(), A + o_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, s) !=
+        const bool two = !sh[1].active.empty();
+        if (two && (ensure_aux(h) != RGS_OK || hipEventRecord(h->fork_ev, s) != hipSuccess ||
+                    hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)) {
+            drop_graphs();
+            return RGS_EDEVICE;
+        }
+        bool ok = true;
+        for (int si = 0; si < kGmresShares && ok; ++si) {
+            GShare& g = sh[si];
+            if (g.active.empty()) continue;
+            const hipStream_t q = si == 0 ? s : h->aux;
+            const MapAt M = map_at(g.gm, g.o_ids, g.o_mrow, g.o_mproj, g.o_pairs);
+            if (use_graph) {
+                if (!g.exec) {
+                    if (!h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess) {
+                        ok = false;
+                        break;
+                    }
+                    if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) {
+                        ok = false;
+                        break;
+                    }
+                    const bool enq = enqueue_cycle(h->capture, M);
+                    const bool ended = hipStreamEndCapture(h->capture, &g.graph) == hipSuccess;
+                    if (!enq || !ended || hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) {
+                        ok = false;
+                        break;
+                    }
+                }
+                ok = hipGraphLaunch(g.exec, q) == hipSuccess;
+            } else {
+                ok = enqueue_cycle(q, M);
+            }
+        }
+        if (two && (hipEventRecord(h->join_ev, h->aux) != hipSuccess ||
+                    hipStreamWaitEvent(s, h->join_ev, 0) != hipSuccess))
+            ok = false;
+        if (!ok ||
+            hipMemcpyAsync(stat.data(), A + o_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
             hipMemcpyAsync(usedh.data(), A + o_used, batch * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(rn.data(), A + o_norm, batch * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(hh.data(), A + o_hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) {
-            drop_graph();
+            (void)hipStreamSynchronize(s);
+            if (h->aux) (void)hipStreamSynchronize(h->aux);
+            drop_graphs();
             return RGS_EDEVICE;
         }
         if (hipStreamSynchronize(s) != hipSuccess) {
-            drop_graph();
+            drop_graphs();
             return RGS_EDEVICE;
         }
         for (int64_t b : active) {
@@ -1763,7 +1834,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
             }
         }
     }
-    drop_graph();
+    drop_graphs();
     const auto t1 = std::chrono::steady_clock::now();
     for (int64_t b = 0; b < batch; ++b) {
         if (item_status) item_status[b] = res[b];
