@@ -299,7 +299,7 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
 // applied to both later, when it is known).  Same row mapping and summation
 // order per vector as stencil_sketch_body.
 // TAB: the entries come from the bf16 table (SK_TABLE), 8 rows per load.
-template <typename TQ, typename T, bool TAB = false>
+template <typename TQ, typename T, bool TAB = false, int DEPTH = kTabDepth>
 __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
                                                   T* __restrict__ t_out, const SketchArgs& sk,
                                                   T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
@@ -329,19 +329,19 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
     if constexpr (TAB) {
         const int no = rem >= RB ? RB / 8 : (int)((rem + 7) / 8);
         const int64_t o0 = blk * (RB / 8);
-        // per sketch row, the block's table groups with kTabDepth loads in flight
+        // per sketch row, the block's table groups with DEPTH loads in flight
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) {
             const int j = threadIdx.x + NT * u;
             if (u < kpt && j < sk.k) {
                 T sx = ax[u], st = at[u];
-                for (int o = 0; o < no; o += kTabDepth) {
-                    tabw_t w[kTabDepth];
+                for (int o = 0; o < no; o += DEPTH) {
+                    tabw_t w[DEPTH];
 #pragma unroll
-                    for (int d = 0; d < kTabDepth; ++d)
+                    for (int d = 0; d < DEPTH; ++d)
                         if (o + d < no) w[d] = tab_load(sk.table, sk.k, o0 + o + d, j);
 #pragma unroll
-                    for (int d = 0; d < kTabDepth; ++d) {
+                    for (int d = 0; d < DEPTH; ++d) {
                         if (o + d < no) {
                             T z[8];
                             tab_unpack<T>(w[d], z);
@@ -549,7 +549,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     T* __restrict__ part_t, const int* __restrict__ status) {
     __shared__ T lds[2 * kProjWaves * kTile];
     RGS_EXIT_IF_STOPPED(status);
-    stencil_dual_body<TQ, T, TAB>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
+    // one system: k <= 512 threads stream the table with 4 loads in flight
+    // (16 measured slower here; the batched row-block launch uses 16)
+    stencil_dual_body<TQ, T, TAB, 4>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
