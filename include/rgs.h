@@ -23,7 +23,12 @@
  *                                    step 3 computes in fp32
  *     R, S, P, b, x and histories are always double.
  *   - Work is ordered on the handle's stream.  Calls that return a report
- *     synchronise that stream before returning.
+ *     synchronise that stream before returning.  Some calls also run part of
+ *     their work on an auxiliary stream the handle creates (default
+ *     priority): rgs_qr (step-1 chunks after the first), rgs_qr_batched and
+ *     rgs_gmres_batched (the second half of the batch).  That work is forked
+ *     from the handle's stream and joined back into it with events within
+ *     the call, so the ordering on the handle's stream is unchanged.
  *   - Errors are negative rgs_status codes; nothing is thrown across the ABI.
  *     Argument errors are detected before any device work is enqueued.
  *   - A handle is not thread-safe: use one handle per host thread.
@@ -201,7 +206,7 @@ const char *rgs_status_string(rgs_status s);
  * failure.  The handle owns all scratch memory. */
 rgs_status rgs_create(rgs_handle **h, int device, rgs_stream stream);
 
-/* Release the handle and its scratch (synchronises its stream first). */
+/* Release the handle and its scratch (synchronises its streams first). */
 rgs_status rgs_destroy(rgs_handle *h);
 
 /* Re-bind the handle to another stream of the same device. */
