@@ -151,7 +151,7 @@ def quality(torch, W, Q, R, S):
     return float(res), float(d2), float(o2)
 
 
-def cpu_baseline(n=1 << 21, m=48, k=2048):
+def cpu_baseline(n=1 << 21, m=64, k=2048):
     """The oracle (fp32 model, SRHT) on a bounded sample, on the host cores."""
     import numpy as np
     import synth
