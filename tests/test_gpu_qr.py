@@ -295,6 +295,40 @@ def test_invalid_arguments_rejected(gpu_handle):
                    rgs.colmajor(200, 4, dt))
 
 
+@pytest.mark.parametrize("n,m,k", [(100, 0, 8), (0, 1, 1), (0, 0, 0)])
+def test_empty_inputs_rejected(gpu_handle, n, m, k):
+    """An empty factorisation (no columns, or no rows) is an argument error,
+    reported before any device work."""
+    rgs = _rgs()
+    dt = torch.float64
+    with pytest.raises(rgs.RgsError) as e:
+        rgs.rgs_qr(gpu_handle, rgs.qr_desc(n, m, k, prec="fp64"), rgs.colmajor(n, m, dt), rgs.colmajor(n, m, dt),
+                   rgs.colmajor(m, m, dt), rgs.colmajor(k, m, dt))
+    assert e.value.status == rgs.RGS_EINVAL
+
+
+def test_empty_batches_rejected(gpu_handle):
+    rgs = _rgs()
+    with pytest.raises(rgs.RgsError) as e:
+        rgs.rgs_qr_batched(gpu_handle, [], sketch="srht", prec="fp32")
+    assert e.value.status == rgs.RGS_EINVAL
+    with pytest.raises(rgs.RgsError) as e:
+        rgs.rgs_gmres_batched(gpu_handle, [], rgs.gmres_desc(10, 32, 1e-6, sketch="srht", prec="fp32"))
+    assert e.value.status == rgs.RGS_EINVAL
+
+
+def test_one_row_one_column(gpu_handle):
+    """n = m = k = 1: the factorisation is W = sign * |W|: q = w / |w| exactly,
+    R = |w| (the sketch of one entry is +-w)."""
+    rgs = _rgs()
+    for sketch in ("gaussian", "srht", "rademacher"):
+        W = np.array([[-3.25]])
+        rep, Q, R, S = run_qr(gpu_handle, W, 1, sketch, "fp64")
+        assert rep.status == 0
+        assert R[0, 0] > 0 and abs(abs(S[0, 0]) - 1.0) <= 1e-15
+        assert abs(Q[0, 0] * R[0, 0] - W[0, 0]) <= 1e-15 * abs(W[0, 0])
+
+
 @pytest.mark.parametrize("sketch", ["srht", "gaussian", "rademacher"])
 def test_bitwise_deterministic(gpu_handle, sketch):
     W = synth.svd_matrix(20000, 32, 1e-4, tag=18)
