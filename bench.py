@@ -319,7 +319,7 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
 
 
 def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=(25, 50, 100, 150, 200, 250, 300),
-              eps_star=0.05):
+              eps_star=0.05, classical=True):
     """The synthetic-function experiment of Sec. 5.1 at the paper's size: W_ij =
     f_mu_j(x_i) = sin(10 (mu_j + x_i)) / (cos(100 (mu_j - x_i)) + 1.1) on n = 10^6
     evenly spaced x in [0, 1] and m = 300 evenly spaced mu in [0, 1], fp32 W,
@@ -327,9 +327,11 @@ def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=
     k in {1500, 5000}.  For prefixes W_i (factorised with the a-posteriori
     certificate, Phi of Theta's size, eps* = 0.05) it reports what the paper
     plots: cond(Q_i), cond(S_i), ||W_i - Q_i R_i|| / ||W_i||, the embedding
-    distortion omega of Theta on range(Q_i) and its bound omega_bar.  The
-    paper's classical comparison methods and its unique-precision RGS are not
-    run.  Metrics are computed in fp64 on the device (measurement code)."""
+    distortion omega of Theta on range(Q_i) and its bound omega_bar.  CGS runs
+    as RGS with Theta = I and one Richardson sweep (beside two sweeps and the
+    Householder solve with Theta = I); MGS, CGS2 and the unique-precision RGS
+    are not run.  Metrics are computed in fp64 on the
+    device (measurement code)."""
     import numpy as np
     W = rgs.colmajor(n, m, torch.float32)
     W.copy_(torch.from_numpy(synth.f_mu_matrix(n, m, np.float64)).to("cuda"))
@@ -367,6 +369,41 @@ def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=
                 (k, i, cond_q, cond_s, err, omega, obar, 1000 * rep.seconds))
             del Q, R, S, Q64, G, C, U, TU
         out["k%d" % k] = rows
+    # Theta = I (k = n): with one Richardson sweep of the least squares the
+    # column step is classical Gram-Schmidt (fp32 projection, inner products in
+    # fp64), the paper's CGS; two sweeps refine the coefficients only (CGS2 in
+    # exact arithmetic, but the rounded projection is not projected again);
+    # the Householder solve is Gram-Schmidt with an exact least squares.
+    # Column i depends on columns <= i only, so one factorisation of all m
+    # columns gives every prefix.
+    # (about 30 s each: the sketch space is n-dimensional, so they run with
+    # --only sec51, not in the default run)
+    for name, sweeps in (("cgs", 1), ("identity_richardson2", 2), ("identity_householder", 0)) if classical else ():
+        Q = rgs.colmajor(n, m, torch.float32)
+        R = rgs.colmajor(m, m, torch.float64)
+        S = rgs.colmajor(n, m, torch.float64)
+        d = rgs.qr_desc(n, m, n, sketch="identity", prec="fp32", ls_sweeps=sweeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = rgs.rgs_qr(h, d, W, Q, R, S)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows = []
+        for i in prefixes:
+            if rep.status != 0 and i > rep.failed_column:
+                break
+            Q64 = Q[:, :i].double()
+            ev = torch.linalg.eigvalsh(Q64.T @ Q64)
+            cond_q = float(torch.sqrt(ev[-1] / ev[0])) if float(ev[0]) > 0 else float("inf")
+            err = float(torch.linalg.norm(W64[:, :i] - Q64 @ R[:i, :i]) / torch.linalg.norm(W64[:, :i]))
+            rows.append({"i": i, "cond_Q": cond_q, "error": err})
+            log("  sec5.1 %s i=%d: cond(Q) %.3e err %.2e" % (name, i, cond_q, err))
+            del Q64
+        out[name] = {"status": rep.status, "failed_column": rep.failed_column, "seconds": dt, "rows": rows,
+                     "precision": "fp32 projection, fp64 least squares, Theta = I, %s" %
+                                  ("%d Richardson sweep%s" % (sweeps, "" if sweeps == 1 else "s") if sweeps
+                                   else "Householder least squares")}
+        del Q, R, S
     del W, W64
     return out
 
@@ -572,7 +609,7 @@ def main():
         out.setdefault("extra", {})["rgmres_convdiff_192"] = gmres_leg(rgs, torch, synth, h)
     if not args.no_extra:
         log("Sec. 5.1 synthetic functions, n = 10^6, m = 300")
-        out.setdefault("extra", {})["sec51_functions"] = sec51_leg(rgs, torch, synth, h)
+        out.setdefault("extra", {})["sec51_functions"] = sec51_leg(rgs, torch, synth, h, classical=False)
     if not args.no_batched:
         log("batched RGS QR (bf16 Q)")
         out["extra"]["batched_qr_2048"] = batched_qr_leg(rgs, torch, synth, h)
