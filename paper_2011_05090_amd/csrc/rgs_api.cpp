@@ -423,14 +423,21 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
         hipStreamSynchronize(s) != hipSuccess)
         return RGS_EDEVICE;
 
-    // host: Cholesky factors of both Gram matrices and their inverses; cond(Phi Q) alongside
+    // host: Cholesky factors of both Gram matrices and their inverses; cond(Phi Q)
+    // on a third thread that runs on through the second device phase
     std::vector<double> Tq(Gh.begin(), Gh.begin() + mm), Tw(Gh.begin() + mm, Gh.end());
     bool ok[2] = {false, false}, ok_c = false;
     double gq_min = NAN, gq_max = NAN;
     std::vector<double> Tinv(2 * mm);
-    std::thread tc([&]() {
+    std::thread tc([&]() {   // reads Gh, which nothing writes from here on
         ok_c = dense::sym_eig_extremes(std::vector<double>(Gh.begin(), Gh.begin() + mm), mi, gq_min, gq_max);
     });
+    struct Joiner {
+        std::thread& t;
+        ~Joiner() {
+            if (t.joinable()) t.join();
+        }
+    } join_tc{tc};   // every return below waits for it
     both([&](int b) {
         std::vector<double>& Tm = b == 0 ? Tq : Tw;
         ok[b] = dense::cholesky_upper(Tm, mi);
@@ -439,8 +446,6 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
             std::copy(inv.begin(), inv.end(), Tinv.begin() + b * mm);
         }
     });
-    tc.join();
-    if (ok_c && gq_min > 0) rep->cert_cond_phi_q = std::sqrt(gq_max / gq_min);
     if (hipMemcpyAsync(Md, Tinv.data(), 2 * mm * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return RGS_EDEVICE;
     if (!launch_dgemm(s, false, ki, mi, mi, thQ, k, Md, m, Y, k) ||
@@ -467,6 +472,8 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
         rep->cert_smin_w = std::sqrt(std::max(lo[1], 0.0));
         rep->cert_smax_w = std::sqrt(std::max(hi[1], 0.0));
     }
+    tc.join();
+    if (ok_c && gq_min > 0) rep->cert_cond_phi_q = std::sqrt(gq_max / gq_min);
     return RGS_OK;
 }
 

@@ -9,17 +9,29 @@
 namespace rgs {
 namespace dense {
 
+namespace {
+
+// sum_p a[p] b[p] over p < n in eight interleaved partial sums: independent
+// chains keep the adders busy where one running sum waits on each add.
+double dot(const double* a, const double* b, int n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int p = 0;
+    for (; p + 8 <= n; p += 8)
+        for (int u = 0; u < 8; ++u) s[u] += a[p + u] * b[p + u];
+    for (; p < n; ++p) s[p & 7] += a[p] * b[p];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+}  // namespace
+
 bool cholesky_upper(std::vector<double>& G, int m) {
     for (int j = 0; j < m; ++j) {
         double* gj = G.data() + (size_t)j * m;
         for (int i = 0; i < j; ++i) {
             const double* ti = G.data() + (size_t)i * m;
-            double s = gj[i];
-            for (int p = 0; p < i; ++p) s -= ti[p] * gj[p];
-            gj[i] = s / ti[i];
+            gj[i] = (gj[i] - dot(ti, gj, i)) / ti[i];
         }
-        double d = gj[j];
-        for (int p = 0; p < j; ++p) d -= gj[p] * gj[p];
+        const double d = gj[j] - dot(gj, gj, j);
         if (!(d > 0.0) || !std::isfinite(d)) return false;
         gj[j] = std::sqrt(d);
         for (int i = j + 1; i < m; ++i) gj[i] = 0.0;
@@ -63,14 +75,12 @@ int sturm_count(const std::vector<double>& d, const std::vector<double>& e2, dou
 
 bool sym_eig_extremes(std::vector<double> A, int m, double& lmin, double& lmax) {
     for (int j = 0; j < m; ++j)
-        for (int i = j; i < m; ++i) {
-            const double v = A[i + (size_t)j * m];
-            if (!std::isfinite(v)) return false;
-            A[j + (size_t)i * m] = v;   // mirror the lower triangle
-        }
+        for (int i = j; i < m; ++i)
+            if (!std::isfinite(A[i + (size_t)j * m])) return false;
     std::vector<double> d(m), e(std::max(m - 1, 0), 0.0), v(m), p(m);
-    // Householder reduction: step j zeroes column j below the subdiagonal and
-    // applies the reflector to both sides of the trailing block.
+    // Householder reduction on the lower triangle only: step j zeroes column j
+    // below the subdiagonal and applies the reflector to both sides of the
+    // trailing block (a symmetric rank-2 update of its lower triangle).
     for (int j = 0; j + 2 < m; ++j) {
         const int r = m - j - 1;
         double* x = A.data() + (size_t)j * m + j + 1;
@@ -84,26 +94,27 @@ bool sym_eig_extremes(std::vector<double> A, int m, double& lmin, double& lmax) 
         const double alpha = x[0] > 0 ? -nrm : nrm;
         for (int i = 0; i < r; ++i) v[i] = x[i];
         v[0] -= alpha;
-        double vv = 0.0;
-        for (int i = 0; i < r; ++i) vv += v[i] * v[i];
+        const double vv = dot(v.data(), v.data(), r);
         e[j] = alpha;
         if (vv == 0.0) continue;
         const double tau = 2.0 / vv;
         double* B = A.data() + (size_t)(j + 1) * m + (j + 1);   // trailing block, leading dimension m
+        // p = tau B v from the stored lower triangle: column c of it gives
+        // p[c] (as a row of B, by symmetry) and adds to p[c+1..r)
         for (int i = 0; i < r; ++i) p[i] = 0.0;
         for (int c = 0; c < r; ++c) {
-            const double vc = tau * v[c];
             const double* bc = B + (size_t)c * m;
-            for (int i = 0; i < r; ++i) p[i] += bc[i] * vc;
+            const double vc = v[c];
+            p[c] += bc[c] * vc + dot(bc + c + 1, v.data() + c + 1, r - c - 1);
+            for (int i = c + 1; i < r; ++i) p[i] += bc[i] * vc;
         }
-        double pv = 0.0;
-        for (int i = 0; i < r; ++i) pv += p[i] * v[i];
-        const double K = 0.5 * tau * pv;
+        for (int i = 0; i < r; ++i) p[i] *= tau;
+        const double K = 0.5 * tau * dot(p.data(), v.data(), r);
         for (int i = 0; i < r; ++i) p[i] -= K * v[i];   // w = p - K v
-        for (int c = 0; c < r; ++c) {
+        for (int c = 0; c < r; ++c) {   // B -= v w^T + w v^T, lower triangle
             double* bc = B + (size_t)c * m;
             const double vc = v[c], wc = p[c];
-            for (int i = 0; i < r; ++i) bc[i] -= v[i] * wc + p[i] * vc;
+            for (int i = c; i < r; ++i) bc[i] -= v[i] * wc + p[i] * vc;
         }
     }
     if (m >= 2) {

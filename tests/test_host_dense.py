@@ -75,7 +75,7 @@ def _sym(m, tag, spread=1.0):
 
 
 @pytest.mark.parametrize("m,spread,tag", [(1, 1.0, 0), (2, 1.0, 1), (3, 0.5, 2), (17, 1e-6, 3), (100, 0.8, 4),
-                                          (64, 3.0, 5)])
+                                          (64, 3.0, 5), (257, 0.9, 8)])
 def test_eig_extremes_match_lapack(driver, m, spread, tag):
     A = _sym(m, tag, spread)
     if tag == 5:
@@ -107,7 +107,7 @@ def test_eig_special_cases(driver):
     assert ok == 0
 
 
-@pytest.mark.parametrize("m", [1, 7, 50])
+@pytest.mark.parametrize("m", [1, 7, 50, 203])
 def test_cholesky_and_inverse(driver, m):
     rng = _rng(10 + m)
     Z = rng.standard_normal((3 * m, m))
