@@ -999,19 +999,34 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c)
                 for (int64_t jt = 0; jt < (kmax + 127) / 128; ++jt)
                     out.push_back(GemmUnit{first, tcnt, (int)blk, (int)jt});
         };
-        for (int64_t q = 0; q < cnt; ++q)   // step 1: 64-column tiles of each item's W
-            for (int64_t c0 = 0; c0 < it_of(q).m; c0 += 64) {
-                const int first = (int)g.g_cols.size(), tcnt = (int)std::min<int64_t>(64, it_of(q).m - c0);
-                for (int c2 = 0; c2 < tcnt; ++c2) g.g_cols.push_back(make_int2((int)q, (int)(c0 + c2)));
-                add_tile(g.g_units_p, first, tcnt, kGemmRowsP);
-            }
+        // Items in a tile share its draws of Z and its MFMA work, which runs over
+        // the largest k (in steps of 32 sketch rows: one wave each) and the largest
+        // n of the tile: tiles are cut from an order by k class, then n (descending)
+        auto by_class = [&](int64_t kstep) {
+            return [&, kstep](int64_t x, int64_t y) {
+                const rgs_qr_item &a = it_of(x), &b = it_of(y);
+                const int64_t ca = (a.k + kstep - 1) / kstep, cb = (b.k + kstep - 1) / kstep;
+                return ca != cb ? ca > cb : a.n > b.n;
+            };
+        };
+        {   // step 1: the columns of every W in tiles of kGemmTileP that may span items
+            std::vector<int64_t> ord((size_t)cnt);
+            for (int64_t q = 0; q < cnt; ++q) ord[q] = q;
+            std::stable_sort(ord.begin(), ord.end(), by_class(32));
+            const int first0 = (int)g.g_cols.size();
+            for (int64_t q : ord)
+                for (int64_t c2 = 0; c2 < it_of(q).m; ++c2) g.g_cols.push_back(make_int2((int)q, (int)c2));
+            const int total = (int)g.g_cols.size() - first0;
+            for (int t0 = 0; t0 < total; t0 += kGemmTileP)
+                add_tile(g.g_units_p, first0 + t0, std::min(kGemmTileP, total - t0), kGemmRowsP);
+        }
         std::vector<int> act;
         for (int w = 0; w < 2; ++w) g.g_at[w].assign((size_t)g.max_m + 1, 0);
-        for (int64_t i = 0; i < g.max_m; ++i) {   // step 4 of column i: active items ordered by n
+        for (int64_t i = 0; i < g.max_m; ++i) {   // step 4 of column i: active items by k class of 128, then n
             const int a = g.active[i];
             act.resize((size_t)a);
             for (int q = 0; q < a; ++q) act[q] = q;
-            std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return it_of(x).n > it_of(y).n; });
+            std::stable_sort(act.begin(), act.end(), by_class(128));
             const int base = (int)g.g_cols.size();
             for (int q = 0; q < a; ++q) g.g_cols.push_back(make_int2(act[q], (int)i));
             for (int w = 0; w < 2; ++w) {
@@ -1176,7 +1191,7 @@ struct QrGroupLauncher {
         if (!launch_batch_init(s, itd, nb, g.max_m * g.max_m)) return RGS_EDEVICE;
         // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
         if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, reinterpret_cast<const GemmUnit*>(A + g.o_gunits_p),
-                                                       (int)g.g_units_p.size(), d_cols, (int)kGemmRowsP, 64))
+                                                       (int)g.g_units_p.size(), d_cols, (int)kGemmRowsP, kGemmTileP))
             return RGS_EDEVICE;
         if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, g.pre_sign[nb],
                                       BlockMap{d_part, nullptr, nb, 0}, g.pre_part[nb],

@@ -358,7 +358,8 @@ __global__ __launch_bounds__(kWG) void kb_gauss_cols(const BatchItem* __restrict
 // B operand for column x = L % 32 of each 32-column sub-tile is the same 4 rows
 // of that column; the next 8 rows are loaded while the current ones are used.
 // Accumulator t of the 32x32 result is sketch row 8 (t / 4) + 4 kk + t % 4 of
-// column L % 32.
+// column L % 32.  A wave whose 32 sketch rows all lie at or past the largest
+// k of the unit's items has nothing to store and returns at once.
 //   STEP4: the columns are column i of the listed items' Q (step 4 of the
 //   column step; partial of chunk blk -> part[blk k_b + j]);
 //   otherwise columns of W (step 1; partial of chunk blk of column c ->
@@ -404,16 +405,16 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int jr = lane & 31, kk = lane >> 5;
     const int j = un.jt * 128 + wave * 32 + jr;   // this lane's sketch row (A operand)
-    const TB* col[2];
-    int64_t nb[2];
-    bool vec[2];
+    const TB* col[NSUB];
+    int64_t nb[NSUB];
+    bool vec[NSUB];
 #pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {   // B operand: column x = lane % 32 of each sub-tile (NSUB of them)
+    for (int s2 = 0; s2 < NSUB; ++s2) {   // B operand: column x = lane % 32 of each 32-column sub-tile
         const int c = s2 * 32 + jr;
         col[s2] = nullptr;
         nb[s2] = 0;
         vec[s2] = false;
-        if (s2 < NSUB && c < un.count) {
+        if (c < un.count) {
             const int2 ic = cols[un.first + c];
             const BatchItem& it = items[ic.x];
             col[s2] = STEP4 ? static_cast<const TB*>(it.Q) + (int64_t)ic.y * it.ldq
@@ -429,31 +430,35 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
         kmax = max(kmax, it.k);
         nmax = max(nmax, it.n);
     }
+    if (un.jt * 128 + wave * 32 >= kmax) return;   // wave-uniform; the kernel has no barrier
     const SketchArgs& sk = items[cols[un.first].x].sk;   // seed, sketch id, instance: shared
     const int64_t r_begin = (int64_t)un.blk * rows;
     const int64_t r_end = min(r_begin + (int64_t)rows, nmax);
-    f32x16 acc0 = {0}, acc1 = {0};
-    float b0[4], b1[4] = {0.f, 0.f, 0.f, 0.f};
-    ld4_rows(col[0], r_begin + 4 * kk, col[0] ? nb[0] : 0, vec[0], b0);
-    if (NSUB > 1) ld4_rows(col[1], r_begin + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
+    f32x16 acc[NSUB];
+    float b[NSUB][4];
+#pragma unroll
+    for (int s2 = 0; s2 < NSUB; ++s2) {
+        acc[s2] = f32x16{0};
+        ld4_rows(col[s2], r_begin + 4 * kk, col[s2] ? nb[s2] : 0, vec[s2], b[s2]);
+    }
     for (int64_t r = r_begin; r < r_end; r += 8) {
         float z[4] = {0.f, 0.f, 0.f, 0.f};
         if (j < kmax) gauss4((uint32_t)(r / 4 + kk), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
-        float c0[4], c1[4] = {0.f, 0.f, 0.f, 0.f};
+        float c[NSUB][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            c0[t] = b0[t];
-            c1[t] = b1[t];
-        }
+        for (int s2 = 0; s2 < NSUB; ++s2)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) c[s2][t] = b[s2][t];
         if (r + 8 < r_end) {   // next 8 rows while these are used
-            ld4_rows(col[0], r + 8 + 4 * kk, col[0] ? nb[0] : 0, vec[0], b0);
-            if (NSUB > 1) ld4_rows(col[1], r + 8 + 4 * kk, col[1] ? nb[1] : 0, vec[1], b1);
+#pragma unroll
+            for (int s2 = 0; s2 < NSUB; ++s2)
+                ld4_rows(col[s2], r + 8 + 4 * kk, col[s2] ? nb[s2] : 0, vec[s2], b[s2]);
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c0[t], acc0, 0, 0, 0);
-            if (NSUB > 1) acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c1[t], acc1, 0, 0, 0);
-        }
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int s2 = 0; s2 < NSUB; ++s2)
+                acc[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[t], c[s2][t], acc[s2], 0, 0, 0);
     }
 #pragma unroll
     for (int s2 = 0; s2 < NSUB; ++s2) {
@@ -467,7 +472,7 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int jj = un.jt * 128 + wave * 32 + 8 * (t / 4) + 4 * kk + (t % 4);
-            if (jj < it.k) out[jj] = s2 ? acc1[t] : acc0[t];
+            if (jj < it.k) out[jj] = acc[s2][t];
         }
     }
 }
