@@ -185,7 +185,7 @@ def test_batched_breakdown_is_per_item(gpu_handle):
 
 def test_batched_gaussian_many_items_matches_oracle(gpu_handle):
     """More than one 64-item tile of the shared-Theta step-4 product and step-1
-    tiles of 128 columns that span items of different n and k (rows past an
+    tiles of 64 columns that span items of different n and k (rows past an
     item's n and sketch rows past its k inside a tile), items spanning up to
     two 16384-row chunks and two 128-row sketch tiles; every item against the
     oracle (Gaussian items share the master matrix, instance 0)."""
