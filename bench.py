@@ -63,6 +63,13 @@ def measured_traffic(n, m, k):
     return rec["traffic_bytes_per_launch"]
 
 
+# Gaussian sketch on the fly: VALU instructions per entry of Theta in the
+# generated code (one Philox4x32-10 call and two Box-Muller pairs give four
+# entries in about 110 instructions, and one fma applies each entry), and the
+# chip's non-packed fp32 VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz
+VALU_INSTR_PER_ENTRY = 28.5
+VALU_LANE_RATE = 256 * 64 * 2.4e9
+
 # the projection kernel and everything its code is built from
 TRAFFIC_SOURCES = ["paper_2011_05090_amd/csrc/rgs_project.hip", "paper_2011_05090_amd/csrc/rgs_proj.hpp",
                    "paper_2011_05090_amd/csrc/rgs_block.hpp", "paper_2011_05090_amd/csrc/rgs_device.hpp",
@@ -548,9 +555,16 @@ def main():
         log("fp32 RGS, Gaussian sketch: 1 step")
         msg, _, repg = run_steps(rgs, torch, h, dg, W32, Q, R, S, 1, 0)
         draws = float(k) * n * (2 * m - 1)
+        # VALU bound of the per-column sketches alone: k n entries per column, each
+        # drawn and applied in about VALU_INSTR_PER_ENTRY instructions, at the
+        # non-packed fp32 issue rate of the chip
+        valu_ms = 1000.0 * k * n * m * VALU_INSTR_PER_ENTRY / VALU_LANE_RATE
         extra["fp32_rgs_gaussian"] = {"ms_per_qr": msg, "gbs": B / (msg / 1000) / 1e9, "status": repg.status,
-                                      "gaussian_draws_per_s": draws / (msg / 1000)}
-        log("  %.2f ms/QR" % msg)
+                                      "gaussian_draws_per_s": draws / (msg / 1000),
+                                      "valu_roofline": {"bound": "alu", "instr_per_entry": VALU_INSTR_PER_ENTRY,
+                                                        "peak_lane_instr_per_s": VALU_LANE_RATE,
+                                                        "bound_ms_per_qr": valu_ms, "frac": valu_ms / msg}}
+        log("  %.2f ms/QR (VALU bound of the column sketches %.0f ms: %.0f%%)" % (msg, valu_ms, 100 * valu_ms / msg))
         # Gaussian sketch with bf16 entries, made once into a table and read by every column
         dgt = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32", flags=rgs.FLAG_THETA_BF16)
         log("fp32 RGS, Gaussian sketch with bf16 entries (table): 1 warmup, 2 steps")
