@@ -378,7 +378,8 @@ def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=
         out["k%d" % k] = rows
     # Theta = I (k = n): with one Richardson sweep of the least squares the
     # column step is classical Gram-Schmidt (fp32 projection, inner products in
-    # fp64), the paper's CGS; two sweeps refine the coefficients only (CGS2 in
+    # fp64; the paper's CGS is float32 throughout); two sweeps refine the
+    # coefficients only (CGS2 in
     # exact arithmetic, but the rounded projection is not projected again);
     # the Householder solve is Gram-Schmidt with an exact least squares.
     # Column i depends on columns <= i only, so one factorisation of all m
