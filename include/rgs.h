@@ -29,7 +29,8 @@
  *     rgs_gmres_batched (the second half of the batch).  That work is forked
  *     from the handle's stream and joined back into it with events within
  *     the call, so the ordering on the handle's stream is unchanged.
- *   - Errors are negative rgs_status codes; nothing is thrown across the ABI.
+ *   - Errors are negative rgs_status codes; nothing is thrown across the ABI
+ *     (a host allocation failure inside a call returns RGS_ENOMEM).
  *     Argument errors are detected before any device work is enqueued.
  *   - A handle is not thread-safe: use one handle per host thread.
  */
@@ -50,8 +51,9 @@ typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream 
 typedef enum {
     RGS_OK = 0,
     RGS_EINVAL = -1,      /* bad argument (sizes, pointers, leading dims, enums) */
-    RGS_ENOMEM = -2,      /* device scratch allocation failed */
-    RGS_EDEVICE = -3,     /* a HIP runtime call or a kernel launch failed */
+    RGS_ENOMEM = -2,      /* device scratch or host memory allocation failed */
+    RGS_EDEVICE = -3,     /* a HIP runtime call or a kernel launch failed, or the
+                             host runtime did (e.g. a worker thread could not start) */
     RGS_EBREAKDOWN = -4,  /* r_ii = 0 or r_ii <= 2^-50 ||p_i||: w_i numerically in
                              span(Q_{i-1}); columns before report.failed_column are valid */
     RGS_ENONFINITE = -5,  /* a sketch p_i or s'_i is not finite (NaN/Inf in the input) */

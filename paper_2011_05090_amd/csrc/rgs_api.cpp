@@ -11,6 +11,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <thread>
 #include <type_traits>
 #include <unordered_map>
@@ -387,10 +389,23 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     double* Gd = Md + 2 * m * m;   // two m x m Gram matrices
     double* part = reinterpret_cast<double*>(A + pl.part_P);
     const size_t mm = (size_t)m * m;
-    auto both = [](auto f) {   // f(0) and f(1) on two host threads
-        std::thread t1([&]() { f(1); });
-        f(0);
+    auto both = [](auto f) {   // f(0) and f(1) on two host threads; an exception of either is rethrown here
+        std::exception_ptr e1;
+        std::thread t1([&]() {
+            try {
+                f(1);
+            } catch (...) {
+                e1 = std::current_exception();
+            }
+        });
+        try {
+            f(0);
+        } catch (...) {
+            t1.join();
+            throw;
+        }
         t1.join();
+        if (e1) std::rethrow_exception(e1);
     };
 
     std::vector<double> Rh(mm);
@@ -430,7 +445,11 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     double gq_min = NAN, gq_max = NAN;
     std::vector<double> Tinv(2 * mm);
     std::thread tc([&]() {   // reads Gh, which nothing writes from here on
-        ok_c = dense::sym_eig_extremes(std::vector<double>(Gh.begin(), Gh.begin() + mm), mi, gq_min, gq_max);
+        try {
+            ok_c = dense::sym_eig_extremes(std::vector<double>(Gh.begin(), Gh.begin() + mm), mi, gq_min, gq_max);
+        } catch (...) {
+            ok_c = false;   // cond(Phi Q) stays NaN
+        }
     });
     struct Joiner {
         std::thread& t;
@@ -830,20 +849,32 @@ std::vector<int64_t> prefix_of(int64_t count, F blocks) {
 }
 
 // Runs f(b) for b in [0, count) on a few host threads (independent items).
+// Joins every thread it started before returning or rethrowing the first
+// exception of any of them.
 template <typename F>
 void parallel_for(int64_t count, F f) {
     const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(16, std::min<int64_t>(count / 64 + 1,
                                                                  (int64_t)std::thread::hardware_concurrency())));
-    if (nt <= 1) {
-        for (int64_t b = 0; b < count; ++b) f(b);
-        return;
-    }
-    std::vector<std::thread> th;
-    for (int64_t t = 0; t < nt; ++t)
-        th.emplace_back([&, t]() {
+    std::vector<std::exception_ptr> err((size_t)nt);
+    auto body = [&](int64_t t) {
+        try {
             for (int64_t b = t; b < count; b += nt) f(b);
-        });
+        } catch (...) {
+            err[(size_t)t] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve((size_t)nt);
+    try {
+        for (int64_t t = 1; t < nt; ++t) th.emplace_back(body, t);
+    } catch (...) {
+        for (auto& x : th) x.join();
+        throw;
+    }
+    body(0);
     for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 // Schedules of the batched Gaussian sketch product that the autotuner picks
@@ -1893,8 +1924,8 @@ const char* rgs_status_string(rgs_status s) {
     switch (s) {
         case RGS_OK: return "success";
         case RGS_EINVAL: return "invalid argument";
-        case RGS_ENOMEM: return "device memory allocation failed";
-        case RGS_EDEVICE: return "HIP runtime or kernel launch failure";
+        case RGS_ENOMEM: return "memory allocation failed (device scratch or host)";
+        case RGS_EDEVICE: return "HIP runtime, kernel launch or host runtime failure";
         case RGS_EBREAKDOWN: return "breakdown: column numerically in the span of the previous ones";
         case RGS_ENONFINITE: return "non-finite sketch (NaN or Inf in the input)";
         case RGS_ENOCONV: return "GMRES did not converge within max_iters";
@@ -1902,7 +1933,7 @@ const char* rgs_status_string(rgs_status s) {
     return "unknown status";
 }
 
-rgs_status rgs_create(rgs_handle** h, int device, rgs_stream stream) {
+rgs_status rgs_create(rgs_handle** h, int device, rgs_stream stream) try {
     if (!h) return RGS_EINVAL;
     *h = nullptr;
     int count = 0;
@@ -1917,6 +1948,10 @@ rgs_status rgs_create(rgs_handle** h, int device, rgs_stream stream) {
     p->stream = static_cast<hipStream_t>(stream);
     *h = p;
     return RGS_OK;
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 rgs_status rgs_destroy(rgs_handle* h) {
@@ -1950,7 +1985,7 @@ rgs_status rgs_set_stream(rgs_handle* h, rgs_stream stream) {
 }
 
 rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ldw, void* Q, int64_t ldq,
-                  double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
+                  double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) try {
     if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
     if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY | RGS_FLAG_THETA_BF16)) != 0)
@@ -1968,10 +2003,14 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
                                          ldr, S, lds, rep);
     return run_qr<float, float, false>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R,
                                        ldr, S, lds, rep);
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, int64_t ldx, int64_t ncols,
-                            double* Y, int64_t ldy) {
+                            double* Y, int64_t ldy) try {
     if (!h || !valid_desc(d, false) || !X || !Y || ncols < 1 || ldx < d->n || ldy < d->k) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     const int sk_kind = sketch_kind(d->sketch);
@@ -1995,10 +2034,14 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
                                                  pl.cc, reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
     if (st != RGS_OK) return st;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j0, int64_t j1, int64_t l0,
-                                  int64_t l1, double* out, int64_t ldo) {
+                                  int64_t l1, double* out, int64_t ldo) try {
     if (!h || !valid_desc(d, false) || !out) return RGS_EINVAL;
     if (j0 < 0 || j1 < j0 || j1 > d->k || l0 < 0 || l1 < l0 || l1 > d->n || ldo < std::max<int64_t>(1, j1 - j0))
         return RGS_EINVAL;
@@ -2020,10 +2063,14 @@ rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j
                         : launch_materialize<float>(h->stream, sk, j0, j1, l0, l1, rsk, out, ldo);
     if (!ok) return RGS_EDEVICE;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc* d, const double* b, double* x,
-                     double* res_hist, int64_t hist_cap, rgs_report* rep) {
+                     double* res_hist, int64_t hist_cap, rgs_report* rep) try {
     if (!h || !A || !b || !x || hist_cap < 0 || (hist_cap > 0 && !res_hist) || !valid_gmres_desc(d))
         return RGS_EINVAL;
     int64_t n = 0;
@@ -2040,9 +2087,13 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     if (d->prec == RGS_P_FP64) return run_gmres<double, double, false>(h, A, d, b, x, res_hist, hist_cap, rep);
     if (d->prec == RGS_P_BF16Q_FP32_LS64) return run_gmres<float, bf16, true>(h, A, d, b, x, res_hist, hist_cap, rep);
     return run_gmres<float, float, false>(h, A, d, b, x, res_hist, hist_cap, rep);
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
-rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec, const void* u, void* w) {
+rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec, const void* u, void* w) try {
     if (!h || !Ad || !u || !w) return RGS_EINVAL;
     if (Ad->nx < 1 || Ad->ny < 1 || Ad->nz < 1) return RGS_EINVAL;
     if (Ad->nx * Ad->ny * Ad->nz > ((int64_t)1 << 31) - 1) return RGS_EINVAL;
@@ -2063,11 +2114,15 @@ rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec
                                                  static_cast<float*>(w), 0, sk, nullptr, status);
     if (!ok) return RGS_EDEVICE;
     return hipStreamSynchronize(h->stream) == hipSuccess ? RGS_OK : RGS_EDEVICE;
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int32_t sketch, int32_t prec,
                           uint64_t seed, uint32_t sketch_id, int32_t* item_status, int64_t* failed_column,
-                          rgs_report* rep) {
+                          rgs_report* rep) try {
     if (!h || batch < 1 || batch > 65535 || !items) return RGS_EINVAL;
     if (sketch != RGS_SKETCH_GAUSSIAN && sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if (prec != RGS_P_FP32_LS64 && prec != RGS_P_BF16Q_FP32_LS64) return RGS_EINVAL;
@@ -2078,10 +2133,14 @@ rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (prec == RGS_P_BF16Q_FP32_LS64)
         return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
     return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,
-                             int32_t* item_status, rgs_report* reps) {
+                             int32_t* item_status, rgs_report* reps) try {
     if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16)) != 0) return RGS_EINVAL;
@@ -2104,6 +2163,10 @@ rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     if (d->prec == RGS_P_BF16Q_FP32_LS64)
         return run_gmres_batched<float, bf16, true>(h, batch, items, d, item_status, reps);
     return run_gmres_batched<float, float, false>(h, batch, items, d, item_status, reps);
+} catch (const std::bad_alloc&) {
+    return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
 }
 
 }  // extern "C"
