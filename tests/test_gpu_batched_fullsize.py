@@ -1,0 +1,110 @@
+"""GPU parity of the batched QR at its full benchmark size: 2048 factorisations
+with n ~ U{4096..262144}, m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and
+bf16-stored Q, in one rgs_qr_batched call -- the inputs and the launch
+configuration bench.py times -- with the P-SRHT (item b uses instance b) and
+with the Gaussian sketch (all items share the master matrix, instance 0).
+
+Every item is checked through properties that hold at any size:
+* status 0, R upper triangular with a positive diagonal, every column of S of
+  unit norm (steps 5-6 normalise in fp64);
+* S R = Theta W up to the rounding of the stored basis: column i of S R is
+  Theta applied to sum_j q_j R_ji + q'_i, and q'_i = w_i - Q r rounded to bf16
+  (relative 2^-8), so ||S R - Theta W||_F <= 4 * 2^-8 ||Theta W||_F with Theta W
+  taken by the library's own sketch hook in fp64;
+* ||I - S^T S||_2 <= 0.1: an item whose step-1 sketch or coefficients came from
+  another item's columns or rows has a sketched basis that is not orthonormal
+  (Delta of order one), while this workload's items stay below 3e-2 (measured
+  maxima over the 2048 items: 3e-3 with the P-SRHT, 2.8e-2 with the Gaussian).
+A few items (the largest and smallest n*m and a middle one for the P-SRHT, the
+two smallest n for the Gaussian, whose oracle draws its k x n entries) are
+compared with the oracle's bf16 model: backward error within 2x of the
+oracle's, Delta within 2x (P-SRHT) or 4x (Gaussian: the device's fp32 entries
+differ from the oracle's fp64 ones in the last bits, so the two runs round
+different entries to bf16, as in the many-item Gaussian test).  R itself is
+not compared: with sigma down to 1e-6 the columns past r_ii / ||w_i|| ~ 2^-8
+are bf16 rounding noise in both runs.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import metrics, rgs as orgs, sketch as osk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BATCH = 2048
+U_BF16 = 2.0 ** -8
+
+
+def _rgs():
+    import paper_2011_05090_amd as rgs
+    return rgs
+
+
+@pytest.fixture(scope="module")
+def batch():
+    rgs = _rgs()
+    ns, ms = synth.batch_qr_sizes(BATCH)
+    items = []
+    for b in range(BATCH):
+        n, m = int(ns[b]), int(ms[b])
+        k = 4 * m
+        W = rgs.colmajor(n, m, torch.float32)
+        W.copy_(synth.svd_matrix_torch(n, m, 1e-6, tag=1000 + b))
+        items.append((W, rgs.colmajor(n, m, torch.bfloat16), rgs.colmajor(m, m, torch.float64),
+                      rgs.colmajor(k, m, torch.float64), k))
+    torch.cuda.synchronize()
+    yield items
+    del items[:]
+    torch.cuda.empty_cache()
+
+
+def _host(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("sketch", ["srht", "gaussian"])
+def test_full_batch(gpu_handle, batch, sketch):
+    rgs = _rgs()
+    print("batched bf16q QR, %s, %d items" % (sketch, len(batch)), flush=True)
+    rep, stat, fcol = rgs.rgs_qr_batched(gpu_handle, batch, sketch=sketch, prec="bf16q")
+    torch.cuda.synchronize()
+    assert rep.status == 0 and all(v == 0 for v in stat) and all(c == -1 for c in fcol)
+    worst_srw, worst_d2 = 0.0, 0.0
+    for b, (W, Q, R, S, k) in enumerate(batch):
+        n, m = W.shape
+        assert torch.all(torch.tril(R, -1) == 0) and bool(torch.all(torch.diagonal(R) > 0)), b
+        assert float(torch.max(torch.abs(torch.linalg.norm(S, dim=0) - 1.0))) <= 1e-12, b
+        TW = rgs.colmajor(k, m, torch.float64)
+        d = rgs.qr_desc(n, m, k, sketch=sketch, prec="fp32", instance=b if sketch == "srht" else 0)
+        rgs.rgs_sketch_apply(gpu_handle, d, W, TW)
+        srw = float(torch.linalg.norm(S @ R - TW) / torch.linalg.norm(TW))
+        ev = np.linalg.eigvalsh((S.T @ S).cpu().numpy())
+        d2 = float(np.max(np.abs(ev - 1.0)))
+        worst_srw, worst_d2 = max(worst_srw, srw), max(worst_d2, d2)
+        assert srw <= 4 * U_BF16, (b, srw)
+        assert d2 <= 0.1, (b, d2)
+        del TW
+    print("  max ||SR - Theta W||/||Theta W|| %.2e, max ||I - S^T S||_2 %.2e" % (worst_srw, worst_d2), flush=True)
+
+    sizes = np.array([W.shape[0] * W.shape[1] for W, *_ in batch])
+    if sketch == "srht":
+        order = np.argsort(sizes, kind="stable")
+        picks = [int(order[-1]), int(order[0]), int(order[len(order) // 2])]
+    else:
+        picks = [int(b) for b in np.argsort([W.shape[0] for W, *_ in batch], kind="stable")[:2]]
+    for b in picks:
+        W, Q, R, S, k = batch[b]
+        n, m = W.shape
+        print("  oracle check: item %d, n %d, m %d, k %d" % (b, n, m, k), flush=True)
+        Wh = W.cpu().numpy().astype(np.float32)
+        theta = osk.make(sketch, n, k, seed=42, instance=b if sketch == "srht" else 0)
+        ref = orgs.rgs_qr(Wh, theta, precision="bf16q")
+        Qh, Rh, Sh = _host(Q), _host(R), _host(S)
+        W64 = Wh.astype(np.float64)
+        be, be_ref = metrics.backward_error(W64, Qh, Rh), metrics.backward_error(W64, ref["Q"], ref["R"])
+        d2, d2_ref = metrics.delta_2(Sh), metrics.delta_2(ref["S"])
+        assert be <= 2 * be_ref, (b, be, be_ref)
+        assert d2 <= (2 if sketch == "srht" else 4) * d2_ref, (b, d2, d2_ref)
