@@ -12,6 +12,12 @@
 * Breakdowns and argument errors.
 * Sec. 5.1 (qualitative, reduced n): in float32, CGS loses orthogonality,
   MGS degrades, multi-precision RGS keeps cond(Q) close to 1.
+* The classical projectors of Sec. 1.2 themselves: MGS in exact arithmetic is
+  Gram-Schmidt (|R| of a Householder QR); in floating point it loses
+  orthogonality at O(u kappa) where CGS loses it at O(u kappa^2) and CGS2
+  keeps it at O(u) (Bjorck; Giraud, Langou, Rozloznik); the float32 variants
+  carry float32 rounding, agree with the fp64 ones to O(u32 kappa) in R, and
+  keep the same ordering.
 """
 
 import math
@@ -193,3 +199,56 @@ def test_bf16q_model_tolerances():
     assert metrics.cond(out["Q"]) < 5.0          # still well conditioned (Gaussian k = 4m)
     out32 = rgs.rgs_qr(W, th, precision="fp32")
     assert metrics.delta_2(out32["S"]) < 1e-2 * metrics.delta_2(out["S"])
+
+
+# ---------------------------------------------------------------------------
+# Classical projectors of Sec. 1.2 (MGS, CGS, CGS2) -- the Sec. 5.1 references
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fn", ["mgs", "cgs", "cgs2"])
+def test_classical_gs_matches_householder_R(fn):
+    """In exact arithmetic every Gram-Schmidt variant gives the positive-diagonal
+    R factor of W; at kappa = 1e2 in fp64 |R| agrees with LAPACK's Householder
+    |R| to rounding."""
+    W = _wellcond(500, 30, smin=1e-2, tag=31)
+    Q, R = getattr(rgs, fn)(W)
+    _, Rh = np.linalg.qr(W)
+    assert np.all(np.diag(R) > 0) and np.all(np.tril(R, -1) == 0)
+    assert np.linalg.norm(np.abs(R) - np.abs(Rh)) / np.linalg.norm(Rh) <= 1e-12
+    assert metrics.backward_error(W, Q, R) <= 1e-14
+
+
+def test_mgs_loses_orthogonality_at_u_kappa_cgs_at_u_kappa2():
+    """MGS: ||I - Q^T Q|| = O(u kappa) (Bjorck 1967); CGS: O(u kappa^2); CGS2: O(u).
+    A slip that makes MGS project the original column (i.e. CGS) or drop a term
+    of the rank-one updates fails the first bound."""
+    W = synth.svd_matrix(2000, 40, 1e-6, tag=32)
+    kap = metrics.cond(W)
+    lm = metrics.orth_loss_2(rgs.mgs(W)[0])
+    lc = metrics.orth_loss_2(rgs.cgs(W)[0])
+    l2 = metrics.orth_loss_2(rgs.cgs2(W)[0])
+    assert lm <= 10 * U64 * kap
+    assert 0.05 * U64 * kap ** 2 <= lc <= 10 * U64 * kap ** 2
+    assert lc >= 1e4 * lm
+    assert l2 <= 100 * U64
+
+
+@pytest.mark.parametrize("fn", ["mgs", "cgs", "cgs2"])
+def test_classical_gs_float32_variants(fn):
+    """The float32 variants compute in float32: R agrees with the fp64 variant to
+    O(u32 kappa) (backward-stable R for all three) but not to fp64 accuracy,
+    and the loss of orthogonality keeps its order in u32:
+    MGS O(u32 kappa), CGS O(u32 kappa^2), CGS2 O(u32)."""
+    W = synth.svd_matrix(1000, 30, 1e-2, tag=33)
+    kap = metrics.cond(W)
+    Q6, R6 = getattr(rgs, fn)(W)
+    Q3, R3 = getattr(rgs, fn)(W, np.float32)
+    assert Q3.dtype == np.float32 and R3.dtype == np.float32
+    dr = np.linalg.norm(R3 - R6) / np.linalg.norm(R6)
+    assert 0.05 * U32 <= dr <= 2 * U32 * kap
+    loss = metrics.orth_loss_2(Q3)
+    bound = {"mgs": 10 * U32 * kap, "cgs": 10 * U32 * kap ** 2, "cgs2": 100 * U32}[fn]
+    assert loss <= bound
+    if fn == "cgs":
+        assert loss >= 10 * U32 * kap          # well above what MGS reaches
+    assert metrics.backward_error(W.astype(np.float32), Q3, R3) <= 10 * U32
