@@ -7,21 +7,31 @@ bench.py times -- with the bf16 and with the fp32 basis.
 * every system converges (status 0), and its true relative residual
   ||b - A x|| / ||b||, recomputed on the host with the oracle's operator in
   fp64, is <= tol and equals the reported one to 1e-6 relative;
-* the two smallest systems against the oracle's RGMRES with the same sketches
-  (fp64 model for the fp32 basis, the bf16 model for the bf16 basis):
-  iteration counts within +-2.
+* 32 systems spread over the size range (ranks round(linspace(0, 255, 32))
+  of the order by n) against the oracle's RGMRES with the same sketches, whose
+  counts are cached in tests/golden/gmres_c5_subset.json (written by
+  tests/golden/make_gmres_refs.py, which runs only the oracle): the fp32 basis
+  within +-2 iterations of the fp64 oracle (Sec. 4.2), on every one of them;
+  the bf16 basis within +-2 of the oracle's bf16 model.  The bf16 basis is
+  *not* held to the fp64 count: storing the Krylov basis with a 2^-9 unit
+  roundoff perturbs the restarted process well beyond two iterations on many
+  systems (the test prints how many of the 32 meet that bar).
 """
+
+import json
+import os
 
 import numpy as np
 import pytest
 
 import synth
-from oracle import gmres as ogm, sketch as osk, stencil as ost
+from oracle import stencil as ost
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 BATCH, RESTART, K, TOL = 256, 50, 200, 1e-6
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gmres_c5_subset.json")
 
 
 def _rgs():
@@ -61,12 +71,17 @@ def test_full_batch(gpu_handle, systems, prec, model):
     del sy
     torch.cuda.empty_cache()
 
-    for i in np.argsort([b.size for _, _, b in systems], kind="stable")[:2]:
-        dims, coeffs, b = systems[int(i)]
-        n = b.size
-        print("  oracle check: system %d, grid %s" % (int(i), dims), flush=True)
-        ref = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b,
-                         lambda c: osk.make("srht", n, K, seed=42, sketch_id=2 + c),
-                         restart=RESTART, tol=TOL, precision=model, max_iters=20000)
-        assert ref["converged"]
-        assert abs(reps[int(i)].iters - ref["iters"]) <= 2, (dims, reps[int(i)].iters, ref["iters"])
+    ref = json.load(open(GOLDEN))
+    assert (ref["batch"], ref["restart"], ref["k"], ref["sketch"]) == (BATCH, RESTART, K, "srht")
+    vs_model, vs_fp64 = [], []
+    for sysref in ref["systems"]:
+        r_model, r64 = sysref[model], sysref["fp64"]
+        i = r_model["index"]
+        assert r_model["converged"] and r64["converged"]
+        assert systems[i][2].size == r_model["n"]
+        vs_model.append(reps[i].iters - r_model["iters"])
+        vs_fp64.append(reps[i].iters - r64["iters"])
+    print("  %s basis vs the oracle's %s model, iteration differences: %s" % (prec, model, vs_model), flush=True)
+    print("  %s basis within +-2 of the fp64 oracle on %d of %d systems" %
+          (prec, sum(1 for d in vs_fp64 if abs(d) <= 2), len(vs_fp64)), flush=True)
+    assert all(abs(d) <= 2 for d in vs_model), vs_model
