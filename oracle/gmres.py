@@ -40,10 +40,13 @@ def _givens(a, b):
 
 
 def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp64",
-           ls="householder", reuse_theta=False, max_cycles=None):
+           ls="householder", reuse_theta=False, max_cycles=None, reverse_projection=False):
     """Restarted randomized GMRES.
 
     apply_A(u, dtype) -> A u in arithmetic ``dtype``; make_theta(cycle) -> sketch.
+    ``reverse_projection`` forms Q_{i-1} r of RGS step 3 over the columns in
+    reverse order: the same step with another summation order, which the
+    precision models leave open (a second valid rounding of the same model).
     Returns dict(x, hist, iters, cycles, true_relres, converged, cond_info).
     hist[t] = |g| / ||b|| after global inner step t.
     """
@@ -100,12 +103,13 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
             p = theta.apply(w.astype(np.float64))   # RGS step 1
             r = _ls(S[:, :i], p, ls)                # RGS step 2
             R[:i, i] = r
+            cols = slice(i - 1, None, -1) if reverse_projection else slice(0, i)
             if bf16:
-                qp = w - Q[:, :i] @ (r * scale[:i]).astype(store)   # RGS step 3 on the stored columns
+                qp = w - Q[:, cols] @ (r * scale[:i])[cols].astype(store)   # RGS step 3 on the stored columns
                 Q[:, i] = bf16_round(qp)
                 sp = theta.apply(Q[:, i].astype(np.float64))        # RGS step 4 of the stored column
             else:
-                qp = w - Q[:, :i] @ r.astype(store)     # RGS step 3
+                qp = w - Q[:, cols] @ r[cols].astype(store)     # RGS step 3
                 sp = theta.apply(qp.astype(np.float64))  # RGS step 4
             rii = np.linalg.norm(sp)                # RGS step 5
             lucky = rii == 0.0 or rii <= BREAKDOWN_RATIO * np.linalg.norm(p)

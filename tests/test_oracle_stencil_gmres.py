@@ -151,3 +151,29 @@ def test_bf16_model_converges_with_rounding():
     assert out["converged"]
     r = b - applyA(out["x"], np.float64)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16q"])
+def test_reversed_projection_order_is_the_same_step(precision):
+    """reverse_projection only reorders the sum Q_{i-1} r of RGS step 3.  In
+    fp64 that changes nothing beyond rounding (iterates within 1e-10); in the
+    fp32 and bf16 models the twin is a second valid rounding: it converges,
+    and it is really a different rounding (some history value differs)."""
+    N, Pe = 9, 30.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=6)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    mk = lambda c: sketch.SRHT(n, 64, seed=42, sketch_id=2 + c)
+    ref = gmres.rgmres(applyA, b, mk, restart=15, tol=1e-6, precision=precision)
+    rev = gmres.rgmres(applyA, b, mk, restart=15, tol=1e-6, precision=precision, reverse_projection=True)
+    assert rev["converged"]
+    r = b - applyA(rev["x"], np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
+    if precision == "fp64":
+        assert rev["iters"] == ref["iters"]
+        np.testing.assert_allclose(rev["hist"], ref["hist"], rtol=1e-8)
+        assert np.linalg.norm(rev["x"] - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+    else:
+        L = min(len(ref["hist"]), len(rev["hist"]))
+        assert np.any(rev["hist"][:L] != ref["hist"][:L])
