@@ -9,6 +9,8 @@ JSON beside this script and the GPU tests compare against them.
     python tests/golden/make_gmres_refs.py c3_srht        # 192^3, P-SRHT k = 400, fp64
     python tests/golden/make_gmres_refs.py c3_gauss64     # 64^3, Gaussian k = 400, fp64
     python tests/golden/make_gmres_refs.py c5_subset [-j 6]  # 32 of the 256 batched systems, fp64 + bf16 models
+    python tests/golden/make_gmres_refs.py c5_twin [-j 6]    # adds the bf16 model with step 3 summed in
+                                                             # reverse column order ("bf16q_rev")
 
 Workloads (the synthetic stand-ins of the convection-diffusion systems):
   * single system: -Lap u + Pe (1,1,1).grad u on the unit cube, Pe = 50,
@@ -38,7 +40,7 @@ from oracle import gmres as ogm, sketch as osk, stencil as ost  # noqa: E402
 BATCH, B_RESTART, B_K, TOL = 256, 50, 200, 1e-6
 
 
-def _solve(N, Pe, b, kind, k, restart, precision):
+def _solve(N, Pe, b, kind, k, restart, precision, reverse=False):
     dims, coeffs = synth.convdiff_coeffs(N, Pe)
     n = N ** 3
     t0 = time.time()
@@ -49,7 +51,8 @@ def _solve(N, Pe, b, kind, k, restart, precision):
         return osk.make(kind, n, k, seed=synth.SKETCH_SEED, sketch_id=2 + c)
 
     ref = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b, theta,
-                     restart=restart, tol=TOL, precision=precision, max_iters=20000)
+                     restart=restart, tol=TOL, precision=precision, max_iters=20000,
+                     reverse_projection=reverse)
     return {"N": int(N), "Pe": float(Pe), "n": int(n), "sketch": kind, "k": int(k), "restart": int(restart),
             "tol": TOL, "precision": precision, "iters": int(ref["iters"]), "cycles": int(ref["cycles"]),
             "true_relres": float(ref["true_relres"]), "converged": bool(ref["converged"]),
@@ -78,16 +81,19 @@ def _c5_one(args):
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     Ns, Pes = synth.batch_gmres_sizes(BATCH)
     N, Pe = int(Ns[i]), float(Pes[i])
-    out = _solve(N, Pe, synth.rhs(N ** 3, tag=1000 + i), "srht", B_K, B_RESTART, precision)
+    rev = precision.endswith("_rev")
+    out = _solve(N, Pe, synth.rhs(N ** 3, tag=1000 + i), "srht", B_K, B_RESTART, precision.replace("_rev", ""),
+                 reverse=rev)
+    out["precision"] = precision
     out["index"] = i
     print("system %d N=%d Pe=%.1f %s: %d iters (%.0f s)" % (i, N, Pe, precision, out["iters"],
                                                            out["oracle_seconds"]), flush=True)
     return out
 
 
-def c5_subset(jobs):
+def c5_subset(jobs, precisions=("fp64", "bf16q")):
     import multiprocessing as mp
-    work = [(i, p) for i in c5_indices() for p in ("fp64", "bf16q")]
+    work = [(i, p) for i in c5_indices() for p in precisions]
     work.sort(key=lambda a: -synth.batch_gmres_sizes(BATCH)[0][a[0]])   # largest first
     with mp.get_context("fork").Pool(jobs) as pool:
         res = pool.map(_c5_one, work, chunksize=1)
@@ -100,9 +106,21 @@ def c5_subset(jobs):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c3_srht", "c3_gauss64", "c5_subset"])
+    ap.add_argument("what", choices=["c3_srht", "c3_gauss64", "c5_subset", "c5_twin"])
     ap.add_argument("-j", type=int, default=6)
     a = ap.parse_args()
+    if a.what == "c5_twin":   # merged into the c5_subset file
+        path = os.path.join(HERE, "gmres_c5_subset.json")
+        out = json.load(open(path))
+        twin = c5_subset(a.j, ("bf16q_rev",))
+        by = {s["bf16q_rev"]["index"]: s["bf16q_rev"] for s in twin["systems"]}
+        for s in out["systems"]:
+            s["bf16q_rev"] = by[s["fp64"]["index"]]
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+            f.write("\n")
+        print("wrote", path)
+        return
     if a.what == "c5_subset":
         out = c5_subset(a.j)
     else:
