@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 2
+#define RGS_ABI_VERSION 3
 
 typedef struct rgs_handle rgs_handle;  /* opaque */
 typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
@@ -57,7 +57,8 @@ typedef enum {
     RGS_EBREAKDOWN = -4,  /* r_ii = 0 or r_ii <= 2^-50 ||p_i||: w_i numerically in
                              span(Q_{i-1}); columns before report.failed_column are valid */
     RGS_ENONFINITE = -5,  /* a sketch p_i or s'_i is not finite (NaN/Inf in the input) */
-    RGS_ENOCONV = -6      /* GMRES hit max_iters; x holds the last iterate */
+    RGS_ENOCONV = -6,     /* GMRES hit max_iters; x holds the last iterate */
+    RGS_ESCRATCH = -7     /* rgs_qr_noalloc: the problem does not fit its fixed scratch */
 } rgs_status;
 
 typedef enum {
@@ -240,6 +241,34 @@ int32_t rgs_last_tuning(const rgs_handle *h);
 rgs_status rgs_qr(rgs_handle *h, const rgs_qr_desc *desc,
                   const void *W, int64_t ldw, void *Q, int64_t ldq,
                   double *R, int64_t ldr, double *S, int64_t lds, rgs_report *rep);
+
+/* rgs_qr without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and status codes as rgs_qr --
+ * the same kernels in the same order, so Q, R and S equal rgs_qr's bit for
+ * bit -- except:
+ *   - the library's scratch is a fixed 64 MiB device array per device (one
+ *     copy on each device, held from the library's load until the process
+ *     ends); its address is looked up when a handle is created on the device.
+ *     No hipMalloc, hipFree, event or stream is created by the call, and no
+ *     host table is copied (the P-SRHT rows are drawn on the device);
+ *   - RGS_ESCRATCH (before any device work) when the factorisation does not
+ *     fit that array: it holds five k x m fp64 matrices (P, the compact-WY
+ *     factors twice), k x ceil(n/8192) partial sums of the working precision,
+ *     at least one column of step-1 partials (64 x k fp64) and O(k + m^2 + n/32)
+ *     more; e.g. k = 2048, m = 512 fits up to n = 2^23 in every precision; P-SRHT also needs
+ *     k <= 4096;
+ *   - desc->flags must be 0 (EINVAL): diagnostics, kernel timing,
+ *     certification and the bf16 table need memory of their own;
+ *   - step 1 runs on the handle's stream only (no auxiliary stream).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (each call initialises what it reads): calls that overlap in time on
+ * one device -- two host threads, or two streams -- race and corrupt each
+ * other's results.  Serialise them.
+ * Returns OK, EINVAL, ESCRATCH, EDEVICE, EBREAKDOWN or ENONFINITE. */
+rgs_status rgs_qr_noalloc(rgs_handle *h, const rgs_qr_desc *desc,
+                          const void *W, int64_t ldw, void *Q, int64_t ldq,
+                          double *R, int64_t ldr, double *S, int64_t lds, rgs_report *rep);
 
 /* A batch of independent RGS QR factorisations (Algorithm 2, Sec. 2.3) of
  * uneven sizes, advanced in lockstep: each column step is one launch of each

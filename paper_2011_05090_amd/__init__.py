@@ -17,7 +17,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librgs.so")
 
-RGS_OK, RGS_EINVAL, RGS_ENOMEM, RGS_EDEVICE, RGS_EBREAKDOWN, RGS_ENONFINITE, RGS_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+(RGS_OK, RGS_EINVAL, RGS_ENOMEM, RGS_EDEVICE, RGS_EBREAKDOWN, RGS_ENONFINITE, RGS_ENOCONV,
+ RGS_ESCRATCH) = 0, -1, -2, -3, -4, -5, -6, -7
 SKETCH = {"gaussian": 0, "srht": 1, "identity": 2, "rademacher": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16q": 2}
 FLAG_DIAGNOSTICS = 1
@@ -95,6 +96,7 @@ SIGNATURES = {
     "rgs_set_tuning": (ctypes.c_int, [_P, ctypes.c_int32]),
     "rgs_last_tuning": (ctypes.c_int32, [_P]),
     "rgs_qr": (ctypes.c_int, [_P, _DESCP, _P, _I64, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(Report)]),
+    "rgs_qr_noalloc": (ctypes.c_int, [_P, _DESCP, _P, _I64, _P, _I64, _P, _I64, _P, _I64, ctypes.POINTER(Report)]),
     "rgs_sketch_apply": (ctypes.c_int, [_P, _DESCP, _P, _I64, _I64, _P, _I64]),
     "rgs_sketch_materialize": (ctypes.c_int, [_P, _DESCP, _I64, _I64, _I64, _I64, _P, _I64]),
     "rgs_gmres": (ctypes.c_int, [_P, ctypes.POINTER(Stencil7), ctypes.POINTER(GmresDesc), _P, _P, _P, _I64,
@@ -229,20 +231,30 @@ def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=
                   sketch=SKETCH[sketch], prec=PREC[prec], flags=flags, ls_sweeps=ls_sweeps)
 
 
-def rgs_qr(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
-    """Algorithm 2 on W -> Q, R, S (all preallocated device tensors).  Returns the Report."""
+def _qr_call(name, handle, desc, W, Q, R, S, allow):
     import torch
     dw, dq = _dtypes(desc.prec)
     n, m, k = desc.n, desc.m, desc.k
     if tuple(W.shape) != (n, m) or tuple(Q.shape) != (n, m) or tuple(R.shape) != (m, m) or tuple(S.shape) != (k, m):
         raise ValueError("shape mismatch")
     rep = Report()
-    st = lib().rgs_qr(handle.ptr, ctypes.byref(desc), _dev(W, "W", dw), _ld(W, n), _dev(Q, "Q", dq), _ld(Q, n),
-                      _dev(R, "R", torch.float64), _ld(R, m), _dev(S, "S", torch.float64), _ld(S, k),
-                      ctypes.byref(rep))
-    _check(st, "rgs_qr", allow)
+    st = getattr(lib(), name)(handle.ptr, ctypes.byref(desc), _dev(W, "W", dw), _ld(W, n), _dev(Q, "Q", dq),
+                              _ld(Q, n), _dev(R, "R", torch.float64), _ld(R, m), _dev(S, "S", torch.float64),
+                              _ld(S, k), ctypes.byref(rep))
+    _check(st, name, allow)
     rep.status = st
     return rep
+
+
+def rgs_qr(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
+    """Algorithm 2 on W -> Q, R, S (all preallocated device tensors).  Returns the Report."""
+    return _qr_call("rgs_qr", handle, desc, W, Q, R, S, allow)
+
+
+def rgs_qr_noalloc(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
+    """rgs_qr in the library's fixed per-device scratch: allocates nothing (RGS_ESCRATCH if the
+    factorisation does not fit it; flags must be 0).  Returns the Report."""
+    return _qr_call("rgs_qr_noalloc", handle, desc, W, Q, R, S, allow)
 
 
 def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id=0,

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <type_traits>
@@ -42,9 +43,42 @@ struct rgs_handle {
     int last_schedule = 0;    // schedule used by the last batched Gaussian call
 };
 
+// Fixed device scratch of rgs_qr_noalloc, for callers that cannot allocate.
+// One copy per device, held from the library's load until the process ends.
+// In host code `scratch` only names the symbol: its device address (different
+// on every device) comes from hipGetSymbolAddress, taken once per device when
+// a handle is created on it (bind_scratch) and used everywhere after that.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 constexpr size_t kAlign = 256;
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// With `device` current: looks up (once per device) the device address of
+// this device's copy of `scratch`.
+rgs_status bind_scratch(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return RGS_OK;   // rgs_qr_noalloc then reports EDEVICE
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return RGS_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+        (void)hipGetLastError();
+        return RGS_EDEVICE;
+    }
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+    return RGS_OK;
+}
+
+char* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 struct Carver {
     size_t off = 0;
@@ -194,10 +228,19 @@ bool valid_desc(const rgs_qr_desc* d, bool need_m) {
 }
 
 // Prepares the sketch tables (SRHT sign bits, sampled rows) in `sk`.
-rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* signs_dev, int* rows_dev) {
+// device_rows: draw the sampled rows on the device (no host table, no copy,
+// no synchronisation) instead of on the host.
+rgs_status setup_sketch(rgs_handle* h, SketchArgs& sk, int64_t n, uint32_t* signs_dev, int* rows_dev,
+                        bool device_rows = false) {
     if (sk.sketch != SK_SRHT) return RGS_OK;
     const int64_t nwords = (n + 31) / 32;
     if (!launch_srht_signs(h->stream, signs_dev, nwords, sk)) return RGS_EDEVICE;
+    if (device_rows) {
+        if (!launch_srht_rows(h->stream, rows_dev, srht_order(n), sk)) return RGS_EDEVICE;
+        sk.signs = signs_dev;
+        sk.rows = rows_dev;
+        return RGS_OK;
+    }
     std::vector<int> rows;
     srht_rows_host(srht_order(n), sk.k, sk, rows);
     if (hipMemcpyAsync(rows_dev, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, h->stream) !=
@@ -224,8 +267,10 @@ struct QrPlan {
 // spread over up to 256 row groups x k/256 row chunks of Theta.
 constexpr int64_t kSplitRows = (int64_t)128 * kProjRows;
 
+// part_budget: bytes for the step-1 partials of the columns sketched together
+// (at least one column's worth is always planned).
 QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool certify = false,
-               bool table = false) {
+               bool table = false, size_t part_budget = (size_t)64 << 20) {
     QrPlan p{};
     Carver c;
     p.nblk = (n + kBlock - 1) / kBlock;
@@ -239,7 +284,7 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool c
                   ? (int)std::min<int64_t>((n + kGSubCol - 1) / kGSubCol, 256)
                   : 0;
     const size_t per_col = (size_t)p.G_P * k * sizeof(double);   // step-1 partials accumulate in fp64
-    p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)((64u << 20) / std::max<size_t>(per_col, 1))));
+    p.cc = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)(part_budget / std::max<size_t>(per_col, 1))));
     p.signs = c.take<uint32_t>((n + 31) / 32 + 4);
     p.rows = c.take<int>(k);
     p.part_proj = c.take<char>(
@@ -496,20 +541,43 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     return RGS_OK;
 }
 
+// fixed != nullptr: the factorisation runs in the caller-independent fixed
+// buffer `fixed` of fixed_bytes (the no-allocation entry point) instead of
+// the handle's arena: nothing is allocated, no event or auxiliary stream is
+// used, step 1 runs chunk by chunk on the handle's stream just before the
+// columns that read each chunk, and the SRHT rows are drawn on the device.
+// Flags that need memory of their own are rejected by the caller.
 template <typename T, typename TQ, bool DEFER>
 rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, TQ* Q, int64_t ldq, double* R,
-                  int64_t ldr, double* S, int64_t lds, rgs_report* rep) {
+                  int64_t ldr, double* S, int64_t lds, rgs_report* rep, char* fixed = nullptr,
+                  size_t fixed_bytes = 0) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = d->n, m = d->m, k = d->k;
     const int sk_kind = sketch_kind(d->sketch);
     const bool want_cert = (d->flags & RGS_FLAG_CERTIFY) != 0 && rep != nullptr;
     const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
-    const QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert, tab);
-    rgs_status st = ensure_arena(h, pl.total);
-    if (st != RGS_OK) return st;
-    char* A = h->arena;
+    QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert, tab);
+    rgs_status st = RGS_OK;
+    char* A = nullptr;
+    if (fixed) {
+        // as many step-1 columns per chunk as the fixed buffer leaves room for
+        const size_t per_col = (size_t)pl.G_P * k * sizeof(double);
+        pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, false, per_col);
+        if (pl.total > fixed_bytes) return RGS_ESCRATCH;
+        const size_t more = (fixed_bytes - pl.total) / std::max<size_t>(per_col, 1);
+        pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, false, per_col * (1 + more));
+        while (pl.total > fixed_bytes && pl.cc > 1)   // alignment padding
+            pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, false, per_col * (size_t)(pl.cc - 1));
+        if (pl.total > fixed_bytes) return RGS_ESCRATCH;
+        A = fixed;
+    } else {
+        st = ensure_arena(h, pl.total);
+        if (st != RGS_OK) return st;
+        A = h->arena;
+    }
     SketchArgs sk = make_sketch(sk_kind, k, d->seed, d->sketch_id, d->instance);
-    st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
+    st = setup_sketch(h, sk, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows),
+                      fixed != nullptr);
     if (st != RGS_OK) return st;
     if (tab && (st = use_table(h, sk, n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
 
@@ -525,7 +593,11 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     if (h->aux &&   // anything a failed call left on the auxiliary stream comes first
         (hipEventRecord(h->join_ev, h->aux) != hipSuccess || hipStreamWaitEvent(s, h->join_ev, 0) != hipSuccess))
         return RGS_EDEVICE;
-    if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
+    if (fixed) {   // the status words: four ints, cleared by a kernel (no memset node)
+        if (!launch_zero_mat(s, reinterpret_cast<double*>(sa.status), 2, 1, 2)) return RGS_EDEVICE;
+    } else if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) {
+        return RGS_EDEVICE;
+    }
     if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
 
     // Step 1 for every column at once: P = Theta W, in chunks of pl.cc columns.
@@ -538,7 +610,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const int64_t nchunk = (m + pl.cc - 1) / pl.cc;
     st = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, std::min<int64_t>(m, pl.cc), pl.G_P, pl.cc, partP, P, k);
     if (st != RGS_OK) return st;
-    if (nchunk > 1) {
+    if (nchunk > 1 && !fixed) {
         if (ensure_aux(h) != RGS_OK || ensure_chunk_events(h, (size_t)nchunk) != RGS_OK ||
             hipEventRecord(h->fork_ev, s) != hipSuccess || hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)
             return RGS_EDEVICE;
@@ -578,9 +650,16 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
         if (split && sketch_col && !launch_gauss_cols<TQ, T>(s, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
             return RGS_EDEVICE;
         if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
-        if (i + 1 < m && (i + 1) % pl.cc == 0 &&   // the next column opens a chunk of P
-            hipStreamWaitEvent(s, h->chunk_ev[(i + 1) / pl.cc], 0) != hipSuccess)
-            return RGS_EDEVICE;
+        if (i + 1 < m && (i + 1) % pl.cc == 0) {   // the next column opens a chunk of P
+            if (fixed) {
+                const int64_t c0 = i + 1;
+                st = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P,
+                                             pl.cc, partP, P + c0 * k, k);
+                if (st != RGS_OK) return st;
+            } else if (hipStreamWaitEvent(s, h->chunk_ev[(i + 1) / pl.cc], 0) != hipSuccess) {
+                return RGS_EDEVICE;
+            }
+        }
         const double* src0 = (i == 0 && !DEFER) ? P : nullptr;
         const bool ok = d->ls_sweeps > 0
                             ? launch_column_richardson<T, T>(s, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr,
@@ -1929,6 +2008,9 @@ const char* rgs_status_string(rgs_status s) {
         case RGS_EBREAKDOWN: return "breakdown: column numerically in the span of the previous ones";
         case RGS_ENONFINITE: return "non-finite sketch (NaN or Inf in the input)";
         case RGS_ENOCONV: return "GMRES did not converge within max_iters";
+        case RGS_ESCRATCH:
+            return "problem larger than the fixed scratch of the no-allocation entry point "
+                   "(64 MiB per device; P-SRHT k <= 4096)";
     }
     return "unknown status";
 }
@@ -1943,6 +2025,7 @@ rgs_status rgs_create(rgs_handle** h, int device, rgs_stream stream) try {
     }
     if (device < 0 || device >= count) return RGS_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return RGS_EDEVICE;
+    if (bind_scratch(device) != RGS_OK) return RGS_EDEVICE;
     rgs_handle* p = new rgs_handle();
     p->device = device;
     p->stream = static_cast<hipStream_t>(stream);
@@ -2005,6 +2088,28 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
                                        ldr, S, lds, rep);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;
+} catch (...) {
+    return RGS_EDEVICE;
+}
+
+rgs_status rgs_qr_noalloc(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ldw, void* Q, int64_t ldq,
+                          double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) try {
+    if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
+    if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
+    if (d->flags != 0) return RGS_EINVAL;   // every flag needs memory or events of its own
+    if (d->m > 4096) return RGS_EINVAL;     // dynamic LDS of the sketch-space kernels
+    if (d->sketch == RGS_SKETCH_SRHT && d->k > kRowsDevMax) return RGS_ESCRATCH;   // device row draw
+    char* buf = scratch_ptr(h->device);
+    if (!buf) return RGS_EDEVICE;
+    if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
+    if (d->prec == RGS_P_FP64)
+        return run_qr<double, double, false>(h, d, static_cast<const double*>(W), ldw, static_cast<double*>(Q), ldq,
+                                             R, ldr, S, lds, rep, buf, kScratchBytes);
+    if (d->prec == RGS_P_BF16Q_FP32_LS64)
+        return run_qr<float, bf16, true>(h, d, static_cast<const float*>(W), ldw, static_cast<bf16*>(Q), ldq, R,
+                                         ldr, S, lds, rep, buf, kScratchBytes);
+    return run_qr<float, float, false>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R,
+                                       ldr, S, lds, rep, buf, kScratchBytes);
 } catch (...) {
     return RGS_EDEVICE;
 }

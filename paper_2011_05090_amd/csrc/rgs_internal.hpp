@@ -12,6 +12,10 @@
 namespace rgs {
 
 bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const SketchArgs& sk);
+// The P-SRHT's k sampled rows of [0, s) drawn on the device (one workgroup),
+// equal to the host draw; k <= kRowsDevMax, s <= 2^31.
+constexpr int kRowsDevMax = 4096;
+bool launch_srht_rows(hipStream_t st, int* rows, int64_t s, const SketchArgs& sk);
 template <typename T, typename PT>
 bool launch_sketch_cols(hipStream_t st, const T* X, int64_t ldx, int64_t n, int ncols, int G,
                         const SketchArgs& sk, PT* partials);

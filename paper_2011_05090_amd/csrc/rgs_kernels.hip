@@ -45,6 +45,58 @@ __global__ void k_srht_signs(uint32_t* __restrict__ signs, int64_t nwords, uint3
     srht_signs_body(signs, nwords, k0, k1, sid, inst, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// The k sampled rows of the P-SRHT (partial Fisher-Yates over [0, s), the
+// same draws and swaps as the host's draw: draw t uses Philox(t, 0xFFFFFFFE,
+// sketch_id, instance) and swaps position t with t + floor((x1 2^32 + x0)
+// (s - t) / 2^64); rows kept in draw order), for callers that cannot copy a
+// host table.  One workgroup: the draws of 256 consecutive t are made in
+// parallel, the swaps -- a sequential chain -- by one lane, on positions < k
+// held directly and positions >= k (at most k of them are ever touched) in an
+// open-addressing table, both in LDS (k <= kRowsDevMax).
+constexpr int kRowsHashBits = 13;   // 8192 slots: load factor <= 1/2 for k <= 4096
+
+__global__ __launch_bounds__(256) void k_srht_rows(int* __restrict__ rows, int64_t s, int k, uint32_t k0,
+                                                   uint32_t k1, uint32_t sid, uint32_t inst) {
+    __shared__ uint32_t low[kRowsDevMax];                       // value at position p < k
+    __shared__ unsigned long long slot[1 << kRowsHashBits];     // (p + 1) << 32 | value for p >= k; 0 = empty
+    __shared__ uint32_t draw[256];
+    for (int p = threadIdx.x; p < k; p += 256) low[p] = (uint32_t)p;
+    for (int p = threadIdx.x; p < (1 << kRowsHashBits); p += 256) slot[p] = 0ull;
+    __syncthreads();
+    for (int t0 = 0; t0 < k; t0 += 256) {
+        const int t = t0 + (int)threadIdx.x;
+        if (t < k) {
+            uint32_t x[4];
+            philox4x32_10((uint32_t)t, kTagRows, sid, inst, k0, k1, x);
+            const uint64_t r64 = ((uint64_t)x[1] << 32) | x[0];
+            draw[threadIdx.x] = (uint32_t)((uint64_t)t + __umul64hi(r64, (uint64_t)(s - t)));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nt = min(256, k - t0);
+            for (int j = 0; j < nt; ++j) {
+                const uint32_t tt = (uint32_t)(t0 + j), ii = draw[j];
+                const uint32_t at = low[tt];
+                uint32_t ai;
+                if (ii < (uint32_t)k) {
+                    ai = low[ii];
+                    low[ii] = at;
+                } else {
+                    uint32_t h = (ii * 2654435761u) >> (32 - kRowsHashBits);
+                    const unsigned long long key = (unsigned long long)(ii + 1u) << 32;
+                    while (slot[h] != 0ull && (slot[h] & 0xFFFFFFFF00000000ull) != key)
+                        h = (h + 1) & ((1u << kRowsHashBits) - 1);
+                    ai = slot[h] == 0ull ? ii : (uint32_t)slot[h];
+                    slot[h] = key | at;
+                }
+                low[tt] = ai;
+                rows[tt] = (int)ai;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Batched: map blocks are (factorisation, 256 groups of 4 sign words).
 __global__ void kb_srht_signs(const BatchItem* __restrict__ items, BlockMap map) {
     const int2 bm = locate(map, blockIdx.x);
@@ -869,6 +921,13 @@ bool launch_srht_signs(hipStream_t st, uint32_t* signs, int64_t nwords, const Sk
     const int64_t nthr = (nwords + 3) / 4;
     hipLaunchKernelGGL(k_srht_signs, dim3(nblocks(nthr, 256)), dim3(256), 0, st, signs, nwords, sk.k0,
                        sk.k1, sk.sid, sk.inst);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+bool launch_srht_rows(hipStream_t st, int* rows, int64_t s, const SketchArgs& sk) {
+    if (sk.k < 1 || sk.k > kRowsDevMax || s < sk.k || s > ((int64_t)1 << 31)) return false;
+    hipLaunchKernelGGL(k_srht_rows, dim3(1), dim3(256), 0, st, rows, s, sk.k, sk.k0, sk.k1, sk.sid, sk.inst);
     RGS_LAUNCH_CHECK();
     return true;
 }

@@ -45,8 +45,8 @@ def test_binding_signatures_cover_the_header():
 
 
 def test_abi_version_and_status_strings(lib):
-    assert rgs.rgs_abi_version() == 2
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    assert rgs.rgs_abi_version() == 3
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = rgs.status_string(code)
         assert s and "unknown" not in s
     assert "unknown" in rgs.status_string(-99)
@@ -56,6 +56,8 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.rgs_create(None, 0, None) == rgs.RGS_EINVAL
     d = rgs.qr_desc(1000, 10, 64)
     assert lib.rgs_qr(None, ctypes.byref(d), None, 1000, None, 1000, None, 10, None, 64, None) == rgs.RGS_EINVAL
+    assert lib.rgs_qr_noalloc(None, ctypes.byref(d), None, 1000, None, 1000, None, 10, None, 64,
+                              None) == rgs.RGS_EINVAL
     assert lib.rgs_destroy(None) == rgs.RGS_EINVAL
     A = rgs.stencil7((4, 4, 4), (6, -1, -1, -1, -1, -1, -1))
     g = rgs.gmres_desc(10, 40, 1e-6)
