@@ -268,12 +268,15 @@ def copy_ceiling(torch, dev, reps=7):
     return 2.0 * (1 << 30) / sorted(times)[len(times) // 2] / 1e9
 
 
-def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian"), steps=2, warmup=1,
-                   gaussian_batch=2048):
+def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian", "gaussian_bf16_table"), steps=2,
+                   warmup=1, gaussian_batch=2048):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
     m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and bf16-stored Q, all in
-    one rgs_qr_batched call, with the P-SRHT and with the Gaussian sketch (the
-    factorisations share one master Gaussian matrix)."""
+    one rgs_qr_batched call, with the P-SRHT, with the Gaussian sketch (the
+    factorisations share one master Gaussian matrix, entries drawn in the
+    products) and with that master matrix's bf16 entries made once per call
+    into a table that the products read through bf16 matrix cores
+    (RGS_FLAG_THETA_BF16)."""
     ns, ms_ = synth.batch_qr_sizes(batch)
     items = []
     t0 = time.perf_counter()
@@ -293,12 +296,14 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
     for sketch in sketches:
         its = items if sketch == "srht" else items[:gaussian_batch]
         B = sum(batched_qr_bytes(W.shape[0], W.shape[1]) for W, *_ in its)
+        lib_sketch = "srht" if sketch == "srht" else "gaussian"
+        flags = rgs.FLAG_THETA_BF16 if sketch == "gaussian_bf16_table" else 0
         for _ in range(warmup):
-            rgs.rgs_qr_batched(h, its, sketch=sketch, prec="bf16q")
+            rgs.rgs_qr_batched(h, its, sketch=lib_sketch, prec="bf16q", flags=flags)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            rep, stat, _ = rgs.rgs_qr_batched(h, its, sketch=sketch, prec="bf16q")
+            rep, stat, _ = rgs.rgs_qr_batched(h, its, sketch=lib_sketch, prec="bf16q", flags=flags)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         bad = sum(1 for v in stat if v != 0)
@@ -308,8 +313,8 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
         for W, Q, R, S, _ in its[:: max(1, len(its) // 8)]:
             be, d2, _ = quality(torch, W, Q.float(), R, S)
             worst_be, worst_d2 = max(worst_be, be), max(worst_d2, d2)
-        if sketch == "gaussian":
-            out["gaussian_schedule"] = rgs.rgs_last_tuning(h)   # autotuned sketch-product schedule (1..4)
+        if sketch != "srht":   # autotuned sketch-product schedule (1..9)
+            out[sketch + "_schedule"] = rgs.rgs_last_tuning(h)
         out[sketch] = {"items": len(its), "seconds": dt, "algorithmic_bytes": B, "gbs": B / dt / 1e9,
                        "pct_hbm_peak": 100.0 * B / dt / 1e9 / HBM_PEAK_GBS, "failed_items": bad,
                        "status": rep.status, "sampled_max_backward_error": worst_be,

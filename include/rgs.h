@@ -94,7 +94,7 @@ typedef enum {
                                     fp64 products and O(m^3) host work.  Not with IDENTITY (EINVAL).
                                     With RGS_FLAG_THETA_BF16, Phi is the Gaussian sketch (not its
                                     bf16 variant). */
-#define RGS_FLAG_THETA_BF16 16u  /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_gmres_batched,
+#define RGS_FLAG_THETA_BF16 16u  /* GAUSSIAN only (rgs_qr, rgs_qr_batched_ex, rgs_gmres, rgs_gmres_batched,
                                     rgs_sketch_apply, rgs_sketch_materialize): the Gaussian sketch
                                     with bf16 entries,
                                     theta = bf16(z)/sqrt(k), z the fp64 Box-Muller value of the
@@ -215,16 +215,19 @@ rgs_status rgs_destroy(rgs_handle *h);
 /* Re-bind the handle to another stream of the same device. */
 rgs_status rgs_set_stream(rgs_handle *h, rgs_stream stream);
 
-/* Autotuner of the batched Gaussian sketch product (rgs_qr_batched with the
- * Gaussian sketch).  Its schedules -- 64 or 32 operand columns per work unit,
- * units in plain or XCD-grouped order -- give identical results; with
- * mode 0 (default) the handle times the four on the first column step of the
- * first call for a batch signature (precision and every (n, m, k)) and keeps
- * the fastest for later calls with that signature; mode 1..4 always uses that
- * schedule (1: 64/plain, 2: 64/XCD, 3: 32/plain, 4: 32/XCD).  EINVAL otherwise. */
+/* Autotuner of the batched Gaussian sketch product (rgs_qr_batched and
+ * rgs_qr_batched_ex with the Gaussian sketch).  Its schedules -- 64, 32 or
+ * 128 operand columns per work unit; units in plain order, grouped so that
+ * the units reading the same columns share an XCD, or with every unit of one
+ * row chunk on one XCD -- give identical results; with mode 0 (default) the
+ * handle times the nine on the first column step of the first call for a
+ * batch signature (precision, sketch entries and every (n, m, k)) and keeps
+ * the fastest for later calls with that signature; mode 1..9 always uses that
+ * schedule (1: 64/plain, 2: 64/XCD, 3: 32/plain, 4: 32/XCD, 5: 64/chunk,
+ * 6: 32/chunk, 7: 128/plain, 8: 128/XCD, 9: 128/chunk).  EINVAL otherwise. */
 rgs_status rgs_set_tuning(rgs_handle *h, int32_t mode);
 
-/* The schedule (1..4) the last batched Gaussian QR on this handle used, 0 if none. */
+/* The schedule (1..9) the last batched Gaussian QR on this handle used, 0 if none. */
 int32_t rgs_last_tuning(const rgs_handle *h);
 
 /* RGS QR factorisation, Algorithm 2 (Sec. 2.3), W = Q R.
@@ -287,6 +290,18 @@ rgs_status rgs_qr_noalloc(rgs_handle *h, const rgs_qr_desc *desc,
 rgs_status rgs_qr_batched(rgs_handle *h, int64_t batch, const rgs_qr_item *items, int32_t sketch,
                           int32_t prec, uint64_t seed, uint32_t sketch_id, int32_t *item_status,
                           int64_t *failed_column, rgs_report *rep);
+
+/* rgs_qr_batched with flags: 0, or RGS_FLAG_THETA_BF16 with the GAUSSIAN
+ * sketch -- the master matrix with bf16 entries, bf16(z)/sqrt(k_b) (the
+ * entries the flag gives rgs_qr), made once per call into a table of
+ * 2 max(k_b) * 16 ceil(max(n_b)/16) bytes of the handle's scratch; the
+ * products of steps 1 and 4 then read it through bf16 matrix-core
+ * instructions (exact products: fp32 columns are split into three bf16
+ * parts, bf16-basis columns are exact; fp32 accumulation) instead of drawing
+ * the entries.  EINVAL for any other flag or sketch. */
+rgs_status rgs_qr_batched_ex(rgs_handle *h, int64_t batch, const rgs_qr_item *items, int32_t sketch,
+                             int32_t prec, uint64_t seed, uint32_t sketch_id, uint32_t flags,
+                             int32_t *item_status, int64_t *failed_column, rgs_report *rep);
 
 /* Y = Theta X for ncols columns (the sketch of steps 1 and 4 of Algorithm 2).
  *   X [n x ncols, ldx >= n], element type per desc->prec; Y [k x ncols, ldy >= k].

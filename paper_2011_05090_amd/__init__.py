@@ -105,6 +105,10 @@ SIGNATURES = {
     "rgs_qr_batched": (ctypes.c_int, [_P, _I64, ctypes.POINTER(QrItem), ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Report)]),
+    "rgs_qr_batched_ex": (ctypes.c_int, [_P, _I64, ctypes.POINTER(QrItem), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(Report)]),
     "rgs_gmres_batched": (ctypes.c_int, [_P, _I64, ctypes.POINTER(GmresItem), ctypes.POINTER(GmresDesc),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Report)]),
 }
@@ -258,8 +262,9 @@ def rgs_qr_noalloc(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINI
 
 
 def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id=0,
-                   allow=(RGS_EBREAKDOWN, RGS_ENONFINITE)):
+                   allow=(RGS_EBREAKDOWN, RGS_ENONFINITE), flags=0):
     """A batch of factorisations; items = list of (W, Q, R, S, k) device tensors.
+    flags: 0 (rgs_qr_batched) or FLAG_THETA_BF16 with the Gaussian sketch (rgs_qr_batched_ex).
     Returns (Report, per-item statuses, per-item failed columns)."""
     import torch
     dw, dq = _dtypes(PREC[prec])
@@ -273,15 +278,19 @@ def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id
     stat = (ctypes.c_int32 * len(items))()
     fcol = (ctypes.c_int64 * len(items))()
     rep = Report()
-    st = lib().rgs_qr_batched(handle.ptr, len(items), arr, SKETCH[sketch], PREC[prec], seed, sketch_id, stat, fcol,
-                              ctypes.byref(rep))
+    if flags:
+        st = lib().rgs_qr_batched_ex(handle.ptr, len(items), arr, SKETCH[sketch], PREC[prec], seed, sketch_id, flags,
+                                     stat, fcol, ctypes.byref(rep))
+    else:
+        st = lib().rgs_qr_batched(handle.ptr, len(items), arr, SKETCH[sketch], PREC[prec], seed, sketch_id, stat,
+                                  fcol, ctypes.byref(rep))
     _check(st, "rgs_qr_batched", allow)
     rep.status = st
     return rep, list(stat), list(fcol)
 
 
 def rgs_set_tuning(handle, mode):
-    """0: autotune the batched Gaussian sketch product per batch signature; 1..4: force a schedule."""
+    """0: autotune the batched Gaussian sketch product per batch signature; 1..9: force a schedule."""
     _check(lib().rgs_set_tuning(handle.ptr, int(mode)), "rgs_set_tuning")
 
 

@@ -958,14 +958,24 @@ void parallel_for(int64_t count, F f) {
 
 // Schedules of the batched Gaussian sketch product that the autotuner picks
 // from: columns per work unit, and the order of the units in the launch --
-// plain, or XCD-grouped (the units of one (column tile, row chunk) pair, which
-// read the same operand columns, are placed 8 apart so that the round-robin
-// dispatch over the 8 XCDs puts them on the same L2).  Every schedule gives
-// the same bits: each partial is one unit's fixed-order sum.
+// plain; XCD-grouped (xcd 1: the units of one (column tile, row chunk) pair,
+// which read the same operand columns, are placed 8 apart so that the
+// round-robin dispatch over the 8 XCDs puts them on the same L2); or
+// chunk-affine (xcd 2: every unit of row chunk b goes to XCD b mod 8, chunk by
+// chunk, tile by tile, so one L2 holds a chunk's sketch entries -- the bf16
+// table's slice -- for all the column tiles that read it, and each tile's
+// columns for all its sketch-row tiles).  Every schedule gives the same bits:
+// each partial is one unit's fixed-order sum.
 struct GemmSchedule {
     int tile, xcd;
 };
-constexpr GemmSchedule kGemmSchedules[4] = {{64, 0}, {64, 1}, {32, 0}, {32, 1}};
+constexpr int kNumSchedules = 9;
+constexpr GemmSchedule kGemmSchedules[kNumSchedules] = {{64, 0},  {64, 1},  {32, 0},  {32, 1}, {64, 2},
+                                                        {32, 2}, {128, 0}, {128, 1}, {128, 2}};
+// Column-tile widths of the step-4 unit lists; unit list of a schedule's tile.
+constexpr int kNumWidths = 3;
+constexpr int kTileWidths[kNumWidths] = {64, 32, 128};
+constexpr int width_index(int tile) { return tile == 64 ? 0 : tile == 32 ? 1 : 2; }
 
 // Streams a batched QR call spreads its factorisations over, and a batched
 // GMRES call its systems.
@@ -981,12 +991,17 @@ void order_units(const std::vector<GemmUnit>& in, size_t a, size_t b, int xcd, s
         out.insert(out.end(), in.begin() + a, in.begin() + b);
         return;
     }
-    // group = consecutive units with the same (first, blk); queue = group index mod 8
     std::vector<std::vector<GemmUnit>> q(8);
-    int g = -1;
-    for (size_t u = a; u < b; ++u) {
-        if (u == a || in[u].first != in[u - 1].first || in[u].blk != in[u - 1].blk) ++g;
-        q[g % 8].push_back(in[u]);
+    if (xcd == 2) {   // queue = row chunk mod 8, ordered by chunk, then (as built) tile and sketch-row tile
+        for (size_t u = a; u < b; ++u) q[in[u].blk % 8].push_back(in[u]);
+        for (auto& qq : q)
+            std::stable_sort(qq.begin(), qq.end(), [](const GemmUnit& x, const GemmUnit& y) { return x.blk < y.blk; });
+    } else {   // group = consecutive units with the same (first, blk); queue = group index mod 8
+        int g = -1;
+        for (size_t u = a; u < b; ++u) {
+            if (u == a || in[u].first != in[u - 1].first || in[u].blk != in[u - 1].blk) ++g;
+            q[g % 8].push_back(in[u]);
+        }
     }
     std::vector<size_t> pos(8, 0);
     for (size_t done = 0; done < b - a;)
@@ -1013,18 +1028,19 @@ struct QrItemOff {
 struct QrGroup {
     std::vector<int64_t> order;   // indices into the caller's items
     int64_t max_m = 0;
+    int64_t rows_p = 0;           // row chunk of the step-1 Gaussian product
     std::vector<int> active;      // active[i]: factorisations with a column i
     std::vector<int64_t> pre_proj, pre_sl, pre_row, pre_sign, pre_part, pre_red;
     std::vector<QrItemOff> off;
     size_t o_rows = 0, o_status = 0, o_items = 0, o_pre = 0, o_gcols = 0, o_gunits_p = 0, o_gunits = 0,
            o_gtune = 0;
     // Gaussian: the step-1 product over (item, column) tiles, and per column the
-    // active items ordered by n (descending) in tiles of 64 or 32; each tile is
+    // active items ordered by n (descending) in tiles of 64, 32 or 128; each tile is
     // split into work units of one row chunk and 128 sketch rows
     std::vector<int2> g_cols;
     std::vector<GemmUnit> g_units_p;   // step 1
-    std::vector<GemmUnit> g_units[2];  // step 4, tile widths 64 and 32, all columns
-    std::vector<size_t> g_at[2];       // per column offsets into g_units[w]
+    std::vector<GemmUnit> g_units[kNumWidths];  // step 4, tile widths kTileWidths, all columns
+    std::vector<size_t> g_at[kNumWidths];       // per column offsets into g_units[w]
     std::vector<BatchItem> bi;
     std::vector<int> rows_all;
     std::vector<int64_t> pre_all;
@@ -1034,8 +1050,8 @@ struct QrGroup {
 
 // step-1 row groups: 4096-row blocks (SRHT, at most 16 groups), 16384-row
 // chunks of the Gaussian product
-int64_t qr_group_gp(int64_t n, int sk_kind) {
-    return sk_kind == SK_GAUSS ? (n + kGemmRowsP - 1) / kGemmRowsP : std::min<int64_t>((n + kBlock - 1) / kBlock, 16);
+int64_t qr_group_gp(int64_t n, int sk_kind, int64_t rows_p) {
+    return sk_kind == SK_GAUSS ? (n + rows_p - 1) / rows_p : std::min<int64_t>((n + kBlock - 1) / kBlock, 16);
 }
 
 // step-4 block partials per column
@@ -1044,7 +1060,12 @@ int64_t qr_group_npart(int64_t n, int sk_kind) {
 }
 
 // Launch tables and workspace layout of one share (g.order already set).
-void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c) {
+// table: the Gaussian products read the bf16 table; step 1 then runs over
+// kGemmRows-row chunks in chunk-affine order (a chunk's table slice for every
+// sketch-row tile fits one L2 beside a tile's columns), otherwise over
+// kGemmRowsP-row chunks in the order built.
+void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, bool table, Carver& c) {
+    g.rows_p = table ? kGemmRows : kGemmRowsP;
     typedef float T;
     const int64_t cnt = (int64_t)g.order.size();
     auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[g.order[q]]; };
@@ -1059,7 +1080,7 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c)
     g.pre_row = prefix_of(cnt, [&](int64_t q) { return (it_of(q).n + 1023) / 1024; });
     g.pre_sign = prefix_of(cnt, [&](int64_t q) { return ((it_of(q).n + 31) / 32 + 1023) / 1024; });
     g.pre_part = prefix_of(
-        cnt, [&](int64_t q) { return sk_kind == SK_GAUSS ? 0 : qr_group_gp(it_of(q).n, sk_kind) * it_of(q).m; });
+        cnt, [&](int64_t q) { return sk_kind == SK_GAUSS ? 0 : qr_group_gp(it_of(q).n, sk_kind, g.rows_p) * it_of(q).m; });
     g.pre_red = prefix_of(cnt, [&](int64_t q) { return ((it_of(q).k + 31) / 32) * it_of(q).m; });
     g.off.resize((size_t)cnt);
     int64_t ktot = 0;
@@ -1070,7 +1091,7 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c)
         QrItemOff& o = g.off[q];
         o.signs = c.take<uint32_t>(sk_kind == SK_SRHT ? (n + 31) / 32 + 4 : 1);
         o.part = c.take<T>(std::max<int64_t>(nproj, qr_group_npart(n, sk_kind)) * k);
-        o.partP = c.take<double>(qr_group_gp(n, sk_kind) * k * m);   // fp64 for SRHT, T for the Gaussian sketch
+        o.partP = c.take<double>(qr_group_gp(n, sk_kind, g.rows_p) * k * m);   // fp64 for SRHT, T for the Gaussian sketch
         o.P = c.take<double>(k * m);
         o.Vc = c.take<double>(k * m);
         o.Vr = c.take<double>(k * m);
@@ -1128,10 +1149,15 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c)
                 for (int64_t c2 = 0; c2 < it_of(q).m; ++c2) g.g_cols.push_back(make_int2((int)q, (int)c2));
             const int total = (int)g.g_cols.size() - first0;
             for (int t0 = 0; t0 < total; t0 += kGemmTileP)
-                add_tile(g.g_units_p, first0 + t0, std::min(kGemmTileP, total - t0), kGemmRowsP);
+                add_tile(g.g_units_p, first0 + t0, std::min(kGemmTileP, total - t0), g.rows_p);
+            if (table) {
+                std::vector<GemmUnit> ord_units;
+                order_units(g.g_units_p, 0, g.g_units_p.size(), 2, ord_units);
+                g.g_units_p.swap(ord_units);
+            }
         }
         std::vector<int> act;
-        for (int w = 0; w < 2; ++w) g.g_at[w].assign((size_t)g.max_m + 1, 0);
+        for (int w = 0; w < kNumWidths; ++w) g.g_at[w].assign((size_t)g.max_m + 1, 0);
         for (int64_t i = 0; i < g.max_m; ++i) {   // step 4 of column i: active items by k class of 128, then n
             const int a = g.active[i];
             act.resize((size_t)a);
@@ -1139,21 +1165,24 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, Carver& c)
             std::stable_sort(act.begin(), act.end(), by_class(128));
             const int base = (int)g.g_cols.size();
             for (int q = 0; q < a; ++q) g.g_cols.push_back(make_int2(act[q], (int)i));
-            for (int w = 0; w < 2; ++w) {
-                const int tile = kGemmSchedules[2 * w].tile;
+            for (int w = 0; w < kNumWidths; ++w) {
+                const int tile = kTileWidths[w];
                 for (int t0 = 0; t0 < a; t0 += tile) add_tile(g.g_units[w], base + t0, std::min(tile, a - t0), kGemmRows);
                 g.g_at[w][i + 1] = g.g_units[w].size();
             }
         }
     }
-    const size_t n_units_max = std::max(g.g_units[0].size(), g.g_units[1].size());
+    size_t n_units_max = 0, n_units_col1 = 0;   // all columns; the first two columns (the tuning step)
+    for (int w = 0; w < kNumWidths; ++w) {
+        n_units_max = std::max(n_units_max, g.g_units[w].size());
+        n_units_col1 = std::max(n_units_col1, g.g_at[w].size() > 2 ? g.g_at[w][2] : (size_t)0);
+    }
     g.o_gcols = c.take<int2>(std::max<size_t>(g.g_cols.size(), 1));
     g.o_gunits_p = c.take<GemmUnit>(std::max<size_t>(g.g_units_p.size(), 1));
     g.o_gunits = c.take<GemmUnit>(std::max<size_t>(n_units_max, 1));
     size_t tune_units = 1;
     if (sk_kind == SK_GAUSS)
-        tune_units = 4 * std::max<size_t>(1, std::max(g.g_at[0].size() > 2 ? g.g_at[0][2] : 0,
-                                                      g.g_at[1].size() > 2 ? g.g_at[1][2] : 0));
+        tune_units = kNumSchedules * std::max<size_t>(1, n_units_col1);
     g.o_gtune = c.take<GemmUnit>(tune_units);
 }
 
@@ -1186,7 +1215,7 @@ void bind_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, uint64_t s
         x.lds = it.lds;
         x.P = reinterpret_cast<double*>(A + o.P);
         x.partP = A + o.partP;
-        x.G_P = (int)qr_group_gp(it.n, sk_kind);
+        x.G_P = (int)qr_group_gp(it.n, sk_kind, g.rows_p);
         x.part = A + o.part;
         x.coef = A + o.coef;
         x.sketch_scale = 1.0 / std::sqrt((double)it.k);
@@ -1256,12 +1285,24 @@ struct QrGroupLauncher {
                   *d_red = nullptr;
     GemmUnit *d_units = nullptr, *d_tune = nullptr;
     const int2* d_cols = nullptr;
+    // RGS_FLAG_THETA_BF16: the master matrix's bf16 entries (tk rows, tgroups groups of 8 columns)
+    const uint16_t* table = nullptr;
+    int tk = 0;
+    int64_t tgroups = 0;
 
     QrGroupLauncher(rgs_handle* h_, QrGroup& g_, int sk, char* A_, hipStream_t s_)
         : h(h_), g(g_), sk_kind(sk), A(A_), s(s_) {}
 
+    // one product of the Gaussian sketch: drawn entries (fp32 MFMA) or table entries (bf16 MFMA)
+    template <typename TB, bool STEP4>
+    bool product(const GemmUnit* units, int nunits, int rows, int tile) {
+        if (table)
+            return launch_batch_table_gemm<TB, STEP4>(s, itd, units, nunits, d_cols, rows, tile, table, tk, tgroups);
+        return launch_batch_gauss_gemm<TB, STEP4>(s, itd, units, nunits, d_cols, rows, tile);
+    }
+
     bool upload_schedule(int sc) {
-        const int w = kGemmSchedules[sc - 1].tile == 64 ? 0 : 1;
+        const int w = width_index(kGemmSchedules[sc - 1].tile);
         g.sched_units.clear();
         for (int64_t i = 0; i < g.max_m; ++i)
             order_units(g.g_units[w], g.g_at[w][i], g.g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, g.sched_units);
@@ -1300,8 +1341,8 @@ struct QrGroupLauncher {
         if (gemm && sched > 0 && !upload_schedule(sched)) return RGS_EDEVICE;
         if (!launch_batch_init(s, itd, nb, g.max_m * g.max_m)) return RGS_EDEVICE;
         // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
-        if (gemm && !launch_batch_gauss_gemm<T, false>(s, itd, reinterpret_cast<const GemmUnit*>(A + g.o_gunits_p),
-                                                       (int)g.g_units_p.size(), d_cols, (int)kGemmRowsP, kGemmTileP))
+        if (gemm && !product<T, false>(reinterpret_cast<const GemmUnit*>(A + g.o_gunits_p), (int)g.g_units_p.size(),
+                                       (int)g.rows_p, kGemmTileP))
             return RGS_EDEVICE;
         if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, g.pre_sign[nb],
                                       BlockMap{d_part, nullptr, nb, 0}, g.pre_part[nb],
@@ -1311,7 +1352,7 @@ struct QrGroupLauncher {
     }
 
     // Column i (i < g.max_m).  sched: the Gaussian step-4 schedule; 0 = time
-    // the four on this column's product (the first column that needs it),
+    // the six on this column's product (the first column that needs it),
     // keep the fastest and record it under sig.
     rgs_status step(int64_t i, int& sched, uint64_t sig) {
         const int a = g.active[i], a1 = g.active[i + 1];
@@ -1321,28 +1362,28 @@ struct QrGroupLauncher {
                                                 (int)i))
             return RGS_EDEVICE;
         if (gemm && sched == 0 && i == i_tune) {
-            std::vector<GemmUnit> tu[4];
-            size_t off_t[5] = {0, 0, 0, 0, 0};
-            for (int sc = 1; sc <= 4; ++sc) {
-                const int w = kGemmSchedules[sc - 1].tile == 64 ? 0 : 1;
+            std::vector<GemmUnit> tu[kNumSchedules];
+            size_t off_t[kNumSchedules + 1] = {};
+            for (int sc = 1; sc <= kNumSchedules; ++sc) {
+                const int w = width_index(kGemmSchedules[sc - 1].tile);
                 order_units(g.g_units[w], g.g_at[w][i], g.g_at[w][i + 1], kGemmSchedules[sc - 1].xcd, tu[sc - 1]);
                 off_t[sc] = off_t[sc - 1] + tu[sc - 1].size();
                 if (hipMemcpyAsync(d_tune + off_t[sc - 1], tu[sc - 1].data(), tu[sc - 1].size() * sizeof(GemmUnit),
                                    hipMemcpyHostToDevice, s) != hipSuccess)
                     return RGS_EDEVICE;
             }
-            if (ensure_events(h, 10) != RGS_OK) return RGS_EDEVICE;
+            if (ensure_events(h, 2 * kNumSchedules) != RGS_OK) return RGS_EDEVICE;
             for (int rep2 = 0; rep2 < 2; ++rep2)   // the first round warms the caches
-                for (int sc = 1; sc <= 4; ++sc) {
+                for (int sc = 1; sc <= kNumSchedules; ++sc) {
                     (void)hipEventRecord(h->events[2 * sc - 2], s);
-                    if (!launch_batch_gauss_gemm<TQ, true>(s, itd, d_tune + off_t[sc - 1], (int)tu[sc - 1].size(),
-                                                           d_cols, (int)kGemmRows, kGemmSchedules[sc - 1].tile))
+                    if (!product<TQ, true>(d_tune + off_t[sc - 1], (int)tu[sc - 1].size(), (int)kGemmRows,
+                                           kGemmSchedules[sc - 1].tile))
                         return RGS_EDEVICE;
                     (void)hipEventRecord(h->events[2 * sc - 1], s);
                 }
             if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;   // tu stays alive till here
             float best = 0.f;
-            for (int sc = 1; sc <= 4; ++sc) {
+            for (int sc = 1; sc <= kNumSchedules; ++sc) {
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, h->events[2 * sc - 2], h->events[2 * sc - 1]);
                 if (sched == 0 || ms < best) {
@@ -1354,10 +1395,9 @@ struct QrGroupLauncher {
         }
         if (gemm && (DEFER || i > 0)) {
             if (uploaded != sched && !upload_schedule(sched)) return RGS_EDEVICE;
-            const int w = kGemmSchedules[sched - 1].tile == 64 ? 0 : 1;
-            if (!launch_batch_gauss_gemm<TQ, true>(s, itd, d_units + g.g_at[w][i],
-                                                   (int)(g.g_at[w][i + 1] - g.g_at[w][i]), d_cols, (int)kGemmRows,
-                                                   kGemmSchedules[sched - 1].tile))
+            const int w = width_index(kGemmSchedules[sched - 1].tile);
+            if (!product<TQ, true>(d_units + g.g_at[w][i], (int)(g.g_at[w][i + 1] - g.g_at[w][i]), (int)kGemmRows,
+                                   kGemmSchedules[sched - 1].tile))
                 return RGS_EDEVICE;
         }
         if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, g.pre_sl[a],
@@ -1375,7 +1415,8 @@ struct QrGroupLauncher {
 
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
-                          uint32_t sid, int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
+                          uint32_t sid, bool use_table, int32_t* item_status, int64_t* failed_column,
+                          rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<int64_t> order((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) order[b] = b;
@@ -1384,11 +1425,26 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     std::vector<QrGroup> grp((size_t)ng);
     for (int64_t q = 0; q < batch; ++q) grp[q % ng].order.push_back(order[q]);
     Carver c;
-    for (QrGroup& g : grp) plan_qr_group(g, items, sk_kind, c);
-    // the batch signature of the tuning cache: precision, shares and every (n, m, k)
+    for (QrGroup& g : grp) plan_qr_group(g, items, sk_kind, use_table, c);
+    // RGS_FLAG_THETA_BF16: one table of the master matrix's bf16 entries,
+    // rows 0 .. max k - 1, columns padded to whole 16-row k-steps of the product
+    int tk = 0;
+    int64_t tgroups = 0;
+    size_t o_table = 0;
+    if (use_table) {
+        int64_t nmax = 0;
+        for (int64_t b = 0; b < batch; ++b) {
+            tk = std::max<int>(tk, (int)items[b].k);
+            nmax = std::max<int64_t>(nmax, items[b].n);
+        }
+        tgroups = 2 * ((nmax + 15) / 16);
+        o_table = c.take<uint16_t>((size_t)tgroups * 8 * (size_t)tk);
+    }
+    // the batch signature of the tuning cache: precision, sketch entries, shares and every (n, m, k)
     uint64_t sig = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
     mix((uint64_t)DEFER);
+    mix((uint64_t)use_table);
     mix((uint64_t)ng);
     for (int64_t q = 0; q < batch; ++q) {
         mix((uint64_t)items[order[q]].n);
@@ -1408,6 +1464,10 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         if (h->tune_mode > 0) sched = h->tune_mode;
         else if (h->gemm_tuned.count(sig)) sched = h->gemm_tuned[sig];
     }
+    // the table is made on the handle's stream before the shares fork from it
+    if (use_table && !launch_theta_table(h->stream, make_sketch(SK_GAUSS, tk, seed, sid, 0u), tgroups * 8,
+                                         reinterpret_cast<uint16_t*>(A + o_table)))
+        return RGS_EDEVICE;
     static_assert(kQrShares == 2, "the shares past the first run on the one auxiliary stream");
     hipStream_t ss[kQrShares] = {h->stream, h->stream};
     if (ng > 1) {
@@ -1417,7 +1477,14 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
             return RGS_EDEVICE;
     }
     std::vector<QrGroupLauncher<TQ, DEFER>> run;
-    for (int gi = 0; gi < ng; ++gi) run.emplace_back(h, grp[gi], sk_kind, A, ss[gi]);
+    for (int gi = 0; gi < ng; ++gi) {
+        run.emplace_back(h, grp[gi], sk_kind, A, ss[gi]);
+        if (use_table) {
+            run.back().table = reinterpret_cast<const uint16_t*>(A + o_table);
+            run.back().tk = tk;
+            run.back().tgroups = tgroups;
+        }
+    }
     rgs_status est = run[0].begin(sched);
     // an untuned Gaussian product: share 0 (it holds the largest m) runs alone
     // up to the column whose product it times, so the timing sees no other work
@@ -2054,7 +2121,7 @@ rgs_status rgs_destroy(rgs_handle* h) {
 }
 
 rgs_status rgs_set_tuning(rgs_handle* h, int32_t mode) {
-    if (!h || mode < 0 || mode > 4) return RGS_EINVAL;
+    if (!h || mode < 0 || mode > kNumSchedules) return RGS_EINVAL;
     h->tune_mode = mode;
     return RGS_OK;
 }
@@ -2225,23 +2292,34 @@ rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec
     return RGS_EDEVICE;
 }
 
-rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int32_t sketch, int32_t prec,
-                          uint64_t seed, uint32_t sketch_id, int32_t* item_status, int64_t* failed_column,
-                          rgs_report* rep) try {
+rgs_status rgs_qr_batched_ex(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int32_t sketch, int32_t prec,
+                             uint64_t seed, uint32_t sketch_id, uint32_t flags, int32_t* item_status,
+                             int64_t* failed_column, rgs_report* rep) try {
     if (!h || batch < 1 || batch > 65535 || !items) return RGS_EINVAL;
     if (sketch != RGS_SKETCH_GAUSSIAN && sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if (prec != RGS_P_FP32_LS64 && prec != RGS_P_BF16Q_FP32_LS64) return RGS_EINVAL;
+    if ((flags & ~RGS_FLAG_THETA_BF16) != 0) return RGS_EINVAL;
+    const bool tab = (flags & RGS_FLAG_THETA_BF16) != 0;
+    if (tab && sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     const int sk_kind = sketch_kind(sketch);
     for (int64_t b = 0; b < batch; ++b)
         if (!valid_item(items[b], sk_kind)) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (prec == RGS_P_BF16Q_FP32_LS64)
-        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
-    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, item_status, failed_column, rep);
+        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, item_status, failed_column,
+                                          rep);
+    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, item_status, failed_column,
+                                        rep);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;
 } catch (...) {
     return RGS_EDEVICE;
+}
+
+rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int32_t sketch, int32_t prec,
+                          uint64_t seed, uint32_t sketch_id, int32_t* item_status, int64_t* failed_column,
+                          rgs_report* rep) {
+    return rgs_qr_batched_ex(h, batch, items, sketch, prec, seed, sketch_id, 0u, item_status, failed_column, rep);
 }
 
 rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,

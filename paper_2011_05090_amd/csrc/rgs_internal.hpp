@@ -67,7 +67,7 @@ bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, c
                            int64_t n_signs, const BlockMap& map_part, int64_t n_part, const BlockMap& map_red,
                            int64_t n_red, bool acc64);
 // Batched Gaussian sketch products with the shared master matrix, one
-// workgroup per GemmUnit over the (item, column) list `cols` (tile: 32 or 64
+// workgroup per GemmUnit over the (item, column) list `cols` (tile: 32, 64 or 128
 // columns per unit, as the units were built): STEP4, column i
 // of Q (partials per `rows`-row chunk into part); otherwise columns of W
 // (partials per chunk into partP, G_P chunks per column).
@@ -77,6 +77,12 @@ constexpr int kGemmTileP = 64;       // operand columns per unit of the step-1 p
 template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
                              const int2* cols, int rows, int tile);
+// The same products with the bf16 Gaussian entries read from the table
+// (tk rows, tgroups groups of 8 columns, the k_theta_table layout) through
+// bf16 MFMA; rows a multiple of 16.
+template <typename TB, bool STEP4>
+bool launch_batch_table_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
+                             const int2* cols, int rows, int tile, const uint16_t* table, int tk, int64_t tgroups);
 template <typename TW, typename TQ, bool DEFER>
 bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map, int64_t nblk,
                           int i);

@@ -529,6 +529,206 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
     }
 }
 
+// The same products with the bf16 Gaussian entries read from a table
+// (RGS_FLAG_THETA_BF16: theta = bf16(z) / sqrt(k_b), the table holding the
+// unscaled bf16(z) of the master matrix, group (o, j) of 8 columns at
+// ((o tk) + j) 8) instead of drawn: bf16 MFMA 32x32x16 with fp32
+// accumulation.  A bf16 column (the stored q'_i of the bf16 basis) is its own
+// B operand, so every product theta x is exact before the fp32 accumulation;
+// an fp32 column x is split exactly into three bf16 parts,
+// x = hi + mid + lo (hi its leading 8 significand bits, mid the next 8, lo the
+// last 8), and takes three MFMAs with the same A -- again exact products.
+//
+// The rows are walked in super-steps of 16 S rows (S k-steps of 16 rows; S = 4
+// for bf16 columns, 2 for fp32).  The sum over rows does not care which rows
+// form which k-step, so lane L (jr = L % 32, kk = L / 32) of wave w takes
+// rows r + 8 S kk + 8 s .. + 7 as its k-slots of k-step s: its B operand for
+// the whole super-step is 8 S contiguous rows of column jr of each 32-column
+// sub-tile (the two kk lanes of a column together read 16 S contiguous rows,
+// 128 bytes, one cache line), loaded one super-step ahead; its A operand for
+// k-step s is table group r / 8 + S kk + s of sketch row
+// j = 128 jt + 32 w + jr (16 bytes; the 32 lanes of one kk read 512
+// contiguous bytes).  Accumulator t is sketch row 8 (t / 4) + 4 kk + t % 4 of
+// column L % 32 (as for the fp32 MFMA), and the partials go where
+// kb_gauss_gemm puts them.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+
+// 8 S contiguous rows r .. r + 8 S - 1 of a column, raw: S u32x4v of 8 bf16
+// (bf16 column) or 2 S of 4 fp32 bit patterns (fp32 column); zeros past n.
+// The split into bf16 parts (split8) is left to the point of use, so the
+// loads stay in flight meanwhile.
+template <typename TB, int S>
+struct RawRows {
+    u32x4v w[sizeof(TB) == 2 ? S : 2 * S];
+};
+
+template <typename TB, int S>
+__device__ __forceinline__ void ld_rows(const TB* __restrict__ col, int64_t r, int64_t n, bool vec,
+                                        RawRows<TB, S>& out) {
+    if constexpr (sizeof(TB) == 2) {
+        const uint16_t* c = reinterpret_cast<const uint16_t*>(col);
+        if (vec && r + 8 * S <= n) {   // columns start 8-byte aligned (ld a multiple of 4)
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const u32x2 lo = *reinterpret_cast<const u32x2*>(c + r + 8 * q);
+                const u32x2 hi = *reinterpret_cast<const u32x2*>(c + r + 8 * q + 4);
+                out.w[q] = u32x4v{lo.x, lo.y, hi.x, hi.y};
+            }
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            uint32_t w[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) w[t] = (r + 8 * q + t < n) ? (uint32_t)c[r + 8 * q + t] : 0u;
+            out.w[q] = u32x4v{w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16), w[6] | (w[7] << 16)};
+        }
+    } else {
+        if (vec && r + 8 * S <= n) {   // 16-byte aligned: ld a multiple of 4, r a multiple of 8
+#pragma unroll
+            for (int q = 0; q < 2 * S; ++q) out.w[q] = *reinterpret_cast<const u32x4v*>(col + r + 4 * q);
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * S; ++q) {
+            uint32_t w[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) w[t] = (r + 4 * q + t < n) ? __float_as_uint((float)col[r + 4 * q + t]) : 0u;
+            out.w[q] = u32x4v{w[0], w[1], w[2], w[3]};
+        }
+    }
+}
+
+// The B operands of k-step s of a super-step: the 8 bf16 words themselves, or
+// the exact split of each of the 8 fp32 values x into hi + mid + lo (leading 8
+// significand bits, the next 8, the last 8), three bf16x8 operands.
+template <typename TB, int S>
+__device__ __forceinline__ void split8(const RawRows<TB, S>& raw, int s, u32x4v parts[3]) {
+    if constexpr (sizeof(TB) == 2) {
+        parts[0] = raw.w[s];
+    } else {
+        uint32_t h[8], m[8], l[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const uint32_t bx = raw.w[2 * s + t / 4][t % 4];
+            h[t] = bx >> 16;
+            const float rem = __uint_as_float(bx) - __uint_as_float(bx & 0xFFFF0000u);   // exact
+            const uint32_t bm = __float_as_uint(rem);
+            m[t] = bm >> 16;
+            l[t] = __float_as_uint(rem - __uint_as_float(bm & 0xFFFF0000u)) >> 16;   // exact: the last 8 bits
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            parts[0][q] = h[2 * q] | (h[2 * q + 1] << 16);
+            parts[1][q] = m[2 * q] | (m[2 * q + 1] << 16);
+            parts[2][q] = l[2 * q] | (l[2 * q + 1] << 16);
+        }
+    }
+}
+
+template <typename TB, bool STEP4, int NSUB>
+__global__ __launch_bounds__(256) void kb_table_gemm(const BatchItem* __restrict__ items,
+                                                     const GemmUnit* __restrict__ units, const int2* __restrict__ cols,
+                                                     int rows, const uint16_t* __restrict__ table, int tk,
+                                                     int64_t tgroups) {
+    constexpr int NP = sizeof(TB) == 2 ? 1 : 3;   // bf16 parts per operand column
+    constexpr int S = sizeof(TB) == 2 ? 4 : 2;    // k-steps per super-step
+    const GemmUnit un = units[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int jr = lane & 31, kk = lane >> 5;
+    const int j = un.jt * 128 + wave * 32 + jr;
+    const TB* col[NSUB];
+    int64_t nb[NSUB];
+    bool vec[NSUB];
+#pragma unroll
+    for (int s2 = 0; s2 < NSUB; ++s2) {
+        const int c = s2 * 32 + jr;
+        col[s2] = nullptr;
+        nb[s2] = 0;
+        vec[s2] = false;
+        if (c < un.count) {
+            const int2 ic = cols[un.first + c];
+            const BatchItem& it = items[ic.x];
+            col[s2] = STEP4 ? static_cast<const TB*>(it.Q) + (int64_t)ic.y * it.ldq
+                            : static_cast<const TB*>(it.W) + (int64_t)ic.y * it.ldw;
+            nb[s2] = it.n;
+            vec[s2] = it.vec_ok != 0;
+        }
+    }
+    int kmax = 0;
+    int64_t nmax = 0;
+    for (int c = 0; c < un.count; ++c) {
+        const BatchItem& it = items[cols[un.first + c].x];
+        kmax = max(kmax, it.k);
+        nmax = max(nmax, it.n);
+    }
+    if (un.jt * 128 + wave * 32 >= kmax) return;   // wave-uniform; the kernel has no barrier
+    const bool jok = j < tk;
+    // rows is a multiple of 16 S, so a super-step never crosses into the next
+    // chunk; rows at or past nmax read zero columns (and zero table groups past
+    // the table), so the last super-step may run past nmax
+    const int64_t r_begin = (int64_t)un.blk * rows;
+    const int64_t r_end = min(r_begin + (int64_t)rows, nmax);
+    const uint16_t* trow = table + (int64_t)j * 8;
+    auto load_a = [&](int64_t o) {
+        return (jok && o < tgroups) ? *reinterpret_cast<const u32x4v*>(trow + o * tk * 8) : u32x4v{0u, 0u, 0u, 0u};
+    };
+    f32x16 acc[NSUB];
+#pragma unroll
+    for (int s2 = 0; s2 < NSUB; ++s2) acc[s2] = f32x16{0};
+    RawRows<TB, S> b[NSUB];
+    u32x4v a[S];
+#pragma unroll
+    for (int s2 = 0; s2 < NSUB; ++s2) ld_rows<TB, S>(col[s2], r_begin + 8 * S * kk, col[s2] ? nb[s2] : 0, vec[s2], b[s2]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) a[s] = load_a(r_begin / 8 + S * kk + s);
+    for (int64_t r = r_begin; r < r_end; r += 16 * S) {
+        RawRows<TB, S> cb[NSUB];
+        u32x4v ca[S];
+#pragma unroll
+        for (int s2 = 0; s2 < NSUB; ++s2) cb[s2] = b[s2];
+#pragma unroll
+        for (int s = 0; s < S; ++s) ca[s] = a[s];
+        const int64_t rn = r + 16 * S;
+        if (rn < r_end) {   // the next super-step's operands while these are used
+#pragma unroll
+            for (int s2 = 0; s2 < NSUB; ++s2)
+                ld_rows<TB, S>(col[s2], rn + 8 * S * kk, col[s2] ? nb[s2] : 0, vec[s2], b[s2]);
+#pragma unroll
+            for (int s = 0; s < S; ++s) a[s] = load_a(rn / 8 + S * kk + s);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, ca[s]);
+#pragma unroll
+            for (int s2 = 0; s2 < NSUB; ++s2) {
+                u32x4v parts[3];
+                split8<TB, S>(cb[s2], s, parts);
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    acc[s2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, parts[p]),
+                                                                      acc[s2], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < NSUB; ++s2) {
+        const int c = s2 * 32 + jr;
+        if (c >= un.count) continue;
+        const int2 ic = cols[un.first + c];
+        const BatchItem& it = items[ic.x];
+        if (r_begin >= it.n) continue;
+        float* out = STEP4 ? static_cast<float*>(it.part) + (int64_t)un.blk * it.k
+                           : static_cast<float*>(it.partP) + ((int64_t)ic.y * it.G_P + un.blk) * it.k;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int jj = un.jt * 128 + wave * 32 + 8 * (t / 4) + 4 * kk + (t % 4);
+            if (jj < it.k) out[jj] = acc[s2][t];
+        }
+    }
+}
+
 // out[j + col*ldo] = scale * sum_{g=0}^{G-1} partials[(col*G + g)*k + j], in fp64 and
 // in a fixed order: 8 contiguous g-ranges summed by 8 threads, then combined in order.
 template <typename PT>
@@ -989,13 +1189,37 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
 }
 
 template <typename TB, bool STEP4>
+bool launch_batch_table_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
+                             const int2* cols, int rows, int tile, const uint16_t* table, int tk, int64_t tgroups) {
+    if (nunits <= 0) return true;
+    if (rows % 64 != 0) return false;   // whole super-steps per chunk
+    if (tile <= 32)
+        hipLaunchKernelGGL((kb_table_gemm<TB, STEP4, 1>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+                           table, tk, tgroups);
+    else if (tile <= 64)
+        hipLaunchKernelGGL((kb_table_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+                           table, tk, tgroups);
+    else if (tile <= 128)
+        hipLaunchKernelGGL((kb_table_gemm<TB, STEP4, 4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+                           table, tk, tgroups);
+    else
+        return false;
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
                              const int2* cols, int rows, int tile) {
     if (nunits == 0) return true;
     if (tile <= 32)
         hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 1>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
-    else
+    else if (tile <= 64)
         hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
+    else if (tile <= 128)
+        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
+    else
+        return false;
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -1298,6 +1522,12 @@ template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const f
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
                                             double*, const double*);
+template bool launch_batch_table_gemm<float, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
+                                                   int, int, const uint16_t*, int, int64_t);
+template bool launch_batch_table_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
+                                                  int, int, const uint16_t*, int, int64_t);
+template bool launch_batch_table_gemm<float, false>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
+                                                    int, int, const uint16_t*, int, int64_t);
 template bool launch_batch_gauss_gemm<float, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
                                                    int, int);
 template bool launch_batch_gauss_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*, int,

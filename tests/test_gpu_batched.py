@@ -229,15 +229,15 @@ def test_batched_gaussian_many_items_matches_oracle(gpu_handle):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16q"])
 def test_gaussian_schedules_give_identical_bits(gpu_handle, prec):
-    """The autotuner's four schedules of the batched Gaussian sketch product
-    (32 / 64 columns per unit, plain / XCD-grouped order) produce the same
+    """The autotuner's nine schedules of the batched Gaussian sketch product
+    (32 / 64 / 128 columns per unit; plain, XCD-grouped or chunk-affine order) produce the same
     bits; the automatic mode picks one of them and keeps it for the signature."""
     rgs = _rgs()
     qd = torch.bfloat16 if prec == "bf16q" else torch.float32
     data = _batch_inputs(40, seed=7, nmax=30000, mmax=24)
     outs = []
     try:
-        for mode in (1, 2, 3, 4, 0, 0):
+        for mode in (1, 2, 3, 4, 5, 6, 7, 8, 9, 0, 0):
             rgs.rgs_set_tuning(gpu_handle, mode)
             items = []
             for W, k in data:
@@ -248,7 +248,7 @@ def test_gaussian_schedules_give_identical_bits(gpu_handle, prec):
             torch.cuda.synchronize()
             assert rep.status == 0
             used = rgs.rgs_last_tuning(gpu_handle)
-            assert used == mode if mode else used in (1, 2, 3, 4)
+            assert used == mode if mode else used in range(1, 10)
             outs.append(items)
     finally:
         rgs.rgs_set_tuning(gpu_handle, 0)

@@ -1,8 +1,10 @@
 """GPU parity of the batched QR at its full benchmark size: 2048 factorisations
 with n ~ U{4096..262144}, m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and
 bf16-stored Q, in one rgs_qr_batched call -- the inputs and the launch
-configuration bench.py times -- with the P-SRHT (item b uses instance b) and
-with the Gaussian sketch (all items share the master matrix, instance 0).
+configuration bench.py times -- with the P-SRHT (item b uses instance b),
+with the Gaussian sketch (all items share the master matrix, instance 0) and
+with that master matrix's bf16 entries read from a table by bf16 matrix-core
+products (RGS_FLAG_THETA_BF16, rgs_qr_batched_ex).
 
 Every item is checked through properties that hold at any size:
 * status 0, R upper triangular with a positive diagonal, every column of S of
@@ -69,11 +71,13 @@ def _host(t):
     return t.detach().double().cpu().numpy()
 
 
-@pytest.mark.parametrize("sketch", ["srht", "gaussian"])
+@pytest.mark.parametrize("sketch", ["srht", "gaussian", "gaussian_bf16"])
 def test_full_batch(gpu_handle, batch, sketch):
     rgs = _rgs()
     print("batched bf16q QR, %s, %d items" % (sketch, len(batch)), flush=True)
-    rep, stat, fcol = rgs.rgs_qr_batched(gpu_handle, batch, sketch=sketch, prec="bf16q")
+    lib_sketch = "srht" if sketch == "srht" else "gaussian"
+    flags = rgs.FLAG_THETA_BF16 if sketch == "gaussian_bf16" else 0
+    rep, stat, fcol = rgs.rgs_qr_batched(gpu_handle, batch, sketch=lib_sketch, prec="bf16q", flags=flags)
     torch.cuda.synchronize()
     assert rep.status == 0 and all(v == 0 for v in stat) and all(c == -1 for c in fcol)
     worst_srw, worst_d2 = 0.0, 0.0
@@ -82,7 +86,7 @@ def test_full_batch(gpu_handle, batch, sketch):
         assert torch.all(torch.tril(R, -1) == 0) and bool(torch.all(torch.diagonal(R) > 0)), b
         assert float(torch.max(torch.abs(torch.linalg.norm(S, dim=0) - 1.0))) <= 1e-12, b
         TW = rgs.colmajor(k, m, torch.float64)
-        d = rgs.qr_desc(n, m, k, sketch=sketch, prec="fp32", instance=b if sketch == "srht" else 0)
+        d = rgs.qr_desc(n, m, k, sketch=lib_sketch, prec="fp32", instance=b if sketch == "srht" else 0, flags=flags)
         rgs.rgs_sketch_apply(gpu_handle, d, W, TW)
         srw = float(torch.linalg.norm(S @ R - TW) / torch.linalg.norm(TW))
         ev = np.linalg.eigvalsh((S.T @ S).cpu().numpy())
@@ -111,7 +115,8 @@ def test_full_batch(gpu_handle, batch, sketch):
         be, be_ref = metrics.backward_error(W64, Qh, Rh), metrics.backward_error(W64, ref["Q"], ref["R"])
         d2, d2_ref = metrics.delta_2(Sh), metrics.delta_2(ref["S"])
         assert be <= 2 * be_ref, (b, be, be_ref)
-        assert d2 <= (2 if sketch == "srht" else 4) * d2_ref, (b, d2, d2_ref)
+        # the table's entries are the oracle's bf16 entries bit for bit, as with the P-SRHT
+        assert d2 <= (4 if sketch == "gaussian" else 2) * d2_ref, (b, d2, d2_ref)
         TW = theta.apply(W64)                                  # the oracle's Theta
         srw = np.linalg.norm(Sh @ Rh - TW) / np.linalg.norm(TW)
         assert srw <= 4 * U_BF16, (b, srw)
