@@ -112,6 +112,16 @@ def test_fullsize_companion_gate(gpu_handle):
 
 
 def test_fullsize_rgmres_true_residual(gpu_handle):
+    """The 192^3 system with the P-SRHT (k = 400, restart 100, fp32 basis):
+    true residual recomputed on the host in fp64, and the iteration count
+    within +-2 of the fp64 oracle's on the same system and sketches (Sec. 4.2),
+    cached in tests/golden/gmres_c3_srht.json by make_gmres_refs.py (the oracle
+    takes about an hour for it)."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gmres_c3_srht.json")))
+    assert (ref["N"], ref["sketch"], ref["k"], ref["restart"], ref["precision"]) == (192, "srht", 400, 100, "fp64")
+    assert ref["converged"]
     rgs = _rgs()
     Ng = 192
     dims, coeffs = synth.convdiff_coeffs(Ng, 50.0)
@@ -127,6 +137,8 @@ def test_fullsize_rgmres_true_residual(gpu_handle):
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6 * (1 + 1e-6)
     assert len(hist) == rep.iters
     assert math.isclose(rep.true_relres, np.linalg.norm(r) / np.linalg.norm(b), rel_tol=1e-6)
+    print("  192^3 srht fp32 basis: %d iterations (fp64 oracle %d)" % (rep.iters, ref["iters"]), flush=True)
+    assert abs(rep.iters - ref["iters"]) <= 2
 
 
 def _gmres_gpu(h, N, sketch, prec, k=400, restart=100, flags=0):
