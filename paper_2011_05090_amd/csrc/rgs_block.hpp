@@ -351,4 +351,73 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Rademacher sketch of one fp32 block (NW = kProjWaves wave tiles, v = this
+// lane's 16 rows) through signed-sum tables: for every aligned 4-row chunk c
+// of the block and every 4-bit sign pattern m, T[c][m] = sum_r (-1)^{m_r} x_{4c+r}
+// (bit r of m set meaning -1).  The block's rows are the same for all k sketch
+// rows, so the tables are built once and each sketch row then adds one table
+// entry per 4 rows, indexed by the nibble of its Philox sign word that covers
+// them (the bit layout of rad_words / rad_sign), instead of applying 4 signs.
+// The tables of half a block (NW/2 wave tiles: 1024 chunks x 16 floats =
+// 64 KiB of LDS, kRadNibLds floats) are built and consumed at a time.  Within
+// a 128-row group the 32 entries are added in row order; the result differs
+// from the sign-by-sign sum only by fp32 rounding.
+// ---------------------------------------------------------------------------
+constexpr int kRadNibLds = (kProjWaves / 2) * kTile / 4 * 16;
+
+template <typename PT, int NW>
+__device__ __forceinline__ void block_sketch_rad_nib(const float v[16], int64_t blk, int64_t n, const SketchArgs& sk,
+                                                     PT acc[kKptMax], float* __restrict__ lds) {
+    static_assert(NW == kProjWaves, "table layout of a kProjWaves block");
+    constexpr int NT = NW * kWave;
+    constexpr int HW = NW / 2;                 // wave tiles per half
+    constexpr int GH = HW * kTile / 128;       // 128-row groups per half
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int kpt = (sk.k + NT - 1) / NT;
+    const int64_t rem = n - blk * (NW * kTile);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t rem_h = rem - (int64_t)h * HW * kTile;
+        if (rem_h <= 0) break;                 // workgroup-uniform
+        if (wave / HW == h) {                  // this half's waves build the tables of their chunks
+            const int wl = wave - h * HW;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float x0 = v[4 * e], x1 = v[4 * e + 1], x2 = v[4 * e + 2], x3 = v[4 * e + 3];
+                const float p[4] = {x0 + x1, -x0 + x1, x0 - x1, -x0 - x1};   // pattern bits 0-1
+                const float q[4] = {x2 + x3, -x2 + x3, x2 - x3, -x2 - x3};   // pattern bits 2-3
+                float* dst = lds + (wl * (kTile / 4) + 64 * e + lane) * 16;
+#pragma unroll
+                for (int m2 = 0; m2 < 4; ++m2) {
+                    const f32x4 o = {p[0] + q[m2], p[1] + q[m2], p[2] + q[m2], p[3] + q[m2]};
+                    *reinterpret_cast<f32x4*>(dst + 4 * m2) = o;
+                }
+            }
+        }
+        __syncthreads();
+        const int ng = rem_h >= HW * kTile ? GH : (int)((rem_h + 127) / 128);
+        const uint32_t g0 = (uint32_t)(blk * (NW * kTile / 128) + h * GH);
+        for (int g = 0; g < ng; ++g) {
+#pragma unroll
+            for (int u = 0; u < kKptMax; ++u) {
+                const int j = t + NT * u;
+                if (u < kpt && j < sk.k) {
+                    uint32_t wd[4];
+                    rad_words(g0 + (uint32_t)g, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, wd);
+                    const float* tg = lds + 32 * g * 16;   // the group's 32 chunks
+                    PT a = acc[u];
+#pragma unroll
+                    for (int c4 = 0; c4 < 4; ++c4)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            a += (PT)tg[(8 * c4 + i) * 16 + ((wd[c4] >> (4 * i)) & 15u)];
+                    acc[u] = a;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace rgs

@@ -631,7 +631,7 @@ template <typename TQ, typename T, int SK>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem* __restrict__ items,
                                                                  const GmresItem* __restrict__ gi,
                                                                  BlockMap map, int i) {
-    __shared__ T lds[kProjWaves * kTile];
+    __shared__ T lds[proj_lds_size<T, SK>()];
     const int2 bm = locate(map, xcd_block(blockIdx.x, gridDim.x));
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);

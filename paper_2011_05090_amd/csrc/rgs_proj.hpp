@@ -9,6 +9,14 @@
 
 namespace rgs {
 
+// LDS elements (of TW) a workgroup running project_body with sketch SK must
+// provide: one block of rows, or the signed-sum tables of the fp32
+// Rademacher sketch.
+template <typename TW, int SK>
+constexpr int proj_lds_size() {
+    return (SK == SK_RADEM && sizeof(TW) == 4) ? kRadNibLds : kProjWaves * kTile;
+}
+
 // Workgroup-uniform early exit once an earlier step has flagged a breakdown:
 // one thread reads the status word, the whole workgroup takes the same branch.
 #define RGS_EXIT_IF_FAILED(status)                      \
@@ -92,7 +100,10 @@ __device__ __forceinline__ void project_body(const TW* __restrict__ w, TQ* __res
         PT acc[kKptMax];
 #pragma unroll
         for (int u = 0; u < kKptMax; ++u) acc[u] = PT(0);
-        block_sketch<TW, PT, SK, NW>(v, blk, n, sk, acc, lds);
+        if constexpr (SK == SK_RADEM && sizeof(TW) == 4)   // lds holds kRadNibLds floats here
+            block_sketch_rad_nib<PT, NW>(v, blk, n, sk, acc, lds);
+        else
+            block_sketch<TW, PT, SK, NW>(v, blk, n, sk, acc, lds);
         PT* out = partials + blk * sk.k;
         constexpr int NT = NW * kWave;
         const int kpt = (sk.k + NT - 1) / NT;

@@ -16,7 +16,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_project(
     const TW* __restrict__ w, TQ* __restrict__ Q, int64_t ldq, int64_t n, int j, const TW* __restrict__ coef,
     const double* __restrict__ invr, int normalize_last, int do_sketch, int vec_ok, SketchArgs sk,
     PT* __restrict__ partials, const int* __restrict__ status) {
-    __shared__ TW lds[kProjWaves * kTile];
+    __shared__ TW lds[proj_lds_size<TW, SK>()];
     RGS_EXIT_IF_FAILED(status);
     project_body<TW, TQ, PT, SK, DEFER>(w, Q, ldq, n, j, coef, invr, normalize_last, do_sketch, vec_ok, sk,
                                         partials, blockIdx.x, lds);
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_project_ws(
 template <typename TW, typename TQ, typename PT, int SK, bool DEFER>
 __global__ __launch_bounds__(kProjWaves * kWave) void kb_project(const BatchItem* __restrict__ items, BlockMap map,
                                                                  int i) {
-    __shared__ TW lds[kProjWaves * kTile];
+    __shared__ TW lds[proj_lds_size<TW, SK>()];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_FAILED(it.sa.status);
