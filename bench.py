@@ -202,7 +202,9 @@ def cpu_baseline(n=1 << 16, m=512, k=2048):
 
 def small_fp64_leg(rgs, torch, synth, h, n=16384, m=64, k=256, steps=20, warmup=3):
     """Plain fp64 RGS with the Gaussian sketch at n = 16384, m = 64, k = 256: a
-    latency-bound size (64 dependent column steps), reported in us per column."""
+    latency-bound size (64 dependent column steps), reported in us per column,
+    launched eagerly and replayed as one captured HIP graph (RGS_FLAG_GRAPH;
+    the first warmup call captures it)."""
     W = rgs.colmajor(n, m, torch.float64)
     W.copy_(torch.from_numpy(synth.svd_matrix(n, m, 1e-6, tag=0)))
     Q = rgs.colmajor(n, m, torch.float64)
@@ -216,6 +218,12 @@ def small_fp64_leg(rgs, torch, synth, h, n=16384, m=64, k=256, steps=20, warmup=
            "norm2_I_minus_StS": d2}
     log("  fp64 RGS n=%d m=%d k=%d Gaussian: %.3f ms/QR (%.1f us/column), ||W-QR||/||W|| %.2e" %
         (n, m, k, ms, 1000.0 * ms / m, res))
+    dg = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp64", flags=rgs.FLAG_GRAPH)
+    ms_g, _, rep_g = run_steps(rgs, torch, h, dg, W, Q, R, S, steps, warmup)
+    res_g, _, _ = quality(torch, W, Q, R, S)
+    out["graph"] = {"ms_per_qr": ms_g, "us_per_column": 1000.0 * ms_g / m, "status": rep_g.status,
+                    "backward_error": res_g}
+    log("  same, graph-replayed: %.3f ms/QR (%.1f us/column)" % (ms_g, 1000.0 * ms_g / m))
     return out
 
 

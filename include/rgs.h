@@ -85,7 +85,12 @@ typedef enum {
 #define RGS_FLAG_DIAGNOSTICS 1u  /* compute step 8 of Algorithm 2 (Delta_m, tilde Delta_m) */
 #define RGS_FLAG_TIME_KERNELS 2u /* time every projection+sketch launch with events */
 #define RGS_FLAG_GRAPH 4u        /* rgs_gmres_batched: capture a restart cycle once as a HIP graph
-                                    and replay it while the set of running systems is unchanged */
+                                    and replay it while the set of running systems is unchanged.
+                                    rgs_qr: capture the factorisation's device work (all columns) once
+                                    as a HIP graph, kept in the handle, and replay it on later calls
+                                    with the same descriptor, pointers and leading dimensions (the
+                                    contents of W may change); step 1 then runs on the handle's
+                                    stream only.  Not with RGS_FLAG_TIME_KERNELS (EINVAL). */
 #define RGS_FLAG_CERTIFY 8u      /* rgs_qr: a-posteriori certification of Theta (Prop. 3.7, Sec. 3)
                                     for V = Q and V = W with a second sketch Phi of the same kind and
                                     size, independent of Theta (counter word 2 = sketch_id + 1) and

@@ -41,6 +41,11 @@ struct rgs_handle {
     std::unordered_map<uint64_t, int> gemm_tuned;
     int tune_mode = 0;        // 0: tune on first use, s > 0: always schedule s
     int last_schedule = 0;    // schedule used by the last batched Gaussian call
+    // RGS_FLAG_GRAPH on rgs_qr: the device work of the last captured call and
+    // the signature (every argument, the arena's address and size) it was captured for
+    hipGraph_t qr_graph = nullptr;
+    hipGraphExec_t qr_exec = nullptr;
+    std::vector<uint64_t> qr_key;
 };
 
 // Fixed device scratch of rgs_qr_noalloc, for callers that cannot allocate.
@@ -593,37 +598,8 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     if (h->aux &&   // anything a failed call left on the auxiliary stream comes first
         (hipEventRecord(h->join_ev, h->aux) != hipSuccess || hipStreamWaitEvent(s, h->join_ev, 0) != hipSuccess))
         return RGS_EDEVICE;
-    if (fixed) {   // the status words: four ints, cleared by a kernel (no memset node)
-        if (!launch_zero_mat(s, reinterpret_cast<double*>(sa.status), 2, 1, 2)) return RGS_EDEVICE;
-    } else if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) {
-        return RGS_EDEVICE;
-    }
-    if (!launch_zero_mat(s, R, m, m, ldr)) return RGS_EDEVICE;
-
-    // Step 1 for every column at once: P = Theta W, in chunks of pl.cc columns.
-    // The first chunk runs on the handle's stream; the others run on the
-    // auxiliary stream beside the first columns' steps, whose latency-bound
-    // sketch-space chains leave the device mostly idle.  Chunk c signals
-    // chunk_ev[c], which the column loop waits for before the least squares
-    // that first reads one of its columns.  The chunks share one partials
-    // buffer, so the auxiliary stream starts after the first chunk.
-    const int64_t nchunk = (m + pl.cc - 1) / pl.cc;
-    st = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, std::min<int64_t>(m, pl.cc), pl.G_P, pl.cc, partP, P, k);
-    if (st != RGS_OK) return st;
-    if (nchunk > 1 && !fixed) {
-        if (ensure_aux(h) != RGS_OK || ensure_chunk_events(h, (size_t)nchunk) != RGS_OK ||
-            hipEventRecord(h->fork_ev, s) != hipSuccess || hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)
-            return RGS_EDEVICE;
-        for (int64_t c = 1; c < nchunk; ++c) {
-            const int64_t c0 = c * pl.cc;
-            st = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P, pl.cc,
-                                         partP, P + c0 * k, k, h->aux);
-            if (st != RGS_OK) return st;
-            if (hipEventRecord(h->chunk_ev[c], h->aux) != hipSuccess) return RGS_EDEVICE;
-        }
-    }
-
-    const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;
+    const bool graph = fixed == nullptr && (d->flags & RGS_FLAG_GRAPH) != 0;
+    const bool timed = (d->flags & RGS_FLAG_TIME_KERNELS) != 0;   // never with a graph (rejected by the caller)
     if (timed && ensure_events(h, 2 * (size_t)m) != RGS_OK) return RGS_EDEVICE;
     const bool vec_ok = (ldq % 4 == 0) && (ldw % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) &&
                         ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
@@ -631,47 +607,120 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const bool split = pl.G_col > 0;
     const int Gp = sk_kind == SK_IDENT ? 1 : (split ? pl.G_col : (int)pl.nproj);
 
-    for (int64_t i = 0; i < m; ++i) {
-        // column i: step 3 (+4, + step 7 of column i-1) with the coefficients solved at the end
-        // of column i-1, then steps 5-6, the Householder append of s_i and step 2 for column i+1
-        const double* pnext = (i + 1 < m) ? P + (i + 1) * k : nullptr;
-        if (timed) (void)hipEventRecord(h->events[2 * i], s);
-        const bool sketch_col = DEFER || i > 0;
-        if (split) {
-            if (!launch_project_rows<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
-                                                   i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
-                                                   sa.status))
-                return RGS_EDEVICE;
-        } else if (!launch_project<T, TQ, DEFER>(s, W + i * ldw, Q, ldq, n, (int)i, coef,
-                                                 i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
-                                                 sketch_col ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status)) {
+    // The factorisation's device work, enqueued on stream q.  With `one`
+    // (fixed scratch, or a graph being captured) everything runs on q: the
+    // status words are cleared by a kernel (no memset node) and step 1 runs
+    // chunk by chunk on q just before the column that first reads each chunk.
+    auto enqueue = [&](hipStream_t q, bool one) -> rgs_status {
+        if (one) {   // the status words: four ints
+            if (!launch_zero_mat(q, reinterpret_cast<double*>(sa.status), 2, 1, 2)) return RGS_EDEVICE;
+        } else if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), q) != hipSuccess) {
             return RGS_EDEVICE;
         }
-        if (split && sketch_col && !launch_gauss_cols<TQ, T>(s, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
-            return RGS_EDEVICE;
-        if (timed) (void)hipEventRecord(h->events[2 * i + 1], s);
-        if (i + 1 < m && (i + 1) % pl.cc == 0) {   // the next column opens a chunk of P
-            if (fixed) {
-                const int64_t c0 = i + 1;
-                st = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P,
-                                             pl.cc, partP, P + c0 * k, k);
-                if (st != RGS_OK) return st;
-            } else if (hipStreamWaitEvent(s, h->chunk_ev[(i + 1) / pl.cc], 0) != hipSuccess) {
+        if (!launch_zero_mat(q, R, m, m, ldr)) return RGS_EDEVICE;
+
+        // Step 1 for every column at once: P = Theta W, in chunks of pl.cc columns.
+        // The first chunk runs on q; the others run on the auxiliary stream
+        // beside the first columns' steps, whose latency-bound sketch-space
+        // chains leave the device mostly idle.  Chunk c signals chunk_ev[c],
+        // which the column loop waits for before the least squares that first
+        // reads one of its columns.  The chunks share one partials buffer, so
+        // the auxiliary stream starts after the first chunk.
+        const int64_t nchunk = (m + pl.cc - 1) / pl.cc;
+        rgs_status r1 = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, std::min<int64_t>(m, pl.cc), pl.G_P, pl.cc, partP, P,
+                                                k, q);
+        if (r1 != RGS_OK) return r1;
+        if (nchunk > 1 && !one) {
+            if (ensure_aux(h) != RGS_OK || ensure_chunk_events(h, (size_t)nchunk) != RGS_OK ||
+                hipEventRecord(h->fork_ev, q) != hipSuccess || hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)
                 return RGS_EDEVICE;
+            for (int64_t c = 1; c < nchunk; ++c) {
+                const int64_t c0 = c * pl.cc;
+                r1 = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P,
+                                             pl.cc, partP, P + c0 * k, k, h->aux);
+                if (r1 != RGS_OK) return r1;
+                if (hipEventRecord(h->chunk_ev[c], h->aux) != hipSuccess) return RGS_EDEVICE;
             }
         }
-        const double* src0 = (i == 0 && !DEFER) ? P : nullptr;
-        const bool ok = d->ls_sweeps > 0
-                            ? launch_column_richardson<T, T>(s, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr,
-                                                             pnext, coef, DEFER ? sa.invr : nullptr, (int)d->ls_sweeps)
-                            : launch_column<T, T>(s, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr, pnext, coef,
-                                                  DEFER ? sa.invr : nullptr);
-        if (!ok) return RGS_EDEVICE;
-    }
-    if constexpr (DEFER) {
-        if (!launch_scale_cols_bf16(s, Q, ldq, n, (int)m, sa.invr, vec_ok ? 1 : 0, sa.status)) return RGS_EDEVICE;
-    } else {
-        if (!launch_scale_col<T>(s, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;
+
+        for (int64_t i = 0; i < m; ++i) {
+            // column i: step 3 (+4, + step 7 of column i-1) with the coefficients solved at the end
+            // of column i-1, then steps 5-6, the Householder append of s_i and step 2 for column i+1
+            const double* pnext = (i + 1 < m) ? P + (i + 1) * k : nullptr;
+            if (timed) (void)hipEventRecord(h->events[2 * i], q);
+            const bool sketch_col = DEFER || i > 0;
+            if (split) {
+                if (!launch_project_rows<T, TQ, DEFER>(q, W + i * ldw, Q, ldq, n, (int)i, coef,
+                                                       i > 0 ? sa.invr + (i - 1) : nullptr,
+                                                       (!DEFER && i > 0) ? 1 : 0, sa.status))
+                    return RGS_EDEVICE;
+            } else if (!launch_project<T, TQ, DEFER>(q, W + i * ldw, Q, ldq, n, (int)i, coef,
+                                                     i > 0 ? sa.invr + (i - 1) : nullptr, (!DEFER && i > 0) ? 1 : 0,
+                                                     sketch_col ? 1 : 0, vec_ok ? 1 : 0, sk, part, sa.status)) {
+                return RGS_EDEVICE;
+            }
+            if (split && sketch_col && !launch_gauss_cols<TQ, T>(q, Q + i * ldq, ldq, n, 1, pl.G_col, sk, part))
+                return RGS_EDEVICE;
+            if (timed) (void)hipEventRecord(h->events[2 * i + 1], q);
+            if (i + 1 < m && (i + 1) % pl.cc == 0) {   // the next column opens a chunk of P
+                if (one) {
+                    const int64_t c0 = i + 1;
+                    r1 = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc),
+                                                 pl.G_P, pl.cc, partP, P + c0 * k, k, q);
+                    if (r1 != RGS_OK) return r1;
+                } else if (hipStreamWaitEvent(q, h->chunk_ev[(i + 1) / pl.cc], 0) != hipSuccess) {
+                    return RGS_EDEVICE;
+                }
+            }
+            const double* src0 = (i == 0 && !DEFER) ? P : nullptr;
+            const bool ok = d->ls_sweeps > 0
+                                ? launch_column_richardson<T, T>(q, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr,
+                                                                 pnext, coef, DEFER ? sa.invr : nullptr,
+                                                                 (int)d->ls_sweeps)
+                                : launch_column<T, T>(q, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr, pnext,
+                                                      coef, DEFER ? sa.invr : nullptr);
+            if (!ok) return RGS_EDEVICE;
+        }
+        if constexpr (DEFER) {
+            if (!launch_scale_cols_bf16(q, Q, ldq, n, (int)m, sa.invr, vec_ok ? 1 : 0, sa.status)) return RGS_EDEVICE;
+        } else {
+            if (!launch_scale_col<T>(q, Q + (m - 1) * ldq, n, sa.invr + (m - 1), sa.status)) return RGS_EDEVICE;
+        }
+        return RGS_OK;
+    };
+
+    if (graph) {
+        // replay the captured work when every argument, the arena and its plan
+        // are those it was captured for; otherwise capture it anew
+        const std::vector<uint64_t> key = {
+            (uint64_t)n, (uint64_t)m, (uint64_t)k, d->seed, d->sketch_id, d->instance, (uint64_t)d->sketch,
+            (uint64_t)d->prec, d->flags, d->ls_sweeps, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
+            (uint64_t)(uintptr_t)Q, (uint64_t)ldq, (uint64_t)(uintptr_t)R, (uint64_t)ldr, (uint64_t)(uintptr_t)S,
+            (uint64_t)lds, (uint64_t)(uintptr_t)A, (uint64_t)pl.total};
+        if (!h->qr_exec || h->qr_key != key) {
+            if (h->qr_exec) (void)hipGraphExecDestroy(h->qr_exec);
+            if (h->qr_graph) (void)hipGraphDestroy(h->qr_graph);
+            h->qr_exec = nullptr;
+            h->qr_graph = nullptr;
+            h->qr_key.clear();
+            if (!h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
+                return RGS_EDEVICE;
+            if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return RGS_EDEVICE;
+            const rgs_status est = enqueue(h->capture, true);
+            hipGraph_t gr = nullptr;
+            const bool ended = hipStreamEndCapture(h->capture, &gr) == hipSuccess;
+            if (est != RGS_OK || !ended || hipGraphInstantiate(&h->qr_exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                h->qr_exec = nullptr;
+                (void)hipGetLastError();
+                return est != RGS_OK ? est : RGS_EDEVICE;
+            }
+            h->qr_graph = gr;
+            h->qr_key = key;
+        }
+        if (hipGraphLaunch(h->qr_exec, s) != hipSuccess) return RGS_EDEVICE;
+    } else if ((st = enqueue(s, fixed != nullptr)) != RGS_OK) {
+        return st;
     }
 
     double* diag = reinterpret_cast<double*>(A + pl.diag);
@@ -2113,6 +2162,8 @@ rgs_status rgs_destroy(rgs_handle* h) {
     for (hipEvent_t e : {h->fork_ev, h->join_ev})
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->chunk_ev) (void)hipEventDestroy(e);
+    if (h->qr_exec) (void)hipGraphExecDestroy(h->qr_exec);
+    if (h->qr_graph) (void)hipGraphDestroy(h->qr_graph);
     if (h->capture) (void)hipStreamDestroy(h->capture);
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->arena) (void)hipFree(h->arena);
@@ -2138,8 +2189,11 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
                   double* R, int64_t ldr, double* S, int64_t lds, rgs_report* rep) try {
     if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
     if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
-    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY | RGS_FLAG_THETA_BF16)) != 0)
+    if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY | RGS_FLAG_THETA_BF16 |
+                      RGS_FLAG_GRAPH)) != 0)
         return RGS_EINVAL;
+    // kernel timing records events between the launches, which a replayed graph does not have
+    if ((d->flags & RGS_FLAG_GRAPH) && (d->flags & RGS_FLAG_TIME_KERNELS)) return RGS_EINVAL;
     // Phi = Theta = I would certify nothing
     if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;
     if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
