@@ -86,6 +86,73 @@ def sources_sha256(files):
     return h.hexdigest()
 
 
+def calibration_copy(torch, dev):
+    """A plain 1 GiB device-to-device copy (1 GiB read + 1 GiB written): the
+    reference the HBM byte counters of a run are scaled by."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("calibration copy: 1 GiB read + 1 GiB written")
+    del src, dst
+
+
+def _pmc_rows(db, counter):
+    import sqlite3
+    con = sqlite3.connect(db)
+    out = list(con.execute("select dispatch_id, kernel_name, value from counters_collection "
+                           "where counter_name=? order by dispatch_id", (counter,)))
+    con.close()
+    return out
+
+
+def write_batched_traffic_record(fetch_db, write_db, sketch, batch=2048):
+    """HBM traffic of one batched QR call (the leg's second call: the first
+    warms up and, for the Gaussian products, tunes their schedule) from two
+    rocprofv3 --pmc databases: every library kernel of the call, summed, with
+    the counters scaled by the closing 1 GiB copy; beside the call's
+    algorithmic bytes.  Written to profiles/rgs_qr_batched_2048_<sketch>_traffic.json."""
+    import synth
+    per = {}
+    kernels = {}
+    for name, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        r = _pmc_rows(db, counter)
+        copies = [v for _, kn, v in r if "copyBuffer" in kn]
+        inits = [d for d, kn, _ in r if "kb_init" in kn]
+        if not copies or len(inits) < 4:
+            raise SystemExit("%s: expected two calls (two shares each) and a closing copy" % db)
+        first = inits[len(inits) // 2]          # the second call's first share starts here
+        factor = copies[-1] * 1024.0 / (1 << 30)
+        tot = 0.0
+        for d, kn, v in r:
+            if d >= first and "rgs::" in kn:
+                tot += v
+                key = kn.split("(")[0]
+                kernels.setdefault(key, {"fetch_kib": 0.0, "write_kib": 0.0, "dispatches": 0})
+                kernels[key][name + "_kib"] += v
+                if name == "fetch":
+                    kernels[key]["dispatches"] += 1
+        per[name] = (tot, copies[-1], factor)
+    ns, ms = synth.batch_qr_sizes(batch)
+    alg = float(sum(batched_qr_bytes(int(n), int(m)) for n, m in zip(ns, ms)))
+    traffic = per["fetch"][0] * 1024.0 / per["fetch"][2] + per["write"][0] * 1024.0 / per["write"][2]
+    rec = {"workload": "batched RGS QR, %d factorisations, n ~ U{4096..262144}, m ~ U{16..128}, k = 4m, fp32 W, "
+                       "bf16 Q, sketch %s; one call" % (batch, sketch),
+           "fetch_kib_raw": per["fetch"][0], "write_kib_raw": per["write"][0],
+           "copy_calibration": {"fetch_size_kib": per["fetch"][1], "write_size_kib": per["write"][1],
+                                "fetch_factor": per["fetch"][2], "write_factor": per["write"][2]},
+           "traffic_bytes": traffic, "algorithmic_bytes": alg, "traffic_over_algorithmic": traffic / alg,
+           "kernels": {k: dict(v, fetch_bytes=v["fetch_kib"] * 1024.0 / per["fetch"][2],
+                               write_bytes=v["write_kib"] * 1024.0 / per["write"][2])
+                       for k, v in sorted(kernels.items(), key=lambda x: -x[1]["fetch_kib"])}}
+    path = os.path.join(ROOT, "profiles", "rgs_qr_batched_2048_%s_traffic.json" % sketch)
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({k: v for k, v in rec.items() if k != "kernels"}, indent=1))
+
+
 def write_traffic_record(fetch_db, write_db, n=1 << 22, m=512, k=2048):
     """Turn two rocprofv3 --pmc databases (FETCH_SIZE, then WRITE_SIZE, of
     ``bench.py --steps 1 --warmup 0 --no-extra --no-cpu-baseline --no-gmres
@@ -538,9 +605,20 @@ def main():
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
                          "databases (no GPU needed) and exit")
+    ap.add_argument("--sketches", default=None,
+                    help="with --only batched-qr: comma-separated legs (srht, gaussian, gaussian_bf16_table)")
+    ap.add_argument("--leg-steps", type=int, default=None, help="with --only: timed calls per leg")
+    ap.add_argument("--leg-warmup", type=int, default=None, help="with --only: untimed calls per leg")
+    ap.add_argument("--batched-traffic", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "SKETCH"),
+                    help="write the HBM-traffic record of one batched QR call from two rocprofv3 --pmc "
+                         "databases of 'bench.py --only batched-qr --sketches SKETCH --leg-warmup 1 "
+                         "--leg-steps 1 --calibrate-copy' (no GPU needed) and exit")
     args = ap.parse_args()
     if args.traffic_record:
         write_traffic_record(*args.traffic_record)
+        return
+    if args.batched_traffic:
+        write_batched_traffic_record(*args.batched_traffic)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -556,7 +634,16 @@ def main():
         h = rgs.Handle(0)
         leg = {"small": small_fp64_leg, "batched-qr": batched_qr_leg, "batched-gmres": batched_gmres_leg,
                "gmres": gmres_leg, "sec51": sec51_leg}[args.only]
-        res = leg(rgs, torch, synth, h)
+        kw = {}
+        if args.leg_steps is not None:
+            kw["steps"] = args.leg_steps
+        if args.leg_warmup is not None:
+            kw["warmup"] = args.leg_warmup
+        if args.sketches and args.only == "batched-qr":
+            kw["sketches"] = tuple(args.sketches.split(","))
+        res = leg(rgs, torch, synth, h, **kw)
+        if args.calibrate_copy:
+            calibration_copy(torch, torch.device("cuda:0"))
         h.close()
         print(json.dumps({"only": args.only, "result": res}), flush=True)
         return
@@ -715,14 +802,7 @@ def main():
         log("batched randomized GMRES")
         out["extra"]["batched_rgmres_256"] = batched_gmres_leg(rgs, torch, synth, h)
     if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy: 1 GiB read + 1 GiB written")
-        del src, dst
+        calibration_copy(torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
