@@ -583,6 +583,22 @@ def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6
                                        "speedup_vs_fp64_gaussian": res["gaussian_fp64"]["seconds_to_tol"] / dt}
     log("  rgmres gaussian(bf16 table)/fp32: %d iters, %d cycles, relres %.2e, %.3f s" %
         (rep.iters, rep.cycles, rep.true_relres, dt))
+    # the P-SRHT with the lagged Arnoldi step (RGS_FLAG_LAG): both sketches of a step in the mat-vec pass
+    for prec in ("fp32", "fp64"):
+        d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec=prec, flags=rgs.FLAG_LAG)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, _ = rgs.rgs_gmres(h, A, d, b, x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bq = 4 if prec == "fp32" else 8
+        nbytes = gmres_bytes(n, rep.iters, rep.cycles, restart, bq, bq)
+        res["srht_lag_%s" % prec] = {"seconds_to_tol": dt, "iters": rep.iters, "cycles": rep.cycles,
+                                     "true_relres": rep.true_relres, "status": rep.status,
+                                     "algorithmic_bytes": nbytes, "gbs": nbytes / dt / 1e9,
+                                     "pct_hbm_peak": 100.0 * nbytes / dt / 1e9 / HBM_PEAK_GBS}
+        log("  rgmres srht(lagged step)/%s: %d iters, %d cycles, relres %.2e, %.3f s" %
+            (prec, rep.iters, rep.cycles, rep.true_relres, dt))
     return res
 
 

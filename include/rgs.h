@@ -109,6 +109,15 @@ typedef enum {
                                     drawn again.  A different (still i.i.d., entries within 2^-8
                                     relative of N(0,1/k)) sketch from the GAUSSIAN one */
 
+#define RGS_FLAG_LAG 32u         /* rgs_gmres with SRHT or RADEMACHER: the lagged Arnoldi step (the
+                                    lagged normalisation of Sec. 2.4) -- the mat-vec kernel computes
+                                    t = A q'_i from the stored, unnormalised q'_i and sketches q'_i
+                                    and t in the same pass, so r_ii = ||Theta q'_i|| and
+                                    p_{i+1} = Theta t / r_ii come out of one reduction, and the
+                                    projection no longer sketches; w_{i+1} = t / r_ii is applied on
+                                    load.  Equal to Algorithm 3 in exact arithmetic.  The GAUSSIAN
+                                    sketch always takes this step (its two sketches share draws). */
+
 /* Describes one RGS factorisation and its sketch Theta (k x n).
  * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
  * regenerated on demand and not stored (Sec. 2.1, seeded generation), except
@@ -150,7 +159,7 @@ typedef struct {
     int32_t sketch;     /* rgs_sketch (GAUSSIAN, SRHT or RADEMACHER; batched: GAUSSIAN or SRHT) */
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
-    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16 is honoured, other bits ignored;
+    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16 and RGS_FLAG_LAG are honoured, other bits ignored;
                            rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
 } rgs_gmres_desc;
 

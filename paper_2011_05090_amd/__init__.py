@@ -26,6 +26,7 @@ FLAG_TIME_KERNELS = 2
 FLAG_GRAPH = 4
 FLAG_CERTIFY = 8
 FLAG_THETA_BF16 = 16
+FLAG_LAG = 32
 
 
 class RgsError(RuntimeError):

@@ -812,8 +812,10 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const size_t ohist = c.take<double>(mcap), oused = c.take<int>(4), or_ = c.take<double>(n);
     const size_t opart = c.take<double>((n + 255) / 256), onorm = c.take<double>(4);
     // Gaussian: the two sketches of an Arnoldi step share their draws (the
-    // mat-vec kernel sketches q'_i and A q'_i together), second partials buffer
-    const bool dual = sk_kind == SK_GAUSS;
+    // mat-vec kernel sketches q'_i and A q'_i together), second partials buffer;
+    // P-SRHT / Rademacher with RGS_FLAG_LAG: the same lagged step
+    const bool dual = sk_kind == SK_GAUSS ||
+                      ((d->flags & RGS_FLAG_LAG) != 0 && (sk_kind == SK_SRHT || sk_kind == SK_RADEM));
     const size_t opart2 = c.take<T>(dual ? pl.nproj * k : 1);
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;

@@ -387,6 +387,45 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
     }
 }
 
+// P-SRHT / Rademacher counterpart of stencil_dual_body (the lagged Arnoldi
+// step, RGS_FLAG_LAG): for the stored column x (unscaled q'_i), t = A x is
+// stored in t_out, and the block's sketch partials of x and of t are taken in
+// the same pass by two applications of the block sketch (the block transform
+// of the projection kernel) -- so the two sketches of the step, s'_i of q'_i
+// and p_{i+1} of A q'_i, come out of one reduction, r_ii and the 1/r_ii of
+// p_{i+1} and w_{i+1} being applied when known.  Rows and their order per
+// vector as in stencil_sketch_body.
+template <typename TQ, typename T, int SK>
+__device__ __forceinline__ void stencil_dual_sk_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
+                                                     T* __restrict__ t_out, const SketchArgs& sk,
+                                                     T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
+                                                     T* __restrict__ lds) {
+    constexpr int NW = kProjWaves, NT = NW * kWave;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool vec = stencil_vec_ok(g, xs, t_out);
+    T xv[16], tv[16];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
+        stencil4<T, TQ>(g, xs, false, 1.0, vec, r0, n, tv + 4 * e, xv + 4 * e);
+        st4<T>(t_out, r0, n, vec, tv + 4 * e);
+    }
+    T ax[kKptMax], at[kKptMax];
+#pragma unroll
+    for (int u = 0; u < kKptMax; ++u) ax[u] = at[u] = T(0);
+    block_sketch<T, T, SK, NW>(xv, blk, n, sk, ax, lds);   // transforms xv, tv in place
+    block_sketch<T, T, SK, NW>(tv, blk, n, sk, at, lds);
+    const int kpt = (sk.k + NT - 1) / NT;
+#pragma unroll
+    for (int u = 0; u < kKptMax; ++u) {
+        const int j = threadIdx.x + NT * u;
+        if (u < kpt && j < sk.k) {
+            part_x[blk * sk.k + j] = ax[u];
+            part_t[blk * sk.k + j] = at[u];
+        }
+    }
+}
+
 // r = b - A x in fp64 for the 256 rows of block blk (256 threads), and the
 // block's partial sum of ||r||^2.
 __device__ __forceinline__ void residual_body(const double* __restrict__ b, const double* __restrict__ x,
@@ -552,6 +591,15 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     // one system: k <= 512 threads stream the table with 4 loads in flight
     // (16 measured slower here; the batched row-block launch uses 16)
     stencil_dual_body<TQ, T, TAB, 4>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
+}
+
+template <typename TQ, typename T, int SK>
+__global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual_sk(
+    const TQ* __restrict__ xs, Grid3 g, int64_t n, T* __restrict__ t_out, SketchArgs sk, T* __restrict__ part_x,
+    T* __restrict__ part_t, const int* __restrict__ status) {
+    __shared__ T lds[kProjWaves * kTile];
+    RGS_EXIT_IF_STOPPED(status);
+    stencil_dual_sk_body<TQ, T, SK>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
@@ -833,12 +881,21 @@ template <typename TQ, typename T>
 bool launch_stencil_dual(hipStream_t st, const StencilArgs& A, const TQ* xs, T* t_out, const SketchArgs& sk,
                          T* part_x, T* part_t, const int* status) {
     const int64_t n = A.nx * A.ny * A.nz;
+    const dim3 grid(nblk_of(n, kProjRows)), thr(kProjWaves * kWave);
     if (sk.sketch == SK_TABLE)
-        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true>), dim3(nblk_of(n, kProjRows)), dim3(kProjWaves * kWave), 0,
-                           st, xs, grid3(A), n, t_out, sk, part_x, part_t, status);
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x, part_t,
+                           status);
+    else if (sk.sketch == SK_GAUSS)
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, false>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
+                           part_t, status);
+    else if (sk.sketch == SK_SRHT)
+        hipLaunchKernelGGL((k_stencil_dual_sk<TQ, T, SK_SRHT>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
+                           part_t, status);
+    else if (sk.sketch == SK_RADEM)
+        hipLaunchKernelGGL((k_stencil_dual_sk<TQ, T, SK_RADEM>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk,
+                           part_x, part_t, status);
     else
-        hipLaunchKernelGGL((k_stencil_dual<TQ, T, false>), dim3(nblk_of(n, kProjRows)), dim3(kProjWaves * kWave), 0,
-                           st, xs, grid3(A), n, t_out, sk, part_x, part_t, status);
+        return false;
     RGS_LAUNCH_CHECK();
     return true;
 }

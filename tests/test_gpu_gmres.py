@@ -57,12 +57,13 @@ def _oracle(N, Pe, restart, k, tol, sketch, precision, tag, max_iters=100000):
     return dims, coeffs, b, out
 
 
-def _gpu(h, dims, coeffs, b, restart, k, tol, sketch, prec, max_iters=100000):
+def _gpu(h, dims, coeffs, b, restart, k, tol, sketch, prec, max_iters=100000, flags=0):
     rgs = _rgs()
     n = b.size
     x = torch.empty(n, dtype=torch.float64, device="cuda")
     rep, hist = rgs.rgs_gmres(h, rgs.stencil7(dims, coeffs),
-                              rgs.gmres_desc(restart, k, tol, max_iters=max_iters, sketch=sketch, prec=prec),
+                              rgs.gmres_desc(restart, k, tol, max_iters=max_iters, sketch=sketch, prec=prec,
+                                             flags=flags),
                               dev(b), x, res_hist=100000)
     torch.cuda.synchronize()
     return rep, np.array(hist), x.cpu().numpy()
@@ -82,6 +83,34 @@ def test_rgmres_fp64_matches_oracle(gpu_handle, sketch):
     # the residual histories agree while both are far above rounding level
     L = min(len(hist), len(ref["hist"]), restart)
     np.testing.assert_allclose(hist[:L], ref["hist"][:L], rtol=1e-8)
+
+
+@pytest.mark.parametrize("sketch,prec", [("srht", "fp64"), ("rademacher", "fp64"), ("srht", "fp32"),
+                                         ("srht", "bf16q")])
+def test_lagged_arnoldi_step_matches_oracle(gpu_handle, sketch, prec):
+    """RGS_FLAG_LAG: the mat-vec kernel sketches the stored q'_i and A q'_i
+    in one pass (one reduction gives r_ii and p_{i+1}), equal to Algorithm 3
+    in exact arithmetic.  fp64: iterations and cycles as the fp64 oracle's
+    (+-2), histories to 1e-8 while above rounding level; fp32: +-2 of the fp64
+    oracle; bf16 basis: converges with the true residual at tol and within the
+    spread of the bf16 model (+-2 of the unlagged device run is not implied:
+    the basis rounding is at 2^-9)."""
+    rgs = _rgs()
+    N, Pe, restart, k, tol = 24, 50.0, 20, 96, 1e-6        # n = 13824: 2 blocks, ragged
+    dims, coeffs, b, ref = _oracle(N, Pe, restart, k, tol, sketch, "fp64", tag=1)
+    rep, hist, x = _gpu(gpu_handle, dims, coeffs, b, restart, k, tol, sketch, prec, flags=rgs.FLAG_LAG)
+    assert rep.status == 0 and ref["converged"]
+    r = b - ost.apply(x, dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
+    if prec == "bf16q":
+        _, _, _, refb = _oracle(N, Pe, restart, k, tol, sketch, "bf16q", tag=1)
+        assert abs(rep.iters - refb["iters"]) <= max(4, refb["iters"] // 20)
+        return
+    assert abs(rep.iters - ref["iters"]) <= 2
+    if prec == "fp64":
+        assert rep.cycles == ref["cycles"]
+        L = min(len(hist), len(ref["hist"]), restart)
+        np.testing.assert_allclose(hist[:L], ref["hist"][:L], rtol=1e-8)
 
 
 def test_rgmres_fp32_basis_iterations_near_fp64_oracle(gpu_handle):
