@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 3
+#define RGS_ABI_VERSION 4
 
 typedef struct rgs_handle rgs_handle;  /* opaque */
 typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
@@ -161,6 +161,11 @@ typedef struct {
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
     uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16 and RGS_FLAG_LAG are honoured, other bits ignored;
                            rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
+    uint32_t ls_sweeps; /* rgs_gmres: step 2 of every Arnoldi step (Alg. 3 on RGS, Sec. 2.3's remark on the
+                           least-squares solver): 0 = Householder QR of S; 1..8 = that many Richardson
+                           iterations on the normal equations, y = S^T p then y += S^T (p - S y), the first
+                           being the sketched classical Gram-Schmidt; EINVAL above 8.  rgs_gmres_batched:
+                           must be 0 */
 } rgs_gmres_desc;
 
 typedef struct {

@@ -52,7 +52,8 @@ class Stencil7(ctypes.Structure):
 class GmresDesc(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int64), ("max_iters", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("sketch", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("reuse_theta", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("prec", ctypes.c_int32), ("reuse_theta", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("ls_sweeps", ctypes.c_uint32)]
 
 
 class QrItem(ctypes.Structure):
@@ -325,9 +326,10 @@ def stencil7(dims, coeffs):
 
 
 def gmres_desc(restart, k, tol, max_iters=100000, sketch="gaussian", prec="fp32", seed=42, reuse_theta=False,
-               flags=0):
+               flags=0, ls_sweeps=0):
+    """ls_sweeps: 0 = Householder least squares in every Arnoldi step, s > 0 = s Richardson sweeps."""
     return GmresDesc(restart=restart, max_iters=max_iters, k=k, tol=tol, seed=seed, sketch=SKETCH[sketch],
-                     prec=PREC[prec], reuse_theta=1 if reuse_theta else 0, flags=flags)
+                     prec=PREC[prec], reuse_theta=1 if reuse_theta else 0, flags=flags, ls_sweeps=ls_sweeps)
 
 
 def rgs_gmres(handle, A, desc, b, x, res_hist=None, allow=(RGS_ENOCONV,)):

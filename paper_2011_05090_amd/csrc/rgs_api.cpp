@@ -842,6 +842,21 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const double scale = sk_kind == SK_IDENT ? 1.0 : 1.0 / std::sqrt((double)k);
     const int Gp = sk_kind == SK_IDENT ? 1 : (int)pl.nproj;
     const bool vec_ok = true;   // ldq % 4 == 0 and the arena is 256-byte aligned
+    // step 2 of an Arnoldi step (Householder QR of S, or ls_sweeps Richardson
+    // iterations on the normal equations) and steps 5-6 with the append of s_i
+    const int sweeps = (int)d->ls_sweeps;
+    auto ls_rhs = [&](const T* partials, int i, const double* scale2) {
+        return sweeps > 0 ? launch_ls_partials_richardson<T, T>(s, sa, partials, Gp, scale, i, S, k, R, mcap, coef,
+                                                                DEFER ? sa.invr : nullptr, scale2, sweeps)
+                          : launch_ls_partials<T, T>(s, sa, partials, Gp, scale, i, R, mcap, coef,
+                                                     DEFER ? sa.invr : nullptr, scale2);
+    };
+    auto column = [&](int i) {
+        return sweeps > 0 ? launch_column_richardson<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr,
+                                                           coef, nullptr, sweeps)
+                          : launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef,
+                                                nullptr);
+    };
 
     // x0 = 0, r0 = b, ||b||
     if (hipMemsetAsync(x, 0, n * sizeof(double), s) != hipSuccess) return RGS_EDEVICE;
@@ -879,17 +894,14 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
             return RGS_EDEVICE;
         // dual: t_1 = A q'_0 with the sketches of q'_0 (part) and t_1 (part2)
         if (dual && !launch_stencil_dual<TQ, T>(s, A, Q, wbuf, sk, part, part2, sa.status)) return RGS_EDEVICE;
-        if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, 0, S, k, R, mcap, nullptr, coef, nullptr))
-            return RGS_EDEVICE;
+        if (!column(0)) return RGS_EDEVICE;
         if (!launch_givens_init(s, R, gv, used)) return RGS_EDEVICE;
         const int64_t steps = std::min<int64_t>(d->restart, d->max_iters - iters);
         for (int64_t ci = 1; ci <= steps; ++ci) {
             const int i = (int)ci;
             if (dual) {
                 // p_i = Theta (A q'_{i-1}) / r_{i-1,i-1} and w_i = (A q'_{i-1}) / r_{i-1,i-1}
-                if (!launch_ls_partials<T, T>(s, sa, part2, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr,
-                                              sa.invr + (i - 1)))
-                    return RGS_EDEVICE;
+                if (!ls_rhs(part2, i, sa.invr + (i - 1))) return RGS_EDEVICE;
                 if (!launch_project_ws<T, TQ, DEFER>(s, wbuf, Q, ldq, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1,
                                                      vec_ok ? 1 : 0, sa.invr + (i - 1), sa.status))
                     return RGS_EDEVICE;
@@ -900,15 +912,12 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
                 if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * ldq, sa.invr + (i - 1), wbuf, 1, sk, part,
                                                   sa.status))
                     return RGS_EDEVICE;
-                if (!launch_ls_partials<T, T>(s, sa, part, Gp, scale, i, R, mcap, coef, DEFER ? sa.invr : nullptr,
-                                              nullptr))
-                    return RGS_EDEVICE;
+                if (!ls_rhs(part, i, nullptr)) return RGS_EDEVICE;
                 if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, ldq, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
                                                   vec_ok ? 1 : 0, sk, part, sa.status))
                     return RGS_EDEVICE;
             }
-            if (!launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef, nullptr))
-                return RGS_EDEVICE;
+            if (!column(i)) return RGS_EDEVICE;
             if (!launch_givens(s, i, R, (int)mcap, Hr, cs, sn, gv, bnorm, d->tol, hist, sa.status, used,
                                (int)steps))
                 return RGS_EDEVICE;
@@ -1617,6 +1626,7 @@ bool valid_gmres_desc(const rgs_gmres_desc* d) {
     if (!d) return false;
     if (d->restart < 1 || d->restart + 1 > d->k || d->restart > 4000 || d->max_iters < 1 || !(d->tol >= 0))
         return false;
+    if (d->ls_sweeps > kMaxSweeps) return false;
     return d->prec == RGS_P_FP64 || d->prec == RGS_P_FP32_LS64 || d->prec == RGS_P_BF16Q_FP32_LS64;
 }
 
@@ -2383,6 +2393,7 @@ rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16)) != 0) return RGS_EINVAL;
+    if (d->ls_sweeps != 0) return RGS_EINVAL;   // the batched solves keep the Householder least squares
     if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     for (int64_t b = 0; b < batch; ++b) {
         const rgs_gmres_item& it = items[b];

@@ -49,6 +49,12 @@ template <typename T>
 bool launch_scale_col(hipStream_t st, T* q, int64_t n, const double* invr, const int* status);
 template <typename T>
 bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, double* R, int64_t ldr, T* coef);
+// Step 2 of an Arnoldi step (right-hand side from block partials) by `sweeps`
+// Richardson iterations on the normal equations (with the Richardson column step).
+template <typename T, typename PT>
+bool launch_ls_partials_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
+                                   double* S, int64_t lds, double* R, int64_t ldr, T* coef, const double* cscale,
+                                   const double* scale2, int sweeps);
 // The column step with step 2 by `sweeps` Richardson iterations on the normal equations.
 template <typename T, typename PT>
 bool launch_column_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,

@@ -871,8 +871,9 @@ template <typename PT, int NT = kGW>
 __global__ __launch_bounds__(NT) void k_qa(const PT* __restrict__ partials, int G, double scale,
                                            const double* __restrict__ src, int k, int i,
                                            const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                           double* __restrict__ pd, const double* __restrict__ scale2) {
-    qa_body<PT, NT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2);
+                                           double* __restrict__ pd, const double* __restrict__ scale2,
+                                           int pstride = 0) {
+    qa_body<PT, NT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2, pstride);
 }
 
 template <int NT = kGW>
@@ -1330,6 +1331,35 @@ __global__ __launch_bounds__(kGW) void k_rres(int k, int i, int mcap, const doub
     rres_body(k, i, mcap, Sc, lds, Sr, pn, y, pdb, blockIdx.x);
 }
 
+// Step 2 for the Arnoldi right-hand side p_i (block partials of the mat-vec
+// kernel, times scale2[0] when given) by `sweeps` Richardson iterations on the
+// normal equations with S_i (kept row-major in Wr by the Richardson column
+// step): p_i into pbuf with the slice partials of S_i^T p_i and ||p_i||^2 in
+// one pass, then the sweeps as in the QR chain (y = S^T p, y += S^T (p - S y)).
+template <typename T, typename PT>
+bool launch_ls_partials_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
+                                   double* S, int64_t lds, double* R, int64_t ldr, T* coef, const double* cscale,
+                                   const double* scale2, int sweeps) {
+    if (i < 1 || sweeps < 1) return false;
+    const int nsl = (a.k + kSlice - 1) / kSlice;
+    hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, (const double*)nullptr, a.k, i,
+                       a.Wr, a.mcap, a.pbuf, a.pdb, scale2, a.mcap + 2);
+    RGS_LAUNCH_CHECK();
+    const unsigned nb = nblocks(i, kGW);
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const int last = sw + 1 == sweeps;
+        hipLaunchKernelGGL(k_rsum<T>, dim3(nb), dim3(kGW), 0, st, i - 1, nsl, a.mcap, a.pdb, a.uh, sw > 0 ? 1 : 0,
+                           last, a.pnorm, R, ldr, coef, cscale);
+        RGS_LAUNCH_CHECK();
+        if (!last) {
+            hipLaunchKernelGGL(k_rres, dim3(nsl), dim3(kGW), 0, st, a.k, i - 1, a.mcap, S, lds, a.Wr, a.pbuf, a.uh,
+                               a.pdb);
+            RGS_LAUNCH_CHECK();
+        }
+    }
+    return true;
+}
+
 // The column step with step 2 by `sweeps` Richardson iterations (sweeps >= 1).
 template <typename T, typename PT>
 bool launch_column_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
@@ -1510,6 +1540,12 @@ template bool launch_ls_partials<float, float>(hipStream_t, const SpaceArgs&, co
                                                double*, int64_t, float*, const double*, const double*);
 template bool launch_ls_partials<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double, int,
                                                  double*, int64_t, double*, const double*, const double*);
+template bool launch_ls_partials_richardson<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double,
+                                                          int, double*, int64_t, double*, int64_t, float*,
+                                                          const double*, const double*, int);
+template bool launch_ls_partials_richardson<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
+                                                            int, double*, int64_t, double*, int64_t, double*,
+                                                            const double*, const double*, int);
 template bool launch_column_richardson<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double,
                                                      const double*, int, double*, int64_t, double*, int64_t,
                                                      const double*, float*, const double*, int);

@@ -154,13 +154,14 @@ __device__ __forceinline__ void ls3_body(int nr, int col, const double* __restri
 // Column step A: s' = scale * (sum of the projection kernel's block partials)
 // (times scale2[0] when given: the 1/r_ii of an Arnoldi vector sketched before
 // its normalisation was known) for slice bid (or a copy of src), stored in sp;
-// per-slice partials of c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i).
+// per-slice partials of c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i), at
+// stride pstride per slice (mcap + 1 when 0).
 template <typename PT, int NT = kGW>
 __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, double scale,
                                         const double* __restrict__ src, int k, int i,
                                         const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
                                         double* __restrict__ pd, int bid,
-                                        const double* __restrict__ scale2 = nullptr) {
+                                        const double* __restrict__ scale2 = nullptr, int pstride = 0) {
     __shared__ double red[kGQ][64];
     __shared__ double xs[kSlice];
     const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
@@ -198,7 +199,7 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
         }
     }
     __syncthreads();
-    double* out = pd + (int64_t)s * (mcap + 1);
+    double* out = pd + (int64_t)s * (pstride ? pstride : mcap + 1);
     for (int c = threadIdx.x; c <= i; c += NT) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 

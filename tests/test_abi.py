@@ -45,7 +45,7 @@ def test_binding_signatures_cover_the_header():
 
 
 def test_abi_version_and_status_strings(lib):
-    assert rgs.rgs_abi_version() == 3
+    assert rgs.rgs_abi_version() == 4
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = rgs.status_string(code)
         assert s and "unknown" not in s
@@ -69,7 +69,7 @@ def test_struct_layouts_match_header_sizes():
     # field-by-field layout of the ABI structs (x86-64, natural alignment)
     assert ctypes.sizeof(rgs.QrDesc) == 8 * 4 + 4 * 6
     assert ctypes.sizeof(rgs.Stencil7) == 8 * 3 + 8 * 7
-    assert ctypes.sizeof(rgs.GmresDesc) == 8 * 5 + 4 * 4
+    assert ctypes.sizeof(rgs.GmresDesc) == 8 * 5 + 4 * 5 + 4   # padded to a multiple of 8
     assert ctypes.sizeof(rgs.Report) == 8 * 14
     assert ctypes.sizeof(rgs.QrItem) == 8 * 11
     assert ctypes.sizeof(rgs.GmresItem) == ctypes.sizeof(rgs.Stencil7) + 8 * 4

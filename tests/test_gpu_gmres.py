@@ -164,3 +164,53 @@ def test_max_iters_cap(gpu_handle):
     assert rep.status == rgs.RGS_ENOCONV
     assert rep.iters == 7 and len(hist) == 7
     assert np.all(np.diff(hist) <= 1e-12)         # GMRES residuals never increase within a cycle
+
+
+@pytest.mark.parametrize("sketch,prec,sweeps,lag", [("srht", "fp64", 1, False), ("srht", "fp64", 2, False),
+                                                    ("gaussian", "fp64", 2, False), ("srht", "fp32", 2, True),
+                                                    ("rademacher", "fp64", 2, True)])
+def test_richardson_least_squares_matches_oracle(gpu_handle, sketch, prec, sweeps, lag):
+    """ls_sweeps: step 2 of every Arnoldi step by Richardson iterations on the
+    normal equations (one sweep: sketched classical Gram-Schmidt; two: its
+    re-orthogonalised form), against the oracle's RGMRES with the same solver
+    ('richardson1' / 'richardson2'): fp64 iterations and cycles (+-2) and the
+    residual histories while far above rounding; fp32 within +-2 of the fp64
+    oracle.  With the lagged step (Gaussian always, P-SRHT / Rademacher with
+    RGS_FLAG_LAG) the right-hand side carries the 1/r_ii of the step before."""
+    rgs = _rgs()
+    N, Pe, restart, k, tol = 24, 50.0, 20, 96, 1e-6
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=1)
+    ref = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b,
+                     lambda c: osk.make(sketch, n, k, seed=42, sketch_id=2 + c),
+                     restart=restart, tol=tol, precision="fp64", ls="richardson%d" % sweeps)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    rep, hist = rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs),
+                              rgs.gmres_desc(restart, k, tol, sketch=sketch, prec=prec, ls_sweeps=sweeps,
+                                             flags=rgs.FLAG_LAG if lag else 0),
+                              dev(b), x, res_hist=100000)
+    torch.cuda.synchronize()
+    hist = np.array(hist)
+    assert rep.status == 0 and ref["converged"]
+    r = b - ost.apply(x.cpu().numpy(), dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
+    assert abs(rep.iters - ref["iters"]) <= 2
+    if prec == "fp64":
+        assert rep.cycles == ref["cycles"]
+        L = min(len(hist), len(ref["hist"]), restart)
+        np.testing.assert_allclose(hist[:L], ref["hist"][:L], rtol=1e-8)
+
+
+def test_richardson_sweeps_rejected(gpu_handle):
+    rgs = _rgs()
+    dims, coeffs = synth.convdiff_coeffs(8, 10.0)
+    b = dev(synth.rhs(512, tag=1))
+    x = torch.empty(512, dtype=torch.float64, device="cuda")
+    with pytest.raises(rgs.RgsError) as e:
+        rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs), rgs.gmres_desc(5, 32, 1e-6, ls_sweeps=9), b, x)
+    assert e.value.status == rgs.RGS_EINVAL
+    with pytest.raises(rgs.RgsError) as e:
+        rgs.rgs_gmres_batched(gpu_handle, [(rgs.stencil7(dims, coeffs), b, x)],
+                              rgs.gmres_desc(5, 32, 1e-6, ls_sweeps=1))
+    assert e.value.status == rgs.RGS_EINVAL
