@@ -1089,6 +1089,7 @@ struct QrGroup {
     std::vector<int64_t> order;   // indices into the caller's items
     int64_t max_m = 0;
     int64_t rows_p = 0;           // row chunk of the step-1 Gaussian product
+    int tile_p = 0;               // operand columns per work unit of the step-1 Gaussian product
     std::vector<int> active;      // active[i]: factorisations with a column i
     std::vector<int64_t> pre_proj, pre_sl, pre_row, pre_sign, pre_part, pre_red;
     std::vector<QrItemOff> off;
@@ -1121,11 +1122,13 @@ int64_t qr_group_npart(int64_t n, int sk_kind) {
 
 // Launch tables and workspace layout of one share (g.order already set).
 // table: the Gaussian products read the bf16 table; step 1 then runs over
-// kGemmRows-row chunks in chunk-affine order (a chunk's table slice for every
-// sketch-row tile fits one L2 beside a tile's columns), otherwise over
-// kGemmRowsP-row chunks in the order built.
+// kGemmRows-row chunks and 128-column tiles in chunk-affine order (a chunk's
+// table slice for every sketch-row tile fits one L2 beside a tile's columns),
+// otherwise over kGemmRowsP-row chunks and kGemmTileP-column tiles in the
+// order built.
 void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, bool table, Carver& c) {
     g.rows_p = table ? kGemmRows : kGemmRowsP;
+    g.tile_p = table ? 128 : kGemmTileP;   // the table's 128 x 128 output tiles (kb_table_gemm_t128)
     typedef float T;
     const int64_t cnt = (int64_t)g.order.size();
     auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[g.order[q]]; };
@@ -1200,7 +1203,7 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, bool table
                 return ca != cb ? ca > cb : a.n > b.n;
             };
         };
-        {   // step 1: the columns of every W in tiles of kGemmTileP that may span items
+        {   // step 1: the columns of every W in tiles of tile_p that may span items
             std::vector<int64_t> ord((size_t)cnt);
             for (int64_t q = 0; q < cnt; ++q) ord[q] = q;
             std::stable_sort(ord.begin(), ord.end(), by_class(32));
@@ -1208,8 +1211,8 @@ void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, bool table
             for (int64_t q : ord)
                 for (int64_t c2 = 0; c2 < it_of(q).m; ++c2) g.g_cols.push_back(make_int2((int)q, (int)c2));
             const int total = (int)g.g_cols.size() - first0;
-            for (int t0 = 0; t0 < total; t0 += kGemmTileP)
-                add_tile(g.g_units_p, first0 + t0, std::min(kGemmTileP, total - t0), g.rows_p);
+            for (int t0 = 0; t0 < total; t0 += g.tile_p)
+                add_tile(g.g_units_p, first0 + t0, std::min(g.tile_p, total - t0), g.rows_p);
             if (table) {
                 std::vector<GemmUnit> ord_units;
                 order_units(g.g_units_p, 0, g.g_units_p.size(), 2, ord_units);
@@ -1402,7 +1405,7 @@ struct QrGroupLauncher {
         if (!launch_batch_init(s, itd, nb, g.max_m * g.max_m)) return RGS_EDEVICE;
         // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
         if (gemm && !product<T, false>(reinterpret_cast<const GemmUnit*>(A + g.o_gunits_p), (int)g.g_units_p.size(),
-                                       (int)g.rows_p, kGemmTileP))
+                                       (int)g.rows_p, g.tile_p))
             return RGS_EDEVICE;
         if (!launch_batch_sketch_p<T>(s, sk_kind, itd, BlockMap{d_sign, nullptr, nb, 0}, g.pre_sign[nb],
                                       BlockMap{d_part, nullptr, nb, 0}, g.pre_part[nb],

@@ -729,6 +729,127 @@ __global__ __launch_bounds__(256) void kb_table_gemm(const BatchItem* __restrict
     }
 }
 
+// The table products over 128-column tiles as a 128 x 128 output tile per
+// workgroup: the four waves take the tile's four 32-column sub-tiles, and all
+// four share the unit's 128 sketch rows.  Per super-step the workgroup loads
+// the table slice of those 128 sketch rows (2 S groups of 8 rows: 4 KiB per
+// k-step pair, 16 KiB at S = 4) into LDS once, with 16-byte loads of whole
+// contiguous rows of the table, double-buffered; each wave reads its A
+// operands there (sketch sub-block q: table group r / 8 + S kk + s of sketch
+// row 128 jt + 32 q + jr, as kb_table_gemm) and streams its own columns as B
+// (the same contiguous row runs).  The table slice is so read once per 128
+// columns instead of once per 32; the arithmetic per output (the same exact
+// products, fp32 accumulation over the same k-steps in the same order) is that
+// of kb_table_gemm, so the partials are the same bits.
+template <typename TB, bool STEP4>
+__global__ __launch_bounds__(256) void kb_table_gemm_t128(const BatchItem* __restrict__ items,
+                                                          const GemmUnit* __restrict__ units,
+                                                          const int2* __restrict__ cols, int rows,
+                                                          const uint16_t* __restrict__ table, int tk, int64_t tgroups) {
+    constexpr int NP = sizeof(TB) == 2 ? 1 : 3;
+    constexpr int S = sizeof(TB) == 2 ? 4 : 2;
+    constexpr int GS = 2 * S;                       // table groups (8 rows each) per super-step
+    __shared__ u32x4v abuf[2][GS * 128];            // [buffer][group][sketch row], 16 bytes each
+    const GemmUnit un = units[blockIdx.x];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int jr = lane & 31, kk = lane >> 5;
+    int kmax = 0;
+    int64_t nmax = 0;
+    for (int c = 0; c < un.count; ++c) {
+        const BatchItem& it = items[cols[un.first + c].x];
+        kmax = max(kmax, it.k);
+        nmax = max(nmax, it.n);
+    }
+    if (un.jt * 128 >= kmax) return;                // workgroup-uniform: before any barrier
+    const int nq = min(4, (kmax - un.jt * 128 + 31) / 32);   // sketch sub-blocks with rows below kmax
+    // this wave's column (B operand) of sub-tile `wave`
+    const int c = wave * 32 + jr;
+    const TB* col = nullptr;
+    int64_t nb = 0;
+    bool vec = false;
+    if (c < un.count) {
+        const int2 ic = cols[un.first + c];
+        const BatchItem& it = items[ic.x];
+        col = STEP4 ? static_cast<const TB*>(it.Q) + (int64_t)ic.y * it.ldq
+                    : static_cast<const TB*>(it.W) + (int64_t)ic.y * it.ldw;
+        nb = it.n;
+        vec = it.vec_ok != 0;
+    }
+    const bool wave_has_cols = wave * 32 < un.count;   // wave-uniform
+    const int64_t r_begin = (int64_t)un.blk * rows;     // rows is a multiple of 16 S
+    const int64_t r_end = min(r_begin + (int64_t)rows, nmax);
+    // cooperative A load: entry e = t + 256 p of the super-step's GS x 128 (group, sketch row) entries
+    constexpr int AP = GS * 128 / 256;
+    auto load_a = [&](int64_t r, u32x4v v[AP]) {
+#pragma unroll
+        for (int p = 0; p < AP; ++p) {
+            const int e = t + 256 * p, g = e >> 7, jl = e & 127;
+            const int64_t o = r / 8 + g;
+            const int j = un.jt * 128 + jl;
+            v[p] = (j < tk && o < tgroups) ? *reinterpret_cast<const u32x4v*>(table + (o * tk + j) * 8)
+                                           : u32x4v{0u, 0u, 0u, 0u};
+        }
+    };
+    f32x16 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f32x16{0};
+    u32x4v av[AP];
+    RawRows<TB, S> b;
+    load_a(r_begin, av);
+    ld_rows<TB, S>(col, r_begin + 8 * S * kk, col ? nb : 0, vec, b);
+#pragma unroll
+    for (int p = 0; p < AP; ++p) abuf[0][t + 256 * p] = av[p];
+    __syncthreads();
+    int cur = 0;
+    for (int64_t r = r_begin; r < r_end; r += 16 * S) {
+        const RawRows<TB, S> cb = b;
+        const int64_t rn = r + 16 * S;
+        const bool more = rn < r_end;                  // workgroup-uniform
+        if (more) {   // the next super-step's operands while these are used
+            load_a(rn, av);
+            ld_rows<TB, S>(col, rn + 8 * S * kk, col ? nb : 0, vec, b);
+        }
+        if (wave_has_cols) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                u32x4v parts[3];
+                split8<TB, S>(cb, s, parts);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q < nq) {
+                        const bf16x8_t a_op = __builtin_bit_cast(bf16x8_t, abuf[cur][(S * kk + s) * 128 + 32 * q + jr]);
+#pragma unroll
+                        for (int pp = 0; pp < NP; ++pp)
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                a_op, __builtin_bit_cast(bf16x8_t, parts[pp]), acc[q], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int p = 0; p < AP; ++p) abuf[cur ^ 1][t + 256 * p] = av[p];
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    if (c >= un.count) return;
+    const int2 ic = cols[un.first + c];
+    const BatchItem& it = items[ic.x];
+    if (r_begin >= it.n) return;
+    float* out = STEP4 ? static_cast<float*>(it.part) + (int64_t)un.blk * it.k
+                       : static_cast<float*>(it.partP) + ((int64_t)ic.y * it.G_P + un.blk) * it.k;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= nq) break;
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) {
+            const int jj = un.jt * 128 + 32 * q + 8 * (tt / 4) + 4 * kk + (tt % 4);
+            if (jj < it.k) out[jj] = acc[q][tt];
+        }
+    }
+}
+
 // out[j + col*ldo] = scale * sum_{g=0}^{G-1} partials[(col*G + g)*k + j], in fp64 and
 // in a fixed order: 8 contiguous g-ranges summed by 8 threads, then combined in order.
 template <typename PT>
@@ -1201,7 +1322,7 @@ bool launch_batch_table_gemm(hipStream_t st, const BatchItem* items, const GemmU
         hipLaunchKernelGGL((kb_table_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
                            table, tk, tgroups);
     else if (tile <= 128)
-        hipLaunchKernelGGL((kb_table_gemm<TB, STEP4, 4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+        hipLaunchKernelGGL((kb_table_gemm_t128<TB, STEP4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
                            table, tk, tgroups);
     else
         return false;
