@@ -1122,13 +1122,12 @@ int64_t qr_group_npart(int64_t n, int sk_kind) {
 
 // Launch tables and workspace layout of one share (g.order already set).
 // table: the Gaussian products read the bf16 table; step 1 then runs over
-// kGemmRows-row chunks and 128-column tiles in chunk-affine order (a chunk's
-// table slice for every sketch-row tile fits one L2 beside a tile's columns),
-// otherwise over kGemmRowsP-row chunks and kGemmTileP-column tiles in the
-// order built.
+// kGemmRows-row chunks in chunk-affine order (a chunk's table slice for every
+// sketch-row tile fits one L2 beside a tile's columns), otherwise over
+// kGemmRowsP-row chunks in the order built; both on 128-column tiles.
 void plan_qr_group(QrGroup& g, const rgs_qr_item* items, int sk_kind, bool table, Carver& c) {
     g.rows_p = table ? kGemmRows : kGemmRowsP;
-    g.tile_p = table ? 128 : kGemmTileP;   // the table's 128 x 128 output tiles (kb_table_gemm_t128)
+    g.tile_p = 128;   // 128 x 128 output tiles (kb_table_gemm_t128 / kb_gauss_gemm_t128)
     typedef float T;
     const int64_t cnt = (int64_t)g.order.size();
     auto it_of = [&](int64_t q) -> const rgs_qr_item& { return items[g.order[q]]; };

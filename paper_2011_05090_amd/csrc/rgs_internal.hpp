@@ -79,7 +79,6 @@ bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, c
 // (partials per chunk into partP, G_P chunks per column).
 constexpr int kGemmRows = 2048;      // row chunk of the step-4 product
 constexpr int kGemmRowsP = 16384;    // row chunk of the step-1 product
-constexpr int kGemmTileP = 64;       // operand columns per unit of the step-1 product
 template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
                              const int2* cols, int rows, int tile);

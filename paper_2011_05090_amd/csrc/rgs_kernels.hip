@@ -529,6 +529,127 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
     }
 }
 
+// The drawn products over 128-column tiles as a 128 x 128 output tile per
+// workgroup: the four waves take the tile's four 32-column sub-tiles and share
+// the unit's 128 sketch rows, whose entries the workgroup draws once per
+// super-step of 32 rows into LDS (each of the 256 threads makes 4 Philox calls,
+// 16 entries; double-buffered) instead of every wave drawing its own 32 sketch
+// rows for its own columns: a quarter of the draws per column of the 32-column
+// tiles.  Each output sees the k-steps of kb_gauss_gemm in the same order
+// (k-step t of the 8-row step at r pairs rows r + t and r + 4 + t), so the
+// partials are the same bits.
+template <typename TB, bool STEP4>
+__global__ __launch_bounds__(256) void kb_gauss_gemm_t128(const BatchItem* __restrict__ items,
+                                                          const GemmUnit* __restrict__ units,
+                                                          const int2* __restrict__ cols, int rows) {
+    constexpr int R = 32;                            // rows per super-step
+    __shared__ float zbuf[2][R][128];
+    const GemmUnit un = units[blockIdx.x];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int jr = lane & 31, kk = lane >> 5;
+    int kmax = 0;
+    int64_t nmax = 0;
+    for (int c = 0; c < un.count; ++c) {
+        const BatchItem& it = items[cols[un.first + c].x];
+        kmax = max(kmax, it.k);
+        nmax = max(nmax, it.n);
+    }
+    if (un.jt * 128 >= kmax) return;                // workgroup-uniform: before any barrier
+    const int nq = min(4, (kmax - un.jt * 128 + 31) / 32);
+    const SketchArgs& sk = items[cols[un.first].x].sk;   // seed, sketch id, instance: shared
+    const int c = wave * 32 + jr;
+    const TB* col = nullptr;
+    int64_t nb = 0;
+    bool vec = false;
+    if (c < un.count) {
+        const int2 ic = cols[un.first + c];
+        const BatchItem& it = items[ic.x];
+        col = STEP4 ? static_cast<const TB*>(it.Q) + (int64_t)ic.y * it.ldq
+                    : static_cast<const TB*>(it.W) + (int64_t)ic.y * it.ldw;
+        nb = it.n;
+        vec = it.vec_ok != 0;
+    }
+    const bool wave_has_cols = wave * 32 < un.count;   // wave-uniform
+    const int64_t r_begin = (int64_t)un.blk * rows;     // rows is a multiple of R
+    const int64_t r_end = min(r_begin + (int64_t)rows, nmax);
+    // draw e = t + 256 p: Philox call for rows r + 4 (e >> 7) .. + 3 of sketch row 128 jt + (e & 127)
+    auto draw = [&](int64_t r, float z[4][4]) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int e = t + 256 * p, jl = e & 127;
+            const int j = un.jt * 128 + jl;
+            z[p][0] = z[p][1] = z[p][2] = z[p][3] = 0.f;
+            if (j < kmax) gauss4((uint32_t)(r / 4 + (e >> 7)), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z[p]);
+        }
+    };
+    auto store = [&](int buf, const float z[4][4]) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int e = t + 256 * p, q4 = e >> 7, jl = e & 127;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) zbuf[buf][4 * q4 + u][jl] = z[p][u];
+        }
+    };
+    f32x16 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f32x16{0};
+    float b[R / 8][4];
+    float z[4][4];
+    draw(r_begin, z);
+#pragma unroll
+    for (int u = 0; u < R / 8; ++u) ld4_rows(col, r_begin + 8 * u + 4 * kk, col ? nb : 0, vec, b[u]);
+    store(0, z);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t r = r_begin; r < r_end; r += R) {
+        float cb[R / 8][4];
+#pragma unroll
+        for (int u = 0; u < R / 8; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cb[u][v] = b[u][v];
+        const int64_t rn = r + R;
+        const bool more = rn < r_end;                  // workgroup-uniform
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < R / 8; ++u) ld4_rows(col, rn + 8 * u + 4 * kk, col ? nb : 0, vec, b[u]);
+        }
+        if (wave_has_cols) {
+#pragma unroll
+            for (int u = 0; u < R / 8; ++u) {
+                if (r + 8 * u >= r_end) break;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < nq)
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(zbuf[cur][8 * u + 4 * kk + tt][32 * q + jr],
+                                                                          cb[u][tt], acc[q], 0, 0, 0);
+            }
+        }
+        if (more) {   // the next super-step's entries, drawn while the loads above are in flight
+            draw(rn, z);
+            store(cur ^ 1, z);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    if (c >= un.count) return;
+    const int2 ic = cols[un.first + c];
+    const BatchItem& it = items[ic.x];
+    if (r_begin >= it.n) return;
+    float* out = STEP4 ? static_cast<float*>(it.part) + (int64_t)un.blk * it.k
+                       : static_cast<float*>(it.partP) + ((int64_t)ic.y * it.G_P + un.blk) * it.k;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= nq) break;
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) {
+            const int jj = un.jt * 128 + 32 * q + 8 * (tt / 4) + 4 * kk + (tt % 4);
+            if (jj < it.k) out[jj] = acc[q][tt];
+        }
+    }
+}
+
 // The same products with the bf16 Gaussian entries read from a table
 // (RGS_FLAG_THETA_BF16: theta = bf16(z) / sqrt(k_b), the table holding the
 // unscaled bf16(z) of the master matrix, group (o, j) of 8 columns at
@@ -1338,8 +1459,8 @@ bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmU
         hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 1>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
     else if (tile <= 64)
         hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
-    else if (tile <= 128)
-        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
+    else if (tile <= 128 && rows % 32 == 0)
+        hipLaunchKernelGGL((kb_gauss_gemm_t128<TB, STEP4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
     else
         return false;
     RGS_LAUNCH_CHECK();
