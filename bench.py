@@ -86,6 +86,72 @@ def sources_sha256(files):
     return h.hexdigest()
 
 
+def classical_gs_fp32(torch, W, variant):
+    """The classical Gram-Schmidt processes the paper compares RGS with
+    (Sec. 1.2, Sec. 5.1), in float32 throughout, on the GPU through torch
+    (comparison code, not part of the library): 'cgs' q' = w - Q (Q^T w);
+    'cgs2' the same projection twice; 'mgs' one previous column at a time;
+    then q = q' / ||q'||.  Returns Q (float32) and R (float32)."""
+    n, m = W.shape
+    Q = torch.empty((m, n), dtype=torch.float32, device=W.device).t()
+    R = torch.zeros((m, m), dtype=torch.float32, device=W.device)
+    for i in range(m):
+        v = W[:, i].float().clone()
+        if i > 0:
+            Qi = Q[:, :i]
+            if variant == "mgs":
+                for j in range(i):
+                    c = torch.dot(Q[:, j], v)
+                    v.sub_(c * Q[:, j])
+                    R[j, i] = c
+            else:
+                y = Qi.t().mv(v)
+                v.sub_(Qi.mv(y))
+                if variant == "cgs2":
+                    y2 = Qi.t().mv(v)
+                    v.sub_(Qi.mv(y2))
+                    y = y + y2
+                R[:i, i] = y
+        nv = torch.linalg.vector_norm(v)
+        R[i, i] = nv
+        Q[:, i] = v / nv
+    return Q, R
+
+
+def cgs2_fp64(torch, W, Q, R):
+    """Classical Gram-Schmidt with reorthogonalisation in fp64 on the GPU, for
+    the comparison the workload names (not part of the library; torch's
+    matrix-vector products, i.e. rocBLAS dgemv): per column
+    q' = w - Q (Q^T w), q'' = q' - Q (Q^T q'), q = q'' / ||q''||, with R
+    accumulating both coefficient vectors.  Four passes over Q_{i-1} per column
+    (8 n (i - 1) bytes each) against RGS's one."""
+    import numpy as np
+    n, m = W.shape
+    R.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(m):
+        v = W[:, i].clone()
+        if i > 0:
+            Qi = Q[:, :i]
+            y1 = Qi.t().mv(v)
+            v.sub_(Qi.mv(y1))
+            y2 = Qi.t().mv(v)
+            v.sub_(Qi.mv(y2))
+            R[:i, i] = y1 + y2
+        nv = torch.linalg.vector_norm(v)
+        R[i, i] = nv
+        Q[:, i] = v / nv
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = float(torch.linalg.norm(W - Q @ R) / torch.linalg.norm(W))
+    o2 = float(np.linalg.norm(np.eye(m) - (Q.t() @ Q).cpu().numpy(), 2))
+    nbytes = 4.0 * 8 * n * m * (m - 1) / 2 + 3.0 * 8 * n * m
+    return {"ms_per_qr": dt * 1000.0, "algorithmic_bytes": nbytes, "gbs": nbytes / dt / 1e9,
+            "backward_error": res, "norm2_I_minus_QtQ": o2,
+            "how": "torch fp64: two Q^T v / v - Q y passes per column (rocBLAS dgemv), one run"}
+
+
 def calibration_copy(torch, dev):
     """A plain 1 GiB device-to-device copy (1 GiB read + 1 GiB written): the
     reference the HBM byte counters of a run are scaled by."""
@@ -462,11 +528,13 @@ def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=
     k in {1500, 5000}.  For prefixes W_i (factorised with the a-posteriori
     certificate, Phi of Theta's size, eps* = 0.05) it reports what the paper
     plots: cond(Q_i), cond(S_i), ||W_i - Q_i R_i|| / ||W_i||, the embedding
-    distortion omega of Theta on range(Q_i) and its bound omega_bar.  CGS runs
-    as RGS with Theta = I and one Richardson sweep (beside two sweeps and the
-    Householder solve with Theta = I); MGS, CGS2 and the unique-precision RGS
-    are not run.  Metrics are computed in fp64 on the
-    device (measurement code)."""
+    distortion omega of Theta on range(Q_i) and its bound omega_bar.  The
+    paper's classical comparisons CGS, MGS and CGS2 run in float32 throughout
+    (inner products, projections and norms), as torch / rocBLAS operations on
+    the same GPU (comparison code, not part of the library); with
+    ``classical`` also RGS with Theta = I (one and two Richardson sweeps, the
+    Householder solve).  The unique-precision RGS is not run.  Metrics are
+    computed in fp64 on the device (measurement code)."""
     import numpy as np
     W = rgs.colmajor(n, m, torch.float32)
     W.copy_(torch.from_numpy(synth.f_mu_matrix(n, m, np.float64)).to("cuda"))
@@ -504,6 +572,24 @@ def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=
                 (k, i, cond_q, cond_s, err, omega, obar, 1000 * rep.seconds))
             del Q, R, S, Q64, G, C, U, TU
         out["k%d" % k] = rows
+    # the classical comparisons in float32 throughout (torch on the device)
+    for name in ("cgs_fp32", "mgs_fp32", "cgs2_fp32"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Q, R = classical_gs_fp32(torch, W, name.split("_")[0])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows = []
+        for i in prefixes:
+            Q64 = Q[:, :i].double()
+            ev = torch.linalg.eigvalsh(Q64.T @ Q64)
+            cond_q = float(torch.sqrt(ev[-1] / ev[0])) if float(ev[0]) > 0 else float("inf")
+            err = float(torch.linalg.norm(W64[:, :i] - Q64 @ R[:i, :i].double()) / torch.linalg.norm(W64[:, :i]))
+            rows.append({"i": i, "cond_Q": cond_q, "error": err})
+            log("  sec5.1 %s i=%d: cond(Q) %.3e err %.2e" % (name, i, cond_q, err))
+            del Q64
+        out[name] = {"seconds": dt, "rows": rows, "precision": "float32 throughout (torch on the GPU, comparison)"}
+        del Q, R
     # Theta = I (k = n): with one Richardson sweep of the least squares the
     # column step is classical Gram-Schmidt (fp32 projection, inner products in
     # fp64; the paper's CGS is float32 throughout); two sweeps refine the
@@ -718,6 +804,14 @@ def main():
                                   "status": rep64.status}
         extra["speedup_fp32_vs_fp64"] = ms64 / ms
         log("  %.2f ms/QR (fp32 path %.2fx faster)" % (ms64, ms64 / ms))
+        # plain fp64 CGS2 on the same GPU, for comparison (not part of the library):
+        # torch / rocBLAS matrix-vector products, two projections per column
+        log("fp64 CGS2 (torch/rocBLAS, comparison): 1 step")
+        extra["fp64_cgs2_torch"] = cgs2_fp64(torch, W64, Q64, R)
+        log("  %.1f ms/QR (fp32 RGS %.1fx faster), ||W-QR||/||W|| %.2e, ||I-Q^TQ||_2 %.2e" %
+            (extra["fp64_cgs2_torch"]["ms_per_qr"], extra["fp64_cgs2_torch"]["ms_per_qr"] / ms,
+             extra["fp64_cgs2_torch"]["backward_error"], extra["fp64_cgs2_torch"]["norm2_I_minus_QtQ"]))
+        extra["fp64_cgs2_torch"]["fp32_rgs_speedup"] = extra["fp64_cgs2_torch"]["ms_per_qr"] / ms
         del Q64
         # Gaussian sketch, fp32 path (VALU-bound on generation)
         dg = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32")
