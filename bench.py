@@ -65,9 +65,10 @@ def measured_traffic(n, m, k):
 
 # Gaussian sketch on the fly: VALU instructions per entry of Theta in the
 # generated code (one Philox4x32-10 call and two Box-Muller pairs give four
-# entries in about 110 instructions, and one fma applies each entry), and the
-# chip's non-packed fp32 VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz
-VALU_INSTR_PER_ENTRY = 28.5
+# entries in 89 instructions -- 16 of them 64-bit multiply-adds and 8
+# transcendental steps, each counted once -- and one fma applies each entry),
+# and the chip's non-packed fp32 VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz
+VALU_INSTR_PER_ENTRY = 23.25
 VALU_LANE_RATE = 256 * 64 * 2.4e9
 
 # the projection kernel and everything its code is built from
