@@ -180,21 +180,25 @@ def write_batched_traffic_record(fetch_db, write_db, sketch, batch=2048):
     warms up and, for the Gaussian products, tunes their schedule) from two
     rocprofv3 --pmc databases: every library kernel of the call, summed, with
     the counters scaled by the closing 1 GiB copy; beside the call's
-    algorithmic bytes.  Written to profiles/rgs_qr_batched_2048_<sketch>_traffic.json."""
+    algorithmic bytes.  A call ends with the closing scale pass of each of its
+    two shares, and the host waits for it before the next call, so the second
+    call is every dispatch after the first call's last scale pass up to its
+    own last one (the table generation of the bf16-table sketch included).
+    Written to profiles/rgs_qr_batched_2048_<sketch>_traffic.json."""
     import synth
     per = {}
     kernels = {}
     for name, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         r = _pmc_rows(db, counter)
         copies = [v for _, kn, v in r if "copyBuffer" in kn]
-        inits = [d for d, kn, _ in r if "kb_init" in kn]
-        if not copies or len(inits) < 4:
+        ends = [d for d, kn, _ in r if "kb_scale" in kn]
+        if not copies or len(ends) < 4:
             raise SystemExit("%s: expected two calls (two shares each) and a closing copy" % db)
-        first = inits[len(inits) // 2]          # the second call's first share starts here
+        after, last = ends[1], ends[3]
         factor = copies[-1] * 1024.0 / (1 << 30)
         tot = 0.0
         for d, kn, v in r:
-            if d >= first and "rgs::" in kn:
+            if after < d <= last and "rgs::" in kn:
                 tot += v
                 key = kn.split("(")[0]
                 kernels.setdefault(key, {"fetch_kib": 0.0, "write_kib": 0.0, "dispatches": 0})
@@ -411,14 +415,15 @@ def copy_ceiling(torch, dev, reps=7):
 
 
 def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian", "gaussian_bf16_table"), steps=2,
-                   warmup=1, gaussian_batch=2048):
+                   warmup=1, gaussian_batch=2048, graph=True):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
     m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and bf16-stored Q, all in
     one rgs_qr_batched call, with the P-SRHT, with the Gaussian sketch (the
     factorisations share one master Gaussian matrix, entries drawn in the
     products) and with that master matrix's bf16 entries made once per call
     into a table that the products read through bf16 matrix cores
-    (RGS_FLAG_THETA_BF16)."""
+    (RGS_FLAG_THETA_BF16).  With ``graph`` each sketch is timed again with
+    the calls replayed from captured graphs (RGS_FLAG_GRAPH)."""
     ns, ms_ = synth.batch_qr_sizes(batch)
     items = []
     t0 = time.perf_counter()
@@ -449,6 +454,18 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         bad = sum(1 for v in stat if v != 0)
+        # the same calls replayed from captured graphs (RGS_FLAG_GRAPH; the first call captures)
+        dt_graph = None
+        if graph:
+            rgs.rgs_qr_batched(h, its, sketch=lib_sketch, prec="bf16q", flags=flags | rgs.FLAG_GRAPH)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rep_g, stat_g, _ = rgs.rgs_qr_batched(h, its, sketch=lib_sketch, prec="bf16q",
+                                                      flags=flags | rgs.FLAG_GRAPH)
+            torch.cuda.synchronize()
+            dt_graph = (time.perf_counter() - t0) / steps
+            bad += sum(1 for v in stat_g if v != 0)
         # quality on a few items (fp64 on the device, spectral norms on the host)
         import numpy as np
         worst_be, worst_d2 = 0.0, 0.0
@@ -458,11 +475,14 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
         if sketch != "srht":   # autotuned sketch-product schedule (1..9)
             out[sketch + "_schedule"] = rgs.rgs_last_tuning(h)
         out[sketch] = {"items": len(its), "seconds": dt, "algorithmic_bytes": B, "gbs": B / dt / 1e9,
-                       "pct_hbm_peak": 100.0 * B / dt / 1e9 / HBM_PEAK_GBS, "failed_items": bad,
+                       "pct_hbm_peak": 100.0 * B / dt / 1e9 / HBM_PEAK_GBS, "graph_seconds": dt_graph,
+                       "failed_items": bad,
                        "status": rep.status, "sampled_max_backward_error": worst_be,
                        "sampled_max_norm2_I_minus_StS": worst_d2}
-        log("  batched %s x%d: %.3f s, %.1f GB/s algorithmic, max sampled ||W-QR||/||W|| %.2e, "
-            "||I-S^TS||_2 %.2e, failed %d" % (sketch, len(its), dt, B / dt / 1e9, worst_be, worst_d2, bad))
+        log("  batched %s x%d: %.3f s (graph replay %s s), %.1f GB/s algorithmic, max sampled "
+            "||W-QR||/||W|| %.2e, ||I-S^TS||_2 %.2e, failed %d"
+            % (sketch, len(its), dt, "-" if dt_graph is None else "%.3f" % dt_graph, B / dt / 1e9,
+               worst_be, worst_d2, bad))
     del items
     torch.cuda.empty_cache()
     return out
@@ -712,9 +732,11 @@ def main():
                     help="with --only batched-qr: comma-separated legs (srht, gaussian, gaussian_bf16_table)")
     ap.add_argument("--leg-steps", type=int, default=None, help="with --only: timed calls per leg")
     ap.add_argument("--leg-warmup", type=int, default=None, help="with --only: untimed calls per leg")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="with --only batched-qr: skip the graph-replayed timing")
     ap.add_argument("--batched-traffic", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "SKETCH"),
                     help="write the HBM-traffic record of one batched QR call from two rocprofv3 --pmc "
-                         "databases of 'bench.py --only batched-qr --sketches SKETCH --leg-warmup 1 "
+                         "databases of 'bench.py --only batched-qr --sketches SKETCH --leg-warmup 1 --no-graph "
                          "--leg-steps 1 --calibrate-copy' (no GPU needed) and exit")
     args = ap.parse_args()
     if args.traffic_record:
@@ -744,6 +766,8 @@ def main():
             kw["warmup"] = args.leg_warmup
         if args.sketches and args.only == "batched-qr":
             kw["sketches"] = tuple(args.sketches.split(","))
+        if args.no_graph and args.only == "batched-qr":
+            kw["graph"] = False
         res = leg(rgs, torch, synth, h, **kw)
         if args.calibrate_copy:
             calibration_copy(torch, torch.device("cuda:0"))

@@ -86,6 +86,7 @@ typedef enum {
 #define RGS_FLAG_TIME_KERNELS 2u /* time every projection+sketch launch with events */
 #define RGS_FLAG_GRAPH 4u        /* rgs_gmres_batched: capture a restart cycle once as a HIP graph
                                     and replay it while the set of running systems is unchanged.
+                                    rgs_qr_batched_ex: see there.
                                     rgs_qr: capture the factorisation's device work (all columns) once
                                     as a HIP graph, kept in the handle, and replay it on later calls
                                     with the same descriptor, pointers and leading dimensions (the
@@ -310,14 +311,24 @@ rgs_status rgs_qr_batched(rgs_handle *h, int64_t batch, const rgs_qr_item *items
                           int32_t prec, uint64_t seed, uint32_t sketch_id, int32_t *item_status,
                           int64_t *failed_column, rgs_report *rep);
 
-/* rgs_qr_batched with flags: 0, or RGS_FLAG_THETA_BF16 with the GAUSSIAN
- * sketch -- the master matrix with bf16 entries, bf16(z)/sqrt(k_b) (the
- * entries the flag gives rgs_qr), made once per call into a table of
- * 2 max(k_b) * 16 ceil(max(n_b)/16) bytes of the handle's scratch; the
- * products of steps 1 and 4 then read it through bf16 matrix-core
- * instructions (exact products: fp32 columns are split into three bf16
- * parts, bf16-basis columns are exact; fp32 accumulation) instead of drawing
- * the entries.  EINVAL for any other flag or sketch. */
+/* rgs_qr_batched with flags, any combination of:
+ *   RGS_FLAG_THETA_BF16 (GAUSSIAN sketch only) -- the master matrix with bf16
+ *     entries, bf16(z)/sqrt(k_b) (the entries the flag gives rgs_qr), made once
+ *     per call into a table of 2 max(k_b) * 16 ceil(max(n_b)/16) bytes of the
+ *     handle's scratch; the products of steps 1 and 4 then read it through
+ *     bf16 matrix-core instructions (exact products: fp32 columns are split
+ *     into three bf16 parts, bf16-basis columns are exact; fp32 accumulation)
+ *     instead of drawing the entries;
+ *   RGS_FLAG_GRAPH -- each of the two streams' kernel sequences (every column
+ *     of its share of the batch) is captured once as a HIP graph, kept in the
+ *     handle, and replayed on later calls with the same items (sizes,
+ *     pointers, leading dimensions; the contents of W may change), sketch,
+ *     seed, sketch_id, precision and flags, while the handle's scratch has not
+ *     moved.  The launch tables are still copied per call, before the graphs
+ *     run.  With the GAUSSIAN sketch, a call whose product schedule is not yet
+ *     tuned for this batch (the first, unless rgs_set_tuning forces one) runs
+ *     eagerly and tunes it.  Results are bitwise those of an eager call.
+ * EINVAL for any other flag, or THETA_BF16 with another sketch. */
 rgs_status rgs_qr_batched_ex(rgs_handle *h, int64_t batch, const rgs_qr_item *items, int32_t sketch,
                              int32_t prec, uint64_t seed, uint32_t sketch_id, uint32_t flags,
                              int32_t *item_status, int64_t *failed_column, rgs_report *rep);

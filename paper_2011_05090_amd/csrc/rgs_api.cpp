@@ -46,6 +46,11 @@ struct rgs_handle {
     hipGraph_t qr_graph = nullptr;
     hipGraphExec_t qr_exec = nullptr;
     std::vector<uint64_t> qr_key;
+    // RGS_FLAG_GRAPH on rgs_qr_batched_ex: one captured kernel sequence per
+    // share of the last captured batch, and its signature
+    hipGraph_t qrb_graph[2] = {nullptr, nullptr};
+    hipGraphExec_t qrb_exec[2] = {nullptr, nullptr};
+    std::vector<uint64_t> qrb_key;
 };
 
 // Fixed device scratch of rgs_qr_noalloc, for callers that cannot allocate.
@@ -1374,6 +1379,12 @@ struct QrGroupLauncher {
     }
 
     rgs_status begin(int sched) {
+        const rgs_status st = upload(sched);
+        return st != RGS_OK ? st : launch_first();
+    }
+
+    // The share's launch tables (host -> device copies, on stream s).
+    rgs_status upload(int sched) {
         gemm = sk_kind == SK_GAUSS;
         nb = (int)g.order.size();
         if ((sk_kind == SK_SRHT && hipMemcpyAsync(A + g.o_rows, g.rows_all.data(), g.rows_all.size() * sizeof(int),
@@ -1401,6 +1412,11 @@ struct QrGroupLauncher {
         // the copies come before the first launch: a copy from pageable host
         // memory can hold the host until the stream has drained
         if (gemm && sched > 0 && !upload_schedule(sched)) return RGS_EDEVICE;
+        return RGS_OK;
+    }
+
+    // The launches before the first column: initialisation and step 1.
+    rgs_status launch_first() {
         if (!launch_batch_init(s, itd, nb, g.max_m * g.max_m)) return RGS_EDEVICE;
         // step 1 for every column of every factorisation: P_b = Theta_b W_b (and the SRHT signs)
         if (gemm && !product<T, false>(reinterpret_cast<const GemmUnit*>(A + g.o_gunits_p), (int)g.g_units_p.size(),
@@ -1477,8 +1493,8 @@ struct QrGroupLauncher {
 
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
-                          uint32_t sid, bool use_table, int32_t* item_status, int64_t* failed_column,
-                          rgs_report* rep) {
+                          uint32_t sid, bool use_table, bool want_graph, int32_t* item_status,
+                          int64_t* failed_column, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<int64_t> order((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) order[b] = b;
@@ -1526,6 +1542,24 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         if (h->tune_mode > 0) sched = h->tune_mode;
         else if (h->gemm_tuned.count(sig)) sched = h->gemm_tuned[sig];
     }
+    std::vector<QrGroupLauncher<TQ, DEFER>> run;
+    for (int gi = 0; gi < ng; ++gi) {
+        run.emplace_back(h, grp[gi], sk_kind, A, h->stream);
+        if (use_table) {
+            run.back().table = reinterpret_cast<const uint16_t*>(A + o_table);
+            run.back().tk = tk;
+            run.back().tgroups = tgroups;
+        }
+    }
+    // RGS_FLAG_GRAPH: every share's kernel sequence (from its initialisation
+    // to the closing scale pass) is captured once as a graph for this batch
+    // signature, arena and schedule, and replayed on its stream; the launch
+    // tables of both shares are copied eagerly, on the handle's stream, before
+    // the first launch of the call.  A call whose Gaussian schedule is not
+    // tuned yet runs eagerly (and tunes it).
+    const bool use_graph = want_graph && (!gemm || sched > 0);
+    for (int gi = 0; gi < ng && use_graph; ++gi)
+        if ((st = run[gi].upload(sched)) != RGS_OK) return st;
     // the table is made on the handle's stream before the shares fork from it
     if (use_table && !launch_theta_table(h->stream, make_sketch(SK_GAUSS, tk, seed, sid, 0u), tgroups * 8,
                                          reinterpret_cast<uint16_t*>(A + o_table)))
@@ -1535,19 +1569,57 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (ng > 1) {
         if (ensure_aux(h) != RGS_OK) return RGS_EDEVICE;
         ss[1] = h->aux;
+        run[1].s = h->aux;
         if (hipEventRecord(h->fork_ev, h->stream) != hipSuccess || hipStreamWaitEvent(h->aux, h->fork_ev, 0) != hipSuccess)
             return RGS_EDEVICE;
     }
-    std::vector<QrGroupLauncher<TQ, DEFER>> run;
-    for (int gi = 0; gi < ng; ++gi) {
-        run.emplace_back(h, grp[gi], sk_kind, A, ss[gi]);
-        if (use_table) {
-            run.back().table = reinterpret_cast<const uint16_t*>(A + o_table);
-            run.back().tk = tk;
-            run.back().tgroups = tgroups;
+    rgs_status est = RGS_OK;
+    if (use_graph) {
+        std::vector<uint64_t> key = {sig, (uint64_t)sched, (uint64_t)(uintptr_t)A, (uint64_t)h->arena_bytes,
+                                     (uint64_t)sk_kind, seed, sid, (uint64_t)use_table, (uint64_t)ng};
+        for (int64_t b = 0; b < batch; ++b) {
+            const rgs_qr_item& it = items[b];
+            for (uint64_t v : {(uint64_t)it.n, (uint64_t)it.m, (uint64_t)it.k, (uint64_t)(uintptr_t)it.W,
+                               (uint64_t)it.ldw, (uint64_t)(uintptr_t)it.Q, (uint64_t)it.ldq,
+                               (uint64_t)(uintptr_t)it.R, (uint64_t)it.ldr, (uint64_t)(uintptr_t)it.S,
+                               (uint64_t)it.lds})
+                key.push_back(v);
         }
-    }
-    rgs_status est = run[0].begin(sched);
+        if (h->qrb_key != key) {
+            for (int gi = 0; gi < 2; ++gi) {
+                if (h->qrb_exec[gi]) (void)hipGraphExecDestroy(h->qrb_exec[gi]);
+                if (h->qrb_graph[gi]) (void)hipGraphDestroy(h->qrb_graph[gi]);
+                h->qrb_exec[gi] = nullptr;
+                h->qrb_graph[gi] = nullptr;
+            }
+            h->qrb_key.clear();
+            if (!h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
+                est = RGS_EDEVICE;
+            for (int gi = 0; gi < ng && est == RGS_OK; ++gi) {
+                QrGroupLauncher<TQ, DEFER>& L = run[gi];
+                L.s = h->capture;
+                if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) {
+                    est = RGS_EDEVICE;
+                    break;
+                }
+                est = L.launch_first();
+                for (int64_t i = 0; i < grp[gi].max_m && est == RGS_OK; ++i) est = L.step(i, sched, sig);
+                if (est == RGS_OK) est = L.end();
+                L.s = ss[gi];
+                hipGraph_t gr = nullptr;
+                const bool ended = hipStreamEndCapture(h->capture, &gr) == hipSuccess;
+                if (est == RGS_OK &&
+                    (!ended || hipGraphInstantiate(&h->qrb_exec[gi], gr, nullptr, nullptr, 0) != hipSuccess))
+                    est = RGS_EDEVICE;
+                h->qrb_graph[gi] = gr;
+                if (est != RGS_OK) (void)hipGetLastError();
+            }
+            if (est == RGS_OK) h->qrb_key = key;
+        }
+        for (int gi = 0; gi < ng && est == RGS_OK; ++gi)
+            if (hipGraphLaunch(h->qrb_exec[gi], ss[gi]) != hipSuccess) est = RGS_EDEVICE;
+    } else {
+        est = run[0].begin(sched);
     // an untuned Gaussian product: share 0 (it holds the largest m) runs alone
     // up to the column whose product it times, so the timing sees no other work
     int64_t done0 = 0;
@@ -1560,6 +1632,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         for (int gi = 0; gi < ng && est == RGS_OK; ++gi)
             if (i < grp[gi].max_m && (gi > 0 || i >= done0)) est = run[gi].step(i, sched, sig);
     for (int gi = 0; gi < ng && est == RGS_OK; ++gi) est = run[gi].end();
+    }
     if (ng > 1) {   // join (also after a failed enqueue, so no work is left behind unordered)
         if (hipEventRecord(h->join_ev, h->aux) != hipSuccess || hipStreamWaitEvent(h->stream, h->join_ev, 0) != hipSuccess)
             est = RGS_EDEVICE;
@@ -2178,6 +2251,10 @@ rgs_status rgs_destroy(rgs_handle* h) {
     for (hipEvent_t e : h->chunk_ev) (void)hipEventDestroy(e);
     if (h->qr_exec) (void)hipGraphExecDestroy(h->qr_exec);
     if (h->qr_graph) (void)hipGraphDestroy(h->qr_graph);
+    for (int gi = 0; gi < 2; ++gi) {
+        if (h->qrb_exec[gi]) (void)hipGraphExecDestroy(h->qrb_exec[gi]);
+        if (h->qrb_graph[gi]) (void)hipGraphDestroy(h->qrb_graph[gi]);
+    }
     if (h->capture) (void)hipStreamDestroy(h->capture);
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->arena) (void)hipFree(h->arena);
@@ -2366,18 +2443,19 @@ rgs_status rgs_qr_batched_ex(rgs_handle* h, int64_t batch, const rgs_qr_item* it
     if (!h || batch < 1 || batch > 65535 || !items) return RGS_EINVAL;
     if (sketch != RGS_SKETCH_GAUSSIAN && sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if (prec != RGS_P_FP32_LS64 && prec != RGS_P_BF16Q_FP32_LS64) return RGS_EINVAL;
-    if ((flags & ~RGS_FLAG_THETA_BF16) != 0) return RGS_EINVAL;
+    if ((flags & ~(RGS_FLAG_THETA_BF16 | RGS_FLAG_GRAPH)) != 0) return RGS_EINVAL;
     const bool tab = (flags & RGS_FLAG_THETA_BF16) != 0;
+    const bool graph = (flags & RGS_FLAG_GRAPH) != 0;
     if (tab && sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     const int sk_kind = sketch_kind(sketch);
     for (int64_t b = 0; b < batch; ++b)
         if (!valid_item(items[b], sk_kind)) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (prec == RGS_P_BF16Q_FP32_LS64)
-        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, item_status, failed_column,
-                                          rep);
-    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, item_status, failed_column,
-                                        rep);
+        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, graph, item_status,
+                                          failed_column, rep);
+    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, graph, item_status,
+                                        failed_column, rep);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;
 } catch (...) {

@@ -82,3 +82,26 @@ def test_committed_traffic_record_is_used_only_while_it_applies(monkeypatch):
     assert bench.measured_traffic(1 << 21, 512, 2048) is None
     monkeypatch.setattr(bench, "sources_sha256", lambda files: "changed")
     assert bench.measured_traffic(1 << 22, 512, 2048) is None
+
+
+def test_batched_traffic_record_takes_the_second_call(tmp_path, monkeypatch):
+    """One batched call = the dispatches after the previous call's last scale
+    pass up to its own last one (two shares, two scale passes per call); the
+    table generation before the second call's shares counts, the first call
+    (warm-up and tuning) and anything after the second call do not."""
+    init, proj, scale, table = "rgs::kb_init(a)", "rgs::kb_qa(a)", "rgs::kb_scale<bf16, true>(a)", "rgs::k_theta_table(a)"
+    call1 = [(table, 1e6), (init, 1.0), (init, 1.0), (proj, 1e6), (proj, 1e6), (scale, 1.0), (scale, 1.0)]
+    call2 = [(table, 7.0), (init, 11.0), (proj, 13.0), (init, 17.0), (proj, 19.0), (scale, 23.0), (scale, 29.0)]
+    after = [(table, 1e6), (init, 1e6), (scale, 1e6), (scale, 1e6)]
+    copy = [("__amd_rocclr_copyBuffer", 524288.0)]
+    _counter_db(tmp_path / "f.db", "FETCH_SIZE", call1 + call2 + after + copy)
+    _counter_db(tmp_path / "w.db", "WRITE_SIZE", call1 + call2 + after + [("__amd_rocclr_copyBuffer", 1048576.0)])
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    bench.write_batched_traffic_record(str(tmp_path / "f.db"), str(tmp_path / "w.db"), "gaussian_bf16_table", batch=4)
+    rec = json.load(open(tmp_path / "profiles" / "rgs_qr_batched_2048_gaussian_bf16_table_traffic.json"))
+    raw = sum(v for _, v in call2)
+    assert rec["fetch_kib_raw"] == raw and rec["write_kib_raw"] == raw
+    assert rec["traffic_bytes"] == pytest.approx(raw * 1024 / 0.5 + raw * 1024 / 1.0)
+    assert rec["kernels"]["rgs::k_theta_table"]["dispatches"] == 1
+    assert rec["kernels"]["rgs::kb_init"]["dispatches"] == 2

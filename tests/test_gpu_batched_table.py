@@ -128,7 +128,7 @@ def test_table_flag_rejected(gpu_handle):
     n, m = W.shape
     items = [(to_dev(W, torch.float32), rgs.colmajor(n, m, torch.float32), rgs.colmajor(m, m, torch.float64),
               rgs.colmajor(k, m, torch.float64), k)]
-    for sketch, flags in (("srht", rgs.FLAG_THETA_BF16), ("gaussian", rgs.FLAG_GRAPH),
+    for sketch, flags in (("srht", rgs.FLAG_THETA_BF16), ("gaussian", rgs.FLAG_LAG),
                           ("gaussian", rgs.FLAG_THETA_BF16 | rgs.FLAG_DIAGNOSTICS)):
         with pytest.raises(rgs.RgsError) as e:
             rgs.rgs_qr_batched(gpu_handle, items, sketch=sketch, prec="fp32", flags=flags)
