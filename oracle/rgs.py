@@ -34,6 +34,13 @@ Precision models (Sec. 2.3, the paragraph after Algorithm 2):
           sketches qb_i, and step 3 uses the stored columns with the
           coefficients y_c / r_cc rounded to float32.  The returned Q is
           bf16(qb_i / r_ii).
+  'fp32u' unique precision u_crs = u_fine = float32 (the comparison of
+          Sec. 5.1): every step in float32 arithmetic -- the sketches of
+          steps 1 and 4 (entries rounded to float32 once), the least squares
+          of step 2 (LAPACK's float32 Householder QR, sgeqrf, and a float32
+          triangular solve),
+          steps 3, 5, 6 and 7.  R, S and P are returned as fp64 arrays that
+          hold float32 values.
 
 Breakdown (not specified by the paper): a non-finite p_i or s'_i, r_ii = 0,
 or r_ii <= 2**-50 ||p_i|| stops the factorisation and reports the column.
@@ -61,9 +68,13 @@ def bf16_round(x):
 
 
 def _ls(S, p, method):
-    """Step 2: argmin_y ||S y - p|| for S (k x j), fp64."""
+    """Step 2: argmin_y ||S y - p|| for S (k x j), in the arithmetic of the
+    operands (fp64, or float32 for the unique-precision model)."""
     if method == "householder":
-        Qs, Rs = np.linalg.qr(S, mode="reduced")
+        if S.dtype == np.float32:   # LAPACK sgeqrf / sorgqr: numpy's qr would work in fp64
+            Qs, Rs = scipy.linalg.qr(S, mode="economic")
+        else:
+            Qs, Rs = np.linalg.qr(S, mode="reduced")
         return scipy.linalg.solve_triangular(Rs, Qs.T @ p, lower=False)
     if method == "richardson1":
         return S.T @ p
@@ -79,10 +90,12 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
     Returns dict(Q, R, S, P).  Q has the storage type of the precision model
     (fp64, or float32 for 'fp32'); R, S and P are fp64.  Raises Breakdown.
     """
-    if precision not in ("fp64", "fp32", "bf16q"):
+    if precision not in ("fp64", "fp32", "bf16q", "fp32u"):
         raise ValueError(precision)
     store = np.float64 if precision == "fp64" else np.float32
     bf16 = precision == "bf16q"
+    # arithmetic of steps 1, 2 and 4-7 (u_fine)
+    fine = np.float32 if precision == "fp32u" else np.float64
     W = np.asarray(W).astype(store)
     n, m = W.shape
     k = theta.k
@@ -96,7 +109,7 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
     P = np.zeros((k, m))
     for i in range(m):                                   # 0-based column index
         w = W[:, i]
-        p = theta.apply(w.astype(np.float64))            # step 1
+        p = theta.apply(w.astype(fine), fine)            # step 1
         P[:, i] = p
         if not np.all(np.isfinite(p)):
             raise Breakdown(i, True)
@@ -113,10 +126,11 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
             qp = w.copy()                                # q'_1 = w_1
             sp = p.copy()                                # s'_1 = p_1
         else:
-            r = _ls(S[:, :i], p, ls)                     # step 2
+            Si = S[:, :i] if fine == np.float64 else S[:, :i].astype(fine)
+            r = _ls(Si, p, ls)                           # step 2
             R[:i, i] = r
             qp = w - Q[:, :i] @ r.astype(store)          # step 3 (u_crs)
-            sp = theta.apply(qp.astype(np.float64))      # step 4
+            sp = theta.apply(qp.astype(fine), fine)      # step 4
         rii = np.linalg.norm(sp)                         # step 5
         if not np.isfinite(rii) or not np.all(np.isfinite(sp)):
             raise Breakdown(i, True)
@@ -128,7 +142,7 @@ def rgs_qr(W, theta, ls="householder", precision="fp64"):
             scale[i] = 1.0 / rii
             Q[:, i] = bf16_round((Qb[:, i].astype(np.float64) * scale[i]).astype(np.float32))   # step 7
         else:
-            Q[:, i] = (qp.astype(np.float64) / rii).astype(store)   # step 7
+            Q[:, i] = (qp.astype(fine) / rii).astype(store)   # step 7
     return {"Q": Q, "R": R, "S": S, "P": P}
 
 

@@ -173,12 +173,13 @@ def srht_rows(s, k, seed, sketch_id, instance):
     return rows
 
 
-def fwht(x):
+def fwht(x, dtype=np.float64):
     """Unnormalised Walsh-Hadamard transform in Sylvester order along axis 0.
 
-    x: array of shape (s, ...) with s a power of two.  Returns H_s @ x.
+    x: array of shape (s, ...) with s a power of two.  Returns H_s @ x,
+    every butterfly computed in arithmetic ``dtype``.
     """
-    y = np.array(x, dtype=np.float64, copy=True)
+    y = np.array(x, dtype=dtype, copy=True)
     s = y.shape[0]
     if s & (s - 1):
         raise ValueError("length must be a power of two")
@@ -199,7 +200,10 @@ def fwht(x):
 # ----------------------------------------------------------------------------
 
 class Sketch:
-    """Common interface: ``apply(X)`` returns Theta @ X in fp64."""
+    """Common interface: ``apply(X, dtype)`` returns Theta @ X computed in
+    arithmetic ``dtype`` (fp64 by default; float32 for the unique-precision
+    model, where the entries are rounded to float32 once and every product
+    and sum is a float32 operation)."""
 
     kind = None
 
@@ -211,7 +215,7 @@ class Sketch:
         """Dense block Theta[j0:j1, l0:l1] (fp64)."""
         raise NotImplementedError
 
-    def apply(self, X):
+    def apply(self, X, dtype=np.float64):
         raise NotImplementedError
 
 
@@ -232,17 +236,17 @@ class Gaussian(Sketch):
         l1 = self.n if l1 is None else l1
         return gaussian_block(self.k, self.seed, self.sketch_id, self.instance, j0, j1, l0, l1)
 
-    def apply(self, X):
-        X = np.asarray(X, dtype=np.float64)
+    def apply(self, X, dtype=np.float64):
+        X = np.asarray(X, dtype=dtype)
         vec = X.ndim == 1
         X2 = X.reshape(self.n, -1)
         if self._dense is not None:
-            Y = self._dense @ X2
+            Y = self._dense.astype(dtype) @ X2
         else:
-            Y = np.zeros((self.k, X2.shape[1]))
+            Y = np.zeros((self.k, X2.shape[1]), dtype=dtype)
             for l0 in range(0, self.n, self.BLOCK):
                 l1 = min(self.n, l0 + self.BLOCK)
-                Y += self.materialize(0, self.k, l0, l1) @ X2[l0:l1]
+                Y += self.materialize(0, self.k, l0, l1).astype(dtype) @ X2[l0:l1]
         return Y[:, 0] if vec else Y
 
 
@@ -281,13 +285,16 @@ class SRHT(Sketch):
         self.d = srht_signs(self.n, seed, sketch_id, instance)
         self.rows = srht_rows(self.s, self.k, seed, sketch_id, instance)
 
-    def apply(self, X):
-        X = np.asarray(X, dtype=np.float64)
+    def apply(self, X, dtype=np.float64):
+        X = np.asarray(X, dtype=dtype)
         vec = X.ndim == 1
         X2 = X.reshape(self.n, -1)
-        pad = np.zeros((self.s, X2.shape[1]))
-        pad[: self.n] = self.d[:, None] * X2
-        Y = fwht(pad)[self.rows] / math.sqrt(self.k)
+        pad = np.zeros((self.s, X2.shape[1]), dtype=dtype)
+        pad[: self.n] = self.d.astype(dtype)[:, None] * X2      # sign flips: exact
+        if dtype == np.float64:
+            Y = fwht(pad)[self.rows] / math.sqrt(self.k)
+        else:   # k**-1/2 rounded to the arithmetic type once, then one product per entry
+            Y = fwht(pad, dtype)[self.rows] * dtype(1.0 / math.sqrt(self.k))
         return Y[:, 0] if vec else Y
 
     def materialize(self, j0=0, j1=None, l0=0, l1=None):
@@ -309,8 +316,8 @@ class Identity(Sketch):
         if self.k != self.n:
             raise ValueError("identity sketch needs k = n")
 
-    def apply(self, X):
-        return np.array(X, dtype=np.float64, copy=True)
+    def apply(self, X, dtype=np.float64):
+        return np.array(X, dtype=dtype, copy=True)
 
     def materialize(self, j0=0, j1=None, l0=0, l1=None):
         j1 = self.k if j1 is None else j1

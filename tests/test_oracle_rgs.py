@@ -18,6 +18,10 @@
   keeps it at O(u) (Bjorck; Giraud, Langou, Rozloznik); the float32 variants
   carry float32 rounding, agree with the fp64 ones to O(u32 kappa) in R, and
   keep the same ordering.
+* The unique-precision model ('fp32u', every step in float32; Sec. 5.1): the
+  closed form above at float32 tolerance, outputs that are float32 values,
+  and rounding at the float32 level in the sketch and least-squares steps
+  (not only in step 3, as in the multi-precision 'fp32').
 """
 
 import math
@@ -252,3 +256,45 @@ def test_classical_gs_float32_variants(fn):
     if fn == "cgs":
         assert loss >= 10 * U32 * kap          # well above what MGS reaches
     assert metrics.backward_error(W.astype(np.float32), Q3, R3) <= 10 * U32
+
+
+@pytest.mark.parametrize("kind,n,m,k", [("srht", 3000, 12, 48), ("gaussian", 900, 10, 40), ("rademacher", 1200, 8, 64)])
+def test_unique_precision_closed_form(kind, n, m, k):
+    """'fp32u': R is the positive-diagonal R factor of qr(Theta W) up to
+    float32 rounding amplified by kappa(W); S R = Theta W to float32
+    rounding; Q = W R^-1 likewise; every R, S entry is a float32 value."""
+    W = _wellcond(n, m, smin=1e-1, tag=11)
+    th = sketch.make(kind, n, k, seed=6)
+    out = rgs.rgs_qr(W, th, precision="fp32u")
+    R, S, Q = out["R"], out["S"], out["Q"]
+    assert Q.dtype == np.float32
+    assert np.array_equal(R.astype(np.float32).astype(np.float64), R)
+    assert np.array_equal(S.astype(np.float32).astype(np.float64), S)
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    W32 = W.astype(np.float32).astype(np.float64)
+    P = th.apply(W32)
+    _, Rq = np.linalg.qr(P)
+    Rq = np.sign(np.diag(Rq))[:, None] * Rq
+    kappa = metrics.cond(W)
+    tol = 50 * U32 * math.sqrt(n) * kappa
+    assert np.linalg.norm(R - Rq) / np.linalg.norm(Rq) <= tol
+    assert np.linalg.norm(S @ R - P) / np.linalg.norm(P) <= tol
+    Qc = np.linalg.solve(Rq.T, W32.T).T
+    assert np.linalg.norm(Q.astype(np.float64) - Qc) / np.linalg.norm(Qc) <= tol
+
+
+def test_unique_precision_rounds_the_sketch_space_steps_in_float32():
+    """Against the multi-precision 'fp32' (float32 only in step 3) on the same
+    input: the float32 sketches and least squares of 'fp32u' move R by more
+    than fp64 rounding and by no more than float32 rounding, and 'fp32u' is
+    the farther of the two from the fp64 factorisation."""
+    n, m, k = 4096, 24, 96
+    W = _wellcond(n, m, smin=1e-1, tag=12)
+    th = sketch.SRHT(n, k, seed=7)
+    u = rgs.rgs_qr(W, th, precision="fp32u")["R"]
+    mp = rgs.rgs_qr(W, th, precision="fp32")["R"]
+    d = rgs.rgs_qr(W.astype(np.float32).astype(np.float64), th, precision="fp64")["R"]
+    scale = np.linalg.norm(d)
+    du, dm = np.linalg.norm(u - d) / scale, np.linalg.norm(mp - d) / scale
+    assert 1e-12 < np.linalg.norm(u - mp) / scale < 1e-4
+    assert du > dm

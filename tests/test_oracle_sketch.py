@@ -213,3 +213,36 @@ def test_omega_equals_bruteforce_embedding_distortion(kind):
     om = metrics.omega(TV, V)
     assert brute <= om * (1 + 1e-12)
     assert brute >= om * (1 - 1e-4)
+
+
+@pytest.mark.parametrize("n,k", [(1000, 64), (4096, 128), (777, 33)])
+def test_srht_float32_apply_is_exact_on_small_integers(n, k):
+    """Unique-precision sketches (float32 arithmetic): on small-integer input
+    every butterfly of the float32 FWHT is exact (|values| <= n * 8 < 2**24),
+    so the float32 apply must equal the integer transform H_s D x, computed
+    here from the dense +-1 definition in int64, times float32(k**-1/2), as
+    one float32 product per entry -- bit for bit."""
+    th = sketch.SRHT(n, k, seed=5)
+    x = np.random.default_rng(n).integers(-8, 9, size=n)
+    signs = np.rint(th.materialize() * math.sqrt(k)).astype(np.int64)   # +-1 entries of H_s D, sampled rows
+    ints = signs @ x
+    want = ints.astype(np.float32) * np.float32(1.0 / math.sqrt(k))
+    got = th.apply(x.astype(np.float32), np.float32)
+    assert got.dtype == np.float32
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "rademacher", "srht"])
+def test_float32_apply_within_the_float32_error_bound(kind):
+    """The float32 apply of each sketch against the fp64 one: every entry of
+    Theta x rounded once to float32, then float32 sums, so |err| <= (n + 2) u32
+    sum_l |theta_jl x_l| (the standard bound for a computed inner product)."""
+    n, k = 1500, 40
+    th = sketch.make(kind, n, k, seed=9)
+    x = np.random.default_rng(3).standard_normal(n).astype(np.float32)
+    y32 = th.apply(x, np.float32)
+    assert y32.dtype == np.float32
+    y64 = th.apply(x.astype(np.float64))
+    bound = (n + 2) * 2.0 ** -24 * (np.abs(th.materialize()) @ np.abs(x.astype(np.float64)))
+    assert np.all(np.abs(y32.astype(np.float64) - y64) <= bound)
+    assert np.any(y32.astype(np.float64) != y64)   # the float32 rounding is there
