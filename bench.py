@@ -554,45 +554,53 @@ def sec51_leg(rgs, torch, synth, h, n=10 ** 6, m=300, ks=(1500, 5000), prefixes=
     (inner products, projections and norms), as torch / rocBLAS operations on
     the same GPU (comparison code, not part of the library); with
     ``classical`` also RGS with Theta = I (one and two Richardson sweeps, the
-    Householder solve).  The unique-precision RGS is not run.  Metrics are
-    computed in fp64 on the device (measurement code)."""
+    Householder solve).  The unique-precision RGS (RGS_P_FP32: every step in
+    float32) runs on the same prefixes and sketches as the multi-precision
+    one (keys up_k1500, up_k5000).  Metrics are computed in fp64 on the device
+    (measurement code)."""
     import numpy as np
     W = rgs.colmajor(n, m, torch.float32)
     W.copy_(torch.from_numpy(synth.f_mu_matrix(n, m, np.float64)).to("cuda"))
     W64 = W.double()
-    out = {"n": n, "m": m, "eps_star": eps_star, "precision": "fp32 projection, fp64 LS", "sketch": "srht"}
-    for k in ks:
-        rows = []
-        for i in prefixes:
-            Wi = W[:, :i]
-            Q = rgs.colmajor(n, i, torch.float32)
-            R = rgs.colmajor(i, i, torch.float64)
-            S = rgs.colmajor(k, i, torch.float64)
-            d = rgs.qr_desc(n, i, k, sketch="srht", prec="fp32", flags=rgs.FLAG_CERTIFY)
-            rep = rgs.rgs_qr(h, d, Wi, Q, R, S)
-            torch.cuda.synchronize()
-            Q64 = Q.double()
-            G = Q64.T @ Q64
-            ev = torch.linalg.eigvalsh(G)
-            cond_q = float(torch.sqrt(ev[-1] / ev[0]))
-            sv = torch.linalg.svdvals(S)
-            cond_s = float(sv[0] / sv[-1])
-            err = float(torch.linalg.norm(W64[:, :i] - Q64 @ R) / torch.linalg.norm(W64[:, :i]))
-            # omega: distortion of Theta on range(Q_i), from an l2-orthonormal basis U = Q C^-1
-            C = torch.linalg.cholesky(G, upper=True)
-            U = Q64 @ torch.linalg.inv(C)          # i x i inverse: cond(Q_i) is O(1)
-            TU = rgs.colmajor(k, i, torch.float64)
-            rgs.rgs_sketch_apply(h, rgs.qr_desc(n, i, k, sketch="srht", prec="fp64"), U.contiguous().T.contiguous().T,
-                                 TU)
-            torch.cuda.synchronize()
-            omega = float(torch.linalg.matrix_norm(torch.eye(i, dtype=torch.float64, device="cuda") - TU.T @ TU, 2))
-            obar = rgs.rgs_omega_bar(rep.cert_smin_q, rep.cert_smax_q, eps_star)
-            rows.append({"i": i, "status": rep.status, "cond_Q": cond_q, "cond_S": cond_s, "error": err,
-                         "omega": omega, "omega_bar": obar, "seconds": rep.seconds})
-            log("  sec5.1 k=%d i=%d: cond(Q) %.3f cond(S) %.3f err %.2e omega %.3f omega_bar %.3f (%.1f ms)" %
-                (k, i, cond_q, cond_s, err, omega, obar, 1000 * rep.seconds))
-            del Q, R, S, Q64, G, C, U, TU
-        out["k%d" % k] = rows
+    out = {"n": n, "m": m, "eps_star": eps_star, "precision": "fp32 projection, fp64 LS", "sketch": "srht",
+           "up_precision": "float32 throughout (unique precision)"}
+    for prec, key in (("fp32", "k%d"), ("fp32u", "up_k%d")):
+        for k in ks:
+            rows = []
+            for i in prefixes:
+                Wi = W[:, :i]
+                Q = rgs.colmajor(n, i, torch.float32)
+                R = rgs.colmajor(i, i, torch.float64)
+                S = rgs.colmajor(k, i, torch.float64)
+                d = rgs.qr_desc(n, i, k, sketch="srht", prec=prec, flags=rgs.FLAG_CERTIFY)
+                rep = rgs.rgs_qr(h, d, Wi, Q, R, S)
+                torch.cuda.synchronize()
+                Q64 = Q.double()
+                G = Q64.T @ Q64
+                ev = torch.linalg.eigvalsh(G)
+                cond_q = float(torch.sqrt(ev[-1] / ev[0])) if float(ev[0]) > 0 else float("inf")
+                sv = torch.linalg.svdvals(S)
+                cond_s = float(sv[0] / sv[-1])
+                err = float(torch.linalg.norm(W64[:, :i] - Q64 @ R) / torch.linalg.norm(W64[:, :i]))
+                omega = float("nan")
+                if cond_q < 1e6:
+                    # omega: distortion of Theta on range(Q_i), from an l2-orthonormal basis U = Q C^-1
+                    C = torch.linalg.cholesky(G, upper=True)
+                    U = Q64 @ torch.linalg.inv(C)          # i x i inverse: cond(Q_i) is moderate
+                    TU = rgs.colmajor(k, i, torch.float64)
+                    rgs.rgs_sketch_apply(h, rgs.qr_desc(n, i, k, sketch="srht", prec="fp64"),
+                                         U.contiguous().T.contiguous().T, TU)
+                    torch.cuda.synchronize()
+                    omega = float(torch.linalg.matrix_norm(torch.eye(i, dtype=torch.float64, device="cuda") -
+                                                           TU.T @ TU, 2))
+                    del C, U, TU
+                obar = rgs.rgs_omega_bar(rep.cert_smin_q, rep.cert_smax_q, eps_star)
+                rows.append({"i": i, "status": rep.status, "cond_Q": cond_q, "cond_S": cond_s, "error": err,
+                             "omega": omega, "omega_bar": obar, "seconds": rep.seconds})
+                log("  sec5.1 %s k=%d i=%d: cond(Q) %.3f cond(S) %.3f err %.2e omega %.3f omega_bar %.3f (%.1f ms)" %
+                    (prec, k, i, cond_q, cond_s, err, omega, obar, 1000 * rep.seconds))
+                del Q, R, S, Q64, G
+            out[key % k] = rows
     # the classical comparisons in float32 throughout (torch on the device)
     for name in ("cgs_fp32", "mgs_fp32", "cgs2_fp32"):
         torch.cuda.synchronize()

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 4
+#define RGS_ABI_VERSION 5
 
 typedef struct rgs_handle rgs_handle;  /* opaque */
 typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
@@ -75,10 +75,18 @@ typedef enum {
 typedef enum {
     RGS_P_FP64 = 0,            /* u_crs = u_fine = fp64 */
     RGS_P_FP32_LS64 = 1,       /* multi-precision model: u_crs = fp32, u_fine = fp64 */
-    RGS_P_BF16Q_FP32_LS64 = 2  /* as FP32_LS64 with the basis stored in bfloat16 (round to nearest
+    RGS_P_BF16Q_FP32_LS64 = 2, /* as FP32_LS64 with the basis stored in bfloat16 (round to nearest
                                   even): columns are kept unnormalised with an fp64 scale 1/r_ii,
                                   step 4 sketches the stored column, the coefficients of step 3
                                   carry the scales, and the returned Q is bf16(q'_i / r_ii) */
+    RGS_P_FP32 = 3             /* unique precision u_crs = u_fine = fp32 (the comparison of
+                                  Sec. 5.1): every step of Algorithm 2 in float32 arithmetic --
+                                  the sketches of steps 1 and 4 (block partials and their sums),
+                                  the Householder least squares of step 2, r_ii, s_i and step 7
+                                  (q'_i times the float32 reciprocal of r_ii); R and S receive
+                                  float32 values.  rgs_qr, rgs_qr_noalloc (Householder solver
+                                  only: ls_sweeps must be 0) and rgs_sketch_apply (float32
+                                  arithmetic); not GMRES or the batched calls (EINVAL) */
 } rgs_precision;
 
 /* Flags for rgs_qr_desc.flags / rgs_gmres_desc.flags */

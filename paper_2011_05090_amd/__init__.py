@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librgs.so")
 (RGS_OK, RGS_EINVAL, RGS_ENOMEM, RGS_EDEVICE, RGS_EBREAKDOWN, RGS_ENONFINITE, RGS_ENOCONV,
  RGS_ESCRATCH) = 0, -1, -2, -3, -4, -5, -6, -7
 SKETCH = {"gaussian": 0, "srht": 1, "identity": 2, "rademacher": 3}
-PREC = {"fp64": 0, "fp32": 1, "bf16q": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16q": 2, "fp32u": 3}
 FLAG_DIAGNOSTICS = 1
 FLAG_TIME_KERNELS = 2
 FLAG_GRAPH = 4
@@ -231,7 +231,8 @@ class Handle:
 
 
 def qr_desc(n, m, k, sketch="srht", prec="fp32", seed=42, sketch_id=0, instance=0, flags=0, ls_sweeps=0):
-    """prec: 'fp64', 'fp32' (fp32 projection, fp64 least squares) or 'bf16q' (bf16 basis).
+    """prec: 'fp64', 'fp32' (fp32 projection, fp64 least squares), 'bf16q' (bf16 basis) or
+    'fp32u' (unique precision: every step in float32).
     ls_sweeps: 0 = Householder least squares, s > 0 = s Richardson sweeps."""
     return QrDesc(n=n, m=m, k=k, seed=seed, sketch_id=sketch_id, instance=instance,
                   sketch=SKETCH[sketch], prec=PREC[prec], flags=flags, ls_sweeps=ls_sweeps)

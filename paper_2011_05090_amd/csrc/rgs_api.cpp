@@ -211,8 +211,11 @@ bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (!d) return false;
     if (d->n < 1 || d->k < 1) return false;
     if (need_m && (d->m < 1 || d->m > d->k)) return false;
-    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64 && d->prec != RGS_P_BF16Q_FP32_LS64) return false;
+    if (d->prec != RGS_P_FP64 && d->prec != RGS_P_FP32_LS64 && d->prec != RGS_P_BF16Q_FP32_LS64 &&
+        d->prec != RGS_P_FP32)
+        return false;
     if (d->ls_sweeps > kMaxSweeps) return false;
+    if (d->prec == RGS_P_FP32 && d->ls_sweeps != 0) return false;   // the float32 chain is Householder only
     switch (d->sketch) {
         case RGS_SKETCH_GAUSSIAN:
             if (d->k > kMaxK) return false;
@@ -368,8 +371,9 @@ rgs_status use_table(rgs_handle* h, SketchArgs& sk, int64_t n, uint16_t* table) 
 // Y = Theta X for ncols columns of X (element type TX; Theta's entries and
 // the staging in T; accumulation and block partials in TA, fp64 for step 1 and
 // the certificate, as the paper's multi-precision model computes sketches at
-// u_fine; reduction in fp64), cc columns per pass.
-template <typename TX, typename T, typename TA>
+// u_fine; reduction in TR: fp64, or float32 with TA for the unique-precision
+// model), cc columns per pass.
+template <typename TX, typename T, typename TA, typename TR = double>
 rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64_t ldx, int64_t n, int64_t ncols,
                          int G, int cc, TA* part, double* out, int64_t ldo, hipStream_t stream = nullptr) {
     hipStream_t st = stream ? stream : h->stream;
@@ -393,7 +397,7 @@ rgs_status sketch_matrix(rgs_handle* h, const SketchArgs& sk, const TX* X, int64
         } else if (!launch_sketch_cols<TX, TA>(st, X + c0 * ldx, ldx, n, nc, G, sk, part)) {
             return RGS_EDEVICE;
         }
-        if (!launch_reduce<TA>(st, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
+        if (!launch_reduce<TA, TR>(st, part, G, sk.k, nc, scale, out + c0 * ldo, ldo)) return RGS_EDEVICE;
     }
     return RGS_OK;
 }
@@ -557,7 +561,10 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
 // used, step 1 runs chunk by chunk on the handle's stream just before the
 // columns that read each chunk, and the SRHT rows are drawn on the device.
 // Flags that need memory of their own are rejected by the caller.
-template <typename T, typename TQ, bool DEFER>
+// TS: arithmetic of the sketch space, steps 1-2 and 4-6 (fp64; float32 for
+// the unique-precision model RGS_P_FP32, whose step-1 partials and their
+// reduction are float32 too).
+template <typename T, typename TQ, bool DEFER, typename TS = double>
 rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, TQ* Q, int64_t ldq, double* R,
                   int64_t ldr, double* S, int64_t lds, rgs_report* rep, char* fixed = nullptr,
                   size_t fixed_bytes = 0) {
@@ -596,7 +603,9 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     T* coef = reinterpret_cast<T*>(A + pl.coef);
     T* part = reinterpret_cast<T*>(A + pl.part_proj);
     // step 1 accumulates in fp64 (R-2), except on the bf16-basis path whose rounding dominates
-    using TP = typename std::conditional<DEFER, T, double>::type;
+    // and in the unique-precision model (float32 throughout)
+    constexpr bool kUnique = std::is_same<TS, float>::value;
+    using TP = typename std::conditional<DEFER || kUnique, T, double>::type;
     TP* partP = reinterpret_cast<TP*>(A + pl.part_P);
 
     hipStream_t s = h->stream;
@@ -632,7 +641,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
         // reads one of its columns.  The chunks share one partials buffer, so
         // the auxiliary stream starts after the first chunk.
         const int64_t nchunk = (m + pl.cc - 1) / pl.cc;
-        rgs_status r1 = sketch_matrix<T, T, TP>(h, sk, W, ldw, n, std::min<int64_t>(m, pl.cc), pl.G_P, pl.cc, partP, P,
+        rgs_status r1 = sketch_matrix<T, T, TP, TS>(h, sk, W, ldw, n, std::min<int64_t>(m, pl.cc), pl.G_P, pl.cc, partP, P,
                                                 k, q);
         if (r1 != RGS_OK) return r1;
         if (nchunk > 1 && !one) {
@@ -641,7 +650,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
                 return RGS_EDEVICE;
             for (int64_t c = 1; c < nchunk; ++c) {
                 const int64_t c0 = c * pl.cc;
-                r1 = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P,
+                r1 = sketch_matrix<T, T, TP, TS>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc), pl.G_P,
                                              pl.cc, partP, P + c0 * k, k, h->aux);
                 if (r1 != RGS_OK) return r1;
                 if (hipEventRecord(h->chunk_ev[c], h->aux) != hipSuccess) return RGS_EDEVICE;
@@ -670,7 +679,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
             if (i + 1 < m && (i + 1) % pl.cc == 0) {   // the next column opens a chunk of P
                 if (one) {
                     const int64_t c0 = i + 1;
-                    r1 = sketch_matrix<T, T, TP>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc),
+                    r1 = sketch_matrix<T, T, TP, TS>(h, sk, W + c0 * ldw, ldw, n, std::min<int64_t>(m - c0, pl.cc),
                                                  pl.G_P, pl.cc, partP, P + c0 * k, k, q);
                     if (r1 != RGS_OK) return r1;
                 } else if (hipStreamWaitEvent(q, h->chunk_ev[(i + 1) / pl.cc], 0) != hipSuccess) {
@@ -682,7 +691,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
                                 ? launch_column_richardson<T, T>(q, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr,
                                                                  pnext, coef, DEFER ? sa.invr : nullptr,
                                                                  (int)d->ls_sweeps)
-                                : launch_column<T, T>(q, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr, pnext,
+                                : launch_column<T, T, TS>(q, sa, part, Gp, scale, src0, (int)i, S, lds, R, ldr, pnext,
                                                       coef, DEFER ? sa.invr : nullptr);
             if (!ok) return RGS_EDEVICE;
         }
@@ -2296,6 +2305,9 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
     if (d->prec == RGS_P_BF16Q_FP32_LS64)
         return run_qr<float, bf16, true>(h, d, static_cast<const float*>(W), ldw, static_cast<bf16*>(Q), ldq, R,
                                          ldr, S, lds, rep);
+    if (d->prec == RGS_P_FP32)
+        return run_qr<float, float, false, float>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q),
+                                                  ldq, R, ldr, S, lds, rep);
     return run_qr<float, float, false>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R,
                                        ldr, S, lds, rep);
 } catch (const std::bad_alloc&) {
@@ -2320,6 +2332,9 @@ rgs_status rgs_qr_noalloc(rgs_handle* h, const rgs_qr_desc* d, const void* W, in
     if (d->prec == RGS_P_BF16Q_FP32_LS64)
         return run_qr<float, bf16, true>(h, d, static_cast<const float*>(W), ldw, static_cast<bf16*>(Q), ldq, R,
                                          ldr, S, lds, rep, buf, kScratchBytes);
+    if (d->prec == RGS_P_FP32)
+        return run_qr<float, float, false, float>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q),
+                                                  ldq, R, ldr, S, lds, rep, buf, kScratchBytes);
     return run_qr<float, float, false>(h, d, static_cast<const float*>(W), ldw, static_cast<float*>(Q), ldq, R,
                                        ldr, S, lds, rep, buf, kScratchBytes);
 } catch (...) {
@@ -2346,6 +2361,10 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     if (d->prec == RGS_P_FP64)
         st = sketch_matrix<double, double, double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P,
                                                    pl.cc, reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
+    else if (d->prec == RGS_P_FP32)   // float32 arithmetic throughout (unique-precision model)
+        st = sketch_matrix<float, float, float, float>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols,
+                                                       pl.G_P, pl.cc, reinterpret_cast<float*>(A + pl.part_P), Y,
+                                                       ldy);
     else
         st = sketch_matrix<float, float, double>(h, sk, static_cast<const float*>(X), ldx, d->n, ncols, pl.G_P,
                                                  pl.cc, reinterpret_cast<double*>(A + pl.part_P), Y, ldy);

@@ -28,7 +28,7 @@ constexpr int kGSubCol = 64;   // rows per sub-block of the single-column Gaussi
 template <typename TX, typename T, typename TA = T>
 bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int ncols, int G, const SketchArgs& sk,
                        TA* partials);
-template <typename PT>
+template <typename PT, typename TR = double>   // TR: arithmetic of the sums
 bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
                    int64_t ldo);
 template <typename TW, typename TQ, bool DEFER>
@@ -60,7 +60,8 @@ template <typename T, typename PT>
 bool launch_column_richardson(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                               const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
                               const double* pnext, T* coef, const double* cscale, int sweeps);
-template <typename T, typename PT>
+// TS: arithmetic of the sketch-space state (fp64; float32 for the unique-precision model).
+template <typename T, typename PT, typename TS = double>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
                    const double* pnext, T* coef, const double* cscale);

@@ -973,32 +973,34 @@ __global__ __launch_bounds__(256) void kb_table_gemm_t128(const BatchItem* __res
 
 // out[j + col*ldo] = scale * sum_{g=0}^{G-1} partials[(col*G + g)*k + j], in fp64 and
 // in a fixed order: 8 contiguous g-ranges summed by 8 threads, then combined in order.
-template <typename PT>
+// TR: the arithmetic of the sums (fp64; float32 for the unique-precision model,
+// whose results are float32 values stored in the fp64 output).
+template <typename PT, typename TR = double>
 __device__ __forceinline__ void reduce_body(const PT* __restrict__ partials, int G, int k, double scale,
                                             double* __restrict__ out, int64_t ldo, int jb, int col) {
-    __shared__ double red[8][32];
+    __shared__ TR red[8][32];
     const int jl = threadIdx.x & 31, part = threadIdx.x >> 5;
     const int j = jb * 32 + jl;
     const int g0 = (int)((int64_t)G * part / 8), g1 = (int)((int64_t)G * (part + 1) / 8);
-    double s = 0.0;
+    TR s = TR(0);
     if (j < k) {
         const PT* p = partials + (int64_t)col * G * k + j;
-        for (int g = g0; g < g1; ++g) s += (double)p[(int64_t)g * k];
+        for (int g = g0; g < g1; ++g) s += (TR)p[(int64_t)g * k];
     }
     red[part][jl] = s;
     __syncthreads();
     if (part == 0 && j < k) {
-        double tot = 0.0;
+        TR tot = TR(0);
 #pragma unroll
         for (int t = 0; t < 8; ++t) tot += red[t][jl];
-        out[j + (int64_t)col * ldo] = tot * scale;
+        out[j + (int64_t)col * ldo] = tot * (TR)scale;
     }
 }
 
-template <typename PT>
+template <typename PT, typename TR = double>
 __global__ __launch_bounds__(kWG) void k_reduce(const PT* __restrict__ partials, int G, int k,
                                                 double scale, double* __restrict__ out, int64_t ldo) {
-    reduce_body<PT>(partials, G, k, scale, out, ldo, blockIdx.x, blockIdx.y);
+    reduce_body<PT, TR>(partials, G, k, scale, out, ldo, blockIdx.x, blockIdx.y);
 }
 
 // Batched: map blocks are (factorisation, 32-row chunk + ceil(k/32) * column) of P.
@@ -1101,56 +1103,63 @@ __global__ __launch_bounds__(kGW) void k_ls2(const double* __restrict__ p, int k
     ls2_body(p, k, i, nsl, Vc, mcap, pd, uh, pnorm, blockIdx.x, cp);
 }
 
-template <typename T, int NT = kGW>
-__global__ __launch_bounds__(NT) void k_ls3(int nr, int col, const double* __restrict__ X, int mcap,
-                                            const double* __restrict__ uh, double* __restrict__ R,
+// The single-factorisation column-step kernels.  TS is the arithmetic of the
+// sketch-space state: fp64, or float32 for the unique-precision model (the
+// workspace buffers are sized for fp64 and hold TS values); R, S, rr and invr
+// are fp64 arrays either way.  Dynamic LDS is sized by the launcher in fp64
+// elements.
+template <typename T, int NT = kGW, typename TS = double>
+__global__ __launch_bounds__(NT) void k_ls3(int nr, int col, const TS* __restrict__ X, int mcap,
+                                            const TS* __restrict__ uh, double* __restrict__ R,
                                             int64_t ldr, T* __restrict__ coef, const double* __restrict__ cscale) {
-    extern __shared__ double us[];  // [nr]
-    ls3_body<T, NT>(nr, col, X, mcap, uh, R, ldr, coef, cscale, blockIdx.x, us);
+    extern __shared__ double us_raw[];  // [nr]
+    ls3_body<T, NT, TS>(nr, col, X, mcap, uh, R, ldr, coef, cscale, blockIdx.x, reinterpret_cast<TS*>(us_raw));
 }
 
-template <typename PT, int NT = kGW>
+template <typename PT, int NT = kGW, typename TS = double>
 __global__ __launch_bounds__(NT) void k_qa(const PT* __restrict__ partials, int G, double scale,
                                            const double* __restrict__ src, int k, int i,
-                                           const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                           double* __restrict__ pd, const double* __restrict__ scale2,
+                                           const TS* __restrict__ Wr, int mcap, TS* __restrict__ sp,
+                                           TS* __restrict__ pd, const double* __restrict__ scale2,
                                            int pstride = 0) {
-    qa_body<PT, NT>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2, pstride);
+    qa_body<PT, NT, TS>(partials, G, scale, src, k, i, Wr, mcap, sp, pd, blockIdx.x, scale2, pstride);
 }
 
-template <int NT = kGW>
-__global__ __launch_bounds__(NT) void k_qb(int k, int i, int nsl, const double* __restrict__ sp,
-                                            const double* __restrict__ Vc, int mcap,
-                                            const double* __restrict__ pd, double* __restrict__ u,
-                                            double* __restrict__ pd2, double* __restrict__ S, int64_t lds,
+template <int NT = kGW, typename TS = double>
+__global__ __launch_bounds__(NT) void k_qb(int k, int i, int nsl, const TS* __restrict__ sp,
+                                            const TS* __restrict__ Vc, int mcap,
+                                            const TS* __restrict__ pd, TS* __restrict__ u,
+                                            TS* __restrict__ pd2, double* __restrict__ S, int64_t lds,
                                             double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
-                                            double* __restrict__ invr, const double* __restrict__ pnorm,
+                                            double* __restrict__ invr, const TS* __restrict__ pnorm,
                                             int* __restrict__ status) {
-    extern __shared__ double c1[];  // [i + 1]
-    qb_body<NT>(k, i, nsl, sp, Vc, mcap, pd, u, pd2, S, lds, R, ldr, rr, invr, pnorm, status, blockIdx.x, c1);
+    extern __shared__ double c1_raw[];  // [i + 1]
+    qb_body<NT, TS>(k, i, nsl, sp, Vc, mcap, pd, u, pd2, S, lds, R, ldr, rr, invr, pnorm, status, blockIdx.x,
+                    reinterpret_cast<TS*>(c1_raw));
 }
 
-template <int NT = kGW>
-__global__ __launch_bounds__(NT) void k_qc(int k, int i, int nsl, const double* __restrict__ u,
-                                            const double* __restrict__ pd2, const double* __restrict__ pn,
-                                            double* __restrict__ v, double* __restrict__ Vc,
-                                            double* __restrict__ Vr, const double* __restrict__ Wr, int mcap,
-                                            double* __restrict__ pd, double* __restrict__ pdb,
-                                            double* __restrict__ tau_a, double* __restrict__ beta_a,
+template <int NT = kGW, typename TS = double>
+__global__ __launch_bounds__(NT) void k_qc(int k, int i, int nsl, const TS* __restrict__ u,
+                                            const TS* __restrict__ pd2, const double* __restrict__ pn,
+                                            TS* __restrict__ v, TS* __restrict__ Vc,
+                                            TS* __restrict__ Vr, const TS* __restrict__ Wr, int mcap,
+                                            TS* __restrict__ pd, TS* __restrict__ pdb,
+                                            TS* __restrict__ tau_a, TS* __restrict__ beta_a,
                                             int* __restrict__ status) {
-    qc_body<NT>(k, i, nsl, u, pd2, pn, v, Vc, Vr, Wr, mcap, pd, pdb, tau_a, beta_a, status, blockIdx.x);
+    qc_body<NT, TS>(k, i, nsl, u, pd2, pn, v, Vc, Vr, Wr, mcap, pd, pdb, tau_a, beta_a, status, blockIdx.x);
 }
 
-template <int NT = kGW>
-__global__ __launch_bounds__(NT) void k_qd(int k, int i, int nsl, const double* __restrict__ v,
-                                            const double* __restrict__ u, const double* __restrict__ pn,
-                                            double* __restrict__ Wc, double* __restrict__ Wr,
-                                            const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                            const double* __restrict__ pdb, double* __restrict__ X,
-                                            double* __restrict__ uh, double* __restrict__ pnorm,
-                                            const double* __restrict__ tau_a, const double* __restrict__ beta_a) {
-    extern __shared__ double dyn[];  // [3 (i + 2)]
-    qd_body<NT>(k, i, nsl, v, u, pn, Wc, Wr, Vc, mcap, pd, pdb, X, uh, pnorm, tau_a, beta_a, blockIdx.x, dyn);
+template <int NT = kGW, typename TS = double>
+__global__ __launch_bounds__(NT) void k_qd(int k, int i, int nsl, const TS* __restrict__ v,
+                                            const TS* __restrict__ u, const double* __restrict__ pn,
+                                            TS* __restrict__ Wc, TS* __restrict__ Wr,
+                                            const TS* __restrict__ Vc, int mcap, const TS* __restrict__ pd,
+                                            const TS* __restrict__ pdb, TS* __restrict__ X,
+                                            TS* __restrict__ uh, TS* __restrict__ pnorm,
+                                            const TS* __restrict__ tau_a, const TS* __restrict__ beta_a) {
+    extern __shared__ double dyn_raw[];  // [3 (i + 2)]
+    qd_body<NT, TS>(k, i, nsl, v, u, pn, Wc, Wr, Vc, mcap, pd, pdb, X, uh, pnorm, tau_a, beta_a, blockIdx.x,
+                    reinterpret_cast<TS*>(dyn_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1495,10 +1504,10 @@ bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, c
     return true;
 }
 
-template <typename PT>
+template <typename PT, typename TR>
 bool launch_reduce(hipStream_t st, const PT* partials, int G, int k, int ncols, double scale, double* out,
                    int64_t ldo) {
-    hipLaunchKernelGGL(k_reduce<PT>, dim3(nblocks(k, 32), ncols), dim3(kWG), 0, st, partials, G, k, scale,
+    hipLaunchKernelGGL((k_reduce<PT, TR>), dim3(nblocks(k, 32), ncols), dim3(kWG), 0, st, partials, G, k, scale,
                        out, ldo);
     RGS_LAUNCH_CHECK();
     return true;
@@ -1630,28 +1639,30 @@ bool launch_column_richardson(hipStream_t st, const SpaceArgs& a, const PT* part
     return true;
 }
 
-template <typename T, typename PT>
+template <typename T, typename PT, typename TS>
 bool launch_column(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale,
                    const double* src, int i, double* S, int64_t lds, double* R, int64_t ldr,
                    const double* pnext, T* coef, const double* cscale) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
     constexpr int NT = kGWS;
-    hipLaunchKernelGGL((k_qa<PT, NT>), dim3(nsl), dim3(NT), 0, st, partials, G, scale, src, a.k, i, a.Wr, a.mcap,
-                       a.sp, a.pd, (const double*)nullptr);
+    auto ws = [](double* p) { return reinterpret_cast<TS*>(p); };   // the workspace in the sketch-space type
+    hipLaunchKernelGGL((k_qa<PT, NT, TS>), dim3(nsl), dim3(NT), 0, st, partials, G, scale, src, a.k, i, ws(a.Wr),
+                       a.mcap, ws(a.sp), ws(a.pd), (const double*)nullptr, 0);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_qb<NT>, dim3(nsl), dim3(NT), (i + 1) * sizeof(double), st, a.k, i, nsl, a.sp, a.Vc, a.mcap,
-                       a.pd, a.u, a.pd2, S, lds, R, ldr, a.rr, a.invr, a.pnorm, a.status);
+    hipLaunchKernelGGL((k_qb<NT, TS>), dim3(nsl), dim3(NT), (i + 1) * sizeof(double), st, a.k, i, nsl, ws(a.sp),
+                       ws(a.Vc), a.mcap, ws(a.pd), ws(a.u), ws(a.pd2), S, lds, R, ldr, a.rr, a.invr, ws(a.pnorm),
+                       a.status);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_qc<NT>, dim3(nsl), dim3(NT), 0, st, a.k, i, nsl, a.u, a.pd2, pnext, a.v, a.Vc, a.Vr,
-                       a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta, a.status);
+    hipLaunchKernelGGL((k_qc<NT, TS>), dim3(nsl), dim3(NT), 0, st, a.k, i, nsl, ws(a.u), ws(a.pd2), pnext, ws(a.v),
+                       ws(a.Vc), ws(a.Vr), ws(a.Wr), a.mcap, ws(a.pd), ws(a.pdb), ws(a.tau), ws(a.beta), a.status);
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_qd<NT>, dim3(nsl + nblocks(i + 1, 64)), dim3(NT), 3 * (i + 2) * sizeof(double), st, a.k,
-                       i, nsl, a.v, a.u, pnext, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
-                       a.beta);
+    hipLaunchKernelGGL((k_qd<NT, TS>), dim3(nsl + nblocks(i + 1, 64)), dim3(NT), 3 * (i + 2) * sizeof(double), st,
+                       a.k, i, nsl, ws(a.v), ws(a.u), pnext, ws(a.Wc), ws(a.Wr), ws(a.Vc), a.mcap, ws(a.pd),
+                       ws(a.pdb), ws(a.X), ws(a.uh), ws(a.pnorm), ws(a.tau), ws(a.beta));
     RGS_LAUNCH_CHECK();
     if (pnext) {
-        hipLaunchKernelGGL((k_ls3<T, NT>), dim3(nblocks(i + 1, 64)), dim3(NT), (i + 1) * sizeof(double), st, i + 1,
-                           i + 1, a.X, a.mcap, a.uh, R, ldr, coef, cscale);
+        hipLaunchKernelGGL((k_ls3<T, NT, TS>), dim3(nblocks(i + 1, 64)), dim3(NT), (i + 1) * sizeof(double), st,
+                           i + 1, i + 1, ws(a.X), a.mcap, ws(a.uh), R, ldr, coef, cscale);
         RGS_LAUNCH_CHECK();
     }
     return true;
@@ -1773,6 +1784,7 @@ template bool launch_gauss_cols<float, float, double>(hipStream_t, const float*,
 template bool launch_gauss_cols<bf16, float, double>(hipStream_t, const bf16*, int64_t, int64_t, int, int,
                                                      const SketchArgs&, double*);
 template bool launch_reduce<float>(hipStream_t, const float*, int, int, int, double, double*, int64_t);
+template bool launch_reduce<float, float>(hipStream_t, const float*, int, int, int, double, double*, int64_t);
 template bool launch_reduce<double>(hipStream_t, const double*, int, int, int, double, double*, int64_t);
 template bool launch_scale_col<float>(hipStream_t, float*, int64_t, const double*, const int*);
 template bool launch_scale_col<double>(hipStream_t, double*, int64_t, const double*, const int*);
@@ -1800,6 +1812,9 @@ template bool launch_column<float, float>(hipStream_t, const SpaceArgs&, const f
 template bool launch_column<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double,
                                             const double*, int, double*, int64_t, double*, int64_t, const double*,
                                             double*, const double*);
+template bool launch_column<float, float, float>(hipStream_t, const SpaceArgs&, const float*, int, double,
+                                                 const double*, int, double*, int64_t, double*, int64_t,
+                                                 const double*, float*, const double*);
 template bool launch_batch_table_gemm<float, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
                                                    int, int, const uint16_t*, int, int64_t);
 template bool launch_batch_table_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,

@@ -37,31 +37,34 @@ constexpr int kBatch = 16;  // loads issued back to back per thread
 constexpr int kSliceBatch = 32;   // the same in the column-parallel slice products
 
 // sum_{s < nsl} pd[s * stride + c] (fixed order in s)
-__device__ __forceinline__ double sum_col(const double* __restrict__ pd, int nsl, int stride, int c) {
-    double acc = 0.0;
+template <typename TS>
+__device__ __forceinline__ TS sum_col(const TS* __restrict__ pd, int nsl, int stride, int c) {
+    TS acc = TS(0);
     for (int s0 = 0; s0 < nsl; s0 += kBatch) {
-        double t[kBatch];
+        TS t[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) t[u] = (s0 + u < nsl) ? pd[(int64_t)(s0 + u) * stride + c] : 0.0;
+        for (int u = 0; u < kBatch; ++u) t[u] = (s0 + u < nsl) ? pd[(int64_t)(s0 + u) * stride + c] : TS(0);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) acc += t[u];
     }
     return acc;
 }
 
-__device__ __forceinline__ void sum_slices(const double* __restrict__ pd, int nsl, int stride, int cnt,
-                                           double* __restrict__ out) {
+template <typename TS>
+__device__ __forceinline__ void sum_slices(const TS* __restrict__ pd, int nsl, int stride, int cnt,
+                                           TS* __restrict__ out) {
     for (int c = threadIdx.x; c < cnt; c += blockDim.x) out[c] = sum_col(pd, nsl, stride, c);
 }
 
 // sum_{rr < 64} M[row(rr), c] * xs[rr], M row-major with row stride mcap; rows
 // past k are clamped (xs is 0 there).
-__device__ __forceinline__ double slice_dot(const double* __restrict__ Mr, int mcap, int r0, int k,
-                                            const double* __restrict__ xs, int c) {
-    double acc = 0.0;
+template <typename TS>
+__device__ __forceinline__ TS slice_dot(const TS* __restrict__ Mr, int mcap, int r0, int k,
+                                        const TS* __restrict__ xs, int c) {
+    TS acc = TS(0);
 #pragma unroll 1
     for (int b = 0; b < kSlice; b += kSliceBatch) {
-        double t[kSliceBatch];
+        TS t[kSliceBatch];
 #pragma unroll
         for (int u = 0; u < kSliceBatch; ++u) t[u] = Mr[(int64_t)min(r0 + b + u, k - 1) * mcap + c];
 #pragma unroll
@@ -70,29 +73,32 @@ __device__ __forceinline__ double slice_dot(const double* __restrict__ Mr, int m
     return acc;
 }
 
-__device__ __forceinline__ double slice_sq(const double* __restrict__ xs) {
-    double acc = 0.0;
+template <typename TS>
+__device__ __forceinline__ TS slice_sq(const TS* __restrict__ xs) {
+    TS acc = TS(0);
     for (int rr = 0; rr < kSlice; ++rr) acc = fma(xs[rr], xs[rr], acc);
     return acc;
 }
 
-__device__ __forceinline__ double slice_xy(const double* __restrict__ xs, const double* __restrict__ ys) {
-    double acc = 0.0;
+template <typename TS>
+__device__ __forceinline__ TS slice_xy(const TS* __restrict__ xs, const TS* __restrict__ ys) {
+    TS acc = TS(0);
     for (int rr = 0; rr < kSlice; ++rr) acc = fma(xs[rr], ys[rr], acc);
     return acc;
 }
 
 // Row-parallel partial: sum over c in [c0, c1) with c = q (mod kGQ), ascending,
 // of M[r, c] * xl[c]; M column-major with leading dimension ld.
-__device__ __forceinline__ double row_part(const double* __restrict__ Mc, int64_t ld, int r, int c0, int c1,
-                                           const double* __restrict__ xl, int q) {
-    double acc = 0.0;
+template <typename TS>
+__device__ __forceinline__ TS row_part(const TS* __restrict__ Mc, int64_t ld, int r, int c0, int c1,
+                                       const TS* __restrict__ xl, int q) {
+    TS acc = TS(0);
     for (int c = c0 + ((q - c0) % kGQ + kGQ) % kGQ; c < c1; c += kGQ * kBatch) {
-        double t[kBatch];
+        TS t[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int cc = c + kGQ * u;
-            t[u] = (cc < c1) ? Mc[r + (int64_t)cc * ld] : 0.0;
+            t[u] = (cc < c1) ? Mc[r + (int64_t)cc * ld] : TS(0);
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -103,8 +109,9 @@ __device__ __forceinline__ double row_part(const double* __restrict__ Mc, int64_
     return acc;
 }
 
-__device__ __forceinline__ double combine16(double (*red)[64], int rl) {
-    double t = 0.0;
+template <typename TS>
+__device__ __forceinline__ TS combine16(TS (*red)[64], int rl) {
+    TS t = TS(0);
 #pragma unroll
     for (int q = 0; q < kGQ; ++q) t += red[q][rl];
     return t;
@@ -132,12 +139,12 @@ __device__ __forceinline__ void ls2_body(const double* __restrict__ p, int k, in
 //   y[r] = sum_{c >= r} X[r, c] uh[c].  Writes R(0:nr, col) and the working-
 // precision coefficients coef[r] = y[r] (times cscale[r] = 1/r_rr when the
 // basis is kept unnormalised).  bid = row block of 64.
-template <typename T, int NT = kGW>
-__device__ __forceinline__ void ls3_body(int nr, int col, const double* __restrict__ X, int mcap,
-                                         const double* __restrict__ uh, double* __restrict__ R, int64_t ldr,
+template <typename T, int NT = kGW, typename TS = double>
+__device__ __forceinline__ void ls3_body(int nr, int col, const TS* __restrict__ X, int mcap,
+                                         const TS* __restrict__ uh, double* __restrict__ R, int64_t ldr,
                                          T* __restrict__ coef, const double* __restrict__ cscale, int bid,
-                                         double* __restrict__ us) {
-    __shared__ double red[kGQ][64];
+                                         TS* __restrict__ us) {
+    __shared__ TS red[kGQ][64];
     for (int c = threadIdx.x; c < nr; c += NT) us[c] = uh[c];
     __syncthreads();
     const int rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
@@ -145,9 +152,9 @@ __device__ __forceinline__ void ls3_body(int nr, int col, const double* __restri
     for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < nr) ? row_part(X, mcap, r, r, nr, us, q) : 0.0;
     __syncthreads();
     if (q0 == 0 && r < nr) {
-        const double y = combine16(red, rl);
+        const TS y = combine16(red, rl);
         R[r + (int64_t)col * ldr] = y;
-        coef[r] = (T)(cscale ? y * cscale[r] : y);
+        coef[r] = (T)(cscale ? y * (TS)cscale[r] : y);
     }
 }
 
@@ -156,19 +163,19 @@ __device__ __forceinline__ void ls3_body(int nr, int col, const double* __restri
 // its normalisation was known) for slice bid (or a copy of src), stored in sp;
 // per-slice partials of c1 = Wm_i^T s' (c < i) and of ||s'||^2 (slot i), at
 // stride pstride per slice (mcap + 1 when 0).
-template <typename PT, int NT = kGW>
+template <typename PT, int NT = kGW, typename TS = double>
 __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, double scale,
                                         const double* __restrict__ src, int k, int i,
-                                        const double* __restrict__ Wr, int mcap, double* __restrict__ sp,
-                                        double* __restrict__ pd, int bid,
+                                        const TS* __restrict__ Wr, int mcap, TS* __restrict__ sp,
+                                        TS* __restrict__ pd, int bid,
                                         const double* __restrict__ scale2 = nullptr, int pstride = 0) {
-    __shared__ double red[kGQ][64];
-    __shared__ double xs[kSlice];
+    __shared__ TS red[kGQ][64];
+    __shared__ TS xs[kSlice];
     const int s = bid, r0 = s * kSlice, rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = r0 + rl;
     if (src) {
         if (q0 == 0) {
-            const double val = (r < k) ? src[r] : 0.0;
+            const TS val = (r < k) ? (TS)src[r] : TS(0);
             xs[rl] = val;
             if (r < k) sp[r] = val;
         }
@@ -176,7 +183,7 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
         // group q sums the block partials g in [G q / 16, G (q+1) / 16), in order
         for (int q = q0; q < kGQ; q += NT / 64) {
             const int g0 = (int)((int64_t)G * q / kGQ), g1 = (int)((int64_t)G * (q + 1) / kGQ);
-            double acc = 0.0;
+            TS acc = TS(0);
             if (r < k) {
                 for (int g = g0; g < g1; g += 32) {
                     // clamped addresses, masked after: loads under a per-element
@@ -185,48 +192,48 @@ __device__ __forceinline__ void qa_body(const PT* __restrict__ partials, int G, 
 #pragma unroll
                     for (int u = 0; u < 32; ++u) t[u] = partials[(int64_t)min(g + u, g1 - 1) * k + r];
 #pragma unroll
-                    for (int u = 0; u < 32; ++u) acc += (g + u < g1) ? (double)t[u] : 0.0;
+                    for (int u = 0; u < 32; ++u) acc += (g + u < g1) ? (TS)t[u] : TS(0);
                 }
             }
             red[q][rl] = acc;
         }
         __syncthreads();
         if (q0 == 0) {
-            double val = (r < k) ? combine16(red, rl) * scale : 0.0;
-            if (scale2) val *= scale2[0];
+            TS val = (r < k) ? combine16(red, rl) * (TS)scale : TS(0);
+            if (scale2) val *= (TS)scale2[0];
             xs[rl] = val;
             if (r < k) sp[r] = val;
         }
     }
     __syncthreads();
-    double* out = pd + (int64_t)s * (pstride ? pstride : mcap + 1);
+    TS* out = pd + (int64_t)s * (pstride ? pstride : mcap + 1);
     for (int c = threadIdx.x; c <= i; c += NT) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
 // Column step B (steps 5-6): r_ii = ||s'||, S(:, i) = s'/r_ii, breakdown test,
 // u = U_i^T s_i = (s' - V c1) / r_ii, per-slice partials of ||u(i+1:k)||^2.
-template <int NT = kGW>
-__device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __restrict__ sp,
-                                        const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                        double* __restrict__ u, double* __restrict__ pd2, double* __restrict__ S,
+template <int NT = kGW, typename TS = double>
+__device__ __forceinline__ void qb_body(int k, int i, int nsl, const TS* __restrict__ sp,
+                                        const TS* __restrict__ Vc, int mcap, const TS* __restrict__ pd,
+                                        TS* __restrict__ u, TS* __restrict__ pd2, double* __restrict__ S,
                                         int64_t lds, double* __restrict__ R, int64_t ldr, double* __restrict__ rr,
-                                        double* __restrict__ invr, const double* __restrict__ pnorm,
-                                        int* __restrict__ status, int bid, double* __restrict__ c1) {
-    __shared__ double red[kGQ][64];
-    __shared__ double tl[64];
+                                        double* __restrict__ invr, const TS* __restrict__ pnorm,
+                                        int* __restrict__ status, int bid, TS* __restrict__ c1) {
+    __shared__ TS red[kGQ][64];
+    __shared__ TS tl[64];
     sum_slices(pd, nsl, mcap + 1, i + 1, c1);
     __syncthreads();
-    const double rii = sqrt(c1[i]);
+    const TS rii = sqrt(c1[i]);
     if (bid == 0 && threadIdx.x == 0) {
         rr[i] = rii;
-        invr[i] = 1.0 / rii;
+        invr[i] = TS(1) / rii;   // the step-7 factor, in the arithmetic of the sketch space
         R[i + (int64_t)i * ldr] = rii;
-        const double pn = (i == 0) ? rii : pnorm[i];
+        const TS pn = (i == 0) ? rii : pnorm[i];
         if (status[0] == 0 && status[2] == 0) {
             if (!isfinite(rii) || !isfinite(pn)) {
                 status[1] = i;
                 status[0] = kStatusNonfinite;
-            } else if (rii == 0.0 || rii <= 0x1p-50 * pn) {
+            } else if (rii == TS(0) || rii <= TS(0x1p-50) * pn) {
                 status[1] = i;
                 status[0] = kStatusBreakdown;
             }
@@ -234,13 +241,13 @@ __device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __r
     }
     const int s = bid, rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = s * kSlice + rl;
-    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < k) ? row_part(Vc, k, r, 0, i, c1, q) : TS(0);
     __syncthreads();
     if (q0 == 0) {
-        double t2 = 0.0;
+        TS t2 = TS(0);
         if (r < k) {
-            const double spr = sp[r];
-            const double val = (spr - combine16(red, rl)) / rii;
+            const TS spr = sp[r];
+            const TS val = (spr - combine16(red, rl)) / rii;
             u[r] = val;
             S[r + (int64_t)i * lds] = spr / rii;
             if (r > i) t2 = val * val;
@@ -249,7 +256,7 @@ __device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __r
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double acc = 0.0;
+        TS acc = TS(0);
         for (int t = 0; t < 64; ++t) acc += tl[t];
         pd2[s] = acc;
     }
@@ -260,27 +267,27 @@ __device__ __forceinline__ void qb_body(int k, int i, int nsl, const double* __r
 // stored as column i of V (both layouts).  Per-slice partials of d = V_i^T v
 // (pd, stride mcap+1) and, when the next right-hand side pn = p_{i+1} is given,
 // of e = Wm_i^T pn, v.pn and ||pn||^2 (pdb, stride mcap+2, slots [0,i), i, i+1).
-template <int NT = kGW>
-__device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __restrict__ u,
-                                        const double* __restrict__ pd2, const double* __restrict__ pn,
-                                        double* __restrict__ v, double* __restrict__ Vc, double* __restrict__ Vr,
-                                        const double* __restrict__ Wr, int mcap, double* __restrict__ pd,
-                                        double* __restrict__ pdb, double* __restrict__ tau_a,
-                                        double* __restrict__ beta_a, int* __restrict__ status, int bid) {
-    __shared__ double vs[kSlice], ps[kSlice];
-    __shared__ double hh[3];
+template <int NT = kGW, typename TS = double>
+__device__ __forceinline__ void qc_body(int k, int i, int nsl, const TS* __restrict__ u,
+                                        const TS* __restrict__ pd2, const double* __restrict__ pn,
+                                        TS* __restrict__ v, TS* __restrict__ Vc, TS* __restrict__ Vr,
+                                        const TS* __restrict__ Wr, int mcap, TS* __restrict__ pd,
+                                        TS* __restrict__ pdb, TS* __restrict__ tau_a,
+                                        TS* __restrict__ beta_a, int* __restrict__ status, int bid) {
+    __shared__ TS vs[kSlice], ps[kSlice];
+    __shared__ TS hh[3];
     if (threadIdx.x == 0) {
-        const double tail2 = sum_col(pd2, nsl, 1, 0);   // ascending s, loads in batches
-        const double x1 = u[i];
-        double beta, tau, scal;
-        if (tail2 == 0.0) {
+        const TS tail2 = sum_col(pd2, nsl, 1, 0);   // ascending s, loads in batches
+        const TS x1 = u[i];
+        TS beta, tau, scal;
+        if (tail2 == TS(0)) {
             beta = x1;
-            tau = 0.0;
-            scal = 0.0;
+            tau = TS(0);
+            scal = TS(0);
         } else {
             beta = -copysign(sqrt(x1 * x1 + tail2), x1);
             tau = (beta - x1) / beta;
-            scal = 1.0 / (x1 - beta);
+            scal = TS(1) / (x1 - beta);
         }
         hh[0] = beta;
         hh[1] = tau;
@@ -288,7 +295,7 @@ __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __r
         if (bid == 0) {
             tau_a[i] = tau;
             beta_a[i] = beta;
-            if (status[0] == 0 && status[2] == 0 && !(fabs(beta) > 0x1p-50)) {   // s_i in span(S_{i-1})
+            if (status[0] == 0 && status[2] == 0 && !(fabs(beta) > TS(0x1p-50))) {   // s_i in span(S_{i-1})
                 status[1] = i;
                 status[0] = kStatusBreakdown;
             }
@@ -298,24 +305,24 @@ __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __r
     const int s = bid, r0 = s * kSlice;
     if (threadIdx.x < kSlice) {
         const int r = r0 + threadIdx.x;
-        double val = 0.0;
+        TS val = TS(0);
         if (r < k) {
-            val = (r < i) ? 0.0 : (r == i ? 1.0 : u[r] * hh[2]);
+            val = (r < i) ? TS(0) : (r == i ? TS(1) : u[r] * hh[2]);
             v[r] = val;
             Vc[r + (int64_t)i * k] = val;
             Vr[(int64_t)r * mcap + i] = val;
         }
         vs[threadIdx.x] = val;
-        ps[threadIdx.x] = (pn && r < k) ? pn[r] : 0.0;
+        ps[threadIdx.x] = (pn && r < k) ? (TS)pn[r] : TS(0);
     }
     __syncthreads();
     const int ntot = pn ? 2 * i + 2 : i;
-    double* outd = pd + (int64_t)s * (mcap + 1);
-    double* oute = pdb + (int64_t)s * (mcap + 2);
+    TS* outd = pd + (int64_t)s * (mcap + 1);
+    TS* oute = pdb + (int64_t)s * (mcap + 2);
     for (int c = threadIdx.x; c < ntot; c += NT) {
         const bool isd = c < i;
         const int ce = isd ? c : c - i;
-        double val;
+        TS val;
         if (isd || ce < i) {
             val = slice_dot(isd ? Vr : Wr, mcap, r0, k, isd ? vs : ps, ce);
         } else {
@@ -332,37 +339,37 @@ __device__ __forceinline__ void qc_body(int k, int i, int nsl, const double* __r
 //   (u(0:i) is R_S(0:i, i)), X(i, i) = 1/beta;
 //   when pn is given, the head of U_{i+1}^T pn for the next column's least squares:
 //   cp = Wm_{i+1}^T pn = [e; tau (v.pn - d.e)],  uh(r) = pn(r) - sum_{c <= min(r,i)} V(r, c) cp(c), r <= i.
-template <int NT = kGW>
-__device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __restrict__ v,
-                                        const double* __restrict__ u, const double* __restrict__ pn,
-                                        double* __restrict__ Wc, double* __restrict__ Wr,
-                                        const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                        const double* __restrict__ pdb, double* __restrict__ X,
-                                        double* __restrict__ uh, double* __restrict__ pnorm,
-                                        const double* __restrict__ tau_a, const double* __restrict__ beta_a,
-                                        int bid, double* __restrict__ dyn) {
-    __shared__ double red[kGQ][64];
-    __shared__ double tree[NT];
+template <int NT = kGW, typename TS = double>
+__device__ __forceinline__ void qd_body(int k, int i, int nsl, const TS* __restrict__ v,
+                                        const TS* __restrict__ u, const double* __restrict__ pn,
+                                        TS* __restrict__ Wc, TS* __restrict__ Wr,
+                                        const TS* __restrict__ Vc, int mcap, const TS* __restrict__ pd,
+                                        const TS* __restrict__ pdb, TS* __restrict__ X,
+                                        TS* __restrict__ uh, TS* __restrict__ pnorm,
+                                        const TS* __restrict__ tau_a, const TS* __restrict__ beta_a,
+                                        int bid, TS* __restrict__ dyn) {
+    __shared__ TS red[kGQ][64];
+    __shared__ TS tree[NT];
     const int rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
-    const double tau = tau_a[i];
+    const TS tau = tau_a[i];
     if (bid < nsl) {
-        double* dsh = dyn;
+        TS* dsh = dyn;
         sum_slices(pd, nsl, mcap + 1, i, dsh);
         __syncthreads();
         const int r = bid * kSlice + rl;
-        for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : 0.0;
+        for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < k) ? row_part(Wc, k, r, 0, i, dsh, q) : TS(0);
         __syncthreads();
         if (q0 == 0 && r < k) {
-            const double val = tau * (v[r] - combine16(red, rl));
+            const TS val = tau * (v[r] - combine16(red, rl));
             Wc[r + (int64_t)i * k] = val;
             Wr[(int64_t)r * mcap + i] = val;
         }
-        if (bid == 0 && threadIdx.x == 0) X[i + (int64_t)i * mcap] = 1.0 / beta_a[i];
+        if (bid == 0 && threadIdx.x == 0) X[i + (int64_t)i * mcap] = TS(1) / beta_a[i];
         return;
     }
-    double* ush = dyn;            // u(0:i)
-    double* dsh = dyn + (i + 1);  // d
-    double* csh = dsh + (i + 1);  // cp
+    TS* ush = dyn;            // u(0:i)
+    TS* dsh = dyn + (i + 1);  // d
+    TS* csh = dsh + (i + 1);  // cp
     for (int c = threadIdx.x; c < i; c += NT) ush[c] = u[c];
     if (pn) {
         for (int c = threadIdx.x; c < 2 * i + 2; c += NT) {
@@ -372,7 +379,7 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
     }
     __syncthreads();
     const int r = (bid - nsl) * 64 + rl;
-    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < i) ? row_part(X, mcap, r, r, i, ush, q) : TS(0);
     __syncthreads();
     if (q0 == 0 && r < i) X[r + (int64_t)i * mcap] = -combine16(red, rl) / beta_a[i];
     if (!pn) return;
@@ -381,10 +388,10 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
     // the leaves threadIdx.x + NT j; the levels wider than NT are summed in
     // its registers, the rest in LDS.
     constexpr int V = kGW / NT;
-    double part[V];
+    TS part[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-        part[j] = 0.0;
+        part[j] = TS(0);
         for (int c = threadIdx.x + NT * j; c < i; c += kGW) part[j] = fma(dsh[c], csh[c], part[j]);
     }
 #pragma unroll
@@ -397,14 +404,14 @@ __device__ __forceinline__ void qd_body(int k, int i, int nsl, const double* __r
         if (threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
         __syncthreads();
     }
-    const double vp = csh[i], pp = csh[i + 1];
+    const TS vp = csh[i], pp = csh[i + 1];
     __syncthreads();
     if (threadIdx.x == 0) csh[i] = tau * (vp - tree[0]);
     if (bid == nsl && threadIdx.x == 0) pnorm[i + 1] = sqrt(pp);
     __syncthreads();
-    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r <= i) ? row_part(Vc, k, r, 0, min(r, i) + 1, csh, q) : TS(0);
     __syncthreads();
-    if (q0 == 0 && r <= i) uh[r] = pn[r] - combine16(red, rl);
+    if (q0 == 0 && r <= i) uh[r] = (TS)pn[r] - combine16(red, rl);
 }
 
 // ---------------------------------------------------------------------------
