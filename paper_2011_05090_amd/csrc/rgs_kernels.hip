@@ -297,6 +297,71 @@ __global__ __launch_bounds__(kWG) void k_rad_cols(const TX* __restrict__ X, int6
     rad_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
 }
 
+// Register-blocked form of k_rad_cols for many columns (step 1, the
+// certificate's sketches): a thread takes J sketch rows
+// j = (jc J + jj) kWG + threadIdx.x and the workgroup's C staged columns, so
+// each staged value read from LDS (the same address in every lane) feeds J
+// fused multiply-adds and each sign feeds C.  Every (j, column) accumulator
+// takes its products in the row order of rad_cols_body, so the partials are
+// the same bits.  SUB is a multiple of 128.
+template <typename TX, typename T, typename TA, int J, int C, int SUB>
+__global__ __launch_bounds__(kWG) void k_rad_cols_rb(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
+                                                     int G, SketchArgs sk, TA* __restrict__ partials) {
+    static_assert(SUB % 128 == 0, "whole 128-row sign groups per sub-block");
+    __shared__ __attribute__((aligned(16))) TA w[C][SUB];
+    const int g = blockIdx.x, c0 = blockIdx.z * C;
+    const int nc = min(C, ncols - c0);
+    int jr[J];
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) jr[jj] = (blockIdx.y * J + jj) * kWG + threadIdx.x;
+    TA acc[J][C];
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[jj][c] = TA(0);
+    const int64_t nsub = (n + SUB - 1) / SUB;
+    for (int64_t sb = g; sb < nsub; sb += G) {
+        const int64_t r0 = sb * SUB;
+        for (int e = threadIdx.x; e < C * SUB; e += kWG) {   // column-major staging: coalesced per column
+            const int c = e / SUB, t = e - c * SUB;
+            const int64_t l = r0 + t;
+            const TA x = (TA)elem_real(X[(int64_t)(c0 + min(c, nc - 1)) * ldx + min(l, n - 1)]);
+            w[c][t] = (c < nc && l < n) ? x : TA(0);
+        }
+        __syncthreads();
+        const int64_t rem = n - r0;
+        const int ng = rem >= SUB ? SUB / 128 : (int)((rem + 127) / 128);
+        const uint32_t b0 = (uint32_t)(r0 / 128);
+        for (int q = 0; q < ng; ++q) {
+            uint32_t wd[J][4];
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj)   // rows past k draw signs that are never stored
+                rad_words(b0 + (uint32_t)q, (uint32_t)jr[jj], sk.sid, sk.inst, sk.k0, sk.k1, wd[jj]);
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+#pragma unroll 4
+                for (int r = 0; r < 32; ++r) {
+                    const int t = 128 * q + 32 * c4 + r;
+                    TA xv[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) xv[c] = w[c][t];
+#pragma unroll
+                    for (int jj = 0; jj < J; ++jj) {
+                        const TA sg = rad_sign<TA>(wd[jj][c4], r);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) acc[jj][c] = fma(sg, xv[c], acc[jj][c]);
+                    }
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (jr[jj] < sk.k && c < nc) partials[((int64_t)(c0 + c) * G + g) * sk.k + jr[jj]] = acc[jj][c];
+}
+
 // Table of the Gaussian sketch with bf16 entries: thread (o, j) draws
 // z(j, 8o .. 8o+7) with the fp64 Box-Muller of two Philox quads, rounds each
 // once to bf16 and writes the group as one 16-byte store at (o k + j) 8
@@ -1426,9 +1491,10 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
     } else if (sk.sketch == SK_RADEM) {
         if (ncols == 1)
             hipLaunchKernelGGL((k_rad_cols<TX, T, TA, 1, 128>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk, partials);
-        else
-            hipLaunchKernelGGL((k_rad_cols<TX, T, TA, kGaussCols, SUBC>), gc, dim3(kWG), 0, st, X, ldx, n, ncols, G,
-                               sk, partials);
+        else   // register-blocked: 4 sketch rows x 8 columns per thread (same bits as k_rad_cols)
+            hipLaunchKernelGGL((k_rad_cols_rb<TX, T, TA, 4, 8, SUBC>),
+                               dim3(G, nblocks(sk.k, 4 * kWG), nblocks(ncols, 8)), dim3(kWG), 0, st, X, ldx, n,
+                               ncols, G, sk, partials);
     } else if (ncols == 1) {   // the single-column sketch of a small-n step: 64-row sub-blocks
         hipLaunchKernelGGL((k_gauss_cols<TX, T, TA, 1, kGSubCol>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
                            partials);
