@@ -47,8 +47,11 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
     ``reverse_projection`` forms Q_{i-1} r of RGS step 3 over the columns in
     reverse order: the same step with another summation order, which the
     precision models leave open (a second valid rounding of the same model).
-    Returns dict(x, hist, iters, cycles, true_relres, converged, cond_info).
-    hist[t] = |g| / ||b|| after global inner step t.
+    Returns dict(x, hist, iters, cycles, true_relres, converged, Q_last,
+    theta_cycle_last): hist[t] = |g| / ||b|| after global inner step t;
+    Q_last holds the last cycle's basis vectors the update used (its first
+    ``used`` stored columns, in fp64; unnormalised in the bf16 model) and
+    theta_cycle_last the argument of make_theta for that cycle.
     """
     if precision not in ("fp64", "fp32", "bf16q"):
         raise ValueError(precision)
@@ -64,8 +67,10 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
     cycle = 0
     converged = False
     true_relres = 1.0
+    Q_last, theta_last = np.zeros((n, 0)), None
     while iters < max_iters and (max_cycles is None or cycle < max_cycles):
-        theta = make_theta(0 if reuse_theta else cycle)
+        theta_last = 0 if reuse_theta else cycle
+        theta = make_theta(theta_last)
         k = theta.k
         mmax = restart + 1
         Q = np.zeros((n, mmax), dtype=store)     # bf16q: the stored, unnormalised columns
@@ -143,6 +148,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
         if bf16:
             y = y * scale[:used]
         x = x + Q[:, :used].astype(np.float64) @ y
+        Q_last = Q[:, :used].astype(np.float64)
         r0 = b - apply_A(x, np.float64)
         true_relres = np.linalg.norm(r0) / bnorm
         cycle += 1
@@ -150,4 +156,5 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
             converged = True
             break
     return {"x": x, "hist": np.array(hist), "iters": iters, "cycles": cycle,
-            "true_relres": true_relres, "converged": converged}
+            "true_relres": true_relres, "converged": converged, "Q_last": Q_last,
+            "theta_cycle_last": theta_last}

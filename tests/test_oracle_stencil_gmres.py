@@ -177,3 +177,26 @@ def test_reversed_projection_order_is_the_same_step(precision):
     else:
         L = min(len(ref["hist"]), len(rev["hist"]))
         assert np.any(rev["hist"][:L] != ref["hist"][:L])
+
+
+@pytest.mark.parametrize("kind", ["srht", "gaussian"])
+def test_last_cycle_basis_is_sketch_orthonormal_and_spans_the_update(kind):
+    """The returned last-cycle basis: its sketch with that cycle's Theta has
+    orthonormal columns (S = Theta Q of RGS, Algorithm 2, in fp64), and the
+    last update of x lies in its span (x_final - x_before = Q_last y)."""
+    N, Pe = 10, 50.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=5)
+    applyA = lambda u, dt: stencil.apply(u, dims, coeffs, dt)
+    make = lambda c: sketch.make(kind, n, 80, seed=42, sketch_id=2 + c)
+    out = gmres.rgmres(applyA, b, make, restart=20, tol=1e-6)
+    Q = out["Q_last"]
+    assert out["converged"] and out["cycles"] >= 2 and Q.shape[1] >= 1
+    assert out["theta_cycle_last"] == out["cycles"] - 1
+    S = make(out["theta_cycle_last"]).apply(Q)
+    assert np.linalg.norm(np.eye(Q.shape[1]) - S.T @ S, 2) <= 1e-12
+    prev = gmres.rgmres(applyA, b, make, restart=20, tol=1e-6, max_cycles=out["cycles"] - 1)
+    dx = out["x"] - prev["x"]
+    y = np.linalg.lstsq(Q, dx, rcond=None)[0]
+    assert np.linalg.norm(dx - Q @ y) <= 1e-12 * np.linalg.norm(out["x"])   # x rounding, not dx, sets the floor
