@@ -107,7 +107,12 @@ typedef enum {
                                     sketches of n x m matrices (Theta Q, Phi Q, Phi W), a few k x m x m
                                     fp64 products and O(m^3) host work.  Not with IDENTITY (EINVAL).
                                     With RGS_FLAG_THETA_BF16, Phi is the Gaussian sketch (not its
-                                    bf16 variant). */
+                                    bf16 variant).
+                                    rgs_gmres: the certificate (Phi with counter word 2 = 1, which no
+                                    cycle's Theta uses) of the last cycle's Theta for V = its basis
+                                    vectors that the last update of x used, in rgs_report.cert_smin_q,
+                                    cert_smax_q, cert_cond_phi_q (the W pair stays NaN: the Arnoldi
+                                    vectors are not kept); Sec. 5.3 reports omega for this basis. */
 #define RGS_FLAG_THETA_BF16 16u  /* GAUSSIAN only (rgs_qr, rgs_qr_batched_ex, rgs_gmres, rgs_gmres_batched,
                                     rgs_sketch_apply, rgs_sketch_materialize): the Gaussian sketch
                                     with bf16 entries,
@@ -168,7 +173,8 @@ typedef struct {
     int32_t sketch;     /* rgs_sketch (GAUSSIAN, SRHT or RADEMACHER; batched: GAUSSIAN or SRHT) */
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
-    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16 and RGS_FLAG_LAG are honoured, other bits ignored;
+    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16, RGS_FLAG_LAG and RGS_FLAG_CERTIFY are honoured,
+                           other bits ignored;
                            rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
     uint32_t ls_sweeps; /* rgs_gmres: step 2 of every Arnoldi step (Alg. 3 on RGS, Sec. 2.3's remark on the
                            least-squares solver): 0 = Householder QR of S; 1..8 = that many Richardson

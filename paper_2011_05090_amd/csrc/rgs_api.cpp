@@ -555,6 +555,54 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     return RGS_OK;
 }
 
+// The certificate of Prop. 3.7 for one basis V (n x m, leading dimension ldv,
+// element TQ): the extreme singular values of (Theta V) X with (Phi V) X
+// orthonormal, and cond_2(Phi V).  Any column scaling of V gives the same
+// values (V -> V M leaves them unchanged), so unnormalised stored columns are
+// certified as they are.  Phi's tables overwrite Theta's (signs, rows): V is
+// sketched with Theta first.  ws: 3 k m + 2 m^2 doubles; part: the plan's
+// step-1 partials.  The values stay NaN where a factorisation fails.
+template <typename TQ, typename T>
+rgs_status certify_basis(rgs_handle* h, const QrPlan& pl, const SketchArgs& theta, const SketchArgs& phi,
+                         const TQ* V, int64_t ldv, int64_t n, int m, int k, double* ws, double* part,
+                         uint32_t* signs, int* rows, double* smin, double* smax, double* cond_phi) {
+    hipStream_t s = h->stream;
+    const size_t mm = (size_t)m * m;
+    double* thV = ws;
+    double* phV = thV + (size_t)k * m;
+    double* Y = phV + (size_t)k * m;
+    double* Md = Y + (size_t)k * m;
+    double* Gd = Md + mm;
+    rgs_status st = sketch_matrix<TQ, T, double>(h, theta, V, ldv, n, m, pl.G_P, pl.cc, part, thV, k);
+    if (st != RGS_OK) return st;
+    SketchArgs ph = phi;
+    if ((st = setup_sketch(h, ph, n, signs, rows)) != RGS_OK) return st;
+    if ((st = sketch_matrix<TQ, T, double>(h, ph, V, ldv, n, m, pl.G_P, pl.cc, part, phV, k)) != RGS_OK) return st;
+    if (!launch_dgemm(s, true, m, m, k, phV, k, phV, k, Gd, m)) return RGS_EDEVICE;
+    std::vector<double> G(mm);
+    if (hipMemcpyAsync(G.data(), Gd, mm * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return RGS_EDEVICE;
+    double gmin = NAN, gmax = NAN;
+    if (dense::sym_eig_extremes(G, m, gmin, gmax) && gmin > 0) *cond_phi = std::sqrt(gmax / gmin);
+    std::vector<double> Tm = G;
+    if (!dense::cholesky_upper(Tm, m)) return RGS_OK;   // Phi V rank-deficient: no certificate
+    const std::vector<double> Tinv = dense::upper_inverse(Tm, m);
+    if (hipMemcpyAsync(Md, Tinv.data(), mm * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        !launch_dgemm(s, false, k, m, m, thV, k, Md, m, Y, k) || !launch_dgemm(s, true, m, m, k, Y, k, Y, k, Gd, m))
+        return RGS_EDEVICE;
+    std::vector<double> C(mm);
+    if (hipMemcpyAsync(C.data(), Gd, mm * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)   // Tinv and C stay alive till here
+        return RGS_EDEVICE;
+    double lo = NAN, hi = NAN;
+    if (dense::sym_eig_extremes(C, m, lo, hi)) {
+        *smin = std::sqrt(std::max(lo, 0.0));
+        *smax = std::sqrt(std::max(hi, 0.0));
+    }
+    return RGS_OK;
+}
+
 // fixed != nullptr: the factorisation runs in the caller-independent fixed
 // buffer `fixed` of fixed_bytes (the no-allocation entry point) instead of
 // the handle's arena: nothing is allocated, no event or auxiliary stream is
@@ -831,6 +879,9 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const bool dual = sk_kind == SK_GAUSS ||
                       ((d->flags & RGS_FLAG_LAG) != 0 && (sk_kind == SK_SRHT || sk_kind == SK_RADEM));
     const size_t opart2 = c.take<T>(dual ? pl.nproj * k : 1);
+    // RGS_FLAG_CERTIFY: the certificate of the last cycle's basis
+    const bool want_cert = (d->flags & RGS_FLAG_CERTIFY) != 0 && rep != nullptr;
+    const size_t ocert = c.take<double>(want_cert ? 3 * k * mcap + 2 * mcap * mcap : 1);
     rgs_status st = ensure_arena(h, c.off + kAlign);
     if (st != RGS_OK) return st;
     char* Ar = h->arena;
@@ -882,6 +933,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     double relres = bnorm > 0 ? 1.0 : 0.0;
     rgs_status result = RGS_OK;
     std::vector<double> hh((size_t)mcap);
+    SketchArgs sk_last{};   // the last cycle's Theta and the basis vectors its update used
+    int u_last = 0;
     while (bnorm > 0 && std::isfinite(bnorm)) {
         if (iters >= d->max_iters) {
             result = RGS_ENOCONV;
@@ -950,6 +1003,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         if (hipStreamSynchronize(s) != hipSuccess) return RGS_EDEVICE;
         ++cycles;
         iters += u;
+        sk_last = sk;
+        u_last = u;
         for (int t = 0; t < u && nhist < hist_cap && res_hist; ++t) res_hist[nhist++] = hh[t];
         relres = rn / bnorm;
         if (stat[0] == kStatusNonfinite || !std::isfinite(rn)) {
@@ -976,6 +1031,18 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         rep->seconds = std::chrono::duration<double>(t1 - t0).count();
         rep->proj_kernel_ms = 0.0;
         rep->proj_launches = iters;
+        if (want_cert && u_last > 0 && result != RGS_ENONFINITE) {
+            // Phi: the same kind and size, counter word 2 = 1, which no cycle's Theta
+            // uses (they take 2 + c); the Gaussian sketch for a bf16-table Theta
+            const int phi_kind = sk_last.sketch == SK_TABLE ? SK_GAUSS : sk_last.sketch;
+            const SketchArgs phi = make_sketch(phi_kind, k, d->seed, 1u, 0);
+            st = certify_basis<TQ, T>(h, pl, sk_last, phi, Q, ldq, n, u_last, (int)k,
+                                      reinterpret_cast<double*>(Ar + ocert), reinterpret_cast<double*>(Ar + pl.part_P),
+                                      reinterpret_cast<uint32_t*>(Ar + pl.signs), reinterpret_cast<int*>(Ar + pl.rows),
+                                      &rep->cert_smin_q, &rep->cert_smax_q, &rep->cert_cond_phi_q);
+            if (st != RGS_OK) return st;
+            rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
     }
     return result;
 }
@@ -2419,6 +2486,7 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     q.prec = d->prec;
     if (!valid_desc(&q, true)) return RGS_EINVAL;
     if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
+    if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;   // Phi = Theta = I
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64) return run_gmres<double, double, false>(h, A, d, b, x, res_hist, hist_cap, rep);
     if (d->prec == RGS_P_BF16Q_FP32_LS64) return run_gmres<float, bf16, true>(h, A, d, b, x, res_hist, hist_cap, rep);
