@@ -414,6 +414,33 @@ def copy_ceiling(torch, dev, reps=7):
     return 2.0 * (1 << 30) / sorted(times)[len(times) // 2] / 1e9
 
 
+def rademacher_leg(rgs, torch, synth, h, n=1 << 22, m=512, k=2048, steps=1, warmup=1):
+    """fp32 RGS with the Rademacher sketch at the headline size (W = U Sigma V^T,
+    sigma 1..1e-8): time per QR, the fused projection + sketch kernel per
+    column (events around every launch), and the quality.  A profiling aid
+    for the kernel's counters (`--only rademacher`)."""
+    W64 = synth.svd_matrix_torch(n, m, 1e-8, tag=0)
+    W = rgs.colmajor(n, m, torch.float32)
+    W.copy_(W64)
+    del W64
+    Q = rgs.colmajor(n, m, torch.float32)
+    R = rgs.colmajor(m, m, torch.float64)
+    S = rgs.colmajor(k, m, torch.float64)
+    d = rgs.qr_desc(n, m, k, sketch="rademacher", prec="fp32", flags=rgs.FLAG_TIME_KERNELS)
+    ms, kern_ms, rep = run_steps(rgs, torch, h, d, W, Q, R, S, steps, warmup)
+    res, d2, o2 = quality(torch, W, Q, R, S)
+    per_col = kern_ms / steps / m
+    out = {"n": n, "m": m, "k": k, "ms_per_qr": ms, "status": rep.status,
+           "projection_ms_per_column": per_col,
+           "projection_gbs": project_bytes(n, m, 4) / m / (per_col / 1000) / 1e9,
+           "backward_error": res, "norm2_I_minus_StS": d2, "norm2_I_minus_QtQ": o2}
+    log("  rademacher fp32: %.1f ms/QR, fused kernel %.3f ms per column (%.0f GB/s), ||W-QR||/||W|| %.2e" %
+        (ms, per_col, out["projection_gbs"], res))
+    del W, Q, R, S
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian", "gaussian_bf16_table"), steps=2,
                    warmup=1, gaussian_batch=2048, graph=True):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
@@ -731,7 +758,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched and small fp64 QR legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--only", choices=["small", "batched-qr", "batched-gmres", "gmres", "sec51"],
+    ap.add_argument("--only", choices=["small", "batched-qr", "batched-gmres", "gmres", "sec51", "rademacher"],
                     help="profiling aid: run only this leg and print its JSON (not the benchmark line)")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
@@ -766,7 +793,7 @@ def main():
     if args.only:
         h = rgs.Handle(0)
         leg = {"small": small_fp64_leg, "batched-qr": batched_qr_leg, "batched-gmres": batched_gmres_leg,
-               "gmres": gmres_leg, "sec51": sec51_leg}[args.only]
+               "gmres": gmres_leg, "sec51": sec51_leg, "rademacher": rademacher_leg}[args.only]
         kw = {}
         if args.leg_steps is not None:
             kw["steps"] = args.leg_steps
