@@ -113,3 +113,27 @@ def test_batched_graph_rejects_unknown_flags(gpu_handle):
         with pytest.raises(rgs.RgsError) as e:
             rgs.rgs_qr_batched(gpu_handle, items, sketch="srht", prec="fp32", flags=bad)
         assert e.value.status == rgs.RGS_EINVAL
+
+
+def test_batched_graph_reports_per_item_failures(gpu_handle):
+    """The status words are cleared and read on every replay: a batch whose
+    contents turn a zero column and a NaN into two items reports them per item
+    on the replay, as the eager call does, and the next replay on healthy
+    contents reports none."""
+    rgs = _rgs()
+    items = _items(_shapes(6, seed=8), "fp32")
+    _fill(items, 5900)
+    good = _call(gpu_handle, items, "srht", "fp32", 0)
+    for rep in range(2):   # capture, replay
+        _same(_call(gpu_handle, items, "srht", "fp32", rgs.FLAG_GRAPH), good)
+    items[2][0][:, 3] = 0.0
+    items[0][0][17, 2] = float("nan")
+    torch.cuda.synchronize()
+    for flags in (0, rgs.FLAG_GRAPH):
+        rep, stat, fcol = rgs.rgs_qr_batched(gpu_handle, items, sketch="srht", prec="fp32", flags=flags)
+        torch.cuda.synchronize()
+        assert rep.status == rgs.RGS_ENONFINITE
+        assert stat == [rgs.RGS_ENONFINITE, 0, rgs.RGS_EBREAKDOWN, 0, 0, 0]
+        assert fcol == [2, -1, 3, -1, -1, -1]
+    _fill(items, 5900)
+    _same(_call(gpu_handle, items, "srht", "fp32", rgs.FLAG_GRAPH), good)

@@ -152,3 +152,29 @@ def test_unique_precision_rejections(gpu_handle):
     with pytest.raises(rgs.RgsError) as e:
         rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs), rgs.gmres_desc(10, 40, 1e-6, prec="fp32u"), b, x)
     assert e.value.status == rgs.RGS_EINVAL
+
+
+def test_unique_precision_breakdown_and_nonfinite(gpu_handle):
+    """The float32 chain keeps the breakdown tests: an exactly zero column is a
+    breakdown at that column (r_ii = 0), a NaN a non-finite sketch; the
+    columns before it match the oracle's fp32u model."""
+    rgs = _rgs()
+    n, m, k = 12000, 10, 64
+    W = synth.svd_matrix(n, m, 1e-1, tag=34).astype(np.float32)
+    W[:, 6] = 0.0
+    Wd = to_dev(W, torch.float32)
+    Q = rgs.colmajor(n, m, torch.float32)
+    R = rgs.colmajor(m, m, torch.float64)
+    S = rgs.colmajor(k, m, torch.float64)
+    rep = rgs.rgs_qr(gpu_handle, rgs.qr_desc(n, m, k, sketch="srht", prec="fp32u"), Wd, Q, R, S)
+    torch.cuda.synchronize()
+    assert rep.status == rgs.RGS_EBREAKDOWN and rep.failed_column == 6
+    orc = orgs.rgs_qr(W[:, :6], osk.SRHT(n, k, seed=42), precision="fp32u")
+    Rh = host(R)[:6, :6]
+    assert np.linalg.norm(Rh - orc["R"]) <= 1e-5 * np.linalg.norm(orc["R"])
+    W[:, 6] = W[:, 1]
+    W[99, 4] = np.nan
+    rep = rgs.rgs_qr(gpu_handle, rgs.qr_desc(n, m, k, sketch="srht", prec="fp32u"), to_dev(W, torch.float32), Q, R,
+                     S)
+    torch.cuda.synchronize()
+    assert rep.status == rgs.RGS_ENONFINITE and rep.failed_column == 4
