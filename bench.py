@@ -725,6 +725,24 @@ def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6
                                        "speedup_vs_fp64_gaussian": res["gaussian_fp64"]["seconds_to_tol"] / dt}
     log("  rgmres gaussian(bf16 table)/fp32: %d iters, %d cycles, relres %.2e, %.3f s" %
         (rep.iters, rep.cycles, rep.true_relres, dt))
+    # the same Gaussian sketch with its entries made once per cycle into a table in the
+    # working precision (RGS_FLAG_THETA_EXACT): the sketch becomes a memory stream
+    for prec in ("fp32", "fp64"):
+        d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="gaussian", prec=prec,
+                           flags=rgs.FLAG_THETA_EXACT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, _ = rgs.rgs_gmres(h, A, d, b, x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bq = 4 if prec == "fp32" else 8
+        nbytes = gmres_bytes(n, rep.iters, rep.cycles, restart, bq, bq)
+        res["gaussian_exact_table_%s" % prec] = {
+            "seconds_to_tol": dt, "iters": rep.iters, "cycles": rep.cycles, "true_relres": rep.true_relres,
+            "status": rep.status, "table_bytes": bq * k * ((n + 7) // 8 * 8),
+            "speedup_vs_drawn": res["gaussian_%s" % prec]["seconds_to_tol"] / dt}
+        log("  rgmres gaussian(exact table)/%s: %d iters, %d cycles, relres %.2e, %.3f s (%.2fx the drawn sketch)" %
+            (prec, rep.iters, rep.cycles, rep.true_relres, dt, res["gaussian_%s" % prec]["seconds_to_tol"] / dt))
     # the P-SRHT with the lagged Arnoldi step (RGS_FLAG_LAG): both sketches of a step in the mat-vec pass
     for prec in ("fp32", "fp64"):
         d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec=prec, flags=rgs.FLAG_LAG)
@@ -901,6 +919,18 @@ def main():
                                                  "backward_error": tres, "norm2_I_minus_StS": td2,
                                                  "norm2_I_minus_QtQ": to2}
         log("  %.2f ms/QR, ||W-QR||/||W|| %.2e, ||I-S^TS||_2 %.2e" % (msgt, tres, td2))
+        # the same Gaussian sketch as the drawn leg, its fp32 entries made once into a table
+        dgx = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32", flags=rgs.FLAG_THETA_EXACT)
+        log("fp32 RGS, Gaussian sketch from its exact fp32 table: 1 warmup, 1 step")
+        msgx, _, repgx = run_steps(rgs, torch, h, dgx, W32, Q, R, S, 1, 1)
+        xres, xd2, xo2 = quality(torch, W32, Q, R, S)
+        extra["fp32_rgs_gaussian_exact_table"] = {"ms_per_qr": msgx, "gbs": B / (msgx / 1000) / 1e9,
+                                                  "status": repgx.status, "table_bytes": 4 * k * n,
+                                                  "speedup_vs_drawn": msg / msgx,
+                                                  "backward_error": xres, "norm2_I_minus_StS": xd2,
+                                                  "norm2_I_minus_QtQ": xo2}
+        log("  %.2f ms/QR (%.2fx the drawn sketch), ||W-QR||/||W|| %.2e, ||I-S^TS||_2 %.2e" %
+            (msgx, msg / msgx, xres, xd2))
         # Rademacher sketch, fp32 path: dense like the Gaussian, 128 signs per Philox call
         dr = rgs.qr_desc(n, m, k, sketch="rademacher", prec="fp32", flags=rgs.FLAG_TIME_KERNELS)
         log("fp32 RGS, Rademacher sketch: 1 warmup, 2 steps")

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 5
+#define RGS_ABI_VERSION 6
 
 typedef struct rgs_handle rgs_handle;  /* opaque */
 typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
@@ -131,11 +131,22 @@ typedef enum {
                                     projection no longer sketches; w_{i+1} = t / r_ii is applied on
                                     load.  Equal to Algorithm 3 in exact arithmetic.  The GAUSSIAN
                                     sketch always takes this step (its two sketches share draws). */
+#define RGS_FLAG_THETA_EXACT 64u /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_sketch_apply; EINVAL with
+                                    RGS_FLAG_THETA_BF16 and on the other calls): the same sketch
+                                    (Sec. 2.1), its entries made once per Theta -- by the Box-Muller
+                                    of the working precision, as every drawn sketch makes them --
+                                    into a table of sizeof(T) k ceil(n/8)*8 bytes (T: double for
+                                    RGS_P_FP64, else float) in the handle's scratch, and read from it
+                                    by every later sketch instead of being drawn again: a sketch
+                                    becomes a memory stream instead of a Philox call and a
+                                    Box-Muller per four entries.  Results agree with the drawn sketch
+                                    up to the order of the sums.  For k n small enough to keep
+                                    (11.3 GB at k = 400, n = 192^3, float). */
 
 /* Describes one RGS factorisation and its sketch Theta (k x n).
  * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
  * regenerated on demand and not stored (Sec. 2.1, seeded generation), except
- * for the bf16 table that RGS_FLAG_THETA_BF16 asks for. */
+ * for the tables that RGS_FLAG_THETA_BF16 and RGS_FLAG_THETA_EXACT ask for. */
 typedef struct {
     int64_t n;           /* rows of W (high dimension), n >= 1 */
     int64_t m;           /* columns of W, 1 <= m <= k */
@@ -173,7 +184,8 @@ typedef struct {
     int32_t sketch;     /* rgs_sketch (GAUSSIAN, SRHT or RADEMACHER; batched: GAUSSIAN or SRHT) */
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
-    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16, RGS_FLAG_LAG and RGS_FLAG_CERTIFY are honoured,
+    uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16, RGS_FLAG_THETA_EXACT, RGS_FLAG_LAG and
+                           RGS_FLAG_CERTIFY are honoured,
                            other bits ignored;
                            rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
     uint32_t ls_sweeps; /* rgs_gmres: step 2 of every Arnoldi step (Alg. 3 on RGS, Sec. 2.3's remark on the

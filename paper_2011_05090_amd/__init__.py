@@ -27,6 +27,7 @@ FLAG_GRAPH = 4
 FLAG_CERTIFY = 8
 FLAG_THETA_BF16 = 16
 FLAG_LAG = 32
+FLAG_THETA_EXACT = 64
 
 
 class RgsError(RuntimeError):

@@ -205,7 +205,9 @@ int sketch_kind(int32_t sketch) {
 }
 
 // Sketches generated entry by entry from Philox (no transform).
-bool dense_sketch(int sk_kind) { return sk_kind == SK_GAUSS || sk_kind == SK_RADEM || sk_kind == SK_TABLE; }
+bool dense_sketch(int sk_kind) {
+    return sk_kind == SK_GAUSS || sk_kind == SK_RADEM || sk_kind == SK_TABLE || sk_kind == SK_TABX;
+}
 
 bool valid_desc(const rgs_qr_desc* d, bool need_m) {
     if (!d) return false;
@@ -282,8 +284,10 @@ constexpr int64_t kSplitRows = (int64_t)128 * kProjRows;
 
 // part_budget: bytes for the step-1 partials of the columns sketched together
 // (at least one column's worth is always planned).
+// table: bytes per entry of a table of Theta (0: none; 2: the bf16 table;
+// sizeof(T): the exact table).
 QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool certify = false,
-               bool table = false, size_t part_budget = (size_t)64 << 20) {
+               size_t table = 0, size_t part_budget = (size_t)64 << 20) {
     QrPlan p{};
     Carver c;
     p.nblk = (n + kBlock - 1) / kBlock;
@@ -327,8 +331,8 @@ QrPlan plan_qr(int64_t n, int64_t m, int64_t k, int sketch, size_t tsize, bool c
     p.diag = c.take<double>(3 * m);
     // certification (Prop. 3.7): six k x m and four m x m fp64 matrices
     p.cert = certify ? c.take<double>(6 * k * m + 4 * m * m) : 0;
-    // Gaussian sketch with bf16 entries: (n + 7) / 8 groups of 8 entries per sketch row
-    p.table = table ? c.take<uint16_t>((size_t)((n + 7) / 8) * 8 * k) : 0;
+    // table of the Gaussian sketch: (n + 7) / 8 groups of 8 entries per sketch row
+    p.table = table ? c.take<char>((size_t)((n + 7) / 8) * 8 * k * table) : 0;
     p.total = c.off + kAlign;
     return p;
 }
@@ -366,6 +370,24 @@ rgs_status use_table(rgs_handle* h, SketchArgs& sk, int64_t n, uint16_t* table) 
     sk.sketch = SK_TABLE;
     sk.table = table;
     return RGS_OK;
+}
+
+// RGS_FLAG_THETA_EXACT: fills the table of the Gaussian sketch sk with its
+// entries in T (in stream order) and switches sk to read it.
+template <typename T>
+rgs_status use_tabx(rgs_handle* h, SketchArgs& sk, int64_t n, T* table) {
+    if (!launch_theta_tabx<T>(h->stream, sk, n, table)) return RGS_EDEVICE;
+    sk.sketch = SK_TABX;
+    sk.tabx = table;
+    return RGS_OK;
+}
+
+// Bytes per entry of the table of Theta that desc flags ask for (T: the
+// working type of the sketches).
+size_t table_entry(uint32_t flags, size_t tsize) {
+    if (flags & RGS_FLAG_THETA_BF16) return 2;
+    if (flags & RGS_FLAG_THETA_EXACT) return tsize;
+    return 0;
 }
 
 // Y = Theta X for ncols columns of X (element type TX; Theta's entries and
@@ -475,7 +497,7 @@ rgs_status certify(rgs_handle* h, const rgs_qr_desc* d, const QrPlan& pl, const 
     rgs_status st = sketch_matrix<TQ, T, double>(h, theta, Q, ldq, n, m, pl.G_P, pl.cc, part, thQ, k);
     if (st != RGS_OK) return st;
     // Phi of a bf16-table Theta is the Gaussian sketch generated on the fly
-    const int phi_kind = theta.sketch == SK_TABLE ? SK_GAUSS : theta.sketch;
+    const int phi_kind = (theta.sketch == SK_TABLE || theta.sketch == SK_TABX) ? SK_GAUSS : theta.sketch;
     SketchArgs phi = make_sketch(phi_kind, k, d->seed, d->sketch_id + 1u, d->instance);
     // Theta's tables are no longer read: Phi's overwrite them in stream order
     st = setup_sketch(h, phi, n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
@@ -621,18 +643,19 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
     const int sk_kind = sketch_kind(d->sketch);
     const bool want_cert = (d->flags & RGS_FLAG_CERTIFY) != 0 && rep != nullptr;
     const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
-    QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert, tab);
+    const bool tabx = (d->flags & RGS_FLAG_THETA_EXACT) != 0;
+    QrPlan pl = plan_qr(n, m, k, sk_kind, sizeof(T), want_cert, table_entry(d->flags, sizeof(T)));
     rgs_status st = RGS_OK;
     char* A = nullptr;
     if (fixed) {
         // as many step-1 columns per chunk as the fixed buffer leaves room for
         const size_t per_col = (size_t)pl.G_P * k * sizeof(double);
-        pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, false, per_col);
+        pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, 0, per_col);
         if (pl.total > fixed_bytes) return RGS_ESCRATCH;
         const size_t more = (fixed_bytes - pl.total) / std::max<size_t>(per_col, 1);
-        pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, false, per_col * (1 + more));
+        pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, 0, per_col * (1 + more));
         while (pl.total > fixed_bytes && pl.cc > 1)   // alignment padding
-            pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, false, per_col * (size_t)(pl.cc - 1));
+            pl = plan_qr(n, m, k, sk_kind, sizeof(T), false, 0, per_col * (size_t)(pl.cc - 1));
         if (pl.total > fixed_bytes) return RGS_ESCRATCH;
         A = fixed;
     } else {
@@ -645,6 +668,7 @@ rgs_status run_qr(rgs_handle* h, const rgs_qr_desc* d, const T* W, int64_t ldw, 
                       fixed != nullptr);
     if (st != RGS_OK) return st;
     if (tab && (st = use_table(h, sk, n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
+    if (tabx && (st = use_tabx<T>(h, sk, n, reinterpret_cast<T*>(A + pl.table))) != RGS_OK) return st;
 
     SpaceArgs sa = space_args(A, pl, k, m);
     double* P = reinterpret_cast<double*>(A + pl.P);
@@ -864,7 +888,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     const int64_t n = A.nx * A.ny * A.nz, mcap = d->restart + 1, k = d->k;
     const int sk_kind = sketch_kind(d->sketch);
     const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
-    const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T), false, tab);
+    const bool tabx = (d->flags & RGS_FLAG_THETA_EXACT) != 0;
+    const QrPlan pl = plan_qr(n, mcap, k, sk_kind, sizeof(T), false, table_entry(d->flags, sizeof(T)));
     Carver c;
     c.off = pl.total;
     const int64_t ldq = (n + 3) / 4 * 4;   // 16-byte aligned columns: every full block takes vector loads
@@ -952,6 +977,14 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
                 sk.sketch = SK_TABLE;
                 sk.table = table;
             }
+        } else if (tabx) {
+            T* table = reinterpret_cast<T*>(Ar + pl.table);
+            if (cycles == 0 || !d->reuse_theta) {
+                if ((st = use_tabx<T>(h, sk, n, table)) != RGS_OK) return st;
+            } else {
+                sk.sketch = SK_TABX;
+                sk.tabx = table;
+            }
         }
         if (hipMemsetAsync(sa.status, 0, 4 * sizeof(int), s) != hipSuccess) return RGS_EDEVICE;
         // RGS step 1 of Algorithm 3: w_1 = r_0
@@ -1034,7 +1067,8 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
         if (want_cert && u_last > 0 && result != RGS_ENONFINITE) {
             // Phi: the same kind and size, counter word 2 = 1, which no cycle's Theta
             // uses (they take 2 + c); the Gaussian sketch for a bf16-table Theta
-            const int phi_kind = sk_last.sketch == SK_TABLE ? SK_GAUSS : sk_last.sketch;
+            const int phi_kind =
+                (sk_last.sketch == SK_TABLE || sk_last.sketch == SK_TABX) ? SK_GAUSS : sk_last.sketch;
             const SketchArgs phi = make_sketch(phi_kind, k, d->seed, 1u, 0);
             st = certify_basis<TQ, T>(h, pl, sk_last, phi, Q, ldq, n, u_last, (int)k,
                                       reinterpret_cast<double*>(Ar + ocert), reinterpret_cast<double*>(Ar + pl.part_P),
@@ -1773,6 +1807,13 @@ bool grid_size(const rgs_stencil7& A, int64_t* n) {
     return true;
 }
 
+// The tables of Theta: GAUSSIAN only, at most one of the two.
+bool valid_table_flags(uint32_t flags, int32_t sketch) {
+    const uint32_t t = flags & (RGS_FLAG_THETA_BF16 | RGS_FLAG_THETA_EXACT);
+    if (t == 0) return true;
+    return sketch == RGS_SKETCH_GAUSSIAN && t != (RGS_FLAG_THETA_BF16 | RGS_FLAG_THETA_EXACT);
+}
+
 bool valid_gmres_desc(const rgs_gmres_desc* d) {
     if (!d) return false;
     if (d->restart < 1 || d->restart + 1 > d->k || d->restart > 4000 || d->max_iters < 1 || !(d->tol >= 0))
@@ -2357,13 +2398,13 @@ rgs_status rgs_qr(rgs_handle* h, const rgs_qr_desc* d, const void* W, int64_t ld
     if (!h || !valid_desc(d, true) || !W || !Q || !R || !S) return RGS_EINVAL;
     if (ldw < d->n || ldq < d->n || ldr < d->m || lds < d->k) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_DIAGNOSTICS | RGS_FLAG_TIME_KERNELS | RGS_FLAG_CERTIFY | RGS_FLAG_THETA_BF16 |
-                      RGS_FLAG_GRAPH)) != 0)
+                      RGS_FLAG_GRAPH | RGS_FLAG_THETA_EXACT)) != 0)
         return RGS_EINVAL;
+    if (!valid_table_flags(d->flags, d->sketch)) return RGS_EINVAL;
     // kernel timing records events between the launches, which a replayed graph does not have
     if ((d->flags & RGS_FLAG_GRAPH) && (d->flags & RGS_FLAG_TIME_KERNELS)) return RGS_EINVAL;
     // Phi = Theta = I would certify nothing
     if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;
-    if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     if (d->m > 4096) return RGS_EINVAL;   // dynamic LDS of the sketch-space kernels
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64)
@@ -2414,10 +2455,11 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     const int sk_kind = sketch_kind(d->sketch);
     const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
-    if (tab && sk_kind != SK_GAUSS) return RGS_EINVAL;
+    const bool tabx = (d->flags & RGS_FLAG_THETA_EXACT) != 0;
+    if (!valid_table_flags(d->flags, d->sketch)) return RGS_EINVAL;
     const size_t tsize = d->prec == RGS_P_FP64 ? sizeof(double) : sizeof(float);
     // W and X are float on the bf16 path
-    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize, false, tab);
+    const QrPlan pl = plan_qr(d->n, ncols, d->k, sk_kind, tsize, false, table_entry(d->flags, tsize));
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -2425,6 +2467,11 @@ rgs_status rgs_sketch_apply(rgs_handle* h, const rgs_qr_desc* d, const void* X, 
     st = setup_sketch(h, sk, d->n, reinterpret_cast<uint32_t*>(A + pl.signs), reinterpret_cast<int*>(A + pl.rows));
     if (st != RGS_OK) return st;
     if (tab && (st = use_table(h, sk, d->n, reinterpret_cast<uint16_t*>(A + pl.table))) != RGS_OK) return st;
+    if (tabx) {
+        st = d->prec == RGS_P_FP64 ? use_tabx<double>(h, sk, d->n, reinterpret_cast<double*>(A + pl.table))
+                                   : use_tabx<float>(h, sk, d->n, reinterpret_cast<float*>(A + pl.table));
+        if (st != RGS_OK) return st;
+    }
     if (d->prec == RGS_P_FP64)
         st = sketch_matrix<double, double, double>(h, sk, static_cast<const double*>(X), ldx, d->n, ncols, pl.G_P,
                                                    pl.cc, reinterpret_cast<double*>(A + pl.part_P), Y, ldy);
@@ -2452,7 +2499,8 @@ rgs_status rgs_sketch_materialize(rgs_handle* h, const rgs_qr_desc* d, int64_t j
     const int sk_kind = sketch_kind(d->sketch);
     const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
     if (tab && sk_kind != SK_GAUSS) return RGS_EINVAL;
-    const QrPlan pl = plan_qr(d->n, 1, d->k, sk_kind, sizeof(double), false, tab);
+    if (d->flags & RGS_FLAG_THETA_EXACT) return RGS_EINVAL;   // the entries are those of the GAUSSIAN sketch
+    const QrPlan pl = plan_qr(d->n, 1, d->k, sk_kind, sizeof(double), false, tab ? 2 : 0);
     rgs_status st = ensure_arena(h, pl.total);
     if (st != RGS_OK) return st;
     char* A = h->arena;
@@ -2485,7 +2533,7 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     q.sketch = d->sketch;
     q.prec = d->prec;
     if (!valid_desc(&q, true)) return RGS_EINVAL;
-    if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
+    if (!valid_table_flags(d->flags, d->sketch)) return RGS_EINVAL;
     if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;   // Phi = Theta = I
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64) return run_gmres<double, double, false>(h, A, d, b, x, res_hist, hist_cap, rep);

@@ -18,6 +18,43 @@ namespace rgs {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+// SK_TABX: group o of sketch row j holds the 8 entries z(j, 8o .. 8o+7) in the
+// working type T as W = 8 sizeof(T) / 16 words of 16 bytes; word w of every
+// sketch row of the group sits in one run, at 16-byte index (o W + w) k + j,
+// so the lanes of a wave (consecutive j) read one contiguous kilobyte per load.
+template <typename T>
+struct TabxGroup;
+template <>
+struct TabxGroup<float> {
+    f32x4 a, b;
+};
+template <>
+struct TabxGroup<double> {
+    f64x2 a, b, c, d;
+};
+__device__ __forceinline__ TabxGroup<float> tabx_load(const float* __restrict__ t, int k, int64_t o, int j) {
+    const f32x4* p = reinterpret_cast<const f32x4*>(t) + 2 * o * k + j;
+    return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + k)};
+}
+__device__ __forceinline__ TabxGroup<double> tabx_load(const double* __restrict__ t, int k, int64_t o, int j) {
+    const f64x2* p = reinterpret_cast<const f64x2*>(t) + 4 * o * k + j;
+    return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + k), __builtin_nontemporal_load(p + 2 * k),
+            __builtin_nontemporal_load(p + 3 * k)};
+}
+__device__ __forceinline__ void tabx_unpack(const TabxGroup<float>& g, float z[8]) {
+    z[0] = g.a.x; z[1] = g.a.y; z[2] = g.a.z; z[3] = g.a.w;
+    z[4] = g.b.x; z[5] = g.b.y; z[6] = g.b.z; z[7] = g.b.w;
+}
+__device__ __forceinline__ void tabx_unpack(const TabxGroup<double>& g, double z[8]) {
+    z[0] = g.a.x; z[1] = g.a.y; z[2] = g.b.x; z[3] = g.b.y;
+    z[4] = g.c.x; z[5] = g.c.y; z[6] = g.d.x; z[7] = g.d.y;
+}
+// groups a thread keeps in flight: 256 bytes, as kTabDepth bf16 groups
+template <typename T>
+constexpr int tabx_depth() {
+    return 256 / (8 * (int)sizeof(T));
+}
+
 // `vec` (aligned columns) lets a partial tile still load its complete 4-row
 // groups as vectors; the group that straddles n is read element by element.
 template <typename T>
@@ -309,6 +346,42 @@ __device__ __forceinline__ void block_sketch(T v[16], int64_t blk, int64_t n, co
                         if (o + d < no) {
                             T z[8];
                             tab_unpack<T>(w[d], z);
+                            const T* x = lds + 8 * (o + d);
+                            a += (PT)(z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3]);
+                            a += (PT)(z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7]);
+                        }
+                    }
+                }
+                acc[u] = a;
+            }
+        }
+        __syncthreads();
+    } else if constexpr (SK == SK_TABX) {   // the SK_TABLE pass with the entries in T
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[wave * kTile + 256 * e + 4 * lane + r] = v[4 * e + r];
+        __syncthreads();
+        const T* tab = static_cast<const T*>(sk.tabx);
+        constexpr int D = tabx_depth<T>();
+        const int64_t rem = n - blk * (NW * kTile);
+        const int no = rem >= NW * kTile ? NW * kTile / 8 : (int)((rem + 7) / 8);
+        const int64_t o0 = blk * (NW * kTile / 8);
+#pragma unroll
+        for (int u = 0; u < kKptMax; ++u) {
+            const int j = t + NT * u;
+            if (u < kpt && j < sk.k) {
+                PT a = acc[u];
+                for (int o = 0; o < no; o += D) {
+                    TabxGroup<T> w[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        if (o + d < no) w[d] = tabx_load(tab, sk.k, o0 + o + d, j);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        if (o + d < no) {
+                            T z[8];
+                            tabx_unpack(w[d], z);
                             const T* x = lds + 8 * (o + d);
                             a += (PT)(z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3]);
                             a += (PT)(z[4] * x[4] + z[5] * x[5] + z[6] * x[6] + z[7] * x[7]);

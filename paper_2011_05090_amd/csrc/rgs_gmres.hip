@@ -298,8 +298,10 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
 // q'_i and p_{i+1} of A q'_i, share every draw; the normalisation 1/r_ii is
 // applied to both later, when it is known).  Same row mapping and summation
 // order per vector as stencil_sketch_body.
-// TAB: the entries come from the bf16 table (SK_TABLE), 8 rows per load.
-template <typename TQ, typename T, bool TAB = false, int DEPTH = kTabDepth>
+// TAB: the entries come from the bf16 table (SK_TABLE), 8 rows per load;
+// EXACT (with TAB): from the table of the entries in T (SK_TABX), 8 rows per
+// 32- or 64-byte group.
+template <typename TQ, typename T, bool TAB = false, int DEPTH = kTabDepth, bool EXACT = false>
 __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
                                                   T* __restrict__ t_out, const SketchArgs& sk,
                                                   T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
@@ -336,15 +338,25 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
             if (u < kpt && j < sk.k) {
                 T sx = ax[u], st = at[u];
                 for (int o = 0; o < no; o += DEPTH) {
-                    tabw_t w[DEPTH];
+                    using group_t = std::conditional_t<EXACT, TabxGroup<T>, tabw_t>;
+                    group_t w[DEPTH];
 #pragma unroll
-                    for (int d = 0; d < DEPTH; ++d)
-                        if (o + d < no) w[d] = tab_load(sk.table, sk.k, o0 + o + d, j);
+                    for (int d = 0; d < DEPTH; ++d) {
+                        if (o + d < no) {
+                            if constexpr (EXACT)
+                                w[d] = tabx_load(static_cast<const T*>(sk.tabx), sk.k, o0 + o + d, j);
+                            else
+                                w[d] = tab_load(sk.table, sk.k, o0 + o + d, j);
+                        }
+                    }
 #pragma unroll
                     for (int d = 0; d < DEPTH; ++d) {
                         if (o + d < no) {
                             T z[8];
-                            tab_unpack<T>(w[d], z);
+                            if constexpr (EXACT)
+                                tabx_unpack(w[d], z);
+                            else
+                                tab_unpack<T>(w[d], z);
                             const T* x = lds + 8 * (o + d);
                             const T* tt = lds + RB + 8 * (o + d);
                             sx += z[0] * x[0] + z[1] * x[1] + z[2] * x[2] + z[3] * x[3];
@@ -582,7 +594,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
                                        lds);
 }
 
-template <typename TQ, typename T, bool TAB>
+template <typename TQ, typename T, bool TAB, bool EXACT = false>
 __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     const TQ* __restrict__ xs, Grid3 g, int64_t n, T* __restrict__ t_out, SketchArgs sk, T* __restrict__ part_x,
     T* __restrict__ part_t, const int* __restrict__ status) {
@@ -590,7 +602,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     RGS_EXIT_IF_STOPPED(status);
     // one system: k <= 512 threads stream the table with 4 loads in flight
     // (16 measured slower here; the batched row-block launch uses 16)
-    stencil_dual_body<TQ, T, TAB, 4>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
+    // (the exact table: 256 bytes in flight per thread)
+    stencil_dual_body<TQ, T, TAB, EXACT ? tabx_depth<T>() : 4, EXACT>(xs, g, n, t_out, sk, part_x, part_t,
+                                                                    xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename TQ, typename T, int SK>
@@ -882,7 +896,10 @@ bool launch_stencil_dual(hipStream_t st, const StencilArgs& A, const TQ* xs, T* 
                          T* part_x, T* part_t, const int* status) {
     const int64_t n = A.nx * A.ny * A.nz;
     const dim3 grid(nblk_of(n, kProjRows)), thr(kProjWaves * kWave);
-    if (sk.sketch == SK_TABLE)
+    if (sk.sketch == SK_TABX)
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true, true>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
+                           part_t, status);
+    else if (sk.sketch == SK_TABLE)
         hipLaunchKernelGGL((k_stencil_dual<TQ, T, true>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x, part_t,
                            status);
     else if (sk.sketch == SK_GAUSS)

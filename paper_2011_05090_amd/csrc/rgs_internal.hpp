@@ -104,6 +104,10 @@ bool launch_diagnostics(hipStream_t st, const double* P, int64_t ldp, const doub
                         const double* R, int64_t ldr, int k, int m, double* gram_out, double* resid_out);
 // Table of the Gaussian sketch with bf16 entries ((n + 7) / 8 * 8 * k entries, SK_TABLE layout).
 bool launch_theta_table(hipStream_t st, const SketchArgs& sk, int64_t n, uint16_t* table);
+// Table of the Gaussian sketch with its entries in T, exactly those the drawn
+// sketch computes ((n + 7) / 8 * 8 * k entries, SK_TABX layout).
+template <typename T>
+bool launch_theta_tabx(hipStream_t st, const SketchArgs& sk, int64_t n, T* table);
 // C = op(A) B in fp64 (op(A) = A^T when transA), the small products of the certification.
 bool launch_dgemm(hipStream_t st, bool transA, int M, int N, int K, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double* C, int64_t ldc);

@@ -391,10 +391,46 @@ __global__ void k_theta_table(SketchArgs sk, int64_t n, int64_t ngroups, uint16_
     *reinterpret_cast<u32x4_t*>(table + idx * 8) = v;
 }
 
+// Exact table of the Gaussian sketch (SK_TABX): thread (o, j) draws
+// z(j, 8o .. 8o+7) with the Box-Muller of the working type T -- the values the
+// drawn pass computes -- and writes the group's 16-byte words at 16-byte
+// indices (o W + w) k + j, W = 8 sizeof(T) / 16 (rows past n hold 0).
+template <typename T>
+__global__ void k_theta_tabx(SketchArgs sk, int64_t n, int64_t ngroups, T* __restrict__ table) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ngroups * sk.k) return;
+    const int64_t o = idx / sk.k;
+    const int j = (int)(idx - o * sk.k);
+    T z[8];
+    gauss4((uint32_t)(2 * o), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+    gauss4((uint32_t)(2 * o + 1), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z + 4);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        if (8 * o + r >= n) z[r] = T(0);
+    if constexpr (sizeof(T) == 4) {
+        f32x4* p = reinterpret_cast<f32x4*>(table) + 2 * o * sk.k + j;
+        f32x4 a, b;
+        a.x = z[0]; a.y = z[1]; a.z = z[2]; a.w = z[3];
+        b.x = z[4]; b.y = z[5]; b.z = z[6]; b.w = z[7];
+        p[0] = a;
+        p[sk.k] = b;
+    } else {
+        f64x2* p = reinterpret_cast<f64x2*>(table) + 4 * o * sk.k + j;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            f64x2 v;
+            v.x = z[2 * h];
+            v.y = z[2 * h + 1];
+            p[h * sk.k] = v;
+        }
+    }
+}
+
 // Table counterpart of gauss_cols_body (same workgroup and partials layout):
 // each 16-byte table load serves 8 rows of sketch row j for the C staged
-// columns.  SUB is a multiple of 8.
-template <typename TX, typename T, typename TA, int C, int SUB>
+// columns (EXACT: the SK_TABX table of the entries in T, 8 rows per 32- or
+// 64-byte group).  SUB is a multiple of 8.
+template <typename TX, typename T, typename TA, int C, int SUB, bool EXACT = false>
 __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols, int G,
                                                 const SketchArgs& sk, TA* __restrict__ partials, int g, int jc,
                                                 int cc, TA (*w)[SUB]) {
@@ -423,7 +459,14 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
             const int64_t o0 = r0 / 8;
             for (int o = 0; o < no; ++o) {
                 TA z[8];
-                tab8<TA>(sk.table, sk.k, o0 + o, j, z);
+                if constexpr (EXACT) {
+                    T ze[8];
+                    tabx_unpack(tabx_load(static_cast<const T*>(sk.tabx), sk.k, o0 + o, j), ze);
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) z[r] = (TA)ze[r];
+                } else {
+                    tab8<TA>(sk.table, sk.k, o0 + o, j, z);
+                }
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const TA* x = w[c] + 8 * o;
@@ -441,11 +484,12 @@ __device__ __forceinline__ void table_cols_body(const TX* __restrict__ X, int64_
     }
 }
 
-template <typename TX, typename T, typename TA, int C, int SUB>
+template <typename TX, typename T, typename TA, int C, int SUB, bool EXACT = false>
 __global__ __launch_bounds__(kWG) void k_table_cols(const TX* __restrict__ X, int64_t ldx, int64_t n, int ncols,
                                                     int G, SketchArgs sk, TA* __restrict__ partials) {
     __shared__ __attribute__((aligned(16))) TA w[C][SUB];
-    table_cols_body<TX, T, TA, C, SUB>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z, w);
+    table_cols_body<TX, T, TA, C, SUB, EXACT>(X, ldx, n, ncols, G, sk, partials, blockIdx.x, blockIdx.y, blockIdx.z,
+                                              w);
 }
 
 // Batched step 1 (Gaussian): map blocks are (factorisation, g + G_P (jc + njc cc)).
@@ -1481,7 +1525,14 @@ bool launch_gauss_cols(hipStream_t st, const TX* X, int64_t ldx, int64_t n, int 
     const dim3 g1(G, jc, 1), gc(G, jc, nblocks(ncols, kGaussCols));
     // columns staged in LDS in TA: 32 x kGSub fp32 or 32 x kGSub/2 fp64 (32 KB)
     constexpr int SUBC = sizeof(TA) > sizeof(float) && sizeof(T) == sizeof(float) ? kGSub / 2 : kGSub;
-    if (sk.sketch == SK_TABLE) {
+    if (sk.sketch == SK_TABX) {
+        if (ncols == 1)
+            hipLaunchKernelGGL((k_table_cols<TX, T, TA, 1, kGSubCol, true>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
+                               partials);
+        else
+            hipLaunchKernelGGL((k_table_cols<TX, T, TA, kGaussCols, SUBC, true>), gc, dim3(kWG), 0, st, X, ldx, n,
+                               ncols, G, sk, partials);
+    } else if (sk.sketch == SK_TABLE) {
         if (ncols == 1)
             hipLaunchKernelGGL((k_table_cols<TX, T, TA, 1, kGSubCol>), g1, dim3(kWG), 0, st, X, ldx, n, 1, G, sk,
                                partials);
@@ -1806,6 +1857,18 @@ bool launch_theta_table(hipStream_t st, const SketchArgs& sk, int64_t n, uint16_
     RGS_LAUNCH_CHECK();
     return true;
 }
+
+template <typename T>
+bool launch_theta_tabx(hipStream_t st, const SketchArgs& sk, int64_t n, T* table) {
+    const int64_t ngroups = (n + 7) / 8;
+    const int64_t work = ngroups * sk.k;
+    hipLaunchKernelGGL(k_theta_tabx<T>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, sk, n, ngroups,
+                       table);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+template bool launch_theta_tabx<float>(hipStream_t, const SketchArgs&, int64_t, float*);
+template bool launch_theta_tabx<double>(hipStream_t, const SketchArgs&, int64_t, double*);
 
 bool launch_dgemm(hipStream_t st, bool transA, int M, int N, int K, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double* C, int64_t ldc) {

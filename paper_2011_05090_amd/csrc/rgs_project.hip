@@ -148,6 +148,10 @@ bool launch_project(hipStream_t st, const TW* w, TQ* Q, int64_t ldq, int64_t n, 
             hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_TABLE, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
                                coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
             break;
+        case SK_TABX:
+            hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_TABX, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
+                               coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);
+            break;
         default:
             hipLaunchKernelGGL((k_project<TW, TQ, TW, SK_IDENT, DEFER>), dim3(nblk), thr, 0, st, w, Q, ldq, n, j,
                                coef, invr, normalize_last, do_sketch, vec_ok, sk, partials, status);

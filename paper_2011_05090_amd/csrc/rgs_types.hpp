@@ -10,7 +10,10 @@ namespace rgs {
 
 // SK_TABLE: the Gaussian sketch with bf16 entries, read from a table made by
 // k_theta_table (entry (j, l) at ((l / 8) k + j) 8 + l % 8, unscaled).
-enum { SK_GAUSS = 0, SK_SRHT = 1, SK_IDENT = 2, SK_RADEM = 3, SK_TABLE = 4 };
+// SK_TABX: the Gaussian sketch itself, its entries drawn once into a table of
+// the working type T (float or double; same layout) by k_theta_tabx and read
+// back by every application instead of being drawn again.
+enum { SK_GAUSS = 0, SK_SRHT = 1, SK_IDENT = 2, SK_RADEM = 3, SK_TABLE = 4, SK_TABX = 5 };
 enum { kStatusOk = 0, kStatusBreakdown = 1, kStatusNonfinite = 2 };
 
 // Everything a kernel needs to regenerate Theta (k x n) on the fly.
@@ -22,6 +25,7 @@ struct SketchArgs {
     const uint32_t* signs;  // SRHT: bit table of D
     const int* rows;        // SRHT: sampled rows of H_s
     const uint16_t* table;  // SK_TABLE: bf16 entries
+    const void* tabx;       // SK_TABX: the entries in the working type
 };
 
 // The 7-point operator: (A u)_l = c[0] u_l + c[1] u_{x-1} + c[2] u_{x+1} + c[3] u_{y-1}

@@ -1,0 +1,202 @@
+"""GPU parity of the exact table of the Gaussian sketch (RGS_FLAG_THETA_EXACT).
+
+The table holds, in the working precision, the very entries that the drawn
+Gaussian sketch computes (Sec. 2.1: Theta is fixed by its seed), so every
+result of a call with the flag equals the same call without it up to the
+order of the floating-point sums:
+
+* Theta X (fp64, fp32, fp32u; one and many columns, ragged n, k across two
+  workgroup row ranges) against the drawn path and the oracle's Gaussian;
+* the factorisation (split and fused step-1 paths, fp64 / fp32 / bf16q /
+  fp32u) against the drawn path, and in fp64 against the oracle;
+* the certificate (Phi: the drawn Gaussian sketch);
+* RGMRES (fresh Theta per cycle and reuse_theta): the same iteration count
+  and residual history as the drawn path, and the oracle's in fp64;
+* the flag's rejections (other sketches, with the bf16 table, on the calls
+  that do not take it).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gmres as ogm, metrics, rgs as orgs, sketch as osk, stencil as ost
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _rgs():
+    import paper_2011_05090_amd as rgs
+    return rgs
+
+
+def to_dev(A, dtype):
+    A = np.asarray(A)
+    if A.ndim == 1:
+        return torch.from_numpy(np.ascontiguousarray(A)).to(dtype=dtype, device="cuda")
+    return torch.from_numpy(np.ascontiguousarray(A.T)).to(dtype=dtype, device="cuda").t()
+
+
+def to_host(t):
+    t = t.detach().cpu()
+    return (t.float() if t.dtype == torch.bfloat16 else t).numpy().astype(np.float64)
+
+
+def _wdtype(prec):
+    return torch.float64 if prec == "fp64" else torch.float32
+
+
+def _qdtype(prec):
+    return {"fp64": torch.float64, "bf16q": torch.bfloat16}.get(prec, torch.float32)
+
+
+def run_qr(h, W, k, prec, flags=0):
+    rgs = _rgs()
+    n, m = W.shape
+    Q, R, S = rgs.colmajor(n, m, _qdtype(prec)), rgs.colmajor(m, m, torch.float64), rgs.colmajor(k, m, torch.float64)
+    d = rgs.qr_desc(n, m, k, sketch="gaussian", prec=prec, flags=flags)
+    rep = rgs.rgs_qr(h, d, to_dev(W, _wdtype(prec)), Q, R, S)
+    torch.cuda.synchronize()
+    return rep, to_host(Q), to_host(R), to_host(S)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32u"])
+@pytest.mark.parametrize("ncols,k", [(1, 96), (37, 96), (37, 300)])
+def test_exact_sketch_apply_matches_drawn(gpu_handle, prec, ncols, k):
+    rgs = _rgs()
+    n = 9000 + 5
+    X = np.random.Generator(np.random.PCG64(5)).standard_normal((n, ncols))
+    if prec != "fp64":
+        X = X.astype(np.float32).astype(np.float64)
+    out = []
+    for flags in (0, rgs.FLAG_THETA_EXACT):
+        d = rgs.qr_desc(n, 1, k, sketch="gaussian", prec=prec, seed=9, sketch_id=3, instance=1, flags=flags)
+        Y = rgs.colmajor(k, ncols, torch.float64)
+        rgs.rgs_sketch_apply(gpu_handle, d, to_dev(X, _wdtype(prec)), Y)
+        torch.cuda.synchronize()
+        out.append(to_host(Y))
+    drawn, exact = out
+    scale = np.abs(drawn).max()
+    # same entries, sums in another order: fp64 (or float32 for fp32u) rounding only
+    tol = {"fp64": 1e-14, "fp32": 1e-14, "fp32u": 2e-6}[prec]
+    assert np.abs(exact - drawn).max() <= tol * scale
+    if prec == "fp64":
+        ref = osk.make("gaussian", n, k, seed=9, sketch_id=3, instance=1).apply(X)
+        assert np.abs(exact - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,m,k", [(16384 + 77, 40, 256), ((1 << 20) + 333, 6, 64)])
+def test_exact_fp64_qr_matches_drawn_and_oracle(gpu_handle, n, m, k):
+    """Split small-n step-1 path, and the fused projection path above 2^20 rows."""
+    rgs = _rgs()
+    W = synth.svd_matrix(n, m, 1e-2, tag=81)
+    rep0, Q0, R0, S0 = run_qr(gpu_handle, W, k, "fp64")
+    rep, Q, R, S = run_qr(gpu_handle, W, k, "fp64", flags=rgs.FLAG_THETA_EXACT)
+    assert rep.status == 0 and rep0.status == 0
+    assert rel(R, R0) <= 1e-13 and rel(S, S0) <= 1e-13
+    assert np.abs(Q - Q0).max() <= 1e-13 * np.abs(Q0).max()
+    ref = orgs.rgs_qr(W, osk.make("gaussian", n, k, seed=42))
+    assert rel(R, ref["R"]) <= 1e-12 and rel(S, ref["S"]) <= 1e-12
+    assert metrics.backward_error(W, Q, R) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp32u", 1e-4), ("bf16q", 1e-2)])
+def test_exact_low_precision_qr_matches_drawn(gpu_handle, prec, tol):
+    rgs = _rgs()
+    n, m, k = 4096 * 5 + 100, 48, 192
+    W = synth.svd_matrix(n, m, 1e-3, tag=82).astype(np.float32).astype(np.float64)
+    rep0, Q0, R0, S0 = run_qr(gpu_handle, W, k, prec)
+    rep, Q, R, S = run_qr(gpu_handle, W, k, prec, flags=rgs.FLAG_THETA_EXACT)
+    assert rep.status == 0 and rep0.status == 0
+    assert rel(R, R0) <= tol and rel(S, S0) <= tol
+    assert metrics.backward_error(W, Q, R) <= (5e-3 if prec == "bf16q" else 1e-5)
+
+
+def test_exact_certificate_matches_drawn(gpu_handle):
+    rgs = _rgs()
+    n, m, k = 3 * 8192 + 123, 30, 192
+    W = synth.svd_matrix(n, m, 1e-2, tag=83)
+    rep0, *_ = run_qr(gpu_handle, W, k, "fp64", flags=rgs.FLAG_CERTIFY)
+    rep, *_ = run_qr(gpu_handle, W, k, "fp64", flags=rgs.FLAG_CERTIFY | rgs.FLAG_THETA_EXACT)
+    for a, b in ((rep.cert_smin_q, rep0.cert_smin_q), (rep.cert_smax_q, rep0.cert_smax_q),
+                 (rep.cert_smin_w, rep0.cert_smin_w), (rep.cert_smax_w, rep0.cert_smax_w),
+                 (rep.cert_cond_phi_q, rep0.cert_cond_phi_q)):
+        assert np.isfinite(a) and abs(a - b) <= 1e-10 * abs(b)
+
+
+@pytest.mark.parametrize("prec,reuse", [("fp64", False), ("fp32", False), ("fp32", True), ("bf16q", False)])
+def test_exact_rgmres_matches_drawn(gpu_handle, prec, reuse):
+    rgs = _rgs()
+    # one Theta for every cycle: each cycle minimises the same sketched residual, so the
+    # restarted iteration stalls once that one is small (here near 9.5e-7 while the true
+    # residual stays above 1e-6: the oracle does the same); 1e-5 is reached in 93 steps
+    N, Pe, restart, k, tol = 24, 50.0, 20, 96, (1e-5 if reuse else 1e-6)
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=84)
+    A = rgs.stencil7(dims, coeffs)
+    runs = []
+    for flags in (0, rgs.FLAG_THETA_EXACT):
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        rep, hist = rgs.rgs_gmres(gpu_handle, A,
+                                  rgs.gmres_desc(restart, k, tol, max_iters=3000, sketch="gaussian", prec=prec,
+                                                 reuse_theta=reuse, flags=flags),
+                                  to_dev(b, torch.float64), x, res_hist=10000)
+        torch.cuda.synchronize()
+        assert rep.status == 0
+        r = b - ost.apply(x.cpu().numpy(), dims, coeffs, np.float64)
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
+        runs.append((rep, np.asarray(hist)))
+    (rep0, h0), (rep1, h1) = runs
+    assert abs(rep1.iters - rep0.iters) <= (0 if prec == "fp64" else 1)
+    L = min(len(h0), len(h1), restart)
+    np.testing.assert_allclose(h1[:L], h0[:L], rtol={"fp64": 1e-10, "fp32": 1e-4, "bf16q": 1e-2}[prec])
+    if prec == "fp64":
+        ref = ogm.rgmres(lambda u, dt: ost.apply(u, dims, coeffs, dt), b,
+                         lambda c: osk.make("gaussian", n, k, seed=42, sketch_id=2 + c),
+                         restart=restart, tol=tol, precision="fp64", max_iters=3000)
+        assert ref["converged"] and abs(rep1.iters - ref["iters"]) <= 2
+        L = min(len(h1), len(ref["hist"]), restart)
+        np.testing.assert_allclose(h1[:L], ref["hist"][:L], rtol=1e-8)
+
+
+def test_exact_flag_rejections(gpu_handle):
+    rgs = _rgs()
+    n, m, k = 1000, 4, 32
+    W = synth.svd_matrix(n, m, 1e-1, tag=85)
+    outs = lambda: (rgs.colmajor(n, m, torch.float64), rgs.colmajor(m, m, torch.float64),
+                    rgs.colmajor(k, m, torch.float64))
+
+    def expect_einval(f):
+        with pytest.raises(rgs.RgsError) as e:
+            f()
+        assert e.value.status == rgs.RGS_EINVAL
+
+    Wd = to_dev(W, torch.float64)
+    for sk in ("srht", "rademacher", "identity"):
+        d = rgs.qr_desc(n, m, k, sketch=sk, prec="fp64", flags=rgs.FLAG_THETA_EXACT)
+        expect_einval(lambda: rgs.rgs_qr(gpu_handle, d, Wd, *outs()))
+    both = rgs.FLAG_THETA_EXACT | rgs.FLAG_THETA_BF16
+    d = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp64", flags=both)
+    expect_einval(lambda: rgs.rgs_qr(gpu_handle, d, Wd, *outs()))
+    expect_einval(lambda: rgs.rgs_sketch_apply(gpu_handle, d, Wd, rgs.colmajor(k, m, torch.float64)))
+    d = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp64", flags=rgs.FLAG_THETA_EXACT)
+    expect_einval(lambda: rgs.rgs_qr_noalloc(gpu_handle, d, Wd, *outs()))
+    expect_einval(lambda: rgs.rgs_sketch_materialize(gpu_handle, d, 0, k, 0, n, rgs.colmajor(k, n, torch.float64)))
+    items = [(to_dev(W, torch.float32), rgs.colmajor(n, m, torch.float32), rgs.colmajor(m, m, torch.float64),
+              rgs.colmajor(k, m, torch.float64), k)]
+    expect_einval(lambda: rgs.rgs_qr_batched(gpu_handle, items, sketch="gaussian", flags=rgs.FLAG_THETA_EXACT))
+    N = 8
+    dims, coeffs = synth.convdiff_coeffs(N, 10.0)
+    b = to_dev(synth.rhs(N ** 3, tag=86), torch.float64)
+    x = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+    for sk, fl in (("srht", rgs.FLAG_THETA_EXACT), ("gaussian", both)):
+        g = rgs.gmres_desc(10, 40, 1e-6, sketch=sk, prec="fp64", flags=fl)
+        expect_einval(lambda: rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs), g, b, x))
+    g = rgs.gmres_desc(10, 40, 1e-6, sketch="gaussian", prec="fp64", flags=rgs.FLAG_THETA_EXACT)
+    expect_einval(lambda: rgs.rgs_gmres_batched(gpu_handle, [(rgs.stencil7(dims, coeffs), b, x)], g))
