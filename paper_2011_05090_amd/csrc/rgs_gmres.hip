@@ -82,49 +82,68 @@ __device__ __forceinline__ T stencil_row(const Grid3& g, int64_t l, const Load& 
     return acc;
 }
 
+// p + i; with a 32-bit index, as a 32-bit byte offset from p (the caller has
+// checked that the column spans less than 4 GiB), which the loads take as one
+// register instead of a 64-bit address.
+template <typename TQ, typename I>
+__device__ __forceinline__ const TQ* at(const TQ* p, I i) {
+    if constexpr (std::is_same<I, uint32_t>::value)
+        return reinterpret_cast<const TQ*>(reinterpret_cast<const char*>(p) + i * (uint32_t)sizeof(TQ));
+    else
+        return p + i;
+}
+
 // Four stored values at rows l .. l+3 (l % 4 == 0, 16-byte aligned fp32 /
 // 8-byte bf16 / 2 x 16-byte fp64 vector loads), widened to double.
-__device__ __forceinline__ void ld4_raw(const float* __restrict__ p, int64_t l, double o[4]) {
-    const f32x4 t = *reinterpret_cast<const f32x4*>(p + l);
+template <typename I>
+__device__ __forceinline__ void ld4_raw(const float* __restrict__ p, I l, double o[4]) {
+    const f32x4 t = *reinterpret_cast<const f32x4*>(at(p, l));
     o[0] = t.x;
     o[1] = t.y;
     o[2] = t.z;
     o[3] = t.w;
 }
-__device__ __forceinline__ void ld4_raw(const double* __restrict__ p, int64_t l, double o[4]) {
-    typedef double f64x2 __attribute__((ext_vector_type(2)));
-    const f64x2 a = *reinterpret_cast<const f64x2*>(p + l), b = *reinterpret_cast<const f64x2*>(p + l + 2);
+template <typename I>
+__device__ __forceinline__ void ld4_raw(const double* __restrict__ p, I l, double o[4]) {
+    const f64x2 a = *reinterpret_cast<const f64x2*>(at(p, l)), b = *reinterpret_cast<const f64x2*>(at(p, l + 2));
     o[0] = a.x;
     o[1] = a.y;
     o[2] = b.x;
     o[3] = b.y;
 }
-__device__ __forceinline__ void ld4_raw(const bf16* __restrict__ p, int64_t l, double o[4]) {
-    const u32x2 t = *reinterpret_cast<const u32x2*>(p + l);
+template <typename I>
+__device__ __forceinline__ void ld4_raw(const bf16* __restrict__ p, I l, double o[4]) {
+    const u32x2 t = *reinterpret_cast<const u32x2*>(at(p, l));
     o[0] = __uint_as_float(t.x << 16);
     o[1] = __uint_as_float(t.x & 0xFFFF0000u);
     o[2] = __uint_as_float(t.y << 16);
     o[3] = __uint_as_float(t.y & 0xFFFF0000u);
 }
 
-// Rows l0 .. l0+3 (l0 % 4 == 0) of w = A u, u = (T)(stored * ir) when scale,
+// Rows l0 .. l0+3 (l0 % 4 == 0) of w = A u, u = (T)(stored * ir) when SCALE,
 // else (T)stored; out[r] = 0 past n, cen[r] = u at row l0 + r.  Same per-row
 // association as stencil_row, so the same bits.  With vec (nx % 4 == 0 and an
 // aligned column) the four rows share y and z: the centre and each of the
 // four y/z neighbour planes are one vector load, plus the two x neighbours
-// outside the group.  Otherwise the rows are stepped from one coordinate
-// division and read element by element.
-template <typename T, typename TQ>
-__device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ qs, bool scale, double ir,
-                                         bool vec, int64_t l0, int64_t n, T out[4], T cen[4]) {
+// outside the group, addressed by 32-bit offsets when O32 (n sizeof(TQ) <
+// 2^32).  Otherwise the rows are stepped from one coordinate division and
+// read element by element.
+template <typename T, typename TQ, bool SCALE, bool O32>
+__device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ qs, double ir, bool vec, int64_t l0,
+                                         int64_t n, T out[4], T cen[4]) {
     const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz, nxy = nx * ny;
     const uint32_t lu = (uint32_t)l0;
     uint32_t z = lu / nxy;
     const uint32_t rem = lu - z * nxy;
     uint32_t y = rem / nx;
     uint32_t x = rem - y * nx;
-    auto cv = [&](double d) -> T { return scale ? (T)(d * ir) : (T)d; };
-    auto ld1 = [&](int64_t idx) -> T { return cv(to_double(qs[idx])); };
+    auto cv = [&](double d) -> T {
+        if constexpr (SCALE)
+            return (T)(d * ir);
+        else
+            return (T)d;
+    };
+    auto ld1 = [&](auto idx) -> T { return cv(to_double(*at(qs, idx))); };
     // results in local arrays with one store sequence at the end: stores
     // through out/cen on several paths keep the caller's array out of registers
     T ro[4], rc[4];
@@ -136,23 +155,27 @@ __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ 
             // every load reads a valid address (a missing neighbour reads the
             // centre group) and the value is dropped afterwards: loads under a
             // condition would each be a branch and a wait
+            using I = typename std::conditional<O32, uint32_t, int64_t>::type;
+            const I lc = (I)l0;
             double a[4], am[4], ap[4], bm[4], bp[4];
             T u[4], ym[4], yp[4], zm[4], zp[4];
             const bool hxm = x > 0, hxp = x + 4 < nx, hym = y > 0, hyp = y + 1 < ny, hzm = z > 0, hzp = z + 1 < nz;
-            ld4_raw(qs, l0, a);
-            ld4_raw(qs, hym ? l0 - nx : l0, am);
-            ld4_raw(qs, hyp ? l0 + nx : l0, ap);
-            ld4_raw(qs, hzm ? l0 - (int64_t)nxy : l0, bm);
-            ld4_raw(qs, hzp ? l0 + (int64_t)nxy : l0, bp);
-            const T xm0 = ld1(hxm ? l0 - 1 : l0), xp0 = ld1(hxp ? l0 + 4 : l0);
+            ld4_raw(qs, lc, a);
+            ld4_raw(qs, hym ? lc - (I)nx : lc, am);
+            ld4_raw(qs, hyp ? lc + (I)nx : lc, ap);
+            ld4_raw(qs, hzm ? lc - (I)nxy : lc, bm);
+            ld4_raw(qs, hzp ? lc + (I)nxy : lc, bp);
+            const T xm0 = ld1(hxm ? lc - 1 : lc), xp0 = ld1(hxp ? lc + 4 : lc);
             const T xm = hxm ? xm0 : T(0), xp = hxp ? xp0 : T(0);
+            // a missing y / z neighbour's value (read from the centre) is dropped by
+            // the term's own condition below
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 u[r] = cv(a[r]);
-                ym[r] = hym ? cv(am[r]) : T(0);
-                yp[r] = hyp ? cv(ap[r]) : T(0);
-                zm[r] = hzm ? cv(bm[r]) : T(0);
-                zp[r] = hzp ? cv(bp[r]) : T(0);
+                ym[r] = cv(am[r]);
+                yp[r] = cv(ap[r]);
+                zm[r] = cv(bm[r]);
+                zp[r] = cv(bp[r]);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -260,12 +283,25 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
     const double ir = invr ? invr[0] : 1.0;
     const bool vec = stencil_vec_ok(g, qs, w);
     T v[16];
+    auto pass = [&](auto scale, auto o32) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
-        T c[4];
-        stencil4<T, TQ>(g, qs, invr != nullptr, ir, vec, r0, n, v + 4 * e, c);
-        st4<T>(w, r0, n, vec, v + 4 * e);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
+            T c[4];
+            stencil4<T, TQ, decltype(scale)::value, decltype(o32)::value>(g, qs, ir, vec, r0, n, v + 4 * e, c);
+            st4<T>(w, r0, n, vec, v + 4 * e);
+        }
+    };
+    const bool o32 = (uint64_t)n * sizeof(TQ) < ((uint64_t)1 << 32);
+    if (invr) {
+        if (o32)
+            pass(std::true_type{}, std::true_type{});
+        else
+            pass(std::true_type{}, std::false_type{});
+    } else if (o32) {
+        pass(std::false_type{}, std::true_type{});
+    } else {
+        pass(std::false_type{}, std::false_type{});
     }
     if (!do_sketch) return;
     if constexpr (SK == SK_IDENT) {
@@ -309,19 +345,25 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
     constexpr int NW = kProjWaves, NT = NW * kWave, RB = NW * kTile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool vec = stencil_vec_ok(g, xs, t_out);
+    auto pass = [&](auto o32) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int local = wave * kTile + 256 * e + 4 * lane;
-        const int64_t r0 = blk * RB + local;
-        T tv[4], xv[4];
-        stencil4<T, TQ>(g, xs, false, 1.0, vec, r0, n, tv, xv);
-        st4<T>(t_out, r0, n, vec, tv);
+        for (int e = 0; e < 4; ++e) {
+            const int local = wave * kTile + 256 * e + 4 * lane;
+            const int64_t r0 = blk * RB + local;
+            T tv[4], xv[4];
+            stencil4<T, TQ, false, decltype(o32)::value>(g, xs, 1.0, vec, r0, n, tv, xv);
+            st4<T>(t_out, r0, n, vec, tv);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            lds[local + r] = xv[r];
-            lds[RB + local + r] = tv[r];
+            for (int r = 0; r < 4; ++r) {
+                lds[local + r] = xv[r];
+                lds[RB + local + r] = tv[r];
+            }
         }
-    }
+    };
+    if ((uint64_t)n * sizeof(TQ) < ((uint64_t)1 << 32))
+        pass(std::true_type{});
+    else
+        pass(std::false_type{});
     __syncthreads();
     const int kpt = (sk.k + NT - 1) / NT;
     T ax[kKptMax], at[kKptMax];
@@ -416,12 +458,18 @@ __device__ __forceinline__ void stencil_dual_sk_body(const TQ* __restrict__ xs, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool vec = stencil_vec_ok(g, xs, t_out);
     T xv[16], tv[16];
+    auto pass = [&](auto o32) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
-        stencil4<T, TQ>(g, xs, false, 1.0, vec, r0, n, tv + 4 * e, xv + 4 * e);
-        st4<T>(t_out, r0, n, vec, tv + 4 * e);
-    }
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
+            stencil4<T, TQ, false, decltype(o32)::value>(g, xs, 1.0, vec, r0, n, tv + 4 * e, xv + 4 * e);
+            st4<T>(t_out, r0, n, vec, tv + 4 * e);
+        }
+    };
+    if ((uint64_t)n * sizeof(TQ) < ((uint64_t)1 << 32))
+        pass(std::true_type{});
+    else
+        pass(std::false_type{});
     T ax[kKptMax], at[kKptMax];
 #pragma unroll
     for (int u = 0; u < kKptMax; ++u) ax[u] = at[u] = T(0);
@@ -585,7 +633,9 @@ __device__ __forceinline__ void xupdate_body(double* __restrict__ x, const TQ* _
 // Single-system kernels
 // ---------------------------------------------------------------------------
 template <typename TQ, typename T, typename PT, int SK>
-__global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_sketch(
+// (at most 80 registers, 6 waves per SIMD: 28.3 instead of 30.6 us per fp32
+// launch at 192^3; the dual kernels are faster without the cap)
+__global__ __launch_bounds__(kProjWaves * kWave, 6) void k_stencil_sketch(
     const TQ* __restrict__ qs, const double* __restrict__ invr, Grid3 g, int64_t n, T* __restrict__ w,
     int do_sketch, SketchArgs sk, PT* __restrict__ partials, const int* __restrict__ status) {
     __shared__ T lds[kProjWaves * kTile];
