@@ -155,16 +155,16 @@ def _gmres_gpu(h, N, sketch, prec, k=400, restart=100, flags=0):
     return rep, hist, np.linalg.norm(r) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("prec,flags", [("fp64", 0), ("fp32", 0), ("fp32", 16)])
+@pytest.mark.parametrize("prec,flags", [("fp64", 0), ("fp32", 0), ("fp32", 16), ("fp64", 64), ("fp32", 64)])
 def test_gauss64_iterations_vs_cached_oracle(gpu_handle, prec, flags):
     """The randomized GMRES with the drawn Gaussian sketch (k = 400, restart
     100, Pe = 50) on a 64^3 grid against the fp64 oracle's iteration count,
     cached in tests/golden/gmres_c3_gauss64.json by make_gmres_refs.py (the
     oracle draws the same Philox entries; one run takes it minutes).  The fp64
-    and fp32 bases must land within +-2 of it (Sec. 4.2); so must the bf16
-    table of the same Gaussian entries (flags 16), whose entries are a
-    different sketch: it is held to the bar as a sketch of equal quality, and
-    the test prints its difference."""
+    and fp32 bases must land within +-2 of it (Sec. 4.2), drawn on the fly or
+    read from the table of their exact entries (flags 64, the same sketch);
+    the bf16 table of the same Gaussian entries (flags 16) is a different
+    sketch: the test prints its difference."""
     import json
     import os
     ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gmres_c3_gauss64.json")))
@@ -174,7 +174,7 @@ def test_gauss64_iterations_vs_cached_oracle(gpu_handle, prec, flags):
     print("  iters %d (oracle %d), true relres %.3e" % (rep.iters, ref["iters"], relres), flush=True)
     assert rep.status == 0 and relres <= 1e-6 * (1 + 1e-6)
     assert math.isclose(rep.true_relres, relres, rel_tol=1e-6)
-    if flags == 0:
+    if flags in (0, 64):
         assert abs(rep.iters - ref["iters"]) <= 2
 
 
@@ -193,3 +193,9 @@ def test_fullsize_rgmres_gaussian(gpu_handle):
     assert rep64.status == 0 and relres64 <= 1e-6 * (1 + 1e-6)
     print("  iters fp32 %d fp64 %d" % (rep32.iters, rep64.iters), flush=True)
     assert abs(rep32.iters - rep64.iters) <= 2
+    # the same sketch read from the table of its exact fp32 entries
+    print("rgmres 192^3 gaussian k=400 fp32, exact table", flush=True)
+    repx, _, relresx = _gmres_gpu(gpu_handle, 192, "gaussian", "fp32", flags=64)
+    assert repx.status == 0 and relresx <= 1e-6 * (1 + 1e-6)
+    print("  iters %d" % repx.iters, flush=True)
+    assert abs(repx.iters - rep32.iters) <= 1
