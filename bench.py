@@ -441,7 +441,8 @@ def rademacher_leg(rgs, torch, synth, h, n=1 << 22, m=512, k=2048, steps=1, warm
     return out
 
 
-def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian", "gaussian_bf16_table"), steps=2,
+def batched_qr_leg(rgs, torch, synth, h, batch=2048,
+                   sketches=("srht", "gaussian", "gaussian_exact_table", "gaussian_bf16_table"), steps=2,
                    warmup=1, gaussian_batch=2048, graph=True):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
     m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and bf16-stored Q, all in
@@ -449,7 +450,9 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
     factorisations share one master Gaussian matrix, entries drawn in the
     products) and with that master matrix's bf16 entries made once per call
     into a table that the products read through bf16 matrix cores
-    (RGS_FLAG_THETA_BF16).  With ``graph`` each sketch is timed again with
+    (RGS_FLAG_THETA_BF16), and with its exact fp32 entries made once per call
+    into a table that the fp32 products read instead of drawing them
+    (RGS_FLAG_THETA_EXACT: the drawn call's bits).  With ``graph`` each sketch is timed again with
     the calls replayed from captured graphs (RGS_FLAG_GRAPH)."""
     ns, ms_ = synth.batch_qr_sizes(batch)
     items = []
@@ -471,7 +474,7 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048, sketches=("srht", "gaussian
         its = items if sketch == "srht" else items[:gaussian_batch]
         B = sum(batched_qr_bytes(W.shape[0], W.shape[1]) for W, *_ in its)
         lib_sketch = "srht" if sketch == "srht" else "gaussian"
-        flags = rgs.FLAG_THETA_BF16 if sketch == "gaussian_bf16_table" else 0
+        flags = {"gaussian_bf16_table": rgs.FLAG_THETA_BF16, "gaussian_exact_table": rgs.FLAG_THETA_EXACT}.get(sketch, 0)
         for _ in range(warmup):
             rgs.rgs_qr_batched(h, its, sketch=lib_sketch, prec="bf16q", flags=flags)
         torch.cuda.synchronize()
@@ -782,7 +785,8 @@ def main():
                     help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
                          "databases (no GPU needed) and exit")
     ap.add_argument("--sketches", default=None,
-                    help="with --only batched-qr: comma-separated legs (srht, gaussian, gaussian_bf16_table)")
+                    help="with --only batched-qr: comma-separated legs (srht, gaussian, gaussian_exact_table, "
+                         "gaussian_bf16_table)")
     ap.add_argument("--leg-steps", type=int, default=None, help="with --only: timed calls per leg")
     ap.add_argument("--leg-warmup", type=int, default=None, help="with --only: untimed calls per leg")
     ap.add_argument("--no-graph", action="store_true",

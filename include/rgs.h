@@ -131,8 +131,9 @@ typedef enum {
                                     projection no longer sketches; w_{i+1} = t / r_ii is applied on
                                     load.  Equal to Algorithm 3 in exact arithmetic.  The GAUSSIAN
                                     sketch always takes this step (its two sketches share draws). */
-#define RGS_FLAG_THETA_EXACT 64u /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_sketch_apply; EINVAL with
-                                    RGS_FLAG_THETA_BF16 and on the other calls): the same sketch
+#define RGS_FLAG_THETA_EXACT 64u /* GAUSSIAN only (rgs_qr, rgs_gmres, rgs_sketch_apply; rgs_qr_batched_ex:
+                                    see there; EINVAL with RGS_FLAG_THETA_BF16 and on the other
+                                    calls): the same sketch
                                     (Sec. 2.1), its entries made once per Theta -- by the Box-Muller
                                     of the working precision, as every drawn sketch makes them --
                                     into a table of sizeof(T) k ceil(n/8)*8 bytes (T: double for
@@ -185,8 +186,7 @@ typedef struct {
     int32_t prec;       /* rgs_precision of the basis, mat-vec and projection */
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
     uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16, RGS_FLAG_THETA_EXACT, RGS_FLAG_LAG and
-                           RGS_FLAG_CERTIFY are honoured,
-                           other bits ignored;
+                           RGS_FLAG_CERTIFY (other bits: EINVAL);
                            rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
     uint32_t ls_sweeps; /* rgs_gmres: step 2 of every Arnoldi step (Alg. 3 on RGS, Sec. 2.3's remark on the
                            least-squares solver): 0 = Householder QR of S; 1..8 = that many Richardson
@@ -345,6 +345,12 @@ rgs_status rgs_qr_batched(rgs_handle *h, int64_t batch, const rgs_qr_item *items
  *     bf16 matrix-core instructions (exact products: fp32 columns are split
  *     into three bf16 parts, bf16-basis columns are exact; fp32 accumulation)
  *     instead of drawing the entries;
+ *   RGS_FLAG_THETA_EXACT (GAUSSIAN sketch only, not with THETA_BF16) -- the
+ *     master matrix's fp32 entries, exactly those the drawn products make,
+ *     made once per call into a table of 4 max(k_b) (32 ceil(max(n_b)/32) + 32)
+ *     bytes of the handle's scratch and read by the fp32 matrix-core products
+ *     of steps 1 and 4 instead of being drawn: results bitwise those of the
+ *     call without the flag;
  *   RGS_FLAG_GRAPH -- each of the two streams' kernel sequences (every column
  *     of its share of the batch) is captured once as a HIP graph, kept in the
  *     handle, and replayed on later calls with the same items (sizes,
@@ -354,7 +360,7 @@ rgs_status rgs_qr_batched(rgs_handle *h, int64_t batch, const rgs_qr_item *items
  *     run.  With the GAUSSIAN sketch, a call whose product schedule is not yet
  *     tuned for this batch (the first, unless rgs_set_tuning forces one) runs
  *     eagerly and tunes it.  Results are bitwise those of an eager call.
- * EINVAL for any other flag, or THETA_BF16 with another sketch. */
+ * EINVAL for any other flag, THETA_BF16 or THETA_EXACT with another sketch, or both. */
 rgs_status rgs_qr_batched_ex(rgs_handle *h, int64_t batch, const rgs_qr_item *items, int32_t sketch,
                              int32_t prec, uint64_t seed, uint32_t sketch_id, uint32_t flags,
                              int32_t *item_status, int64_t *failed_column, rgs_report *rep);

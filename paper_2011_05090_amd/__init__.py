@@ -268,8 +268,8 @@ def rgs_qr_noalloc(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINI
 def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id=0,
                    allow=(RGS_EBREAKDOWN, RGS_ENONFINITE), flags=0):
     """A batch of factorisations; items = list of (W, Q, R, S, k) device tensors.
-    flags: 0 (rgs_qr_batched), or FLAG_THETA_BF16 (Gaussian sketch only) and/or FLAG_GRAPH
-    (rgs_qr_batched_ex).
+    flags: 0 (rgs_qr_batched), or FLAG_THETA_BF16 or FLAG_THETA_EXACT (Gaussian sketch only)
+    and/or FLAG_GRAPH (rgs_qr_batched_ex).
     Returns (Report, per-item statuses, per-item failed columns)."""
     import torch
     dw, dq = _dtypes(PREC[prec])

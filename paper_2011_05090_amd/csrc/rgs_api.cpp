@@ -1462,20 +1462,23 @@ struct QrGroupLauncher {
                   *d_red = nullptr;
     GemmUnit *d_units = nullptr, *d_tune = nullptr;
     const int2* d_cols = nullptr;
-    // RGS_FLAG_THETA_BF16: the master matrix's bf16 entries (tk rows, tgroups groups of 8 columns)
+    // RGS_FLAG_THETA_BF16: the master matrix's bf16 entries (tk rows, tgroups groups of 8 columns);
+    // RGS_FLAG_THETA_EXACT: its exact fp32 entries (tk rows, SK_TABX layout)
     const uint16_t* table = nullptr;
+    const float* tabx = nullptr;
     int tk = 0;
     int64_t tgroups = 0;
 
     QrGroupLauncher(rgs_handle* h_, QrGroup& g_, int sk, char* A_, hipStream_t s_)
         : h(h_), g(g_), sk_kind(sk), A(A_), s(s_) {}
 
-    // one product of the Gaussian sketch: drawn entries (fp32 MFMA) or table entries (bf16 MFMA)
+    // one product of the Gaussian sketch: drawn or exact-table entries (fp32 MFMA) or bf16 table entries
+    // (bf16 MFMA)
     template <typename TB, bool STEP4>
     bool product(const GemmUnit* units, int nunits, int rows, int tile) {
         if (table)
             return launch_batch_table_gemm<TB, STEP4>(s, itd, units, nunits, d_cols, rows, tile, table, tk, tgroups);
-        return launch_batch_gauss_gemm<TB, STEP4>(s, itd, units, nunits, d_cols, rows, tile);
+        return launch_batch_gauss_gemm<TB, STEP4>(s, itd, units, nunits, d_cols, rows, tile, tabx, tk);
     }
 
     bool upload_schedule(int sc) {
@@ -1603,7 +1606,7 @@ struct QrGroupLauncher {
 
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
-                          uint32_t sid, bool use_table, bool want_graph, int32_t* item_status,
+                          uint32_t sid, bool use_table, bool use_tabx, bool want_graph, int32_t* item_status,
                           int64_t* failed_column, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<int64_t> order((size_t)batch);
@@ -1628,11 +1631,24 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
         tgroups = 2 * ((nmax + 15) / 16);
         o_table = c.take<uint16_t>((size_t)tgroups * 8 * (size_t)tk);
     }
+    // RGS_FLAG_THETA_EXACT: the master matrix's fp32 entries, rows 0 .. max k - 1,
+    // columns to the last 4-row draw any product reads (a 32-row super-step past n)
+    int64_t tcols = 0;
+    if (use_tabx) {
+        int64_t nmax = 0;
+        for (int64_t b = 0; b < batch; ++b) {
+            tk = std::max<int>(tk, (int)items[b].k);
+            nmax = std::max<int64_t>(nmax, items[b].n);
+        }
+        tcols = (nmax + 31) / 32 * 32 + 32;
+        o_table = c.take<float>((size_t)tcols * (size_t)tk);
+    }
     // the batch signature of the tuning cache: precision, sketch entries, shares and every (n, m, k)
     uint64_t sig = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
     mix((uint64_t)DEFER);
     mix((uint64_t)use_table);
+    mix((uint64_t)use_tabx);
     mix((uint64_t)ng);
     for (int64_t q = 0; q < batch; ++q) {
         mix((uint64_t)items[order[q]].n);
@@ -1660,6 +1676,10 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
             run.back().tk = tk;
             run.back().tgroups = tgroups;
         }
+        if (use_tabx) {
+            run.back().tabx = reinterpret_cast<const float*>(A + o_table);
+            run.back().tk = tk;
+        }
     }
     // RGS_FLAG_GRAPH: every share's kernel sequence (from its initialisation
     // to the closing scale pass) is captured once as a graph for this batch
@@ -1674,6 +1694,9 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (use_table && !launch_theta_table(h->stream, make_sketch(SK_GAUSS, tk, seed, sid, 0u), tgroups * 8,
                                          reinterpret_cast<uint16_t*>(A + o_table)))
         return RGS_EDEVICE;
+    if (use_tabx && !launch_theta_tabx<float>(h->stream, make_sketch(SK_GAUSS, tk, seed, sid, 0u), tcols,
+                                              reinterpret_cast<float*>(A + o_table)))
+        return RGS_EDEVICE;
     static_assert(kQrShares == 2, "the shares past the first run on the one auxiliary stream");
     hipStream_t ss[kQrShares] = {h->stream, h->stream};
     if (ng > 1) {
@@ -1686,7 +1709,8 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     rgs_status est = RGS_OK;
     if (use_graph) {
         std::vector<uint64_t> key = {sig, (uint64_t)sched, (uint64_t)(uintptr_t)A, (uint64_t)h->arena_bytes,
-                                     (uint64_t)sk_kind, seed, sid, (uint64_t)use_table, (uint64_t)ng};
+                                     (uint64_t)sk_kind, seed, sid, (uint64_t)use_table, (uint64_t)use_tabx,
+                                     (uint64_t)ng};
         for (int64_t b = 0; b < batch; ++b) {
             const rgs_qr_item& it = items[b];
             for (uint64_t v : {(uint64_t)it.n, (uint64_t)it.m, (uint64_t)it.k, (uint64_t)(uintptr_t)it.W,
@@ -2533,6 +2557,8 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     q.sketch = d->sketch;
     q.prec = d->prec;
     if (!valid_desc(&q, true)) return RGS_EINVAL;
+    if ((d->flags & ~(RGS_FLAG_THETA_BF16 | RGS_FLAG_THETA_EXACT | RGS_FLAG_LAG | RGS_FLAG_CERTIFY)) != 0)
+        return RGS_EINVAL;
     if (!valid_table_flags(d->flags, d->sketch)) return RGS_EINVAL;
     if ((d->flags & RGS_FLAG_CERTIFY) && d->sketch == RGS_SKETCH_IDENTITY) return RGS_EINVAL;   // Phi = Theta = I
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
@@ -2578,18 +2604,19 @@ rgs_status rgs_qr_batched_ex(rgs_handle* h, int64_t batch, const rgs_qr_item* it
     if (!h || batch < 1 || batch > 65535 || !items) return RGS_EINVAL;
     if (sketch != RGS_SKETCH_GAUSSIAN && sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if (prec != RGS_P_FP32_LS64 && prec != RGS_P_BF16Q_FP32_LS64) return RGS_EINVAL;
-    if ((flags & ~(RGS_FLAG_THETA_BF16 | RGS_FLAG_GRAPH)) != 0) return RGS_EINVAL;
+    if ((flags & ~(RGS_FLAG_THETA_BF16 | RGS_FLAG_THETA_EXACT | RGS_FLAG_GRAPH)) != 0) return RGS_EINVAL;
     const bool tab = (flags & RGS_FLAG_THETA_BF16) != 0;
+    const bool tabx = (flags & RGS_FLAG_THETA_EXACT) != 0;
     const bool graph = (flags & RGS_FLAG_GRAPH) != 0;
-    if (tab && sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
+    if (!valid_table_flags(flags, sketch)) return RGS_EINVAL;
     const int sk_kind = sketch_kind(sketch);
     for (int64_t b = 0; b < batch; ++b)
         if (!valid_item(items[b], sk_kind)) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (prec == RGS_P_BF16Q_FP32_LS64)
-        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, graph, item_status,
+        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, tabx, graph, item_status,
                                           failed_column, rep);
-    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, graph, item_status,
+    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, tabx, graph, item_status,
                                         failed_column, rep);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;

@@ -80,9 +80,11 @@ bool launch_batch_sketch_p(hipStream_t st, int sketch, const BatchItem* items, c
 // (partials per chunk into partP, G_P chunks per column).
 constexpr int kGemmRows = 2048;      // row chunk of the step-4 product
 constexpr int kGemmRowsP = 16384;    // row chunk of the step-1 product
+// tabx (RGS_FLAG_THETA_EXACT): the entries read from the exact fp32 table of
+// the master matrix (tk rows, SK_TABX layout) instead of drawn, same bits.
 template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
-                             const int2* cols, int rows, int tile);
+                             const int2* cols, int rows, int tile, const float* tabx = nullptr, int tk = 0);
 // The same products with the bf16 Gaussian entries read from the table
 // (tk rows, tgroups groups of 8 columns, the k_theta_table layout) through
 // bf16 MFMA; rows a multiple of 16.

@@ -558,10 +558,14 @@ __device__ __forceinline__ void ld4_rows(const TB* __restrict__ col, int64_t r, 
     }
 }
 
-template <typename TB, bool STEP4, int NSUB>
+// TABX: the entries are read from the exact fp32 table of the master matrix
+// (RGS_FLAG_THETA_EXACT; the SK_TABX layout, whose 16-byte word q tk + j holds
+// z(j, 4q .. 4q+3), made by the same fp32 Box-Muller) instead of drawn: the
+// same A operands, so the same bits.
+template <typename TB, bool STEP4, int NSUB, bool TABX = false>
 __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict__ items,
                                                      const GemmUnit* __restrict__ units, const int2* __restrict__ cols,
-                                                     int rows) {
+                                                     int rows, const float* __restrict__ tabx = nullptr, int tk = 0) {
     const GemmUnit un = units[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int jr = lane & 31, kk = lane >> 5;
@@ -604,7 +608,18 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
     }
     for (int64_t r = r_begin; r < r_end; r += 8) {
         float z[4] = {0.f, 0.f, 0.f, 0.f};
-        if (j < kmax) gauss4((uint32_t)(r / 4 + kk), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+        if (j < kmax) {
+            if constexpr (TABX) {
+                const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(tabx) +
+                                                           (r / 4 + kk) * tk + j);
+                z[0] = v.x;
+                z[1] = v.y;
+                z[2] = v.z;
+                z[3] = v.w;
+            } else {
+                gauss4((uint32_t)(r / 4 + kk), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+            }
+        }
         float c[NSUB][4];
 #pragma unroll
         for (int s2 = 0; s2 < NSUB; ++s2)
@@ -647,10 +662,11 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm(const BatchItem* __restrict
 // tiles.  Each output sees the k-steps of kb_gauss_gemm in the same order
 // (k-step t of the 8-row step at r pairs rows r + t and r + 4 + t), so the
 // partials are the same bits.
-template <typename TB, bool STEP4>
+template <typename TB, bool STEP4, bool TABX = false>
 __global__ __launch_bounds__(256) void kb_gauss_gemm_t128(const BatchItem* __restrict__ items,
                                                           const GemmUnit* __restrict__ units,
-                                                          const int2* __restrict__ cols, int rows) {
+                                                          const int2* __restrict__ cols, int rows,
+                                                          const float* __restrict__ tabx = nullptr, int tk = 0) {
     constexpr int R = 32;                            // rows per super-step
     __shared__ float zbuf[2][R][128];
     const GemmUnit un = units[blockIdx.x];
@@ -688,7 +704,18 @@ __global__ __launch_bounds__(256) void kb_gauss_gemm_t128(const BatchItem* __res
             const int e = t + 256 * p, jl = e & 127;
             const int j = un.jt * 128 + jl;
             z[p][0] = z[p][1] = z[p][2] = z[p][3] = 0.f;
-            if (j < kmax) gauss4((uint32_t)(r / 4 + (e >> 7)), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z[p]);
+            if (j < kmax) {
+                if constexpr (TABX) {   // (kb_gauss_gemm: the table's word for the same Philox call)
+                    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(tabx) +
+                                                               (r / 4 + (e >> 7)) * tk + j);
+                    z[p][0] = v.x;
+                    z[p][1] = v.y;
+                    z[p][2] = v.z;
+                    z[p][3] = v.w;
+                } else {
+                    gauss4((uint32_t)(r / 4 + (e >> 7)), (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z[p]);
+                }
+            }
         }
     };
     auto store = [&](int buf, const float z[4][4]) {
@@ -1579,16 +1606,32 @@ bool launch_batch_table_gemm(hipStream_t st, const BatchItem* items, const GemmU
 
 template <typename TB, bool STEP4>
 bool launch_batch_gauss_gemm(hipStream_t st, const BatchItem* items, const GemmUnit* units, int nunits,
-                             const int2* cols, int rows, int tile) {
+                             const int2* cols, int rows, int tile, const float* tabx, int tk) {
     if (nunits == 0) return true;
-    if (tile <= 32)
-        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 1>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
-    else if (tile <= 64)
-        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
-    else if (tile <= 128 && rows % 32 == 0)
-        hipLaunchKernelGGL((kb_gauss_gemm_t128<TB, STEP4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows);
-    else
+    if (tabx) {
+        if (tile <= 32)
+            hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 1, true>), dim3(nunits), dim3(256), 0, st, items, units,
+                               cols, rows, tabx, tk);
+        else if (tile <= 64)
+            hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 2, true>), dim3(nunits), dim3(256), 0, st, items, units,
+                               cols, rows, tabx, tk);
+        else if (tile <= 128 && rows % 32 == 0)
+            hipLaunchKernelGGL((kb_gauss_gemm_t128<TB, STEP4, true>), dim3(nunits), dim3(256), 0, st, items, units,
+                               cols, rows, tabx, tk);
+        else
+            return false;
+    } else if (tile <= 32) {
+        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 1>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+                           nullptr, 0);
+    } else if (tile <= 64) {
+        hipLaunchKernelGGL((kb_gauss_gemm<TB, STEP4, 2>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+                           nullptr, 0);
+    } else if (tile <= 128 && rows % 32 == 0) {
+        hipLaunchKernelGGL((kb_gauss_gemm_t128<TB, STEP4>), dim3(nunits), dim3(256), 0, st, items, units, cols, rows,
+                           nullptr, 0);
+    } else {
         return false;
+    }
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -1951,11 +1994,11 @@ template bool launch_batch_table_gemm<bf16, true>(hipStream_t, const BatchItem*,
 template bool launch_batch_table_gemm<float, false>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
                                                     int, int, const uint16_t*, int, int64_t);
 template bool launch_batch_gauss_gemm<float, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
-                                                   int, int);
+                                                   int, int, const float*, int);
 template bool launch_batch_gauss_gemm<bf16, true>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*, int,
-                                                  int);
+                                                  int, const float*, int);
 template bool launch_batch_gauss_gemm<float, false>(hipStream_t, const BatchItem*, const GemmUnit*, int, const int2*,
-                                                    int, int);
+                                                    int, int, const float*, int);
 template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, const BlockMap&, int64_t,
                                           const BlockMap&, int64_t, const BlockMap&, int64_t, bool);
 template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,

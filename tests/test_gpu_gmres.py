@@ -214,3 +214,20 @@ def test_richardson_sweeps_rejected(gpu_handle):
         rgs.rgs_gmres_batched(gpu_handle, [(rgs.stencil7(dims, coeffs), b, x)],
                               rgs.gmres_desc(5, 32, 1e-6, ls_sweeps=1))
     assert e.value.status == rgs.RGS_EINVAL
+
+
+def test_unknown_flag_bits_rejected(gpu_handle):
+    """rgs_gmres takes RGS_FLAG_THETA_BF16, THETA_EXACT, LAG and CERTIFY; any
+    other bit (the QR-only flags, an undefined bit) is an argument error."""
+    rgs = _rgs()
+    dims, coeffs = synth.convdiff_coeffs(8, 10.0)
+    b = dev(synth.rhs(8 ** 3, tag=91))
+    x = torch.empty(8 ** 3, dtype=torch.float64, device="cuda")
+    for bad in (rgs.FLAG_DIAGNOSTICS, rgs.FLAG_TIME_KERNELS, rgs.FLAG_GRAPH, 1 << 10):
+        with pytest.raises(rgs.RgsError) as e:
+            rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs),
+                          rgs.gmres_desc(10, 40, 1e-6, sketch="srht", prec="fp64", flags=bad), b, x)
+        assert e.value.status == rgs.RGS_EINVAL
+    rep, _ = rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs),
+                           rgs.gmres_desc(10, 40, 1e-6, sketch="srht", prec="fp64", flags=rgs.FLAG_LAG), b, x)
+    assert rep.status == 0

@@ -84,3 +84,22 @@ def test_graph_with_kernel_timing_rejected(gpu_handle):
     with pytest.raises(rgs.RgsError) as e:
         rgs.rgs_qr(gpu_handle, d, W, Q, R, S)
     assert e.value.status == rgs.RGS_EINVAL
+
+
+def test_graph_with_exact_table(gpu_handle):
+    """RGS_FLAG_GRAPH with RGS_FLAG_THETA_EXACT: the table is made eagerly on
+    every call, before the replay; each replay equals the eager call with the
+    same table bit for bit."""
+    rgs = _rgs()
+    n, m, k = 16384 + 36, 20, 128
+    W, Q, R, S = _buffers(n, m, k, "fp32")
+    d = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32", seed=9, flags=rgs.FLAG_GRAPH | rgs.FLAG_THETA_EXACT)
+    de = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp32", seed=9, flags=rgs.FLAG_THETA_EXACT)
+    for rnd in range(3):
+        W.copy_(torch.from_numpy(synth.svd_matrix(n, m, 10.0 ** -(2 + rnd), tag=420 + rnd)))
+        Q.fill_(float("nan"))
+        assert rgs.rgs_qr(gpu_handle, d, W, Q, R, S).status == 0
+        _, Q0, R0, S0 = _buffers(n, m, k, "fp32")
+        assert rgs.rgs_qr(gpu_handle, de, W, Q0, R0, S0).status == 0
+        torch.cuda.synchronize()
+        assert torch.equal(Q, Q0) and torch.equal(R, R0) and torch.equal(S, S0), rnd

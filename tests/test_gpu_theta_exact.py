@@ -13,7 +13,7 @@ order of the floating-point sums:
 * RGMRES (fresh Theta per cycle and reuse_theta): the same iteration count
   and residual history as the drawn path, and the oracle's in fp64;
 * the flag's rejections (other sketches, with the bf16 table, on the calls
-  that do not take it).
+  that do not take it).  The batched QR's exact table: test_gpu_batched_exact.py.
 """
 
 import numpy as np
@@ -188,9 +188,6 @@ def test_exact_flag_rejections(gpu_handle):
     d = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp64", flags=rgs.FLAG_THETA_EXACT)
     expect_einval(lambda: rgs.rgs_qr_noalloc(gpu_handle, d, Wd, *outs()))
     expect_einval(lambda: rgs.rgs_sketch_materialize(gpu_handle, d, 0, k, 0, n, rgs.colmajor(k, n, torch.float64)))
-    items = [(to_dev(W, torch.float32), rgs.colmajor(n, m, torch.float32), rgs.colmajor(m, m, torch.float64),
-              rgs.colmajor(k, m, torch.float64), k)]
-    expect_einval(lambda: rgs.rgs_qr_batched(gpu_handle, items, sketch="gaussian", flags=rgs.FLAG_THETA_EXACT))
     N = 8
     dims, coeffs = synth.convdiff_coeffs(N, 10.0)
     b = to_dev(synth.rhs(N ** 3, tag=86), torch.float64)
