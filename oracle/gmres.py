@@ -23,6 +23,13 @@ Precision 'bf16q' is 'fp32' with the basis stored in bfloat16, as in the
 qb_i = bf16(q'_i) with the fp64 scale 1/r_ii, its sketch is taken of qb_i, the
 mat-vec input is fl32(qb_{i-1} / r_{i-1,i-1}), the projection uses the stored
 columns with coefficients fl32(y_c / r_cc), and x += sum_c qb_c (y_c / r_cc).
+Precision 'fp32u' is the configuration of the GMRES experiment of Sec. 5.3:
+unique-precision RGS, i.e. every step of Algorithm 2 in float32 (the
+sketches, the least squares, the projection, r_ii, s_i and q_i, as the
+'fp32u' model of ``oracle.rgs``), while the products with A are computed in
+fp64 (from the float32 basis vector, the result rounded once to float32 for
+the RGS step) and the Givens rotations, x and the restart residual stay in
+fp64.
 """
 
 import numpy as np
@@ -48,15 +55,19 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
     reverse order: the same step with another summation order, which the
     precision models leave open (a second valid rounding of the same model).
     Returns dict(x, hist, iters, cycles, true_relres, converged, Q_last,
-    theta_cycle_last): hist[t] = |g| / ||b|| after global inner step t;
+    S_last, theta_cycle_last): hist[t] = |g| / ||b|| after global inner step t;
     Q_last holds the last cycle's basis vectors the update used (its first
-    ``used`` stored columns, in fp64; unnormalised in the bf16 model) and
-    theta_cycle_last the argument of make_theta for that cycle.
+    ``used`` stored columns, in fp64; unnormalised in the bf16 model), S_last
+    their sketches s_i (fp64 array) and theta_cycle_last the argument of
+    make_theta for that cycle.
     """
-    if precision not in ("fp64", "fp32", "bf16q"):
+    if precision not in ("fp64", "fp32", "bf16q", "fp32u"):
         raise ValueError(precision)
     store = np.float64 if precision == "fp64" else np.float32
     bf16 = precision == "bf16q"
+    unique = precision == "fp32u"
+    # arithmetic of the sketches and of RGS steps 2 and 4-7
+    fine = np.float32 if unique else np.float64
     b = np.asarray(b, dtype=np.float64)
     n = b.size
     bnorm = np.linalg.norm(b)
@@ -67,7 +78,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
     cycle = 0
     converged = False
     true_relres = 1.0
-    Q_last, theta_last = np.zeros((n, 0)), None
+    Q_last, S_last, theta_last = np.zeros((n, 0)), None, None
     while iters < max_iters and (max_cycles is None or cycle < max_cycles):
         theta_last = 0 if reuse_theta else cycle
         theta = make_theta(theta_last)
@@ -83,7 +94,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
             Q[:, 0] = bf16_round(w)
             p = theta.apply(Q[:, 0].astype(np.float64))
         else:
-            p = theta.apply(w.astype(np.float64))
+            p = theta.apply(w.astype(fine), fine)
         r11 = np.linalg.norm(p)
         if r11 == 0.0:
             converged = True
@@ -93,7 +104,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
         if bf16:
             scale[0] = 1.0 / r11
         else:
-            Q[:, 0] = (w.astype(np.float64) / r11).astype(store)
+            Q[:, 0] = (w.astype(fine) / r11).astype(store)
         g = np.zeros(mmax)
         g[0] = r11
         cs = np.zeros(mmax)
@@ -104,9 +115,12 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
                 q_prev = (Q[:, i - 1].astype(np.float64) * scale[i - 1]).astype(store)
             else:
                 q_prev = Q[:, i - 1]
-            w = apply_A(q_prev, store)              # step 3 of Algorithm 3
-            p = theta.apply(w.astype(np.float64))   # RGS step 1
-            r = _ls(S[:, :i], p, ls)                # RGS step 2
+            if unique:                              # step 3 of Algorithm 3, in fp64 (Sec. 5.3)
+                w = apply_A(q_prev, np.float64).astype(store)
+            else:
+                w = apply_A(q_prev, store)          # step 3 of Algorithm 3
+            p = theta.apply(w.astype(fine), fine)   # RGS step 1
+            r = _ls(S[:, :i] if not unique else S[:, :i].astype(fine), p, ls)   # RGS step 2
             R[:i, i] = r
             cols = slice(i - 1, None, -1) if reverse_projection else slice(0, i)
             if bf16:
@@ -115,7 +129,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
                 sp = theta.apply(Q[:, i].astype(np.float64))        # RGS step 4 of the stored column
             else:
                 qp = w - Q[:, cols] @ r[cols].astype(store)     # RGS step 3
-                sp = theta.apply(qp.astype(np.float64))  # RGS step 4
+                sp = theta.apply(qp.astype(fine), fine)  # RGS step 4
             rii = np.linalg.norm(sp)                # RGS step 5
             lucky = rii == 0.0 or rii <= BREAKDOWN_RATIO * np.linalg.norm(p)
             R[i, i] = 0.0 if lucky else rii
@@ -124,7 +138,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
                 if bf16:
                     scale[i] = 1.0 / rii            # RGS step 7, kept as a scale
                 else:
-                    Q[:, i] = (qp.astype(np.float64) / rii).astype(store)  # RGS step 7
+                    Q[:, i] = (qp.astype(fine) / rii).astype(store)  # RGS step 7
             # Hessenberg column i-1 (0-based) = R(0:i+1, i); Givens in fp64
             h = R[: i + 1, i].copy()
             for t in range(i - 1):
@@ -149,6 +163,7 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
             y = y * scale[:used]
         x = x + Q[:, :used].astype(np.float64) @ y
         Q_last = Q[:, :used].astype(np.float64)
+        S_last = S[:, :used].copy()
         r0 = b - apply_A(x, np.float64)
         true_relres = np.linalg.norm(r0) / bnorm
         cycle += 1
@@ -157,4 +172,4 @@ def rgmres(apply_A, b, make_theta, restart, tol, max_iters=100000, precision="fp
             break
     return {"x": x, "hist": np.array(hist), "iters": iters, "cycles": cycle,
             "true_relres": true_relres, "converged": converged, "Q_last": Q_last,
-            "theta_cycle_last": theta_last}
+            "S_last": S_last, "theta_cycle_last": theta_last}

@@ -200,3 +200,47 @@ def test_last_cycle_basis_is_sketch_orthonormal_and_spans_the_update(kind):
     dx = out["x"] - prev["x"]
     y = np.linalg.lstsq(Q, dx, rcond=None)[0]
     assert np.linalg.norm(dx - Q @ y) <= 1e-12 * np.linalg.norm(out["x"])   # x rounding, not dx, sets the floor
+
+
+@pytest.mark.parametrize("sk", ["srht", "gaussian"])
+def test_unique_precision_model_is_sec53(sk):
+    """'fp32u' is the configuration of the GMRES experiment of Sec. 5.3: RGS in
+    float32 throughout, the products with A and the Givens rotations in fp64.
+    * every product with A is requested in fp64 (the 'fp32' multi-precision
+      model asks for float32 products inside a cycle);
+    * the basis vectors and their sketches are float32 values (the 'fp32'
+      model's sketches are fp64 values);
+    * it reaches tol in the fp64 true residual within +-2 iterations of the
+      fp64 model (Sec. 5.3: the unique-precision RGS already gives a nearly
+      optimal solution);
+    * it is a different rounding from the 'fp32' model: the histories agree to
+      1e-3 but not to 1e-9."""
+    N, Pe = 9, 30.0
+    dims, coeffs = synth.convdiff_coeffs(N, Pe)
+    n = N ** 3
+    b = synth.rhs(n, tag=7)
+    mk = lambda c: sketch.make(sk, n, 64, seed=42, sketch_id=2 + c)
+    asked = {}
+
+    def applyA(prec):
+        def f(u, dt):
+            asked.setdefault(prec, set()).add(np.dtype(dt))
+            return stencil.apply(u, dims, coeffs, dt)
+        return f
+
+    ref = gmres.rgmres(applyA("fp64"), b, mk, restart=15, tol=1e-6, precision="fp64")
+    mp = gmres.rgmres(applyA("fp32"), b, mk, restart=15, tol=1e-6, precision="fp32")
+    up = gmres.rgmres(applyA("fp32u"), b, mk, restart=15, tol=1e-6, precision="fp32u")
+    assert asked["fp32u"] == {np.dtype(np.float64)}
+    assert np.dtype(np.float32) in asked["fp32"]
+    for key in ("Q_last", "S_last"):
+        v = up[key]
+        assert np.array_equal(v.astype(np.float32).astype(np.float64), v), key
+    assert not np.array_equal(mp["S_last"].astype(np.float32).astype(np.float64), mp["S_last"])
+    assert up["converged"] and ref["converged"]
+    r = b - stencil.apply(up["x"], dims, coeffs, np.float64)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
+    assert abs(up["iters"] - ref["iters"]) <= 2
+    L = min(len(up["hist"]), len(mp["hist"]))
+    np.testing.assert_allclose(up["hist"][:L], mp["hist"][:L], rtol=1e-3)
+    assert np.max(np.abs(up["hist"][:L] / mp["hist"][:L] - 1)) > 1e-9
