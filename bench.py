@@ -746,6 +746,22 @@ def gmres_leg(rgs, torch, synth, h, N=192, Pe=50.0, restart=100, k=400, tol=1e-6
             "speedup_vs_drawn": res["gaussian_%s" % prec]["seconds_to_tol"] / dt}
         log("  rgmres gaussian(exact table)/%s: %d iters, %d cycles, relres %.2e, %.3f s (%.2fx the drawn sketch)" %
             (prec, rep.iters, rep.cycles, rep.true_relres, dt, res["gaussian_%s" % prec]["seconds_to_tol"] / dt))
+    # the configuration of the GMRES experiment of Sec. 5.3: unique-precision (float32) RGS with the
+    # products with A in fp64 (RGS_P_FP32)
+    for sketch in ("srht", "gaussian"):
+        d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch=sketch, prec="fp32u")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, _ = rgs.rgs_gmres(h, A, d, b, x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nbytes = gmres_bytes(n, rep.iters, rep.cycles, restart, 4, 4)
+        res["%s_fp32u" % sketch] = {"seconds_to_tol": dt, "iters": rep.iters, "cycles": rep.cycles,
+                                    "true_relres": rep.true_relres, "status": rep.status,
+                                    "algorithmic_bytes": nbytes, "gbs": nbytes / dt / 1e9,
+                                    "speedup_vs_fp64": res["%s_fp64" % sketch]["seconds_to_tol"] / dt}
+        log("  rgmres %s/fp32u (Sec. 5.3: float32 RGS, fp64 mat-vec): %d iters, %d cycles, relres %.2e, %.3f s" %
+            (sketch, rep.iters, rep.cycles, rep.true_relres, dt))
     # the P-SRHT with the lagged Arnoldi step (RGS_FLAG_LAG): both sketches of a step in the mat-vec pass
     for prec in ("fp32", "fp64"):
         d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec=prec, flags=rgs.FLAG_LAG)

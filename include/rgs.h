@@ -86,7 +86,11 @@ typedef enum {
                                   (q'_i times the float32 reciprocal of r_ii); R and S receive
                                   float32 values.  rgs_qr, rgs_qr_noalloc (Householder solver
                                   only: ls_sweeps must be 0) and rgs_sketch_apply (float32
-                                  arithmetic); not GMRES or the batched calls (EINVAL) */
+                                  arithmetic); rgs_gmres: the configuration of the GMRES
+                                  experiment of Sec. 5.3 -- this RGS as the Arnoldi step, the
+                                  products with A in fp64 from the float32 basis vector (rounded
+                                  once to float32), Givens rotations, x and the restart residual
+                                  in fp64 (ls_sweeps 0); not the batched calls (EINVAL) */
 } rgs_precision;
 
 /* Flags for rgs_qr_desc.flags / rgs_gmres_desc.flags */
@@ -416,8 +420,9 @@ rgs_status rgs_gmres_batched(rgs_handle *h, int64_t batch, const rgs_gmres_item 
                              const rgs_gmres_desc *desc, int32_t *item_status, rgs_report *reps);
 
 /* w = A u for the 7-point operator (the mat-vec of Algorithm 3, step 3), in
- * the working precision of `prec` (u, w: float for FP32_LS64, double for FP64).
- * Test hook.  Synchronous. */
+ * the working precision of `prec` (u, w: float for FP32_LS64, double for FP64;
+ * FP32: float u and w with the arithmetic in fp64, the mat-vec of RGS_P_FP32
+ * GMRES).  Test hook.  Synchronous. */
 rgs_status rgs_stencil_apply(rgs_handle *h, const rgs_stencil7 *A, int32_t prec,
                              const void *u, void *w);
 

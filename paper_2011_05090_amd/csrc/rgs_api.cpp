@@ -880,7 +880,10 @@ StencilArgs stencil_args(const rgs_stencil7* A) {
 // Restarted randomized GMRES (Sec. 4.2) driven from the host: one restart
 // cycle is enqueued in full (its inner steps stop themselves on the device
 // once converged), then the host synchronises once to read the true residual.
-template <typename T, typename TQ, bool DEFER>
+// TS: the arithmetic of the sketch space (fp64; float32 for the configuration
+// of Sec. 5.3, unique-precision RGS, whose products with A are then computed
+// in fp64 and rounded once to float32).
+template <typename T, typename TQ, bool DEFER, typename TS = double>
 rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc* d, const double* b, double* x,
                      double* res_hist, int64_t hist_cap, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -938,15 +941,17 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
     auto ls_rhs = [&](const T* partials, int i, const double* scale2) {
         return sweeps > 0 ? launch_ls_partials_richardson<T, T>(s, sa, partials, Gp, scale, i, S, k, R, mcap, coef,
                                                                 DEFER ? sa.invr : nullptr, scale2, sweeps)
-                          : launch_ls_partials<T, T>(s, sa, partials, Gp, scale, i, R, mcap, coef,
-                                                     DEFER ? sa.invr : nullptr, scale2);
+                          : launch_ls_partials<T, T, TS>(s, sa, partials, Gp, scale, i, R, mcap, coef,
+                                                         DEFER ? sa.invr : nullptr, scale2);
     };
     auto column = [&](int i) {
         return sweeps > 0 ? launch_column_richardson<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr,
                                                            coef, nullptr, sweeps)
-                          : launch_column<T, T>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr, coef,
-                                                nullptr);
+                          : launch_column<T, T, TS>(s, sa, part, Gp, scale, nullptr, i, S, k, R, mcap, nullptr,
+                                                    coef, nullptr);
     };
+    // the arithmetic of the products with A
+    using TC = typename std::conditional<std::is_same<TS, float>::value, double, T>::type;
 
     // x0 = 0, r0 = b, ||b||
     if (hipMemsetAsync(x, 0, n * sizeof(double), s) != hipSuccess) return RGS_EDEVICE;
@@ -993,7 +998,7 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
                                           part, sa.status))
             return RGS_EDEVICE;
         // dual: t_1 = A q'_0 with the sketches of q'_0 (part) and t_1 (part2)
-        if (dual && !launch_stencil_dual<TQ, T>(s, A, Q, wbuf, sk, part, part2, sa.status)) return RGS_EDEVICE;
+        if (dual && !launch_stencil_dual<TQ, T, TC>(s, A, Q, wbuf, sk, part, part2, sa.status)) return RGS_EDEVICE;
         if (!column(0)) return RGS_EDEVICE;
         if (!launch_givens_init(s, R, gv, used)) return RGS_EDEVICE;
         const int64_t steps = std::min<int64_t>(d->restart, d->max_iters - iters);
@@ -1005,12 +1010,12 @@ rgs_status run_gmres(rgs_handle* h, const rgs_stencil7* Ad, const rgs_gmres_desc
                 if (!launch_project_ws<T, TQ, DEFER>(s, wbuf, Q, ldq, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1,
                                                      vec_ok ? 1 : 0, sa.invr + (i - 1), sa.status))
                     return RGS_EDEVICE;
-                if (!launch_stencil_dual<TQ, T>(s, A, Q + i * ldq, wbuf, sk, part, part2, sa.status))
+                if (!launch_stencil_dual<TQ, T, TC>(s, A, Q + i * ldq, wbuf, sk, part, part2, sa.status))
                     return RGS_EDEVICE;
             } else {
                 // w_i = A q_{i-1}, sketched: p_i (step 3 of Algorithm 3, step 1 of Algorithm 2)
-                if (!launch_stencil_sketch<TQ, T>(s, A, Q + (i - 1) * ldq, sa.invr + (i - 1), wbuf, 1, sk, part,
-                                                  sa.status))
+                if (!launch_stencil_sketch<TQ, T, TC>(s, A, Q + (i - 1) * ldq, sa.invr + (i - 1), wbuf, 1, sk,
+                                                      part, sa.status))
                     return RGS_EDEVICE;
                 if (!ls_rhs(part, i, nullptr)) return RGS_EDEVICE;
                 if (!launch_project<T, TQ, DEFER>(s, wbuf, Q, ldq, n, i, coef, sa.invr + (i - 1), DEFER ? 0 : 1, 1,
@@ -1843,6 +1848,8 @@ bool valid_gmres_desc(const rgs_gmres_desc* d) {
     if (d->restart < 1 || d->restart + 1 > d->k || d->restart > 4000 || d->max_iters < 1 || !(d->tol >= 0))
         return false;
     if (d->ls_sweeps > kMaxSweeps) return false;
+    // the unique-precision float32 chain is Householder only
+    if (d->prec == RGS_P_FP32) return d->ls_sweeps == 0;
     return d->prec == RGS_P_FP64 || d->prec == RGS_P_FP32_LS64 || d->prec == RGS_P_BF16Q_FP32_LS64;
 }
 
@@ -2564,6 +2571,8 @@ rgs_status rgs_gmres(rgs_handle* h, const rgs_stencil7* A, const rgs_gmres_desc*
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (d->prec == RGS_P_FP64) return run_gmres<double, double, false>(h, A, d, b, x, res_hist, hist_cap, rep);
     if (d->prec == RGS_P_BF16Q_FP32_LS64) return run_gmres<float, bf16, true>(h, A, d, b, x, res_hist, hist_cap, rep);
+    if (d->prec == RGS_P_FP32)   // the configuration of Sec. 5.3
+        return run_gmres<float, float, false, float>(h, A, d, b, x, res_hist, hist_cap, rep);
     return run_gmres<float, float, false>(h, A, d, b, x, res_hist, hist_cap, rep);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;
@@ -2575,7 +2584,7 @@ rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec
     if (!h || !Ad || !u || !w) return RGS_EINVAL;
     if (Ad->nx < 1 || Ad->ny < 1 || Ad->nz < 1) return RGS_EINVAL;
     if (Ad->nx * Ad->ny * Ad->nz > ((int64_t)1 << 31) - 1) return RGS_EINVAL;
-    if (prec != RGS_P_FP64 && prec != RGS_P_FP32_LS64) return RGS_EINVAL;
+    if (prec != RGS_P_FP64 && prec != RGS_P_FP32_LS64 && prec != RGS_P_FP32) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     rgs_status st = ensure_arena(h, 4096);
     if (st != RGS_OK) return st;
@@ -2587,6 +2596,9 @@ rgs_status rgs_stencil_apply(rgs_handle* h, const rgs_stencil7* Ad, int32_t prec
     if (prec == RGS_P_FP64)
         ok = launch_stencil_sketch<double, double>(h->stream, A, static_cast<const double*>(u), nullptr,
                                                    static_cast<double*>(w), 0, sk, nullptr, status);
+    else if (prec == RGS_P_FP32)   // float32 vectors, the product in fp64 (Sec. 5.3)
+        ok = launch_stencil_sketch<float, float, double>(h->stream, A, static_cast<const float*>(u), nullptr,
+                                                         static_cast<float*>(w), 0, sk, nullptr, status);
     else
         ok = launch_stencil_sketch<float, float>(h->stream, A, static_cast<const float*>(u), nullptr,
                                                  static_cast<float*>(w), 0, sk, nullptr, status);
@@ -2633,6 +2645,7 @@ rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
 rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,
                              int32_t* item_status, rgs_report* reps) try {
     if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
+    if (d->prec == RGS_P_FP32) return RGS_EINVAL;   // the unique-precision model: rgs_gmres only
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16)) != 0) return RGS_EINVAL;
     if (d->ls_sweeps != 0) return RGS_EINVAL;   // the batched solves keep the Householder least squares

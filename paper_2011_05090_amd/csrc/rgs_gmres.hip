@@ -127,8 +127,9 @@ __device__ __forceinline__ void ld4_raw(const bf16* __restrict__ p, I l, double 
 // four y/z neighbour planes are one vector load, plus the two x neighbours
 // outside the group, addressed by 32-bit offsets when O32 (n sizeof(TQ) <
 // 2^32).  Otherwise the rows are stepped from one coordinate division and
-// read element by element.
-template <typename T, typename TQ, bool SCALE, bool O32>
+// read element by element.  TC: the arithmetic of the products with A (T, or
+// fp64 for the configuration of Sec. 5.3, the result rounded once to T).
+template <typename T, typename TQ, bool SCALE, bool O32, typename TC = T>
 __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ qs, double ir, bool vec, int64_t l0,
                                          int64_t n, T out[4], T cen[4]) {
     const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz, nxy = nx * ny;
@@ -179,14 +180,14 @@ __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ 
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                T acc = (T)g.c0 * u[r];
-                acc = acc + (x + r > 0 ? (T)g.cxm * (r > 0 ? u[r - 1] : xm) : T(0));
-                acc = acc + (x + r + 1 < nx ? (T)g.cxp * (r < 3 ? u[r + 1] : xp) : T(0));
-                acc = acc + (y > 0 ? (T)g.cym * ym[r] : T(0));
-                acc = acc + (y + 1 < ny ? (T)g.cyp * yp[r] : T(0));
-                acc = acc + (z > 0 ? (T)g.czm * zm[r] : T(0));
-                acc = acc + (z + 1 < nz ? (T)g.czp * zp[r] : T(0));
-                ro[r] = acc;
+                TC acc = (TC)g.c0 * (TC)u[r];
+                acc = acc + (x + r > 0 ? (TC)g.cxm * (TC)(r > 0 ? u[r - 1] : xm) : TC(0));
+                acc = acc + (x + r + 1 < nx ? (TC)g.cxp * (TC)(r < 3 ? u[r + 1] : xp) : TC(0));
+                acc = acc + (y > 0 ? (TC)g.cym * (TC)ym[r] : TC(0));
+                acc = acc + (y + 1 < ny ? (TC)g.cyp * (TC)yp[r] : TC(0));
+                acc = acc + (z > 0 ? (TC)g.czm * (TC)zm[r] : TC(0));
+                acc = acc + (z + 1 < nz ? (TC)g.czp * (TC)zp[r] : TC(0));
+                ro[r] = (T)acc;
                 rc[r] = u[r];
             }
         }
@@ -204,14 +205,14 @@ __device__ __forceinline__ void stencil4(const Grid3& g, const TQ* __restrict__ 
             const T vxm = ld1(hxm ? lc - 1 : lc), vxp = ld1(hxp ? lc + 1 : lc);
             const T vym = ld1(hym ? lc - nx : lc), vyp = ld1(hyp ? lc + nx : lc);
             const T vzm = ld1(hzm ? lc - (int64_t)nxy : lc), vzp = ld1(hzp ? lc + (int64_t)nxy : lc);
-            T acc = (T)g.c0 * c;
-            acc = acc + (hxm ? (T)g.cxm * vxm : T(0));
-            acc = acc + (hxp ? (T)g.cxp * vxp : T(0));
-            acc = acc + (hym ? (T)g.cym * vym : T(0));
-            acc = acc + (hyp ? (T)g.cyp * vyp : T(0));
-            acc = acc + (hzm ? (T)g.czm * vzm : T(0));
-            acc = acc + (hzp ? (T)g.czp * vzp : T(0));
-            ro[r] = live ? acc : T(0);
+            TC acc = (TC)g.c0 * (TC)c;
+            acc = acc + (hxm ? (TC)g.cxm * (TC)vxm : TC(0));
+            acc = acc + (hxp ? (TC)g.cxp * (TC)vxp : TC(0));
+            acc = acc + (hym ? (TC)g.cym * (TC)vym : TC(0));
+            acc = acc + (hyp ? (TC)g.cyp * (TC)vyp : TC(0));
+            acc = acc + (hzm ? (TC)g.czm * (TC)vzm : TC(0));
+            acc = acc + (hzp ? (TC)g.czp * (TC)vzp : TC(0));
+            ro[r] = live ? (T)acc : T(0);
             rc[r] = live ? c : T(0);
             if (++x == nx) {
                 x = 0;
@@ -273,7 +274,7 @@ __device__ __forceinline__ bool stencil_vec_ok(const Grid3& g, const TQ* qs, con
 // to T exactly as a normalising projection pass stores it), then the block's
 // sketch partials of w.  Block layout identical to the projection kernel
 // (kProjWaves wave tiles of 1024 rows).
-template <typename TQ, typename T, typename PT, int SK>
+template <typename TQ, typename T, typename PT, int SK, typename TC = T>
 __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, const double* __restrict__ invr,
                                                     const Grid3& g, int64_t n, T* __restrict__ w, int do_sketch,
                                                     const SketchArgs& sk, PT* __restrict__ partials, int64_t blk,
@@ -288,7 +289,7 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
         for (int e = 0; e < 4; ++e) {
             const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
             T c[4];
-            stencil4<T, TQ, decltype(scale)::value, decltype(o32)::value>(g, qs, ir, vec, r0, n, v + 4 * e, c);
+            stencil4<T, TQ, decltype(scale)::value, decltype(o32)::value, TC>(g, qs, ir, vec, r0, n, v + 4 * e, c);
             st4<T>(w, r0, n, vec, v + 4 * e);
         }
     };
@@ -337,7 +338,7 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
 // TAB: the entries come from the bf16 table (SK_TABLE), 8 rows per load;
 // EXACT (with TAB): from the table of the entries in T (SK_TABX), 8 rows per
 // 32- or 64-byte group.
-template <typename TQ, typename T, bool TAB = false, int DEPTH = kTabDepth, bool EXACT = false>
+template <typename TQ, typename T, bool TAB = false, int DEPTH = kTabDepth, bool EXACT = false, typename TC = T>
 __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
                                                   T* __restrict__ t_out, const SketchArgs& sk,
                                                   T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
@@ -351,7 +352,7 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
             const int local = wave * kTile + 256 * e + 4 * lane;
             const int64_t r0 = blk * RB + local;
             T tv[4], xv[4];
-            stencil4<T, TQ, false, decltype(o32)::value>(g, xs, 1.0, vec, r0, n, tv, xv);
+            stencil4<T, TQ, false, decltype(o32)::value, TC>(g, xs, 1.0, vec, r0, n, tv, xv);
             st4<T>(t_out, r0, n, vec, tv);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -449,7 +450,7 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
 // and p_{i+1} of A q'_i, come out of one reduction, r_ii and the 1/r_ii of
 // p_{i+1} and w_{i+1} being applied when known.  Rows and their order per
 // vector as in stencil_sketch_body.
-template <typename TQ, typename T, int SK>
+template <typename TQ, typename T, int SK, typename TC = T>
 __device__ __forceinline__ void stencil_dual_sk_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
                                                      T* __restrict__ t_out, const SketchArgs& sk,
                                                      T* __restrict__ part_x, T* __restrict__ part_t, int64_t blk,
@@ -462,7 +463,7 @@ __device__ __forceinline__ void stencil_dual_sk_body(const TQ* __restrict__ xs, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t r0 = blk * (NW * kTile) + wave * kTile + 256 * e + 4 * lane;
-            stencil4<T, TQ, false, decltype(o32)::value>(g, xs, 1.0, vec, r0, n, tv + 4 * e, xv + 4 * e);
+            stencil4<T, TQ, false, decltype(o32)::value, TC>(g, xs, 1.0, vec, r0, n, tv + 4 * e, xv + 4 * e);
             st4<T>(t_out, r0, n, vec, tv + 4 * e);
         }
     };
@@ -632,19 +633,19 @@ __device__ __forceinline__ void xupdate_body(double* __restrict__ x, const TQ* _
 // ---------------------------------------------------------------------------
 // Single-system kernels
 // ---------------------------------------------------------------------------
-template <typename TQ, typename T, typename PT, int SK>
 // (at most 80 registers, 6 waves per SIMD: 28.3 instead of 30.6 us per fp32
 // launch at 192^3; the dual kernels are faster without the cap)
+template <typename TQ, typename T, typename PT, int SK, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave, 6) void k_stencil_sketch(
     const TQ* __restrict__ qs, const double* __restrict__ invr, Grid3 g, int64_t n, T* __restrict__ w,
     int do_sketch, SketchArgs sk, PT* __restrict__ partials, const int* __restrict__ status) {
     __shared__ T lds[kProjWaves * kTile];
     RGS_EXIT_IF_STOPPED(status);
-    stencil_sketch_body<TQ, T, PT, SK>(qs, invr, g, n, w, do_sketch, sk, partials, xcd_block(blockIdx.x, gridDim.x),
-                                       lds);
+    stencil_sketch_body<TQ, T, PT, SK, TC>(qs, invr, g, n, w, do_sketch, sk, partials,
+                                           xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
-template <typename TQ, typename T, bool TAB, bool EXACT = false>
+template <typename TQ, typename T, bool TAB, bool EXACT = false, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     const TQ* __restrict__ xs, Grid3 g, int64_t n, T* __restrict__ t_out, SketchArgs sk, T* __restrict__ part_x,
     T* __restrict__ part_t, const int* __restrict__ status) {
@@ -653,17 +654,17 @@ __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual(
     // one system: k <= 512 threads stream the table with 4 loads in flight
     // (16 measured slower here; the batched row-block launch uses 16)
     // (the exact table: 256 bytes in flight per thread)
-    stencil_dual_body<TQ, T, TAB, EXACT ? tabx_depth<T>() : 4, EXACT>(xs, g, n, t_out, sk, part_x, part_t,
-                                                                    xcd_block(blockIdx.x, gridDim.x), lds);
+    stencil_dual_body<TQ, T, TAB, EXACT ? tabx_depth<T>() : 4, EXACT, TC>(xs, g, n, t_out, sk, part_x, part_t,
+                                                                        xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
-template <typename TQ, typename T, int SK>
+template <typename TQ, typename T, int SK, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave) void k_stencil_dual_sk(
     const TQ* __restrict__ xs, Grid3 g, int64_t n, T* __restrict__ t_out, SketchArgs sk, T* __restrict__ part_x,
     T* __restrict__ part_t, const int* __restrict__ status) {
     __shared__ T lds[kProjWaves * kTile];
     RGS_EXIT_IF_STOPPED(status);
-    stencil_dual_sk_body<TQ, T, SK>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
+    stencil_dual_sk_body<TQ, T, SK, TC>(xs, g, n, t_out, sk, part_x, part_t, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ b, const double* __restrict__ x,
@@ -919,47 +920,47 @@ __global__ __launch_bounds__(256) void kg_norm_finish(const GmresItem* __restric
 
 static inline unsigned nblk_of(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
 
-template <typename TQ, typename T>
+template <typename TQ, typename T, typename TC>
 bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, const double* invr, T* w,
                            int do_sketch, const SketchArgs& sk, T* partials, const int* status) {
     const int64_t n = A.nx * A.ny * A.nz;
     const Grid3 g = grid3(A);
     const dim3 grid(nblk_of(n, kProjRows)), thr(kProjWaves * kWave);
     if (sk.sketch == SK_SRHT)
-        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_SRHT>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_SRHT, TC>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
     else if (sk.sketch == SK_GAUSS)
-        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_GAUSS>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_GAUSS, TC>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
     else if (sk.sketch == SK_RADEM)
-        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_RADEM>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_RADEM, TC>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
     else
-        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_IDENT>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
+        hipLaunchKernelGGL((k_stencil_sketch<TQ, T, T, SK_IDENT, TC>), grid, thr, 0, st, qs, invr, g, n, w, do_sketch,
                            sk, partials, status);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-template <typename TQ, typename T>
+template <typename TQ, typename T, typename TC>
 bool launch_stencil_dual(hipStream_t st, const StencilArgs& A, const TQ* xs, T* t_out, const SketchArgs& sk,
                          T* part_x, T* part_t, const int* status) {
     const int64_t n = A.nx * A.ny * A.nz;
     const dim3 grid(nblk_of(n, kProjRows)), thr(kProjWaves * kWave);
     if (sk.sketch == SK_TABX)
-        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true, true>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true, true, TC>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
                            part_t, status);
     else if (sk.sketch == SK_TABLE)
-        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x, part_t,
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, true, false, TC>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x, part_t,
                            status);
     else if (sk.sketch == SK_GAUSS)
-        hipLaunchKernelGGL((k_stencil_dual<TQ, T, false>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
+        hipLaunchKernelGGL((k_stencil_dual<TQ, T, false, false, TC>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
                            part_t, status);
     else if (sk.sketch == SK_SRHT)
-        hipLaunchKernelGGL((k_stencil_dual_sk<TQ, T, SK_SRHT>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
+        hipLaunchKernelGGL((k_stencil_dual_sk<TQ, T, SK_SRHT, TC>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk, part_x,
                            part_t, status);
     else if (sk.sketch == SK_RADEM)
-        hipLaunchKernelGGL((k_stencil_dual_sk<TQ, T, SK_RADEM>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk,
+        hipLaunchKernelGGL((k_stencil_dual_sk<TQ, T, SK_RADEM, TC>), grid, thr, 0, st, xs, grid3(A), n, t_out, sk,
                            part_x, part_t, status);
     else
         return false;
@@ -1145,12 +1146,17 @@ bool launch_gbatch_residual(hipStream_t st, const GmresItem* gi, const BlockMap&
     return true;
 }
 
-template bool launch_stencil_sketch<float, float>(hipStream_t, const StencilArgs&, const float*, const double*,
-                                                  float*, int, const SketchArgs&, float*, const int*);
-template bool launch_stencil_sketch<double, double>(hipStream_t, const StencilArgs&, const double*, const double*,
-                                                    double*, int, const SketchArgs&, double*, const int*);
-template bool launch_stencil_sketch<bf16, float>(hipStream_t, const StencilArgs&, const bf16*, const double*,
-                                                 float*, int, const SketchArgs&, float*, const int*);
+template bool launch_stencil_sketch<float, float, float>(hipStream_t, const StencilArgs&, const float*,
+                                                         const double*, float*, int, const SketchArgs&, float*,
+                                                         const int*);
+template bool launch_stencil_sketch<float, float, double>(hipStream_t, const StencilArgs&, const float*,
+                                                          const double*, float*, int, const SketchArgs&, float*,
+                                                          const int*);
+template bool launch_stencil_sketch<double, double, double>(hipStream_t, const StencilArgs&, const double*,
+                                                            const double*, double*, int, const SketchArgs&,
+                                                            double*, const int*);
+template bool launch_stencil_sketch<bf16, float, float>(hipStream_t, const StencilArgs&, const bf16*, const double*,
+                                                        float*, int, const SketchArgs&, float*, const int*);
 template bool launch_cast<float>(hipStream_t, const double*, float*, int64_t);
 template bool launch_cast<double>(hipStream_t, const double*, double*, int64_t);
 template bool launch_update_x<float>(hipStream_t, const double*, int, const double*, const int*, double*, double*,
@@ -1173,12 +1179,14 @@ template bool launch_gbatch_project<float, bf16, true>(hipStream_t, int, const B
                                                        const BlockMap&, int64_t, int);
 template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
 template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
-template bool launch_stencil_dual<float, float>(hipStream_t, const StencilArgs&, const float*, float*,
-                                                const SketchArgs&, float*, float*, const int*);
-template bool launch_stencil_dual<double, double>(hipStream_t, const StencilArgs&, const double*, double*,
-                                                  const SketchArgs&, double*, double*, const int*);
-template bool launch_stencil_dual<bf16, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
-                                               const SketchArgs&, float*, float*, const int*);
+template bool launch_stencil_dual<float, float, float>(hipStream_t, const StencilArgs&, const float*, float*,
+                                                       const SketchArgs&, float*, float*, const int*);
+template bool launch_stencil_dual<float, float, double>(hipStream_t, const StencilArgs&, const float*, float*,
+                                                        const SketchArgs&, float*, float*, const int*);
+template bool launch_stencil_dual<double, double, double>(hipStream_t, const StencilArgs&, const double*, double*,
+                                                          const SketchArgs&, double*, double*, const int*);
+template bool launch_stencil_dual<bf16, float, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
+                                                      const SketchArgs&, float*, float*, const int*);
 template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool);
 template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
                                                          const BlockMap&, int64_t, int, bool);

@@ -114,12 +114,14 @@ bool launch_theta_tabx(hipStream_t st, const SketchArgs& sk, int64_t n, T* table
 bool launch_dgemm(hipStream_t st, bool transA, int M, int N, int K, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double* C, int64_t ldc);
 
-template <typename TQ, typename T>
+// TC: the arithmetic of the product with A (T; fp64 for the configuration of
+// Sec. 5.3, the result rounded once to T).
+template <typename TQ, typename T, typename TC = T>
 bool launch_stencil_sketch(hipStream_t st, const StencilArgs& A, const TQ* qs, const double* invr, T* w,
                            int do_sketch, const SketchArgs& sk, T* partials, const int* status);
 // Gaussian, fused-sketch Arnoldi step: t = A xs and the block partials of both
 // sketches (xs: part_x, t: part_t) from one generation of Theta.
-template <typename TQ, typename T>
+template <typename TQ, typename T, typename TC = T>
 bool launch_stencil_dual(hipStream_t st, const StencilArgs& A, const TQ* xs, T* t_out, const SketchArgs& sk,
                          T* part_x, T* part_t, const int* status);
 bool launch_residual(hipStream_t st, const StencilArgs& A, const double* b, const double* x, double* r,
@@ -134,7 +136,8 @@ bool launch_update_x(hipStream_t st, const double* Hr, int mcap, const double* g
                      double* x, const TQ* Q, int64_t ldq, int64_t n, const double* invr);
 // Step 2 when the right-hand side arrives as block partials (Arnoldi): reduce to
 // a.pbuf, then the least-squares solve of column i (R(0:i, i) and coef).
-template <typename T, typename PT>
+// TS: the arithmetic of the sketch space (fp64; float32 for the unique-precision model).
+template <typename T, typename PT, typename TS = double>
 bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
                         double* R, int64_t ldr, T* coef, const double* cscale, const double* scale2);
 

@@ -1231,12 +1231,12 @@ __global__ __launch_bounds__(kGW) void k_ls1(const double* __restrict__ p, int k
     for (int c = threadIdx.x; c <= i; c += kGW) out[c] = (c < i) ? slice_dot(Wr, mcap, r0, k, xs, c) : slice_sq(xs);
 }
 
-__global__ __launch_bounds__(kGW) void k_ls2(const double* __restrict__ p, int k, int i, int nsl,
-                                             const double* __restrict__ Vc, int mcap,
-                                             const double* __restrict__ pd, double* __restrict__ uh,
-                                             double* __restrict__ pnorm) {
-    extern __shared__ double cp[];  // [i + 1]
-    ls2_body(p, k, i, nsl, Vc, mcap, pd, uh, pnorm, blockIdx.x, cp);
+template <typename TS = double>
+__global__ __launch_bounds__(kGW) void k_ls2(const TS* __restrict__ p, int k, int i, int nsl,
+                                             const TS* __restrict__ Vc, int mcap, const TS* __restrict__ pd,
+                                             TS* __restrict__ uh, TS* __restrict__ pnorm) {
+    extern __shared__ double cp_raw[];  // [i + 1]
+    ls2_body<kGW, TS>(p, k, i, nsl, Vc, mcap, pd, uh, pnorm, blockIdx.x, reinterpret_cast<TS*>(cp_raw));
 }
 
 // The single-factorisation column-step kernels.  TS is the arithmetic of the
@@ -1693,8 +1693,8 @@ bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, doubl
     hipLaunchKernelGGL(k_ls1, dim3(nsl), dim3(kGW), 0, st, p, a.k, i, a.Wr, a.mcap, a.pd);
     RGS_LAUNCH_CHECK();
     const unsigned nrb = nblocks(i, 64);
-    hipLaunchKernelGGL(k_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, p, a.k, i, nsl, a.Vc, a.mcap,
-                       a.pd, a.uh, a.pnorm);
+    hipLaunchKernelGGL(k_ls2<double>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, p, a.k, i, nsl, a.Vc,
+                       a.mcap, a.pd, a.uh, a.pnorm);
     RGS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, a.X, a.mcap, a.uh, R,
                        ldr, coef, (const double*)nullptr);
@@ -1702,19 +1702,20 @@ bool launch_ls(hipStream_t st, const SpaceArgs& a, const double* p, int i, doubl
     return true;
 }
 
-template <typename T, typename PT>
+template <typename T, typename PT, typename TS>
 bool launch_ls_partials(hipStream_t st, const SpaceArgs& a, const PT* partials, int G, double scale, int i,
                         double* R, int64_t ldr, T* coef, const double* cscale, const double* scale2) {
     const int nsl = (a.k + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_qa<PT>, dim3(nsl), dim3(kGW), 0, st, partials, G, scale, (const double*)nullptr, a.k, i,
-                       a.Wr, a.mcap, a.pbuf, a.pd, scale2);
+    auto ws = [](double* p) { return reinterpret_cast<TS*>(p); };   // the workspace in the sketch-space type
+    hipLaunchKernelGGL((k_qa<PT, kGW, TS>), dim3(nsl), dim3(kGW), 0, st, partials, G, scale, (const double*)nullptr,
+                       a.k, i, ws(a.Wr), a.mcap, ws(a.pbuf), ws(a.pd), scale2, 0);
     RGS_LAUNCH_CHECK();
     const unsigned nrb = nblocks(i, 64);
-    hipLaunchKernelGGL(k_ls2, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, a.pbuf, a.k, i, nsl, a.Vc,
-                       a.mcap, a.pd, a.uh, a.pnorm);
+    hipLaunchKernelGGL(k_ls2<TS>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, ws(a.pbuf), a.k, i, nsl,
+                       ws(a.Vc), a.mcap, ws(a.pd), ws(a.uh), ws(a.pnorm));
     RGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ls3<T>, dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, a.X, a.mcap, a.uh, R,
-                       ldr, coef, cscale);
+    hipLaunchKernelGGL((k_ls3<T, kGW, TS>), dim3(nrb), dim3(kGW), (i + 1) * sizeof(double), st, i, i, ws(a.X),
+                       a.mcap, ws(a.uh), R, ldr, coef, cscale);
     RGS_LAUNCH_CHECK();
     return true;
 }
@@ -1966,6 +1967,8 @@ template bool launch_ls_partials<float, float>(hipStream_t, const SpaceArgs&, co
                                                double*, int64_t, float*, const double*, const double*);
 template bool launch_ls_partials<double, double>(hipStream_t, const SpaceArgs&, const double*, int, double, int,
                                                  double*, int64_t, double*, const double*, const double*);
+template bool launch_ls_partials<float, float, float>(hipStream_t, const SpaceArgs&, const float*, int, double, int,
+                                                      double*, int64_t, float*, const double*, const double*);
 template bool launch_ls_partials_richardson<float, float>(hipStream_t, const SpaceArgs&, const float*, int, double,
                                                           int, double*, int64_t, double*, int64_t, float*,
                                                           const double*, const double*, int);

@@ -119,18 +119,19 @@ __device__ __forceinline__ TS combine16(TS (*red)[64], int rl) {
 
 // Step 2, part 2: c = sum of slice partials; head of U_i^T p:
 //   uh[r] = p[r] - sum_{c <= r} V[r, c] c[c],  r < i.
-template <int NT = kGW>
-__device__ __forceinline__ void ls2_body(const double* __restrict__ p, int k, int i, int nsl,
-                                         const double* __restrict__ Vc, int mcap, const double* __restrict__ pd,
-                                         double* __restrict__ uh, double* __restrict__ pnorm, int bid,
-                                         double* __restrict__ cp) {
-    __shared__ double red[kGQ][64];
+template <int NT = kGW, typename TS = double>
+__device__ __forceinline__ void ls2_body(const TS* __restrict__ p, int k, int i, int nsl,
+                                         const TS* __restrict__ Vc, int mcap, const TS* __restrict__ pd,
+                                         TS* __restrict__ uh, TS* __restrict__ pnorm, int bid,
+                                         TS* __restrict__ cp) {
+    __shared__ TS red[kGQ][64];
     sum_slices(pd, nsl, mcap + 1, i + 1, cp);
     __syncthreads();
     if (bid == 0 && threadIdx.x == 0) pnorm[i] = sqrt(cp[i]);
     const int rl = threadIdx.x & 63, q0 = threadIdx.x >> 6;
     const int r = bid * 64 + rl;
-    for (int q = q0; q < kGQ; q += NT / 64) red[q][rl] = (r < i) ? row_part(Vc, k, r, 0, min(r, i - 1) + 1, cp, q) : 0.0;
+    for (int q = q0; q < kGQ; q += NT / 64)
+        red[q][rl] = (r < i) ? row_part(Vc, k, r, 0, min(r, i - 1) + 1, cp, q) : TS(0);
     __syncthreads();
     if (q0 == 0 && r < i) uh[r] = p[r] - combine16(red, rl);
 }

@@ -13,7 +13,8 @@ oracle's 'fp32u' model on the same W and Theta.
   steps can have); S R = Theta W and Q = W R^-1 to float32 rounding; and the
   rounding of the sketch-space steps is at the float32 level (the device sits
   farther from the fp64 result than the multi-precision 'fp32' does).
-* Rejected: Richardson sweeps, GMRES and the batched calls.
+* Rejected: Richardson sweeps and the batched calls (GMRES takes the precision
+  in the configuration of Sec. 5.3, test_gpu_gmres_unique.py).
 """
 
 import math
@@ -146,12 +147,7 @@ def test_unique_precision_rejections(gpu_handle):
     with pytest.raises(rgs.RgsError) as e:
         rgs.rgs_qr_batched(gpu_handle, [(W, Q, R, S, k)], sketch="srht", prec="fp32u")
     assert e.value.status == rgs.RGS_EINVAL
-    dims, coeffs = synth.convdiff_coeffs(16, 10.0)
-    b = torch.from_numpy(synth.rhs(16 ** 3, tag=0)).cuda()
-    x = torch.empty_like(b)
-    with pytest.raises(rgs.RgsError) as e:
-        rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs), rgs.gmres_desc(10, 40, 1e-6, prec="fp32u"), b, x)
-    assert e.value.status == rgs.RGS_EINVAL
+    # (rgs_gmres takes the precision in the configuration of Sec. 5.3: test_gpu_gmres_unique.py)
 
 
 def test_unique_precision_breakdown_and_nonfinite(gpu_handle):
