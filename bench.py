@@ -362,6 +362,14 @@ def small_fp64_leg(rgs, torch, synth, h, n=16384, m=64, k=256, steps=20, warmup=
     out["graph"] = {"ms_per_qr": ms_g, "us_per_column": 1000.0 * ms_g / m, "status": rep_g.status,
                     "backward_error": res_g}
     log("  same, graph-replayed: %.3f ms/QR (%.1f us/column)" % (ms_g, 1000.0 * ms_g / m))
+    # the same sketch read from the table of its exact fp64 entries (made once per call)
+    for key, fl in (("exact_table", rgs.FLAG_THETA_EXACT), ("exact_table_graph", rgs.FLAG_THETA_EXACT | rgs.FLAG_GRAPH)):
+        dx = rgs.qr_desc(n, m, k, sketch="gaussian", prec="fp64", flags=fl)
+        ms_x, _, rep_x = run_steps(rgs, torch, h, dx, W, Q, R, S, steps, warmup)
+        res_x, _, _ = quality(torch, W, Q, R, S)
+        out[key] = {"ms_per_qr": ms_x, "us_per_column": 1000.0 * ms_x / m, "status": rep_x.status,
+                    "backward_error": res_x}
+        log("  same, %s: %.3f ms/QR (%.1f us/column)" % (key.replace("_", " "), ms_x, 1000.0 * ms_x / m))
     return out
 
 
