@@ -633,10 +633,11 @@ __device__ __forceinline__ void xupdate_body(double* __restrict__ x, const TQ* _
 // ---------------------------------------------------------------------------
 // Single-system kernels
 // ---------------------------------------------------------------------------
-// (at most 80 registers, 6 waves per SIMD: 28.3 instead of 30.6 us per fp32
-// launch at 192^3; the dual kernels are faster without the cap)
+// (fp32: at most 80 registers, 6 waves per SIMD: 28.3 instead of 30.6 us per
+// launch at 192^3; the dual kernels are faster without the cap, and fp64 blocks
+// are held to fewer waves by their LDS anyway)
 template <typename TQ, typename T, typename PT, int SK, typename TC = T>
-__global__ __launch_bounds__(kProjWaves * kWave, 6) void k_stencil_sketch(
+__global__ __launch_bounds__(kProjWaves * kWave, sizeof(T) == 4 ? 6 : 1) void k_stencil_sketch(
     const TQ* __restrict__ qs, const double* __restrict__ invr, Grid3 g, int64_t n, T* __restrict__ w,
     int do_sketch, SketchArgs sk, PT* __restrict__ partials, const int* __restrict__ status) {
     __shared__ T lds[kProjWaves * kTile];
