@@ -165,6 +165,28 @@ def test_exact_rgmres_matches_drawn(gpu_handle, prec, reuse):
         np.testing.assert_allclose(h1[:L], ref["hist"][:L], rtol=1e-8)
 
 
+def test_exact_rgmres_certificate_matches_drawn(gpu_handle):
+    """RGS_FLAG_CERTIFY with the exact table in rgs_gmres: Theta read from the
+    table (the same sketch), Phi drawn; the certificate equals the drawn run's."""
+    rgs = _rgs()
+    N, restart, k = 20, 150, 300
+    dims, coeffs = synth.convdiff_coeffs(N, 50.0)
+    b = torch.from_numpy(synth.rhs(N ** 3, tag=87)).cuda()
+    reps = []
+    for flags in (rgs.FLAG_CERTIFY, rgs.FLAG_CERTIFY | rgs.FLAG_THETA_EXACT):
+        x = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+        rep, _ = rgs.rgs_gmres(gpu_handle, rgs.stencil7(dims, coeffs),
+                               rgs.gmres_desc(restart, k, 1e-6, sketch="gaussian", prec="fp64", flags=flags), b, x)
+        torch.cuda.synchronize()
+        assert rep.status == 0
+        reps.append(rep)
+    r0, r1 = reps
+    assert r0.iters == r1.iters
+    for a, c in ((r1.cert_smin_q, r0.cert_smin_q), (r1.cert_smax_q, r0.cert_smax_q),
+                 (r1.cert_cond_phi_q, r0.cert_cond_phi_q)):
+        assert np.isfinite(a) and abs(a - c) <= 1e-8 * abs(c)
+
+
 def test_exact_flag_rejections(gpu_handle):
     rgs = _rgs()
     n, m, k = 1000, 4, 32
