@@ -196,7 +196,7 @@ typedef struct {
                            least-squares solver): 0 = Householder QR of S; 1..8 = that many Richardson
                            iterations on the normal equations, y = S^T p then y += S^T (p - S y), the first
                            being the sketched classical Gram-Schmidt; EINVAL above 8.  rgs_gmres_batched:
-                           must be 0 */
+                           the same (every system, with the single solver's bits) */
 } rgs_gmres_desc;
 
 typedef struct {

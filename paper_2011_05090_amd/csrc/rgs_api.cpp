@@ -2146,9 +2146,24 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         return tab ? launch_gbatch_stencil_dual_rows<T, TQ>(q, itd, gid, M.pairs, (int64_t)M.gm.pairs.size(), ii)
                    : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(M), n_proj(M), ii, false);
     };
+    // step 2: Householder (the compact-WY chain) or ls_sweeps Richardson sweeps
+    const int sweeps = (int)d->ls_sweeps;
     auto enqueue_cycle = [&](hipStream_t q, const MapAt& M) -> bool {
         const int nsl = M.gm.nsl, cnt = M.gm.count();
         const BlockMap none{nullptr, nullptr, 0, 0};
+        auto ls_step = [&](int ii, int dualflag) {
+            const int rbl = (ii + 63) / 64, rbs = (ii + kRsumCoefs - 1) / kRsumCoefs;
+            return sweeps > 0 ? launch_gbatch_ls_richardson<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbs),
+                                                               n_uni(M, rbs), ii, dualflag, sweeps)
+                              : launch_gbatch_ls<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl),
+                                                    n_uni(M, rbl), ii, dualflag);
+        };
+        auto column_step = [&](int ii) {
+            const int rbq = (ii + 1 + 63) / 64;   // column-step blocks beyond the slices
+            return sweeps > 0 ? launch_gbatch_column_richardson<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), ii)
+                              : launch_batch_column<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + rbq),
+                                                       n_uni(M, nsl + rbq), none, 0, ii);
+        };
         if (!launch_gbatch_reset(q, itd, m_sys(M), cnt)) return false;
         if (!launch_gbatch_cast<T>(q, gid, m_row(M), n_row(M))) return false;
         if (dual) {
@@ -2157,29 +2172,21 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         } else if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), 0)) {
             return false;
         }
-        if (!launch_batch_column<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + 1), n_uni(M, nsl + 1), none,
-                                    0, 0))
-            return false;
+        if (!column_step(0)) return false;
         if (!launch_gbatch_givens_init(q, itd, gid, m_sys(M), cnt)) return false;
         for (int64_t i = 1; i <= restart; ++i) {
             const int ii = (int)i;
-            const int rbl = (int)((i + 63) / 64);       // row blocks of the i x i solve
-            const int rbq = (int)((i + 1 + 63) / 64);   // column-step blocks beyond the slices
             if (dual) {
-                if (!launch_gbatch_ls<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl), n_uni(M, rbl), ii, 1) ||
-                    !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(M), n_proj(M), ii) ||
+                if (!ls_step(ii, 1) || !launch_gbatch_project_ws<T, TQ, DEFER>(q, itd, gid, m_proj(M), n_proj(M), ii) ||
                     !dual_step(q, M, ii))
                     return false;
             } else {
                 if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii)) return false;
-                if (!launch_gbatch_ls<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl), n_uni(M, rbl), ii, 0))
-                    return false;
+                if (!ls_step(ii, 0)) return false;
                 if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii))
                     return false;
             }
-            if (!launch_batch_column<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + rbq),
-                                        n_uni(M, nsl + rbq), none, 0, ii))
-                return false;
+            if (!column_step(ii)) return false;
             if (!launch_gbatch_givens(q, itd, gid, m_sys(M), cnt, ii)) return false;
         }
         return launch_gbatch_finish<TQ>(q, itd, gid, m_sys(M), cnt, m_row(M), n_row(M));
@@ -2648,7 +2655,6 @@ rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     if (d->prec == RGS_P_FP32) return RGS_EINVAL;   // the unique-precision model: rgs_gmres only
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16)) != 0) return RGS_EINVAL;
-    if (d->ls_sweeps != 0) return RGS_EINVAL;   // the batched solves keep the Householder least squares
     if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     for (int64_t b = 0; b < batch; ++b) {
         const rgs_gmres_item& it = items[b];

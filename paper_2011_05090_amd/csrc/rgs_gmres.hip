@@ -860,6 +860,57 @@ __global__ __launch_bounds__(kGWB) void kg_ls3(const BatchItem* __restrict__ ite
                       bm.y, us);
 }
 
+// Step 2 by Richardson sweeps on the normal equations (ls_sweeps > 0; the
+// bodies and workgroup size of the single-system kernels, so a batched solve
+// keeps the bits of separate ones): the reduction of kg_lsa into the slice
+// partials of S^T p and ||p||^2 (stride mcap + 2), ...
+template <typename PT>
+__global__ __launch_bounds__(kGW) void kg_lsr(const BatchItem* __restrict__ items, BlockMap map, int i, int dual) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    qa_body<PT, kGW>(static_cast<const PT*>(dual ? it.part2 : it.part), it.nproj, it.sketch_scale, nullptr, a.k, i,
+                     a.Wr, a.mcap, a.pbuf, a.pdb, bm.y, dual ? a.invr + (i - 1) : nullptr, a.mcap + 2);
+}
+
+// ... the sums of a sweep (y, R(0:i+1, i+1) and the coefficients after the last) ...
+template <typename T>
+__global__ __launch_bounds__(kGW) void kg_rsum(const BatchItem* __restrict__ items, BlockMap map, int i,
+                                              int accumulate, int last) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    rsum_body<T>(i, it.nsl, a.mcap, a.pdb, a.uh, accumulate, last, a.pnorm, it.R, it.ldr, static_cast<T*>(it.coef),
+                 it.defer ? a.invr : nullptr, bm.y);
+}
+
+// ... the residual partials of one more sweep ...
+__global__ __launch_bounds__(kGW) void kg_rres(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    rres_body(a.k, i, a.mcap, it.S, it.lds, a.Wr, a.pbuf, a.uh, a.pdb, bm.y);
+}
+
+// ... and the column step: s' and the slice partials of ||s'||^2, then r_ii,
+// s_i (both layouts) and the breakdown test.
+template <typename PT>
+__global__ __launch_bounds__(kGW) void kg_rqa(const BatchItem* __restrict__ items, BlockMap map) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    qa_body<PT, kGW>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, nullptr, a.k, 0, a.Wr, a.mcap, a.sp,
+                     a.pd, bm.y);
+}
+
+__global__ __launch_bounds__(kGW) void kg_rb(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    rb_body(a.k, i, it.nsl, a.sp, a.pd, a.mcap, it.S, it.lds, a.Wr, it.R, it.ldr, a.rr, a.invr, a.pnorm, a.status,
+            nullptr, a.pdb, bm.y);
+}
+
 __global__ void kg_givens_init(const BatchItem* __restrict__ items, const GmresItem* __restrict__ gi,
                                BlockMap map) {
     const int2 bm = locate(map, blockIdx.x);
@@ -1110,6 +1161,38 @@ bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& ma
     return true;
 }
 
+static_assert(kRsumCoefs == kGW, "a kg_rsum workgroup sums kGW coefficients");
+
+template <typename T>
+bool launch_gbatch_ls_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl,
+                                 const BlockMap& map_rs, int64_t nrs, int i, int dual, int sweeps) {
+    if (nsl == 0) return true;
+    if (i < 1 || sweeps < 1) return false;
+    hipLaunchKernelGGL(kg_lsr<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i, dual);
+    RGS_LAUNCH_CHECK();
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const int last = sw + 1 == sweeps;
+        hipLaunchKernelGGL(kg_rsum<T>, dim3(nrs), dim3(kGW), 0, st, items, map_rs, i - 1, sw > 0 ? 1 : 0, last);
+        RGS_LAUNCH_CHECK();
+        if (!last) {
+            hipLaunchKernelGGL(kg_rres, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i - 1);
+            RGS_LAUNCH_CHECK();
+        }
+    }
+    return true;
+}
+
+template <typename T>
+bool launch_gbatch_column_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl,
+                                     int i) {
+    if (nsl == 0) return true;
+    hipLaunchKernelGGL(kg_rqa<T>, dim3(nsl), dim3(kGW), 0, st, items, map_sl);
+    RGS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kg_rb, dim3(nsl), dim3(kGW), 0, st, items, map_sl, i);
+    RGS_LAUNCH_CHECK();
+    return true;
+}
+
 bool launch_gbatch_givens_init(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_sys,
                                int64_t nsys) {
     if (nsys == 0) return true;
@@ -1179,6 +1262,12 @@ template bool launch_gbatch_project<double, double, false>(hipStream_t, int, con
 template bool launch_gbatch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const GmresItem*,
                                                        const BlockMap&, int64_t, int);
 template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
+template bool launch_gbatch_ls_richardson<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,
+                                                 const BlockMap&, int64_t, int, int, int);
+template bool launch_gbatch_ls_richardson<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,
+                                                  const BlockMap&, int64_t, int, int, int);
+template bool launch_gbatch_column_richardson<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, int);
+template bool launch_gbatch_column_richardson<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, int);
 template bool launch_gbatch_ls<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
 template bool launch_stencil_dual<float, float, float>(hipStream_t, const StencilArgs&, const float*, float*,
                                                        const SketchArgs&, float*, float*, const int*);

@@ -158,6 +158,16 @@ bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, c
 template <typename T>
 bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl, const BlockMap& map_rb,
                       int64_t nrb, int i, int dual);
+// The same step, and the column step, with the least squares by `sweeps`
+// Richardson iterations on the normal equations (map_rs: blocks of
+// kRsumCoefs coefficients per system).
+constexpr int kRsumCoefs = 1024;
+template <typename T>
+bool launch_gbatch_ls_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl,
+                                 const BlockMap& map_rs, int64_t nrs, int i, int dual, int sweeps);
+template <typename T>
+bool launch_gbatch_column_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl,
+                                     int i);
 template <typename T, typename TQ>
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                                 int64_t nproj, int i, bool table);

@@ -212,7 +212,7 @@ def test_richardson_sweeps_rejected(gpu_handle):
     assert e.value.status == rgs.RGS_EINVAL
     with pytest.raises(rgs.RgsError) as e:
         rgs.rgs_gmres_batched(gpu_handle, [(rgs.stencil7(dims, coeffs), b, x)],
-                              rgs.gmres_desc(5, 32, 1e-6, ls_sweeps=1))
+                              rgs.gmres_desc(5, 32, 1e-6, ls_sweeps=9))
     assert e.value.status == rgs.RGS_EINVAL
 
 

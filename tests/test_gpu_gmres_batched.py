@@ -3,7 +3,9 @@ bf16-basis RGMRES.
 
 * every system of a batched solve equals a separate rgs_gmres call on it bit
   for bit (x, residual history, iteration and cycle counts), for both
-  sketches and the fp64 / fp32 / bf16 bases, with a fresh sketch per cycle;
+  sketches and the fp64 / fp32 / bf16 bases, with a fresh sketch per cycle,
+  with the Householder least squares and with one or two Richardson sweeps
+  (ls_sweeps, eager and graph-replayed);
 * the graph-replayed cycles equal the eagerly launched ones bit for bit (the
   graph is replayed once per cycle, and re-captured when systems drop out);
 * against the oracle: fp64 and fp32 bases converge within +-2 iterations of
@@ -77,6 +79,28 @@ def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec, table):
     desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec,
                           flags=rgs.FLAG_THETA_BF16 if table else 0)
     st, stat, reps, hists, xs = _batched(gpu_handle, systems, desc)
+    assert st == 0 and stat == [0] * len(systems)
+    for sysm, rep, hist, x in zip(systems, reps, hists, xs):
+        rep1, hist1, x1 = _single(gpu_handle, sysm, desc)
+        assert rep1.status == 0
+        assert (rep.iters, rep.cycles) == (rep1.iters, rep1.cycles)
+        assert rep.true_relres == rep1.true_relres
+        assert hist == hist1
+        assert torch.equal(x, x1)
+
+
+@pytest.mark.parametrize("sketch,prec,sweeps,graph", [("srht", "fp32", 1, False), ("srht", "fp64", 2, False),
+                                                      ("gaussian", "fp32", 2, False), ("gaussian", "bf16q", 2, True),
+                                                      ("srht", "bf16q", 2, True)])
+def test_batched_richardson_equals_single_calls_bitwise(gpu_handle, sketch, prec, sweeps, graph):
+    """Step 2 by Richardson sweeps on the normal equations in the batched
+    solver: the single solver's bodies and workgroups, so the same bits."""
+    rgs = _rgs()
+    systems = _systems(6, tag=5)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, ls_sweeps=sweeps)
+    bdesc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec, ls_sweeps=sweeps,
+                           flags=rgs.FLAG_GRAPH if graph else 0)
+    st, stat, reps, hists, xs = _batched(gpu_handle, systems, bdesc)
     assert st == 0 and stat == [0] * len(systems)
     for sysm, rep, hist, x in zip(systems, reps, hists, xs):
         rep1, hist1, x1 = _single(gpu_handle, sysm, desc)
