@@ -589,6 +589,19 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
                                      "max_true_relres": max(r.true_relres for r in reps)}
     log("  batched rgmres srht/bf16q, 2 Richardson sweeps, x%d: %.3f s, %d converged, %d iterations in all" %
         (len(systems), dt, out["srht_richardson2_bf16q"]["converged"], out["srht_richardson2_bf16q"]["total_iters"]))
+    # the same with the lagged Arnoldi step (RGS_FLAG_LAG: both sketches of a step in the mat-vec pass)
+    d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec="bf16q",
+                       flags=rgs.FLAG_GRAPH | rgs.FLAG_LAG)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stat, reps, _ = rgs.rgs_gmres_batched(h, systems, d)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["srht_lag_bf16q"] = {"seconds_to_tol": dt, "status": st, "converged": sum(1 for v in stat if v == 0),
+                             "total_iters": int(sum(r.iters for r in reps)),
+                             "max_true_relres": max(r.true_relres for r in reps)}
+    log("  batched rgmres srht/bf16q, lagged step, x%d: %.3f s, %d converged, %d iterations in all" %
+        (len(systems), dt, out["srht_lag_bf16q"]["converged"], out["srht_lag_bf16q"]["total_iters"]))
     return out
 
 

@@ -127,8 +127,9 @@ typedef enum {
                                     drawn again.  A different (still i.i.d., entries within 2^-8
                                     relative of N(0,1/k)) sketch from the GAUSSIAN one */
 
-#define RGS_FLAG_LAG 32u         /* rgs_gmres with SRHT or RADEMACHER: the lagged Arnoldi step (the
-                                    lagged normalisation of Sec. 2.4) -- the mat-vec kernel computes
+#define RGS_FLAG_LAG 32u         /* rgs_gmres with SRHT or RADEMACHER, rgs_gmres_batched with SRHT:
+                                    the lagged Arnoldi step (the lagged normalisation of Sec. 2.4)
+                                    -- the mat-vec kernel computes
                                     t = A q'_i from the stored, unnormalised q'_i and sketches q'_i
                                     and t in the same pass, so r_ii = ||Theta q'_i|| and
                                     p_{i+1} = Theta t / r_ii come out of one reduction, and the
@@ -191,7 +192,7 @@ typedef struct {
     int32_t reuse_theta;/* 0: cycle c uses sketch_id 2+c (fresh Theta); 1: always sketch_id 2 */
     uint32_t flags;     /* rgs_gmres: RGS_FLAG_THETA_BF16, RGS_FLAG_THETA_EXACT, RGS_FLAG_LAG and
                            RGS_FLAG_CERTIFY (other bits: EINVAL);
-                           rgs_gmres_batched: RGS_FLAG_GRAPH and/or RGS_FLAG_THETA_BF16 */
+                           rgs_gmres_batched: RGS_FLAG_GRAPH, RGS_FLAG_THETA_BF16, RGS_FLAG_LAG */
     uint32_t ls_sweeps; /* rgs_gmres: step 2 of every Arnoldi step (Alg. 3 on RGS, Sec. 2.3's remark on the
                            least-squares solver): 0 = Householder QR of S; 1..8 = that many Richardson
                            iterations on the normal equations, y = S^T p then y += S^T (p - S y), the first

@@ -1902,6 +1902,8 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     // Gaussian sketch with bf16 entries: entry (j, l) does not depend on n, so
     // one table over the largest n serves every system of the cycle
     const bool tab = (d->flags & RGS_FLAG_THETA_BF16) != 0;
+    // RGS_FLAG_LAG with the P-SRHT: the lagged step (the Gaussian sketch takes it anyway)
+    const bool lag = (d->flags & RGS_FLAG_LAG) != 0 && sk_kind == SK_SRHT;
     std::vector<int64_t> ns((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) grid_size(items[b].A, &ns[b]);
     const int64_t nmax = *std::max_element(ns.begin(), ns.end());
@@ -1923,7 +1925,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
         o.R = c.take<double>(mcap * mcap);
         o.S = c.take<double>(k * mcap);
         o.part = c.take<T>(nproj * k);
-        o.part2 = c.take<T>(sk_kind == SK_GAUSS ? nproj * k : 1);
+        o.part2 = c.take<T>(sk_kind == SK_GAUSS || lag ? nproj * k : 1);
         o.coef = c.take<T>(mcap);
         o.Vc = c.take<double>(k * mcap);
         o.Vr = c.take<double>(k * mcap);
@@ -2139,12 +2141,14 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     auto drop_graphs = [&]() {
         for (GShare& g : sh) drop_graph(g);
     };
-    const bool dual = sk_kind == SK_GAUSS;   // the two sketches of an Arnoldi step share their draws
+    // the two sketches of an Arnoldi step in the mat-vec pass: the Gaussian sketch
+    // (they share their draws), or the P-SRHT with the lagged step
+    const bool dual = sk_kind == SK_GAUSS || lag;
     // the dual mat-vec + sketch step: with the bf16 table in row-block-major
     // order (the systems share the table's entries), else system by system
     auto dual_step = [&](hipStream_t q, const MapAt& M, int ii) -> bool {
         return tab ? launch_gbatch_stencil_dual_rows<T, TQ>(q, itd, gid, M.pairs, (int64_t)M.gm.pairs.size(), ii)
-                   : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(M), n_proj(M), ii, false);
+                   : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(M), n_proj(M), ii, false, lag);
     };
     // step 2: Householder (the compact-WY chain) or ls_sweeps Richardson sweeps
     const int sweeps = (int)d->ls_sweeps;
@@ -2654,7 +2658,7 @@ rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
     if (d->prec == RGS_P_FP32) return RGS_EINVAL;   // the unique-precision model: rgs_gmres only
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
-    if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16)) != 0) return RGS_EINVAL;
+    if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16 | RGS_FLAG_LAG)) != 0) return RGS_EINVAL;
     if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
     for (int64_t b = 0; b < batch; ++b) {
         const rgs_gmres_item& it = items[b];

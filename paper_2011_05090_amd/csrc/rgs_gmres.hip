@@ -769,6 +769,22 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const Batc
                              lds);
 }
 
+// The lagged P-SRHT step (RGS_FLAG_LAG): t = A q'_i and the block partials of
+// both sketches, the body of k_stencil_dual_sk.
+template <typename TQ, typename T>
+__global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_sk(const BatchItem* __restrict__ items,
+                                                                         const GmresItem* __restrict__ gi,
+                                                                         BlockMap map, int i) {
+    __shared__ T lds[kProjWaves * kTile];
+    const int2 bm = locate(map, xcd_block(blockIdx.x, gridDim.x));
+    const BatchItem& it = items[bm.x];
+    RGS_EXIT_IF_STOPPED(it.sa.status);
+    const GmresItem& g = gi[bm.x];
+    stencil_dual_sk_body<TQ, T, SK_SRHT>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+                                         static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part),
+                                         static_cast<T*>(it.part2), bm.y, lds);
+}
+
 // The bf16-table variant with the L2 in mind: workgroup b -> (row block r,
 // system) from a host-built list.  The table's entries do not depend on the
 // system, so every system with a row block r reads the same k x kProjRows
@@ -1100,9 +1116,12 @@ bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, c
 
 template <typename T, typename TQ>
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
-                                int64_t nproj, int i, bool table) {
+                                int64_t nproj, int i, bool table, bool lag_srht) {
     if (nproj == 0) return true;
-    if (table)
+    if (lag_srht)
+        hipLaunchKernelGGL((kg_stencil_dual_sk<TQ, T>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
+                           map_proj, i);
+    else if (table)
         hipLaunchKernelGGL((kg_stencil_dual<TQ, T, true>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
                            map_proj, i);
     else
@@ -1277,10 +1296,10 @@ template bool launch_stencil_dual<double, double, double>(hipStream_t, const Ste
                                                           const SketchArgs&, double*, double*, const int*);
 template bool launch_stencil_dual<bf16, float, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
                                                       const SketchArgs&, float*, float*, const int*);
-template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool);
+template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool, bool);
 template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
-                                                         const BlockMap&, int64_t, int, bool);
-template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool);
+                                                         const BlockMap&, int64_t, int, bool, bool);
+template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool, bool);
 template bool launch_gbatch_stencil_dual_rows<float, float>(hipStream_t, const BatchItem*, const GmresItem*,
                                                             const int2*, int64_t, int);
 template bool launch_gbatch_stencil_dual_rows<double, double>(hipStream_t, const BatchItem*, const GmresItem*,

@@ -169,8 +169,9 @@ template <typename T>
 bool launch_gbatch_column_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl,
                                      int i);
 template <typename T, typename TQ>
+// (lag_srht: the lagged P-SRHT step of RGS_FLAG_LAG instead of the Gaussian one)
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
-                                int64_t nproj, int i, bool table);
+                                int64_t nproj, int i, bool table, bool lag_srht = false);
 template <typename T, typename TQ>
 bool launch_gbatch_stencil_dual_rows(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* pairs,
                                      int64_t npairs, int i);

@@ -5,7 +5,7 @@ bf16-basis RGMRES.
   for bit (x, residual history, iteration and cycle counts), for both
   sketches and the fp64 / fp32 / bf16 bases, with a fresh sketch per cycle,
   with the Householder least squares and with one or two Richardson sweeps
-  (ls_sweeps, eager and graph-replayed);
+  (ls_sweeps, eager and graph-replayed), and with the lagged P-SRHT step;
 * the graph-replayed cycles equal the eagerly launched ones bit for bit (the
   graph is replayed once per cycle, and re-captured when systems drop out);
 * against the oracle: fp64 and fp32 bases converge within +-2 iterations of
@@ -107,6 +107,26 @@ def test_batched_richardson_equals_single_calls_bitwise(gpu_handle, sketch, prec
         assert rep1.status == 0
         assert (rep.iters, rep.cycles) == (rep1.iters, rep1.cycles)
         assert rep.true_relres == rep1.true_relres
+        assert hist == hist1
+        assert torch.equal(x, x1)
+
+
+@pytest.mark.parametrize("prec,graph", [("fp32", False), ("fp64", False), ("bf16q", True)])
+def test_batched_lagged_step_equals_single_calls_bitwise(gpu_handle, prec, graph):
+    """RGS_FLAG_LAG with the P-SRHT in the batched solver: the mat-vec pass
+    sketches q'_i and A q'_i (the body of the single solver's lagged kernel),
+    so every system equals a separate lagged rgs_gmres call bit for bit."""
+    rgs = _rgs()
+    systems = _systems(6, tag=6)
+    desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch="srht", prec=prec, flags=rgs.FLAG_LAG)
+    bdesc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch="srht", prec=prec,
+                           flags=rgs.FLAG_LAG | (rgs.FLAG_GRAPH if graph else 0))
+    st, stat, reps, hists, xs = _batched(gpu_handle, systems, bdesc)
+    assert st == 0 and stat == [0] * len(systems)
+    for sysm, rep, hist, x in zip(systems, reps, hists, xs):
+        rep1, hist1, x1 = _single(gpu_handle, sysm, desc)
+        assert rep1.status == 0
+        assert (rep.iters, rep.cycles) == (rep1.iters, rep1.cycles)
         assert hist == hist1
         assert torch.equal(x, x1)
 
