@@ -450,7 +450,8 @@ def rademacher_leg(rgs, torch, synth, h, n=1 << 22, m=512, k=2048, steps=1, warm
 
 
 def batched_qr_leg(rgs, torch, synth, h, batch=2048,
-                   sketches=("srht", "gaussian", "gaussian_exact_table", "gaussian_bf16_table"), steps=2,
+                   sketches=("srht", "srht_richardson2", "gaussian", "gaussian_exact_table",
+                             "gaussian_bf16_table"), steps=2,
                    warmup=1, gaussian_batch=2048, graph=True):
     """Batched RGS QR: ``batch`` factorisations with n ~ U{4096..262144},
     m ~ U{16..128}, k = 4m, sigma 1..1e-6, fp32 W and bf16-stored Q, all in
@@ -460,8 +461,10 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048,
     into a table that the products read through bf16 matrix cores
     (RGS_FLAG_THETA_BF16), and with its exact fp32 entries made once per call
     into a table that the fp32 products read instead of drawing them
-    (RGS_FLAG_THETA_EXACT: the drawn call's bits).  With ``graph`` each sketch is timed again with
-    the calls replayed from captured graphs (RGS_FLAG_GRAPH)."""
+    (RGS_FLAG_THETA_EXACT: the drawn call's bits); ``srht_richardson2`` is the
+    P-SRHT with step 2 by two Richardson sweeps (RGS_FLAG_LS_SWEEPS(2)).  With
+    ``graph`` each sketch is timed again with the calls replayed from captured
+    graphs (RGS_FLAG_GRAPH)."""
     ns, ms_ = synth.batch_qr_sizes(batch)
     items = []
     t0 = time.perf_counter()
@@ -479,10 +482,11 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048,
     out = {"batch": batch, "n_range": [4096, 262144], "m_range": [16, 128], "k": "4m", "q_dtype": "bf16",
            "sigma_min": 1e-6}
     for sketch in sketches:
-        its = items if sketch == "srht" else items[:gaussian_batch]
+        lib_sketch = "srht" if sketch.startswith("srht") else "gaussian"
+        its = items if lib_sketch == "srht" else items[:gaussian_batch]
         B = sum(batched_qr_bytes(W.shape[0], W.shape[1]) for W, *_ in its)
-        lib_sketch = "srht" if sketch == "srht" else "gaussian"
-        flags = {"gaussian_bf16_table": rgs.FLAG_THETA_BF16, "gaussian_exact_table": rgs.FLAG_THETA_EXACT}.get(sketch, 0)
+        flags = {"gaussian_bf16_table": rgs.FLAG_THETA_BF16, "gaussian_exact_table": rgs.FLAG_THETA_EXACT,
+                 "srht_richardson2": rgs.flag_ls_sweeps(2)}.get(sketch, 0)
         for _ in range(warmup):
             rgs.rgs_qr_batched(h, its, sketch=lib_sketch, prec="bf16q", flags=flags)
         torch.cuda.synchronize()
@@ -510,7 +514,7 @@ def batched_qr_leg(rgs, torch, synth, h, batch=2048,
         for W, Q, R, S, _ in its[:: max(1, len(its) // 8)]:
             be, d2, _ = quality(torch, W, Q.float(), R, S)
             worst_be, worst_d2 = max(worst_be, be), max(worst_d2, d2)
-        if sketch != "srht":   # autotuned sketch-product schedule (1..9)
+        if lib_sketch != "srht":   # autotuned sketch-product schedule (1..9)
             out[sketch + "_schedule"] = rgs.rgs_last_tuning(h)
         out[sketch] = {"items": len(its), "seconds": dt, "algorithmic_bytes": B, "gbs": B / dt / 1e9,
                        "pct_hbm_peak": 100.0 * B / dt / 1e9 / HBM_PEAK_GBS, "graph_seconds": dt_graph,
@@ -836,8 +840,8 @@ def main():
                     help="write the projection kernel's HBM-traffic record from two rocprofv3 --pmc "
                          "databases (no GPU needed) and exit")
     ap.add_argument("--sketches", default=None,
-                    help="with --only batched-qr: comma-separated legs (srht, gaussian, gaussian_exact_table, "
-                         "gaussian_bf16_table)")
+                    help="with --only batched-qr: comma-separated legs (srht, srht_richardson2, gaussian, "
+                         "gaussian_exact_table, gaussian_bf16_table)")
     ap.add_argument("--leg-steps", type=int, default=None, help="with --only: timed calls per leg")
     ap.add_argument("--leg-warmup", type=int, default=None, help="with --only: untimed calls per leg")
     ap.add_argument("--no-graph", action="store_true",

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 6
+#define RGS_ABI_VERSION 7
 
 typedef struct rgs_handle rgs_handle;  /* opaque */
 typedef void *rgs_stream;              /* a hipStream_t; NULL = the null stream */
@@ -148,6 +148,12 @@ typedef enum {
                                     Box-Muller per four entries.  Results agree with the drawn sketch
                                     up to the order of the sums.  For k n small enough to keep
                                     (11.3 GB at k = 400, n = 192^3, float). */
+/* rgs_qr_batched_ex only: step 2 of every factorisation of the call by s = 1..8
+ * Richardson sweeps on the normal equations, exactly as rgs_qr_desc.ls_sweeps = s
+ * gives rgs_qr (remark on the least-squares solver, Sec. 2.3); s = 0 keeps the
+ * Householder QR of S.  The count sits in bits 24..27 of flags; EINVAL above 8. */
+#define RGS_FLAG_LS_SWEEPS(s) (((uint32_t)(s)&15u) << 24)
+#define RGS_FLAG_LS_SWEEPS_MASK (15u << 24)
 
 /* Describes one RGS factorisation and its sketch Theta (k x n).
  * Theta is defined by (sketch, k, seed, sketch_id, instance) alone, so it is
@@ -365,7 +371,12 @@ rgs_status rgs_qr_batched(rgs_handle *h, int64_t batch, const rgs_qr_item *items
  *     run.  With the GAUSSIAN sketch, a call whose product schedule is not yet
  *     tuned for this batch (the first, unless rgs_set_tuning forces one) runs
  *     eagerly and tunes it.  Results are bitwise those of an eager call.
- * EINVAL for any other flag, THETA_BF16 or THETA_EXACT with another sketch, or both. */
+ *   RGS_FLAG_LS_SWEEPS(s), s = 1..8 -- step 2 by s Richardson sweeps instead
+ *     of the Householder QR of S (the kernels of rgs_qr with ls_sweeps = s:
+ *     with the SRHT sketch every factorisation is bitwise that of a separate
+ *     rgs_qr call with instance b and ls_sweeps = s).
+ * EINVAL for any other flag, THETA_BF16 or THETA_EXACT with another sketch, both, or more than
+ * 8 sweeps. */
 rgs_status rgs_qr_batched_ex(rgs_handle *h, int64_t batch, const rgs_qr_item *items, int32_t sketch,
                              int32_t prec, uint64_t seed, uint32_t sketch_id, uint32_t flags,
                              int32_t *item_status, int64_t *failed_column, rgs_report *rep);

@@ -265,13 +265,19 @@ def rgs_qr_noalloc(handle, desc, W, Q, R, S, allow=(RGS_EBREAKDOWN, RGS_ENONFINI
     return _qr_call("rgs_qr_noalloc", handle, desc, W, Q, R, S, allow)
 
 
+def flag_ls_sweeps(s):
+    """RGS_FLAG_LS_SWEEPS(s): rgs_qr_batched_ex's step 2 by s Richardson sweeps."""
+    return (int(s) & 15) << 24
+
+
 def rgs_qr_batched(handle, items, sketch="srht", prec="fp32", seed=42, sketch_id=0,
-                   allow=(RGS_EBREAKDOWN, RGS_ENONFINITE), flags=0):
+                   allow=(RGS_EBREAKDOWN, RGS_ENONFINITE), flags=0, ls_sweeps=0):
     """A batch of factorisations; items = list of (W, Q, R, S, k) device tensors.
     flags: 0 (rgs_qr_batched), or FLAG_THETA_BF16 or FLAG_THETA_EXACT (Gaussian sketch only)
-    and/or FLAG_GRAPH (rgs_qr_batched_ex).
+    and/or FLAG_GRAPH (rgs_qr_batched_ex); ls_sweeps > 0 adds flag_ls_sweeps(ls_sweeps).
     Returns (Report, per-item statuses, per-item failed columns)."""
     import torch
+    flags |= flag_ls_sweeps(ls_sweeps)
     dw, dq = _dtypes(PREC[prec])
     arr = (QrItem * len(items))()
     for b, (W, Q, R, S, k) in enumerate(items):

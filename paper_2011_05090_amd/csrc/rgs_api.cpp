@@ -1473,6 +1473,7 @@ struct QrGroupLauncher {
     const float* tabx = nullptr;
     int tk = 0;
     int64_t tgroups = 0;
+    int sweeps = 0;   // step 2: 0 = Householder QR of S, else Richardson sweeps
 
     QrGroupLauncher(rgs_handle* h_, QrGroup& g_, int sk, char* A_, hipStream_t s_)
         : h(h_), g(g_), sk_kind(sk), A(A_), s(s_) {}
@@ -1596,6 +1597,15 @@ struct QrGroupLauncher {
                                    kGemmSchedules[sched - 1].tile))
                 return RGS_EDEVICE;
         }
+        if (sweeps > 0) {
+            const int rs = (int)((i + 1 + kRsumCoefs - 1) / kRsumCoefs);
+            return launch_batch_column_richardson<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, g.pre_sl[a],
+                                                     BlockMap{d_sl, nullptr, a1, 0}, g.pre_sl[a1],
+                                                     BlockMap{nullptr, nullptr, a1, rs}, (int64_t)rs * a1, (int)i,
+                                                     sweeps)
+                       ? RGS_OK
+                       : RGS_EDEVICE;
+        }
         if (!launch_batch_column<T>(s, itd, BlockMap{d_sl, nullptr, a, 0}, g.pre_sl[a],
                                     BlockMap{d_sl, nullptr, a, rb}, g.pre_sl[a] + (int64_t)rb * a,
                                     BlockMap{nullptr, nullptr, a1, rb}, (int64_t)rb * a1, (int)i))
@@ -1611,8 +1621,8 @@ struct QrGroupLauncher {
 
 template <typename TQ, bool DEFER>
 rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items, int sk_kind, uint64_t seed,
-                          uint32_t sid, bool use_table, bool use_tabx, bool want_graph, int32_t* item_status,
-                          int64_t* failed_column, rgs_report* rep) {
+                          uint32_t sid, bool use_table, bool use_tabx, int sweeps, bool want_graph,
+                          int32_t* item_status, int64_t* failed_column, rgs_report* rep) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<int64_t> order((size_t)batch);
     for (int64_t b = 0; b < batch; ++b) order[b] = b;
@@ -1676,6 +1686,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     std::vector<QrGroupLauncher<TQ, DEFER>> run;
     for (int gi = 0; gi < ng; ++gi) {
         run.emplace_back(h, grp[gi], sk_kind, A, h->stream);
+        run.back().sweeps = sweeps;
         if (use_table) {
             run.back().table = reinterpret_cast<const uint16_t*>(A + o_table);
             run.back().tk = tk;
@@ -1715,7 +1726,7 @@ rgs_status run_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
     if (use_graph) {
         std::vector<uint64_t> key = {sig, (uint64_t)sched, (uint64_t)(uintptr_t)A, (uint64_t)h->arena_bytes,
                                      (uint64_t)sk_kind, seed, sid, (uint64_t)use_table, (uint64_t)use_tabx,
-                                     (uint64_t)ng};
+                                     (uint64_t)sweeps, (uint64_t)ng};
         for (int64_t b = 0; b < batch; ++b) {
             const rgs_qr_item& it = items[b];
             for (uint64_t v : {(uint64_t)it.n, (uint64_t)it.m, (uint64_t)it.k, (uint64_t)(uintptr_t)it.W,
@@ -2627,7 +2638,10 @@ rgs_status rgs_qr_batched_ex(rgs_handle* h, int64_t batch, const rgs_qr_item* it
     if (!h || batch < 1 || batch > 65535 || !items) return RGS_EINVAL;
     if (sketch != RGS_SKETCH_GAUSSIAN && sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if (prec != RGS_P_FP32_LS64 && prec != RGS_P_BF16Q_FP32_LS64) return RGS_EINVAL;
-    if ((flags & ~(RGS_FLAG_THETA_BF16 | RGS_FLAG_THETA_EXACT | RGS_FLAG_GRAPH)) != 0) return RGS_EINVAL;
+    if ((flags & ~(RGS_FLAG_THETA_BF16 | RGS_FLAG_THETA_EXACT | RGS_FLAG_GRAPH | RGS_FLAG_LS_SWEEPS_MASK)) != 0)
+        return RGS_EINVAL;
+    const uint32_t sweeps = (flags & RGS_FLAG_LS_SWEEPS_MASK) >> 24;
+    if (sweeps > kMaxSweeps) return RGS_EINVAL;
     const bool tab = (flags & RGS_FLAG_THETA_BF16) != 0;
     const bool tabx = (flags & RGS_FLAG_THETA_EXACT) != 0;
     const bool graph = (flags & RGS_FLAG_GRAPH) != 0;
@@ -2637,10 +2651,10 @@ rgs_status rgs_qr_batched_ex(rgs_handle* h, int64_t batch, const rgs_qr_item* it
         if (!valid_item(items[b], sk_kind)) return RGS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return RGS_EDEVICE;
     if (prec == RGS_P_BF16Q_FP32_LS64)
-        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, tabx, graph, item_status,
-                                          failed_column, rep);
-    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, tabx, graph, item_status,
-                                        failed_column, rep);
+        return run_qr_batched<bf16, true>(h, batch, items, sk_kind, seed, sketch_id, tab, tabx, (int)sweeps, graph,
+                                          item_status, failed_column, rep);
+    return run_qr_batched<float, false>(h, batch, items, sk_kind, seed, sketch_id, tab, tabx, (int)sweeps, graph,
+                                        item_status, failed_column, rep);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;
 } catch (...) {

@@ -97,6 +97,13 @@ bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, co
 template <typename TW>
 bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
                          const BlockMap& map_qd, int64_t n_qd, const BlockMap& map_ls, int64_t n_ls, int i);
+// step 2 by `sweeps` Richardson sweeps: the column step of every factorisation in
+// map_sl (its slices), the sweeps over those with a column i+1 (map_next: their
+// slices; map_rs: their blocks of kRsumCoefs coefficients)
+template <typename TW>
+bool launch_batch_column_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
+                                    const BlockMap& map_next, int64_t n_next, const BlockMap& map_rs, int64_t n_rs,
+                                    int i, int sweeps);
 template <typename TQ, bool DEFER>
 bool launch_batch_scale(hipStream_t st, const BatchItem* items, const BlockMap& map, int64_t nblk);
 template <typename T>

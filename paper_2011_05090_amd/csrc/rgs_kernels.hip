@@ -1351,6 +1351,51 @@ __global__ __launch_bounds__(kGWB) void kb_ls3(const BatchItem* __restrict__ ite
                        it.defer ? a.invr : nullptr, bm.y, us);
 }
 
+// Step 2 by Richardson sweeps on the normal equations (remark on the
+// least-squares solver, Sec. 2.3): the bodies and kGW-thread shape of the
+// single-factorisation kernels, so a batched factorisation keeps the bits of a
+// separate one.  The column step: s' and the slice partials of ||s'||^2 ...
+template <typename PT>
+__global__ __launch_bounds__(kGW) void kb_rqa(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    const bool from_p = (i == 0 && !it.defer);
+    qa_body<PT, kGW>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, from_p ? it.P : nullptr, a.k, 0,
+                     a.Wr, a.mcap, a.sp, a.pd, bm.y);
+}
+
+// ... r_ii, s_i (both layouts), the breakdown test and, for a factorisation
+// with a column i+1, the slice partials of S^T p_{i+1} and ||p_{i+1}||^2 ...
+__global__ __launch_bounds__(kGW) void kb_rb(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    const double* pn = (i + 1 < it.m) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
+    rb_body(a.k, i, it.nsl, a.sp, a.pd, a.mcap, it.S, it.lds, a.Wr, it.R, it.ldr, a.rr, a.invr, a.pnorm, a.status,
+            pn, a.pdb, bm.y);
+}
+
+// ... the sums of a sweep (y, then R(0:i+1, i+1) and the coefficients of
+// column i+1 after the last) ...
+template <typename TW>
+__global__ __launch_bounds__(kGW) void kb_rsum(const BatchItem* __restrict__ items, BlockMap map, int i,
+                                              int accumulate, int last) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    rsum_body<TW>(i, it.nsl, a.mcap, a.pdb, a.uh, accumulate, last, a.pnorm, it.R, it.ldr,
+                  static_cast<TW*>(it.coef), it.defer ? a.invr : nullptr, bm.y);
+}
+
+// ... and the residual partials of one more sweep.
+__global__ __launch_bounds__(kGW) void kb_rres(const BatchItem* __restrict__ items, BlockMap map, int i) {
+    const int2 bm = locate(map, blockIdx.x);
+    const BatchItem& it = items[bm.x];
+    const SpaceArgs& a = it.sa;
+    rres_body(a.k, i, a.mcap, it.S, it.lds, a.Wr, it.P + (int64_t)(i + 1) * a.k, a.uh, a.pdb, bm.y);
+}
+
 __global__ void k_zero_mat(double* __restrict__ A, int64_t rows, int64_t cols, int64_t lda) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows * cols) return;
@@ -1859,6 +1904,30 @@ bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap&
     return true;
 }
 
+template <typename TW>
+bool launch_batch_column_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
+                                    const BlockMap& map_next, int64_t n_next, const BlockMap& map_rs, int64_t n_rs,
+                                    int i, int sweeps) {
+    if (sweeps < 1) return false;
+    if (n_sl > 0) {
+        hipLaunchKernelGGL(kb_rqa<TW>, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
+        RGS_LAUNCH_CHECK();
+        hipLaunchKernelGGL(kb_rb, dim3(n_sl), dim3(kGW), 0, st, items, map_sl, i);
+        RGS_LAUNCH_CHECK();
+    }
+    if (n_rs == 0) return true;   // no factorisation has a column i+1
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const int last = sw + 1 == sweeps;
+        hipLaunchKernelGGL(kb_rsum<TW>, dim3(n_rs), dim3(kGW), 0, st, items, map_rs, i, sw > 0 ? 1 : 0, last);
+        RGS_LAUNCH_CHECK();
+        if (!last) {
+            hipLaunchKernelGGL(kb_rres, dim3(n_next), dim3(kGW), 0, st, items, map_next, i);
+            RGS_LAUNCH_CHECK();
+        }
+    }
+    return true;
+}
+
 template <typename TQ, bool DEFER>
 bool launch_batch_scale(hipStream_t st, const BatchItem* items, const BlockMap& map, int64_t nblk) {
     if (nblk == 0) return true;
@@ -2008,6 +2077,8 @@ template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const Bl
                                          int64_t, const BlockMap&, int64_t, int);
 template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
                                          int64_t, const BlockMap&, int64_t, int);
+template bool launch_batch_column_richardson<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,
+                                                     const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
 template bool launch_batch_scale<float, false>(hipStream_t, const BatchItem*, const BlockMap&, int64_t);
 template bool launch_batch_scale<bf16, true>(hipStream_t, const BatchItem*, const BlockMap&, int64_t);
 template bool launch_materialize<float>(hipStream_t, const SketchArgs&, int64_t, int64_t, int64_t, int64_t,

@@ -45,7 +45,7 @@ def test_binding_signatures_cover_the_header():
 
 
 def test_abi_version_and_status_strings(lib):
-    assert rgs.rgs_abi_version() == 6
+    assert rgs.rgs_abi_version() == 7
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = rgs.status_string(code)
         assert s and "unknown" not in s

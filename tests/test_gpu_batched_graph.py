@@ -4,7 +4,8 @@ and replayed on later calls with the same items.  Every replay must equal an
 eager call on the same input bit for bit -- after the contents of W change in
 place (what a replay is for), with eager work and synchronisations between
 replays, after a call with a different batch forced a new capture, and for the
-P-SRHT, the drawn Gaussian and its bf16 table, in both batched precisions.
+P-SRHT, the drawn Gaussian and its bf16 table, in both batched precisions,
+and with step 2 by Richardson sweeps.
 A Gaussian batch whose product schedule is not tuned yet runs its first call
 eagerly (and tunes it); that call must match as well."""
 
@@ -61,8 +62,10 @@ def _shapes(count, seed):
     return out
 
 
+# extra flags: 16 = the bf16 table of Theta; s << 24 = step 2 by s Richardson sweeps
 CASES = [("srht", "fp32", 0), ("srht", "bf16q", 0), ("gaussian", "fp32", 0), ("gaussian", "bf16q", 0),
-         ("gaussian", "fp32", 16), ("gaussian", "bf16q", 16)]
+         ("gaussian", "fp32", 16), ("gaussian", "bf16q", 16), ("srht", "fp32", 2 << 24),
+         ("gaussian", "bf16q", 1 << 24)]
 
 
 @pytest.mark.parametrize("sketch,prec,extra", CASES)
