@@ -579,33 +579,25 @@ def batched_gmres_leg(rgs, torch, synth, h, batch=256, restart=50, k=200, tol=1e
                                              "within_2": sum(1 for v in diff if abs(v) <= 2)}
             res[prec]["speedup_vs_fp64"] = res["fp64"]["seconds_to_tol"] / res[prec]["seconds_to_tol"]
         out[variant] = res
-    # the P-SRHT systems with step 2 by two Richardson sweeps on the normal equations (Sec. 2.3's remark)
-    d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec="bf16q", flags=rgs.FLAG_GRAPH,
-                       ls_sweeps=2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, stat, reps, _ = rgs.rgs_gmres_batched(h, systems, d)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["srht_richardson2_bf16q"] = {"seconds_to_tol": dt, "status": st,
-                                     "converged": sum(1 for v in stat if v == 0),
-                                     "total_iters": int(sum(r.iters for r in reps)),
-                                     "max_true_relres": max(r.true_relres for r in reps)}
-    log("  batched rgmres srht/bf16q, 2 Richardson sweeps, x%d: %.3f s, %d converged, %d iterations in all" %
-        (len(systems), dt, out["srht_richardson2_bf16q"]["converged"], out["srht_richardson2_bf16q"]["total_iters"]))
-    # the same with the lagged Arnoldi step (RGS_FLAG_LAG: both sketches of a step in the mat-vec pass)
-    d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec="bf16q",
-                       flags=rgs.FLAG_GRAPH | rgs.FLAG_LAG)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, stat, reps, _ = rgs.rgs_gmres_batched(h, systems, d)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["srht_lag_bf16q"] = {"seconds_to_tol": dt, "status": st, "converged": sum(1 for v in stat if v == 0),
-                             "total_iters": int(sum(r.iters for r in reps)),
-                             "max_true_relres": max(r.true_relres for r in reps)}
-    log("  batched rgmres srht/bf16q, lagged step, x%d: %.3f s, %d converged, %d iterations in all" %
-        (len(systems), dt, out["srht_lag_bf16q"]["converged"], out["srht_lag_bf16q"]["total_iters"]))
+    # variants of the P-SRHT systems, graph-replayed: step 2 by two Richardson sweeps on the normal
+    # equations (Sec. 2.3's remark), the lagged Arnoldi step (RGS_FLAG_LAG: both sketches of a step in
+    # the mat-vec pass), and the unique-precision model of Sec. 5.3 (float32 RGS, fp64 products with A)
+    for key, label, prec, extra_flags, sweeps in (
+            ("srht_richardson2_bf16q", "srht/bf16q, 2 Richardson sweeps", "bf16q", 0, 2),
+            ("srht_lag_bf16q", "srht/bf16q, lagged step", "bf16q", rgs.FLAG_LAG, 0),
+            ("srht_fp32u", "srht/fp32u (Sec. 5.3)", "fp32u", 0, 0)):
+        d = rgs.gmres_desc(restart, k, tol, max_iters=20000, sketch="srht", prec=prec,
+                           flags=rgs.FLAG_GRAPH | extra_flags, ls_sweeps=sweeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, stat, reps, _ = rgs.rgs_gmres_batched(h, systems, d)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[key] = {"seconds_to_tol": dt, "status": st, "converged": sum(1 for v in stat if v == 0),
+                    "total_iters": int(sum(r.iters for r in reps)),
+                    "max_true_relres": max(r.true_relres for r in reps)}
+        log("  batched rgmres %s, x%d: %.3f s, %d converged, %d iterations in all" %
+            (label, len(systems), dt, out[key]["converged"], out[key]["total_iters"]))
     return out
 
 

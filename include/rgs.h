@@ -90,7 +90,9 @@ typedef enum {
                                   experiment of Sec. 5.3 -- this RGS as the Arnoldi step, the
                                   products with A in fp64 from the float32 basis vector (rounded
                                   once to float32), Givens rotations, x and the restart residual
-                                  in fp64 (ls_sweeps 0); not the batched calls (EINVAL) */
+                                  in fp64 (ls_sweeps 0), and rgs_gmres_batched the same, every
+                                  system bit for bit a separate rgs_gmres call; not
+                                  rgs_qr_batched(_ex) (EINVAL) */
 } rgs_precision;
 
 /* Flags for rgs_qr_desc.flags / rgs_gmres_desc.flags */
@@ -403,8 +405,9 @@ rgs_status rgs_sketch_materialize(rgs_handle *h, const rgs_qr_desc *desc, int64_
  *   res_hist (host, may be NULL) receives |g_i|/||b||_2 after each inner step,
  *      up to hist_cap entries (the sketched residual ||Theta(b - A x_i)||, Sec. 4.2).
  *   rep (host, may be NULL).
- * desc->prec: FP64, FP32_LS64 or BF16Q_FP32_LS64 (basis stored unnormalised in
- * bf16 with fp64 scales; the mat-vec input is fl32(stored column / r_ii)).
+ * desc->prec: FP64, FP32_LS64, BF16Q_FP32_LS64 (basis stored unnormalised in
+ * bf16 with fp64 scales; the mat-vec input is fl32(stored column / r_ii)) or
+ * FP32 (the configuration of Sec. 5.3, see rgs_precision).
  * Returns OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE or ENOCONV. */
 rgs_status rgs_gmres(rgs_handle *h, const rgs_stencil7 *A, const rgs_gmres_desc *desc,
                      const double *b, double *x, double *res_hist, int64_t hist_cap,

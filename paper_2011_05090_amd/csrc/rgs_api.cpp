@@ -1901,9 +1901,13 @@ void build_gmres_maps(GmresMaps& g, const std::vector<int64_t>& active, const st
     g.nsl = (int)((k + kSlice - 1) / kSlice);
 }
 
-template <typename T, typename TQ, bool DEFER>
+// TS: the sketch-space arithmetic, fp64, or float32 in the unique-precision
+// model (RGS_P_FP32), whose products with A run in fp64 (TC) from the float32
+// basis vectors, as in rgs_gmres
+template <typename T, typename TQ, bool DEFER, typename TS = double>
 rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,
                              int32_t* item_status, rgs_report* reps) {
+    using TC = typename std::conditional<std::is_same<TS, float>::value, double, T>::type;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = h->stream;
     const int sk_kind = sketch_kind(d->sketch);
@@ -2158,8 +2162,9 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     // the dual mat-vec + sketch step: with the bf16 table in row-block-major
     // order (the systems share the table's entries), else system by system
     auto dual_step = [&](hipStream_t q, const MapAt& M, int ii) -> bool {
-        return tab ? launch_gbatch_stencil_dual_rows<T, TQ>(q, itd, gid, M.pairs, (int64_t)M.gm.pairs.size(), ii)
-                   : launch_gbatch_stencil_dual<T, TQ>(q, itd, gid, m_proj(M), n_proj(M), ii, false, lag);
+        return tab ? launch_gbatch_stencil_dual_rows<T, TQ, TC>(q, itd, gid, M.pairs, (int64_t)M.gm.pairs.size(),
+                                                                ii)
+                   : launch_gbatch_stencil_dual<T, TQ, TC>(q, itd, gid, m_proj(M), n_proj(M), ii, false, lag);
     };
     // step 2: Householder (the compact-WY chain) or ls_sweeps Richardson sweeps
     const int sweeps = (int)d->ls_sweeps;
@@ -2170,13 +2175,13 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
             const int rbl = (ii + 63) / 64, rbs = (ii + kRsumCoefs - 1) / kRsumCoefs;
             return sweeps > 0 ? launch_gbatch_ls_richardson<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbs),
                                                                n_uni(M, rbs), ii, dualflag, sweeps)
-                              : launch_gbatch_ls<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl),
+                              : launch_gbatch_ls<T, TS>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, rbl),
                                                     n_uni(M, rbl), ii, dualflag);
         };
         auto column_step = [&](int ii) {
             const int rbq = (ii + 1 + 63) / 64;   // column-step blocks beyond the slices
             return sweeps > 0 ? launch_gbatch_column_richardson<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), ii)
-                              : launch_batch_column<T>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + rbq),
+                              : launch_batch_column<T, TS>(q, itd, m_uni(M, nsl), n_uni(M, nsl), m_uni(M, nsl + rbq),
                                                        n_uni(M, nsl + rbq), none, 0, ii);
         };
         if (!launch_gbatch_reset(q, itd, m_sys(M), cnt)) return false;
@@ -2196,7 +2201,7 @@ rgs_status run_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
                     !dual_step(q, M, ii))
                     return false;
             } else {
-                if (!launch_gbatch_stencil<T, TQ>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii)) return false;
+                if (!launch_gbatch_stencil<T, TQ, TC>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii)) return false;
                 if (!ls_step(ii, 0)) return false;
                 if (!launch_gbatch_project<T, TQ, DEFER>(q, sk_kind, itd, gid, m_proj(M), n_proj(M), ii))
                     return false;
@@ -2670,7 +2675,6 @@ rgs_status rgs_qr_batched(rgs_handle* h, int64_t batch, const rgs_qr_item* items
 rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item* items, const rgs_gmres_desc* d,
                              int32_t* item_status, rgs_report* reps) try {
     if (!h || batch < 1 || batch > 65535 || !items || !valid_gmres_desc(d)) return RGS_EINVAL;
-    if (d->prec == RGS_P_FP32) return RGS_EINVAL;   // the unique-precision model: rgs_gmres only
     if (d->sketch != RGS_SKETCH_GAUSSIAN && d->sketch != RGS_SKETCH_SRHT) return RGS_EINVAL;
     if ((d->flags & ~(RGS_FLAG_GRAPH | RGS_FLAG_THETA_BF16 | RGS_FLAG_LAG)) != 0) return RGS_EINVAL;
     if ((d->flags & RGS_FLAG_THETA_BF16) && d->sketch != RGS_SKETCH_GAUSSIAN) return RGS_EINVAL;
@@ -2691,6 +2695,8 @@ rgs_status rgs_gmres_batched(rgs_handle* h, int64_t batch, const rgs_gmres_item*
     if (d->prec == RGS_P_FP64) return run_gmres_batched<double, double, false>(h, batch, items, d, item_status, reps);
     if (d->prec == RGS_P_BF16Q_FP32_LS64)
         return run_gmres_batched<float, bf16, true>(h, batch, items, d, item_status, reps);
+    if (d->prec == RGS_P_FP32)
+        return run_gmres_batched<float, float, false, float>(h, batch, items, d, item_status, reps);
     return run_gmres_batched<float, float, false>(h, batch, items, d, item_status, reps);
 } catch (const std::bad_alloc&) {
     return RGS_ENOMEM;

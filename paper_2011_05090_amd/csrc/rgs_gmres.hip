@@ -741,7 +741,9 @@ __global__ __launch_bounds__(256) void kg_cast(const GmresItem* __restrict__ gi,
     if (l < g.n) static_cast<T*>(g.w)[l] = (T)g.r[l];
 }
 
-template <typename TQ, typename T, int SK>
+// TC: the arithmetic of the product with A (T, or fp64 from the float32 basis
+// vector in the unique-precision model)
+template <typename TQ, typename T, int SK, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem* __restrict__ items,
                                                                  const GmresItem* __restrict__ gi,
                                                                  BlockMap map, int i) {
@@ -750,12 +752,12 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil(const BatchItem
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
-    stencil_sketch_body<TQ, T, T, SK>(static_cast<const TQ*>(it.Q) + (int64_t)(i - 1) * it.ldq,
+    stencil_sketch_body<TQ, T, T, SK, TC>(static_cast<const TQ*>(it.Q) + (int64_t)(i - 1) * it.ldq,
                                       it.sa.invr + (i - 1), grid3(g.A), it.n, static_cast<T*>(g.w), 1, it.sk,
                                       static_cast<T*>(it.part), bm.y, lds);
 }
 
-template <typename TQ, typename T, bool TAB>
+template <typename TQ, typename T, bool TAB, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const BatchItem* __restrict__ items,
                                                                       const GmresItem* __restrict__ gi,
                                                                       BlockMap map, int i) {
@@ -764,14 +766,15 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual(const Batc
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
-    stencil_dual_body<TQ, T, TAB>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+    stencil_dual_body<TQ, T, TAB, kTabDepth, false, TC>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq,
+                                                        grid3(g.A), it.n,
                              static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part), static_cast<T*>(it.part2), bm.y,
                              lds);
 }
 
 // The lagged P-SRHT step (RGS_FLAG_LAG): t = A q'_i and the block partials of
 // both sketches, the body of k_stencil_dual_sk.
-template <typename TQ, typename T>
+template <typename TQ, typename T, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_sk(const BatchItem* __restrict__ items,
                                                                          const GmresItem* __restrict__ gi,
                                                                          BlockMap map, int i) {
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_sk(const B
     const BatchItem& it = items[bm.x];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[bm.x];
-    stencil_dual_sk_body<TQ, T, SK_SRHT>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+    stencil_dual_sk_body<TQ, T, SK_SRHT, TC>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
                                          static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part),
                                          static_cast<T*>(it.part2), bm.y, lds);
 }
@@ -793,7 +796,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_sk(const B
 // resident on one XCD share one slice, which its L2 then serves after one read
 // from HBM.  An entry with r < 0 is an idle slot.  Same body per (system,
 // block) as kg_stencil_dual, so the same bits.
-template <typename TQ, typename T>
+template <typename TQ, typename T, typename TC = T>
 __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_rows(const BatchItem* __restrict__ items,
                                                                            const GmresItem* __restrict__ gi,
                                                                            const int2* __restrict__ pairs, int i) {
@@ -803,7 +806,8 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_stencil_dual_rows(const
     const BatchItem& it = items[p.y];
     RGS_EXIT_IF_STOPPED(it.sa.status);
     const GmresItem& g = gi[p.y];
-    stencil_dual_body<TQ, T, true>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq, grid3(g.A), it.n,
+    stencil_dual_body<TQ, T, true, kTabDepth, false, TC>(static_cast<const TQ*>(it.Q) + (int64_t)i * it.ldq,
+                                                         grid3(g.A), it.n,
                                    static_cast<T*>(g.w), it.sk, static_cast<T*>(it.part), static_cast<T*>(it.part2),
                                    p.x, lds);
 }
@@ -845,35 +849,39 @@ __global__ __launch_bounds__(kProjWaves * kWave) void kg_project(const BatchItem
 // Step 2 for the Arnoldi right-hand side p_i (block partials of the mat-vec
 // kernel): reduce to pbuf with the per-slice partials of Wm^T p, then the head
 // of U^T p, then y = R_S^{-1} uh -> R(0:i, i) and the projection coefficients.
-template <typename PT>
+// TS: the sketch-space arithmetic (fp64, or float32 in the unique-precision model)
+template <typename PT, typename TS = double>
 __global__ __launch_bounds__(kGWB) void kg_lsa(const BatchItem* __restrict__ items, BlockMap map,
                                               int i, int dual) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     // dual: p_i arrives as the sketch of A q'_{i-1} (part2), scaled by 1/r_{i-1,i-1} here
-    qa_body<PT, kGWB>(static_cast<const PT*>(dual ? it.part2 : it.part), it.nproj, it.sketch_scale, nullptr, a.k, i,
-                      a.Wr, a.mcap, a.pbuf, a.pd, bm.y, dual ? a.invr + (i - 1) : nullptr);
+    qa_body<PT, kGWB, TS>(static_cast<const PT*>(dual ? it.part2 : it.part), it.nproj, it.sketch_scale, nullptr, a.k,
+                          i, ws_as<TS>(a.Wr), a.mcap, ws_as<TS>(a.pbuf), ws_as<TS>(a.pd), bm.y,
+                          dual ? a.invr + (i - 1) : nullptr);
 }
 
+template <typename TS = double>
 __global__ __launch_bounds__(kGWB) void kg_ls2(const BatchItem* __restrict__ items, BlockMap map,
                                               int i) {
     extern __shared__ double cp[];  // [i + 1]
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    ls2_body<kGWB>(a.pbuf, a.k, i, it.nsl, a.Vc, a.mcap, a.pd, a.uh, a.pnorm, bm.y, cp);
+    ls2_body<kGWB, TS>(ws_as<TS>(a.pbuf), a.k, i, it.nsl, ws_as<TS>(a.Vc), a.mcap, ws_as<TS>(a.pd), ws_as<TS>(a.uh),
+                       ws_as<TS>(a.pnorm), bm.y, ws_as<TS>(cp));
 }
 
-template <typename T>
+template <typename T, typename TS = double>
 __global__ __launch_bounds__(kGWB) void kg_ls3(const BatchItem* __restrict__ items, BlockMap map,
                                               int i) {
     extern __shared__ double us[];  // [i]
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    ls3_body<T, kGWB>(i, i, a.X, a.mcap, a.uh, it.R, it.ldr, static_cast<T*>(it.coef), it.defer ? a.invr : nullptr,
-                      bm.y, us);
+    ls3_body<T, kGWB, TS>(i, i, ws_as<TS>(a.X), a.mcap, ws_as<TS>(a.uh), it.R, it.ldr, static_cast<T*>(it.coef),
+                          it.defer ? a.invr : nullptr, bm.y, ws_as<TS>(us));
 }
 
 // Step 2 by Richardson sweeps on the normal equations (ls_sweeps > 0; the
@@ -1101,41 +1109,41 @@ bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const BlockMap& map
     return true;
 }
 
-template <typename T, typename TQ>
+template <typename T, typename TQ, typename TC>
 bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
                            const BlockMap& map_proj, int64_t nproj, int i) {
     if (nproj == 0) return true;
     const dim3 thr(kProjWaves * kWave);
     if (sketch == SK_SRHT)
-        hipLaunchKernelGGL((kg_stencil<TQ, T, SK_SRHT>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
+        hipLaunchKernelGGL((kg_stencil<TQ, T, SK_SRHT, TC>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
     else
-        hipLaunchKernelGGL((kg_stencil<TQ, T, SK_GAUSS>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
+        hipLaunchKernelGGL((kg_stencil<TQ, T, SK_GAUSS, TC>), dim3(nproj), thr, 0, st, items, gi, map_proj, i);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-template <typename T, typename TQ>
+template <typename T, typename TQ, typename TC>
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                                 int64_t nproj, int i, bool table, bool lag_srht) {
     if (nproj == 0) return true;
     if (lag_srht)
-        hipLaunchKernelGGL((kg_stencil_dual_sk<TQ, T>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
+        hipLaunchKernelGGL((kg_stencil_dual_sk<TQ, T, TC>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
                            map_proj, i);
     else if (table)
-        hipLaunchKernelGGL((kg_stencil_dual<TQ, T, true>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
-                           map_proj, i);
+        hipLaunchKernelGGL((kg_stencil_dual<TQ, T, true, TC>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items,
+                           gi, map_proj, i);
     else
-        hipLaunchKernelGGL((kg_stencil_dual<TQ, T, false>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items, gi,
-                           map_proj, i);
+        hipLaunchKernelGGL((kg_stencil_dual<TQ, T, false, TC>), dim3(nproj), dim3(kProjWaves * kWave), 0, st, items,
+                           gi, map_proj, i);
     RGS_LAUNCH_CHECK();
     return true;
 }
 
-template <typename T, typename TQ>
+template <typename T, typename TQ, typename TC>
 bool launch_gbatch_stencil_dual_rows(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* pairs,
                                      int64_t npairs, int i) {
     if (npairs == 0) return true;
-    hipLaunchKernelGGL((kg_stencil_dual_rows<TQ, T>), dim3(npairs), dim3(kProjWaves * kWave), 0, st, items, gi,
+    hipLaunchKernelGGL((kg_stencil_dual_rows<TQ, T, TC>), dim3(npairs), dim3(kProjWaves * kWave), 0, st, items, gi,
                        pairs, i);
     RGS_LAUNCH_CHECK();
     return true;
@@ -1164,17 +1172,17 @@ bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, c
     return true;
 }
 
-template <typename T>
+template <typename T, typename TS>
 bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl, const BlockMap& map_rb,
                       int64_t nrb, int i, int dual) {
     if (nsl > 0) {
-        hipLaunchKernelGGL(kg_lsa<T>, dim3(nsl), dim3(kGWB), 0, st, items, map_sl, i, dual);
+        hipLaunchKernelGGL((kg_lsa<T, TS>), dim3(nsl), dim3(kGWB), 0, st, items, map_sl, i, dual);
         RGS_LAUNCH_CHECK();
     }
     if (nrb > 0) {
-        hipLaunchKernelGGL(kg_ls2, dim3(nrb), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_rb, i);
+        hipLaunchKernelGGL(kg_ls2<TS>, dim3(nrb), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_rb, i);
         RGS_LAUNCH_CHECK();
-        hipLaunchKernelGGL(kg_ls3<T>, dim3(nrb), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_rb, i);
+        hipLaunchKernelGGL((kg_ls3<T, TS>), dim3(nrb), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_rb, i);
         RGS_LAUNCH_CHECK();
     }
     return true;
@@ -1271,6 +1279,8 @@ template bool launch_update_x<bf16>(hipStream_t, const double*, int, const doubl
 template bool launch_gbatch_cast<float>(hipStream_t, const GmresItem*, const BlockMap&, int64_t);
 template bool launch_gbatch_cast<double>(hipStream_t, const GmresItem*, const BlockMap&, int64_t);
 template bool launch_gbatch_stencil<float, float>(hipStream_t, int, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
+template bool launch_gbatch_stencil<float, float, double>(hipStream_t, int, const BatchItem*, const GmresItem*,
+                                                          const BlockMap&, int64_t, int);
 template bool launch_gbatch_stencil<double, double>(hipStream_t, int, const BatchItem*, const GmresItem*,
                                                     const BlockMap&, int64_t, int);
 template bool launch_gbatch_stencil<float, bf16>(hipStream_t, int, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int);
@@ -1281,6 +1291,8 @@ template bool launch_gbatch_project<double, double, false>(hipStream_t, int, con
 template bool launch_gbatch_project<float, bf16, true>(hipStream_t, int, const BatchItem*, const GmresItem*,
                                                        const BlockMap&, int64_t, int);
 template bool launch_gbatch_ls<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&, int64_t, int, int);
+template bool launch_gbatch_ls<float, float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
+                                             int64_t, int, int);
 template bool launch_gbatch_ls_richardson<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,
                                                  const BlockMap&, int64_t, int, int, int);
 template bool launch_gbatch_ls_richardson<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,
@@ -1297,11 +1309,15 @@ template bool launch_stencil_dual<double, double, double>(hipStream_t, const Ste
 template bool launch_stencil_dual<bf16, float, float>(hipStream_t, const StencilArgs&, const bf16*, float*,
                                                       const SketchArgs&, float*, float*, const int*);
 template bool launch_gbatch_stencil_dual<float, float>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool, bool);
+template bool launch_gbatch_stencil_dual<float, float, double>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                               const BlockMap&, int64_t, int, bool, bool);
 template bool launch_gbatch_stencil_dual<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
                                                          const BlockMap&, int64_t, int, bool, bool);
 template bool launch_gbatch_stencil_dual<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*, const BlockMap&, int64_t, int, bool, bool);
 template bool launch_gbatch_stencil_dual_rows<float, float>(hipStream_t, const BatchItem*, const GmresItem*,
                                                             const int2*, int64_t, int);
+template bool launch_gbatch_stencil_dual_rows<float, float, double>(hipStream_t, const BatchItem*, const GmresItem*,
+                                                                    const int2*, int64_t, int);
 template bool launch_gbatch_stencil_dual_rows<double, double>(hipStream_t, const BatchItem*, const GmresItem*,
                                                               const int2*, int64_t, int);
 template bool launch_gbatch_stencil_dual_rows<float, bf16>(hipStream_t, const BatchItem*, const GmresItem*,

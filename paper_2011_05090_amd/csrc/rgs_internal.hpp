@@ -94,7 +94,7 @@ bool launch_batch_table_gemm(hipStream_t st, const BatchItem* items, const GemmU
 template <typename TW, typename TQ, bool DEFER>
 bool launch_batch_project(hipStream_t st, int sketch, const BatchItem* items, const BlockMap& map, int64_t nblk,
                           int i);
-template <typename TW>
+template <typename TW, typename TS = double>
 bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
                          const BlockMap& map_qd, int64_t n_qd, const BlockMap& map_ls, int64_t n_ls, int i);
 // step 2 by `sweeps` Richardson sweeps: the column step of every factorisation in
@@ -156,13 +156,13 @@ bool launch_gbatch_reset(hipStream_t st, const BatchItem* items, const BlockMap&
 bool launch_gbatch_zero_x(hipStream_t st, const GmresItem* gi, const BlockMap& map_row, int64_t nrow);
 template <typename T>
 bool launch_gbatch_cast(hipStream_t st, const GmresItem* gi, const BlockMap& map_row, int64_t nrow);
-template <typename T, typename TQ>
+template <typename T, typename TQ, typename TC = T>
 bool launch_gbatch_stencil(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
                            const BlockMap& map_proj, int64_t nproj, int i);
 template <typename T, typename TQ, bool DEFER>
 bool launch_gbatch_project(hipStream_t st, int sketch, const BatchItem* items, const GmresItem* gi,
                            const BlockMap& map_proj, int64_t nproj, int i);
-template <typename T>
+template <typename T, typename TS = double>
 bool launch_gbatch_ls(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl, const BlockMap& map_rb,
                       int64_t nrb, int i, int dual);
 // The same step, and the column step, with the least squares by `sweeps`
@@ -175,11 +175,11 @@ bool launch_gbatch_ls_richardson(hipStream_t st, const BatchItem* items, const B
 template <typename T>
 bool launch_gbatch_column_richardson(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t nsl,
                                      int i);
-template <typename T, typename TQ>
+template <typename T, typename TQ, typename TC = T>
 // (lag_srht: the lagged P-SRHT step of RGS_FLAG_LAG instead of the Gaussian one)
 bool launch_gbatch_stencil_dual(hipStream_t st, const BatchItem* items, const GmresItem* gi, const BlockMap& map_proj,
                                 int64_t nproj, int i, bool table, bool lag_srht = false);
-template <typename T, typename TQ>
+template <typename T, typename TQ, typename TC = T>
 bool launch_gbatch_stencil_dual_rows(hipStream_t st, const BatchItem* items, const GmresItem* gi, const int2* pairs,
                                      int64_t npairs, int i);
 template <typename T, typename TQ, bool DEFER>

@@ -22,6 +22,7 @@
 // bitwise reproducible run to run.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rgs_map.hpp"
 #include "rgs_step.hpp"
@@ -1303,42 +1304,50 @@ __global__ __launch_bounds__(NT) void k_qd(int k, int i, int nsl, const TS* __re
 // Every factorisation in the map is at column i.  pnext is P(:, i+1) when the
 // factorisation has a column i+1, and nothing otherwise.
 // ---------------------------------------------------------------------------
-template <typename PT>
+// TS: the sketch-space arithmetic (fp64, or float32 for the unique-precision
+// GMRES systems); the workspace buffers hold TS values, R, S, rr and invr are fp64
+template <typename PT, typename TS = double>
 __global__ __launch_bounds__(kGWB) void kb_qa(const BatchItem* __restrict__ items, BlockMap map, int i) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const bool from_p = (i == 0 && !it.defer && it.P != nullptr);   // GMRES systems carry no P
-    qa_body<PT, kGWB>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, from_p ? it.P : nullptr, a.k, i,
-                      a.Wr, a.mcap, a.sp, a.pd, bm.y);
+    qa_body<PT, kGWB, TS>(static_cast<const PT*>(it.part), it.npart, it.sketch_scale, from_p ? it.P : nullptr, a.k,
+                          i, ws_as<TS>(a.Wr), a.mcap, ws_as<TS>(a.sp), ws_as<TS>(a.pd), bm.y);
 }
 
+template <typename TS = double>
 __global__ __launch_bounds__(kGWB) void kb_qb(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double c1[];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
-    qb_body<kGWB>(a.k, i, it.nsl, a.sp, a.Vc, a.mcap, a.pd, a.u, a.pd2, it.S, it.lds, it.R, it.ldr, a.rr, a.invr,
-                  a.pnorm, a.status, bm.y, c1);
+    qb_body<kGWB, TS>(a.k, i, it.nsl, ws_as<TS>(a.sp), ws_as<TS>(a.Vc), a.mcap, ws_as<TS>(a.pd), ws_as<TS>(a.u),
+                      ws_as<TS>(a.pd2), it.S, it.lds, it.R, it.ldr, a.rr, a.invr, ws_as<TS>(a.pnorm), a.status, bm.y,
+                      ws_as<TS>(c1));
 }
 
+template <typename TS = double>
 __global__ __launch_bounds__(kGWB) void kb_qc(const BatchItem* __restrict__ items, BlockMap map, int i) {
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
-    qc_body<kGWB>(a.k, i, it.nsl, a.u, a.pd2, pn, a.v, a.Vc, a.Vr, a.Wr, a.mcap, a.pd, a.pdb, a.tau, a.beta,
-                  a.status, bm.y);
+    qc_body<kGWB, TS>(a.k, i, it.nsl, ws_as<TS>(a.u), ws_as<TS>(a.pd2), pn, ws_as<TS>(a.v), ws_as<TS>(a.Vc),
+                      ws_as<TS>(a.Vr), ws_as<TS>(a.Wr), a.mcap, ws_as<TS>(a.pd), ws_as<TS>(a.pdb), ws_as<TS>(a.tau),
+                      ws_as<TS>(a.beta), a.status, bm.y);
 }
 
+template <typename TS = double>
 __global__ __launch_bounds__(kGWB) void kb_qd(const BatchItem* __restrict__ items, BlockMap map, int i) {
     extern __shared__ double dyn[];
     const int2 bm = locate(map, blockIdx.x);
     const BatchItem& it = items[bm.x];
     const SpaceArgs& a = it.sa;
     const double* pn = (i + 1 < it.m && it.P) ? it.P + (int64_t)(i + 1) * a.k : nullptr;
-    qd_body<kGWB>(a.k, i, it.nsl, a.v, a.u, pn, a.Wc, a.Wr, a.Vc, a.mcap, a.pd, a.pdb, a.X, a.uh, a.pnorm, a.tau,
-                  a.beta, bm.y, dyn);
+    qd_body<kGWB, TS>(a.k, i, it.nsl, ws_as<TS>(a.v), ws_as<TS>(a.u), pn, ws_as<TS>(a.Wc), ws_as<TS>(a.Wr),
+                      ws_as<TS>(a.Vc), a.mcap, ws_as<TS>(a.pd), ws_as<TS>(a.pdb), ws_as<TS>(a.X), ws_as<TS>(a.uh),
+                      ws_as<TS>(a.pnorm), ws_as<TS>(a.tau), ws_as<TS>(a.beta), bm.y, ws_as<TS>(dyn));
 }
 
 template <typename TW>
@@ -1882,19 +1891,20 @@ bool launch_batch_init(hipStream_t st, const BatchItem* items, int nitems, int64
     return true;
 }
 
-template <typename TW>
+template <typename TW, typename TS>
 bool launch_batch_column(hipStream_t st, const BatchItem* items, const BlockMap& map_sl, int64_t n_sl,
                          const BlockMap& map_qd, int64_t n_qd, const BlockMap& map_ls, int64_t n_ls, int i) {
+    if (!std::is_same<TS, double>::value && n_ls > 0) return false;   // kb_ls3 reads an fp64 workspace
     if (n_sl > 0) {
-        hipLaunchKernelGGL(kb_qa<TW>, dim3(n_sl), dim3(kGWB), 0, st, items, map_sl, i);
+        hipLaunchKernelGGL((kb_qa<TW, TS>), dim3(n_sl), dim3(kGWB), 0, st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
-        hipLaunchKernelGGL(kb_qb, dim3(n_sl), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_sl, i);
+        hipLaunchKernelGGL(kb_qb<TS>, dim3(n_sl), dim3(kGWB), (i + 1) * sizeof(double), st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
-        hipLaunchKernelGGL(kb_qc, dim3(n_sl), dim3(kGWB), 0, st, items, map_sl, i);
+        hipLaunchKernelGGL(kb_qc<TS>, dim3(n_sl), dim3(kGWB), 0, st, items, map_sl, i);
         RGS_LAUNCH_CHECK();
     }
     if (n_qd > 0) {
-        hipLaunchKernelGGL(kb_qd, dim3(n_qd), dim3(kGWB), 3 * (i + 2) * sizeof(double), st, items, map_qd, i);
+        hipLaunchKernelGGL(kb_qd<TS>, dim3(n_qd), dim3(kGWB), 3 * (i + 2) * sizeof(double), st, items, map_qd, i);
         RGS_LAUNCH_CHECK();
     }
     if (n_ls > 0) {
@@ -2075,6 +2085,8 @@ template bool launch_batch_sketch_p<float>(hipStream_t, int, const BatchItem*, c
                                           const BlockMap&, int64_t, const BlockMap&, int64_t, bool);
 template bool launch_batch_column<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
                                          int64_t, const BlockMap&, int64_t, int);
+template bool launch_batch_column<float, float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,
+                                                const BlockMap&, int64_t, const BlockMap&, int64_t, int);
 template bool launch_batch_column<double>(hipStream_t, const BatchItem*, const BlockMap&, int64_t, const BlockMap&,
                                          int64_t, const BlockMap&, int64_t, int);
 template bool launch_batch_column_richardson<float>(hipStream_t, const BatchItem*, const BlockMap&, int64_t,

@@ -32,6 +32,12 @@ constexpr int kGWB = 256;   // threads of the batched sketch-space kernels
 // the 1024-thread shape is faster (each thread one column group); 256 threads
 // cost ≈ 8 µs per column at k = 2048
 constexpr int kGWS = kGW;
+// the sketch-space workspace (buffers sized for fp64) viewed in the
+// sketch-space type TS
+template <typename TS>
+__device__ __forceinline__ TS* ws_as(double* p) {
+    return reinterpret_cast<TS*>(p);
+}
 constexpr int kGQ = 16;     // column groups of the row-parallel products
 constexpr int kBatch = 16;  // loads issued back to back per thread
 constexpr int kSliceBatch = 32;   // the same in the column-parallel slice products

@@ -3,7 +3,8 @@ bf16-basis RGMRES.
 
 * every system of a batched solve equals a separate rgs_gmres call on it bit
   for bit (x, residual history, iteration and cycle counts), for both
-  sketches and the fp64 / fp32 / bf16 bases, with a fresh sketch per cycle,
+  sketches and the fp64 / fp32 / bf16 bases and the unique-precision model
+  of Sec. 5.3, with a fresh sketch per cycle,
   with the Householder least squares and with one or two Richardson sweeps
   (ls_sweeps, eager and graph-replayed), and with the lagged P-SRHT step;
 * the graph-replayed cycles equal the eagerly launched ones bit for bit (the
@@ -70,10 +71,13 @@ def _single(h, system, desc, hist_cap=4000):
 @pytest.mark.parametrize("sketch,prec,table", [("srht", "fp32", False), ("gaussian", "fp32", False),
                                                ("srht", "bf16q", False), ("gaussian", "bf16q", False),
                                                ("srht", "fp64", False), ("gaussian", "fp32", True),
-                                               ("gaussian", "bf16q", True)])
+                                               ("gaussian", "bf16q", True), ("srht", "fp32u", False),
+                                               ("gaussian", "fp32u", False), ("gaussian", "fp32u", True)])
 def test_batched_equals_single_calls_bitwise(gpu_handle, sketch, prec, table):
     """table: the Gaussian sketch with bf16 entries; the batched call's one
-    table over the largest n gives every system the entries of its own."""
+    table over the largest n gives every system the entries of its own.
+    fp32u: the unique-precision model of Sec. 5.3 (float32 RGS, fp64 products
+    with A)."""
     rgs = _rgs()
     systems = _systems(6, tag=1)
     desc = rgs.gmres_desc(RESTART, K, TOL, max_iters=3000, sketch=sketch, prec=prec,
@@ -111,7 +115,7 @@ def test_batched_richardson_equals_single_calls_bitwise(gpu_handle, sketch, prec
         assert torch.equal(x, x1)
 
 
-@pytest.mark.parametrize("prec,graph", [("fp32", False), ("fp64", False), ("bf16q", True)])
+@pytest.mark.parametrize("prec,graph", [("fp32", False), ("fp64", False), ("bf16q", True), ("fp32u", True)])
 def test_batched_lagged_step_equals_single_calls_bitwise(gpu_handle, prec, graph):
     """RGS_FLAG_LAG with the P-SRHT in the batched solver: the mat-vec pass
     sketches q'_i and A q'_i (the body of the single solver's lagged kernel),

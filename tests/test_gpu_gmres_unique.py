@@ -11,8 +11,9 @@ restart residual in fp64.
   residual histories to float32 rounding, the true residual recomputed on the
   host;
 * the 192^3 system with the P-SRHT against the cached fp64 oracle count;
-* the precision is refused with Richardson least squares and by the batched
-  solver.
+* the precision is refused with Richardson least squares, by the single and
+  the batched solver (the batched solver takes it otherwise: its bitwise
+  tests sit with the other batched GMRES tests).
 """
 
 import json
@@ -114,5 +115,6 @@ def test_unique_precision_refusals(gpu_handle):
         rgs.rgs_gmres(gpu_handle, A, rgs.gmres_desc(10, 40, 1e-6, sketch="srht", prec="fp32u", ls_sweeps=1), b, x)
     assert e.value.status == rgs.RGS_EINVAL
     with pytest.raises(rgs.RgsError) as e:
-        rgs.rgs_gmres_batched(gpu_handle, [(A, b, x)], rgs.gmres_desc(10, 40, 1e-6, sketch="srht", prec="fp32u"))
+        rgs.rgs_gmres_batched(gpu_handle, [(A, b, x)],
+                              rgs.gmres_desc(10, 40, 1e-6, sketch="srht", prec="fp32u", ls_sweeps=1))
     assert e.value.status == rgs.RGS_EINVAL
