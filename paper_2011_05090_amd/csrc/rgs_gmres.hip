@@ -338,6 +338,29 @@ __device__ __forceinline__ void stencil_sketch_body(const TQ* __restrict__ qs, c
 // TAB: the entries come from the bf16 table (SK_TABLE), 8 rows per load;
 // EXACT (with TAB): from the table of the entries in T (SK_TABX), 8 rows per
 // 32- or 64-byte group.
+// Segments per sketch row of the drawn dual sketch: with one row per thread,
+// k < NT leaves NT - k lanes idle (k = 400 of 512: one SIMD in four half
+// loaded; k = 200: half the waves idle).  Splitting each row's quads of the
+// block into S segments gives k S (row, segment) tasks over ceil(k S / NT)
+// rounds; S is the smallest count that keeps 95 % of the lanes busy (else the
+// best up to kKptMax), and 1 when k already does.  Uniform over the grid.
+__device__ __forceinline__ int dual_segments(int k, int nt) {
+    if (k >= nt || 20 * k >= 19 * nt) return 1;
+    int best = 1;
+    int64_t bnum = k, bden = nt;   // busy lanes / lane slots of the best count so far
+    for (int S = 2; S <= kKptMax; ++S) {
+        const int64_t tasks = (int64_t)k * S, slots = (tasks + nt - 1) / nt * nt;
+        if (slots / nt > kKptMax) break;
+        if (20 * tasks >= 19 * slots) return S;
+        if (tasks * bden > bnum * slots) {
+            best = S;
+            bnum = tasks;
+            bden = slots;
+        }
+    }
+    return best;
+}
+
 template <typename TQ, typename T, bool TAB = false, int DEPTH = kTabDepth, bool EXACT = false, typename TC = T>
 __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, const Grid3& g, int64_t n,
                                                   T* __restrict__ t_out, const SketchArgs& sk,
@@ -416,19 +439,68 @@ __device__ __forceinline__ void stencil_dual_body(const TQ* __restrict__ xs, con
     } else {
         const int nq = rem >= RB ? RB / 4 : (int)((rem + 3) / 4);
         const uint32_t q0 = (uint32_t)(blk * (RB / 4));
-        for (int q = 0; q < nq; ++q) {
-            const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
-            const T t0 = lds[RB + 4 * q], t1 = lds[RB + 4 * q + 1], t2 = lds[RB + 4 * q + 2],
-                    t3 = lds[RB + 4 * q + 3];
+        const int S = dual_segments(sk.k, NT);
+        if (S == 1) {
+            for (int q = 0; q < nq; ++q) {
+                const T x0 = lds[4 * q], x1 = lds[4 * q + 1], x2 = lds[4 * q + 2], x3 = lds[4 * q + 3];
+                const T t0 = lds[RB + 4 * q], t1 = lds[RB + 4 * q + 1], t2 = lds[RB + 4 * q + 2],
+                        t3 = lds[RB + 4 * q + 3];
+#pragma unroll
+                for (int u = 0; u < kKptMax; ++u) {
+                    const int j = threadIdx.x + NT * u;
+                    if (u < kpt && j < sk.k) {
+                        T z[4];
+                        gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+                        ax[u] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
+                        at[u] += z[0] * t0 + z[1] * t1 + z[2] * t2 + z[3] * t3;
+                    }
+                }
+            }
+        } else {
+            // k < NT: task tau = s k + j sums row j over segment s of the block's
+            // quads, so that the k S tasks keep every lane busy; then row j adds
+            // its S segment sums in segment order
+            const int ntask = sk.k * S;
 #pragma unroll
             for (int u = 0; u < kKptMax; ++u) {
-                const int j = threadIdx.x + NT * u;
-                if (u < kpt && j < sk.k) {
-                    T z[4];
-                    gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
-                    ax[u] += z[0] * x0 + z[1] * x1 + z[2] * x2 + z[3] * x3;
-                    at[u] += z[0] * t0 + z[1] * t1 + z[2] * t2 + z[3] * t3;
+                const int tau = threadIdx.x + NT * u;
+                if (tau < ntask) {
+                    const int j = tau % sk.k, sg = tau / sk.k;
+                    const int qa = (int)((int64_t)nq * sg / S), qb = (int)((int64_t)nq * (sg + 1) / S);
+                    T sx = T(0), st = T(0);
+                    for (int q = qa; q < qb; ++q) {
+                        T z[4];
+                        gauss4(q0 + (uint32_t)q, (uint32_t)j, sk.sid, sk.inst, sk.k0, sk.k1, z);
+                        sx += z[0] * lds[4 * q] + z[1] * lds[4 * q + 1] + z[2] * lds[4 * q + 2] +
+                              z[3] * lds[4 * q + 3];
+                        st += z[0] * lds[RB + 4 * q] + z[1] * lds[RB + 4 * q + 1] + z[2] * lds[RB + 4 * q + 2] +
+                              z[3] * lds[RB + 4 * q + 3];
+                    }
+                    ax[u] = sx;
+                    at[u] = st;
                 }
+            }
+            __syncthreads();   // every task has read x and t: their LDS takes the segment sums
+#pragma unroll
+            for (int u = 0; u < kKptMax; ++u) {
+                const int tau = threadIdx.x + NT * u;
+                if (tau < ntask) {
+                    lds[tau] = ax[u];
+                    lds[RB + tau] = at[u];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kKptMax; ++u) ax[u] = at[u] = T(0);
+            const int j = threadIdx.x;   // kpt == 1
+            if (j < sk.k) {
+                T sx = lds[j], st = lds[RB + j];
+                for (int sg = 1; sg < S; ++sg) {
+                    sx += lds[sg * sk.k + j];
+                    st += lds[RB + sg * sk.k + j];
+                }
+                ax[0] = sx;
+                at[0] = st;
             }
         }
     }

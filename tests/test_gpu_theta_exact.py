@@ -153,7 +153,9 @@ def test_exact_rgmres_matches_drawn(gpu_handle, prec, reuse):
         assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
         runs.append((rep, np.asarray(hist)))
     (rep0, h0), (rep1, h1) = runs
-    assert abs(rep1.iters - rep0.iters) <= (0 if prec == "fp64" else 1)
+    # the two sum the sketch in different orders; with a bf16 basis (u = 2^-8) the count
+    # follows that rounding, so its bar is the +-2 of the bf16 model's other comparisons
+    assert abs(rep1.iters - rep0.iters) <= {"fp64": 0, "fp32": 1, "bf16q": 2}[prec]
     L = min(len(h0), len(h1), restart)
     np.testing.assert_allclose(h1[:L], h0[:L], rtol={"fp64": 1e-10, "fp32": 1e-4, "bf16q": 1e-2}[prec])
     if prec == "fp64":
